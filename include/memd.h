@@ -1,0 +1,197 @@
+/*
+ * memd.h -- C-ABI of the MI355X (gfx950) MEMD library: the per-timestep
+ * lattice update of Maxwell Equations Molecular Dynamics with a spatially
+ * varying permittivity (Fahrenberger & Holm, "Computing Coulomb Interaction
+ * in Inhomogeneous Dielectric Media via a Local Electrostatics Lattice
+ * Algorithm", arXiv:1309.7859).
+ *
+ * Lattice and fields
+ *   L x L x L periodic cubic lattice, spacing a, volume V = (L a)^3, Ns = L^3.
+ *   Site v = (i, j, k) sits at a*v; linear index v = i + L*(j + L*k), x fastest.
+ *   Links carry D and the permittivity, plaquettes carry B, vertices carry
+ *   the interpolated charges (section "Extension of the algorithm", Fig. 2a).
+ *   Link (v, d) runs from v to v + e_d; plaquette (v, d) has corner v and
+ *   normal d.  Field arrays crossing this boundary are FP64, structure of
+ *   arrays, component-major: X[d*Ns + v], d = 0 (x), 1 (y), 2 (z).
+ *   Positions are unfolded (never wrapped), xyz interleaved per ion: r[3*i + d].
+ *   Units: eps0 = 1; Gauss's law a^2 * sum_d [D_d(v) - D_d(v - e_d)] = q_v.
+ *
+ * Pointers
+ *   Every array argument may point to host memory or to device memory of the
+ *   context's GPU; the library tells them apart itself.  Inputs are copied (or,
+ *   for device pointers, consumed in stream order) before the call returns
+ *   control of host memory: the caller keeps ownership and may reuse a host
+ *   buffer at once.  A device input must stay valid until the context's
+ *   stream has reached the call.  Outputs go to caller-allocated buffers.
+ *
+ * Ordering and threads
+ *   A context owns one HIP stream (the caller's, or its own when NULL is given)
+ *   and enqueues all work there.  memd_step returns once the work is enqueued.
+ *   Calls that return results (forces, energy, residual, dipole, state, solve)
+ *   wait for the stream.  A context is not thread-safe.
+ *
+ * Errors
+ *   Every call returns a memd_status; no C++ exception crosses this boundary.
+ *   After MEMD_EDEVICE the context is poisoned and only memd_destroy is valid.
+ */
+#ifndef MEMD_H
+#define MEMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct memd_ctx memd_ctx;
+
+typedef enum {
+    MEMD_OK = 0,
+    MEMD_EINVAL = -1,       /* bad argument (NULL pointer, L < 2, a <= 0, ...) */
+    MEMD_ENOMEM = -2,       /* device allocation failed */
+    MEMD_ENONNEUTRAL = -3,  /* |sum q| > 1e-12 sum |q|: no periodic solution of Gauss's law */
+    MEMD_EUNSTABLE = -4,    /* Courant number c dt sqrt(3) / (a sqrt(eps_min)) >= 1 */
+    MEMD_ESTATE = -5,       /* call out of order (e.g. step before the initial solve) */
+    MEMD_ENOCONV = -6,      /* the relaxation did not reach the tolerance */
+    MEMD_EDEVICE = -7       /* a HIP call failed; the context is poisoned */
+} memd_status;
+
+typedef enum {
+    MEMD_FP64 = 0,        /* D, B, eta stored and propagated in FP64 */
+    MEMD_FP32_MIXED = 1   /* D, B, eta in FP32; initial solve, dipole, energies and the
+                             Gauss audit in FP64 */
+} memd_precision;
+
+typedef enum {
+    MEMD_EPS_UNIFORM = 0, /* eps[0]: one value everywhere */
+    MEMD_EPS_SITE = 1,    /* eps[Ns]: one value per lattice site, mapped to links */
+    MEMD_EPS_LINK = 2,    /* eps[3*Ns]: one value per link, component-major */
+    MEMD_EPS_ZSITE = 3    /* eps[L]: site value per z plane (a planar profile), mapped to links */
+} memd_eps_mode;
+
+typedef struct {
+    int L;              /* lattice points per side, >= 2 */
+    double a;           /* lattice spacing, > 0 */
+    double dt;          /* time step, > 0 */
+    double c;           /* artificial speed of light, c^2 = 1/f_mass; <= 0: set at the first
+                           memd_set_permittivity for a Courant number of 1/4 */
+    int precision;      /* memd_precision */
+    int audit_every;    /* Gauss audit every this many steps inside memd_step (0 = never) */
+    int energy_every;   /* energy evaluation every this many steps inside memd_step (0 = never) */
+} memd_params;
+
+typedef struct {
+    double W_E;          /* 1/2 a^3 sum_links D^2 / eps */
+    double W_B;          /* (c^2/2) a^3 sum_plaquettes B^{n+1/2} B^{n+3/2} (leapfrog shadow form) */
+    double U_self;       /* sum_i q_i^2 S(f_i) / (2 eps_cell a): lattice self energy */
+    double U_dip;        /* sum_d P_d^2 / (2 V eps_h_d): uniform-mode energy removed by the
+                            dipole correction */
+    double E_corrected;  /* W_E + W_B - U_self - U_dip */
+} memd_energy_t;
+
+/* Create a context: lattice, ions and the device buffers.
+ * Section "Extension of the algorithm" (the method's two parts: an initial
+ * solution of Gauss's law, then its propagation).  q[n] charges, r0[3n]
+ * unfolded positions.  hip_stream: a hipStream_t, or NULL for a stream of the
+ * library's own.  The permittivity starts uniform, eps = 1.
+ * Errors: EINVAL (bad params or pointers, n < 0), ENONNEUTRAL, ENOMEM, EDEVICE. */
+memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n_ions,
+                              const double *q, const double *r0, void *hip_stream);
+
+/* Map a permittivity onto the links (section "Extension of the algorithm",
+ * Fig. 2b and eq. dielectric-interpolation): for SITE and ZSITE modes the
+ * link takes the mean of its two site values, or, where their ratio exceeds
+ * interface_ratio (<= 0 selects 4), the harmonic combination
+ * 1/eps = 1/(2 eps1) + 1/(2 eps2) of an interface link.  Also forms the
+ * directional harmonic means used by the dipole correction.  Allowed during a
+ * run: D and B are kept.  eps values must be > 0.
+ * Errors: EINVAL (mode, NULL, eps <= 0), EUNSTABLE (Courant number >= 1), EDEVICE. */
+memd_status memd_set_permittivity(memd_ctx *ctx, int mode, const double *eps,
+                                  double interface_ratio);
+
+/* Salt-dependent permittivity per link (the introduction: the permittivity
+ * of water falls with the salt concentration): eps = eps_w - slope * c with c
+ * the linear-interpolated ion count per a^3, averaged over the periodic
+ * 3 x 3 x 3 vertex box and over the two ends of each link; floored at
+ * eps_floor.  Evaluated now and, when every > 0, again inside memd_step
+ * before every step whose index is a multiple of `every`.
+ * Errors: EINVAL (eps_w <= 0, eps_floor <= 0, every < 0), EUNSTABLE, EDEVICE. */
+memd_status memd_set_salt_permittivity(memd_ctx *ctx, double eps_w, double slope,
+                                       double eps_floor, int every);
+
+/* Initial solution of Gauss's law (Fig. 1: plane -> line -> vertex recursion),
+ * the uniform mode set to -P/V (section "Periodicity"), then relaxation to
+ * curl E = 0 by minimising the field energy (the paragraph after the
+ * recursion), all in FP64 on the GPU; B is set to 0.  Stops when
+ * a max|C(eta D)| <= tol max|eta D| (tol <= 0 selects 1e-13).
+ * iters_out and curl_residual_out may be NULL.
+ * Errors: ENOCONV (not converged within max_iter; the best D is kept), EDEVICE. */
+memd_status memd_initial_gauss_solve(memd_ctx *ctx, double tol, int max_iter,
+                                     int *iters_out, double *curl_residual_out);
+
+/* Advance nsteps time steps with prescribed displacements disp[nsteps*n*3]
+ * (step-major, then ion, then xyz).  Each step (eqs. faraday/ampere with
+ * E = D/eps, eq. constraint): B -= dt C(eta D); D += dt c^2 C^T B; the ions
+ * move by their displacement, axis by axis, depositing their currents on the
+ * links so that Gauss's law holds exactly; then the dipole moment of the
+ * unfolded positions and the corrected forces (eq. force without v x B,
+ * self-energy and dipole corrections) are formed on the device.  Audit and
+ * energy run at their configured cadence.  Asynchronous.
+ * Errors: ESTATE (no initial solve or state yet), EINVAL, EDEVICE. */
+memd_status memd_step(memd_ctx *ctx, const double *disp, int nsteps);
+
+/* Forces F_out[3n] on the ions at the current state (FP64). */
+memd_status memd_forces(memd_ctx *ctx, double *F_out);
+
+/* Energies of the current state (FP64 accumulation). */
+memd_status memd_energy(memd_ctx *ctx, memd_energy_t *out);
+
+/* Gauss audit of the current state: R_v = a^2 div D(v) - q_v with q_v the
+ * linear assignment of the ions, max_v |R_v| and rms (FP64).  Either output
+ * may be NULL. */
+memd_status memd_gauss_residual(memd_ctx *ctx, double *max_abs, double *rms);
+
+/* Dipole moment of the unfolded positions, P = sum_i q_i r_i (FP64). */
+memd_status memd_dipole(memd_ctx *ctx, double P[3]);
+
+/* Results of the audits and energy evaluations run inside memd_step since the
+ * last call (oldest first).  audit: 2 doubles per entry (max, rms); energy: 5
+ * doubles per entry (memd_energy_t order).  *count receives the number of
+ * entries available (capped at max_entries when copying).  Either buffer may
+ * be NULL to query the count. */
+memd_status memd_history(memd_ctx *ctx, double *audit, double *energy, int max_entries,
+                         int *audit_count, int *energy_count);
+
+/* Copy the state out / in: D[3*Ns], B[3*Ns] (B at the last half step), r[3n].
+ * memd_set_state also marks the context ready to step (it replaces the
+ * initial solve).  Any of the three may be NULL to skip it. */
+memd_status memd_get_state(memd_ctx *ctx, double *D, double *B, double *r);
+memd_status memd_set_state(memd_ctx *ctx, const double *D, const double *B, const double *r);
+
+/* Introspection: the context's stream (hipStream_t), the speed of light in use,
+ * and the directional harmonic-mean permittivities eps_h[3]. */
+memd_status memd_get_stream(memd_ctx *ctx, void **stream);
+memd_status memd_get_params(memd_ctx *ctx, double *c, double eps_h[3], double *eps_min);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch of the named kernel family (0 leapfrog, 1 deposit, 2 forces,
+ * 3 audit, 4 energy, 5 dipole, 6 salt).  enable != 0 starts a fresh
+ * collection.  memd_profile_read waits for the stream and returns the total
+ * milliseconds and the launch count of one family. */
+memd_status memd_profile_enable(memd_ctx *ctx, int enable);
+memd_status memd_profile_read(memd_ctx *ctx, int family, double *total_ms, long *launches);
+
+/* Tile configuration of the leapfrog kernel: rows per thread (1, 2 or 4: a
+ * tile of 64 x 4*rows sites per plane) and planes per z-chunk (>= 1).
+ * 0 keeps the current value. */
+memd_status memd_set_tiling(memd_ctx *ctx, int rows_per_thread, int planes_per_chunk);
+
+void memd_destroy(memd_ctx *ctx);
+const char *memd_strerror(memd_status status);
+int memd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

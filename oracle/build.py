@@ -14,7 +14,7 @@ def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "memd_oracle.c")
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
-           "-ffp-contract=off", "-Wall", "-Wno-unknown-pragmas",
+           "-ffp-contract=off", "-Wall", "-Wno-unknown-pragmas", "-Wno-maybe-uninitialized",
            "-o", tmp, src, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

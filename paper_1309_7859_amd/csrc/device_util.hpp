@@ -1,0 +1,90 @@
+// device_util.hpp -- small device helpers: index wrapping, folding of unfolded
+// coordinates, deterministic wavefront/block reductions (64-wide wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace memd {
+
+// Periodic wrap of i in [-L, inf) to [0, L).
+__device__ __forceinline__ int wrapc(int i, int L) {
+    if (i < 0) return i + L;
+    if (i >= L) return i % L;
+    return i;
+}
+
+// Fold an unfolded coordinate: t = u/a, k = floor(t), f = t - k in [0, 1),
+// folded cell c = k mod L.
+__device__ __forceinline__ void fold(double u, double a, int L, int &c, double &f) {
+    double t = u / a;
+    double fl = floor(t);
+    f = t - fl;
+    long long k = (long long)fl;
+    long long m = k % (long long)L;
+    if (m < 0) m += L;
+    c = (int)m;
+}
+
+__device__ __forceinline__ double lin_w(int o, double f) { return o ? f : 1.0 - f; }
+
+__device__ __forceinline__ size_t site_index(int i, int j, int k, int L) {
+    return (size_t)i + (size_t)L * ((size_t)j + (size_t)L * (size_t)k);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block-wide sums of N values (blockDim.x a multiple of 64, <= 1024).  The
+// result is returned to every thread; the summation order is fixed.
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N]) {
+    __shared__ double sh[N][16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) sh[i][wid] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += sh[i][w];
+        v[i] = s;
+    }
+}
+
+__device__ __forceinline__ double block_max(double v) {
+    __shared__ double sh[16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_max(v);
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double m = sh[0];
+    for (int w = 1; w < nw; ++w) m = fmax(m, sh[w]);
+    return m;
+}
+
+// Map the hardware block id to a logical tile id so that consecutive logical
+// tiles (spatial neighbours sharing halos) land on the same XCD: blocks are
+// dealt round-robin over the 8 XCDs of an MI355X.
+__device__ __forceinline__ int xcd_logical(int b, int nb) {
+    if ((nb & 7) != 0) return b;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+}  // namespace memd

@@ -1,0 +1,628 @@
+// kernels_field.hip -- lattice-field kernels for gfx950: the fused leapfrog
+// (Faraday + Ampere), energy and Gauss-audit reductions, permittivity maps.
+//
+// Leapfrog (eqs. faraday/bfield with E = D/eps, eqs. ampere/dfield):
+//   B^{n+1/2} = B^{n-1/2} - dt C(eta D^n)
+//   D*        = D^n + dt c^2 C^T B^{n+1/2}
+// with the discrete curl of the original lattice method:
+//   (C X)_d(v)   = [X_d2(v+e_d1) - X_d2(v) - X_d1(v+e_d2) + X_d1(v)] / a
+//   (C^T Y)_d(v) = [Y_d2(v) - Y_d2(v-e_d1) - Y_d1(v) + Y_d1(v-e_d2)] / a
+// One pass reads D, B (and eta) once and writes D, B once: the workgroup owns
+// a 64 x (4 R) column of sites and marches through a chunk of z planes,
+// staging eta*D of the current and next plane (with a one-site halo) and the
+// new B of the current plane (with a -1 halo) in LDS.  The new B of the
+// plane below stays in registers.  Input and output are separate buffers
+// (ping-pong), so tiles never see each other's results.
+#include "device_util.hpp"
+#include "memd_internal.hpp"
+
+namespace memd {
+
+template <typename T>
+struct LfArgs {
+    const T *__restrict__ Din;
+    const T *__restrict__ Bin;
+    T *__restrict__ Dout;
+    T *__restrict__ Bout;
+    const T *__restrict__ eta_link;
+    const T *__restrict__ eta_prof;
+    T eta_uni;
+    T kB;  // dt / a
+    T kD;  // dt c^2 / a
+    int L;
+    size_t Ns;
+    int ntx, nty, tz;
+};
+
+template <typename T, int EM>
+__device__ __forceinline__ T eta_at(const LfArgs<T> &A, int d, int gz, size_t off) {
+    if constexpr (EM == ETA_UNIFORM) {
+        return A.eta_uni;
+    } else if constexpr (EM == ETA_ZPROF) {
+        return A.eta_prof[d * A.L + gz];
+    } else {
+        return A.eta_link[(size_t)d * A.Ns + off];
+    }
+}
+
+template <typename T, int EM, int R>
+__global__ __launch_bounds__(256) void k_leapfrog(LfArgs<T> A) {
+    constexpr int TX = 64, TY = 4 * R;
+    __shared__ T sX[2][3][TY + 2][TX + 2];
+    __shared__ T sB[3][TY + 1][TX + 1];
+
+    const int L = A.L;
+    const size_t Ns = A.Ns, LL = (size_t)L * L;
+    const int logical = xcd_logical(blockIdx.x, gridDim.x);
+    const int tile_x = logical % A.ntx;
+    const int rest = logical / A.ntx;
+    const int tile_y = rest % A.nty;
+    const int chunk = rest / A.nty;
+    const int x0 = tile_x * TX, y0 = tile_y * TY, z0 = chunk * A.tz;
+    const int z1 = min(z0 + A.tz, L);
+    const int lx = threadIdx.x & 63, wy = threadIdx.x >> 6;
+    const int xx = lx + 1;
+    const int gx = wrapc(x0 + lx, L);
+    const bool xact = (x0 + lx) < L;
+    const T kB = A.kB, kD = A.kD;
+
+    int gyo[R];
+    bool act[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        gyo[r] = wrapc(y0 + wy + 4 * r, L);
+        act[r] = xact && (y0 + wy + 4 * r) < L;
+    }
+
+    // Stage eta*D of plane gz into sX[buf] (own sites, halo rows and columns);
+    // own D values go to Dreg.
+    auto load_plane = [&](int buf, int gz, T (&Dreg)[R][3]) {
+        const size_t zoff = (size_t)gz * LL;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const size_t off = zoff + (size_t)gyo[r] * L + gx;
+            const int yy = wy + 4 * r + 1;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const T v = A.Din[(size_t)d * Ns + off];
+                Dreg[r][d] = v;
+                sX[buf][d][yy][xx] = eta_at<T, EM>(A, d, gz, off) * v;
+            }
+        }
+        if (wy < 2) {
+            const int yy = wy ? TY + 1 : 0;
+            const int gy = wrapc(y0 - 1 + yy, L);
+            const size_t off = zoff + (size_t)gy * L + gx;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                sX[buf][d][yy][xx] = eta_at<T, EM>(A, d, gz, off) * A.Din[(size_t)d * Ns + off];
+        } else if (lx < TY + 2) {
+            const int xc = (wy == 2) ? 0 : TX + 1;
+            const int gxx = wrapc(x0 - 1 + xc, L);
+            const int gy = wrapc(y0 - 1 + lx, L);
+            const size_t off = zoff + (size_t)gy * L + gxx;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                sX[buf][d][lx][xc] = eta_at<T, EM>(A, d, gz, off) * A.Din[(size_t)d * Ns + off];
+        }
+    };
+
+    T Dc[R][3], Dn[R][3], prevB[R][2];
+
+    // Prologue: new B_x, B_y of the plane below the chunk, for the own sites.
+    {
+        const int gzp = wrapc(z0 - 1, L);
+        T dummy[R][3];
+        load_plane(0, gzp, dummy);
+        load_plane(1, z0, Dc);
+        T bo[R][2];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const size_t off = (size_t)gzp * LL + (size_t)gyo[r] * L + gx;
+            bo[r][0] = A.Bin[off];
+            bo[r][1] = A.Bin[Ns + off];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int yy = wy + 4 * r + 1;
+            prevB[r][0] = bo[r][0] - kB * (sX[0][2][yy + 1][xx] - sX[0][2][yy][xx] -
+                                           sX[1][1][yy][xx] + sX[0][1][yy][xx]);
+            prevB[r][1] = bo[r][1] - kB * (sX[1][0][yy][xx] - sX[0][0][yy][xx] -
+                                           sX[0][2][yy][xx + 1] + sX[0][2][yy][xx]);
+        }
+        __syncthreads();
+    }
+
+    int cur = 1;
+    for (int k = z0; k < z1; ++k) {
+        const int nxt = cur ^ 1;
+        const int gzn = wrapc(k + 1, L);
+        const size_t zoff = (size_t)k * LL;
+        load_plane(nxt, gzn, Dn);
+
+        T Bo[R][3];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const size_t off = zoff + (size_t)gyo[r] * L + gx;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Bo[r][d] = A.Bin[(size_t)d * Ns + off];
+        }
+        // halo B^{n-1/2}: row y0-1 (B_x, B_z) on wave 0, column x0-1 (B_y, B_z) on wave 1
+        T hb0 = 0, hb1 = 0;
+        if (wy == 0) {
+            const size_t off = zoff + (size_t)wrapc(y0 - 1, L) * L + gx;
+            hb0 = A.Bin[off];
+            hb1 = A.Bin[2 * Ns + off];
+        } else if (wy == 1 && lx < TY) {
+            const size_t off = zoff + (size_t)wrapc(y0 + lx, L) * L + wrapc(x0 - 1, L);
+            hb0 = A.Bin[Ns + off];
+            hb1 = A.Bin[2 * Ns + off];
+        }
+        __syncthreads();
+
+        // Faraday: new B on the own sites
+        T Bn[R][3];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int yy = wy + 4 * r + 1;
+            Bn[r][0] = Bo[r][0] - kB * (sX[cur][2][yy + 1][xx] - sX[cur][2][yy][xx] -
+                                        sX[nxt][1][yy][xx] + sX[cur][1][yy][xx]);
+            Bn[r][1] = Bo[r][1] - kB * (sX[nxt][0][yy][xx] - sX[cur][0][yy][xx] -
+                                        sX[cur][2][yy][xx + 1] + sX[cur][2][yy][xx]);
+            Bn[r][2] = Bo[r][2] - kB * (sX[cur][1][yy][xx + 1] - sX[cur][1][yy][xx] -
+                                        sX[cur][0][yy + 1][xx] + sX[cur][0][yy][xx]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sB[d][yy][xx] = Bn[r][d];
+            if (act[r]) {
+                const size_t off = zoff + (size_t)gyo[r] * L + gx;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) A.Bout[(size_t)d * Ns + off] = Bn[r][d];
+            }
+        }
+        // Faraday on the -1 halo
+        if (wy == 0) {
+            sB[0][0][xx] = hb0 - kB * (sX[cur][2][1][xx] - sX[cur][2][0][xx] -
+                                       sX[nxt][1][0][xx] + sX[cur][1][0][xx]);
+            sB[2][0][xx] = hb1 - kB * (sX[cur][1][0][xx + 1] - sX[cur][1][0][xx] -
+                                       sX[cur][0][1][xx] + sX[cur][0][0][xx]);
+        } else if (wy == 1 && lx < TY) {
+            const int yy = lx + 1;
+            sB[1][yy][0] = hb0 - kB * (sX[nxt][0][yy][0] - sX[cur][0][yy][0] -
+                                       sX[cur][2][yy][1] + sX[cur][2][yy][0]);
+            sB[2][yy][0] = hb1 - kB * (sX[cur][1][yy][1] - sX[cur][1][yy][0] -
+                                       sX[cur][0][yy + 1][0] + sX[cur][0][yy][0]);
+        }
+        __syncthreads();
+
+        // Ampere: new D on the own sites
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int yy = wy + 4 * r + 1;
+            const T dx = Dc[r][0] + kD * (Bn[r][2] - sB[2][yy - 1][xx] - Bn[r][1] + prevB[r][1]);
+            const T dy = Dc[r][1] + kD * (Bn[r][0] - prevB[r][0] - Bn[r][2] + sB[2][yy][xx - 1]);
+            const T dz = Dc[r][2] + kD * (Bn[r][1] - sB[1][yy][xx - 1] - Bn[r][0] + sB[0][yy - 1][xx]);
+            if (act[r]) {
+                const size_t off = zoff + (size_t)gyo[r] * L + gx;
+                A.Dout[off] = dx;
+                A.Dout[Ns + off] = dy;
+                A.Dout[2 * Ns + off] = dz;
+            }
+            prevB[r][0] = Bn[r][0];
+            prevB[r][1] = Bn[r][1];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Dc[r][d] = Dn[r][d];
+        }
+        cur = nxt;
+    }
+}
+
+template <typename T, int EM>
+static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, void *Dout,
+                              void *Bout) {
+    LfArgs<T> A;
+    A.Din = (const T *)Din;
+    A.Bin = (const T *)Bin;
+    A.Dout = (T *)Dout;
+    A.Bout = (T *)Bout;
+    A.eta_link = (const T *)c->eta_link;
+    A.eta_prof = (const T *)c->eta_prof;
+    A.eta_uni = (T)c->eta_uni;
+    A.kB = (T)(c->dt / c->a);
+    A.kD = (T)(c->dt * c->c * c->c / c->a);
+    A.L = c->L;
+    A.Ns = c->Ns;
+    const int R = c->lf_rows;
+    const int TY = 4 * R;
+    A.ntx = (c->L + 63) / 64;
+    A.nty = (c->L + TY - 1) / TY;
+    A.tz = c->lf_tz;
+    const int nz = (c->L + A.tz - 1) / A.tz;
+    const int nblk = A.ntx * A.nty * nz;
+    if (R == 1)
+        hipLaunchKernelGGL((k_leapfrog<T, EM, 1>), dim3(nblk), dim3(256), 0, c->stream, A);
+    else if (R == 2)
+        hipLaunchKernelGGL((k_leapfrog<T, EM, 2>), dim3(nblk), dim3(256), 0, c->stream, A);
+    else
+        hipLaunchKernelGGL((k_leapfrog<T, EM, 4>), dim3(nblk), dim3(256), 0, c->stream, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout) {
+    if (c->fp32) {
+        switch (c->eta_mode) {
+            case ETA_UNIFORM: return launch_lf_t<float, ETA_UNIFORM>(c, Din, Bin, Dout, Bout);
+            case ETA_ZPROF: return launch_lf_t<float, ETA_ZPROF>(c, Din, Bin, Dout, Bout);
+            default: return launch_lf_t<float, ETA_LINK>(c, Din, Bin, Dout, Bout);
+        }
+    }
+    switch (c->eta_mode) {
+        case ETA_UNIFORM: return launch_lf_t<double, ETA_UNIFORM>(c, Din, Bin, Dout, Bout);
+        case ETA_ZPROF: return launch_lf_t<double, ETA_ZPROF>(c, Din, Bin, Dout, Bout);
+        default: return launch_lf_t<double, ETA_LINK>(c, Din, Bin, Dout, Bout);
+    }
+}
+
+// ------------------------------------------------------------------ energy
+
+template <typename T>
+struct FieldView {
+    const T *D;
+    const T *B;
+    const T *eta_link;
+    const T *eta_prof;
+    double eta_uni;
+    int mode;
+    int L;
+    size_t Ns;
+};
+
+template <typename T>
+__device__ __forceinline__ double eta_fv(const FieldView<T> &V, int d, int k, size_t off) {
+    if (V.mode == ETA_UNIFORM) return V.eta_uni;
+    if (V.mode == ETA_ZPROF) return (double)V.eta_prof[d * V.L + k];
+    return (double)V.eta_link[(size_t)d * V.Ns + off];
+}
+
+template <typename T>
+__device__ __forceinline__ double X_at(const FieldView<T> &V, int d, int i, int j, int k) {
+    const size_t off = site_index(i, j, k, V.L);
+    return eta_fv(V, d, k, off) * (double)V.D[(size_t)d * V.Ns + off];
+}
+
+// W_E = 1/2 a^3 sum eta D^2 and W_B = (c^2/2) a^3 sum B (B - dt C(eta D)), per block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_energy_field(FieldView<T> V, double kB, double *partials) {
+    const int L = V.L;
+    double we = 0.0, wb = 0.0;
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < V.Ns;
+         v += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(v % L), j = (int)((v / L) % L), k = (int)(v / ((size_t)L * L));
+        const int ip = (i + 1 == L) ? 0 : i + 1, jp = (j + 1 == L) ? 0 : j + 1,
+                  kp = (k + 1 == L) ? 0 : k + 1;
+        double X[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double Dd = (double)V.D[(size_t)d * V.Ns + v];
+            X[d] = eta_fv(V, d, k, v) * Dd;
+            we += X[d] * Dd;
+        }
+        const double cx = X_at(V, 2, i, jp, k) - X[2] - X_at(V, 1, i, j, kp) + X[1];
+        const double cy = X_at(V, 0, i, j, kp) - X[0] - X_at(V, 2, ip, j, k) + X[2];
+        const double cz = X_at(V, 1, ip, j, k) - X[1] - X_at(V, 0, i, jp, k) + X[0];
+        const double bx = (double)V.B[v], by = (double)V.B[V.Ns + v], bz = (double)V.B[2 * V.Ns + v];
+        wb += bx * (bx - kB * cx) + by * (by - kB * cy) + bz * (bz - kB * cz);
+    }
+    double s[2] = {we, wb};
+    block_sum<2>(s);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s[0];
+        partials[2 * blockIdx.x + 1] = s[1];
+    }
+}
+
+template <typename T>
+static FieldView<T> make_view(memd_ctx *c, const void *D, const void *B) {
+    FieldView<T> V;
+    V.D = (const T *)D;
+    V.B = (const T *)B;
+    V.eta_link = (const T *)c->eta_link;
+    V.eta_prof = (const T *)c->eta_prof;
+    V.eta_uni = c->eta_uni;
+    V.mode = c->eta_mode;
+    V.L = c->L;
+    V.Ns = c->Ns;
+    return V;
+}
+
+static int site_blocks(size_t Ns) {
+    size_t b = (Ns + kThreads - 1) / kThreads;
+    return (int)(b < (size_t)kRedBlocks ? b : (size_t)kRedBlocks);
+}
+
+hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
+                               int *nblk) {
+    const int nb = site_blocks(c->Ns);
+    *nblk = nb;
+    const double kB = c->dt / c->a;
+    if (c->fp32)
+        hipLaunchKernelGGL(k_energy_field<float>, dim3(nb), dim3(kThreads), 0, c->stream,
+                           make_view<float>(c, D, B), kB, partials);
+    else
+        hipLaunchKernelGGL(k_energy_field<double>, dim3(nb), dim3(kThreads), 0, c->stream,
+                           make_view<double>(c, D, B), kB, partials);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- audit
+
+// R_v = a^2 sum_d [D_d(v) - D_d(v-e_d)] - rho_v in FP64; rho is cleared after
+// reading so that it is all-zero for the next charge assignment.
+template <typename T>
+__global__ __launch_bounds__(256) void k_audit(const T *__restrict__ D, double *__restrict__ rho,
+                                               int L, size_t Ns, double a2, double *partials) {
+    double mx = 0.0, ss = 0.0;
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns;
+         v += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(v % L), j = (int)((v / L) % L), k = (int)(v / ((size_t)L * L));
+        const size_t vx = site_index(i == 0 ? L - 1 : i - 1, j, k, L);
+        const size_t vy = site_index(i, j == 0 ? L - 1 : j - 1, k, L);
+        const size_t vz = site_index(i, j, k == 0 ? L - 1 : k - 1, L);
+        const double dv = ((double)D[v] - (double)D[vx]) + ((double)D[Ns + v] - (double)D[Ns + vy]) +
+                          ((double)D[2 * Ns + v] - (double)D[2 * Ns + vz]);
+        const double R = a2 * dv - rho[v];
+        rho[v] = 0.0;
+        mx = fmax(mx, fabs(R));
+        ss += R * R;
+    }
+    double s[1] = {ss};
+    block_sum<1>(s);
+    const double m = block_max(mx);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = m;
+        partials[2 * blockIdx.x + 1] = s[0];
+    }
+}
+
+hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk) {
+    const int nb = site_blocks(c->Ns);
+    *nblk = nb;
+    const double a2 = c->a * c->a;
+    if (c->fp32)
+        hipLaunchKernelGGL(k_audit<float>, dim3(nb), dim3(kThreads), 0, c->stream, (const float *)D,
+                           c->rho, c->L, c->Ns, a2, partials);
+    else
+        hipLaunchKernelGGL(k_audit<double>, dim3(nb), dim3(kThreads), 0, c->stream,
+                           (const double *)D, c->rho, c->L, c->Ns, a2, partials);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ casts
+
+template <typename S, typename D>
+__global__ void k_convert(const S *__restrict__ src, D *__restrict__ dst, size_t count) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < count;
+         t += (size_t)gridDim.x * blockDim.x)
+        dst[t] = (D)src[t];
+}
+
+static int grid_for(size_t count) {
+    size_t b = (count + kThreads - 1) / kThreads;
+    if (b > 8192) b = 8192;
+    return (int)(b ? b : 1);
+}
+
+hipError_t launch_cast(hipStream_t s, const double *src, void *dst, size_t count, bool to_fp32) {
+    if (to_fp32)
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(count)), dim3(kThreads), 0, s, src,
+                           (float *)dst, count);
+    else
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(grid_for(count)), dim3(kThreads), 0, s, src,
+                           (double *)dst, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_uncast(hipStream_t s, const void *src, double *dst, size_t count, bool from_fp32) {
+    if (from_fp32)
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(count)), dim3(kThreads), 0, s,
+                           (const float *)src, dst, count);
+    else
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(grid_for(count)), dim3(kThreads), 0, s,
+                           (const double *)src, dst, count);
+    return hipGetLastError();
+}
+
+__global__ void k_fill(double *dst, double v, size_t count) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < count;
+         t += (size_t)gridDim.x * blockDim.x)
+        dst[t] = v;
+}
+
+hipError_t launch_fill(hipStream_t s, double *dst, double v, size_t count) {
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(count)), dim3(kThreads), 0, s, dst, v, count);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ permittivity
+
+// Fig. 2b / eq. dielectric-interpolation: mean of the two site values, or the
+// harmonic combination on an interface link (ratio above `ratio`), decided in
+// FP64.
+__device__ __forceinline__ double link_eps(double e1, double e2, double ratio) {
+    const double hi = e1 > e2 ? e1 : e2, lo = e1 > e2 ? e2 : e1;
+    if (hi / lo > ratio) return 1.0 / (0.5 / e1 + 0.5 / e2);
+    return 0.5 * (e1 + e2);
+}
+
+template <typename T>
+__global__ void k_eta_site(const double *__restrict__ eps, double ratio, int L, size_t Ns,
+                           T *__restrict__ eta) {
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns;
+         v += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(v % L), j = (int)((v / L) % L), k = (int)(v / ((size_t)L * L));
+        const double e = eps[v];
+        const double ex = eps[site_index(i + 1 == L ? 0 : i + 1, j, k, L)];
+        const double ey = eps[site_index(i, j + 1 == L ? 0 : j + 1, k, L)];
+        const double ez = eps[site_index(i, j, k + 1 == L ? 0 : k + 1, L)];
+        eta[v] = (T)(1.0 / link_eps(e, ex, ratio));
+        eta[Ns + v] = (T)(1.0 / link_eps(e, ey, ratio));
+        eta[2 * Ns + v] = (T)(1.0 / link_eps(e, ez, ratio));
+    }
+}
+
+template <typename T>
+__global__ void k_eta_link(const double *__restrict__ eps, size_t count, T *__restrict__ eta) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < count;
+         t += (size_t)gridDim.x * blockDim.x)
+        eta[t] = (T)(1.0 / eps[t]);
+}
+
+// planar profile: x and y links lie inside one plane (both ends equal), z
+// links join plane k to plane k+1.
+template <typename T>
+__global__ void k_eta_zprof(const double *__restrict__ epsz, double ratio, int L, T *__restrict__ prof) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= L) return;
+    const double e = epsz[k], en = epsz[k + 1 == L ? 0 : k + 1];
+    const double inplane = 1.0 / link_eps(e, e, ratio);
+    prof[k] = (T)inplane;
+    prof[L + k] = (T)inplane;
+    prof[2 * L + k] = (T)(1.0 / link_eps(e, en, ratio));
+}
+
+hipError_t launch_eta_from_link(memd_ctx *c, const double *eps_link, void *eta) {
+    const size_t cnt = 3 * c->Ns;
+    if (c->fp32)
+        hipLaunchKernelGGL(k_eta_link<float>, dim3(grid_for(cnt)), dim3(kThreads), 0, c->stream, eps_link,
+                           cnt, (float *)eta);
+    else
+        hipLaunchKernelGGL(k_eta_link<double>, dim3(grid_for(cnt)), dim3(kThreads), 0, c->stream, eps_link,
+                           cnt, (double *)eta);
+    return hipGetLastError();
+}
+
+hipError_t launch_eta_zprof(memd_ctx *c, const double *eps_z, double ratio, void *prof) {
+    const int nb = (c->L + kThreads - 1) / kThreads;
+    if (c->fp32)
+        hipLaunchKernelGGL(k_eta_zprof<float>, dim3(nb), dim3(kThreads), 0, c->stream, eps_z, ratio, c->L,
+                           (float *)prof);
+    else
+        hipLaunchKernelGGL(k_eta_zprof<double>, dim3(nb), dim3(kThreads), 0, c->stream, eps_z, ratio, c->L,
+                           (double *)prof);
+    return hipGetLastError();
+}
+
+hipError_t launch_eta_from_site(memd_ctx *c, const double *eps_site, double ratio, void *eta) {
+    if (c->fp32)
+        hipLaunchKernelGGL(k_eta_site<float>, dim3(grid_for(c->Ns)), dim3(kThreads), 0, c->stream, eps_site,
+                           ratio, c->L, c->Ns, (float *)eta);
+    else
+        hipLaunchKernelGGL(k_eta_site<double>, dim3(grid_for(c->Ns)), dim3(kThreads), 0, c->stream, eps_site,
+                           ratio, c->L, c->Ns, (double *)eta);
+    return hipGetLastError();
+}
+
+// Per-block sums of eta_d over all d-links and the maximum eta (-> eps_min).
+template <typename T>
+__global__ __launch_bounds__(256) void k_eta_sums(const T *__restrict__ eta_link,
+                                                  const T *__restrict__ eta_prof, double eta_uni,
+                                                  int mode, int L, size_t Ns, double *partials) {
+    double s[3] = {0.0, 0.0, 0.0};
+    double mx = 0.0;
+    const size_t LL = (size_t)L * L;
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns;
+         v += (size_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double e;
+            if (mode == ETA_UNIFORM) e = eta_uni;
+            else if (mode == ETA_ZPROF) e = (double)eta_prof[d * L + (int)(v / LL)];
+            else e = (double)eta_link[(size_t)d * Ns + v];
+            s[d] += e;
+            mx = fmax(mx, e);
+        }
+    }
+    block_sum<3>(s);
+    const double m = block_max(mx);
+    if (threadIdx.x == 0) {
+        partials[4 * blockIdx.x] = s[0];
+        partials[4 * blockIdx.x + 1] = s[1];
+        partials[4 * blockIdx.x + 2] = s[2];
+        partials[4 * blockIdx.x + 3] = m;
+    }
+}
+
+hipError_t launch_eta_sums(memd_ctx *c, double *partials, int *nblk) {
+    const int nb = site_blocks(c->Ns);
+    *nblk = nb;
+    if (c->fp32)
+        hipLaunchKernelGGL(k_eta_sums<float>, dim3(nb), dim3(kThreads), 0, c->stream,
+                           (const float *)c->eta_link, (const float *)c->eta_prof, c->eta_uni, c->eta_mode,
+                           c->L, c->Ns, partials);
+    else
+        hipLaunchKernelGGL(k_eta_sums<double>, dim3(nb), dim3(kThreads), 0, c->stream,
+                           (const double *)c->eta_link, (const double *)c->eta_prof, c->eta_uni,
+                           c->eta_mode, c->L, c->Ns, partials);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------- salt permittivity
+
+// nbar_v = (1/27) sum over the periodic 3x3x3 vertex box of cnt / a^3
+__global__ void k_box_mean(const double *__restrict__ cnt, int L, size_t Ns, double inv_cell,
+                           double *__restrict__ nbar) {
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns;
+         v += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(v % L), j = (int)((v / L) % L), k = (int)(v / ((size_t)L * L));
+        double s = 0.0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx)
+                    s += cnt[site_index(wrapc(i + dx, L), wrapc(j + dy, L), wrapc(k + dz, L), L)] * inv_cell;
+        nbar[v] = s / 27.0;
+    }
+}
+
+template <typename T>
+__global__ void k_salt_link(const double *__restrict__ nbar, int L, size_t Ns, double eps_w,
+                            double slope, double eps_floor, T *__restrict__ eta) {
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns;
+         v += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(v % L), j = (int)((v / L) % L), k = (int)(v / ((size_t)L * L));
+        const double n0 = nbar[v];
+        const double nb[3] = {nbar[site_index(i + 1 == L ? 0 : i + 1, j, k, L)],
+                              nbar[site_index(i, j + 1 == L ? 0 : j + 1, k, L)],
+                              nbar[site_index(i, j, k + 1 == L ? 0 : k + 1, L)]};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double cl = 0.5 * (n0 + nb[d]);
+            double e = eps_w - slope * cl;
+            e = e < eps_floor ? eps_floor : e;
+            eta[(size_t)d * Ns + v] = (T)(1.0 / e);
+        }
+    }
+}
+
+hipError_t launch_salt(memd_ctx *c) {
+    hipError_t e;
+    const int g = grid_for(c->Ns);
+    if ((e = launch_fill(c->stream, c->salt_cnt, 0.0, c->Ns)) != hipSuccess) return e;
+    if ((e = launch_spread(c, nullptr, c->salt_cnt)) != hipSuccess) return e;
+    const double a3 = c->a * c->a * c->a;
+    hipLaunchKernelGGL(k_box_mean, dim3(g), dim3(kThreads), 0, c->stream, c->salt_cnt, c->L, c->Ns,
+                       1.0 / a3, c->salt_nbar);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (c->fp32)
+        hipLaunchKernelGGL(k_salt_link<float>, dim3(g), dim3(kThreads), 0, c->stream, c->salt_nbar, c->L, c->Ns,
+                           c->salt_w, c->salt_slope, c->salt_floor, (float *)c->eta_link);
+    else
+        hipLaunchKernelGGL(k_salt_link<double>, dim3(g), dim3(kThreads), 0, c->stream, c->salt_nbar, c->L,
+                           c->Ns, c->salt_w, c->salt_slope, c->salt_floor, (double *)c->eta_link);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int nb = 0;
+    if ((e = launch_eta_sums(c, c->partials, &nb)) != hipSuccess) return e;
+    return launch_finalize_epsh(c->stream, c->partials, nb, (double)c->Ns, c->scal + S_EPSH,
+                                c->scal + S_ETAMAX);
+}
+
+}  // namespace memd

@@ -1,0 +1,512 @@
+// kernels_solve.hip -- the initial solution of Gauss's law on the GPU, FP64:
+// plane -> line -> vertex recursion (Fig. 1), the uniform mode set to -P/V
+// (section "Periodicity"), and the relaxation to curl E = 0 by minimising the
+// field energy over D + C^T theta (conjugate gradients on C eta C^T theta =
+// -C eta D with a Jacobi preconditioner; D is updated in place of theta).
+// Also the periodic lattice Green's function used by the self-energy
+// correction (eq. greens and the Brillouin-zone sum that follows it).
+#include "device_util.hpp"
+#include "memd_internal.hpp"
+
+#include <cmath>
+
+namespace memd {
+
+// ----------------------------------------------------------- recursion
+
+// Q[k] = sum over plane k of rho (one block per plane).
+__global__ __launch_bounds__(256) void k_plane_sum(const double *__restrict__ rho, int L, double *Q) {
+    const int k = blockIdx.x;
+    const size_t LL = (size_t)L * L;
+    double s[1] = {0.0};
+    for (size_t t = threadIdx.x; t < LL; t += blockDim.x) s[0] += rho[(size_t)k * LL + t];
+    block_sum<1>(s);
+    if (threadIdx.x == 0) Q[k] = s[0];
+}
+
+// qbar_k = Q_k / L^2; Dz_k = (sum_{k' <= k} qbar_k') / a^2 (one thread).
+__global__ void k_zprefix(const double *Q, int L, double a2, double *qbar, double *dz) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double run = 0.0;
+    for (int k = 0; k < L; ++k) {
+        const double qp = Q[k] / ((double)L * L);
+        qbar[k] = qp;
+        run += qp;
+        dz[k] = run / a2;
+    }
+}
+
+// qline[j,k] = sum_i (rho - qbar_k) / L   (one thread per line).
+__global__ void k_line_sum(const double *__restrict__ rho, const double *__restrict__ qbar, int L,
+                           double *qline) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= L * L) return;
+    const int k = t / L;
+    const double qb = qbar[k];
+    const size_t base = (size_t)t * L;
+    double s = 0.0;
+    for (int i = 0; i < L; ++i) s += rho[base + i] - qb;
+    qline[t] = s / (double)L;
+}
+
+// Dy[j,k] = (sum_{j' <= j} qline[j',k]) / a^2   (one thread per plane).
+__global__ void k_yprefix(const double *__restrict__ qline, int L, double a2, double *dy) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= L) return;
+    double run = 0.0;
+    for (int j = 0; j < L; ++j) {
+        run += qline[(size_t)k * L + j];
+        dy[(size_t)k * L + j] = run / a2;
+    }
+}
+
+// Per line (j,k): D_z, D_y from the prefixes; D_x from the running sum over i
+// of the remaining vertex charge rho - qbar_k - qline_jk.
+__global__ void k_row_fill(const double *__restrict__ rho, const double *__restrict__ qbar,
+                           const double *__restrict__ qline, const double *__restrict__ dz,
+                           const double *__restrict__ dy, int L, double a2, double *D) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= L * L) return;
+    const size_t Ns = (size_t)L * L * L;
+    const int k = t / L;
+    const double qb = qbar[k], ql = qline[t], vz = dz[k], vy = dy[t];
+    const size_t base = (size_t)t * L;
+    double run = 0.0;
+    for (int i = 0; i < L; ++i) {
+        const double rem = (rho[base + i] - qb) - ql;
+        run += rem;
+        D[base + i] = run / a2;
+        D[Ns + base + i] = vy;
+        D[2 * Ns + base + i] = vz;
+    }
+}
+
+hipError_t solve_recursion(memd_ctx *c, double *D) {
+    hipError_t e;
+    const int L = c->L;
+    const double a2 = c->a * c->a;
+    // rho <- charge assignment of the ions (rho is all-zero on entry)
+    if ((e = launch_spread(c, c->q, c->rho)) != hipSuccess) return e;
+    double *w = nullptr;
+    const size_t LL = (size_t)L * L;
+    if ((e = hipMallocAsync((void **)&w, (3 * L + 2 * LL) * sizeof(double), c->stream)) != hipSuccess) return e;
+    double *Q = w, *qbar = w + L, *dz = w + 2 * L, *qline = w + 3 * L, *dy = w + 3 * L + LL;
+    hipLaunchKernelGGL(k_plane_sum, dim3(L), dim3(kThreads), 0, c->stream, c->rho, L, Q);
+    hipLaunchKernelGGL(k_zprefix, dim3(1), dim3(64), 0, c->stream, Q, L, a2, qbar, dz);
+    const int nl = (int)((LL + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_line_sum, dim3(nl), dim3(kThreads), 0, c->stream, c->rho, qbar, L, qline);
+    hipLaunchKernelGGL(k_yprefix, dim3((L + 63) / 64), dim3(64), 0, c->stream, qline, L, a2, dy);
+    hipLaunchKernelGGL(k_row_fill, dim3(nl), dim3(kThreads), 0, c->stream, c->rho, qbar, qline, dz, dy, L,
+                       a2, D);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // restore the all-zero invariant of rho
+    if ((e = launch_fill(c->stream, c->rho, 0.0, c->Ns)) != hipSuccess) return e;
+    return hipFreeAsync(w, c->stream);
+}
+
+// ----------------------------------------------------------- mean shift
+
+__global__ __launch_bounds__(256) void k_dsum(const double *__restrict__ D, size_t Ns, double *partials) {
+    double s[3] = {0.0, 0.0, 0.0};
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns;
+         v += (size_t)gridDim.x * blockDim.x) {
+        s[0] += D[v];
+        s[1] += D[Ns + v];
+        s[2] += D[2 * Ns + v];
+    }
+    block_sum<3>(s);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = s[0];
+        partials[3 * blockIdx.x + 1] = s[1];
+        partials[3 * blockIdx.x + 2] = s[2];
+    }
+}
+
+// D_d += -P_d / V - sum_d / Ns
+__global__ void k_shift(double *D, size_t Ns, const double *sums, const double *P, double V) {
+    __shared__ double sh[3];
+    if (threadIdx.x < 3) sh[threadIdx.x] = -P[threadIdx.x] / V - sums[threadIdx.x] / (double)Ns;
+    __syncthreads();
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < 3 * Ns;
+         t += (size_t)gridDim.x * blockDim.x)
+        D[t] += sh[t / Ns];
+}
+
+static int red_blocks(size_t Ns) {
+    size_t b = (Ns + kThreads - 1) / kThreads;
+    return (int)(b < (size_t)kRedBlocks ? b : (size_t)kRedBlocks);
+}
+
+hipError_t solve_mean_shift(memd_ctx *c, double *D) {
+    hipError_t e;
+    int nb = 0;
+    if ((e = launch_dipole(c, c->partials, &nb)) != hipSuccess) return e;
+    if ((e = launch_finalize_dipole(c->stream, c->partials, nb, c->scal + S_P)) != hipSuccess) return e;
+    const int nr = red_blocks(c->Ns);
+    hipLaunchKernelGGL(k_dsum, dim3(nr), dim3(kThreads), 0, c->stream, D, c->Ns, c->partials);
+    if ((e = launch_finalize_sum(c->stream, c->partials, nr, 3, c->scal + S_MEAN)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_shift, dim3(red_blocks(3 * c->Ns)), dim3(kThreads), 0, c->stream, D, c->Ns,
+                       c->scal + S_MEAN, c->scal + S_P, c->V);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ relaxation
+
+struct CgArgs {
+    int L;
+    size_t Ns;
+    double inv_a;
+    const double *eta;  // FP64 eta [3Ns] (expanded for the solve)
+};
+
+__device__ __forceinline__ void site_ijk(size_t v, int L, int &i, int &j, int &k) {
+    i = (int)(v % L);
+    j = (int)((v / L) % L);
+    k = (int)(v / ((size_t)L * L));
+}
+
+// out = sgn * C(eta * X) (plaquettes); optional partials: max|out| and max|eta X|,
+// or the dot <p, out>.
+template <bool WITH_MAX, bool WITH_DOT>
+__global__ __launch_bounds__(256) void k_curl_eta(CgArgs A, const double *__restrict__ X, double sgn,
+                                                  double *__restrict__ out, const double *__restrict__ p,
+                                                  double *partials, const int *stop) {
+    if (stop && *stop) return;
+    const int L = A.L;
+    const size_t Ns = A.Ns;
+    double m1 = 0.0, m2 = 0.0, dot = 0.0;
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns;
+         v += (size_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        site_ijk(v, L, i, j, k);
+        const size_t vx = site_index(i + 1 == L ? 0 : i + 1, j, k, L);
+        const size_t vy = site_index(i, j + 1 == L ? 0 : j + 1, k, L);
+        const size_t vz = site_index(i, j, k + 1 == L ? 0 : k + 1, L);
+        auto Xe = [&](int d, size_t s) { return A.eta[(size_t)d * Ns + s] * X[(size_t)d * Ns + s]; };
+        const double x0 = Xe(0, v), x1 = Xe(1, v), x2 = Xe(2, v);
+        const double cx = (Xe(2, vy) - x2 - Xe(1, vz) + x1) * A.inv_a;
+        const double cy = (Xe(0, vz) - x0 - Xe(2, vx) + x2) * A.inv_a;
+        const double cz = (Xe(1, vx) - x1 - Xe(0, vy) + x0) * A.inv_a;
+        const double o0 = sgn * cx, o1 = sgn * cy, o2 = sgn * cz;
+        out[v] = o0;
+        out[Ns + v] = o1;
+        out[2 * Ns + v] = o2;
+        if (WITH_MAX) {
+            m1 = fmax(m1, fmax(fabs(o0), fmax(fabs(o1), fabs(o2))));
+            m2 = fmax(m2, fmax(fabs(x0), fmax(fabs(x1), fabs(x2))));
+        }
+        if (WITH_DOT) dot += p[v] * o0 + p[Ns + v] * o1 + p[2 * Ns + v] * o2;
+    }
+    if (WITH_MAX) {
+        const double a1 = block_max(m1);
+        const double a2 = block_max(m2);
+        if (threadIdx.x == 0) {
+            partials[2 * blockIdx.x] = a1;
+            partials[2 * blockIdx.x + 1] = a2;
+        }
+    }
+    if (WITH_DOT) {
+        double s[1] = {dot};
+        block_sum<1>(s);
+        if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
+    }
+}
+
+// w = C^T p (links)
+__global__ __launch_bounds__(256) void k_curl_adj(CgArgs A, const double *__restrict__ p,
+                                                  double *__restrict__ w, const int *stop) {
+    if (stop && *stop) return;
+    const int L = A.L;
+    const size_t Ns = A.Ns;
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns;
+         v += (size_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        site_ijk(v, L, i, j, k);
+        const size_t vx = site_index(i == 0 ? L - 1 : i - 1, j, k, L);
+        const size_t vy = site_index(i, j == 0 ? L - 1 : j - 1, k, L);
+        const size_t vz = site_index(i, j, k == 0 ? L - 1 : k - 1, L);
+        const double p0 = p[v], p1 = p[Ns + v], p2 = p[2 * Ns + v];
+        w[v] = (p2 - p[2 * Ns + vy] - p1 + p[Ns + vz]) * A.inv_a;
+        w[Ns + v] = (p0 - p[vz] - p2 + p[2 * Ns + vx]) * A.inv_a;
+        w[2 * Ns + v] = (p1 - p[Ns + vx] - p0 + p[vy]) * A.inv_a;
+    }
+}
+
+// dinv = a^2 / (sum of eta on the 4 links of each plaquette)
+__global__ void k_dinv(CgArgs A, double a2, double *dinv) {
+    const int L = A.L;
+    const size_t Ns = A.Ns;
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns;
+         v += (size_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        site_ijk(v, L, i, j, k);
+        const size_t vx = site_index(i + 1 == L ? 0 : i + 1, j, k, L);
+        const size_t vy = site_index(i, j + 1 == L ? 0 : j + 1, k, L);
+        const size_t vz = site_index(i, j, k + 1 == L ? 0 : k + 1, L);
+        const double *e = A.eta;
+        dinv[v] = a2 / (e[2 * Ns + vy] + e[2 * Ns + v] + e[Ns + vz] + e[Ns + v]);
+        dinv[Ns + v] = a2 / (e[vz] + e[v] + e[2 * Ns + vx] + e[2 * Ns + v]);
+        dinv[2 * Ns + v] = a2 / (e[Ns + vx] + e[Ns + v] + e[vy] + e[v]);
+    }
+}
+
+// z = dinv * r; partial <r, z>
+__global__ __launch_bounds__(256) void k_precond(const double *__restrict__ dinv, const double *__restrict__ r,
+                                                 double *__restrict__ z, size_t M, double *partials) {
+    double s[1] = {0.0};
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < M; t += (size_t)gridDim.x * blockDim.x) {
+        const double zz = dinv[t] * r[t];
+        z[t] = zz;
+        s[0] += r[t] * zz;
+    }
+    block_sum<1>(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
+}
+
+// CG scalar slots (relative to S_CG)
+enum { CG_RZ = 0, CG_ALPHA = 1, CG_BETA = 2, CG_RMAX = 3, CG_DEN = 4, CG_TOL = 5, CG_AINV = 6 };
+
+// alpha = rz / <p, q>; a non-positive curvature stops the sweep (flag 2).
+__global__ void k_cg_alpha(const double *partials, int nblk, double *cg, int *flags) {
+    if (flags[0]) return;
+    double s[1] = {0.0};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s[0] += partials[b];
+    block_sum<1>(s);
+    if (threadIdx.x == 0) {
+        if (!(s[0] > 0.0)) {
+            flags[0] = 2;
+        } else {
+            cg[CG_ALPHA] = cg[CG_RZ] / s[0];
+        }
+    }
+}
+
+// D += alpha w; r -= alpha q; z = dinv r; partials: <r,z>, max|r|
+__global__ __launch_bounds__(256) void k_cg_update(double *__restrict__ D, double *__restrict__ r,
+                                                   double *__restrict__ z, const double *__restrict__ w,
+                                                   const double *__restrict__ q,
+                                                   const double *__restrict__ dinv, size_t M, const double *cg,
+                                                   double *partials, const int *flags) {
+    if (flags[0]) return;
+    const double alpha = cg[CG_ALPHA];
+    double s[1] = {0.0};
+    double mx = 0.0;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < M; t += (size_t)gridDim.x * blockDim.x) {
+        D[t] += alpha * w[t];
+        const double rr = r[t] - alpha * q[t];
+        r[t] = rr;
+        const double zz = dinv[t] * rr;
+        z[t] = zz;
+        s[0] += rr * zz;
+        mx = fmax(mx, fabs(rr));
+    }
+    block_sum<1>(s);
+    const double m = block_max(mx);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s[0];
+        partials[2 * blockIdx.x + 1] = m;
+    }
+}
+
+// beta = rz_new / rz; when the recursive residual passes the test, flag 1.
+__global__ void k_cg_beta(const double *partials, int nblk, double a, double *cg, int *flags, int *iters) {
+    if (flags[0]) return;
+    double s[1] = {0.0};
+    double mx = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        s[0] += partials[2 * b];
+        mx = fmax(mx, partials[2 * b + 1]);
+    }
+    block_sum<1>(s);
+    const double m = block_max(mx);
+    if (threadIdx.x == 0) {
+        cg[CG_BETA] = s[0] / cg[CG_RZ];
+        cg[CG_RZ] = s[0];
+        cg[CG_RMAX] = m;
+        iters[0] += 1;
+        if (a * m <= cg[CG_TOL] * cg[CG_DEN]) flags[0] = 1;
+    }
+}
+
+// p = z + beta p, only for the iteration whose beta was just formed (the
+// iteration counter equals `expected`): this also runs in the iteration where
+// the recursive test passed, so a rejected test continues consistently.
+__global__ void k_cg_p(double *__restrict__ p, const double *__restrict__ z, size_t M, const double *cg,
+                       const int *flags, int expected) {
+    if (flags[0] == 2 || flags[1] != expected) return;
+    const double beta = cg[CG_BETA];
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < M; t += (size_t)gridDim.x * blockDim.x)
+        p[t] = z[t] + beta * p[t];
+}
+
+template <typename T>
+__global__ void k_eta_expand(const T *eta_link, const T *eta_prof, double eta_uni, int mode, int L, size_t Ns,
+                             double *out) {
+    const size_t LL = (size_t)L * L;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < 3 * Ns;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const int d = (int)(t / Ns);
+        const size_t v = t % Ns;
+        double e;
+        if (mode == ETA_UNIFORM) e = eta_uni;
+        else if (mode == ETA_ZPROF) e = (double)eta_prof[d * L + (int)(v / LL)];
+        else e = (double)eta_link[t];
+        out[t] = e;
+    }
+}
+
+__global__ void k_cg_set(double *cg, double den, double tol, int *flags) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        cg[CG_DEN] = den;
+        cg[CG_TOL] = tol;
+        flags[0] = 0;
+    }
+}
+
+__global__ void k_copy(const double *__restrict__ s, double *__restrict__ d, size_t M) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < M; t += (size_t)gridDim.x * blockDim.x)
+        d[t] = s[t];
+}
+
+static int grid_m(size_t M) {
+    size_t b = (M + kThreads - 1) / kThreads;
+    if (b > (size_t)kRedBlocks) b = kRedBlocks;
+    return (int)(b ? b : 1);
+}
+
+memd_status solve_relax(memd_ctx *c, double *D, double tol, int max_iter, int *iters_out, double *res_out) {
+    const size_t Ns = c->Ns, M = 3 * Ns;
+    hipStream_t s = c->stream;
+    double *buf = nullptr;
+    // eta, dinv, r, z, p, w, q, Dbest
+    if (hipMallocAsync((void **)&buf, 8 * M * sizeof(double), s) != hipSuccess) return MEMD_ENOMEM;
+    double *eta = buf, *dinv = buf + M, *r = buf + 2 * M, *z = buf + 3 * M, *p = buf + 4 * M,
+           *w = buf + 5 * M, *q = buf + 6 * M, *Dbest = buf + 7 * M;
+    int *flags = nullptr;
+    if (hipMallocAsync((void **)&flags, 4 * sizeof(int), s) != hipSuccess) {
+        hipFreeAsync(buf, s);
+        return MEMD_ENOMEM;
+    }
+    hipMemsetAsync(flags, 0, 4 * sizeof(int), s);
+    const int g = grid_m(Ns), gm = grid_m(M);
+    if (c->fp32)
+        hipLaunchKernelGGL(k_eta_expand<float>, dim3(gm), dim3(kThreads), 0, s, (const float *)c->eta_link,
+                           (const float *)c->eta_prof, c->eta_uni, c->eta_mode, c->L, Ns, eta);
+    else
+        hipLaunchKernelGGL(k_eta_expand<double>, dim3(gm), dim3(kThreads), 0, s, (const double *)c->eta_link,
+                           (const double *)c->eta_prof, c->eta_uni, c->eta_mode, c->L, Ns, eta);
+    CgArgs A{c->L, Ns, 1.0 / c->a, eta};
+    hipLaunchKernelGGL(k_dinv, dim3(g), dim3(kThreads), 0, s, A, c->a * c->a, dinv);
+    double *cg = c->scal + S_CG;
+    double *part = c->partials;
+
+    memd_status st = MEMD_OK;
+    int it_total = 0, stalls = 0;
+    double best = HUGE_VAL, res = HUGE_VAL;
+    bool first = true, converged = false;
+    const int chunk = 10;
+    for (;;) {
+        // residual replacement: r = -C(eta D) from D; test on the true residual
+        hipLaunchKernelGGL((k_curl_eta<true, false>), dim3(g), dim3(kThreads), 0, s, A, D, -1.0, r, nullptr,
+                           part, nullptr);
+        double h[2 * kRedBlocks];
+        hipMemcpyAsync(h, part, 2 * g * sizeof(double), hipMemcpyDeviceToHost, s);
+        int hf[2] = {0, 0};
+        hipMemcpyAsync(hf, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            st = MEMD_EDEVICE;
+            break;
+        }
+        double rmax = 0.0, den = 0.0;
+        for (int b = 0; b < g; ++b) {
+            rmax = fmax(rmax, h[2 * b]);
+            den = fmax(den, h[2 * b + 1]);
+        }
+        it_total = hf[1];
+        res = den > 0.0 ? c->a * rmax / den : 0.0;
+        if (hf[0] == 1) ++stalls;  // the recursive residual had passed the test
+        if (res <= tol) {
+            converged = true;
+            break;
+        }
+        if (res < best) {
+            best = res;
+            hipLaunchKernelGGL(k_copy, dim3(gm), dim3(kThreads), 0, s, D, Dbest, M);
+        }
+        if (it_total >= max_iter || stalls >= 3 || res > 1e3 * best) {
+            hipLaunchKernelGGL(k_copy, dim3(gm), dim3(kThreads), 0, s, Dbest, D, M);
+            res = best;
+            break;
+        }
+        hipLaunchKernelGGL(k_precond, dim3(gm), dim3(kThreads), 0, s, dinv, r, z, M, part);
+        launch_finalize_sum(s, part, gm, 1, cg + CG_RZ);
+        if (first || hf[0] == 2) {
+            hipLaunchKernelGGL(k_copy, dim3(gm), dim3(kThreads), 0, s, z, p, M);
+            first = false;
+        }
+        hipLaunchKernelGGL(k_cg_set, dim3(1), dim3(64), 0, s, cg, den, tol, flags);
+        for (int t = 0; t < chunk; ++t) {
+            hipLaunchKernelGGL(k_curl_adj, dim3(g), dim3(kThreads), 0, s, A, p, w, flags);
+            hipLaunchKernelGGL((k_curl_eta<false, true>), dim3(g), dim3(kThreads), 0, s, A, w, 1.0, q, p, part,
+                               flags);
+            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kThreads), 0, s, part, g, cg, flags);
+            hipLaunchKernelGGL(k_cg_update, dim3(gm), dim3(kThreads), 0, s, D, r, z, w, q, dinv, M, cg, part,
+                               flags);
+            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(kThreads), 0, s, part, gm, c->a, cg, flags, flags + 1);
+            hipLaunchKernelGGL(k_cg_p, dim3(gm), dim3(kThreads), 0, s, p, z, M, cg, flags, it_total + t + 1);
+        }
+        if (hipGetLastError() != hipSuccess) {
+            st = MEMD_EDEVICE;
+            break;
+        }
+    }
+    hipFreeAsync(flags, s);
+    hipFreeAsync(buf, s);
+    if (hipStreamSynchronize(s) != hipSuccess) st = MEMD_EDEVICE;
+    if (iters_out) *iters_out = it_total;
+    if (res_out) *res_out = res;
+    if (st == MEMD_OK && !converged) st = MEMD_ENOCONV;
+    return st;
+}
+
+// ------------------------------------------------------- Green's function
+
+// G(n) = (1/Ns) sum_{k != 0} cos(k.n) / sum_d 4 sin^2(k_d/2), k = 2 pi m / L,
+// at n = (0,0,0), (1,0,0), (1,1,0), (1,1,1).
+__global__ __launch_bounds__(256) void k_greens(int L, double *partials) {
+    const size_t Ns = (size_t)L * L * L;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    const double pi = 3.14159265358979323846;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < Ns; t += (size_t)gridDim.x * blockDim.x) {
+        if (t == 0) continue;
+        const int mx = (int)(t % L), my = (int)((t / L) % L), mz = (int)(t / ((size_t)L * L));
+        const double hx = sin(pi * mx / L), hy = sin(pi * my / L), hz = sin(pi * mz / L);
+        const double inv = 1.0 / (4.0 * hx * hx + 4.0 * hy * hy + 4.0 * hz * hz);
+        const double cx = cos(2.0 * pi * mx / L), cy = cos(2.0 * pi * my / L), cz = cos(2.0 * pi * mz / L);
+        s[0] += inv;
+        s[1] += cx * inv;
+        s[2] += cx * cy * inv;
+        s[3] += cx * cy * cz * inv;
+    }
+    block_sum<4>(s);
+    if (threadIdx.x == 0)
+        for (int w = 0; w < 4; ++w) partials[4 * blockIdx.x + w] = s[w];
+}
+
+__global__ void k_greens_fin(const double *partials, int nblk, double Ns, double *G) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+        for (int w = 0; w < 4; ++w) s[w] += partials[4 * b + w];
+    block_sum<4>(s);
+    if (threadIdx.x == 0)
+        for (int w = 0; w < 4; ++w) G[w] = s[w] / Ns;
+}
+
+hipError_t launch_greens(memd_ctx *c, double *G) {
+    const int g = grid_m(c->Ns);
+    hipLaunchKernelGGL(k_greens, dim3(g), dim3(kThreads), 0, c->stream, c->L, c->partials);
+    hipLaunchKernelGGL(k_greens_fin, dim3(1), dim3(kThreads), 0, c->stream, c->partials, g, (double)c->Ns, G);
+    return hipGetLastError();
+}
+
+}  // namespace memd

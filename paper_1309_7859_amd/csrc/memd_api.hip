@@ -1,0 +1,630 @@
+// memd_api.hip -- the C-ABI of libmemd: context life cycle, argument checks,
+// buffer ownership, stream ordering and the per-step launch sequence.  Every
+// computation runs in the kernels of kernels_*.hip; this file only moves
+// inputs and outputs and enqueues launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "memd_internal.hpp"
+
+using namespace memd;
+
+namespace {
+
+constexpr int kHistCap = 4096;
+
+#define CK(expr)                                  \
+    do {                                          \
+        hipError_t _e = (expr);                   \
+        if (_e != hipSuccess) {                   \
+            c->poisoned = true;                   \
+            return MEMD_EDEVICE;                  \
+        }                                         \
+    } while (0)
+
+#define CHECK_CTX(c)                              \
+    do {                                          \
+        if (!(c)) return MEMD_EINVAL;             \
+        if ((c)->poisoned) return MEMD_EDEVICE;   \
+        if (hipSetDevice((c)->device) != hipSuccess) return MEMD_EDEVICE; \
+    } while (0)
+
+bool is_device_ptr(const void *p) {
+    hipPointerAttribute_t at;
+    hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice;
+}
+
+// Copy bytes from a host or device pointer into device memory, in stream
+// order, and wait so that the caller may reuse a host buffer at once.
+hipError_t copy_in(memd_ctx *c, void *dst, const void *src, size_t bytes) {
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, c->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(c->stream);
+}
+
+hipError_t copy_out(memd_ctx *c, void *dst, const void *src, size_t bytes) {
+    if (bytes == 0) return hipStreamSynchronize(c->stream);
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, c->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(c->stream);
+}
+
+hipError_t ensure_stage(memd_ctx *c, size_t bytes) {
+    if (c->stage_bytes >= bytes) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return e;
+    if (c->stage) hipFree(c->stage);
+    c->stage = nullptr;
+    c->stage_bytes = 0;
+    e = hipMalloc((void **)&c->stage, bytes);
+    if (e != hipSuccess) return e;
+    c->stage_bytes = bytes;
+    return hipSuccess;
+}
+
+void prof_begin(memd_ctx *c, int fam) {
+    if (!c->prof_on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) == hipSuccess) {
+        hipEventRecord(e, c->stream);
+        c->prof[fam].start.push_back(e);
+    }
+}
+
+void prof_end(memd_ctx *c, int fam) {
+    if (!c->prof_on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) == hipSuccess) {
+        hipEventRecord(e, c->stream);
+        c->prof[fam].stop.push_back(e);
+    }
+}
+
+void prof_clear(memd_ctx *c) {
+    for (int f = 0; f < F_NFAM; ++f) {
+        for (auto e : c->prof[f].start) hipEventDestroy(e);
+        for (auto e : c->prof[f].stop) hipEventDestroy(e);
+        c->prof[f].start.clear();
+        c->prof[f].stop.clear();
+    }
+}
+
+double courant(const memd_ctx *c) {
+    return c->c * c->dt * std::sqrt(3.0) / (c->a * std::sqrt(c->eps_min));
+}
+
+size_t partial_doubles(int n) {
+    const size_t ion_blocks = (size_t)((n + kThreads - 1) / kThreads + 1);
+    return (size_t)kRedBlocks * 8 + ion_blocks * 4;
+}
+
+double *ion_partials(memd_ctx *c) { return c->partials + (size_t)kRedBlocks * 4; }
+
+// Read eps_h and the largest eta back, fix c on first use, check Courant.
+memd_status finish_permittivity(memd_ctx *c) {
+    double h[4];
+    CK(hipMemcpyAsync(h, c->scal + S_EPSH, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CK(hipMemcpyAsync(h + 3, c->scal + S_ETAMAX, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CK(hipStreamSynchronize(c->stream));
+    c->eps_h[0] = h[0];
+    c->eps_h[1] = h[1];
+    c->eps_h[2] = h[2];
+    c->eps_min = 1.0 / h[3];
+    if (!c->c_fixed) {
+        c->c = 0.25 * (c->a / c->dt) * std::sqrt(c->eps_min / 3.0);
+        c->c_fixed = true;
+    }
+    if (!(courant(c) < 1.0)) return MEMD_EUNSTABLE;
+    return MEMD_OK;
+}
+
+memd_status refresh_eta(memd_ctx *c) {
+    int nb = 0;
+    CK(launch_eta_sums(c, c->partials, &nb));
+    CK(launch_finalize_epsh(c->stream, c->partials, nb, (double)c->Ns, c->scal + S_EPSH, c->scal + S_ETAMAX));
+    return finish_permittivity(c);
+}
+
+memd_status ensure_eta_link(memd_ctx *c) {
+    if (c->eta_link) return MEMD_OK;
+    CK(hipMalloc(&c->eta_link, 3 * c->Ns * c->tsize));
+    return MEMD_OK;
+}
+
+// Energy of the current state into dst (and hist when given).
+hipError_t enqueue_energy(memd_ctx *c, double *dst, double *hist) {
+    hipError_t e;
+    int fb = 0, ib = 0;
+    prof_begin(c, F_ENERGY);
+    if ((e = launch_energy_field(c, c->D[c->cur], c->B[c->cur], c->partials, &fb)) != hipSuccess) return e;
+    if ((e = launch_uself(c, ion_partials(c), &ib)) != hipSuccess) return e;
+    e = launch_finalize_energy(c, c->partials, fb, ion_partials(c), ib, dst, hist);
+    prof_end(c, F_ENERGY);
+    return e;
+}
+
+// Gauss audit of the current state (rho must already hold the assignment).
+hipError_t enqueue_audit(memd_ctx *c, double *hist) {
+    hipError_t e;
+    int nb = 0;
+    prof_begin(c, F_AUDIT);
+    if ((e = launch_audit(c, c->D[c->cur], c->partials, &nb)) != hipSuccess) return e;
+    e = launch_finalize_audit(c->stream, c->partials, nb, (double)c->Ns, c->scal + S_AUDIT, hist);
+    prof_end(c, F_AUDIT);
+    return e;
+}
+
+hipError_t enqueue_dipole_forces(memd_ctx *c) {
+    hipError_t e;
+    int nb = 0;
+    prof_begin(c, F_DIPOLE);
+    if ((e = launch_dipole(c, c->partials, &nb)) != hipSuccess) return e;
+    if ((e = launch_finalize_dipole(c->stream, c->partials, nb, c->scal + S_P)) != hipSuccess) return e;
+    prof_end(c, F_DIPOLE);
+    prof_begin(c, F_FORCES);
+    e = launch_forces(c, c->D[c->cur]);
+    prof_end(c, F_FORCES);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int memd_version(void) { return 1; }
+
+const char *memd_strerror(memd_status s) {
+    switch (s) {
+        case MEMD_OK: return "ok";
+        case MEMD_EINVAL: return "invalid argument";
+        case MEMD_ENOMEM: return "device allocation failed";
+        case MEMD_ENONNEUTRAL: return "charges are not neutral";
+        case MEMD_EUNSTABLE: return "Courant number c dt sqrt(3)/(a sqrt(eps_min)) >= 1";
+        case MEMD_ESTATE: return "call out of order";
+        case MEMD_ENOCONV: return "relaxation did not converge";
+        case MEMD_EDEVICE: return "HIP device error";
+    }
+    return "unknown status";
+}
+
+void memd_destroy(memd_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    prof_clear(c);
+    void *bufs[] = {c->D[0], c->D[1], c->B[0], c->B[1], c->eta_prof, c->eta_link, c->q, c->r, c->F,
+                    c->stage, c->rho, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt,
+                    c->salt_nbar};
+    for (void *b : bufs)
+        if (b) hipFree(b);
+    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const double *q, const double *r0,
+                              void *hip_stream) {
+    if (!out || !p) return MEMD_EINVAL;
+    *out = nullptr;
+    if (p->L < 2 || !(p->a > 0.0) || !(p->dt > 0.0) || n < 0 ||
+        (p->precision != MEMD_FP64 && p->precision != MEMD_FP32_MIXED) || p->audit_every < 0 ||
+        p->energy_every < 0 || !std::isfinite(p->a) || !std::isfinite(p->dt) || !std::isfinite(p->c))
+        return MEMD_EINVAL;
+    if (n > 0 && (!q || !r0)) return MEMD_EINVAL;
+    const size_t Ns = (size_t)p->L * p->L * p->L;
+    if (p->L > 2048) return MEMD_EINVAL;
+
+    memd_ctx *c = new (std::nothrow) memd_ctx();
+    if (!c) return MEMD_ENOMEM;
+    c->p = *p;
+    c->n = n;
+    c->L = p->L;
+    c->Ns = Ns;
+    c->a = p->a;
+    c->dt = p->dt;
+    c->V = std::pow(p->L * p->a, 3);
+    c->fp32 = p->precision == MEMD_FP32_MIXED;
+    c->tsize = c->fp32 ? sizeof(float) : sizeof(double);
+    c->lf_rows = 2;
+    c->lf_tz = 16;
+    c->hist_cap = kHistCap;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return MEMD_EDEVICE;
+    }
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+        c->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return MEMD_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+
+    auto fail = [&](memd_status s) {
+        memd_destroy(c);
+        return s;
+    };
+
+    // neutrality (needs the charges on the host)
+    std::vector<double> hq((size_t)n);
+    if (n > 0) {
+        if (hipMemcpy(hq.data(), q, (size_t)n * sizeof(double), hipMemcpyDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MEMD_EINVAL);
+        }
+        double s = 0.0, sa = 0.0;
+        for (double x : hq) {
+            if (!std::isfinite(x)) return fail(MEMD_EINVAL);
+            s += x;
+            sa += std::fabs(x);
+        }
+        if (std::fabs(s) > 1e-12 * sa) return fail(MEMD_ENONNEUTRAL);
+    }
+
+    const size_t fb = 3 * Ns * c->tsize;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    if (hipMalloc(&c->D[0], fb) != hipSuccess || hipMalloc(&c->D[1], fb) != hipSuccess ||
+        hipMalloc(&c->B[0], fb) != hipSuccess || hipMalloc(&c->B[1], fb) != hipSuccess ||
+        hipMalloc(&c->eta_prof, 3 * (size_t)c->L * c->tsize) != hipSuccess ||
+        hipMalloc((void **)&c->q, nn * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->r, 3 * nn * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->F, 3 * nn * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->rho, Ns * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->partials, partial_doubles(n) * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->scal, S_COUNT * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->hist_audit, 2 * (size_t)kHistCap * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->hist_energy, 5 * (size_t)kHistCap * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MEMD_ENOMEM);
+    }
+    hipStream_t s = c->stream;
+    for (int b = 0; b < 2; ++b) {
+        hipMemsetAsync(c->D[b], 0, fb, s);
+        hipMemsetAsync(c->B[b], 0, fb, s);
+    }
+    hipMemsetAsync(c->rho, 0, Ns * sizeof(double), s);
+    hipMemsetAsync(c->scal, 0, S_COUNT * sizeof(double), s);
+    hipMemsetAsync(c->F, 0, 3 * nn * sizeof(double), s);
+    if (n > 0) {
+        if (copy_in(c, c->q, q, (size_t)n * sizeof(double)) != hipSuccess ||
+            copy_in(c, c->r, r0, 3 * (size_t)n * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MEMD_EINVAL);
+        }
+    }
+    // permittivity 1 everywhere until set
+    c->eta_mode = ETA_UNIFORM;
+    c->eta_uni = 1.0;
+    c->eps_min = 1.0;
+    c->c = p->c;
+    c->c_fixed = p->c > 0.0;
+    if (launch_greens(c, c->scal + S_G) != hipSuccess) return fail(MEMD_EDEVICE);
+    memd_status st = refresh_eta(c);
+    if (st == MEMD_EDEVICE) return fail(st);
+    if (!c->c_fixed) c->c = 0.25 * (c->a / c->dt) * std::sqrt(1.0 / 3.0);
+    c->c_fixed = p->c > 0.0;  // a default c is chosen again at the first memd_set_permittivity
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(MEMD_EDEVICE);
+    *out = c;
+    return MEMD_OK;
+}
+
+memd_status memd_set_permittivity(memd_ctx *c, int mode, const double *eps, double ratio) {
+    CHECK_CTX(c);
+    if (!eps) return MEMD_EINVAL;
+    if (!(ratio > 0.0)) ratio = 4.0;
+    size_t count;
+    switch (mode) {
+        case MEMD_EPS_UNIFORM: count = 1; break;
+        case MEMD_EPS_SITE: count = c->Ns; break;
+        case MEMD_EPS_LINK: count = 3 * c->Ns; break;
+        case MEMD_EPS_ZSITE: count = (size_t)c->L; break;
+        default: return MEMD_EINVAL;
+    }
+    std::vector<double> h(count);
+    if (hipMemcpy(h.data(), eps, count * sizeof(double), hipMemcpyDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return MEMD_EINVAL;
+    }
+    for (double x : h)
+        if (!(x > 0.0) || !std::isfinite(x)) return MEMD_EINVAL;
+    c->salt_every = 0;
+    if (mode == MEMD_EPS_UNIFORM) {
+        c->eta_mode = ETA_UNIFORM;
+        c->eta_uni = 1.0 / h[0];
+    } else {
+        CK(ensure_stage(c, count * sizeof(double)));
+        CK(copy_in(c, c->stage, h.data(), count * sizeof(double)));
+        if (mode == MEMD_EPS_ZSITE) {
+            CK(launch_eta_zprof(c, c->stage, ratio, c->eta_prof));
+            c->eta_mode = ETA_ZPROF;
+        } else {
+            memd_status st = ensure_eta_link(c);
+            if (st != MEMD_OK) return st;
+            if (mode == MEMD_EPS_SITE)
+                CK(launch_eta_from_site(c, c->stage, ratio, c->eta_link));
+            else
+                CK(launch_eta_from_link(c, c->stage, c->eta_link));
+            c->eta_mode = ETA_LINK;
+        }
+    }
+    return refresh_eta(c);
+}
+
+memd_status memd_set_salt_permittivity(memd_ctx *c, double eps_w, double slope, double eps_floor, int every) {
+    CHECK_CTX(c);
+    if (!(eps_w > 0.0) || !(eps_floor > 0.0) || every < 0 || !std::isfinite(slope)) return MEMD_EINVAL;
+    memd_status st = ensure_eta_link(c);
+    if (st != MEMD_OK) return st;
+    if (!c->salt_cnt) {
+        CK(hipMalloc((void **)&c->salt_cnt, c->Ns * sizeof(double)));
+        CK(hipMalloc((void **)&c->salt_nbar, c->Ns * sizeof(double)));
+    }
+    c->salt_w = eps_w;
+    c->salt_slope = slope;
+    c->salt_floor = eps_floor;
+    c->eta_mode = ETA_LINK;
+    CK(launch_salt(c));
+    st = finish_permittivity(c);
+    c->salt_every = every;
+    return st;
+}
+
+memd_status memd_initial_gauss_solve(memd_ctx *c, double tol, int max_iter, int *iters_out, double *res_out) {
+    CHECK_CTX(c);
+    if (!(tol > 0.0)) tol = 1e-13;
+    if (max_iter <= 0) max_iter = 1000000;
+    if (!c->c_fixed) {
+        c->c = 0.25 * (c->a / c->dt) * std::sqrt(c->eps_min / 3.0);
+        c->c_fixed = true;
+    }
+    if (!(courant(c) < 1.0)) return MEMD_EUNSTABLE;
+    const size_t M = 3 * c->Ns;
+    double *Dw = nullptr;
+    if (c->fp32) {
+        CK(hipMallocAsync((void **)&Dw, M * sizeof(double), c->stream));
+    } else {
+        Dw = (double *)c->D[c->cur];
+    }
+    CK(solve_recursion(c, Dw));
+    CK(solve_mean_shift(c, Dw));
+    memd_status st = solve_relax(c, Dw, tol, max_iter, iters_out, res_out);
+    if (st == MEMD_EDEVICE || st == MEMD_ENOMEM) {
+        if (st == MEMD_EDEVICE) c->poisoned = true;
+        return st;
+    }
+    if (c->fp32) {
+        CK(launch_cast(c->stream, Dw, c->D[c->cur], M, true));
+        CK(hipFreeAsync(Dw, c->stream));
+    }
+    CK(hipMemsetAsync(c->B[c->cur], 0, M * c->tsize, c->stream));
+    CK(enqueue_dipole_forces(c));
+    CK(hipStreamSynchronize(c->stream));
+    c->ready = true;
+    c->step_index = 0;
+    return st;
+}
+
+memd_status memd_step(memd_ctx *c, const double *disp, int nsteps) {
+    CHECK_CTX(c);
+    if (!c->ready) return MEMD_ESTATE;
+    if (nsteps < 0) return MEMD_EINVAL;
+    if (nsteps == 0) return MEMD_OK;
+    if (c->n > 0 && !disp) return MEMD_EINVAL;
+    const size_t per = 3 * (size_t)c->n;
+    const double *dd = disp;
+    if (c->n > 0 && !is_device_ptr(disp)) {
+        CK(ensure_stage(c, per * nsteps * sizeof(double)));
+        CK(copy_in(c, c->stage, disp, per * nsteps * sizeof(double)));
+        dd = c->stage;
+    }
+    for (int t = 0; t < nsteps; ++t) {
+        if (c->salt_every > 0 && c->step_index % c->salt_every == 0) {
+            prof_begin(c, F_SALT);
+            CK(launch_salt(c));
+            prof_end(c, F_SALT);
+        }
+        const int nx = c->cur ^ 1;
+        prof_begin(c, F_LEAPFROG);
+        CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx]));
+        prof_end(c, F_LEAPFROG);
+        const long next = c->step_index + 1;
+        const bool audit_now = c->p.audit_every > 0 && next % c->p.audit_every == 0;
+        const bool energy_now = c->p.energy_every > 0 && next % c->p.energy_every == 0;
+        int nb = 0;
+        prof_begin(c, F_DEPOSIT);
+        CK(launch_deposit(c, c->D[nx], dd + per * t, audit_now, c->partials, &nb));
+        CK(launch_finalize_dipole(c->stream, c->partials, nb, c->scal + S_P));
+        prof_end(c, F_DEPOSIT);
+        c->cur = nx;
+        prof_begin(c, F_FORCES);
+        CK(launch_forces(c, c->D[c->cur]));
+        prof_end(c, F_FORCES);
+        if (audit_now) {
+            const int slot = c->hist_audit_n < c->hist_cap ? c->hist_audit_n : c->hist_cap - 1;
+            CK(enqueue_audit(c, c->hist_audit + 2 * (size_t)slot));
+            if (c->hist_audit_n < c->hist_cap) ++c->hist_audit_n;
+        }
+        if (energy_now) {
+            const int slot = c->hist_energy_n < c->hist_cap ? c->hist_energy_n : c->hist_cap - 1;
+            CK(enqueue_energy(c, c->scal + S_ENERGY, c->hist_energy + 5 * (size_t)slot));
+            if (c->hist_energy_n < c->hist_cap) ++c->hist_energy_n;
+        }
+        c->step_index = next;
+    }
+    if (dd != disp) CK(hipStreamSynchronize(c->stream));  // the staging buffer is reused
+    return MEMD_OK;
+}
+
+memd_status memd_forces(memd_ctx *c, double *F_out) {
+    CHECK_CTX(c);
+    if (!F_out && c->n > 0) return MEMD_EINVAL;
+    if (!c->ready) return MEMD_ESTATE;
+    CK(copy_out(c, F_out, c->F, 3 * (size_t)c->n * sizeof(double)));
+    return MEMD_OK;
+}
+
+memd_status memd_energy(memd_ctx *c, memd_energy_t *out) {
+    CHECK_CTX(c);
+    if (!out) return MEMD_EINVAL;
+    CK(enqueue_energy(c, c->scal + S_ENERGY, nullptr));
+    double h[5];
+    CK(copy_out(c, h, c->scal + S_ENERGY, 5 * sizeof(double)));
+    out->W_E = h[0];
+    out->W_B = h[1];
+    out->U_self = h[2];
+    out->U_dip = h[3];
+    out->E_corrected = h[4];
+    return MEMD_OK;
+}
+
+memd_status memd_gauss_residual(memd_ctx *c, double *max_abs, double *rms) {
+    CHECK_CTX(c);
+    CK(launch_spread(c, c->q, c->rho));
+    CK(enqueue_audit(c, nullptr));
+    double h[2];
+    CK(copy_out(c, h, c->scal + S_AUDIT, 2 * sizeof(double)));
+    if (max_abs) *max_abs = h[0];
+    if (rms) *rms = h[1];
+    return MEMD_OK;
+}
+
+memd_status memd_dipole(memd_ctx *c, double P[3]) {
+    CHECK_CTX(c);
+    if (!P) return MEMD_EINVAL;
+    int nb = 0;
+    CK(launch_dipole(c, c->partials, &nb));
+    CK(launch_finalize_dipole(c->stream, c->partials, nb, c->scal + S_P));
+    CK(copy_out(c, P, c->scal + S_P, 3 * sizeof(double)));
+    return MEMD_OK;
+}
+
+memd_status memd_history(memd_ctx *c, double *audit, double *energy, int max_entries, int *audit_count,
+                         int *energy_count) {
+    CHECK_CTX(c);
+    const int na = c->hist_audit_n, ne = c->hist_energy_n;
+    if (audit_count) *audit_count = na;
+    if (energy_count) *energy_count = ne;
+    if (audit && max_entries > 0) {
+        const int k = na < max_entries ? na : max_entries;
+        CK(copy_out(c, audit, c->hist_audit, 2 * (size_t)k * sizeof(double)));
+    }
+    if (energy && max_entries > 0) {
+        const int k = ne < max_entries ? ne : max_entries;
+        CK(copy_out(c, energy, c->hist_energy, 5 * (size_t)k * sizeof(double)));
+    }
+    if (audit || energy) {
+        c->hist_audit_n = 0;
+        c->hist_energy_n = 0;
+    }
+    return MEMD_OK;
+}
+
+memd_status memd_get_state(memd_ctx *c, double *D, double *B, double *r) {
+    CHECK_CTX(c);
+    const size_t M = 3 * c->Ns;
+    if (D || B) CK(ensure_stage(c, M * sizeof(double)));
+    if (D) {
+        CK(launch_uncast(c->stream, c->D[c->cur], c->stage, M, c->fp32));
+        CK(copy_out(c, D, c->stage, M * sizeof(double)));
+    }
+    if (B) {
+        CK(launch_uncast(c->stream, c->B[c->cur], c->stage, M, c->fp32));
+        CK(copy_out(c, B, c->stage, M * sizeof(double)));
+    }
+    if (r) CK(copy_out(c, r, c->r, 3 * (size_t)c->n * sizeof(double)));
+    return MEMD_OK;
+}
+
+memd_status memd_set_state(memd_ctx *c, const double *D, const double *B, const double *r) {
+    CHECK_CTX(c);
+    const size_t M = 3 * c->Ns;
+    if (D || B) CK(ensure_stage(c, M * sizeof(double)));
+    if (D) {
+        CK(copy_in(c, c->stage, D, M * sizeof(double)));
+        CK(launch_cast(c->stream, c->stage, c->D[c->cur], M, c->fp32));
+    }
+    if (B) {
+        CK(hipStreamSynchronize(c->stream));
+        CK(copy_in(c, c->stage, B, M * sizeof(double)));
+        CK(launch_cast(c->stream, c->stage, c->B[c->cur], M, c->fp32));
+    }
+    if (r) CK(copy_in(c, c->r, r, 3 * (size_t)c->n * sizeof(double)));
+    if (!c->c_fixed) {
+        c->c = 0.25 * (c->a / c->dt) * std::sqrt(c->eps_min / 3.0);
+        c->c_fixed = true;
+    }
+    CK(enqueue_dipole_forces(c));
+    CK(hipStreamSynchronize(c->stream));
+    c->ready = true;
+    return MEMD_OK;
+}
+
+memd_status memd_get_stream(memd_ctx *c, void **stream) {
+    CHECK_CTX(c);
+    if (!stream) return MEMD_EINVAL;
+    *stream = (void *)c->stream;
+    return MEMD_OK;
+}
+
+memd_status memd_get_params(memd_ctx *c, double *cc, double eps_h[3], double *eps_min) {
+    CHECK_CTX(c);
+    if (cc) *cc = c->c;
+    if (eps_h) {
+        double h[3];
+        CK(copy_out(c, h, c->scal + S_EPSH, 3 * sizeof(double)));
+        eps_h[0] = h[0];
+        eps_h[1] = h[1];
+        eps_h[2] = h[2];
+    }
+    if (eps_min) *eps_min = c->eps_min;
+    return MEMD_OK;
+}
+
+memd_status memd_profile_enable(memd_ctx *c, int enable) {
+    CHECK_CTX(c);
+    CK(hipStreamSynchronize(c->stream));
+    prof_clear(c);
+    c->prof_on = enable != 0;
+    return MEMD_OK;
+}
+
+memd_status memd_profile_read(memd_ctx *c, int family, double *total_ms, long *launches) {
+    CHECK_CTX(c);
+    if (family < 0 || family >= F_NFAM) return MEMD_EINVAL;
+    CK(hipStreamSynchronize(c->stream));
+    const auto &P = c->prof[family];
+    const size_t m = P.start.size() < P.stop.size() ? P.start.size() : P.stop.size();
+    double tot = 0.0;
+    for (size_t t = 0; t < m; ++t) {
+        float ms = 0.0f;
+        CK(hipEventElapsedTime(&ms, P.start[t], P.stop[t]));
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (long)m;
+    return MEMD_OK;
+}
+
+memd_status memd_set_tiling(memd_ctx *c, int rows, int planes) {
+    CHECK_CTX(c);
+    if (rows != 0 && rows != 1 && rows != 2 && rows != 4) return MEMD_EINVAL;
+    if (planes < 0) return MEMD_EINVAL;
+    if (rows) c->lf_rows = rows;
+    if (planes) c->lf_tz = planes;
+    return MEMD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// memd_internal.hpp -- context layout and launch interfaces shared by the
+// translation units of libmemd (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/memd.h"
+
+namespace memd {
+
+// Offsets into the per-context device scalar block (FP64).
+enum ScalarSlot : int {
+    S_P = 0,        // dipole moment P[3]
+    S_EPSH = 3,     // directional harmonic means eps_h[3]
+    S_G = 6,        // lattice Green's function G[4] at (000),(100),(110),(111)
+    S_AUDIT = 10,   // last audit: max, rms
+    S_ENERGY = 12,  // last energy: 5 values
+    S_CG = 20,      // conjugate-gradient scalars (20 slots)
+    S_MEAN = 40,    // mean of D per direction [3]
+    S_ETAMAX = 44,  // maximum eta over the links (1 / eps_min)
+    S_COUNT = 64
+};
+
+enum EtaMode : int { ETA_UNIFORM = 0, ETA_ZPROF = 1, ETA_LINK = 2 };
+
+enum Family : int {
+    F_LEAPFROG = 0, F_DEPOSIT = 1, F_FORCES = 2, F_AUDIT = 3, F_ENERGY = 4, F_DIPOLE = 5,
+    F_SALT = 6, F_NFAM = 7
+};
+
+constexpr int kRedBlocks = 1024;   // grid of the site-loop reductions
+constexpr int kThreads = 256;      // threads per block of the plain kernels
+
+struct EtaDesc {
+    int mode;
+    double uni;            // ETA_UNIFORM
+    const void *prof;      // ETA_ZPROF: T[3*L]: eta_x(k), eta_y(k), eta_z(k)
+    const void *link;      // ETA_LINK:  T[3*Ns]
+};
+
+struct ProfileEvents {
+    std::vector<hipEvent_t> start, stop;
+};
+
+}  // namespace memd
+
+struct memd_ctx {
+    memd_params p;
+    int n;
+    int L;
+    size_t Ns;
+    double a, dt, c, V;
+    bool fp32;
+    size_t tsize;  // sizeof(T) of the field storage
+
+    hipStream_t stream;
+    bool own_stream;
+    int device;
+
+    // permittivity
+    int eta_mode;
+    double eta_uni;
+    void *eta_prof;   // T[3L]
+    void *eta_link;   // T[3Ns]
+    double eps_h[3];
+    double eps_min;
+    bool c_fixed;
+    int salt_every;
+    double salt_w, salt_slope, salt_floor;
+    double *salt_cnt;   // FP64 [Ns] work for the salt permittivity
+    double *salt_nbar;  // FP64 [Ns]
+
+    // fields: ping-pong buffers, cur holds the live state
+    void *D[2];
+    void *B[2];
+    int cur;
+
+    // ions
+    double *q;     // [n]
+    double *r;     // [3n]
+    double *F;     // [3n]
+    double *stage;       // FP64 staging buffer for host inputs / FP32 casts
+    size_t stage_bytes;
+
+    // reductions and audit
+    double *rho;       // FP64 [Ns], kept all-zero between uses
+    double *partials;  // FP64 [kRedBlocks * 8]
+    double *scal;      // FP64 [S_COUNT]
+    double *hist_audit;   // FP64 [2*hist_cap]
+    double *hist_energy;  // FP64 [5*hist_cap]
+    int hist_cap;
+    int hist_audit_n, hist_energy_n;
+
+    bool ready;      // initial solve done or state set
+    bool poisoned;
+    long step_index;
+
+    // leapfrog tiling
+    int lf_rows;
+    int lf_tz;
+
+    // profiling
+    bool prof_on;
+    memd::ProfileEvents prof[memd::F_NFAM];
+};
+
+namespace memd {
+
+// ---- launchers (field kernels) ----
+hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout);
+hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
+                               int *nblk);
+hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk);
+hipError_t launch_cast(hipStream_t s, const double *src, void *dst, size_t count, bool to_fp32);
+hipError_t launch_uncast(hipStream_t s, const void *src, double *dst, size_t count, bool from_fp32);
+hipError_t launch_eta_from_link(memd_ctx *c, const double *eps_link, void *eta_link);
+hipError_t launch_eta_from_site(memd_ctx *c, const double *eps_site, double ratio, void *eta_link);
+hipError_t launch_eta_zprof(memd_ctx *c, const double *eps_z, double ratio, void *prof);
+hipError_t launch_eta_sums(memd_ctx *c, double *partials, int *nblk);
+hipError_t launch_salt(memd_ctx *c);
+hipError_t launch_fill(hipStream_t s, double *dst, double v, size_t count);
+
+// ---- launchers (ion kernels) ----
+hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_rho,
+                          double *partials, int *nblk);
+hipError_t launch_spread(memd_ctx *c, const double *charges_or_null, double *dst);
+hipError_t launch_dipole(memd_ctx *c, double *partials, int *nblk);
+hipError_t launch_forces(memd_ctx *c, const void *D);
+hipError_t launch_uself(memd_ctx *c, double *partials, int *nblk);
+
+// ---- launchers (reductions / finalisers) ----
+// Sum `width` doubles per block over nblk partial blocks into dst[width] (fixed order).
+hipError_t launch_finalize_sum(hipStream_t s, const double *partials, int nblk, int width,
+                               double *dst);
+// Audit finaliser: partials hold (max, sumsq) per block -> dst = (max, rms); also appends.
+hipError_t launch_finalize_audit(hipStream_t s, const double *partials, int nblk, double Ns,
+                                 double *dst, double *hist);
+// Energy finaliser: field partials (we, wb) + ion partials (uself) -> 5 energies.
+hipError_t launch_finalize_energy(memd_ctx *c, const double *fpart, int fblk,
+                                  const double *ipart, int iblk, double *dst, double *hist);
+hipError_t launch_finalize_dipole(hipStream_t s, const double *partials, int nblk,
+                                  double *P);
+hipError_t launch_finalize_epsh(hipStream_t s, const double *partials, int nblk, double Ns,
+                                double *epsh, double *etamax);
+hipError_t launch_greens(memd_ctx *c, double *G);
+
+// ---- initial solve (FP64) ----
+hipError_t solve_recursion(memd_ctx *c, double *D);
+hipError_t solve_mean_shift(memd_ctx *c, double *D);
+memd_status solve_relax(memd_ctx *c, double *D, double tol, int max_iter, int *iters,
+                        double *res);
+
+
+}  // namespace memd

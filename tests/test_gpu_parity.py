@@ -1,0 +1,297 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Step parity starts from a shared state (the oracle's initial solution is
+uploaded with memd_set_state), so solver termination differences do not enter
+the step path; the initial solve is compared separately.  Tolerances: forces
+max|dF| / RMS|F| <= 1e-10 (FP64), 1e-4 (FP32); Gauss residual <= 1e-12
+(FP64), 1e-5 max|q| (FP32); energies relative 1e-10 (FP64); dipole 1e-12.
+"""
+import numpy as np
+import pytest
+
+from paper_1309_7859_amd import memd
+from paper_1309_7859_amd import workloads as W
+from tests.gpu_helpers import (apply_eps, energy_err, force_err, pair, rel, require_gpu,
+                               share_state)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _rng_system(seed, n, L, valence2=False):
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0, L, size=(n, 3))
+    q = np.array([1.0 if i % 2 == 0 else -1.0 for i in range(n)])
+    if valence2:
+        q[:2] *= 2
+    return rng, q, r
+
+
+# ------------------------------------------------------------ initial solve
+
+@pytest.mark.parametrize("case", ["c1", "site12", "zsite16", "link10"])
+def test_initial_solve_parity(case):
+    if case == "c1":
+        w = W.WORKLOADS["c1"]
+        s = W.make_system(w, steps=0)
+        q, r, L = s["q"], s["r0"], w.L
+        S, G = pair(L, q, r)
+        apply_eps(S, G, "uniform", 1.0)
+    elif case == "site12":
+        L = 12
+        rng, q, r = _rng_system(5, 10, L, True)
+        eps = 2.0 + 60.0 * rng.uniform(size=L ** 3) ** 2
+        S, G = pair(L, q, r, eps_min=eps.min())
+        apply_eps(S, G, "site", eps_site=eps)
+    elif case == "zsite16":
+        L = 16
+        rng, q, r = _rng_system(6, 12, L)
+        ez = W.tanh_slab(L, 1.0)
+        S, G = pair(L, q, r, eps_min=ez.min())
+        apply_eps(S, G, "zsite", eps_z=ez)
+    else:
+        L = 10
+        rng, q, r = _rng_system(7, 8, L)
+        el = 1.0 + 9.0 * rng.uniform(size=3 * L ** 3)
+        S, G = pair(L, q, r, eps_min=el.min())
+        apply_eps(S, G, "link", eps_link=el)
+    rc, it, res = S.initial_solve(1e-13)
+    assert rc == 0
+    st, git, gres = G.solve(1e-13)
+    assert st == memd.OK and gres <= 1e-13
+    D, B, rr = G.state()
+    E = S.eta * D
+    Eref = S.eta * S.D
+    assert np.max(np.abs(E - Eref)) <= 1e-9 * np.max(np.abs(Eref))
+    assert np.max(np.abs(B)) == 0.0
+    m, _ = G.gauss_residual()
+    assert m <= 1e-12
+    assert force_err(G.forces(), S.forces()[0]) <= 1e-8
+
+
+# -------------------------------------------------------------- step parity
+
+def run_parity(S, G, disp, checks, ftol, gtol, etol, audit_each=False):
+    n = disp.shape[0]
+    for t in range(n):
+        S.step(disp[t])
+        G.step(disp[t], 1)
+        if audit_each or (t + 1) in checks:
+            m, _ = G.gauss_residual()
+            assert m <= gtol, (t, m)
+        if (t + 1) in checks:
+            Fo, _ = S.forces()
+            assert force_err(G.forces(), Fo) <= ftol, t
+            P = G.dipole()
+            Po = S.dipole()
+            assert np.max(np.abs(P - Po)) <= 1e-12 * max(1.0, np.max(np.abs(Po)))
+            if etol is not None:
+                errs = energy_err(G.energy(), S.energy())
+                assert max(errs.values()) <= etol, (t, errs)
+
+
+def test_c1_fp64_full_run():
+    """Plain FP64 MEMD on the 8^3 two-charge workload, all 200 steps."""
+    w = W.WORKLOADS["c1"]
+    s = W.make_system(w)
+    S, G = pair(w.L, s["q"], s["r0"])
+    apply_eps(S, G, "uniform", 1.0)
+    S.initial_solve(1e-13)
+    share_state(S, G)
+    run_parity(S, G, s["disp"], {1, 50, 100, 150, 200}, 1e-10, 1e-12, 1e-10, audit_each=True)
+
+
+@pytest.mark.parametrize("prec", [memd.FP64, memd.FP32_MIXED])
+def test_c2_parity(prec):
+    """32^3, 1000 ions, eps = 80: the first 100 of the 1000 steps."""
+    w = W.WORKLOADS["c2"]
+    s = W.make_system(w, steps=100)
+    S, G = pair(w.L, s["q"], s["r0"], eps_min=80.0, precision=prec)
+    apply_eps(S, G, "uniform", 80.0)
+    S.initial_solve(1e-13)
+    share_state(S, G)
+    if prec == memd.FP64:
+        run_parity(S, G, s["disp"], {1, 10, 100}, 1e-10, 1e-12, 1e-10)
+    else:
+        run_parity(S, G, s["disp"], {1, 10, 100}, 1e-4, 1e-5, 1e-4)
+
+
+def test_c3_fp32_slab():
+    """64^3, 10^4 ions, tanh slab 2 -> 80 (site profile per plane), FP32 fields."""
+    w = W.WORKLOADS["c3"]
+    s = W.make_system(w, steps=20)
+    ez = s["eps_z"]
+    S, G = pair(w.L, s["q"], s["r0"], eps_min=ez.min(), precision=memd.FP32_MIXED)
+    apply_eps(S, G, "zsite", eps_z=ez)
+    S.initial_solve(1e-12)
+    share_state(S, G)
+    run_parity(S, G, s["disp"], {1, 20}, 1e-4, 1e-5, 1e-4)
+
+
+def test_zsite_equals_site_mode():
+    """A planar profile given per plane and the same profile given per site
+    produce the same run."""
+    L = 16
+    rng, q, r = _rng_system(8, 20, L)
+    ez = W.slab_between(L, 70.0, 3.0)
+    c = W.default_c(1.0, 0.01, ez.min())
+    A = memd.Context(L, q, r, c=c)
+    B = memd.Context(L, q, r, c=c)
+    A.set_permittivity(memd.EPS_ZSITE, ez)
+    B.set_permittivity(memd.EPS_SITE, np.repeat(ez, L * L))
+    A.solve()
+    B.solve()
+    disp = rng.normal(0, 0.05, size=(10, 20, 3))
+    for t in range(10):
+        A.step(disp[t], 1)
+        B.step(disp[t], 1)
+    assert force_err(A.forces(), B.forces()) <= 1e-12
+
+
+def test_salt_permittivity_parity():
+    """Salt-dependent eps per link recomputed every 5 steps (FP64)."""
+    L = 16
+    rng = np.random.default_rng(9)
+    n = 400
+    r = rng.uniform(0, L, size=(n, 3))
+    q = np.repeat([1.0, -1.0, 2.0, -2.0], n // 4)
+    S, G = pair(L, q, r, eps_min=70.0)
+    S.set_eps_salt()
+    G.set_salt(80.0, 15.0, 1.0, every=5)
+    S.initial_solve(1e-13)
+    share_state(S, G)
+    disp = rng.normal(0, 0.05, size=(15, n, 3))
+    for t in range(15):
+        if t % 5 == 0:
+            S.set_eps_salt()
+        S.step(disp[t])
+        G.step(disp[t], 1)
+    Fo, _ = S.forces()
+    assert force_err(G.forces(), Fo) <= 1e-10
+    errs = energy_err(G.energy(), S.energy())
+    assert max(errs.values()) <= 1e-10
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5])
+def test_large_moves_wraparound(L):
+    """Face crossings of several cells per axis, wrap-around, unfolded positions."""
+    rng, q, r = _rng_system(10 + L, 6, L, True)
+    el = 1.0 + 4.0 * rng.uniform(size=3 * L ** 3)
+    S, G = pair(L, q, r, dt=0.05, c=3.0)
+    apply_eps(S, G, "link", eps_link=el)
+    S.initial_solve(1e-13)
+    share_state(S, G)
+    disp = rng.uniform(-2.5, 2.5, size=(20, 6, 3)) * (rng.uniform(size=(20, 6, 1)) < 0.6)
+    run_parity(S, G, disp, {5, 20}, 1e-10, 1e-12, 1e-10, audit_each=True)
+    assert np.allclose(G.state()[2], S.r, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("L,rows,tz", [(17, 1, 3), (24, 2, 16), (48, 4, 5), (65, 2, 7), (70, 1, 64)])
+def test_leapfrog_ragged_tiles(L, rows, tz):
+    """The fused leapfrog on lattice sizes that do not divide into tiles, from a
+    random field state, against the oracle's Faraday + Ampere (no ions)."""
+    rng = np.random.default_rng(L)
+    q = np.zeros(0)
+    r = np.zeros((0, 3))
+    el = 1.0 + 3.0 * rng.uniform(size=3 * L ** 3)
+    S, G = pair(L, q, r, dt=0.05, c=2.0)
+    apply_eps(S, G, "link", eps_link=el)
+    memd.memd_set_tiling(G.ctx, rows, tz)
+    D = rng.normal(size=3 * L ** 3)
+    B = rng.normal(size=3 * L ** 3)
+    S.set_state(D, B, r)
+    G.set_state(D, B, r.reshape(-1))
+    for _ in range(3):
+        S.faraday()
+        S.ampere()
+    G.step(np.zeros(0), 3)
+    Dg, Bg, _ = G.state()
+    assert np.max(np.abs(Dg - S.D)) <= 1e-12 * np.max(np.abs(S.D))
+    assert np.max(np.abs(Bg - S.B)) <= 1e-12 * np.max(np.abs(S.B))
+
+
+def test_tilings_bitwise_identical():
+    """Every tile shape computes the same arithmetic: results agree bit for bit."""
+    L = 32
+    rng = np.random.default_rng(3)
+    D = rng.normal(size=3 * L ** 3)
+    B = rng.normal(size=3 * L ** 3)
+    ez = W.tanh_slab(L, 1.0)
+    outs = []
+    for rows, tz in [(1, 1), (2, 16), (4, 32), (2, 5)]:
+        G = memd.Context(L, np.zeros(0), np.zeros((0, 3)), dt=0.05, c=1.0)
+        G.set_permittivity(memd.EPS_ZSITE, ez)
+        memd.memd_set_tiling(G.ctx, rows, tz)
+        G.set_state(D, B, np.zeros(0))
+        G.step(np.zeros(0), 4)
+        outs.append(G.state()[:2])
+        G.close()
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+def test_history_matches_explicit_calls():
+    L = 12
+    rng, q, r = _rng_system(11, 30, L)
+    G = memd.Context(L, q, r, audit_every=2, energy_every=3)
+    G.set_permittivity(memd.EPS_UNIFORM, [4.0])
+    G.solve()
+    disp = rng.normal(0, 0.05, size=(6, 30, 3))
+    G.step(disp, 6)
+    A, E = G.history()
+    assert A.shape == (3, 2) and E.shape == (2, 5)
+    assert np.all(A[:, 0] <= 1e-12)
+    e = G.energy()
+    assert E[-1, 0] == pytest.approx(e["W_E"], rel=1e-14)
+    assert E[-1, 4] == pytest.approx(e["E_corrected"], rel=1e-12, abs=1e-14)
+
+
+def test_device_pointer_inputs():
+    """Inputs and outputs given as device memory (torch tensors) behave like
+    host arrays."""
+    import torch
+    L = 8
+    rng, q, r = _rng_system(12, 6, L)
+    disp = rng.normal(0, 0.1, size=(5, 6, 3))
+    Gh = memd.Context(L, q, r)
+    Gh.solve()
+    Gh.step(disp, 5)
+    qd = torch.tensor(q, dtype=torch.float64, device="cuda")
+    rd = torch.tensor(r.reshape(-1), dtype=torch.float64, device="cuda")
+    dd = torch.tensor(disp.reshape(-1), dtype=torch.float64, device="cuda")
+    Gd = memd.Context(L, qd, rd)
+    Gd.solve()
+    memd.memd_step(Gd.ctx, dd, 5)
+    Fd = torch.zeros(18, dtype=torch.float64, device="cuda")
+    memd.memd_forces(Gd.ctx, Fd)
+    assert force_err(Fd.cpu().numpy().reshape(6, 3), Gh.forces()) <= 1e-12
+
+
+def test_error_codes():
+    L = 8
+    q = np.array([1.0, -1.0])
+    r = np.array([[1.0, 2.0, 3.0], [4.0, 5.0, 6.0]])
+    with pytest.raises(memd.MemdError) as e:
+        memd.Context(L, np.array([1.0, 1.0]), r)
+    assert e.value.status == memd.ENONNEUTRAL
+    with pytest.raises(memd.MemdError) as e:
+        memd.Context(1, q, r)
+    assert e.value.status == memd.EINVAL
+    G = memd.Context(L, q, r)
+    with pytest.raises(memd.MemdError) as e:
+        G.step(np.zeros((2, 3)), 1)
+    assert e.value.status == memd.ESTATE
+    with pytest.raises(memd.MemdError) as e:
+        G.set_permittivity(memd.EPS_UNIFORM, [-1.0])
+    assert e.value.status == memd.EINVAL
+    H = memd.Context(L, q, r, c=1000.0)
+    with pytest.raises(memd.MemdError) as e:
+        H.set_permittivity(memd.EPS_UNIFORM, [1.0])
+    assert e.value.status == memd.EUNSTABLE
+    with pytest.raises(memd.MemdError) as e:
+        memd.memd_set_tiling(G.ctx, 3, 0)
+    assert e.value.status == memd.EINVAL
