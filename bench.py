@@ -1,0 +1,245 @@
+"""MEMD step throughput on one MI355X.
+
+Workload c4: 128^3 periodic lattice, 10^5 ions (45 000 x (+-1), 5 000 x (+-2))
+at seeded uniform positions, salt-dependent permittivity per link
+(eps = 80 - 15 c_local, c_local the 3x3x3-smoothed linear-interpolated ion
+density) recomputed every 50 steps, seeded Gaussian prescribed displacements
+(sigma = 0.02 a), FP32 fields with FP64 positions, dipole, Gauss audit and
+energies.  One step = leapfrog (Faraday + Ampere) + ion move and current
+deposit + dipole + corrected forces; the Gauss audit, the energy evaluation
+and the permittivity recompute run every 50 steps inside the timed region.
+Inputs (including all displacements) are resident in HBM before timing.
+
+Prints one JSON line: value = lattice-site updates per second (whole job),
+plus ion-steps/s, the leapfrog kernel's roofline object (HIP-event timing of
+every launch in the timed region) and the FP64 CPU oracle's throughput on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MEMD lattice-site updates/s + ion-steps/s; p50/p99 latency for batched replicas"
+HBM_PEAK_GBS = 8000.0
+CADENCE = 50
+
+# Algorithmic bytes (each value read once / written once).
+#   leapfrog, per site: read D[3], B[3], eta[3] (per-link permittivity), write D[3], B[3]
+#   deposit, per ion: r rw (48), disp (24), q (8), 12 link read-modify-writes
+#   forces, per ion: r (24), q (8), 12 D + 12 eta reads, F write (24)
+
+
+def leapfrog_bytes_per_site(fp32: bool, per_link_eps: bool) -> int:
+    t = 4 if fp32 else 8
+    return (15 if per_link_eps else 12) * t
+
+
+def ion_bytes_per_step(fp32: bool) -> int:
+    t = 4 if fp32 else 8
+    deposit = 48 + 24 + 8 + 12 * 2 * t
+    forces = 24 + 8 + 24 * t + 24
+    return deposit + forces
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_1309_7859_amd", "csrc", "kernels_field.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(precision: str):
+    """HBM bytes per leapfrog launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"leapfrog_c4_{precision}_hbm_traffic.md")
+    if not os.path.exists(p):
+        return None
+    text = open(p).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    if not m or not h or h.group(1) != kernel_source_hash():
+        return None
+    return float(m.group(1))
+
+
+def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None):
+    import torch
+    from paper_1309_7859_amd import memd
+    from paper_1309_7859_amd import workloads as W
+
+    fp32 = precision == "fp32"
+    s = W.make_system(w, steps=0)
+    stream = W.DisplacementStream(w)
+    disp = torch.from_numpy(stream.take(warmup + steps)).to("cuda").contiguous()
+    torch.cuda.synchronize()
+    if copy_mb:
+        # a plain copy of known size: calibrates the HBM byte counters under rocprofv3
+        src = torch.empty(copy_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    G = memd.Context(w.L, s["q"], s["r0"], a=w.a, dt=w.dt, c=0.0,
+                     precision=memd.FP32_MIXED if fp32 else memd.FP64,
+                     audit_every=CADENCE, energy_every=CADENCE)
+    G.set_salt(80.0, 15.0, 1.0, every=CADENCE)
+    t0 = time.perf_counter()
+    st, iters, res = G.solve(1e-12, check=False)
+    t_solve = time.perf_counter() - t0
+    if tile:
+        memd.memd_set_tiling(G.ctx, tile[0], tile[1])
+        tile_used = tuple(tile) + (None,)
+    else:
+        tile_used = memd.memd_autotune(G.ctx, 10, None)
+    c_used, eps_h, eps_min = G.params_in_use()
+    per = 3 * w.n
+    base = disp.data_ptr()
+    if warmup:
+        memd.memd_step(G.ctx, base, warmup)
+    torch.cuda.synchronize()
+    memd.memd_profile_enable(G.ctx, 1 << memd.FAMILIES["leapfrog"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    memd.memd_step(G.ctx, base + 8 * per * warmup, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lf_ms, lf_n = memd.memd_profile_read(G.ctx, "leapfrog")
+    memd.memd_profile_enable(G.ctx, 0)
+    audits, energies = G.history()
+    gauss_max = float(np.max(audits[:, 0])) if len(audits) else None
+    G.close()
+    return dict(wall=wall, lf_ms=lf_ms, lf_n=lf_n, solve_s=t_solve, solve_iters=iters, tile=tile_used,
+                solve_res=res, solve_status=st, c=c_used, eps_min=eps_min, gauss_max=gauss_max,
+                energy_last=energies[-1].tolist() if len(energies) else None)
+
+
+def cpu_baseline(w, sample_steps: int):
+    """The FP64 oracle on a bounded sample of the same workload: sample_steps
+    steps (leapfrog, deposit, dipole, forces) plus one permittivity recompute,
+    one Gauss audit and one energy evaluation, amortised at the GPU cadence
+    of one per 50 steps.  The oracle starts from the recursion solution (its
+    CG relaxation at 128^3 is a one-off that is not part of a step)."""
+    import oracle
+    from paper_1309_7859_amd import workloads as W
+
+    s = W.make_system(w, steps=0)
+    disp = W.DisplacementStream(w).take(sample_steps)
+    S = oracle.System(w.L, w.a, w.dt, 1.0, s["q"], s["r0"])
+    t0 = time.perf_counter()
+    S.set_eps_salt()
+    t_salt = time.perf_counter() - t0
+    S.c = W.default_c(w.a, w.dt, float(np.min(1.0 / S.eta)))
+    S.recursion_only()
+    t0 = time.perf_counter()
+    for t in range(sample_steps):
+        S.step(disp[t])
+        S.forces()
+    t_steps = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    S.gauss_residual()
+    S.energy()
+    t_obs = time.perf_counter() - t0
+    per_step = t_steps / sample_steps + (t_salt + t_obs) / CADENCE
+    return dict(per_step=per_step, cores=oracle.threads(),
+                total=t_steps + t_salt + t_obs)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--fp64-steps", type=int, default=200,
+                    help="steps of the FP64 variant reported beside the main line (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=30, help="oracle sample size (0 = skip)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="run a plain copy of this many MiB first (counter calibration)")
+    ap.add_argument("--tile", type=str, default="", help="rows,planes of the leapfrog tile")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build measures the "
+              "single-GPU path; sharding across GPUs is described in DESIGN.md, not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_1309_7859_amd import workloads as W
+
+    w = W.WORKLOADS["c4"]
+    tile = tuple(int(x) for x in args.tile.split(",")) if args.tile else None
+    fp32 = args.precision == "fp32"
+    r = gpu_run(w, args.steps, args.warmup, args.precision, args.copy_mb, tile)
+    sites = w.sites
+    value = sites * args.steps / r["wall"]
+    ion_steps = w.n * args.steps / r["wall"]
+
+    lf_avg_s = r["lf_ms"] / 1e3 / max(r["lf_n"], 1)
+    lf_bytes = leapfrog_bytes_per_site(fp32, True) * sites
+    achieved = lf_bytes / lf_avg_s / 1e9
+    traffic = load_traffic(args.precision)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": (round(traffic / lf_avg_s / 1e9, 1) if traffic else None),
+            "kernel": "k_leapfrog (fused Faraday + Ampere)",
+            "algorithmic_bytes_per_launch": lf_bytes, "avg_launch_us": round(lf_avg_s * 1e6, 2),
+            "launches": r["lf_n"],
+            "tile": {"x": 64, "y": 4 * r["tile"][0], "z_chunk": r["tile"][1],
+                     "autotuned_us": r["tile"][2]}}
+    if traffic:
+        roof["traffic_bytes_per_launch"] = traffic
+    step_bytes = lf_bytes + ion_bytes_per_step(fp32) * w.n
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "site-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(r["wall"] * 1e3 / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 fields, f64 positions/reductions" if fp32 else "f64",
+        "data": "synthetic: seeded uniform ions, Gaussian displacements (c4 recipe)",
+        "config": {"workload": "c4: 128^3 lattice, 1e5 ions (10% +-2), salt eps per link every 50 "
+                               "steps, audit+energy every 50 steps",
+                   "L": w.L, "n_ions": w.n, "precision": args.precision, "c": r["c"],
+                   "dt": w.dt, "sigma": w.sigma},
+        "ion_steps_per_s": round(ion_steps, 1),
+        "step_hbm_frac": round(step_bytes / (r["wall"] / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": roof,
+        "gauss_residual_max": r["gauss_max"],
+        "initial_solve": {"seconds": round(r["solve_s"], 3), "iterations": r["solve_iters"],
+                          "curl_residual": r["solve_res"], "status": r["solve_status"]},
+    }
+    if fp32 and args.fp64_steps > 0:
+        r64 = gpu_run(w, args.fp64_steps, min(args.warmup, 20), "fp64")
+        lf64 = r64["lf_ms"] / 1e3 / max(r64["lf_n"], 1)
+        b64 = leapfrog_bytes_per_site(False, True) * sites
+        out["fp64_variant"] = {
+            "value": round(sites * args.fp64_steps / r64["wall"], 1),
+            "ion_steps_per_s": round(w.n * args.fp64_steps / r64["wall"], 1),
+            "ms_per_step": round(r64["wall"] * 1e3 / args.fp64_steps, 5),
+            "leapfrog_frac": round(b64 / lf64 / 1e9 / HBM_PEAK_GBS, 4),
+            "steps": args.fp64_steps}
+    if args.cpu_steps > 0:
+        cb = cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"] = {
+            "value": round(sites / cb["per_step"], 1), "unit": "site-updates/s",
+            "cores": cb["cores"], "kind": "oracle",
+            "sample": f"{args.cpu_steps} c4 steps (leapfrog, deposit, dipole, forces) + 1 salt "
+                      f"recompute + 1 audit + 1 energy amortised at 1/50, FP64, from the recursion "
+                      f"solution; {cb['total']:.1f} s of CPU work",
+            "ion_steps_per_s": round(w.n / cb["per_step"], 1)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -141,6 +141,16 @@ memd_status memd_initial_gauss_solve(memd_ctx *ctx, double tol, int max_iter,
  * Errors: ESTATE (no initial solve or state yet), EINVAL, EDEVICE. */
 memd_status memd_step(memd_ctx *ctx, const double *disp, int nsteps);
 
+/* Same step as memd_step, with the displacements drawn on the device from the
+ * counter-based stream of `seed` (Philox4x32-10 of Salmon et al. 2011; ion i,
+ * step t = steps done since the initial solve, counters (i, t, 0, 0) and
+ * (i, t, 1, 0), key = the two 32-bit halves of seed, 53-bit uniforms,
+ * Box-Muller), times sigma.  memd_seeded_displacements returns the same
+ * numbers for one step into out[3n] (host or device memory).
+ * Errors: ESTATE, EINVAL (sigma < 0), EDEVICE. */
+memd_status memd_step_seeded(memd_ctx *ctx, uint64_t seed, double sigma, int nsteps);
+memd_status memd_seeded_displacements(uint64_t seed, int step, int n, double sigma, double *out);
+
 /* Forces F_out[3n] on the ions at the current state (FP64). */
 memd_status memd_forces(memd_ctx *ctx, double *F_out);
 
@@ -175,10 +185,11 @@ memd_status memd_get_stream(memd_ctx *ctx, void **stream);
 memd_status memd_get_params(memd_ctx *ctx, double *c, double eps_h[3], double *eps_min);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
- * every launch of the named kernel family (0 leapfrog, 1 deposit, 2 forces,
- * 3 audit, 4 energy, 5 dipole, 6 salt).  enable != 0 starts a fresh
- * collection.  memd_profile_read waits for the stream and returns the total
- * milliseconds and the launch count of one family. */
+ * every launch of a kernel family (0 leapfrog, 1 deposit, 2 forces, 3 audit,
+ * 4 energy, 5 dipole, 6 salt).  enable = 0 stops, 1 times every family, any
+ * other value is a bit mask (1 << family) of the families to time; each call
+ * starts a fresh collection.  memd_profile_read waits for the stream and
+ * returns the total milliseconds and the launch count of one family. */
 memd_status memd_profile_enable(memd_ctx *ctx, int enable);
 memd_status memd_profile_read(memd_ctx *ctx, int family, double *total_ms, long *launches);
 
@@ -187,9 +198,59 @@ memd_status memd_profile_read(memd_ctx *ctx, int family, double *total_ms, long 
  * 0 keeps the current value. */
 memd_status memd_set_tiling(memd_ctx *ctx, int rows_per_thread, int planes_per_chunk);
 
+/* Tile-shape autotuner of the leapfrog kernel: times every candidate shape
+ * (reps launches each, HIP events) on the context's buffers without changing
+ * its state, keeps the fastest, and appends it to the text cache at
+ * cache_path (NULL: no cache).  A cache entry for the same lattice size,
+ * precision and permittivity representation is used without measuring.
+ * Outputs may be NULL. */
+memd_status memd_autotune(memd_ctx *ctx, int reps, const char *cache_path, int *rows_out,
+                          int *planes_out, double *us_out);
+
 void memd_destroy(memd_ctx *ctx);
 const char *memd_strerror(memd_status status);
 int memd_version(void);
+
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of independent replicas (FP32 fields; each replica is a
+ * full MEMD system of its own: lattice size, ions, planar or uniform
+ * permittivity, step count, displacement stream).  Requests queue on submit;
+ * memd_server_progress admits queued requests while the device-memory budget
+ * (resident buffers plus the FP64 solver's work vectors) and the slot count
+ * allow, initialises them on worker threads (own streams: context,
+ * permittivity, FP64 initial solve to solve_tol, leapfrog tile autotune with
+ * the cache file tune_cache), joins initialised replicas to the device-resident
+ * replica table, replays the captured step graph `global_steps` times (every
+ * resident replica advances one step per replay), and retires finished
+ * replicas (forces, energies and Gauss residual kept for memd_server_poll;
+ * device memory returned).  Times are seconds since memd_server_create.
+ * Not thread-safe: one caller drives a server. */
+typedef struct memd_server memd_server;
+
+typedef enum {
+    MEMD_REQ_PENDING = 0, MEMD_REQ_INIT = 1, MEMD_REQ_READY = 2, MEMD_REQ_ACTIVE = 3,
+    MEMD_REQ_DONE = 4, MEMD_REQ_FAILED = 5
+} memd_request_state;
+
+memd_status memd_server_create(memd_server **out, size_t hbm_budget_bytes, int max_slots,
+                               int init_workers, double solve_tol, const char *tune_cache,
+                               void *hip_stream);
+/* eps_mode: MEMD_EPS_UNIFORM (eps[1]) or MEMD_EPS_ZSITE (eps[L]).  Inputs are
+ * copied (host memory).  A request larger than the whole budget fails at once
+ * (state FAILED, ENOMEM). */
+memd_status memd_server_submit(memd_server *srv, const memd_params *p, int n, const double *q,
+                               const double *r0, int eps_mode, const double *eps, int nsteps,
+                               uint64_t seed, double sigma, uint64_t *req_id);
+memd_status memd_server_progress(memd_server *srv, int global_steps, int *active, int *queued,
+                                 int *finished);
+/* state: memd_request_state.  F_out[3n], E_out and gauss_max are filled once
+ * DONE; a FAILED request returns its error code. */
+memd_status memd_server_poll(memd_server *srv, uint64_t req_id, int *state, double *F_out,
+                             memd_energy_t *E_out, double *gauss_max, double *t_arrival,
+                             double *t_done);
+memd_status memd_server_stats(memd_server *srv, long *global_steps, long *replica_steps,
+                              size_t *bytes_in_use);
+memd_status memd_server_destroy(memd_server *srv);
 
 #ifdef __cplusplus
 }

@@ -38,6 +38,7 @@ def _load():
     i, d = C.c_int, C.c_double
     sig = {
         "orc_version": (i, []),
+        "orc_threads": (i, []),
         "orc_spread": (None, [i, d, i, _P, _P, _P]),
         "orc_eps_site_to_link": (i, [i, _P, d, _P]),
         "orc_eps_derived": (None, [i, _P, _P, _P, _P]),
@@ -64,6 +65,11 @@ def _load():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    U = C.POINTER(C.c_uint)
+    lib.orc_philox4x32_10.restype = None
+    lib.orc_philox4x32_10.argtypes = [U, U, U]
+    lib.orc_seeded_displacements.restype = None
+    lib.orc_seeded_displacements.argtypes = [C.c_ulonglong, i, i, d, _P]
     _lib = lib
     return lib
 
@@ -156,6 +162,24 @@ def dipole(q, r) -> np.ndarray:
     P = np.zeros(3)
     _load().orc_dipole(len(q), _ptr(q), _ptr(r), _ptr(P))
     return P
+
+
+def philox4x32_10(ctr, key):
+    c = (C.c_uint * 4)(*[int(x) & 0xffffffff for x in ctr])
+    k = (C.c_uint * 2)(*[int(x) & 0xffffffff for x in key])
+    o = (C.c_uint * 4)()
+    _load().orc_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def seeded_displacements(seed: int, step: int, n: int, sigma: float) -> np.ndarray:
+    out = np.zeros(3 * n)
+    _load().orc_seeded_displacements(int(seed), int(step), int(n), float(sigma), _ptr(out))
+    return out.reshape(n, 3)
+
+
+def threads() -> int:
+    return _load().orc_threads()
 
 
 def default_c(a: float, dt: float, eps_min: float, nu: float = 0.25) -> float:

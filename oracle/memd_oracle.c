@@ -18,6 +18,13 @@
 
 int orc_version(void) { return 1; }
 
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif
+
 /* ------------------------------------------------------------------ lattice */
 
 static long wrapi(long i, int L) {
@@ -671,4 +678,60 @@ void orc_energy(int L, double a, double dt, double c, const double *eta, const d
     out[3] = ud;
     out[4] = we + wb - U_self - ud;
     free(Bn);
+}
+
+/* ------------------------------------------------ counter-based displacements */
+
+/* Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC 2011): each round
+ * multiplies words 0 and 2 by fixed odd constants, and the 64-bit products'
+ * halves are xored with words 1 and 3 and the round key; the key is bumped by
+ * the Weyl constants before every round but the first. */
+void orc_philox4x32_10(const unsigned int ctr[4], const unsigned int key[2], unsigned int out[4]) {
+    unsigned long long m0 = 0xD2511F53ull, m1 = 0xCD9E8D57ull;
+    unsigned int x[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    unsigned int k[2] = {key[0], key[1]};
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        if (rnd) {
+            k[0] += 0x9E3779B9u;
+            k[1] += 0xBB67AE85u;
+        }
+        unsigned long long a = m0 * (unsigned long long)x[0];
+        unsigned long long b = m1 * (unsigned long long)x[2];
+        unsigned int y0 = (unsigned int)(b >> 32) ^ x[1] ^ k[0];
+        unsigned int y1 = (unsigned int)b;
+        unsigned int y2 = (unsigned int)(a >> 32) ^ x[3] ^ k[1];
+        unsigned int y3 = (unsigned int)a;
+        x[0] = y0;
+        x[1] = y1;
+        x[2] = y2;
+        x[3] = y3;
+    }
+    for (int t = 0; t < 4; ++t) out[t] = x[t];
+}
+
+/* Displacements of n ions at step t from the stream of `seed`: per ion two
+ * Philox calls with counters (i, t, 0, 0) and (i, t, 1, 0), key = (low, high
+ * 32 bits of seed); each call gives two 53-bit uniforms in [0, 1) from word
+ * pairs (w0, w1), (w2, w3) as ((wa >> 5) 2^26 + (wb >> 6)) / 2^53, turned into
+ * normals by Box-Muller with radius sqrt(-2 log(1 - ua)) and angle 2 pi ub
+ * (cosine, then sine).  The first call gives x and y, the second z. */
+void orc_seeded_displacements(unsigned long long seed, int t, int n, double sigma, double *out) {
+    const double two_pi = 6.283185307179586476925286766559;
+    unsigned int key[2] = {(unsigned int)(seed & 0xffffffffull), (unsigned int)(seed >> 32)};
+    for (int i = 0; i < n; ++i) {
+        double z[4];
+        for (int j = 0; j < 2; ++j) {
+            unsigned int ctr[4] = {(unsigned int)i, (unsigned int)t, (unsigned int)j, 0u};
+            unsigned int w[4];
+            orc_philox4x32_10(ctr, key, w);
+            double ua = ((double)(w[0] >> 5) * 67108864.0 + (double)(w[1] >> 6)) / 9007199254740992.0;
+            double ub = ((double)(w[2] >> 5) * 67108864.0 + (double)(w[3] >> 6)) / 9007199254740992.0;
+            double rad = sqrt(-2.0 * log(1.0 - ua));
+            z[2 * j] = rad * cos(two_pi * ub);
+            z[2 * j + 1] = rad * sin(two_pi * ub);
+        }
+        out[3 * i] = sigma * z[0];
+        out[3 * i + 1] = sigma * z[1];
+        out[3 * i + 2] = sigma * z[2];
+    }
 }

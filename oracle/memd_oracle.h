@@ -22,6 +22,8 @@ extern "C" {
 #endif
 
 int orc_version(void);
+/* OpenMP threads the stencil loops use. */
+int orc_threads(void);
 
 /* Linear (cloud-in-cell) charge assignment to the 8 corners of the cell
  * (section "Self energy interaction"; section "Error estimates"). */
@@ -88,6 +90,11 @@ void orc_forces(int L, double a, int n, const double *q, const double *r, const 
 void orc_energy(int L, double a, double dt, double c, const double *eta, const double *D,
                 const double *B, double U_self, const double P[3], const double eps_h[3],
                 double out[5]);
+
+/* Philox4x32-10 counter-based generator and the seeded Gaussian displacement
+ * stream built on it (ion i, step t). */
+void orc_philox4x32_10(const unsigned int ctr[4], const unsigned int key[2], unsigned int out[4]);
+void orc_seeded_displacements(unsigned long long seed, int t, int n, double sigma, double *out);
 
 #ifdef __cplusplus
 }

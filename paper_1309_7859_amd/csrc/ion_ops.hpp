@@ -1,0 +1,169 @@
+// ion_ops.hpp -- per-ion device operations shared by the single-system and
+// the batched replica kernels: the current deposit of one ion's move and the
+// corrected force on one ion.
+#pragma once
+
+#include "device_util.hpp"
+#include "memd_internal.hpp"
+
+namespace memd {
+
+// Permittivity seen by the ion kernels: one value, a per-plane profile, or
+// one value per link.
+template <typename T>
+struct EtaView {
+    int mode;
+    double uni;
+    const T *prof;  // [3L]
+    const T *link;  // [3Ns]
+    __device__ __forceinline__ double at(int d, int k, size_t off, int L, size_t Ns) const {
+        if (mode == ETA_UNIFORM) return uni;
+        if (mode == ETA_ZPROF) return (double)prof[d * L + k];
+        return (double)link[(size_t)d * Ns + off];
+    }
+};
+
+// Current assignment that keeps Gauss's law (eq. constraint): the ion moves by
+// du axis by axis (x, y, z), the others held at their current values.  Along
+// the moving axis the path is cut at cell faces; the piece [ua, ub] inside
+// cell kc carries the current q (ub - ua)/a onto the 4 links of that cell
+// along d with the transverse linear weights:
+//   D_d(kc, c1 + o1, c2 + o2) -= q (ub - ua)/a * w(o1; f1) w(o2; f2) / a^2.
+// u is updated in place.  Accumulation uses hardware float/double atomics.
+template <typename T>
+__device__ __forceinline__ void deposit_ion(int L, size_t Ns, double a, double qi, double (&u)[3],
+                                            const double (&du)[3], T *__restrict__ D) {
+    const double a2 = a * a;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+        int c1, c2;
+        double f1, f2;
+        fold(u[d1], a, L, c1, f1);
+        fold(u[d2], a, L, c2, f2);
+        const double u0 = u[d];
+        const double u1 = u0 + du[d];
+        if (u1 != u0) {
+            const double lo = u0 < u1 ? u0 : u1, hi = u0 < u1 ? u1 : u0;
+            const double sgn = u1 > u0 ? 1.0 : -1.0;
+            const long long klo = (long long)floor(lo / a), khi = (long long)floor(hi / a);
+            const int c1p = c1 + 1 == L ? 0 : c1 + 1, c2p = c2 + 1 == L ? 0 : c2 + 1;
+            for (long long kc = klo; kc <= khi; ++kc) {
+                const double s0 = (double)kc * a, s1 = (double)(kc + 1) * a;
+                const double sa = lo > s0 ? lo : s0;
+                const double sb = hi < s1 ? hi : s1;
+                const double len = sb - sa;
+                if (!(len > 0.0)) continue;
+                const double amount = qi * sgn * (len / a) / a2;
+                long long km = kc % (long long)L;
+                if (km < 0) km += L;
+                int x[3];
+                x[d] = (int)km;
+#pragma unroll
+                for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                    for (int o1 = 0; o1 < 2; ++o1) {
+                        x[d1] = o1 ? c1p : c1;
+                        x[d2] = o2 ? c2p : c2;
+                        const double val = amount * lin_w(o1, f1) * lin_w(o2, f2);
+                        unsafeAtomicAdd(&D[(size_t)d * Ns + site_index(x[0], x[1], x[2], L)], (T)(-val));
+                    }
+            }
+        }
+        u[d] = u1;
+    }
+}
+
+// Linear assignment of charge qi at u to the 8 corners of its cell (FP64 atomics).
+__device__ __forceinline__ void spread_ion(int L, double a, double qi, const double (&u)[3],
+                                           double *__restrict__ dst) {
+    int cc[3];
+    double ff[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fold(u[d], a, L, cc[d], ff[d]);
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+        const double w = lin_w(ox, ff[0]) * lin_w(oy, ff[1]) * lin_w(oz, ff[2]);
+        const int xi = ox ? (cc[0] + 1 == L ? 0 : cc[0] + 1) : cc[0];
+        const int yi = oy ? (cc[1] + 1 == L ? 0 : cc[1] + 1) : cc[1];
+        const int zi = oz ? (cc[2] + 1 == L ? 0 : cc[2] + 1) : cc[2];
+        unsafeAtomicAdd(&dst[site_index(xi, yi, zi, L)], qi * w);
+    }
+}
+
+// Cell self-energy sum S(f) = sum_{o,o'} w_o w_o' G(o - o') and its gradient:
+// per axis, equal corners weigh alpha = 1 - beta, different corners
+// beta = 2 f (1 - f); G depends on the number of differing axes.
+__device__ __forceinline__ void self_sum(const double *G, const double f[3], double &S, double dS[3]) {
+    double be[3], al[3], db[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        be[d] = 2.0 * f[d] * (1.0 - f[d]);
+        al[d] = 1.0 - be[d];
+        db[d] = 2.0 - 4.0 * f[d];
+    }
+    S = 0.0;
+    dS[0] = dS[1] = dS[2] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int m0 = m & 1, m1 = (m >> 1) & 1, m2 = m >> 2;
+        const double g = G[m0 + m1 + m2];
+        const double f0 = m0 ? be[0] : al[0], f1 = m1 ? be[1] : al[1], f2 = m2 ? be[2] : al[2];
+        const double g0 = m0 ? db[0] : -db[0], g1 = m1 ? db[1] : -db[1], g2 = m2 ? db[2] : -db[2];
+        S += g * f0 * f1 * f2;
+        dS[0] += g * g0 * f1 * f2;
+        dS[1] += g * f0 * g1 * f2;
+        dS[2] += g * f0 * f1 * g2;
+    }
+}
+
+// Corrected force on one ion (eq. force without v x B; F = +q E):
+//   q sum_{4 d-links of the cell} w w eta_d D_d
+//   - F_self (lattice Green's-function self force, eps_cell = harmonic mean of
+//     the cell's 12 edges)
+//   + q P_d / (V eps_h_d)   (dipole correction, section "Periodicity").
+// Returns the ion's self energy.
+template <typename T>
+__device__ __forceinline__ double force_ion(int L, size_t Ns, double a, double V, double qi,
+                                            const double (&u)[3], const T *__restrict__ D,
+                                            const EtaView<T> &eta, const double *G, const double *P,
+                                            const double *epsh, double (&F)[3]) {
+    int c[3];
+    double f[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fold(u[d], a, L, c[d], f[d]);
+    const int cp[3] = {c[0] + 1 == L ? 0 : c[0] + 1, c[1] + 1 == L ? 0 : c[1] + 1, c[2] + 1 == L ? 0 : c[2] + 1};
+    double Flat[3];
+    double etasum = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+        double s = 0.0;
+#pragma unroll
+        for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+            for (int o1 = 0; o1 < 2; ++o1) {
+                int x[3] = {c[0], c[1], c[2]};
+                x[d1] = o1 ? cp[d1] : c[d1];
+                x[d2] = o2 ? cp[d2] : c[d2];
+                const size_t off = site_index(x[0], x[1], x[2], L);
+                const double e = eta.at(d, x[2], off, L, Ns);
+                etasum += e;
+                s += lin_w(o1, f[d1]) * lin_w(o2, f[d2]) * (e * (double)D[(size_t)d * Ns + off]);
+            }
+        Flat[d] = qi * s;
+    }
+    const double eps_cell = 12.0 / etasum;
+    double S, dS[3];
+    self_sum(G, f, S, dS);
+    const double pref = qi * qi / (2.0 * eps_cell * a);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double Fself = -pref * dS[d] / a;
+        F[d] = Flat[d] - Fself + qi * P[d] / (V * epsh[d]);
+    }
+    return pref * S;
+}
+
+}  // namespace memd

@@ -1,0 +1,184 @@
+// kernels_batch.hip -- one global step of many independent MEMD replicas
+// (different L, ion counts, permittivity profiles) in four launches with
+// fixed grids.  The replica table lives in device memory and may change
+// between launches (replicas join and leave) without re-capturing the graph
+// that holds the launches: every workgroup walks the work items (leapfrog
+// tiles, ion blocks) of all listed replicas with a grid stride, finds the
+// owner replica by binary search over the item offsets, and skips replicas
+// that have finished.  Fields are FP32; positions, dipole and the ion
+// arithmetic are FP64; displacements come from the replica's Philox stream.
+#include "device_util.hpp"
+#include "ion_ops.hpp"
+#include "leapfrog_tile.hpp"
+#include "memd_internal.hpp"
+#include "philox.hpp"
+#include "serve_internal.hpp"
+
+namespace memd {
+
+__device__ __forceinline__ int find_rep(const RepDesc *__restrict__ tab, int count, int item, bool by_tiles) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int off = by_tiles ? tab[mid].tile_off : tab[mid].ion_off;
+        if (off <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+union BatchSmem {
+    LfSmem<float, 1> s1;
+    LfSmem<float, 2> s2;
+};
+
+__global__ __launch_bounds__(256) void k_batch_leapfrog(const RepDesc *__restrict__ tab,
+                                                        const int *__restrict__ hdr) {
+    __shared__ BatchSmem U;
+    const int count = hdr[0], total = hdr[1];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int ri = find_rep(tab, count, item, true);
+        const RepDesc &R = tab[ri];
+        const int step = *R.step;
+        if (step >= R.nsteps) continue;
+        const int local = item - R.tile_off;
+        const int tile_x = local % R.ntx;
+        const int rest = local / R.ntx;
+        const int cur = step & 1;
+        LfArgs<float> A;
+        A.Din = R.D[cur];
+        A.Bin = R.B[cur];
+        A.Dout = R.D[cur ^ 1];
+        A.Bout = R.B[cur ^ 1];
+        A.eta_link = nullptr;
+        A.eta_prof = R.eta_prof;
+        A.eta_uni = R.eta_uni;
+        A.kB = R.kB;
+        A.kD = R.kD;
+        A.L = R.L;
+        A.Ns = (size_t)R.L * R.L * R.L;
+        A.ntx = R.ntx;
+        A.nty = R.nty;
+        A.tz = R.tz;
+        __syncthreads();  // the previous item may have used another LDS layout
+        if (R.rows == 1) {
+            if (R.eta_mode == ETA_UNIFORM)
+                leapfrog_tile<float, ETA_UNIFORM, 1>(A, tile_x, rest % R.nty, rest / R.nty, U.s1);
+            else
+                leapfrog_tile<float, ETA_ZPROF, 1>(A, tile_x, rest % R.nty, rest / R.nty, U.s1);
+        } else {
+            if (R.eta_mode == ETA_UNIFORM)
+                leapfrog_tile<float, ETA_UNIFORM, 2>(A, tile_x, rest % R.nty, rest / R.nty, U.s2);
+            else
+                leapfrog_tile<float, ETA_ZPROF, 2>(A, tile_x, rest % R.nty, rest / R.nty, U.s2);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_deposit(const RepDesc *__restrict__ tab,
+                                                       const int *__restrict__ hdr) {
+    const int count = hdr[0], total = hdr[2];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int ri = find_rep(tab, count, item, false);
+        const RepDesc &R = tab[ri];
+        const int step = *R.step;
+        if (step >= R.nsteps) continue;
+        const int b = item - R.ion_off;
+        const int i = b * blockDim.x + threadIdx.x;
+        double P[3] = {0.0, 0.0, 0.0};
+        if (i < R.n) {
+            const size_t Ns = (size_t)R.L * R.L * R.L;
+            double u[3] = {R.r[3 * i], R.r[3 * i + 1], R.r[3 * i + 2]};
+            double du[3];
+            philox_displacement(R.seed, (uint32_t)step, (uint32_t)i, R.sigma, du);
+            const double qi = R.q[i];
+            deposit_ion<float>(R.L, Ns, R.a, qi, u, du, R.D[(step & 1) ^ 1]);
+            R.r[3 * i] = u[0];
+            R.r[3 * i + 1] = u[1];
+            R.r[3 * i + 2] = u[2];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) P[d] = qi * u[d];
+        }
+        block_sum<3>(P);
+        if (threadIdx.x == 0) {
+            R.dip[3 * b] = P[0];
+            R.dip[3 * b + 1] = P[1];
+            R.dip[3 * b + 2] = P[2];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_forces(const RepDesc *__restrict__ tab,
+                                                      const int *__restrict__ hdr) {
+    __shared__ double Psh[3];
+    const int count = hdr[0], total = hdr[2];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int ri = find_rep(tab, count, item, false);
+        const RepDesc &R = tab[ri];
+        const int step = *R.step;
+        if (step >= R.nsteps) continue;
+        const int b = item - R.ion_off;
+        double s[3] = {0.0, 0.0, 0.0};
+        for (int k = threadIdx.x; k < R.iblocks; k += blockDim.x)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) s[d] += R.dip[3 * k + d];
+        block_sum<3>(s);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                Psh[d] = s[d];
+                if (b == 0) R.scal[S_P + d] = s[d];
+            }
+        }
+        __syncthreads();
+        const int i = b * blockDim.x + threadIdx.x;
+        if (i < R.n) {
+            const size_t Ns = (size_t)R.L * R.L * R.L;
+            const double u[3] = {R.r[3 * i], R.r[3 * i + 1], R.r[3 * i + 2]};
+            EtaView<float> ev{R.eta_mode, (double)R.eta_uni, R.eta_prof, nullptr};
+            double F[3];
+            force_ion<float>(R.L, Ns, R.a, R.V, R.q[i], u, R.D[(step & 1) ^ 1], ev, R.scal + S_G, Psh,
+                             R.scal + S_EPSH, F);
+            R.F[3 * i] = F[0];
+            R.F[3 * i + 1] = F[1];
+            R.F[3 * i + 2] = F[2];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_batch_advance(const RepDesc *__restrict__ tab, const int *__restrict__ hdr) {
+    const int count = hdr[0];
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < count; r += gridDim.x * blockDim.x) {
+        int *st = tab[r].step;
+        if (*st < tab[r].nsteps) *st += 1;
+    }
+}
+
+hipError_t launch_batch_step(hipStream_t s, const RepDesc *tab, const int *hdr, int lf_grid, int ion_grid) {
+    hipLaunchKernelGGL(k_batch_leapfrog, dim3(lf_grid), dim3(256), 0, s, tab, hdr);
+    hipLaunchKernelGGL(k_batch_deposit, dim3(ion_grid), dim3(256), 0, s, tab, hdr);
+    hipLaunchKernelGGL(k_batch_forces, dim3(ion_grid), dim3(256), 0, s, tab, hdr);
+    hipLaunchKernelGGL(k_batch_advance, dim3(4), dim3(256), 0, s, tab, hdr);
+    return hipGetLastError();
+}
+
+// Displacements of a seeded stream (the single-system seeded step and tests).
+__global__ void k_philox_disp(uint64_t seed, uint32_t t, int n, double sigma, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double du[3];
+    philox_displacement(seed, t, (uint32_t)i, sigma, du);
+    out[3 * i] = du[0];
+    out[3 * i + 1] = du[1];
+    out[3 * i + 2] = du[2];
+}
+
+hipError_t launch_philox_disp(hipStream_t s, uint64_t seed, uint32_t t, int n, double sigma, double *out) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_philox_disp, dim3((n + 255) / 256), dim3(256), 0, s, seed, t, n, sigma, out);
+    return hipGetLastError();
+}
+
+}  // namespace memd

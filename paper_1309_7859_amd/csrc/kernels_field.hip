@@ -1,220 +1,19 @@
 // kernels_field.hip -- lattice-field kernels for gfx950: the fused leapfrog
-// (Faraday + Ampere), energy and Gauss-audit reductions, permittivity maps.
-//
-// Leapfrog (eqs. faraday/bfield with E = D/eps, eqs. ampere/dfield):
-//   B^{n+1/2} = B^{n-1/2} - dt C(eta D^n)
-//   D*        = D^n + dt c^2 C^T B^{n+1/2}
-// with the discrete curl of the original lattice method:
-//   (C X)_d(v)   = [X_d2(v+e_d1) - X_d2(v) - X_d1(v+e_d2) + X_d1(v)] / a
-//   (C^T Y)_d(v) = [Y_d2(v) - Y_d2(v-e_d1) - Y_d1(v) + Y_d1(v-e_d2)] / a
-// One pass reads D, B (and eta) once and writes D, B once: the workgroup owns
-// a 64 x (4 R) column of sites and marches through a chunk of z planes,
-// staging eta*D of the current and next plane (with a one-site halo) and the
-// new B of the current plane (with a -1 halo) in LDS.  The new B of the
-// plane below stays in registers.  Input and output are separate buffers
-// (ping-pong), so tiles never see each other's results.
+// (Faraday + Ampere, body in leapfrog_tile.hpp), energy and Gauss-audit
+// reductions, permittivity maps, the salt-dependent permittivity.
 #include "device_util.hpp"
+#include "leapfrog_tile.hpp"
 #include "memd_internal.hpp"
 
 namespace memd {
 
-template <typename T>
-struct LfArgs {
-    const T *__restrict__ Din;
-    const T *__restrict__ Bin;
-    T *__restrict__ Dout;
-    T *__restrict__ Bout;
-    const T *__restrict__ eta_link;
-    const T *__restrict__ eta_prof;
-    T eta_uni;
-    T kB;  // dt / a
-    T kD;  // dt c^2 / a
-    int L;
-    size_t Ns;
-    int ntx, nty, tz;
-};
-
-template <typename T, int EM>
-__device__ __forceinline__ T eta_at(const LfArgs<T> &A, int d, int gz, size_t off) {
-    if constexpr (EM == ETA_UNIFORM) {
-        return A.eta_uni;
-    } else if constexpr (EM == ETA_ZPROF) {
-        return A.eta_prof[d * A.L + gz];
-    } else {
-        return A.eta_link[(size_t)d * A.Ns + off];
-    }
-}
-
 template <typename T, int EM, int R>
 __global__ __launch_bounds__(256) void k_leapfrog(LfArgs<T> A) {
-    constexpr int TX = 64, TY = 4 * R;
-    __shared__ T sX[2][3][TY + 2][TX + 2];
-    __shared__ T sB[3][TY + 1][TX + 1];
-
-    const int L = A.L;
-    const size_t Ns = A.Ns, LL = (size_t)L * L;
+    __shared__ LfSmem<T, R> S;
     const int logical = xcd_logical(blockIdx.x, gridDim.x);
     const int tile_x = logical % A.ntx;
     const int rest = logical / A.ntx;
-    const int tile_y = rest % A.nty;
-    const int chunk = rest / A.nty;
-    const int x0 = tile_x * TX, y0 = tile_y * TY, z0 = chunk * A.tz;
-    const int z1 = min(z0 + A.tz, L);
-    const int lx = threadIdx.x & 63, wy = threadIdx.x >> 6;
-    const int xx = lx + 1;
-    const int gx = wrapc(x0 + lx, L);
-    const bool xact = (x0 + lx) < L;
-    const T kB = A.kB, kD = A.kD;
-
-    int gyo[R];
-    bool act[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        gyo[r] = wrapc(y0 + wy + 4 * r, L);
-        act[r] = xact && (y0 + wy + 4 * r) < L;
-    }
-
-    // Stage eta*D of plane gz into sX[buf] (own sites, halo rows and columns);
-    // own D values go to Dreg.
-    auto load_plane = [&](int buf, int gz, T (&Dreg)[R][3]) {
-        const size_t zoff = (size_t)gz * LL;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const size_t off = zoff + (size_t)gyo[r] * L + gx;
-            const int yy = wy + 4 * r + 1;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const T v = A.Din[(size_t)d * Ns + off];
-                Dreg[r][d] = v;
-                sX[buf][d][yy][xx] = eta_at<T, EM>(A, d, gz, off) * v;
-            }
-        }
-        if (wy < 2) {
-            const int yy = wy ? TY + 1 : 0;
-            const int gy = wrapc(y0 - 1 + yy, L);
-            const size_t off = zoff + (size_t)gy * L + gx;
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-                sX[buf][d][yy][xx] = eta_at<T, EM>(A, d, gz, off) * A.Din[(size_t)d * Ns + off];
-        } else if (lx < TY + 2) {
-            const int xc = (wy == 2) ? 0 : TX + 1;
-            const int gxx = wrapc(x0 - 1 + xc, L);
-            const int gy = wrapc(y0 - 1 + lx, L);
-            const size_t off = zoff + (size_t)gy * L + gxx;
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-                sX[buf][d][lx][xc] = eta_at<T, EM>(A, d, gz, off) * A.Din[(size_t)d * Ns + off];
-        }
-    };
-
-    T Dc[R][3], Dn[R][3], prevB[R][2];
-
-    // Prologue: new B_x, B_y of the plane below the chunk, for the own sites.
-    {
-        const int gzp = wrapc(z0 - 1, L);
-        T dummy[R][3];
-        load_plane(0, gzp, dummy);
-        load_plane(1, z0, Dc);
-        T bo[R][2];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const size_t off = (size_t)gzp * LL + (size_t)gyo[r] * L + gx;
-            bo[r][0] = A.Bin[off];
-            bo[r][1] = A.Bin[Ns + off];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int yy = wy + 4 * r + 1;
-            prevB[r][0] = bo[r][0] - kB * (sX[0][2][yy + 1][xx] - sX[0][2][yy][xx] -
-                                           sX[1][1][yy][xx] + sX[0][1][yy][xx]);
-            prevB[r][1] = bo[r][1] - kB * (sX[1][0][yy][xx] - sX[0][0][yy][xx] -
-                                           sX[0][2][yy][xx + 1] + sX[0][2][yy][xx]);
-        }
-        __syncthreads();
-    }
-
-    int cur = 1;
-    for (int k = z0; k < z1; ++k) {
-        const int nxt = cur ^ 1;
-        const int gzn = wrapc(k + 1, L);
-        const size_t zoff = (size_t)k * LL;
-        load_plane(nxt, gzn, Dn);
-
-        T Bo[R][3];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const size_t off = zoff + (size_t)gyo[r] * L + gx;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) Bo[r][d] = A.Bin[(size_t)d * Ns + off];
-        }
-        // halo B^{n-1/2}: row y0-1 (B_x, B_z) on wave 0, column x0-1 (B_y, B_z) on wave 1
-        T hb0 = 0, hb1 = 0;
-        if (wy == 0) {
-            const size_t off = zoff + (size_t)wrapc(y0 - 1, L) * L + gx;
-            hb0 = A.Bin[off];
-            hb1 = A.Bin[2 * Ns + off];
-        } else if (wy == 1 && lx < TY) {
-            const size_t off = zoff + (size_t)wrapc(y0 + lx, L) * L + wrapc(x0 - 1, L);
-            hb0 = A.Bin[Ns + off];
-            hb1 = A.Bin[2 * Ns + off];
-        }
-        __syncthreads();
-
-        // Faraday: new B on the own sites
-        T Bn[R][3];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int yy = wy + 4 * r + 1;
-            Bn[r][0] = Bo[r][0] - kB * (sX[cur][2][yy + 1][xx] - sX[cur][2][yy][xx] -
-                                        sX[nxt][1][yy][xx] + sX[cur][1][yy][xx]);
-            Bn[r][1] = Bo[r][1] - kB * (sX[nxt][0][yy][xx] - sX[cur][0][yy][xx] -
-                                        sX[cur][2][yy][xx + 1] + sX[cur][2][yy][xx]);
-            Bn[r][2] = Bo[r][2] - kB * (sX[cur][1][yy][xx + 1] - sX[cur][1][yy][xx] -
-                                        sX[cur][0][yy + 1][xx] + sX[cur][0][yy][xx]);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) sB[d][yy][xx] = Bn[r][d];
-            if (act[r]) {
-                const size_t off = zoff + (size_t)gyo[r] * L + gx;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) A.Bout[(size_t)d * Ns + off] = Bn[r][d];
-            }
-        }
-        // Faraday on the -1 halo
-        if (wy == 0) {
-            sB[0][0][xx] = hb0 - kB * (sX[cur][2][1][xx] - sX[cur][2][0][xx] -
-                                       sX[nxt][1][0][xx] + sX[cur][1][0][xx]);
-            sB[2][0][xx] = hb1 - kB * (sX[cur][1][0][xx + 1] - sX[cur][1][0][xx] -
-                                       sX[cur][0][1][xx] + sX[cur][0][0][xx]);
-        } else if (wy == 1 && lx < TY) {
-            const int yy = lx + 1;
-            sB[1][yy][0] = hb0 - kB * (sX[nxt][0][yy][0] - sX[cur][0][yy][0] -
-                                       sX[cur][2][yy][1] + sX[cur][2][yy][0]);
-            sB[2][yy][0] = hb1 - kB * (sX[cur][1][yy][1] - sX[cur][1][yy][0] -
-                                       sX[cur][0][yy + 1][0] + sX[cur][0][yy][0]);
-        }
-        __syncthreads();
-
-        // Ampere: new D on the own sites
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int yy = wy + 4 * r + 1;
-            const T dx = Dc[r][0] + kD * (Bn[r][2] - sB[2][yy - 1][xx] - Bn[r][1] + prevB[r][1]);
-            const T dy = Dc[r][1] + kD * (Bn[r][0] - prevB[r][0] - Bn[r][2] + sB[2][yy][xx - 1]);
-            const T dz = Dc[r][2] + kD * (Bn[r][1] - sB[1][yy][xx - 1] - Bn[r][0] + sB[0][yy - 1][xx]);
-            if (act[r]) {
-                const size_t off = zoff + (size_t)gyo[r] * L + gx;
-                A.Dout[off] = dx;
-                A.Dout[Ns + off] = dy;
-                A.Dout[2 * Ns + off] = dz;
-            }
-            prevB[r][0] = Bn[r][0];
-            prevB[r][1] = Bn[r][1];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) Dc[r][d] = Dn[r][d];
-        }
-        cur = nxt;
-    }
+    leapfrog_tile<T, EM, R>(A, tile_x, rest % A.nty, rest / A.nty, S);
 }
 
 template <typename T, int EM>

@@ -2,92 +2,50 @@
 // assignment, dipole moment, corrected forces; deterministic finalisers of
 // the per-block partial sums; the lattice Green's function table.
 #include "device_util.hpp"
+#include "ion_ops.hpp"
 #include "memd_internal.hpp"
+#include "philox.hpp"
 
 namespace memd {
 
 // ----------------------------------------------------------- deposition
 
-// Current assignment that keeps Gauss's law (eq. constraint): each ion moves
-// by its displacement axis by axis (x, y, z), the others held at their
-// current values.  Along the moving axis the path is cut at cell faces; the
-// piece [ua, ub] inside cell kc carries the current q (ub - ua)/a onto the 4
-// links of that cell along d with the transverse linear weights:
-//   D_d(kc, c1 + o1, c2 + o2) -= q (ub - ua)/a * w(o1; f1) w(o2; f2) / a^2.
-// Accumulation into D uses hardware float/double atomics (the lattice is
-// sparse in ions, so contention is rare).  The block sums of q r^{n+1} (dipole)
-// are written to partials[3*block].  When spread_rho is set the new charge
-// assignment q w_v(r^{n+1}) is added to rho (FP64) for the Gauss audit.
+// The deposit kernel: threads take the ions in the order of `order` (binned
+// by lattice row, so that neighbouring threads update neighbouring links),
+// move each ion by its displacement while depositing its current, write the
+// new position, and form block sums of q r^{n+1} for the dipole moment.  When
+// spread_rho is set the new charge assignment is added to rho (FP64) for the
+// Gauss audit.
 template <typename T>
 __global__ __launch_bounds__(256) void k_deposit(int n, int L, size_t Ns, double a,
                                                  const double *__restrict__ q, double *__restrict__ r,
                                                  const double *__restrict__ disp, T *__restrict__ D,
                                                  int spread_rho, double *__restrict__ rho,
-                                                 double *__restrict__ partials) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+                                                 const int *__restrict__ order,
+                                                 double *__restrict__ partials, uint64_t seed, uint32_t t,
+                                                 double sigma) {
+    // consecutive (spatially sorted) slots stay on one XCD and share its L2
+    const int slot = xcd_logical(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     double P[3] = {0.0, 0.0, 0.0};
-    if (i < n) {
+    if (slot < n) {
+        const int i = order ? order[slot] : slot;
         const double qi = q[i];
-        const double a2 = a * a;
         double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-            int c1, c2;
-            double f1, f2;
-            fold(u[d1], a, L, c1, f1);
-            fold(u[d2], a, L, c2, f2);
-            const double u0 = u[d];
-            const double u1 = u0 + disp[3 * i + d];
-            if (u1 != u0) {
-                const double lo = u0 < u1 ? u0 : u1, hi = u0 < u1 ? u1 : u0;
-                const double sgn = u1 > u0 ? 1.0 : -1.0;
-                const long long klo = (long long)floor(lo / a), khi = (long long)floor(hi / a);
-                const int c1p = c1 + 1 == L ? 0 : c1 + 1, c2p = c2 + 1 == L ? 0 : c2 + 1;
-                for (long long kc = klo; kc <= khi; ++kc) {
-                    const double s0 = (double)kc * a, s1 = (double)(kc + 1) * a;
-                    const double sa = lo > s0 ? lo : s0;
-                    const double sb = hi < s1 ? hi : s1;
-                    const double len = sb - sa;
-                    if (!(len > 0.0)) continue;
-                    const double amount = qi * sgn * (len / a) / a2;
-                    long long km = kc % (long long)L;
-                    if (km < 0) km += L;
-                    int x[3];
-                    x[d] = (int)km;
-#pragma unroll
-                    for (int o2 = 0; o2 < 2; ++o2)
-#pragma unroll
-                        for (int o1 = 0; o1 < 2; ++o1) {
-                            x[d1] = o1 ? c1p : c1;
-                            x[d2] = o2 ? c2p : c2;
-                            const double val = amount * lin_w(o1, f1) * lin_w(o2, f2);
-                            unsafeAtomicAdd(&D[(size_t)d * Ns + site_index(x[0], x[1], x[2], L)], (T)(-val));
-                        }
-                }
-            }
-            u[d] = u1;
+        double du[3];
+        if (disp) {
+            du[0] = disp[3 * i];
+            du[1] = disp[3 * i + 1];
+            du[2] = disp[3 * i + 2];
+        } else {
+            philox_displacement(seed, t, (uint32_t)i, sigma, du);
         }
+        deposit_ion<T>(L, Ns, a, qi, u, du, D);
         r[3 * i] = u[0];
         r[3 * i + 1] = u[1];
         r[3 * i + 2] = u[2];
 #pragma unroll
         for (int d = 0; d < 3; ++d) P[d] = qi * u[d];
-        if (spread_rho) {
-            int cc[3];
-            double ff[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) fold(u[d], a, L, cc[d], ff[d]);
-#pragma unroll
-            for (int o = 0; o < 8; ++o) {
-                const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-                const double w = lin_w(ox, ff[0]) * lin_w(oy, ff[1]) * lin_w(oz, ff[2]);
-                const int xi = ox ? (cc[0] + 1 == L ? 0 : cc[0] + 1) : cc[0];
-                const int yi = oy ? (cc[1] + 1 == L ? 0 : cc[1] + 1) : cc[1];
-                const int zi = oz ? (cc[2] + 1 == L ? 0 : cc[2] + 1) : cc[2];
-                unsafeAtomicAdd(&rho[site_index(xi, yi, zi, L)], qi * w);
-            }
-        }
+        if (spread_rho) spread_ion(L, a, qi, u, rho);
     }
     block_sum<3>(P);
     if (threadIdx.x == 0) {
@@ -98,17 +56,21 @@ __global__ __launch_bounds__(256) void k_deposit(int n, int L, size_t Ns, double
 }
 
 static int ion_blocks(int n) { return n > 0 ? (n + kThreads - 1) / kThreads : 1; }
+// grid of the sorted-order ion kernels: a multiple of the 8 XCDs
+static int ion_blocks_x8(int n) { return (ion_blocks(n) + 7) / 8 * 8; }
 
 hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_rho,
-                          double *partials, int *nblk) {
-    const int nb = ion_blocks(c->n);
+                          double *partials, int *nblk, uint64_t seed, uint32_t t, double sigma) {
+    const int nb = ion_blocks_x8(c->n);
     *nblk = nb;
     if (c->fp32)
         hipLaunchKernelGGL(k_deposit<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
-                           c->q, c->r, disp, (float *)D, spread_rho ? 1 : 0, c->rho, partials);
+                           c->q, c->r, disp, (float *)D, spread_rho ? 1 : 0, c->rho, c->order, partials, seed, t,
+                           sigma);
     else
         hipLaunchKernelGGL(k_deposit<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
-                           c->q, c->r, disp, (double *)D, spread_rho ? 1 : 0, c->rho, partials);
+                           c->q, c->r, disp, (double *)D, spread_rho ? 1 : 0, c->rho, c->order, partials, seed, t,
+                           sigma);
     return hipGetLastError();
 }
 
@@ -120,20 +82,8 @@ __global__ __launch_bounds__(256) void k_spread(int n, int L, double a, const do
                                                 const double *__restrict__ r, double *__restrict__ dst) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double qi = q ? q[i] : 1.0;
-    int cc[3];
-    double ff[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) fold(r[3 * i + d], a, L, cc[d], ff[d]);
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-        const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-        const double w = lin_w(ox, ff[0]) * lin_w(oy, ff[1]) * lin_w(oz, ff[2]);
-        const int xi = ox ? (cc[0] + 1 == L ? 0 : cc[0] + 1) : cc[0];
-        const int yi = oy ? (cc[1] + 1 == L ? 0 : cc[1] + 1) : cc[1];
-        const int zi = oz ? (cc[2] + 1 == L ? 0 : cc[2] + 1) : cc[2];
-        unsafeAtomicAdd(&dst[site_index(xi, yi, zi, L)], qi * w);
-    }
+    const double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
+    spread_ion(L, a, q ? q[i] : 1.0, u, dst);
 }
 
 hipError_t launch_spread(memd_ctx *c, const double *charges_or_null, double *dst) {
@@ -179,91 +129,48 @@ struct ForceArgs {
     const T *D, *eta_link, *eta_prof;
     double eta_uni;
     int mode;
-    const double *scal;  // P, eps_h, G
+    double *scal;        // P, eps_h, G
     double *F;
     double *uself_partials;  // optional: per-block sums of the self energy
+    const int *order;        // optional: ion order (binned by lattice row)
+    const double *dip_partials;  // optional: deposit's per-block q r sums -> P
+    int dip_nblk;
 };
 
-template <typename T>
-__device__ __forceinline__ double eta_f(const ForceArgs<T> &A, int d, int k, size_t off) {
-    if (A.mode == ETA_UNIFORM) return A.eta_uni;
-    if (A.mode == ETA_ZPROF) return (double)A.eta_prof[d * A.L + k];
-    return (double)A.eta_link[(size_t)d * A.Ns + off];
-}
-
-// Cell self-energy sum S(f) = sum_{o,o'} w_o w_o' G(o - o') and its gradient:
-// per axis, equal corners weigh alpha = 1 - beta, different corners
-// beta = 2 f (1 - f); G depends on the number of differing axes.
-__device__ __forceinline__ void self_sum(const double *G, const double f[3], double &S, double dS[3]) {
-    double be[3], al[3], db[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        be[d] = 2.0 * f[d] * (1.0 - f[d]);
-        al[d] = 1.0 - be[d];
-        db[d] = 2.0 - 4.0 * f[d];
-    }
-    S = 0.0;
-    dS[0] = dS[1] = dS[2] = 0.0;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const int m0 = m & 1, m1 = (m >> 1) & 1, m2 = m >> 2;
-        const double g = G[m0 + m1 + m2];
-        const double f0 = m0 ? be[0] : al[0], f1 = m1 ? be[1] : al[1], f2 = m2 ? be[2] : al[2];
-        const double g0 = m0 ? db[0] : -db[0], g1 = m1 ? db[1] : -db[1], g2 = m2 ? db[2] : -db[2];
-        S += g * f0 * f1 * f2;
-        dS[0] += g * g0 * f1 * f2;
-        dS[1] += g * f0 * g1 * f2;
-        dS[2] += g * f0 * f1 * g2;
-    }
-}
-
-// F_i = q_i sum_{4 d-links of the cell} w w E_d  (eq. force without v x B; F = +qE)
-//       - F_self (lattice Green's-function self force, eps_cell = harmonic mean
-//         of the cell's 12 edges)
-//       + q_i P_d / (V eps_h_d)  (dipole correction, section "Periodicity").
+// Forces on every ion (ion_ops.hpp: force_ion); threads follow `order`.
 template <typename T>
 __global__ __launch_bounds__(256) void k_forces(ForceArgs<T> A) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double Psh[3];
+    if (A.dip_partials) {
+        // every block forms P from the deposit's partial sums in the same fixed
+        // order; block 0 also stores it for the energy and the dipole queries
+        double s[3] = {0.0, 0.0, 0.0};
+        for (int b = threadIdx.x; b < A.dip_nblk; b += blockDim.x)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) s[d] += A.dip_partials[3 * b + d];
+        block_sum<3>(s);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                Psh[d] = s[d];
+                if (blockIdx.x == 0) A.scal[S_P + d] = s[d];
+            }
+        }
+    } else if (threadIdx.x < 3) {
+        Psh[threadIdx.x] = A.scal[S_P + threadIdx.x];
+    }
+    __syncthreads();
+    const int slot = xcd_logical(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     double us = 0.0;
-    if (i < A.n) {
-        const int L = A.L;
-        int c[3];
-        double f[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) fold(A.r[3 * i + d], A.a, L, c[d], f[d]);
-        const int cp[3] = {c[0] + 1 == L ? 0 : c[0] + 1, c[1] + 1 == L ? 0 : c[1] + 1,
-                           c[2] + 1 == L ? 0 : c[2] + 1};
-        const double qi = A.q[i];
-        double Flat[3];
-        double etasum = 0.0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-            double s = 0.0;
-#pragma unroll
-            for (int o2 = 0; o2 < 2; ++o2)
-#pragma unroll
-                for (int o1 = 0; o1 < 2; ++o1) {
-                    int x[3] = {c[0], c[1], c[2]};
-                    x[d1] = o1 ? cp[d1] : c[d1];
-                    x[d2] = o2 ? cp[d2] : c[d2];
-                    const size_t off = site_index(x[0], x[1], x[2], L);
-                    const double e = eta_f(A, d, x[2], off);
-                    etasum += e;
-                    s += lin_w(o1, f[d1]) * lin_w(o2, f[d2]) * (e * (double)A.D[(size_t)d * A.Ns + off]);
-                }
-            Flat[d] = qi * s;
-        }
-        const double eps_cell = 12.0 / etasum;
-        double S, dS[3];
-        self_sum(A.scal + S_G, f, S, dS);
-        const double pref = qi * qi / (2.0 * eps_cell * A.a);
-        us = pref * S;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double Fself = -pref * dS[d] / A.a;
-            A.F[3 * i + d] = Flat[d] - Fself + qi * A.scal[S_P + d] / (A.V * A.scal[S_EPSH + d]);
-        }
+    if (slot < A.n) {
+        const int i = A.order ? A.order[slot] : slot;
+        const double u[3] = {A.r[3 * i], A.r[3 * i + 1], A.r[3 * i + 2]};
+        EtaView<T> ev{A.mode, A.eta_uni, A.eta_prof, A.eta_link};
+        double F[3];
+        us = force_ion<T>(A.L, A.Ns, A.a, A.V, A.q[i], u, A.D, ev, A.scal + S_G, Psh, A.scal + S_EPSH, F);
+        A.F[3 * i] = F[0];
+        A.F[3 * i + 1] = F[1];
+        A.F[3 * i + 2] = F[2];
     }
     if (A.uself_partials) {
         double s[1] = {us};
@@ -290,31 +197,116 @@ static ForceArgs<T> force_args(memd_ctx *c, const void *D) {
     A.scal = c->scal;
     A.F = c->F;
     A.uself_partials = nullptr;
+    A.order = c->order;
+    A.dip_partials = nullptr;
+    A.dip_nblk = 0;
     return A;
 }
 
-hipError_t launch_forces(memd_ctx *c, const void *D) {
+hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk) {
     if (c->n == 0) return hipSuccess;
-    const int nb = ion_blocks(c->n);
-    if (c->fp32)
-        hipLaunchKernelGGL(k_forces<float>, dim3(nb), dim3(kThreads), 0, c->stream, force_args<float>(c, D));
-    else
-        hipLaunchKernelGGL(k_forces<double>, dim3(nb), dim3(kThreads), 0, c->stream, force_args<double>(c, D));
+    const int nb = ion_blocks_x8(c->n);
+    if (c->fp32) {
+        auto A = force_args<float>(c, D);
+        A.dip_partials = dip_partials;
+        A.dip_nblk = dip_nblk;
+        hipLaunchKernelGGL(k_forces<float>, dim3(nb), dim3(kThreads), 0, c->stream, A);
+    } else {
+        auto A = force_args<double>(c, D);
+        A.dip_partials = dip_partials;
+        A.dip_nblk = dip_nblk;
+        hipLaunchKernelGGL(k_forces<double>, dim3(nb), dim3(kThreads), 0, c->stream, A);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- ion binning
+
+// Counting sort of the ions by lattice row (y, z cell of the position): the
+// deposit and force kernels then visit neighbouring ions together.
+__global__ void k_bin_count(int n, int L, double a, const double *__restrict__ r, int *__restrict__ count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cy, cz;
+    double f;
+    fold(r[3 * i + 1], a, L, cy, f);
+    fold(r[3 * i + 2], a, L, cz, f);
+    atomicAdd(&count[cy + L * cz], 1);
+}
+
+// Exclusive scan of count[0..nb) into cursor[0..nb) (one block of 1024):
+// the bins are taken in tiles of 1024, each scanned with wavefront prefix
+// sums plus a pass over the 16 wavefront totals.
+__global__ __launch_bounds__(1024) void k_bin_scan(const int *__restrict__ count, int nb, int *__restrict__ cursor) {
+    __shared__ int wsum[16];
+    __shared__ int carry;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += 1024) {
+        const int v = (base + t < nb) ? count[base + t] : 0;
+        int x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        int before = carry;
+        for (int w = 0; w < wid; ++w) before += wsum[w];
+        if (base + t < nb) cursor[base + t] = before + x - v;
+        __syncthreads();
+        if (t == 1023) carry = before + x;
+        __syncthreads();
+    }
+}
+
+__global__ void k_bin_scatter(int n, int L, double a, const double *__restrict__ r, int *__restrict__ cursor,
+                              int *__restrict__ order) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cy, cz;
+    double f;
+    fold(r[3 * i + 1], a, L, cy, f);
+    fold(r[3 * i + 2], a, L, cz, f);
+    const int slot = atomicAdd(&cursor[cy + L * cz], 1);
+    order[slot] = i;
+}
+
+__global__ void k_fill_int(int *dst, int v, size_t count) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < count; t += (size_t)gridDim.x * blockDim.x)
+        dst[t] = v;
+}
+
+hipError_t launch_bin_ions(memd_ctx *c) {
+    if (c->n == 0 || !c->order) return hipSuccess;
+    const int nb = c->L * c->L;
+    const int g = (int)((nb + kThreads - 1) / kThreads) < 4096 ? (nb + kThreads - 1) / kThreads : 4096;
+    int *count = c->bins, *cursor = c->bins + nb;
+    hipLaunchKernelGGL(k_fill_int, dim3(g), dim3(kThreads), 0, c->stream, count, 0, (size_t)nb);
+    hipLaunchKernelGGL(k_bin_count, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->r,
+                       count);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, count, nb, cursor);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
+                       c->r, cursor, c->order);
     return hipGetLastError();
 }
 
 // Self energies (through the force kernel, writing the same forces again).
 hipError_t launch_uself(memd_ctx *c, double *partials, int *nblk) {
-    const int nb = ion_blocks(c->n);
+    const int nb = ion_blocks_x8(c->n);
     *nblk = nb;
     const void *D = c->D[c->cur];
     if (c->fp32) {
         auto A = force_args<float>(c, D);
         A.uself_partials = partials;
+        A.order = nullptr;  // index order: the self-energy sum is then deterministic
         hipLaunchKernelGGL(k_forces<float>, dim3(nb), dim3(kThreads), 0, c->stream, A);
     } else {
         auto A = force_args<double>(c, D);
         A.uself_partials = partials;
+        A.order = nullptr;
         hipLaunchKernelGGL(k_forces<double>, dim3(nb), dim3(kThreads), 0, c->stream, A);
     }
     return hipGetLastError();

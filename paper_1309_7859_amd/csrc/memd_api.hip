@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "memd_internal.hpp"
+#include "serve_internal.hpp"
 
 using namespace memd;
 
@@ -74,7 +75,7 @@ hipError_t ensure_stage(memd_ctx *c, size_t bytes) {
 }
 
 void prof_begin(memd_ctx *c, int fam) {
-    if (!c->prof_on) return;
+    if (!c->prof_on || !(c->prof_mask & (1u << fam))) return;
     hipEvent_t e;
     if (hipEventCreate(&e) == hipSuccess) {
         hipEventRecord(e, c->stream);
@@ -83,7 +84,7 @@ void prof_begin(memd_ctx *c, int fam) {
 }
 
 void prof_end(memd_ctx *c, int fam) {
-    if (!c->prof_on) return;
+    if (!c->prof_on || !(c->prof_mask & (1u << fam))) return;
     hipEvent_t e;
     if (hipEventCreate(&e) == hipSuccess) {
         hipEventRecord(e, c->stream);
@@ -173,7 +174,7 @@ hipError_t enqueue_dipole_forces(memd_ctx *c) {
     if ((e = launch_finalize_dipole(c->stream, c->partials, nb, c->scal + S_P)) != hipSuccess) return e;
     prof_end(c, F_DIPOLE);
     prof_begin(c, F_FORCES);
-    e = launch_forces(c, c->D[c->cur]);
+    e = launch_forces(c, c->D[c->cur], nullptr, 0);
     prof_end(c, F_FORCES);
     return e;
 }
@@ -204,6 +205,7 @@ void memd_destroy(memd_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     prof_clear(c);
     void *bufs[] = {c->D[0], c->D[1], c->B[0], c->B[1], c->eta_prof, c->eta_link, c->q, c->r, c->F,
+                    c->order, c->bins,
                     c->stage, c->rho, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt,
                     c->salt_nbar};
     for (void *b : bufs)
@@ -237,6 +239,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     c->tsize = c->fp32 ? sizeof(float) : sizeof(double);
     c->lf_rows = 2;
     c->lf_tz = 16;
+    c->sort_every = 8;
     c->hist_cap = kHistCap;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -282,6 +285,8 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
         hipMalloc((void **)&c->q, nn * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->r, 3 * nn * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->F, 3 * nn * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->order, nn * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&c->bins, 2 * (size_t)p->L * p->L * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->rho, Ns * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->partials, partial_doubles(n) * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->scal, S_COUNT * sizeof(double)) != hipSuccess ||
@@ -304,6 +309,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
             (void)hipGetLastError();
             return fail(MEMD_EINVAL);
         }
+        if (launch_bin_ions(c) != hipSuccess) return fail(MEMD_EDEVICE);
     }
     // permittivity 1 everywhere until set
     c->eta_mode = ETA_UNIFORM;
@@ -417,19 +423,14 @@ memd_status memd_initial_gauss_solve(memd_ctx *c, double tol, int max_iter, int 
     return st;
 }
 
-memd_status memd_step(memd_ctx *c, const double *disp, int nsteps) {
-    CHECK_CTX(c);
-    if (!c->ready) return MEMD_ESTATE;
-    if (nsteps < 0) return MEMD_EINVAL;
-    if (nsteps == 0) return MEMD_OK;
-    if (c->n > 0 && !disp) return MEMD_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// The per-step launch sequence (displacements from disp, or from the Philox
+// stream of `seed` when disp is null).
+memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, double sigma) {
     const size_t per = 3 * (size_t)c->n;
-    const double *dd = disp;
-    if (c->n > 0 && !is_device_ptr(disp)) {
-        CK(ensure_stage(c, per * nsteps * sizeof(double)));
-        CK(copy_in(c, c->stage, disp, per * nsteps * sizeof(double)));
-        dd = c->stage;
-    }
     for (int t = 0; t < nsteps; ++t) {
         if (c->salt_every > 0 && c->step_index % c->salt_every == 0) {
             prof_begin(c, F_SALT);
@@ -444,13 +445,14 @@ memd_status memd_step(memd_ctx *c, const double *disp, int nsteps) {
         const bool audit_now = c->p.audit_every > 0 && next % c->p.audit_every == 0;
         const bool energy_now = c->p.energy_every > 0 && next % c->p.energy_every == 0;
         int nb = 0;
+        if (c->sort_every > 0 && c->step_index % c->sort_every == 0) CK(launch_bin_ions(c));
         prof_begin(c, F_DEPOSIT);
-        CK(launch_deposit(c, c->D[nx], dd + per * t, audit_now, c->partials, &nb));
-        CK(launch_finalize_dipole(c->stream, c->partials, nb, c->scal + S_P));
+        CK(launch_deposit(c, c->D[nx], dd ? dd + per * t : nullptr, audit_now, c->partials, &nb, seed,
+                          (uint32_t)c->step_index, sigma));
         prof_end(c, F_DEPOSIT);
         c->cur = nx;
         prof_begin(c, F_FORCES);
-        CK(launch_forces(c, c->D[c->cur]));
+        CK(launch_forces(c, c->D[c->cur], c->partials, nb));
         prof_end(c, F_FORCES);
         if (audit_now) {
             const int slot = c->hist_audit_n < c->hist_cap ? c->hist_audit_n : c->hist_cap - 1;
@@ -464,8 +466,50 @@ memd_status memd_step(memd_ctx *c, const double *disp, int nsteps) {
         }
         c->step_index = next;
     }
+    return MEMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+memd_status memd_step(memd_ctx *c, const double *disp, int nsteps) {
+    CHECK_CTX(c);
+    if (!c->ready) return MEMD_ESTATE;
+    if (nsteps < 0) return MEMD_EINVAL;
+    if (nsteps == 0) return MEMD_OK;
+    if (c->n > 0 && !disp) return MEMD_EINVAL;
+    const size_t per = 3 * (size_t)c->n;
+    const double *dd = disp;
+    if (c->n > 0 && !is_device_ptr(disp)) {
+        CK(ensure_stage(c, per * nsteps * sizeof(double)));
+        CK(copy_in(c, c->stage, disp, per * nsteps * sizeof(double)));
+        dd = c->stage;
+    }
+    memd_status st = run_steps(c, c->n > 0 ? dd : nullptr, nsteps, 0, 0.0);
+    if (st != MEMD_OK) return st;
     if (dd != disp) CK(hipStreamSynchronize(c->stream));  // the staging buffer is reused
     return MEMD_OK;
+}
+
+memd_status memd_step_seeded(memd_ctx *c, uint64_t seed, double sigma, int nsteps) {
+    CHECK_CTX(c);
+    if (!c->ready) return MEMD_ESTATE;
+    if (nsteps < 0 || !(sigma >= 0.0) || !std::isfinite(sigma)) return MEMD_EINVAL;
+    return run_steps(c, nullptr, nsteps, seed, sigma);
+}
+
+memd_status memd_seeded_displacements(uint64_t seed, int step, int n, double sigma, double *out) {
+    if (n < 0 || step < 0 || !(sigma >= 0.0) || (n > 0 && !out)) return MEMD_EINVAL;
+    if (n == 0) return MEMD_OK;
+    double *d = nullptr;
+    if (hipMalloc((void **)&d, 3 * (size_t)n * sizeof(double)) != hipSuccess) return MEMD_ENOMEM;
+    memd_status st = MEMD_OK;
+    if (launch_philox_disp(nullptr, seed, (uint32_t)step, n, sigma, d) != hipSuccess ||
+        hipMemcpy(out, d, 3 * (size_t)n * sizeof(double), hipMemcpyDefault) != hipSuccess)
+        st = MEMD_EDEVICE;
+    hipFree(d);
+    return st;
 }
 
 memd_status memd_forces(memd_ctx *c, double *F_out) {
@@ -561,7 +605,10 @@ memd_status memd_set_state(memd_ctx *c, const double *D, const double *B, const 
         CK(copy_in(c, c->stage, B, M * sizeof(double)));
         CK(launch_cast(c->stream, c->stage, c->B[c->cur], M, c->fp32));
     }
-    if (r) CK(copy_in(c, c->r, r, 3 * (size_t)c->n * sizeof(double)));
+    if (r) {
+        CK(copy_in(c, c->r, r, 3 * (size_t)c->n * sizeof(double)));
+        CK(launch_bin_ions(c));
+    }
     if (!c->c_fixed) {
         c->c = 0.25 * (c->a / c->dt) * std::sqrt(c->eps_min / 3.0);
         c->c_fixed = true;
@@ -598,6 +645,7 @@ memd_status memd_profile_enable(memd_ctx *c, int enable) {
     CK(hipStreamSynchronize(c->stream));
     prof_clear(c);
     c->prof_on = enable != 0;
+    c->prof_mask = enable == 1 ? 0xffffffffu : (unsigned)enable;
     return MEMD_OK;
 }
 
@@ -616,6 +664,106 @@ memd_status memd_profile_read(memd_ctx *c, int family, double *total_ms, long *l
     if (total_ms) *total_ms = tot;
     if (launches) *launches = (long)m;
     return MEMD_OK;
+}
+
+}  // extern "C"
+
+// Tile-shape autotuner of the leapfrog kernel.  Each candidate (rows per
+// thread x planes per z-chunk) is launched `reps` times on the context's own
+// buffers and timed with HIP events; the leapfrog writes only the inactive
+// ping-pong buffers, so the state is untouched.  The winner is kept in the
+// context and, when cache_path is given, in a text cache keyed by lattice
+// size, precision and permittivity representation.
+memd_status memd::autotune_leapfrog(memd_ctx *c, int reps, const char *cache_path, int max_rows, int *rows_out,
+                                    int *planes_out, double *us_out) {
+    CHECK_CTX(c);
+    if (reps <= 0) reps = 10;
+    char key[112];
+    snprintf(key, sizeof(key), "leapfrog L=%d prec=%d eta=%d rmax=%d", c->L, c->fp32 ? 1 : 0, c->eta_mode,
+             max_rows);
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "r");
+        if (f) {
+            char line[256];
+            int br = 0, bp = 0;
+            double bu = 0.0;
+            bool hit = false;
+            while (fgets(line, sizeof(line), f)) {
+                const size_t kl = strlen(key);
+                if (strncmp(line, key, kl) == 0 && line[kl] == ' ') {
+                    int rr = 0, pp = 0;
+                    double uu = 0.0;
+                    if (sscanf(line + kl, " rows=%d planes=%d us=%lf", &rr, &pp, &uu) == 3 &&
+                        (rr == 1 || rr == 2 || rr == 4) && pp >= 1) {
+                        br = rr;
+                        bp = pp;
+                        bu = uu;
+                        hit = true;
+                    }
+                }
+            }
+            fclose(f);
+            if (hit) {
+                c->lf_rows = br;
+                c->lf_tz = bp;
+                if (rows_out) *rows_out = br;
+                if (planes_out) *planes_out = bp;
+                if (us_out) *us_out = bu;
+                return MEMD_OK;
+            }
+        }
+    }
+    const int rows_c[3] = {1, 2, 4};
+    const int planes_c[6] = {2, 4, 8, 16, 32, 64};
+    int best_r = c->lf_rows, best_p = c->lf_tz;
+    double best_us = HUGE_VAL;
+    hipEvent_t e0, e1;
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    const int nx = c->cur ^ 1;
+    for (int ri = 0; ri < 3; ++ri)
+        for (int pi = 0; pi < 6; ++pi) {
+            if (rows_c[ri] > max_rows) continue;
+            const int pl = planes_c[pi];
+            if (pl > c->L && pi > 0) continue;
+            c->lf_rows = rows_c[ri];
+            c->lf_tz = pl;
+            CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx]));
+            CK(hipEventRecord(e0, c->stream));
+            for (int t = 0; t < reps; ++t) CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx]));
+            CK(hipEventRecord(e1, c->stream));
+            CK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            CK(hipEventElapsedTime(&ms, e0, e1));
+            const double us = 1e3 * ms / reps;
+            if (us < best_us) {
+                best_us = us;
+                best_r = rows_c[ri];
+                best_p = pl;
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->lf_rows = best_r;
+    c->lf_tz = best_p;
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s rows=%d planes=%d us=%.3f\n", key, best_r, best_p, best_us);
+            fclose(f);
+        }
+    }
+    if (rows_out) *rows_out = best_r;
+    if (planes_out) *planes_out = best_p;
+    if (us_out) *us_out = best_us;
+    return MEMD_OK;
+}
+
+extern "C" {
+
+memd_status memd_autotune(memd_ctx *c, int reps, const char *cache_path, int *rows_out, int *planes_out,
+                          double *us_out) {
+    return autotune_leapfrog(c, reps, cache_path, 4, rows_out, planes_out, us_out);
 }
 
 memd_status memd_set_tiling(memd_ctx *c, int rows, int planes) {

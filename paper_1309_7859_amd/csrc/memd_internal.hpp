@@ -83,6 +83,9 @@ struct memd_ctx {
     double *q;     // [n]
     double *r;     // [3n]
     double *F;     // [3n]
+    int *order;    // [n] ion visiting order (binned by lattice row), refreshed every sort_every steps
+    int *bins;     // [2 L^2] bin counts and cursors
+    int sort_every;
     double *stage;       // FP64 staging buffer for host inputs / FP32 casts
     size_t stage_bytes;
 
@@ -105,6 +108,7 @@ struct memd_ctx {
 
     // profiling
     bool prof_on;
+    unsigned prof_mask;
     memd::ProfileEvents prof[memd::F_NFAM];
 };
 
@@ -125,11 +129,14 @@ hipError_t launch_salt(memd_ctx *c);
 hipError_t launch_fill(hipStream_t s, double *dst, double v, size_t count);
 
 // ---- launchers (ion kernels) ----
+// disp == nullptr: displacements from the Philox stream (seed, step t, sigma)
 hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_rho,
-                          double *partials, int *nblk);
+                          double *partials, int *nblk, uint64_t seed = 0, uint32_t t = 0,
+                          double sigma = 0.0);
 hipError_t launch_spread(memd_ctx *c, const double *charges_or_null, double *dst);
 hipError_t launch_dipole(memd_ctx *c, double *partials, int *nblk);
-hipError_t launch_forces(memd_ctx *c, const void *D);
+hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk);
+hipError_t launch_bin_ions(memd_ctx *c);
 hipError_t launch_uself(memd_ctx *c, double *partials, int *nblk);
 
 // ---- launchers (reductions / finalisers) ----
@@ -147,6 +154,10 @@ hipError_t launch_finalize_dipole(hipStream_t s, const double *partials, int nbl
 hipError_t launch_finalize_epsh(hipStream_t s, const double *partials, int nblk, double Ns,
                                 double *epsh, double *etamax);
 hipError_t launch_greens(memd_ctx *c, double *G);
+
+// tile autotuner with a bound on the rows per thread (the batched kernel holds <= 2)
+memd_status autotune_leapfrog(memd_ctx *c, int reps, const char *cache_path, int max_rows, int *rows_out,
+                              int *planes_out, double *us_out);
 
 // ---- initial solve (FP64) ----
 hipError_t solve_recursion(memd_ctx *c, double *D);

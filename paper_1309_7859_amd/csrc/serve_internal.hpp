@@ -1,0 +1,41 @@
+// serve_internal.hpp -- the device-resident replica table read by the batched
+// kernels (one entry per resident replica, ordered by item offsets).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace memd {
+
+struct RepDesc {
+    // geometry and tiling
+    int L, n;
+    int rows, tz;          // leapfrog tile: 64 x (4 rows) sites, tz planes per chunk
+    int ntx, nty, nzc;
+    int tiles, iblocks;    // leapfrog work items, ion blocks of 256
+    int tile_off, ion_off; // first item of this replica in the global item ranges
+    int eta_mode;          // ETA_UNIFORM or ETA_ZPROF
+    int nsteps;
+    float eta_uni, kB, kD; // 1/eps, dt/a, dt c^2/a
+    double a, V, sigma;
+    uint64_t seed;
+    // buffers (owned by the replica's context)
+    float *D[2];
+    float *B[2];
+    const float *eta_prof;
+    const double *q;
+    double *r;
+    double *F;
+    double *scal;  // P, eps_h, G of the replica
+    double *dip;   // [3 * iblocks] partial sums of q r
+    int *step;     // steps done (device counter)
+};
+
+// table header on the device: {count, total leapfrog tiles, total ion blocks}
+constexpr int kHdrInts = 4;
+
+hipError_t launch_batch_step(hipStream_t s, const RepDesc *tab, const int *hdr, int lf_grid, int ion_grid);
+hipError_t launch_philox_disp(hipStream_t s, uint64_t seed, uint32_t t, int n, double sigma, double *out);
+
+}  // namespace memd

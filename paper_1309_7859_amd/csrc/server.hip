@@ -1,0 +1,492 @@
+// server.hip -- continuous-batching server of independent MEMD replicas.
+//
+// Requests (lattice size, ions, permittivity profile, step count, seed of the
+// displacement stream) are queued on submit.  Admission is by device-memory
+// budget and slot count: an admitted request is initialised by a worker thread
+// on a stream of its own (context, permittivity, FP64 initial solve, tile
+// autotune), which overlaps with the batched steps of the resident replicas.
+// Each global step advances every resident replica by one time step with one
+// replay of a captured HIP graph (batched leapfrog, deposit, forces, counter
+// advance); the replica table the graph reads lives in device memory and is
+// rewritten between replays when replicas join or leave.  Finished replicas
+// are retired (forces, energy, Gauss audit copied out, memory returned) and
+// their slots reused.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "memd_internal.hpp"
+#include "serve_internal.hpp"
+
+using namespace memd;
+
+namespace {
+
+enum ReqState { Q_PENDING = 0, Q_INIT = 1, Q_READY = 2, Q_ACTIVE = 3, Q_DONE = 4, Q_FAILED = 5 };
+
+struct Request {
+    uint64_t id;
+    memd_params p;
+    int n;
+    std::vector<double> q, r0, eps;
+    int eps_mode;
+    int nsteps;
+    uint64_t seed;
+    double sigma;
+    double t_arrival = 0.0, t_admit = 0.0, t_ready = 0.0, t_done = 0.0;
+    int state = Q_PENDING;
+    memd_status error = MEMD_OK;
+    memd_ctx *ctx = nullptr;
+    size_t bytes_resident = 0, bytes_peak = 0;
+    int rows = 2, tz = 8;
+    double *dip = nullptr;
+    int slot = -1;
+    std::vector<double> F;
+    memd_energy_t E{};
+    double gauss = 0.0;
+};
+
+size_t resident_bytes(int L, int n) {
+    const size_t Ns = (size_t)L * L * L;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    return 4 * 3 * Ns * sizeof(float)            // D, B ping-pong
+           + Ns * sizeof(double)                 // rho
+           + 2 * (size_t)L * L * sizeof(int)     // bins
+           + nn * (7 * sizeof(double) + sizeof(int))
+           + (2 + 5) * 4096 * sizeof(double)     // histories
+           + 3 * (size_t)L * sizeof(float) + (1 << 16);
+}
+
+size_t solve_bytes(int L) {
+    const size_t Ns = (size_t)L * L * L;
+    return (8 * 3 + 3) * Ns * sizeof(double);  // CG work vectors + the FP64 D being solved
+}
+
+}  // namespace
+
+struct memd_server {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    size_t budget = 0, used = 0;
+    int max_slots = 0;
+    int slots_used = 0;       // admitted and not yet retired
+    double solve_tol = 1e-8;
+    std::string tune_cache;
+    std::chrono::steady_clock::time_point t0;
+
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stopping = false;
+    std::vector<std::thread> workers;
+    std::deque<Request *> init_queue;   // admitted, waiting for a worker
+    std::deque<Request *> pending;      // waiting for admission
+    std::vector<Request *> ready;       // initialised, waiting to join the table
+    std::map<uint64_t, std::unique_ptr<Request>> all;
+    std::vector<Request *> active;      // resident replicas (table order)
+    uint64_t next_id = 1;
+
+    RepDesc *d_tab = nullptr;
+    int *d_hdr = nullptr;
+    int *d_steps = nullptr;       // one counter per slot
+    RepDesc *h_tab = nullptr;     // pinned mirrors
+    int *h_hdr = nullptr;
+    int *h_steps = nullptr;
+    std::vector<int> free_slots;
+    bool table_dirty = true;
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int lf_grid = 2048, ion_grid = 1024;
+
+    long global_steps = 0, replica_steps = 0, done_count = 0, failed_count = 0;
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+void worker_main(memd_server *s) {
+    hipSetDevice(s->device);
+    for (;;) {
+        Request *rq = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait(lk, [&] { return s->stopping || !s->init_queue.empty(); });
+            if (s->stopping) return;
+            rq = s->init_queue.front();
+            s->init_queue.pop_front();
+        }
+        memd_status st = memd_init_lattice(&rq->ctx, &rq->p, rq->n, rq->q.data(), rq->r0.data(), nullptr);
+        if (st == MEMD_OK) st = memd_set_permittivity(rq->ctx, rq->eps_mode, rq->eps.data(), 4.0);
+        if (st == MEMD_OK) st = memd_initial_gauss_solve(rq->ctx, s->solve_tol, 0, nullptr, nullptr);
+        if (st == MEMD_OK) {
+            const char *cache = s->tune_cache.empty() ? nullptr : s->tune_cache.c_str();
+            // the batched leapfrog holds tiles of 1 or 2 rows per thread
+            st = autotune_leapfrog(rq->ctx, 5, cache, 2, &rq->rows, &rq->tz, nullptr);
+        }
+        if (st == MEMD_OK) {
+            const int ib = rq->n > 0 ? (rq->n + 255) / 256 : 1;
+            if (hipMalloc((void **)&rq->dip, 3 * (size_t)ib * sizeof(double)) != hipSuccess) st = MEMD_ENOMEM;
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        rq->t_ready = s->now();
+        if (st == MEMD_OK) {
+            rq->state = Q_READY;
+            s->ready.push_back(rq);
+            s->used -= (rq->bytes_peak - rq->bytes_resident);
+        } else {
+            rq->state = Q_FAILED;
+            rq->error = st;
+            rq->t_done = rq->t_ready;
+            if (rq->ctx) memd_destroy(rq->ctx);
+            rq->ctx = nullptr;
+            s->used -= rq->bytes_peak;
+            --s->slots_used;
+            ++s->failed_count;
+        }
+    }
+}
+
+// Admission: pending requests join the init queue, in arrival order, while
+// device memory (peak need: resident buffers plus the solver's work vectors)
+// and slots allow.
+void admit(memd_server *s) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    while (!s->pending.empty()) {
+        Request *rq = s->pending.front();
+        if (s->slots_used >= s->max_slots) break;
+        if (s->used + rq->bytes_peak > s->budget) break;
+        s->pending.pop_front();
+        s->used += rq->bytes_peak;
+        ++s->slots_used;
+        rq->state = Q_INIT;
+        rq->t_admit = s->now();
+        s->init_queue.push_back(rq);
+    }
+    s->cv.notify_all();
+}
+
+void fill_desc(const Request *rq, int slot, int *d_steps, RepDesc &d) {
+    memd_ctx *c = rq->ctx;
+    d.L = c->L;
+    d.n = c->n;
+    d.rows = rq->rows;
+    d.tz = rq->tz;
+    d.ntx = (c->L + 63) / 64;
+    d.nty = (c->L + 4 * d.rows - 1) / (4 * d.rows);
+    d.nzc = (c->L + d.tz - 1) / d.tz;
+    d.tiles = d.ntx * d.nty * d.nzc;
+    d.iblocks = c->n > 0 ? (c->n + 255) / 256 : 1;
+    d.eta_mode = c->eta_mode;
+    d.nsteps = rq->nsteps;
+    d.eta_uni = (float)c->eta_uni;
+    d.kB = (float)(c->dt / c->a);
+    d.kD = (float)(c->dt * c->c * c->c / c->a);
+    d.a = c->a;
+    d.V = c->V;
+    d.sigma = rq->sigma;
+    d.seed = rq->seed;
+    d.D[0] = (float *)c->D[0];
+    d.D[1] = (float *)c->D[1];
+    d.B[0] = (float *)c->B[0];
+    d.B[1] = (float *)c->B[1];
+    d.eta_prof = (const float *)c->eta_prof;
+    d.q = c->q;
+    d.r = c->r;
+    d.F = c->F;
+    d.scal = c->scal;
+    d.dip = rq->dip;
+    d.step = d_steps + slot;
+}
+
+hipError_t upload_table(memd_server *s) {
+    int toff = 0, ioff = 0;
+    for (size_t k = 0; k < s->active.size(); ++k) {
+        Request *rq = s->active[k];
+        RepDesc &d = s->h_tab[k];
+        fill_desc(rq, rq->slot, s->d_steps, d);
+        d.tile_off = toff;
+        d.ion_off = ioff;
+        toff += d.tiles;
+        ioff += d.iblocks;
+    }
+    s->h_hdr[0] = (int)s->active.size();
+    s->h_hdr[1] = toff;
+    s->h_hdr[2] = ioff;
+    s->h_hdr[3] = 0;
+    hipError_t e;
+    if (!s->active.empty())
+        if ((e = hipMemcpyAsync(s->d_tab, s->h_tab, s->active.size() * sizeof(RepDesc), hipMemcpyHostToDevice,
+                                s->stream)) != hipSuccess)
+            return e;
+    if ((e = hipMemcpyAsync(s->d_hdr, s->h_hdr, kHdrInts * sizeof(int), hipMemcpyHostToDevice, s->stream)) !=
+        hipSuccess)
+        return e;
+    s->table_dirty = false;
+    return hipSuccess;
+}
+
+hipError_t ensure_graph(memd_server *s) {
+    if (s->exec) return hipSuccess;
+    hipError_t e;
+    if ((e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    launch_batch_step(s->stream, s->d_tab, s->d_hdr, s->lf_grid, s->ion_grid);
+    if ((e = hipStreamEndCapture(s->stream, &s->graph)) != hipSuccess) return e;
+    return hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0);
+}
+
+// Join initialised replicas (slot, zeroed step counter).
+hipError_t join_ready(memd_server *s) {
+    std::vector<Request *> joining;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        joining.swap(s->ready);
+    }
+    for (Request *rq : joining) {
+        rq->slot = s->free_slots.back();
+        s->free_slots.pop_back();
+        s->h_steps[rq->slot] = 0;
+        hipError_t e = hipMemcpyAsync(s->d_steps + rq->slot, s->h_steps + rq->slot, sizeof(int),
+                                      hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return e;
+        rq->state = Q_ACTIVE;
+        s->active.push_back(rq);
+        s->table_dirty = true;
+    }
+    return hipSuccess;
+}
+
+// Retire finished replicas: results out, context destroyed, memory and slot freed.
+hipError_t retire(memd_server *s) {
+    std::vector<Request *> keep;
+    for (Request *rq : s->active) {
+        const int st = s->h_steps[rq->slot];
+        if (st < rq->nsteps) {
+            keep.push_back(rq);
+            continue;
+        }
+        memd_ctx *c = rq->ctx;
+        c->cur = rq->nsteps & 1;
+        c->step_index = rq->nsteps;
+        rq->F.assign(3 * (size_t)rq->n, 0.0);
+        memd_status ms = memd_forces(c, rq->F.data());
+        if (ms == MEMD_OK) ms = memd_energy(c, &rq->E);
+        if (ms == MEMD_OK) ms = memd_gauss_residual(c, &rq->gauss, nullptr);
+        bool finite = std::isfinite(rq->E.E_corrected);
+        for (double f : rq->F) finite = finite && std::isfinite(f);
+        rq->t_done = s->now();
+        rq->state = (ms == MEMD_OK && finite) ? Q_DONE : Q_FAILED;
+        rq->error = ms != MEMD_OK ? ms : (finite ? MEMD_OK : MEMD_EDEVICE);
+        memd_destroy(c);
+        rq->ctx = nullptr;
+        hipFree(rq->dip);
+        rq->dip = nullptr;
+        s->free_slots.push_back(rq->slot);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->used -= rq->bytes_resident;
+            --s->slots_used;
+            if (rq->state == Q_DONE) ++s->done_count;
+            else ++s->failed_count;
+        }
+        s->table_dirty = true;
+    }
+    s->active.swap(keep);
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+memd_status memd_server_create(memd_server **out, size_t hbm_budget_bytes, int max_slots, int init_workers,
+                               double solve_tol, const char *tune_cache, void *hip_stream) {
+    if (!out || hbm_budget_bytes == 0 || max_slots <= 0 || init_workers <= 0 || init_workers > 64)
+        return MEMD_EINVAL;
+    *out = nullptr;
+    memd_server *s = new (std::nothrow) memd_server();
+    if (!s) return MEMD_ENOMEM;
+    s->budget = hbm_budget_bytes;
+    s->max_slots = max_slots;
+    s->solve_tol = solve_tol > 0.0 ? solve_tol : 1e-8;
+    if (tune_cache) s->tune_cache = tune_cache;
+    s->t0 = std::chrono::steady_clock::now();
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return MEMD_EDEVICE;
+    }
+    if (hip_stream) {
+        s->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete s;
+            return MEMD_EDEVICE;
+        }
+        s->own_stream = true;
+    }
+    if (hipMalloc((void **)&s->d_tab, (size_t)max_slots * sizeof(RepDesc)) != hipSuccess ||
+        hipMalloc((void **)&s->d_hdr, kHdrInts * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&s->d_steps, (size_t)max_slots * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_tab, (size_t)max_slots * sizeof(RepDesc), 0) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_hdr, kHdrInts * sizeof(int), 0) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_steps, (size_t)max_slots * sizeof(int), 0) != hipSuccess) {
+        memd_server_destroy(s);
+        return MEMD_ENOMEM;
+    }
+    memset(s->h_hdr, 0, kHdrInts * sizeof(int));
+    memset(s->h_steps, 0, (size_t)max_slots * sizeof(int));
+    for (int k = max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
+    if (upload_table(s) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess) {
+        memd_server_destroy(s);
+        return MEMD_EDEVICE;
+    }
+    for (int w = 0; w < init_workers; ++w) s->workers.emplace_back(worker_main, s);
+    *out = s;
+    return MEMD_OK;
+}
+
+memd_status memd_server_submit(memd_server *s, const memd_params *p, int n, const double *q, const double *r0,
+                               int eps_mode, const double *eps, int nsteps, uint64_t seed, double sigma,
+                               uint64_t *req_id) {
+    if (!s || !p || !req_id || n < 0 || nsteps < 0 || (n > 0 && (!q || !r0)) || !eps || !(sigma >= 0.0))
+        return MEMD_EINVAL;
+    if (eps_mode != MEMD_EPS_UNIFORM && eps_mode != MEMD_EPS_ZSITE) return MEMD_EINVAL;
+    if (p->L < 2 || p->L > 1024) return MEMD_EINVAL;
+    auto rq = std::make_unique<Request>();
+    rq->p = *p;
+    rq->p.precision = MEMD_FP32_MIXED;
+    rq->p.audit_every = 0;
+    rq->p.energy_every = 0;
+    rq->n = n;
+    rq->q.assign(q, q + n);
+    rq->r0.assign(r0, r0 + 3 * (size_t)n);
+    const size_t ne = eps_mode == MEMD_EPS_UNIFORM ? 1 : (size_t)p->L;
+    rq->eps.assign(eps, eps + ne);
+    rq->eps_mode = eps_mode;
+    rq->nsteps = nsteps;
+    rq->seed = seed;
+    rq->sigma = sigma;
+    rq->bytes_resident = resident_bytes(p->L, n);
+    rq->bytes_peak = rq->bytes_resident + solve_bytes(p->L);
+    std::lock_guard<std::mutex> lk(s->mu);
+    rq->id = s->next_id++;
+    rq->t_arrival = s->now();
+    *req_id = rq->id;
+    if (rq->bytes_peak > s->budget) {
+        rq->state = Q_FAILED;
+        rq->error = MEMD_ENOMEM;
+        rq->t_done = rq->t_arrival;
+        ++s->failed_count;
+    } else {
+        s->pending.push_back(rq.get());
+    }
+    s->all[rq->id] = std::move(rq);
+    return MEMD_OK;
+}
+
+memd_status memd_server_progress(memd_server *s, int global_steps, int *active, int *pending, int *done) {
+    if (!s || global_steps < 0) return MEMD_EINVAL;
+    if (hipSetDevice(s->device) != hipSuccess) return MEMD_EDEVICE;
+    admit(s);
+    if (join_ready(s) != hipSuccess) return MEMD_EDEVICE;
+    if (s->table_dirty) {
+        if (upload_table(s) != hipSuccess) return MEMD_EDEVICE;
+        if (s->active.empty() && hipStreamSynchronize(s->stream) != hipSuccess) return MEMD_EDEVICE;
+    }
+    if (!s->active.empty() && global_steps > 0) {
+        if (ensure_graph(s) != hipSuccess) return MEMD_EDEVICE;
+        for (int t = 0; t < global_steps; ++t)
+            if (hipGraphLaunch(s->exec, s->stream) != hipSuccess) return MEMD_EDEVICE;
+        s->global_steps += global_steps;
+        if (hipMemcpyAsync(s->h_steps, s->d_steps, (size_t)s->max_slots * sizeof(int), hipMemcpyDeviceToHost,
+                           s->stream) != hipSuccess)
+            return MEMD_EDEVICE;
+        if (hipStreamSynchronize(s->stream) != hipSuccess) return MEMD_EDEVICE;
+        if (retire(s) != hipSuccess) return MEMD_EDEVICE;
+        admit(s);
+    } else if (s->active.empty()) {
+        // nothing resident: let the workers run
+        std::this_thread::sleep_for(std::chrono::microseconds(200));
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (active) *active = (int)s->active.size();
+    if (pending) *pending = (int)(s->pending.size() + s->init_queue.size() + s->ready.size());
+    if (done) *done = (int)(s->done_count + s->failed_count);
+    return MEMD_OK;
+}
+
+memd_status memd_server_poll(memd_server *s, uint64_t req_id, int *state, double *F_out, memd_energy_t *E_out,
+                             double *gauss_max, double *t_arrival, double *t_done) {
+    if (!s) return MEMD_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(req_id);
+    if (it == s->all.end()) return MEMD_EINVAL;
+    Request *rq = it->second.get();
+    if (state) *state = rq->state;
+    if (t_arrival) *t_arrival = rq->t_arrival;
+    if (t_done) *t_done = rq->t_done;
+    if (rq->state == Q_DONE) {
+        if (F_out && !rq->F.empty()) memcpy(F_out, rq->F.data(), rq->F.size() * sizeof(double));
+        if (E_out) *E_out = rq->E;
+        if (gauss_max) *gauss_max = rq->gauss;
+    }
+    if (rq->state == Q_FAILED) return rq->error;
+    return MEMD_OK;
+}
+
+memd_status memd_server_stats(memd_server *s, long *global_steps, long *replica_steps, size_t *bytes_in_use) {
+    if (!s) return MEMD_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    long rs = 0;
+    for (const auto &kv : s->all)
+        if (kv.second->state == Q_DONE) rs += kv.second->nsteps;
+    if (global_steps) *global_steps = s->global_steps;
+    if (replica_steps) *replica_steps = rs;
+    if (bytes_in_use) *bytes_in_use = s->used;
+    return MEMD_OK;
+}
+
+memd_status memd_server_destroy(memd_server *s) {
+    if (!s) return MEMD_EINVAL;
+    hipSetDevice(s->device);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->cv.notify_all();
+    for (auto &t : s->workers) t.join();
+    if (s->stream) hipStreamSynchronize(s->stream);
+    for (auto &kv : s->all) {
+        Request *rq = kv.second.get();
+        if (rq->ctx) memd_destroy(rq->ctx);
+        if (rq->dip) hipFree(rq->dip);
+    }
+    if (s->exec) hipGraphExecDestroy(s->exec);
+    if (s->graph) hipGraphDestroy(s->graph);
+    if (s->d_tab) hipFree(s->d_tab);
+    if (s->d_hdr) hipFree(s->d_hdr);
+    if (s->d_steps) hipFree(s->d_steps);
+    if (s->h_tab) hipHostFree(s->h_tab);
+    if (s->h_hdr) hipHostFree(s->h_hdr);
+    if (s->h_steps) hipHostFree(s->h_steps);
+    if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+    delete s;
+    return MEMD_OK;
+}
+
+}  // extern "C"

@@ -71,6 +71,16 @@ def load():
         "memd_profile_enable": [vp, i],
         "memd_profile_read": [vp, i, dp, C.POINTER(C.c_long)],
         "memd_set_tiling": [vp, i, i],
+        "memd_autotune": [vp, i, C.c_char_p, C.POINTER(i), C.POINTER(i), dp],
+        "memd_step_seeded": [vp, C.c_uint64, d, i],
+        "memd_seeded_displacements": [C.c_uint64, i, i, d, vp],
+        "memd_server_create": [C.POINTER(vp), C.c_size_t, i, i, d, C.c_char_p, vp],
+        "memd_server_submit": [vp, C.POINTER(memd_params), i, vp, vp, i, vp, i, C.c_uint64, d,
+                               C.POINTER(C.c_uint64)],
+        "memd_server_progress": [vp, i, C.POINTER(i), C.POINTER(i), C.POINTER(i)],
+        "memd_server_poll": [vp, C.c_uint64, C.POINTER(i), vp, C.POINTER(memd_energy_t), dp, dp, dp],
+        "memd_server_stats": [vp, C.POINTER(C.c_long), C.POINTER(C.c_long), C.POINTER(C.c_size_t)],
+        "memd_server_destroy": [vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -227,6 +237,83 @@ def memd_profile_read(ctx: int, family) -> tuple:
 
 def memd_set_tiling(ctx: int, rows_per_thread: int = 0, planes_per_chunk: int = 0):
     _check(load().memd_set_tiling(ctx, rows_per_thread, planes_per_chunk), "memd_set_tiling")
+
+
+def memd_autotune(ctx: int, reps: int = 10, cache_path: str | None = None):
+    rr = C.c_int()
+    pp = C.c_int()
+    us = C.c_double()
+    path = cache_path.encode() if cache_path else None
+    _check(load().memd_autotune(ctx, reps, path, C.byref(rr), C.byref(pp), C.byref(us)),
+           "memd_autotune")
+    return rr.value, pp.value, us.value
+
+
+def memd_step_seeded(ctx: int, seed: int, sigma: float, nsteps: int):
+    _check(load().memd_step_seeded(ctx, int(seed), float(sigma), int(nsteps)), "memd_step_seeded")
+
+
+def memd_seeded_displacements(seed: int, step: int, n: int, sigma: float) -> np.ndarray:
+    out = np.zeros(3 * n)
+    _check(load().memd_seeded_displacements(int(seed), int(step), int(n), float(sigma), _addr(out)),
+           "memd_seeded_displacements")
+    return out.reshape(n, 3)
+
+
+# ---------------------------------------------------------------- serving
+
+REQ_PENDING, REQ_INIT, REQ_READY, REQ_ACTIVE, REQ_DONE, REQ_FAILED = range(6)
+
+
+def memd_server_create(hbm_budget_bytes: int, max_slots: int = 512, init_workers: int = 4,
+                       solve_tol: float = 1e-8, tune_cache: str | None = None, hip_stream=None) -> int:
+    srv = C.c_void_p()
+    _check(load().memd_server_create(C.byref(srv), int(hbm_budget_bytes), int(max_slots),
+                                     int(init_workers), float(solve_tol),
+                                     tune_cache.encode() if tune_cache else None, hip_stream),
+           "memd_server_create")
+    return srv.value
+
+
+def memd_server_submit(srv: int, params: memd_params, q, r0, eps_mode: int, eps, nsteps: int,
+                       seed: int, sigma: float) -> int:
+    q, r0, eps = _f64(q), _f64(r0), _f64(np.atleast_1d(eps))
+    rid = C.c_uint64()
+    _check(load().memd_server_submit(srv, C.byref(params), len(q), _addr(q), _addr(r0), eps_mode,
+                                     _addr(eps), int(nsteps), int(seed), float(sigma), C.byref(rid)),
+           "memd_server_submit")
+    return rid.value
+
+
+def memd_server_progress(srv: int, global_steps: int):
+    a, p, f = C.c_int(), C.c_int(), C.c_int()
+    _check(load().memd_server_progress(srv, int(global_steps), C.byref(a), C.byref(p), C.byref(f)),
+           "memd_server_progress")
+    return a.value, p.value, f.value
+
+
+def memd_server_poll(srv: int, req_id: int, n: int):
+    """Returns (state, status, F (n,3) or None, energy dict or None, gauss, t_arrival, t_done)."""
+    st = C.c_int()
+    F = np.zeros(3 * max(n, 1))
+    E = memd_energy_t()
+    g, ta, td = C.c_double(), C.c_double(), C.c_double()
+    status = load().memd_server_poll(srv, int(req_id), C.byref(st), _addr(F), C.byref(E), C.byref(g),
+                                     C.byref(ta), C.byref(td))
+    done = st.value == REQ_DONE
+    return (st.value, status, F[:3 * n].reshape(n, 3) if done else None,
+            E.as_dict() if done else None, g.value, ta.value, td.value)
+
+
+def memd_server_stats(srv: int):
+    gs, rs, by = C.c_long(), C.c_long(), C.c_size_t()
+    _check(load().memd_server_stats(srv, C.byref(gs), C.byref(rs), C.byref(by)), "memd_server_stats")
+    return gs.value, rs.value, by.value
+
+
+def memd_server_destroy(srv: int):
+    if srv:
+        _check(load().memd_server_destroy(srv), "memd_server_destroy")
 
 
 def memd_destroy(ctx: int):

@@ -295,3 +295,27 @@ def test_error_codes():
     with pytest.raises(memd.MemdError) as e:
         memd.memd_set_tiling(G.ctx, 3, 0)
     assert e.value.status == memd.EINVAL
+
+
+def test_autotune_keeps_state_and_caches(tmp_path):
+    """The autotuner leaves the state alone, picks a valid tile and reuses its cache."""
+    L = 32
+    rng, q, r = _rng_system(13, 40, L)
+    G = memd.Context(L, q, r)
+    G.set_permittivity(memd.EPS_UNIFORM, [2.0])
+    G.solve()
+    before = G.state()
+    cache = str(tmp_path / "tiles.txt")
+    rows, planes, us = memd.memd_autotune(G.ctx, 3, cache)
+    assert rows in (1, 2, 4) and planes >= 1 and us > 0
+    after = G.state()
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    assert open(cache).read().count("leapfrog L=32") == 1
+    rows2, planes2, _ = memd.memd_autotune(G.ctx, 3, cache)
+    assert (rows2, planes2) == (rows, planes)
+    assert open(cache).read().count("leapfrog L=32") == 1
+    disp = rng.normal(0, 0.05, size=(3, 40, 3))
+    G.step(disp, 3)
+    m, _ = G.gauss_residual()
+    assert m <= 1e-12

@@ -500,3 +500,31 @@ def test_image_force_planar_interface(orc):
         pred = qp / (4 * math.pi * eps1 * (2 * d) ** 2)
         assert dF > 0
         assert abs(dF - pred) <= 0.10 * pred, (d, dF, pred)
+
+
+# ------------------------------------------------------- seeded displacements
+
+def test_philox_known_answers(orc):
+    """The oracle's Philox4x32-10 reproduces the published known-answer vectors."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for w in rows:
+        v = [int(x, 16) for x in w]
+        assert orc.philox4x32_10(v[0:4], v[4:6]) == v[6:10]
+
+
+def test_seeded_displacements_are_standard_normal(orc):
+    """Box-Muller on 53-bit uniforms: moments of N(0, sigma^2), independent
+    components, and a different stream for a different seed or step."""
+    n = 100000
+    d = orc.seeded_displacements(2024, 3, n, 0.5)
+    assert np.all(np.abs(d.mean(0)) < 0.5 * 5 / np.sqrt(n))
+    assert np.allclose(d.std(0), 0.5, rtol=0.01)
+    assert np.allclose(np.mean(d ** 4, 0) / 0.5 ** 4, 3.0, rtol=0.05)
+    c = np.corrcoef(d.T)
+    assert np.max(np.abs(c - np.eye(3))) < 0.02
+    assert not np.array_equal(d, orc.seeded_displacements(2025, 3, n, 0.5))
+    assert not np.array_equal(d, orc.seeded_displacements(2024, 4, n, 0.5))
+    assert np.array_equal(d, orc.seeded_displacements(2024, 3, n, 0.5))
