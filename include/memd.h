@@ -251,6 +251,8 @@ memd_status memd_server_poll(memd_server *srv, uint64_t req_id, int *state, doub
 memd_status memd_server_stats(memd_server *srv, long *global_steps, long *replica_steps,
                               size_t *bytes_in_use);
 memd_status memd_server_destroy(memd_server *srv);
+/* Text of the last device error a server call returned (empty if none). */
+const char *memd_server_last_error(memd_server *srv);
 
 #ifdef __cplusplus
 }

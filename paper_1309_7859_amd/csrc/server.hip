@@ -112,6 +112,7 @@ struct memd_server {
     int lf_grid = 2048, ion_grid = 1024;
 
     long global_steps = 0, replica_steps = 0, done_count = 0, failed_count = 0;
+    char last_error[160] = {0};
 
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -241,13 +242,19 @@ hipError_t upload_table(memd_server *s) {
     return hipSuccess;
 }
 
-hipError_t ensure_graph(memd_server *s) {
-    if (s->exec) return hipSuccess;
+// The step graph reads the replica table from device memory, so it is
+// captured once, when the server is created (before any worker runs).
+hipError_t capture_graph(memd_server *s) {
     hipError_t e;
-    if ((e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    if ((e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
     launch_batch_step(s->stream, s->d_tab, s->d_hdr, s->lf_grid, s->ion_grid);
     if ((e = hipStreamEndCapture(s->stream, &s->graph)) != hipSuccess) return e;
     return hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0);
+}
+
+memd_status fail_dev(memd_server *s, const char *what, hipError_t e) {
+    snprintf(s->last_error, sizeof(s->last_error), "%s: %s", what, hipGetErrorString(e));
+    return MEMD_EDEVICE;
 }
 
 // Join initialised replicas (slot, zeroed step counter).
@@ -351,7 +358,8 @@ memd_status memd_server_create(memd_server **out, size_t hbm_budget_bytes, int m
     memset(s->h_hdr, 0, kHdrInts * sizeof(int));
     memset(s->h_steps, 0, (size_t)max_slots * sizeof(int));
     for (int k = max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
-    if (upload_table(s) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess) {
+    if (upload_table(s) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess ||
+        capture_graph(s) != hipSuccess) {
         memd_server_destroy(s);
         return MEMD_EDEVICE;
     }
@@ -401,23 +409,24 @@ memd_status memd_server_submit(memd_server *s, const memd_params *p, int n, cons
 
 memd_status memd_server_progress(memd_server *s, int global_steps, int *active, int *pending, int *done) {
     if (!s || global_steps < 0) return MEMD_EINVAL;
-    if (hipSetDevice(s->device) != hipSuccess) return MEMD_EDEVICE;
+    hipError_t e;
+    if ((e = hipSetDevice(s->device)) != hipSuccess) return fail_dev(s, "hipSetDevice", e);
     admit(s);
-    if (join_ready(s) != hipSuccess) return MEMD_EDEVICE;
+    if ((e = join_ready(s)) != hipSuccess) return fail_dev(s, "join", e);
     if (s->table_dirty) {
-        if (upload_table(s) != hipSuccess) return MEMD_EDEVICE;
-        if (s->active.empty() && hipStreamSynchronize(s->stream) != hipSuccess) return MEMD_EDEVICE;
+        if ((e = upload_table(s)) != hipSuccess) return fail_dev(s, "table upload", e);
+        if (s->active.empty() && (e = hipStreamSynchronize(s->stream)) != hipSuccess)
+            return fail_dev(s, "table sync", e);
     }
     if (!s->active.empty() && global_steps > 0) {
-        if (ensure_graph(s) != hipSuccess) return MEMD_EDEVICE;
         for (int t = 0; t < global_steps; ++t)
-            if (hipGraphLaunch(s->exec, s->stream) != hipSuccess) return MEMD_EDEVICE;
+            if ((e = hipGraphLaunch(s->exec, s->stream)) != hipSuccess) return fail_dev(s, "hipGraphLaunch", e);
         s->global_steps += global_steps;
-        if (hipMemcpyAsync(s->h_steps, s->d_steps, (size_t)s->max_slots * sizeof(int), hipMemcpyDeviceToHost,
-                           s->stream) != hipSuccess)
-            return MEMD_EDEVICE;
-        if (hipStreamSynchronize(s->stream) != hipSuccess) return MEMD_EDEVICE;
-        if (retire(s) != hipSuccess) return MEMD_EDEVICE;
+        if ((e = hipMemcpyAsync(s->h_steps, s->d_steps, (size_t)s->max_slots * sizeof(int),
+                                hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
+            return fail_dev(s, "step counters", e);
+        if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return fail_dev(s, "step sync", e);
+        if ((e = retire(s)) != hipSuccess) return fail_dev(s, "retire", e);
         admit(s);
     } else if (s->active.empty()) {
         // nothing resident: let the workers run
@@ -425,10 +434,13 @@ memd_status memd_server_progress(memd_server *s, int global_steps, int *active, 
     }
     std::lock_guard<std::mutex> lk(s->mu);
     if (active) *active = (int)s->active.size();
-    if (pending) *pending = (int)(s->pending.size() + s->init_queue.size() + s->ready.size());
+    // queued: waiting for admission, or admitted and not yet resident
+    if (pending) *pending = (int)s->pending.size() + s->slots_used - (int)s->active.size();
     if (done) *done = (int)(s->done_count + s->failed_count);
     return MEMD_OK;
 }
+
+const char *memd_server_last_error(memd_server *s) { return s ? s->last_error : ""; }
 
 memd_status memd_server_poll(memd_server *s, uint64_t req_id, int *state, double *F_out, memd_energy_t *E_out,
                              double *gauss_max, double *t_arrival, double *t_done) {

@@ -91,6 +91,8 @@ def load():
     lib.memd_strerror.argtypes = [C.c_int]
     lib.memd_strerror.restype = C.c_char_p
     lib.memd_version.restype = C.c_int
+    lib.memd_server_last_error.argtypes = [vp]
+    lib.memd_server_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -287,9 +289,14 @@ def memd_server_submit(srv: int, params: memd_params, q, r0, eps_mode: int, eps,
 
 def memd_server_progress(srv: int, global_steps: int):
     a, p, f = C.c_int(), C.c_int(), C.c_int()
-    _check(load().memd_server_progress(srv, int(global_steps), C.byref(a), C.byref(p), C.byref(f)),
-           "memd_server_progress")
+    st = load().memd_server_progress(srv, int(global_steps), C.byref(a), C.byref(p), C.byref(f))
+    if st != OK:
+        raise MemdError(st, "memd_server_progress (" + memd_server_last_error(srv) + ")")
     return a.value, p.value, f.value
+
+
+def memd_server_last_error(srv: int) -> str:
+    return (load().memd_server_last_error(srv) or b"").decode()
 
 
 def memd_server_poll(srv: int, req_id: int, n: int):
