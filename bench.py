@@ -162,10 +162,15 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--fp64-steps", type=int, default=200,
                     help="steps of the FP64 variant reported beside the main line (0 = skip)")
-    ap.add_argument("--cpu-steps", type=int, default=30, help="oracle sample size (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=100, help="oracle sample size (0 = skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
     ap.add_argument("--tile", type=str, default="", help="rows,planes of the leapfrog tile")
+    ap.add_argument("--serve-count", type=int, default=512,
+                    help="replicas in the serving stream (0 = skip the serving measurement)")
+    ap.add_argument("--serve-rate", type=float, default=500.0, help="Poisson arrival rate (1/s)")
+    ap.add_argument("--serve-fp64-count", type=int, default=24,
+                    help="replicas of the same stream run one by one on the FP64 single-system path")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -238,7 +243,43 @@ def main():
                       f"recompute + 1 audit + 1 energy amortised at 1/50, FP64, from the recursion "
                       f"solution; {cb['total']:.1f} s of CPU work",
             "ion_steps_per_s": round(w.n / cb["per_step"], 1)}
+    if args.serve_count > 0:
+        out["serving"] = serving_run(args.serve_count, args.serve_rate, args.serve_fp64_count)
     print(json.dumps(out), flush=True)
+
+
+def serving_run(count, rate, fp64_count):
+    """Workload c5: a Poisson stream of independent replicas (L in {16, 24, 32,
+    48, 64}, ion counts log-uniform in [100, 8000], uniform or tanh-slab eps in
+    [2, 80], 100-2000 steps each, sigma = 0.02 a), served by the batched FP32
+    server under a 200 GB budget; beside it the first fp64_count replicas of
+    the same stream run one after another on the plain FP64 single-system path."""
+    from paper_1309_7859_amd import serve
+    from paper_1309_7859_amd import workloads as W
+
+    specs = W.serving_stream(count, rate)
+    tune_cache = os.path.join(ROOT, "_build_tune_cache.txt")
+    if os.path.exists(tune_cache):
+        os.remove(tune_cache)
+    r = serve.run_stream(specs, 200 << 30, max_slots=count, workers=8, poll_steps=4,
+                         tune_cache=tune_cache)
+    if os.path.exists(tune_cache):
+        os.remove(tune_cache)
+    out = {"workload": f"c5: {count} replicas, Poisson {rate:g}/s, L in (16,24,32,48,64), "
+                       "n 100-8000, uniform or tanh-slab eps, 100-2000 steps, FP32, 200 GB budget",
+           "replica_steps_per_s": round(r["replica_steps_per_s"], 1),
+           "site_updates_per_s": round(r["site_updates_per_s"], 1),
+           "p50_latency_s": round(r["p50"], 4), "p99_latency_s": round(r["p99"], 4),
+           "makespan_s": round(r["makespan"], 3), "done": r["done"], "failed": r["failed"],
+           "global_steps": r["global_steps"]}
+    if fp64_count > 0:
+        b = serve.run_sequential_fp64(specs[:fp64_count])
+        out["fp64_single_system_baseline"] = {
+            "replicas": fp64_count, "replica_steps_per_s": round(b["replica_steps_per_s"], 1),
+            "site_updates_per_s": round(b["site_updates_per_s"], 1),
+            "p50_latency_s": round(b["p50"], 4), "p99_latency_s": round(b["p99"], 4),
+            "makespan_s": round(b["makespan"], 3)}
+    return out
 
 
 if __name__ == "__main__":

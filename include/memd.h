@@ -198,6 +198,20 @@ memd_status memd_profile_read(memd_ctx *ctx, int family, double *total_ms, long 
  * 0 keeps the current value. */
 memd_status memd_set_tiling(memd_ctx *ctx, int rows_per_thread, int planes_per_chunk);
 
+/* Options of the step.  fuse_deposit = 1 (default): on lattices of 16 or
+ * more sites per side the current deposit of ions that move less than a per
+ * axis (and stay within one row of where they were last binned) runs inside
+ * the leapfrog kernel, each tile adding the contributions to the links it
+ * owns; the other ions, and every ion when fuse_deposit = 0, deposit with
+ * global atomics.  sort_every: steps between re-binnings of the ions by
+ * lattice row (default 8; 0 = never after the first).  Both forms give the
+ * same result up to the order of floating-point additions. */
+memd_status memd_set_options(memd_ctx *ctx, int fuse_deposit, int sort_every);
+/* bad_moves: displacement components rejected so far (not finite, or longer
+ * than (L + 1024) a; they are taken as 0).  fused_path: 1 if the next
+ * step runs the fused deposit.  Either may be NULL. */
+memd_status memd_counters(memd_ctx *ctx, unsigned long *bad_moves, int *fused_path);
+
 /* Tile-shape autotuner of the leapfrog kernel: times every candidate shape
  * (reps launches each, HIP events) on the context's buffers without changing
  * its state, keeps the fastest, and appends it to the text cache at

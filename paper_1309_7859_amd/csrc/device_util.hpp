@@ -27,6 +27,19 @@ __device__ __forceinline__ void fold(double u, double a, int L, int &c, double &
     c = (int)m;
 }
 
+// The same fold with u/a formed as u * inv_a when a is a power of two (then
+// the product is exactly the quotient, so every cell decision is unchanged).
+__device__ __forceinline__ void fold_fast(double u, double a, double inv_a, bool a_pow2, int L, int &c,
+                                          double &f) {
+    const double t = a_pow2 ? u * inv_a : u / a;
+    const double fl = floor(t);
+    f = t - fl;
+    long long k = (long long)fl;
+    long long m = k % (long long)L;
+    if (m < 0) m += L;
+    c = (int)m;
+}
+
 __device__ __forceinline__ double lin_w(int o, double f) { return o ? f : 1.0 - f; }
 
 __device__ __forceinline__ size_t site_index(int i, int j, int k, int L) {

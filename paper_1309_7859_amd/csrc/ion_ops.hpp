@@ -23,6 +23,19 @@ struct EtaView {
     }
 };
 
+// A displacement component that is not finite or longer than (L + 1024) a is
+// not a move the method can take in one step: it is replaced by 0 and counted
+// in *bad (when given), which bounds every face-crossing loop.
+__device__ __forceinline__ void sanitize_move(double (&du)[3], double a, int L, unsigned int *bad) {
+    const double lim = ((double)L + 1024.0) * a;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        if (!(fabs(du[d]) <= lim)) {
+            du[d] = 0.0;
+            if (bad) atomicAdd(bad, 1u);
+        }
+}
+
 // Current assignment that keeps Gauss's law (eq. constraint): the ion moves by
 // du axis by axis (x, y, z), the others held at their current values.  Along
 // the moving axis the path is cut at cell faces; the piece [ua, ub] inside
@@ -68,6 +81,55 @@ __device__ __forceinline__ void deposit_ion(int L, size_t Ns, double a, double q
                         const double val = amount * lin_w(o1, f1) * lin_w(o2, f2);
                         unsafeAtomicAdd(&D[(size_t)d * Ns + site_index(x[0], x[1], x[2], L)], (T)(-val));
                     }
+            }
+        }
+        u[d] = u1;
+    }
+}
+
+// One lane's share of deposit_ion: the same dimension-split walk, but only the
+// links of axis `dm` with transverse corner (o1, o2) = (corner & 1, corner >> 1)
+// are updated.  Sixteen lanes per ion (dm = 0..2, corner = 0..3; dm = 3 idle)
+// together make every update of deposit_ion, with u advanced identically in
+// all of them.
+template <typename T>
+__device__ __forceinline__ void deposit_ion_part(int L, size_t Ns, double a, double qi, double (&u)[3],
+                                                 const double (&du)[3], T *__restrict__ D, int dm,
+                                                 int corner) {
+    const double a2 = a * a;
+    const int o1 = corner & 1, o2 = corner >> 1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double u0 = u[d];
+        const double u1 = u0 + du[d];
+        if (d == dm && u1 != u0) {
+            const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+            int c1, c2;
+            double f1, f2;
+            fold(u[d1], a, L, c1, f1);
+            fold(u[d2], a, L, c2, f2);
+            const double w = lin_w(o1, f1) * lin_w(o2, f2);
+            const int x1 = o1 ? (c1 + 1 == L ? 0 : c1 + 1) : c1;
+            const int x2 = o2 ? (c2 + 1 == L ? 0 : c2 + 1) : c2;
+            const double lo = u0 < u1 ? u0 : u1, hi = u0 < u1 ? u1 : u0;
+            const double sgn = u1 > u0 ? 1.0 : -1.0;
+            const long long klo = (long long)floor(lo / a), khi = (long long)floor(hi / a);
+            for (long long kc = klo; kc <= khi; ++kc) {
+                const double s0 = (double)kc * a, s1 = (double)(kc + 1) * a;
+                const double sa = lo > s0 ? lo : s0;
+                const double sb = hi < s1 ? hi : s1;
+                const double len = sb - sa;
+                if (!(len > 0.0)) continue;
+                const double amount = qi * sgn * (len / a) / a2;
+                long long km = kc % (long long)L;
+                if (km < 0) km += L;
+                int x[3];
+                x[d] = (int)km;
+                x[d1] = x1;
+                x[d2] = x2;
+                const double val = amount * lin_w(o1, f1) * lin_w(o2, f2);
+                (void)w;
+                unsafeAtomicAdd(&D[(size_t)d * Ns + site_index(x[0], x[1], x[2], L)], (T)(-val));
             }
         }
         u[d] = u1;

@@ -91,6 +91,7 @@ __global__ __launch_bounds__(256) void k_batch_deposit(const RepDesc *__restrict
             double u[3] = {R.r[3 * i], R.r[3 * i + 1], R.r[3 * i + 2]};
             double du[3];
             philox_displacement(R.seed, (uint32_t)step, (uint32_t)i, R.sigma, du);
+            sanitize_move(du, R.a, R.L, nullptr);
             const double qi = R.q[i];
             deposit_ion<float>(R.L, Ns, R.a, qi, u, du, R.D[(step & 1) ^ 1]);
             R.r[3 * i] = u[0];

@@ -1,6 +1,8 @@
 // kernels_field.hip -- lattice-field kernels for gfx950: the fused leapfrog
 // (Faraday + Ampere, body in leapfrog_tile.hpp), energy and Gauss-audit
 // reductions, permittivity maps, the salt-dependent permittivity.
+#include <hip/hip_ext.h>
+
 #include "device_util.hpp"
 #include "leapfrog_tile.hpp"
 #include "memd_internal.hpp"
@@ -16,9 +18,20 @@ __global__ __launch_bounds__(256) void k_leapfrog(LfArgs<T> A) {
     leapfrog_tile<T, EM, R>(A, tile_x, rest % A.nty, rest / A.nty, S);
 }
 
+// The leapfrog with the deposit of the regular ions fused in (leapfrog_tile.hpp).
+template <typename T, int EM, int R>
+__global__ __launch_bounds__(256) void k_leapfrog_dep(LfArgs<T> A, DepArgs P) {
+    __shared__ LfSmem<T, R> S;
+    __shared__ DepSmem<T, R> DS;
+    const int logical = xcd_logical(blockIdx.x, gridDim.x);
+    const int tile_x = logical % A.ntx;
+    const int rest = logical / A.ntx;
+    leapfrog_tile<T, EM, R, true>(A, tile_x, rest % A.nty, rest / A.nty, S, &P, &DS);
+}
+
 template <typename T, int EM>
-static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, void *Dout,
-                              void *Bout) {
+static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout,
+                              hipEvent_t e0, hipEvent_t e1, const DepArgs *dep) {
     LfArgs<T> A;
     A.Din = (const T *)Din;
     A.Bin = (const T *)Bin;
@@ -38,27 +51,54 @@ static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, voi
     A.tz = c->lf_tz;
     const int nz = (c->L + A.tz - 1) / A.tz;
     const int nblk = A.ntx * A.nty * nz;
+    if (dep) {
+        if (R == 1)
+            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 1>), dim3(nblk), dim3(256), 0, c->stream, e0, e1, 0, A,
+                                  *dep);
+        else
+            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 2>), dim3(nblk), dim3(256), 0, c->stream, e0, e1, 0, A,
+                                  *dep);
+        return hipGetLastError();
+    }
     if (R == 1)
-        hipLaunchKernelGGL((k_leapfrog<T, EM, 1>), dim3(nblk), dim3(256), 0, c->stream, A);
+        hipExtLaunchKernelGGL((k_leapfrog<T, EM, 1>), dim3(nblk), dim3(256), 0, c->stream, e0, e1, 0, A);
     else if (R == 2)
-        hipLaunchKernelGGL((k_leapfrog<T, EM, 2>), dim3(nblk), dim3(256), 0, c->stream, A);
+        hipExtLaunchKernelGGL((k_leapfrog<T, EM, 2>), dim3(nblk), dim3(256), 0, c->stream, e0, e1, 0, A);
     else
-        hipLaunchKernelGGL((k_leapfrog<T, EM, 4>), dim3(nblk), dim3(256), 0, c->stream, A);
+        hipExtLaunchKernelGGL((k_leapfrog<T, EM, 4>), dim3(nblk), dim3(256), 0, c->stream, e0, e1, 0, A);
     return hipGetLastError();
 }
 
-hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout) {
+bool fused_deposit_ok(const memd_ctx *c) {
+    return c->fuse_deposit && c->n > 0 && c->L >= 16 && c->lf_tz <= kDepTZ &&
+           c->lf_rows <= (c->fp32 ? 2 : 1);
+}
+
+hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout, hipEvent_t e0,
+                           hipEvent_t e1, const double *disp, uint64_t seed, uint32_t t, double sigma,
+                           bool with_deposit) {
+    DepArgs P;
+    const DepArgs *dp = nullptr;
+    if (with_deposit) {
+        hipError_t e = launch_pack_ions(c, disp, seed, t, sigma);
+        if (e != hipSuccess) return e;
+        P.rec = (const IonRec *)c->ionrec;
+        P.row_count = c->bins;
+        P.row_start = c->bins + (size_t)c->L * c->L;
+        P.a = c->a;
+        dp = &P;
+    }
     if (c->fp32) {
         switch (c->eta_mode) {
-            case ETA_UNIFORM: return launch_lf_t<float, ETA_UNIFORM>(c, Din, Bin, Dout, Bout);
-            case ETA_ZPROF: return launch_lf_t<float, ETA_ZPROF>(c, Din, Bin, Dout, Bout);
-            default: return launch_lf_t<float, ETA_LINK>(c, Din, Bin, Dout, Bout);
+            case ETA_UNIFORM: return launch_lf_t<float, ETA_UNIFORM>(c, Din, Bin, Dout, Bout, e0, e1, dp);
+            case ETA_ZPROF: return launch_lf_t<float, ETA_ZPROF>(c, Din, Bin, Dout, Bout, e0, e1, dp);
+            default: return launch_lf_t<float, ETA_LINK>(c, Din, Bin, Dout, Bout, e0, e1, dp);
         }
     }
     switch (c->eta_mode) {
-        case ETA_UNIFORM: return launch_lf_t<double, ETA_UNIFORM>(c, Din, Bin, Dout, Bout);
-        case ETA_ZPROF: return launch_lf_t<double, ETA_ZPROF>(c, Din, Bin, Dout, Bout);
-        default: return launch_lf_t<double, ETA_LINK>(c, Din, Bin, Dout, Bout);
+        case ETA_UNIFORM: return launch_lf_t<double, ETA_UNIFORM>(c, Din, Bin, Dout, Bout, e0, e1, dp);
+        case ETA_ZPROF: return launch_lf_t<double, ETA_ZPROF>(c, Din, Bin, Dout, Bout, e0, e1, dp);
+        default: return launch_lf_t<double, ETA_LINK>(c, Din, Bin, Dout, Bout, e0, e1, dp);
     }
 }
 

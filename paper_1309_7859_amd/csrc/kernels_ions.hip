@@ -3,6 +3,7 @@
 // the per-block partial sums; the lattice Green's function table.
 #include "device_util.hpp"
 #include "ion_ops.hpp"
+#include "leapfrog_tile.hpp"
 #include "memd_internal.hpp"
 #include "philox.hpp"
 
@@ -10,22 +11,23 @@ namespace memd {
 
 // ----------------------------------------------------------- deposition
 
-// The deposit kernel: threads take the ions in the order of `order` (binned
-// by lattice row, so that neighbouring threads update neighbouring links),
-// move each ion by its displacement while depositing its current, write the
-// new position, and form block sums of q r^{n+1} for the dipole moment.  When
-// spread_rho is set the new charge assignment is added to rho (FP64) for the
-// Gauss audit.
+// The deposit kernel: sixteen lanes per ion (one per axis and transverse
+// corner, deposit_ion_part), ions taken in the order of `order` (binned by
+// lattice row, so that neighbouring lanes update neighbouring links).  Lane 0
+// of each ion writes the new position and, when spread_rho is set, adds the
+// new charge assignment to rho (FP64) for the Gauss audit.  Block sums of
+// q r^{n+1} go to partials (summed in block order by k_fin_dipole).
 template <typename T>
 __global__ __launch_bounds__(256) void k_deposit(int n, int L, size_t Ns, double a,
                                                  const double *__restrict__ q, double *__restrict__ r,
                                                  const double *__restrict__ disp, T *__restrict__ D,
                                                  int spread_rho, double *__restrict__ rho,
                                                  const int *__restrict__ order,
-                                                 double *__restrict__ partials, uint64_t seed, uint32_t t,
-                                                 double sigma) {
-    // consecutive (spatially sorted) slots stay on one XCD and share its L2
-    const int slot = xcd_logical(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+                                                 double *__restrict__ partials, unsigned int *bad,
+                                                 uint64_t seed, uint32_t t, double sigma) {
+    const int lane = threadIdx.x & 15;
+    // consecutive (spatially sorted) ions stay on one XCD and share its L2
+    const int slot = xcd_logical(blockIdx.x, gridDim.x) * (blockDim.x >> 4) + (threadIdx.x >> 4);
     double P[3] = {0.0, 0.0, 0.0};
     if (slot < n) {
         const int i = order ? order[slot] : slot;
@@ -37,9 +39,123 @@ __global__ __launch_bounds__(256) void k_deposit(int n, int L, size_t Ns, double
             du[1] = disp[3 * i + 1];
             du[2] = disp[3 * i + 2];
         } else {
+            if (lane == 0) philox_displacement(seed, t, (uint32_t)i, sigma, du);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) du[d] = __shfl(du[d], 0, 16);
+        }
+        sanitize_move(du, a, L, lane == 0 ? bad : nullptr);
+        deposit_ion_part<T>(L, Ns, a, qi, u, du, D, lane >> 2, lane & 3);
+        if (lane == 0) {
+            r[3 * i] = u[0];
+            r[3 * i + 1] = u[1];
+            r[3 * i + 2] = u[2];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) P[d] = qi * u[d];
+            if (spread_rho) spread_ion(L, a, qi, u, rho);
+        }
+    }
+    block_sum<3>(P);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = P[0];
+        partials[3 * blockIdx.x + 1] = P[1];
+        partials[3 * blockIdx.x + 2] = P[2];
+    }
+}
+
+static int ion_blocks(int n) { return n > 0 ? (n + kThreads - 1) / kThreads : 1; }
+// grid of the sorted-order ion kernels (lanes_per_ion lanes per ion): a
+// multiple of the 8 XCDs
+static int ion_blocks_x8(int n, int lanes_per_ion = 1) {
+    const long long t = (long long)(n > 0 ? n : 1) * lanes_per_ion;
+    const int b = (int)((t + kThreads - 1) / kThreads);
+    return (b + 7) / 8 * 8;
+}
+
+hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_rho,
+                          double *partials, int *nblk, uint64_t seed, uint32_t t, double sigma) {
+    const int nb = ion_blocks_x8(c->n, 16);
+    *nblk = nb;
+    if (c->fp32)
+        hipLaunchKernelGGL(k_deposit<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
+                           c->q, c->r, disp, (float *)D, spread_rho ? 1 : 0, c->rho, c->order, partials,
+                           c->bad_moves, seed, t, sigma);
+    else
+        hipLaunchKernelGGL(k_deposit<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
+                           c->q, c->r, disp, (double *)D, spread_rho ? 1 : 0, c->rho, c->order, partials,
+                           c->bad_moves, seed, t, sigma);
+    return hipGetLastError();
+}
+
+// Records of the ions in bin order for the fused deposit: slot s holds ion
+// order[s] (position r^n, displacement from disp or from the Philox stream,
+// rejected components taken as 0, charge, bin row).
+__global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const double *__restrict__ q,
+                                                   const double *__restrict__ r, const double *__restrict__ disp,
+                                                   const int *__restrict__ order, const int *__restrict__ binrow,
+                                                   IonRec *__restrict__ rec, uint64_t seed, uint32_t t, double sigma) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int i = order[s];
+    double du[3];
+    if (disp) {
+        du[0] = disp[3 * i];
+        du[1] = disp[3 * i + 1];
+        du[2] = disp[3 * i + 2];
+    } else {
+        philox_displacement(seed, t, (uint32_t)i, sigma, du);
+    }
+    sanitize_move(du, a, L, nullptr);
+    IonRec o;
+    o.u[0] = r[3 * i];
+    o.u[1] = r[3 * i + 1];
+    o.u[2] = r[3 * i + 2];
+    o.du[0] = du[0];
+    o.du[1] = du[1];
+    o.du[2] = du[2];
+    o.q = q[i];
+    o.binrow = (double)binrow[i];
+    rec[s] = o;
+}
+
+hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma) {
+    if (c->n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_ions, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->q,
+                       c->r, disp, c->order, c->binrow, (IonRec *)c->ionrec, seed, t, sigma);
+    return hipGetLastError();
+}
+
+// Ion update after the leapfrog with the fused deposit: ions in index order
+// (so the dipole's block sums are in a fixed order), the regularity test of
+// the fused deposit repeated on the same bits; irregular ions deposit their
+// whole move here with global atomics, every ion is moved, and block sums of
+// q r^{n+1} go to partials (plus rho for the audit when spread_rho is set).
+template <typename T>
+__global__ __launch_bounds__(256) void k_ion_update(int n, int L, size_t Ns, double a,
+                                                    const double *__restrict__ q, double *__restrict__ r,
+                                                    const double *__restrict__ disp, T *__restrict__ D,
+                                                    const int *__restrict__ binrow, int spread_rho,
+                                                    double *__restrict__ rho, double *__restrict__ partials,
+                                                    unsigned int *bad, uint64_t seed, uint32_t t, double sigma) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double P[3] = {0.0, 0.0, 0.0};
+    if (i < n) {
+        double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
+        double du[3];
+        if (disp) {
+            du[0] = disp[3 * i];
+            du[1] = disp[3 * i + 1];
+            du[2] = disp[3 * i + 2];
+        } else {
             philox_displacement(seed, t, (uint32_t)i, sigma, du);
         }
-        deposit_ion<T>(L, Ns, a, qi, u, du, D);
+        sanitize_move(du, a, L, bad);
+        const double qi = q[i];
+        if (ion_regular(a, L, u, du, binrow[i])) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) u[d] = u[d] + du[d];
+        } else {
+            deposit_ion<T>(L, Ns, a, qi, u, du, D);
+        }
         r[3 * i] = u[0];
         r[3 * i + 1] = u[1];
         r[3 * i + 2] = u[2];
@@ -55,22 +171,18 @@ __global__ __launch_bounds__(256) void k_deposit(int n, int L, size_t Ns, double
     }
 }
 
-static int ion_blocks(int n) { return n > 0 ? (n + kThreads - 1) / kThreads : 1; }
-// grid of the sorted-order ion kernels: a multiple of the 8 XCDs
-static int ion_blocks_x8(int n) { return (ion_blocks(n) + 7) / 8 * 8; }
-
-hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_rho,
-                          double *partials, int *nblk, uint64_t seed, uint32_t t, double sigma) {
-    const int nb = ion_blocks_x8(c->n);
+hipError_t launch_ion_update(memd_ctx *c, void *D, const double *disp, bool spread_rho, double *partials,
+                             int *nblk, uint64_t seed, uint32_t t, double sigma) {
+    const int nb = ion_blocks(c->n);
     *nblk = nb;
     if (c->fp32)
-        hipLaunchKernelGGL(k_deposit<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
-                           c->q, c->r, disp, (float *)D, spread_rho ? 1 : 0, c->rho, c->order, partials, seed, t,
-                           sigma);
+        hipLaunchKernelGGL(k_ion_update<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
+                           c->q, c->r, disp, (float *)D, c->binrow, spread_rho ? 1 : 0, c->rho, partials,
+                           c->bad_moves, seed, t, sigma);
     else
-        hipLaunchKernelGGL(k_deposit<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
-                           c->q, c->r, disp, (double *)D, spread_rho ? 1 : 0, c->rho, c->order, partials, seed, t,
-                           sigma);
+        hipLaunchKernelGGL(k_ion_update<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
+                           c->q, c->r, disp, (double *)D, c->binrow, spread_rho ? 1 : 0, c->rho, partials,
+                           c->bad_moves, seed, t, sigma);
     return hipGetLastError();
 }
 
@@ -137,13 +249,14 @@ struct ForceArgs {
     int dip_nblk;
 };
 
-// Forces on every ion (ion_ops.hpp: force_ion); threads follow `order`.
+// Forces on every ion, four lanes per ion following `order`: lane d < 3
+// gathers E_d on the 4 d-links of the cell; the 12 eta of the cell (its
+// permittivity for the self-energy correction) are summed across the lanes.
+// Lattice part, self force and dipole correction as in force_ion.
 template <typename T>
 __global__ __launch_bounds__(256) void k_forces(ForceArgs<T> A) {
     __shared__ double Psh[3];
     if (A.dip_partials) {
-        // every block forms P from the deposit's partial sums in the same fixed
-        // order; block 0 also stores it for the energy and the dipole queries
         double s[3] = {0.0, 0.0, 0.0};
         for (int b = threadIdx.x; b < A.dip_nblk; b += blockDim.x)
 #pragma unroll
@@ -160,22 +273,54 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs<T> A) {
         Psh[threadIdx.x] = A.scal[S_P + threadIdx.x];
     }
     __syncthreads();
-    const int slot = xcd_logical(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 3;
+    const int slot = (xcd_logical(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 2;
     double us = 0.0;
-    if (slot < A.n) {
-        const int i = A.order ? A.order[slot] : slot;
-        const double u[3] = {A.r[3 * i], A.r[3 * i + 1], A.r[3 * i + 2]};
-        EtaView<T> ev{A.mode, A.eta_uni, A.eta_prof, A.eta_link};
-        double F[3];
-        us = force_ion<T>(A.L, A.Ns, A.a, A.V, A.q[i], u, A.D, ev, A.scal + S_G, Psh, A.scal + S_EPSH, F);
-        A.F[3 * i] = F[0];
-        A.F[3 * i + 1] = F[1];
-        A.F[3 * i + 2] = F[2];
+    const bool live = slot < A.n;
+    const int i = live ? (A.order ? A.order[slot] : slot) : 0;
+    int c[3];
+    double f[3];
+    double s = 0.0, esum = 0.0;
+    const double qi = live ? A.q[i] : 0.0;
+    if (live) {
+        const int L = A.L;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fold(A.r[3 * i + d], A.a, L, c[d], f[d]);
+        if (lane < 3) {
+            const int d = lane, d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+            EtaView<T> ev{A.mode, A.eta_uni, A.eta_prof, A.eta_link};
+#pragma unroll
+            for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                for (int o1 = 0; o1 < 2; ++o1) {
+                    int x[3] = {c[0], c[1], c[2]};
+                    x[d1] = o1 ? (c[d1] + 1 == L ? 0 : c[d1] + 1) : c[d1];
+                    x[d2] = o2 ? (c[d2] + 1 == L ? 0 : c[d2] + 1) : c[d2];
+                    const size_t off = site_index(x[0], x[1], x[2], L);
+                    const double e = ev.at(d, x[2], off, L, A.Ns);
+                    esum += e;
+                    s += lin_w(o1, f[d1]) * lin_w(o2, f[d2]) * (e * (double)A.D[(size_t)d * A.Ns + off]);
+                }
+        }
+    }
+    esum += __shfl_xor(esum, 1, 4);
+    esum += __shfl_xor(esum, 2, 4);
+    if (live) {
+        const double eps_cell = 12.0 / esum;
+        double S, dS[3];
+        self_sum(A.scal + S_G, f, S, dS);
+        const double pref = qi * qi / (2.0 * eps_cell * A.a);
+        if (lane < 3) {
+            const int d = lane;
+            const double Fself = -pref * dS[d] / A.a;
+            A.F[3 * i + d] = qi * s - Fself + qi * Psh[d] / (A.V * A.scal[S_EPSH + d]);
+        }
+        if (lane == 0) us = pref * S;
     }
     if (A.uself_partials) {
-        double s[1] = {us};
-        block_sum<1>(s);
-        if (threadIdx.x == 0) A.uself_partials[blockIdx.x] = s[0];
+        double v[1] = {us};
+        block_sum<1>(v);
+        if (threadIdx.x == 0) A.uself_partials[blockIdx.x] = v[0];
     }
 }
 
@@ -205,7 +350,7 @@ static ForceArgs<T> force_args(memd_ctx *c, const void *D) {
 
 hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk) {
     if (c->n == 0) return hipSuccess;
-    const int nb = ion_blocks_x8(c->n);
+    const int nb = ion_blocks_x8(c->n, 4);
     if (c->fp32) {
         auto A = force_args<float>(c, D);
         A.dip_partials = dip_partials;
@@ -237,7 +382,8 @@ __global__ void k_bin_count(int n, int L, double a, const double *__restrict__ r
 // Exclusive scan of count[0..nb) into cursor[0..nb) (one block of 1024):
 // the bins are taken in tiles of 1024, each scanned with wavefront prefix
 // sums plus a pass over the 16 wavefront totals.
-__global__ __launch_bounds__(1024) void k_bin_scan(const int *__restrict__ count, int nb, int *__restrict__ cursor) {
+__global__ __launch_bounds__(1024) void k_bin_scan(const int *__restrict__ count, int nb, int *__restrict__ start,
+                                                   int *__restrict__ cursor) {
     __shared__ int wsum[16];
     __shared__ int carry;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
@@ -255,7 +401,10 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const int *__restrict__ count
         __syncthreads();
         int before = carry;
         for (int w = 0; w < wid; ++w) before += wsum[w];
-        if (base + t < nb) cursor[base + t] = before + x - v;
+        if (base + t < nb) {
+            start[base + t] = before + x - v;
+            cursor[base + t] = before + x - v;
+        }
         __syncthreads();
         if (t == 1023) carry = before + x;
         __syncthreads();
@@ -263,15 +412,17 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const int *__restrict__ count
 }
 
 __global__ void k_bin_scatter(int n, int L, double a, const double *__restrict__ r, int *__restrict__ cursor,
-                              int *__restrict__ order) {
+                              int *__restrict__ order, int *__restrict__ binrow) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int cy, cz;
     double f;
     fold(r[3 * i + 1], a, L, cy, f);
     fold(r[3 * i + 2], a, L, cz, f);
-    const int slot = atomicAdd(&cursor[cy + L * cz], 1);
+    const int row = cy + L * cz;
+    const int slot = atomicAdd(&cursor[row], 1);
     order[slot] = i;
+    binrow[i] = row;
 }
 
 __global__ void k_fill_int(int *dst, int v, size_t count) {
@@ -283,19 +434,19 @@ hipError_t launch_bin_ions(memd_ctx *c) {
     if (c->n == 0 || !c->order) return hipSuccess;
     const int nb = c->L * c->L;
     const int g = (int)((nb + kThreads - 1) / kThreads) < 4096 ? (nb + kThreads - 1) / kThreads : 4096;
-    int *count = c->bins, *cursor = c->bins + nb;
+    int *count = c->bins, *start = c->bins + nb, *cursor = c->bins + 2 * (size_t)nb;
     hipLaunchKernelGGL(k_fill_int, dim3(g), dim3(kThreads), 0, c->stream, count, 0, (size_t)nb);
     hipLaunchKernelGGL(k_bin_count, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->r,
                        count);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, count, nb, cursor);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, count, nb, start, cursor);
     hipLaunchKernelGGL(k_bin_scatter, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
-                       c->r, cursor, c->order);
+                       c->r, cursor, c->order, c->binrow);
     return hipGetLastError();
 }
 
 // Self energies (through the force kernel, writing the same forces again).
 hipError_t launch_uself(memd_ctx *c, double *partials, int *nblk) {
-    const int nb = ion_blocks_x8(c->n);
+    const int nb = ion_blocks_x8(c->n, 4);
     *nblk = nb;
     const void *D = c->D[c->cur];
     if (c->fp32) {

@@ -14,7 +14,9 @@
 #pragma once
 
 #include "device_util.hpp"
+#include "ion_ops.hpp"
 #include "memd_internal.hpp"
+#include "philox.hpp"
 
 namespace memd {
 
@@ -45,6 +47,54 @@ __device__ __forceinline__ T eta_at(const LfArgs<T> &A, int d, int gz, size_t of
     }
 }
 
+// Ions for the deposit fused into the leapfrog.  Ions are binned by lattice
+// row (y, z) of their position at the last sort; an ion is "regular" when
+// every displacement component is shorter than a and its current row is
+// within one row (y and z) of its bin row.  A regular ion starting in cell c
+// deposits only on links whose origin lies in [c - 1, c + 2] per axis, so a
+// tile finds every regular ion touching its links in the bin rows
+// [y0 - 3, y0 + TY + 1] x [z0 - 3, z0 + TZ + 1].  Other ions are deposited
+// by the follow-up ion kernel with global atomics.
+// One record per ion in bin order (written each step by k_pack_ions):
+// position r^n, displacement, charge, bin row.
+struct IonRec {
+    double u[3], du[3], q, binrow;
+};
+
+struct DepArgs {
+    const IonRec *rec;      // [n] records in bin order
+    const int *row_start;   // [L^2] first slot of each row
+    const int *row_count;   // [L^2]
+    double a;
+};
+
+constexpr int kDepTZ = 4;  // planes per z-chunk when the deposit is fused
+
+__device__ __forceinline__ bool ion_regular(double a, int L, const double (&u)[3], const double (&du)[3],
+                                            int binrow) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        if (!(fabs(du[d]) < a)) return false;
+    int cy, cz;
+    double f;
+    fold(u[1], a, L, cy, f);
+    fold(u[2], a, L, cz, f);
+    int dy = cy - binrow % L, dz = cz - binrow / L;
+    if (dy > L / 2) dy -= L;
+    if (dy < -L / 2) dy += L;
+    if (dz > L / 2) dz -= L;
+    if (dz < -L / 2) dz += L;
+    return dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+}
+
+
+template <typename T, int R>
+struct DepSmem {
+    T acc[3][kDepTZ][4 * R][64];
+    int rowpre[(4 * R + 5) * (kDepTZ + 5) + 1];
+    int rowbase[(4 * R + 5) * (kDepTZ + 5)];  // first slot of each candidate row minus rowpre
+};
+
 // LDS of one tile: eta*D of two planes with a one-site halo, new B of one
 // plane with a -1 halo.
 template <typename T, int R>
@@ -56,9 +106,10 @@ struct LfSmem {
 // One workgroup (256 threads) advances the tile (tile_x, tile_y) over the z
 // planes of `chunk`.  Every load wraps periodically; stores are masked to the
 // lattice, so any L >= 2 works with any tile shape.
-template <typename T, int EM, int R>
+template <typename T, int EM, int R, bool DEP = false>
 __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, int tile_y, int chunk,
-                                              LfSmem<T, R> &S) {
+                                              LfSmem<T, R> &S, const DepArgs *dep = nullptr,
+                                              DepSmem<T, R> *DS = nullptr) {
     constexpr int TX = 64, TY = 4 * R;
     auto &sX = S.sX;
     auto &sB = S.sB;
@@ -113,6 +164,102 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
                 sX[buf][d][lx][xc] = eta_at<T, EM>(A, d, gz, off) * A.Din[(size_t)d * Ns + off];
         }
     };
+
+    if constexpr (DEP) {
+        // Deposit of the regular ions on the links this tile owns (x in
+        // [x0, x0+64), y in [y0, y0+TY), z in [z0, z1)), accumulated in LDS.
+        T *accf = &DS->acc[0][0][0][0];
+        for (int t = threadIdx.x; t < 3 * kDepTZ * TY * 64; t += blockDim.x) accf[t] = (T)0;
+        const int nry = TY + 5, nrz = (z1 - z0) + 5, nrows = nry * nrz;
+        for (int t = threadIdx.x; t < nrows; t += blockDim.x) {
+            const int by = wrapc(y0 - 3 + t % nry + L, L), bz = wrapc(z0 - 3 + t / nry + L, L);
+            DS->rowpre[t + 1] = dep->row_count[by + L * bz];
+            DS->rowbase[t] = dep->row_start[by + L * bz];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int run = 0;
+            DS->rowpre[0] = 0;
+            for (int t = 1; t <= nrows; ++t) {
+                run += DS->rowpre[t];
+                DS->rowpre[t] = run;
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < nrows; t += blockDim.x) DS->rowbase[t] -= DS->rowpre[t];
+        __syncthreads();
+        const int total = DS->rowpre[nrows];
+        const double a = dep->a, a2 = a * a;
+        const double inv_a = 1.0 / a, inv_a2 = 1.0 / a2;
+        int ea;
+        const bool a_pow2 = frexp(a, &ea) == 0.5;
+        const int ylim = min(y0 + TY, L), zlim = z1;
+        for (int cidx = threadIdx.x; cidx < total; cidx += blockDim.x) {
+            int lo = 0, hi = nrows - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (DS->rowpre[mid] <= cidx) lo = mid;
+                else hi = mid - 1;
+            }
+            const IonRec &rc = dep->rec[DS->rowbase[lo] + cidx];
+            double u[3] = {rc.u[0], rc.u[1], rc.u[2]};
+            const double du[3] = {rc.du[0], rc.du[1], rc.du[2]};
+            {
+                // a regular ion in start cell c touches x in [c-1, c+2] only
+                // (periodic: cx in [x0 - 2, x0 + TX] modulo L; no filter when the
+                // window covers the whole lattice)
+                int cx;
+                double fx;
+                fold_fast(u[0], a, inv_a, a_pow2, L, cx, fx);
+                const int dxm = ((cx - x0 + 2) % L + L) % L;
+                if (L > TX + 4 && dxm > TX + 2) continue;
+            }
+            if (!ion_regular(a, L, u, du, (int)rc.binrow)) continue;
+            const double qi = rc.q;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+                const double u0 = u[d], u1 = u0 + du[d];
+                if (u1 != u0) {
+                    int c1, c2;
+                    double f1, f2;
+                    fold_fast(u[d1], a, inv_a, a_pow2, L, c1, f1);
+                    fold_fast(u[d2], a, inv_a, a_pow2, L, c2, f2);
+                    const double lo_ = u0 < u1 ? u0 : u1, hi_ = u0 < u1 ? u1 : u0;
+                    const double sgn = u1 > u0 ? 1.0 : -1.0;
+                    const long long klo = (long long)floor(a_pow2 ? lo_ * inv_a : lo_ / a);
+                    const long long khi = (long long)floor(a_pow2 ? hi_ * inv_a : hi_ / a);
+                    for (long long kc = klo; kc <= khi; ++kc) {
+                        const double s0 = (double)kc * a, s1 = (double)(kc + 1) * a;
+                        const double sa = lo_ > s0 ? lo_ : s0;
+                        const double sb = hi_ < s1 ? hi_ : s1;
+                        const double len = sb - sa;
+                        if (!(len > 0.0)) continue;
+                        const double amount =
+                            a_pow2 ? qi * sgn * (len * inv_a) * inv_a2 : qi * sgn * (len / a) / a2;
+                        long long km = kc % (long long)L;
+                        if (km < 0) km += L;
+#pragma unroll
+                        for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                            for (int o1 = 0; o1 < 2; ++o1) {
+                                int x[3];
+                                x[d] = (int)km;
+                                x[d1] = o1 ? (c1 + 1 == L ? 0 : c1 + 1) : c1;
+                                x[d2] = o2 ? (c2 + 1 == L ? 0 : c2 + 1) : c2;
+                                if (x[0] < x0 || x[0] >= x0 + TX || x[1] < y0 || x[1] >= ylim || x[2] < z0 ||
+                                    x[2] >= zlim)
+                                    continue;
+                                const double val = amount * lin_w(o1, f1) * lin_w(o2, f2);
+                                atomicAdd(&DS->acc[d][x[2] - z0][x[1] - y0][x[0] - x0], (T)(-val));
+                            }
+                    }
+                }
+                u[d] = u1;
+            }
+        }
+        __syncthreads();
+    }
 
     T Dc[R][3], Dn[R][3], prevB[R][2];
 
@@ -211,9 +358,16 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             const T dz = Dc[r][2] + kD * (Bn[r][1] - sB[1][yy][xx - 1] - Bn[r][0] + sB[0][yy - 1][xx]);
             if (act[r]) {
                 const size_t off = zoff + (size_t)gyo[r] * L + gx;
-                A.Dout[off] = dx;
-                A.Dout[Ns + off] = dy;
-                A.Dout[2 * Ns + off] = dz;
+                if constexpr (DEP) {
+                    const int kz = k - z0, ky = wy + 4 * r;
+                    A.Dout[off] = dx + DS->acc[0][kz][ky][lx];
+                    A.Dout[Ns + off] = dy + DS->acc[1][kz][ky][lx];
+                    A.Dout[2 * Ns + off] = dz + DS->acc[2][kz][ky][lx];
+                } else {
+                    A.Dout[off] = dx;
+                    A.Dout[Ns + off] = dy;
+                    A.Dout[2 * Ns + off] = dz;
+                }
             }
             prevB[r][0] = Bn[r][0];
             prevB[r][1] = Bn[r][1];

@@ -92,6 +92,21 @@ void prof_end(memd_ctx *c, int fam) {
     }
 }
 
+// A start/stop event pair attached to one launch (hipExtLaunchKernelGGL
+// records them at the kernel's own start and end, with no marker packets).
+void prof_pair(memd_ctx *c, int fam, hipEvent_t *e0, hipEvent_t *e1) {
+    *e0 = *e1 = nullptr;
+    if (!c->prof_on || !(c->prof_mask & (1u << fam))) return;
+    if (hipEventCreate(e0) != hipSuccess) return;
+    if (hipEventCreate(e1) != hipSuccess) {
+        hipEventDestroy(*e0);
+        *e0 = nullptr;
+        return;
+    }
+    c->prof[fam].start.push_back(*e0);
+    c->prof[fam].stop.push_back(*e1);
+}
+
 void prof_clear(memd_ctx *c) {
     for (int f = 0; f < F_NFAM; ++f) {
         for (auto e : c->prof[f].start) hipEventDestroy(e);
@@ -105,9 +120,17 @@ double courant(const memd_ctx *c) {
     return c->c * c->dt * std::sqrt(3.0) / (c->a * std::sqrt(c->eps_min));
 }
 
+// Reduction scratch: site-loop partials (<= 4 per block of kRedBlocks), the
+// deposit's dipole partials (3 per block of 16 ions), the self-energy
+// partials (1 per block of 64 ions, from offset kRedBlocks * 4).
 size_t partial_doubles(int n) {
-    const size_t ion_blocks = (size_t)((n + kThreads - 1) / kThreads + 1);
-    return (size_t)kRedBlocks * 8 + ion_blocks * 4;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    const size_t dep = 3 * (nn / 16 + 16);
+    const size_t us = (size_t)kRedBlocks * 4 + nn / 64 + 16;
+    size_t m = (size_t)kRedBlocks * 8;
+    if (dep > m) m = dep;
+    if (us > m) m = us;
+    return m + 64;
 }
 
 double *ion_partials(memd_ctx *c) { return c->partials + (size_t)kRedBlocks * 4; }
@@ -205,7 +228,7 @@ void memd_destroy(memd_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     prof_clear(c);
     void *bufs[] = {c->D[0], c->D[1], c->B[0], c->B[1], c->eta_prof, c->eta_link, c->q, c->r, c->F,
-                    c->order, c->bins,
+                    c->order, c->bins, c->binrow, c->bad_moves, c->ionrec,
                     c->stage, c->rho, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt,
                     c->salt_nbar};
     for (void *b : bufs)
@@ -237,9 +260,10 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     c->V = std::pow(p->L * p->a, 3);
     c->fp32 = p->precision == MEMD_FP32_MIXED;
     c->tsize = c->fp32 ? sizeof(float) : sizeof(double);
-    c->lf_rows = 2;
-    c->lf_tz = 16;
+    c->lf_rows = c->fp32 ? 2 : 1;
+    c->lf_tz = 4;
     c->sort_every = 8;
+    c->fuse_deposit = true;
     c->hist_cap = kHistCap;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -286,7 +310,10 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
         hipMalloc((void **)&c->r, 3 * nn * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->F, 3 * nn * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->order, nn * sizeof(int)) != hipSuccess ||
-        hipMalloc((void **)&c->bins, 2 * (size_t)p->L * p->L * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&c->bins, 3 * (size_t)p->L * p->L * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&c->binrow, nn * sizeof(int)) != hipSuccess ||
+        hipMalloc(&c->ionrec, nn * 8 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->bad_moves, sizeof(unsigned int)) != hipSuccess ||
         hipMalloc((void **)&c->rho, Ns * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->partials, partial_doubles(n) * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->scal, S_COUNT * sizeof(double)) != hipSuccess ||
@@ -301,6 +328,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
         hipMemsetAsync(c->B[b], 0, fb, s);
     }
     hipMemsetAsync(c->rho, 0, Ns * sizeof(double), s);
+    hipMemsetAsync(c->bad_moves, 0, sizeof(unsigned int), s);
     hipMemsetAsync(c->scal, 0, S_COUNT * sizeof(double), s);
     hipMemsetAsync(c->F, 0, 3 * nn * sizeof(double), s);
     if (n > 0) {
@@ -438,21 +466,28 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
             prof_end(c, F_SALT);
         }
         const int nx = c->cur ^ 1;
-        prof_begin(c, F_LEAPFROG);
-        CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx]));
-        prof_end(c, F_LEAPFROG);
         const long next = c->step_index + 1;
         const bool audit_now = c->p.audit_every > 0 && next % c->p.audit_every == 0;
         const bool energy_now = c->p.energy_every > 0 && next % c->p.energy_every == 0;
+        const double *dstep = dd ? dd + per * t : nullptr;
+        const uint32_t tstep = (uint32_t)c->step_index;
         int nb = 0;
         if (c->sort_every > 0 && c->step_index % c->sort_every == 0) CK(launch_bin_ions(c));
+        const bool fused = fused_deposit_ok(c);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        prof_pair(c, F_LEAPFROG, &e0, &e1);
+        CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx], e0, e1, dstep, seed, tstep, sigma,
+                           fused));
         prof_begin(c, F_DEPOSIT);
-        CK(launch_deposit(c, c->D[nx], dd ? dd + per * t : nullptr, audit_now, c->partials, &nb, seed,
-                          (uint32_t)c->step_index, sigma));
+        if (fused)
+            CK(launch_ion_update(c, c->D[nx], dstep, audit_now, c->partials, &nb, seed, tstep, sigma));
+        else
+            CK(launch_deposit(c, c->D[nx], dstep, audit_now, c->partials, &nb, seed, tstep, sigma));
+        CK(launch_finalize_dipole(c->stream, c->partials, nb, c->scal + S_P));
         prof_end(c, F_DEPOSIT);
         c->cur = nx;
         prof_begin(c, F_FORCES);
-        CK(launch_forces(c, c->D[c->cur], c->partials, nb));
+        CK(launch_forces(c, c->D[c->cur], nullptr, 0));  // P was formed by the deposit
         prof_end(c, F_FORCES);
         if (audit_now) {
             const int slot = c->hist_audit_n < c->hist_cap ? c->hist_audit_n : c->hist_cap - 1;
@@ -715,6 +750,11 @@ memd_status memd::autotune_leapfrog(memd_ctx *c, int reps, const char *cache_pat
     }
     const int rows_c[3] = {1, 2, 4};
     const int planes_c[6] = {2, 4, 8, 16, 32, 64};
+    // with ions on a lattice of 16 or more, the step runs the leapfrog with the
+    // deposit fused in: only its tile shapes are candidates, and it is timed
+    // with Philox displacements (sigma = 0.02 a) into the inactive buffer
+    const bool want_fused = c->fuse_deposit && c->n > 0 && c->L >= 16;
+    const int saved_rows = c->lf_rows, saved_tz = c->lf_tz;
     int best_r = c->lf_rows, best_p = c->lf_tz;
     double best_us = HUGE_VAL;
     hipEvent_t e0, e1;
@@ -728,9 +768,14 @@ memd_status memd::autotune_leapfrog(memd_ctx *c, int reps, const char *cache_pat
             if (pl > c->L && pi > 0) continue;
             c->lf_rows = rows_c[ri];
             c->lf_tz = pl;
-            CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx]));
+            if (want_fused && !fused_deposit_ok(c)) continue;
+            const double sg = want_fused ? 0.02 * c->a : 0.0;
+            CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx], nullptr, nullptr, nullptr, 0, 0,
+                               sg, want_fused));
             CK(hipEventRecord(e0, c->stream));
-            for (int t = 0; t < reps; ++t) CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx]));
+            for (int t = 0; t < reps; ++t)
+                CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx], nullptr, nullptr, nullptr, 0,
+                                   0, sg, want_fused));
             CK(hipEventRecord(e1, c->stream));
             CK(hipEventSynchronize(e1));
             float ms = 0.0f;
@@ -744,6 +789,10 @@ memd_status memd::autotune_leapfrog(memd_ctx *c, int reps, const char *cache_pat
         }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    if (best_us == HUGE_VAL) {
+        best_r = saved_rows;
+        best_p = saved_tz;
+    }
     c->lf_rows = best_r;
     c->lf_tz = best_p;
     if (cache_path) {
@@ -764,6 +813,23 @@ extern "C" {
 memd_status memd_autotune(memd_ctx *c, int reps, const char *cache_path, int *rows_out, int *planes_out,
                           double *us_out) {
     return autotune_leapfrog(c, reps, cache_path, 4, rows_out, planes_out, us_out);
+}
+
+memd_status memd_set_options(memd_ctx *c, int fuse_deposit, int sort_every) {
+    CHECK_CTX(c);
+    if (fuse_deposit < 0 || fuse_deposit > 1 || sort_every < 0) return MEMD_EINVAL;
+    c->fuse_deposit = fuse_deposit != 0;
+    c->sort_every = sort_every;
+    return MEMD_OK;
+}
+
+memd_status memd_counters(memd_ctx *c, unsigned long *bad_moves, int *fused_path) {
+    CHECK_CTX(c);
+    unsigned int h = 0;
+    CK(copy_out(c, &h, c->bad_moves, sizeof(unsigned int)));
+    if (bad_moves) *bad_moves = h;
+    if (fused_path) *fused_path = fused_deposit_ok(c) ? 1 : 0;
+    return MEMD_OK;
 }
 
 memd_status memd_set_tiling(memd_ctx *c, int rows, int planes) {

@@ -84,7 +84,11 @@ struct memd_ctx {
     double *r;     // [3n]
     double *F;     // [3n]
     int *order;    // [n] ion visiting order (binned by lattice row), refreshed every sort_every steps
-    int *bins;     // [2 L^2] bin counts and cursors
+    int *bins;     // [3 L^2] bin counts, row starts, cursors
+    int *binrow;   // [n] bin row of each ion at the last sort
+    void *ionrec;  // [n] 64-byte ion records in bin order (fused deposit)
+    unsigned int *bad_moves;  // rejected displacement components (not finite or > L a)
+    bool fuse_deposit;
     int sort_every;
     double *stage;       // FP64 staging buffer for host inputs / FP32 casts
     size_t stage_bytes;
@@ -115,7 +119,18 @@ struct memd_ctx {
 namespace memd {
 
 // ---- launchers (field kernels) ----
-hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout);
+// ev0/ev1 (optional): events recorded at the kernel's start and end.
+// with_deposit: the regular ions' deposit is fused in (displacements from disp,
+// or from the Philox stream when disp is null); requires fused_deposit_ok(c).
+hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, const double *disp = nullptr,
+                           uint64_t seed = 0, uint32_t t = 0, double sigma = 0.0, bool with_deposit = false);
+bool fused_deposit_ok(const memd_ctx *c);
+hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma);
+// Ion update after the fused leapfrog: irregular ions deposited with global
+// atomics, every position advanced, dipole partials (and rho for the audit).
+hipError_t launch_ion_update(memd_ctx *c, void *D, const double *disp, bool spread_rho, double *partials,
+                             int *nblk, uint64_t seed, uint32_t t, double sigma);
 hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
                                int *nblk);
 hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk);

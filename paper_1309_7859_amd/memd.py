@@ -73,6 +73,8 @@ def load():
         "memd_set_tiling": [vp, i, i],
         "memd_autotune": [vp, i, C.c_char_p, C.POINTER(i), C.POINTER(i), dp],
         "memd_step_seeded": [vp, C.c_uint64, d, i],
+        "memd_set_options": [vp, i, i],
+        "memd_counters": [vp, C.POINTER(C.c_ulong), C.POINTER(i)],
         "memd_seeded_displacements": [C.c_uint64, i, i, d, vp],
         "memd_server_create": [C.POINTER(vp), C.c_size_t, i, i, d, C.c_char_p, vp],
         "memd_server_submit": [vp, C.POINTER(memd_params), i, vp, vp, i, vp, i, C.c_uint64, d,
@@ -249,6 +251,17 @@ def memd_autotune(ctx: int, reps: int = 10, cache_path: str | None = None):
     _check(load().memd_autotune(ctx, reps, path, C.byref(rr), C.byref(pp), C.byref(us)),
            "memd_autotune")
     return rr.value, pp.value, us.value
+
+
+def memd_set_options(ctx: int, fuse_deposit: int = 1, sort_every: int = 8):
+    _check(load().memd_set_options(ctx, int(fuse_deposit), int(sort_every)), "memd_set_options")
+
+
+def memd_counters(ctx: int):
+    b = C.c_ulong()
+    f = C.c_int()
+    _check(load().memd_counters(ctx, C.byref(b), C.byref(f)), "memd_counters")
+    return b.value, f.value
 
 
 def memd_step_seeded(ctx: int, seed: int, sigma: float, nsteps: int):

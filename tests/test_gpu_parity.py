@@ -319,3 +319,83 @@ def test_autotune_keeps_state_and_caches(tmp_path):
     G.step(disp, 3)
     m, _ = G.gauss_residual()
     assert m <= 1e-12
+
+
+def _mixed_moves(rng, steps, n, big_frac=0.05):
+    """Small Gaussian moves with a fraction of components replaced by jumps of
+    up to 2.5 a (ions that the fused deposit leaves to the atomic path)."""
+    d = rng.normal(0, 0.05, size=(steps, n, 3))
+    big = rng.uniform(size=d.shape) < big_frac
+    d[big] = rng.uniform(-2.5, 2.5, size=int(big.sum()))
+    return d
+
+
+@pytest.mark.parametrize("prec", [memd.FP64, memd.FP32_MIXED])
+def test_fused_deposit_matches_atomic_path_and_oracle(prec):
+    """The deposit fused into the leapfrog (tile-owned links) and the global
+    atomic deposit give the oracle's result, with jumps of up to 2.5 a mixed in."""
+    L, n = 32, 600
+    rng = np.random.default_rng(21)
+    r = rng.uniform(0, L, size=(n, 3))
+    q = np.tile([1.0, -1.0, 2.0, -2.0], n // 4)
+    el = 2.0 + 20.0 * rng.uniform(size=3 * L ** 3)
+    S, G = pair(L, q, r, dt=0.01, eps_min=el.min(), precision=prec)
+    c = W.default_c(1.0, 0.01, el.min())
+    H = memd.Context(L, q, r, c=c, precision=prec)
+    apply_eps(S, G, "link", eps_link=el)
+    H.set_permittivity(memd.EPS_LINK, el)
+    memd.memd_set_options(H.ctx, 0, 8)
+    S.initial_solve(1e-13)
+    share_state(S, G)
+    H.set_state(*S.state())
+    assert memd.memd_counters(G.ctx)[1] == 1 and memd.memd_counters(H.ctx)[1] == 0
+    disp = _mixed_moves(rng, 12, n)
+    ftol, gtol = (1e-10, 1e-12) if prec == memd.FP64 else (1e-4, 1e-5 * 2)
+    for t in range(12):
+        S.step(disp[t])
+        G.step(disp[t], 1)
+        H.step(disp[t], 1)
+        assert G.gauss_residual()[0] <= gtol
+    Fo, _ = S.forces()
+    assert force_err(G.forces(), Fo) <= ftol
+    assert force_err(H.forces(), Fo) <= ftol
+    assert np.max(np.abs(G.state()[2] - S.r)) <= 1e-12
+
+
+def test_fused_deposit_with_stale_bins():
+    """Bins never refreshed (sort_every = 0) while ions drift several rows: the
+    drifted ions fall back to the atomic path and the result stays exact."""
+    L, n = 24, 300
+    rng = np.random.default_rng(22)
+    r = rng.uniform(0, L, size=(n, 3))
+    q = np.tile([1.0, -1.0], n // 2)
+    S, G = pair(L, q, r, dt=0.01, eps_min=5.0)
+    apply_eps(S, G, "uniform", 5.0)
+    memd.memd_set_options(G.ctx, 1, 0)
+    S.initial_solve(1e-13)
+    share_state(S, G)
+    disp = rng.normal(0, 0.4, size=(25, n, 3))
+    run_parity(S, G, disp, {5, 25}, 1e-10, 1e-12, 1e-10, audit_each=True)
+
+
+def test_rejected_moves_are_counted_and_taken_as_zero():
+    L, n = 16, 40
+    rng = np.random.default_rng(23)
+    r = rng.uniform(0, L, size=(n, 3))
+    q = np.tile([1.0, -1.0], n // 2)
+    S, G = pair(L, q, r, dt=0.01, eps_min=3.0)
+    apply_eps(S, G, "uniform", 3.0)
+    S.initial_solve(1e-13)
+    share_state(S, G)
+    disp = rng.normal(0, 0.05, size=(3, n, 3))
+    disp[1, 3, 0] = np.nan
+    disp[2, 7, 2] = 1e9
+    clean = disp.copy()
+    clean[1, 3, 0] = 0.0
+    clean[2, 7, 2] = 0.0
+    for t in range(3):
+        S.step(clean[t])
+        G.step(disp[t], 1)
+    assert memd.memd_counters(G.ctx)[0] == 2
+    assert force_err(G.forces(), S.forces()[0]) <= 1e-10
+    assert G.gauss_residual()[0] <= 1e-12
