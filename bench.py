@@ -36,9 +36,10 @@ HBM_PEAK_GBS = 8000.0
 CADENCE = 50
 
 # Algorithmic bytes (each value read once / written once).
-#   leapfrog, per site: read D[3], B[3], eta[3] (per-link permittivity), write D[3], B[3]
-#   deposit, per ion: r rw (48), disp (24), q (8), 12 link read-modify-writes
-#   forces, per ion: r (24), q (8), 12 D + 12 eta reads, F write (24)
+#   leapfrog, per site: read D[3], B[3], eta[3] (per-link permittivity), write D[3], B[3];
+#     with the fused deposit also the ion's 64-byte record
+#   ion side, per ion: pack (60 read + 64 write), update (60 read + 24 write),
+#     forces (r, q, 12 D + 12 eta, F write)
 
 
 def leapfrog_bytes_per_site(fp32: bool, per_link_eps: bool) -> int:
@@ -48,14 +49,17 @@ def leapfrog_bytes_per_site(fp32: bool, per_link_eps: bool) -> int:
 
 def ion_bytes_per_step(fp32: bool) -> int:
     t = 4 if fp32 else 8
-    deposit = 48 + 24 + 8 + 12 * 2 * t
+    pack_update = (60 + 64) + (60 + 24)
     forces = 24 + 8 + 24 * t + 24
-    return deposit + forces
+    return pack_update + forces
 
 
 def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_1309_7859_amd", "csrc", "kernels_field.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the sources of the leapfrog kernels (plain and with the fused deposit)."""
+    h = hashlib.sha256()
+    for f in ("kernels_field.hip", "leapfrog_tile.hpp", "ion_ops.hpp", "device_util.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1309_7859_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(precision: str):
@@ -115,10 +119,12 @@ def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None):
     wall = time.perf_counter() - t0
     lf_ms, lf_n = memd.memd_profile_read(G.ctx, "leapfrog")
     memd.memd_profile_enable(G.ctx, 0)
+    bad_moves, fused = memd.memd_counters(G.ctx)
     audits, energies = G.history()
     gauss_max = float(np.max(audits[:, 0])) if len(audits) else None
     G.close()
     return dict(wall=wall, lf_ms=lf_ms, lf_n=lf_n, solve_s=t_solve, solve_iters=iters, tile=tile_used,
+                fused=bool(fused), bad_moves=bad_moves,
                 solve_res=res, solve_status=st, c=c_used, eps_min=eps_min, gauss_max=gauss_max,
                 energy_last=energies[-1].tolist() if len(energies) else None)
 
@@ -192,13 +198,15 @@ def main():
     ion_steps = w.n * args.steps / r["wall"]
 
     lf_avg_s = r["lf_ms"] / 1e3 / max(r["lf_n"], 1)
-    lf_bytes = leapfrog_bytes_per_site(fp32, True) * sites
+    # the fused kernel also reads each ion's 64-byte record once
+    lf_bytes = leapfrog_bytes_per_site(fp32, True) * sites + (64 * w.n if r["fused"] else 0)
     achieved = lf_bytes / lf_avg_s / 1e9
     traffic = load_traffic(args.precision)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (round(traffic / lf_avg_s / 1e9, 1) if traffic else None),
-            "kernel": "k_leapfrog (fused Faraday + Ampere)",
+            "kernel": ("k_leapfrog_dep (Faraday + Ampere + tile-owned current deposit)" if r["fused"]
+                       else "k_leapfrog (Faraday + Ampere)"),
             "algorithmic_bytes_per_launch": lf_bytes, "avg_launch_us": round(lf_avg_s * 1e6, 2),
             "launches": r["lf_n"],
             "tile": {"x": 64, "y": 4 * r["tile"][0], "z_chunk": r["tile"][1],

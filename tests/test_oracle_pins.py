@@ -528,3 +528,35 @@ def test_seeded_displacements_are_standard_normal(orc):
     assert not np.array_equal(d, orc.seeded_displacements(2025, 3, n, 0.5))
     assert not np.array_equal(d, orc.seeded_displacements(2024, 4, n, 0.5))
     assert np.array_equal(d, orc.seeded_displacements(2024, 3, n, 0.5))
+
+
+@pytest.mark.parametrize("L,eps", [(6, 1.0), (8, 2.5)])
+def test_static_energy_is_lattice_pair_energy(orc, L, eps):
+    """With uniform eps the relaxed field energy is the lattice Coulomb energy
+    1/2 sum q_v q_v' G(v - v')/(eps a) (FFT) plus the uniform-mode energy
+    P^2/(2 V eps); removing the self energies and that mode leaves the pair
+    energy sum_{i<j} q_i q_j/(eps a) w G w (brute force)."""
+    rng = np.random.default_rng(80 + L)
+    a = 1.0
+    q, r = neutral_ions(rng, 6, L, a, valence2=True)
+    S = orc.System(L, a, 0.01, 10.0, q, r)
+    S.set_eps_uniform(eps)
+    S.initial_solve(1e-13)
+    e = S.energy()
+    rho = refs.to_zyx(S.rho(), L)
+    T = refs.green_table(L)
+    coul = 0.5 * np.sum(rho * np.real(np.fft.ifftn(np.fft.fftn(rho) * np.fft.fftn(T)))) / (eps * a)
+    V = (L * a) ** 3
+    P = S.dipole()
+    assert e["W_E"] == pytest.approx(coul + P @ P / (2 * V * eps), rel=1e-11)
+    assert e["U_dip"] == pytest.approx(P @ P / (2 * V * eps), rel=1e-14)
+    pair = 0.0
+    corners = [refs.cic_corners(r[i], a, L) for i in range(len(q))]
+    for i in range(len(q)):
+        for j in range(i + 1, len(q)):
+            s = 0.0
+            for (vi, wi, _) in corners[i]:
+                for (vj, wj, _) in corners[j]:
+                    s += wi * wj * T[(vi[2] - vj[2]) % L, (vi[1] - vj[1]) % L, (vi[0] - vj[0]) % L]
+            pair += q[i] * q[j] / (eps * a) * s
+    assert e["E_corrected"] == pytest.approx(pair, rel=1e-10, abs=1e-13)
