@@ -111,14 +111,14 @@ def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None):
     if warmup:
         memd.memd_step(G.ctx, base, warmup)
     torch.cuda.synchronize()
-    memd.memd_profile_enable(G.ctx, 1 << memd.FAMILIES["leapfrog"])
+    memd.memd_profile_enable(G.ctx, ["leapfrog"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     memd.memd_step(G.ctx, base + 8 * per * warmup, steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lf_ms, lf_n = memd.memd_profile_read(G.ctx, "leapfrog")
-    memd.memd_profile_enable(G.ctx, 0)
+    memd.memd_profile_enable(G.ctx, [])
     bad_moves, fused = memd.memd_counters(G.ctx)
     audits, energies = G.history()
     gauss_max = float(np.max(audits[:, 0])) if len(audits) else None

@@ -185,12 +185,15 @@ memd_status memd_get_stream(memd_ctx *ctx, void **stream);
 memd_status memd_get_params(memd_ctx *ctx, double *c, double eps_h[3], double *eps_min);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
- * every launch of a kernel family (0 leapfrog, 1 deposit, 2 forces, 3 audit,
- * 4 energy, 5 dipole, 6 salt).  enable = 0 stops, 1 times every family, any
- * other value is a bit mask (1 << family) of the families to time; each call
- * starts a fresh collection.  memd_profile_read waits for the stream and
- * returns the total milliseconds and the launch count of one family. */
-memd_status memd_profile_enable(memd_ctx *ctx, int enable);
+ * launches of the kernel families (0 leapfrog, 1 deposit, 2 forces, 3 audit,
+ * 4 energy, 5 dipole, 6 salt).  mask is a bit mask (1 << family) of the
+ * families to time, -1 all of them, 0 stops timing; every >= 1 times one
+ * launch in `every` of each family (the leapfrog's events ride on its own
+ * launch; the other families use marker events, which cost several
+ * microseconds each).  Each call starts a fresh collection.
+ * memd_profile_read waits for the stream and returns the total milliseconds
+ * and the number of timed launches of one family. */
+memd_status memd_profile_enable(memd_ctx *ctx, int mask, int every);
 memd_status memd_profile_read(memd_ctx *ctx, int family, double *total_ms, long *launches);
 
 /* Tile configuration of the leapfrog kernel: rows per thread (1, 2 or 4: a

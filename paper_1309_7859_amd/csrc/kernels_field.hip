@@ -82,7 +82,8 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
     if (with_deposit) {
         hipError_t e = launch_pack_ions(c, disp, seed, t, sigma);
         if (e != hipSuccess) return e;
-        P.rec = (const IonRec *)c->ionrec;
+        P.head = (const int4 *)c->ionrec;
+        P.con = (const int4 *)c->ionrec + c->n;
         P.row_count = c->bins;
         P.row_start = c->bins + (size_t)c->L * c->L;
         P.a = c->a;

@@ -86,41 +86,113 @@ hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_
     return hipGetLastError();
 }
 
-// Records of the ions in bin order for the fused deposit: slot s holds ion
-// order[s] (position r^n, displacement from disp or from the Philox stream,
-// rejected components taken as 0, charge, bin row).
+// Records of the ions in bin order for the fused deposit (leapfrog_tile.hpp,
+// DepCon): ions are read in index order (coalesced), four lanes per ion, and
+// ion i's record goes to its slot slot_of[i].  Lane d < 3 walks
+// axis d of the dimension-split move from the position the earlier axes left
+// (the arithmetic of deposit_ion, bit for bit) and stores each link
+// contribution -q (ub - ua)/a w w / a^2 (in the field type) with its code;
+// lane 3 writes the head.  An irregular ion gets the head count -1.
+template <typename T>
 __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const double *__restrict__ q,
                                                    const double *__restrict__ r, const double *__restrict__ disp,
-                                                   const int *__restrict__ order, const int *__restrict__ binrow,
-                                                   IonRec *__restrict__ rec, uint64_t seed, uint32_t t, double sigma) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int i = order[s];
+                                                   const int *__restrict__ slot_of, const int *__restrict__ binrow,
+                                                   int4 *__restrict__ head, DepCon<T> *__restrict__ con,
+                                                   uint64_t seed, uint32_t t, double sigma) {
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+    const int lane = threadIdx.x & 3;
+    if (i >= n) return;  // whole groups of four leave together
+    const int s = slot_of[i];
+    double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
     double du[3];
     if (disp) {
         du[0] = disp[3 * i];
         du[1] = disp[3 * i + 1];
         du[2] = disp[3 * i + 2];
     } else {
-        philox_displacement(seed, t, (uint32_t)i, sigma, du);
+        if (lane == 0) philox_displacement(seed, t, (uint32_t)i, sigma, du);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) du[d] = __shfl(du[d], 0, 4);
     }
     sanitize_move(du, a, L, nullptr);
-    IonRec o;
-    o.u[0] = r[3 * i];
-    o.u[1] = r[3 * i + 1];
-    o.u[2] = r[3 * i + 2];
-    o.du[0] = du[0];
-    o.du[1] = du[1];
-    o.du[2] = du[2];
-    o.q = q[i];
-    o.binrow = (double)binrow[i];
-    rec[s] = o;
+    int c0[3];
+    {
+        double f;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fold(u[d], a, L, c0[d], f);
+    }
+    const bool regular = ion_regular(a, L, u, du, binrow[i]);
+    int nc = 0;
+    if (regular && lane < 3) {
+        const int d = lane;
+        const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+        // the position after the moves of the axes before d
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+            if (e < d) u[e] = u[e] + du[e];
+        const double u0 = u[d], u1 = u0 + du[d];
+        DepCon<T> &o = con[s];
+        unsigned int words[2] = {0u, 0u};
+        if (u1 != u0) {
+            const double qi = q[i], a2 = a * a;
+            int c1, c2;
+            double f1, f2;
+            fold(u[d1], a, L, c1, f1);
+            fold(u[d2], a, L, c2, f2);
+            const double lo = u0 < u1 ? u0 : u1, hi = u0 < u1 ? u1 : u0;
+            const double sgn = u1 > u0 ? 1.0 : -1.0;
+            const long long klo = (long long)floor(lo / a), khi = (long long)floor(hi / a);
+            for (long long kc = klo; kc <= khi && nc < kConPerAxis; ++kc) {
+                const double s0 = (double)kc * a, s1 = (double)(kc + 1) * a;
+                const double sa = lo > s0 ? lo : s0;
+                const double sb = hi < s1 ? hi : s1;
+                const double len = sb - sa;
+                if (!(len > 0.0)) continue;
+                const double amount = qi * sgn * (len / a) / a2;
+                long long km = kc % (long long)L;
+                if (km < 0) km += L;
+#pragma unroll
+                for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                    for (int o1 = 0; o1 < 2; ++o1) {
+                        int x[3];
+                        x[d] = (int)km;
+                        x[d1] = o1 ? (c1 + 1 == L ? 0 : c1 + 1) : c1;
+                        x[d2] = o2 ? (c2 + 1 == L ? 0 : c2 + 1) : c2;
+                        // offset + 1 taken modulo L into [0, L): the offsets
+                        // of a regular ion lie in [-1, 2]
+                        unsigned int code = 0u;
+#pragma unroll
+                        for (int e = 0; e < 3; ++e) {
+                            int off = x[e] - c0[e] + 1;
+                            off += off < 0 ? L : (off >= L ? -L : 0);
+                            code |= (unsigned int)off << (2 * e);
+                        }
+                        const double val = amount * lin_w(o1, f1) * lin_w(o2, f2);
+                        words[nc >> 2] |= code << (8 * (nc & 3));
+                        o.val[kConPerAxis * d + nc] = (T)(-val);
+                        ++nc;
+                    }
+            }
+        }
+        o.code[2 * d] = words[0];
+        o.code[2 * d + 1] = words[1];
+    }
+    const int n0 = __shfl(nc, 0, 4), n1 = __shfl(nc, 1, 4), n2 = __shfl(nc, 2, 4);
+    if (lane == 3) head[s] = make_int4(c0[0], c0[1], c0[2], regular ? (n0 | (n1 << 4) | (n2 << 8)) : -1);
 }
 
 hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma) {
     if (c->n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_ions, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->q,
-                       c->r, disp, c->order, c->binrow, (IonRec *)c->ionrec, seed, t, sigma);
+    const int nb = (int)(((size_t)c->n * 4 + kThreads - 1) / kThreads);
+    if (c->fp32)
+        hipLaunchKernelGGL(k_pack_ions<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L,
+                           c->a, c->q, c->r, disp, c->slot, c->binrow, (int4 *)c->ionrec,
+                           (DepCon<float> *)((int4 *)c->ionrec + c->n), seed, t, sigma);
+    else
+        hipLaunchKernelGGL(k_pack_ions<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L,
+                           c->a, c->q, c->r, disp, c->slot, c->binrow, (int4 *)c->ionrec,
+                           (DepCon<double> *)((int4 *)c->ionrec + c->n), seed, t, sigma);
     return hipGetLastError();
 }
 
@@ -379,40 +451,68 @@ __global__ void k_bin_count(int n, int L, double a, const double *__restrict__ r
     atomicAdd(&count[cy + L * cz], 1);
 }
 
-// Exclusive scan of count[0..nb) into cursor[0..nb) (one block of 1024):
-// the bins are taken in tiles of 1024, each scanned with wavefront prefix
-// sums plus a pass over the 16 wavefront totals.
+// Exclusive scan of count[0..nb) into start and cursor (one block of 1024).
+// The bins are taken in super-tiles of 16384: every thread loads its four
+// runs of four bins (bins base + 4096 j + 4t .. +3) at once, then the four
+// tiles of 4096 are scanned in turn (sums of four, wavefront prefix sums,
+// the 16 wavefront totals in LDS) with a running carry.
 __global__ __launch_bounds__(1024) void k_bin_scan(const int *__restrict__ count, int nb, int *__restrict__ start,
                                                    int *__restrict__ cursor) {
     __shared__ int wsum[16];
-    __shared__ int carry;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    if (t == 0) carry = 0;
-    __syncthreads();
-    for (int base = 0; base < nb; base += 1024) {
-        const int v = (base + t < nb) ? count[base + t] : 0;
-        int x = v;
+    int carry = 0;
+    for (int base = 0; base < nb; base += 16384) {
+        int v[4][4];
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
+        for (int j = 0; j < 4; ++j) {
+            const int idx = base + 4096 * j + 4 * t;
+            if (idx + 3 < nb && (nb & 3) == 0) {
+                const int4 w = *reinterpret_cast<const int4 *>(count + idx);
+                v[j][0] = w.x;
+                v[j][1] = w.y;
+                v[j][2] = w.z;
+                v[j][3] = w.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[j][e] = idx + e < nb ? count[idx + e] : 0;
+            }
         }
-        if (lane == 63) wsum[wid] = x;
-        __syncthreads();
-        int before = carry;
-        for (int w = 0; w < wid; ++w) before += wsum[w];
-        if (base + t < nb) {
-            start[base + t] = before + x - v;
-            cursor[base + t] = before + x - v;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int idx = base + 4096 * j + 4 * t;
+            const int s4 = v[j][0] + v[j][1] + v[j][2] + v[j][3];
+            int x = s4;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            if (lane == 63) wsum[wid] = x;
+            __syncthreads();
+            int before = carry, total = 0;
+#pragma unroll
+            for (int w = 0; w < 16; ++w) {
+                const int ws = wsum[w];
+                if (w < wid) before += ws;
+                total += ws;
+            }
+            int run = before + x - s4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (idx + e < nb) {
+                    start[idx + e] = run;
+                    cursor[idx + e] = run;
+                }
+                run += v[j][e];
+            }
+            carry += total;
+            __syncthreads();
         }
-        __syncthreads();
-        if (t == 1023) carry = before + x;
-        __syncthreads();
     }
 }
 
 __global__ void k_bin_scatter(int n, int L, double a, const double *__restrict__ r, int *__restrict__ cursor,
-                              int *__restrict__ order, int *__restrict__ binrow) {
+                              int *__restrict__ order, int *__restrict__ slot_of, int *__restrict__ binrow) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int cy, cz;
@@ -422,6 +522,7 @@ __global__ void k_bin_scatter(int n, int L, double a, const double *__restrict__
     const int row = cy + L * cz;
     const int slot = atomicAdd(&cursor[row], 1);
     order[slot] = i;
+    slot_of[i] = slot;
     binrow[i] = row;
 }
 
@@ -440,7 +541,7 @@ hipError_t launch_bin_ions(memd_ctx *c) {
                        count);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, count, nb, start, cursor);
     hipLaunchKernelGGL(k_bin_scatter, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
-                       c->r, cursor, c->order, c->binrow);
+                       c->r, cursor, c->order, c->slot, c->binrow);
     return hipGetLastError();
 }
 

@@ -55,14 +55,25 @@ __device__ __forceinline__ T eta_at(const LfArgs<T> &A, int d, int gz, size_t of
 // tile finds every regular ion touching its links in the bin rows
 // [y0 - 3, y0 + TY + 1] x [z0 - 3, z0 + TZ + 1].  Other ions are deposited
 // by the follow-up ion kernel with global atomics.
-// One record per ion in bin order (written each step by k_pack_ions):
-// position r^n, displacement, charge, bin row.
-struct IonRec {
-    double u[3], du[3], q, binrow;
+// Records of the ions in bin order, written each step by k_pack_ions, in two
+// arrays: a head per ion (start cell x, y, z and the contribution counts n_d
+// of the three axes in bits 4d..4d+3; -1 marks an ion left to the atomic
+// path) and the contributions of a regular ion's whole move: axis d of the
+// dimension-split move crosses at most 2 cells, 4 links each, stored in slots
+// 8d..8d+7 as a code byte (link-origin offset from the start cell plus one
+// in bits 0-1 (x), 2-3 (y), 4-5 (z); offsets lie in [-1, 2]) and the value to
+// add to D_d there.
+constexpr int kConPerAxis = 8;
+
+template <typename T>
+struct DepCon {
+    unsigned int code[3 * kConPerAxis / 4];
+    T val[3 * kConPerAxis];
 };
 
 struct DepArgs {
-    const IonRec *rec;      // [n] records in bin order
+    const int4 *head;       // [n] start cell (x, y, z) and ncon, in bin order
+    const void *con;        // [n] DepCon<T>, in bin order
     const int *row_start;   // [L^2] first slot of each row
     const int *row_count;   // [L^2]
     double a;
@@ -171,28 +182,43 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         T *accf = &DS->acc[0][0][0][0];
         for (int t = threadIdx.x; t < 3 * kDepTZ * TY * 64; t += blockDim.x) accf[t] = (T)0;
         const int nry = TY + 5, nrz = (z1 - z0) + 5, nrows = nry * nrz;
-        for (int t = threadIdx.x; t < nrows; t += blockDim.x) {
-            const int by = wrapc(y0 - 3 + t % nry + L, L), bz = wrapc(z0 - 3 + t / nry + L, L);
-            DS->rowpre[t + 1] = dep->row_count[by + L * bz];
-            DS->rowbase[t] = dep->row_start[by + L * bz];
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int run = 0;
-            DS->rowpre[0] = 0;
-            for (int t = 1; t <= nrows; ++t) {
-                run += DS->rowpre[t];
-                DS->rowpre[t] = run;
+        static_assert((4 * R + 5) * (kDepTZ + 5) <= 128, "candidate rows: two per lane of one wavefront");
+        if (wy == 0) {
+            // wavefront 0: counts and starts of the candidate rows, two rows
+            // per lane, prefix sums with cross-lane shifts
+            int cnt[2], st[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int t = 2 * lx + j;
+                cnt[j] = 0;
+                st[j] = 0;
+                if (t < nrows) {
+                    const int by = wrapc(y0 - 3 + t % nry + L, L), bz = wrapc(z0 - 3 + t / nry + L, L);
+                    cnt[j] = dep->row_count[by + L * bz];
+                    st[j] = dep->row_start[by + L * bz];
+                }
+            }
+            const int pair = cnt[0] + cnt[1];
+            int incl = pair;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o, 64);
+                if (lx >= o) incl += y;
+            }
+            const int excl = incl - pair;
+            if (lx == 0) DS->rowpre[0] = 0;
+            if (2 * lx < nrows) {
+                DS->rowpre[2 * lx + 1] = excl + cnt[0];
+                DS->rowbase[2 * lx] = st[0] - excl;
+            }
+            if (2 * lx + 1 < nrows) {
+                DS->rowpre[2 * lx + 2] = incl;
+                DS->rowbase[2 * lx + 1] = st[1] - (excl + cnt[0]);
             }
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < nrows; t += blockDim.x) DS->rowbase[t] -= DS->rowpre[t];
-        __syncthreads();
         const int total = DS->rowpre[nrows];
-        const double a = dep->a, a2 = a * a;
-        const double inv_a = 1.0 / a, inv_a2 = 1.0 / a2;
-        int ea;
-        const bool a_pow2 = frexp(a, &ea) == 0.5;
+        const DepCon<T> *con = (const DepCon<T> *)dep->con;
         const int ylim = min(y0 + TY, L), zlim = z1;
         for (int cidx = threadIdx.x; cidx < total; cidx += blockDim.x) {
             int lo = 0, hi = nrows - 1;
@@ -201,61 +227,32 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
                 if (DS->rowpre[mid] <= cidx) lo = mid;
                 else hi = mid - 1;
             }
-            const IonRec &rc = dep->rec[DS->rowbase[lo] + cidx];
-            double u[3] = {rc.u[0], rc.u[1], rc.u[2]};
-            const double du[3] = {rc.du[0], rc.du[1], rc.du[2]};
-            {
-                // a regular ion in start cell c touches x in [c-1, c+2] only
-                // (periodic: cx in [x0 - 2, x0 + TX] modulo L; no filter when the
-                // window covers the whole lattice)
-                int cx;
-                double fx;
-                fold_fast(u[0], a, inv_a, a_pow2, L, cx, fx);
-                const int dxm = ((cx - x0 + 2) % L + L) % L;
-                if (L > TX + 4 && dxm > TX + 2) continue;
-            }
-            if (!ion_regular(a, L, u, du, (int)rc.binrow)) continue;
-            const double qi = rc.q;
+            const int slot = DS->rowbase[lo] + cidx;
+            const int4 h = dep->head[slot];
+            if (h.w <= 0) continue;
+            // the links of a regular ion starting in cell c have origins in
+            // [c - 1, c + 2] per axis: skip ions that cannot touch this tile
+            // (periodic; no test along an axis the window covers)
+            const int ex = ((h.x - x0 + 2) % L + L) % L, ey = ((h.y - y0 + 2) % L + L) % L,
+                      ez = ((h.z - z0 + 2) % L + L) % L;
+            if ((L > TX + 4 && ex > TX + 2) || (L > TY + 4 && ey > TY + 2) || (L > (z1 - z0) + 4 && ez > (z1 - z0) + 2))
+                continue;
+            const DepCon<T> &cn = con[slot];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-                const double u0 = u[d], u1 = u0 + du[d];
-                if (u1 != u0) {
-                    int c1, c2;
-                    double f1, f2;
-                    fold_fast(u[d1], a, inv_a, a_pow2, L, c1, f1);
-                    fold_fast(u[d2], a, inv_a, a_pow2, L, c2, f2);
-                    const double lo_ = u0 < u1 ? u0 : u1, hi_ = u0 < u1 ? u1 : u0;
-                    const double sgn = u1 > u0 ? 1.0 : -1.0;
-                    const long long klo = (long long)floor(a_pow2 ? lo_ * inv_a : lo_ / a);
-                    const long long khi = (long long)floor(a_pow2 ? hi_ * inv_a : hi_ / a);
-                    for (long long kc = klo; kc <= khi; ++kc) {
-                        const double s0 = (double)kc * a, s1 = (double)(kc + 1) * a;
-                        const double sa = lo_ > s0 ? lo_ : s0;
-                        const double sb = hi_ < s1 ? hi_ : s1;
-                        const double len = sb - sa;
-                        if (!(len > 0.0)) continue;
-                        const double amount =
-                            a_pow2 ? qi * sgn * (len * inv_a) * inv_a2 : qi * sgn * (len / a) / a2;
-                        long long km = kc % (long long)L;
-                        if (km < 0) km += L;
-#pragma unroll
-                        for (int o2 = 0; o2 < 2; ++o2)
-#pragma unroll
-                            for (int o1 = 0; o1 < 2; ++o1) {
-                                int x[3];
-                                x[d] = (int)km;
-                                x[d1] = o1 ? (c1 + 1 == L ? 0 : c1 + 1) : c1;
-                                x[d2] = o2 ? (c2 + 1 == L ? 0 : c2 + 1) : c2;
-                                if (x[0] < x0 || x[0] >= x0 + TX || x[1] < y0 || x[1] >= ylim || x[2] < z0 ||
-                                    x[2] >= zlim)
-                                    continue;
-                                const double val = amount * lin_w(o1, f1) * lin_w(o2, f2);
-                                atomicAdd(&DS->acc[d][x[2] - z0][x[1] - y0][x[0] - x0], (T)(-val));
-                            }
-                    }
+                const int nd = (h.w >> (4 * d)) & 15;
+                if (nd == 0) continue;
+                const unsigned int w0 = cn.code[2 * d], w1 = cn.code[2 * d + 1];
+                for (int k = 0; k < nd; ++k) {
+                    const unsigned int code = ((k < 4 ? w0 : w1) >> (8 * (k & 3))) & 255u;
+                    int xx = h.x + (int)(code & 3) - 1, yy = h.y + (int)((code >> 2) & 3) - 1,
+                        zz = h.z + (int)((code >> 4) & 3) - 1;
+                    xx += xx < 0 ? L : (xx >= L ? -L : 0);
+                    yy += yy < 0 ? L : (yy >= L ? -L : 0);
+                    zz += zz < 0 ? L : (zz >= L ? -L : 0);
+                    if (xx < x0 || xx >= x0 + TX || yy < y0 || yy >= ylim || zz < z0 || zz >= zlim) continue;
+                    atomicAdd(&DS->acc[d][zz - z0][yy - y0][xx - x0], cn.val[kConPerAxis * d + k]);
                 }
-                u[d] = u1;
             }
         }
         __syncthreads();

@@ -10,6 +10,7 @@
 #include <new>
 #include <vector>
 
+#include "leapfrog_tile.hpp"
 #include "memd_internal.hpp"
 #include "serve_internal.hpp"
 
@@ -74,21 +75,37 @@ hipError_t ensure_stage(memd_ctx *c, size_t bytes) {
     return hipSuccess;
 }
 
+// Whether this launch of family fam is one of the timed ones.
+static bool prof_take(memd_ctx *c, int fam) {
+    if (!c->prof_on || !(c->prof_mask & (1u << fam))) return false;
+    return c->prof[fam].seen++ % c->prof_every == 0;
+}
+
 void prof_begin(memd_ctx *c, int fam) {
-    if (!c->prof_on || !(c->prof_mask & (1u << fam))) return;
+    auto &P = c->prof[fam];
+    P.open = false;
+    if (!prof_take(c, fam)) return;
     hipEvent_t e;
     if (hipEventCreate(&e) == hipSuccess) {
-        hipEventRecord(e, c->stream);
-        c->prof[fam].start.push_back(e);
+        if (hipEventRecord(e, c->stream) == hipSuccess) {
+            P.start.push_back(e);
+            P.open = true;
+        } else {
+            hipEventDestroy(e);
+        }
     }
 }
 
 void prof_end(memd_ctx *c, int fam) {
-    if (!c->prof_on || !(c->prof_mask & (1u << fam))) return;
+    auto &P = c->prof[fam];
+    if (!P.open) return;
+    P.open = false;
     hipEvent_t e;
-    if (hipEventCreate(&e) == hipSuccess) {
-        hipEventRecord(e, c->stream);
-        c->prof[fam].stop.push_back(e);
+    if (hipEventCreate(&e) == hipSuccess && hipEventRecord(e, c->stream) == hipSuccess) {
+        P.stop.push_back(e);
+    } else {
+        hipEventDestroy(P.start.back());
+        P.start.pop_back();
     }
 }
 
@@ -96,7 +113,7 @@ void prof_end(memd_ctx *c, int fam) {
 // records them at the kernel's own start and end, with no marker packets).
 void prof_pair(memd_ctx *c, int fam, hipEvent_t *e0, hipEvent_t *e1) {
     *e0 = *e1 = nullptr;
-    if (!c->prof_on || !(c->prof_mask & (1u << fam))) return;
+    if (!prof_take(c, fam)) return;
     if (hipEventCreate(e0) != hipSuccess) return;
     if (hipEventCreate(e1) != hipSuccess) {
         hipEventDestroy(*e0);
@@ -113,6 +130,8 @@ void prof_clear(memd_ctx *c) {
         for (auto e : c->prof[f].stop) hipEventDestroy(e);
         c->prof[f].start.clear();
         c->prof[f].stop.clear();
+        c->prof[f].seen = 0;
+        c->prof[f].open = false;
     }
 }
 
@@ -228,7 +247,7 @@ void memd_destroy(memd_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     prof_clear(c);
     void *bufs[] = {c->D[0], c->D[1], c->B[0], c->B[1], c->eta_prof, c->eta_link, c->q, c->r, c->F,
-                    c->order, c->bins, c->binrow, c->bad_moves, c->ionrec,
+                    c->order, c->slot, c->bins, c->binrow, c->bad_moves, c->ionrec,
                     c->stage, c->rho, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt,
                     c->salt_nbar};
     for (void *b : bufs)
@@ -253,6 +272,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     if (!c) return MEMD_ENOMEM;
     c->p = *p;
     c->n = n;
+    c->prof_every = 1;
     c->L = p->L;
     c->Ns = Ns;
     c->a = p->a;
@@ -310,9 +330,11 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
         hipMalloc((void **)&c->r, 3 * nn * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->F, 3 * nn * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->order, nn * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&c->slot, nn * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->bins, 3 * (size_t)p->L * p->L * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->binrow, nn * sizeof(int)) != hipSuccess ||
-        hipMalloc(&c->ionrec, nn * 8 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->ionrec, nn * (sizeof(int4) + (c->fp32 ? sizeof(DepCon<float>) : sizeof(DepCon<double>)))) !=
+            hipSuccess ||
         hipMalloc((void **)&c->bad_moves, sizeof(unsigned int)) != hipSuccess ||
         hipMalloc((void **)&c->rho, Ns * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->partials, partial_doubles(n) * sizeof(double)) != hipSuccess ||
@@ -483,11 +505,12 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
             CK(launch_ion_update(c, c->D[nx], dstep, audit_now, c->partials, &nb, seed, tstep, sigma));
         else
             CK(launch_deposit(c, c->D[nx], dstep, audit_now, c->partials, &nb, seed, tstep, sigma));
-        CK(launch_finalize_dipole(c->stream, c->partials, nb, c->scal + S_P));
         prof_end(c, F_DEPOSIT);
         c->cur = nx;
         prof_begin(c, F_FORCES);
-        CK(launch_forces(c, c->D[c->cur], nullptr, 0));  // P was formed by the deposit
+        // every force block sums the deposit's per-block q r partials into P
+        // (block 0 also stores it)
+        CK(launch_forces(c, c->D[c->cur], c->partials, nb));
         prof_end(c, F_FORCES);
         if (audit_now) {
             const int slot = c->hist_audit_n < c->hist_cap ? c->hist_audit_n : c->hist_cap - 1;
@@ -675,12 +698,14 @@ memd_status memd_get_params(memd_ctx *c, double *cc, double eps_h[3], double *ep
     return MEMD_OK;
 }
 
-memd_status memd_profile_enable(memd_ctx *c, int enable) {
+memd_status memd_profile_enable(memd_ctx *c, int mask, int every) {
     CHECK_CTX(c);
+    if (every < 1) return MEMD_EINVAL;
     CK(hipStreamSynchronize(c->stream));
     prof_clear(c);
-    c->prof_on = enable != 0;
-    c->prof_mask = enable == 1 ? 0xffffffffu : (unsigned)enable;
+    c->prof_on = mask != 0;
+    c->prof_mask = (unsigned)mask;
+    c->prof_every = every;
     return MEMD_OK;
 }
 

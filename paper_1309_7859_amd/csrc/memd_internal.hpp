@@ -44,6 +44,8 @@ struct EtaDesc {
 
 struct ProfileEvents {
     std::vector<hipEvent_t> start, stop;
+    long seen = 0;  // launches of the family since the collection started
+    bool open = false;  // a begin event is waiting for its end
 };
 
 }  // namespace memd
@@ -84,9 +86,10 @@ struct memd_ctx {
     double *r;     // [3n]
     double *F;     // [3n]
     int *order;    // [n] ion visiting order (binned by lattice row), refreshed every sort_every steps
+    int *slot;     // [n] inverse of order: the slot of ion i
     int *bins;     // [3 L^2] bin counts, row starts, cursors
     int *binrow;   // [n] bin row of each ion at the last sort
-    void *ionrec;  // [n] 64-byte ion records in bin order (fused deposit)
+    void *ionrec;  // ion records in bin order for the fused deposit: [n] int4 heads, then [n] contributions
     unsigned int *bad_moves;  // rejected displacement components (not finite or > L a)
     bool fuse_deposit;
     int sort_every;
@@ -113,6 +116,7 @@ struct memd_ctx {
     // profiling
     bool prof_on;
     unsigned prof_mask;
+    int prof_every;
     memd::ProfileEvents prof[memd::F_NFAM];
 };
 

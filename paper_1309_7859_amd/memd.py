@@ -68,7 +68,7 @@ def load():
         "memd_set_state": [vp, vp, vp, vp],
         "memd_get_stream": [vp, C.POINTER(vp)],
         "memd_get_params": [vp, dp, vp, dp],
-        "memd_profile_enable": [vp, i],
+        "memd_profile_enable": [vp, i, i],
         "memd_profile_read": [vp, i, dp, C.POINTER(C.c_long)],
         "memd_set_tiling": [vp, i, i],
         "memd_autotune": [vp, i, C.c_char_p, C.POINTER(i), C.POINTER(i), dp],
@@ -227,8 +227,16 @@ def memd_get_params(ctx: int):
     return c.value, eh, em.value
 
 
-def memd_profile_enable(ctx: int, enable: bool = True):
-    _check(load().memd_profile_enable(ctx, 1 if enable else 0), "memd_profile_enable")
+def memd_profile_enable(ctx: int, families=None, every: int = 1):
+    """Time the kernel families named in `families` (all when None, none when
+    empty) on one launch in `every`."""
+    if families is None:
+        mask = -1
+    else:
+        mask = 0
+        for f in families:
+            mask |= 1 << (FAMILIES[f] if isinstance(f, str) else int(f))
+    _check(load().memd_profile_enable(ctx, mask, every), "memd_profile_enable")
 
 
 def memd_profile_read(ctx: int, family) -> tuple:
