@@ -15,29 +15,36 @@ __device__ __forceinline__ int wrapc(int i, int L) {
     return i;
 }
 
+// x / a, as an exponent shift when a is a power of two (then exactly the
+// quotient), else a division.  a is the same for every lane, so the branch
+// does not diverge; FP64 division is a long instruction sequence on the GPU.
+__device__ __forceinline__ double div_a(double x, double a) {
+    int e;
+    const double m = frexp(a, &e);
+    return m == 0.5 ? ldexp(x, 1 - e) : x / a;
+}
+
+// k mod L in [0, L) for an integer-valued double k with |k| < 2^51 L: the
+// quotient's floor comes from k * (1/L), is off by at most one, and one
+// correction fixes it; k - L q is then exact.  (No 64-bit integer division,
+// which is a long software sequence on the GPU.)  The final clamp never
+// changes a correct result.
+__device__ __forceinline__ int mod_cell(double k, int L) {
+    const double Ld = (double)L;
+    double m = k - Ld * floor(k * (1.0 / Ld));
+    if (m < 0.0) m += Ld;
+    else if (m >= Ld) m -= Ld;
+    const int c = (int)m;
+    return c < 0 ? 0 : (c >= L ? L - 1 : c);
+}
+
 // Fold an unfolded coordinate: t = u/a, k = floor(t), f = t - k in [0, 1),
 // folded cell c = k mod L.
 __device__ __forceinline__ void fold(double u, double a, int L, int &c, double &f) {
-    double t = u / a;
-    double fl = floor(t);
-    f = t - fl;
-    long long k = (long long)fl;
-    long long m = k % (long long)L;
-    if (m < 0) m += L;
-    c = (int)m;
-}
-
-// The same fold with u/a formed as u * inv_a when a is a power of two (then
-// the product is exactly the quotient, so every cell decision is unchanged).
-__device__ __forceinline__ void fold_fast(double u, double a, double inv_a, bool a_pow2, int L, int &c,
-                                          double &f) {
-    const double t = a_pow2 ? u * inv_a : u / a;
+    const double t = div_a(u, a);
     const double fl = floor(t);
     f = t - fl;
-    long long k = (long long)fl;
-    long long m = k % (long long)L;
-    if (m < 0) m += L;
-    c = (int)m;
+    c = mod_cell(fl, L);
 }
 
 __device__ __forceinline__ double lin_w(int o, double f) { return o ? f : 1.0 - f; }

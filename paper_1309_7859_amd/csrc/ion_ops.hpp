@@ -59,17 +59,16 @@ __device__ __forceinline__ void deposit_ion(int L, size_t Ns, double a, double q
         if (u1 != u0) {
             const double lo = u0 < u1 ? u0 : u1, hi = u0 < u1 ? u1 : u0;
             const double sgn = u1 > u0 ? 1.0 : -1.0;
-            const long long klo = (long long)floor(lo / a), khi = (long long)floor(hi / a);
+            const double klo = floor(div_a(lo, a)), khi = floor(div_a(hi, a));
             const int c1p = c1 + 1 == L ? 0 : c1 + 1, c2p = c2 + 1 == L ? 0 : c2 + 1;
-            for (long long kc = klo; kc <= khi; ++kc) {
-                const double s0 = (double)kc * a, s1 = (double)(kc + 1) * a;
+            for (double kc = klo; kc <= khi; kc += 1.0) {
+                const double s0 = kc * a, s1 = (kc + 1.0) * a;
                 const double sa = lo > s0 ? lo : s0;
                 const double sb = hi < s1 ? hi : s1;
                 const double len = sb - sa;
                 if (!(len > 0.0)) continue;
-                const double amount = qi * sgn * (len / a) / a2;
-                long long km = kc % (long long)L;
-                if (km < 0) km += L;
+                const double amount = div_a(qi * sgn * div_a(len, a), a2);
+                const int km = mod_cell(kc, L);
                 int x[3];
                 x[d] = (int)km;
 #pragma unroll
@@ -113,16 +112,15 @@ __device__ __forceinline__ void deposit_ion_part(int L, size_t Ns, double a, dou
             const int x2 = o2 ? (c2 + 1 == L ? 0 : c2 + 1) : c2;
             const double lo = u0 < u1 ? u0 : u1, hi = u0 < u1 ? u1 : u0;
             const double sgn = u1 > u0 ? 1.0 : -1.0;
-            const long long klo = (long long)floor(lo / a), khi = (long long)floor(hi / a);
-            for (long long kc = klo; kc <= khi; ++kc) {
-                const double s0 = (double)kc * a, s1 = (double)(kc + 1) * a;
+            const double klo = floor(div_a(lo, a)), khi = floor(div_a(hi, a));
+            for (double kc = klo; kc <= khi; kc += 1.0) {
+                const double s0 = kc * a, s1 = (kc + 1.0) * a;
                 const double sa = lo > s0 ? lo : s0;
                 const double sb = hi < s1 ? hi : s1;
                 const double len = sb - sa;
                 if (!(len > 0.0)) continue;
-                const double amount = qi * sgn * (len / a) / a2;
-                long long km = kc % (long long)L;
-                if (km < 0) km += L;
+                const double amount = div_a(qi * sgn * div_a(len, a), a2);
+                const int km = mod_cell(kc, L);
                 int x[3];
                 x[d] = (int)km;
                 x[d1] = x1;

@@ -70,7 +70,7 @@ static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, voi
 }
 
 bool fused_deposit_ok(const memd_ctx *c) {
-    return c->fuse_deposit && c->n > 0 && c->L >= 16 && c->lf_tz <= kDepTZ &&
+    return c->fuse_deposit && c->n > 0 && c->L >= 16 && c->L <= 1024 && c->lf_tz <= kDepTZ &&
            c->lf_rows <= (c->fp32 ? 2 : 1);
 }
 

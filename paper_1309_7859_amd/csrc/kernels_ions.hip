@@ -88,11 +88,11 @@ hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_
 
 // Records of the ions in bin order for the fused deposit (leapfrog_tile.hpp,
 // DepCon): ions are read in index order (coalesced), four lanes per ion, and
-// ion i's record goes to its slot slot_of[i].  Lane d < 3 walks
-// axis d of the dimension-split move from the position the earlier axes left
-// (the arithmetic of deposit_ion, bit for bit) and stores each link
-// contribution -q (ub - ua)/a w w / a^2 (in the field type) with its code;
-// lane 3 writes the head.  An irregular ion gets the head count -1.
+// ion i's record goes to its slot slot_of[i].  Lane d < 3 takes axis d of the
+// dimension-split move from the position the earlier axes left (the
+// arithmetic of deposit_ion, bit for bit) and writes its box corner and the
+// values -q (ub - ua)/a w w / a^2 (in the field type); lane 3 writes the
+// head.  An irregular ion gets the head -1.
 template <typename T>
 __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const double *__restrict__ q,
                                                    const double *__restrict__ r, const double *__restrict__ disp,
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const
         for (int d = 0; d < 3; ++d) fold(u[d], a, L, c0[d], f);
     }
     const bool regular = ion_regular(a, L, u, du, binrow[i]);
-    int nc = 0;
+    unsigned int g = 0u;
     if (regular && lane < 3) {
         const int d = lane;
         const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
@@ -131,9 +131,8 @@ __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const
         for (int e = 0; e < 3; ++e)
             if (e < d) u[e] = u[e] + du[e];
         const double u0 = u[d], u1 = u0 + du[d];
-        DepCon<T> &o = con[s];
-        unsigned int words[2] = {0u, 0u};
         if (u1 != u0) {
+            DepCon<T> &o = con[s];
             const double qi = q[i], a2 = a * a;
             int c1, c2;
             double f1, f2;
@@ -141,45 +140,33 @@ __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const
             fold(u[d2], a, L, c2, f2);
             const double lo = u0 < u1 ? u0 : u1, hi = u0 < u1 ? u1 : u0;
             const double sgn = u1 > u0 ? 1.0 : -1.0;
-            const long long klo = (long long)floor(lo / a), khi = (long long)floor(hi / a);
-            for (long long kc = klo; kc <= khi && nc < kConPerAxis; ++kc) {
-                const double s0 = (double)kc * a, s1 = (double)(kc + 1) * a;
+            const double klo = floor(div_a(lo, a)), khi = floor(div_a(hi, a));
+            int corner[3];
+            corner[d] = mod_cell(klo, L);
+            corner[d1] = c1;
+            corner[d2] = c2;
+            g = (unsigned)pack_cell(corner[0], corner[1], corner[2]) | kGroupOn | (khi > klo ? kGroupTwo : 0u);
+            // a regular move spans at most two cells along the axis
+#pragma unroll
+            for (int cell = 0; cell < 2; ++cell) {
+                const double kc = cell ? khi : klo;
+                const double s0 = kc * a, s1 = (kc + 1.0) * a;
                 const double sa = lo > s0 ? lo : s0;
                 const double sb = hi < s1 ? hi : s1;
                 const double len = sb - sa;
-                if (!(len > 0.0)) continue;
-                const double amount = qi * sgn * (len / a) / a2;
-                long long km = kc % (long long)L;
-                if (km < 0) km += L;
+                const double amount = (cell == 0 || khi > klo) && len > 0.0 ? div_a(qi * sgn * div_a(len, a), a2) : 0.0;
 #pragma unroll
                 for (int o2 = 0; o2 < 2; ++o2)
 #pragma unroll
-                    for (int o1 = 0; o1 < 2; ++o1) {
-                        int x[3];
-                        x[d] = (int)km;
-                        x[d1] = o1 ? (c1 + 1 == L ? 0 : c1 + 1) : c1;
-                        x[d2] = o2 ? (c2 + 1 == L ? 0 : c2 + 1) : c2;
-                        // offset + 1 taken modulo L into [0, L): the offsets
-                        // of a regular ion lie in [-1, 2]
-                        unsigned int code = 0u;
-#pragma unroll
-                        for (int e = 0; e < 3; ++e) {
-                            int off = x[e] - c0[e] + 1;
-                            off += off < 0 ? L : (off >= L ? -L : 0);
-                            code |= (unsigned int)off << (2 * e);
-                        }
-                        const double val = amount * lin_w(o1, f1) * lin_w(o2, f2);
-                        words[nc >> 2] |= code << (8 * (nc & 3));
-                        o.val[kConPerAxis * d + nc] = (T)(-val);
-                        ++nc;
-                    }
+                    for (int o1 = 0; o1 < 2; ++o1)
+                        o.val[kConPerAxis * d + 4 * cell + 2 * o2 + o1] =
+                            (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
             }
         }
-        o.code[2 * d] = words[0];
-        o.code[2 * d + 1] = words[1];
     }
-    const int n0 = __shfl(nc, 0, 4), n1 = __shfl(nc, 1, 4), n2 = __shfl(nc, 2, 4);
-    if (lane == 3) head[s] = make_int4(c0[0], c0[1], c0[2], regular ? (n0 | (n1 << 4) | (n2 << 8)) : -1);
+    const unsigned g0 = __shfl(g, 0, 4), g1 = __shfl(g, 1, 4), g2 = __shfl(g, 2, 4);
+    if (lane == 3)
+        head[s] = make_int4(regular ? pack_cell(c0[0], c0[1], c0[2]) : -1, (int)g0, (int)g1, (int)g2);
 }
 
 hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma) {

@@ -55,24 +55,31 @@ __device__ __forceinline__ T eta_at(const LfArgs<T> &A, int d, int gz, size_t of
 // tile finds every regular ion touching its links in the bin rows
 // [y0 - 3, y0 + TY + 1] x [z0 - 3, z0 + TZ + 1].  Other ions are deposited
 // by the follow-up ion kernel with global atomics.
+//
 // Records of the ions in bin order, written each step by k_pack_ions, in two
-// arrays: a head per ion (start cell x, y, z and the contribution counts n_d
-// of the three axes in bits 4d..4d+3; -1 marks an ion left to the atomic
-// path) and the contributions of a regular ion's whole move: axis d of the
-// dimension-split move crosses at most 2 cells, 4 links each, stored in slots
-// 8d..8d+7 as a code byte (link-origin offset from the start cell plus one
-// in bits 0-1 (x), 2-3 (y), 4-5 (z); offsets lie in [-1, 2]) and the value to
-// add to D_d there.
+// arrays.  The head: the start cell packed as x | y << 10 | z << 20 (-1 for
+// an ion left to the atomic path), then one word per axis d of the
+// dimension-split move: the corner of the 2 x 2 x 2 box of links it touches
+// (the first cell along d, the perpendicular cells c_d1, c_d2 of the
+// position it moves from), packed the same way, bit 30 set when the move
+// crosses into a second cell along d, bit 31 set when there is a move.  The
+// values: slot 8d + 4 cell + 2 o2 + o1 holds what is added to D_d at cell
+// `cell` along d and c_d1 + o1, c_d2 + o2 (each wrapped).  Lattices up to
+// 1024 per side.
 constexpr int kConPerAxis = 8;
+constexpr unsigned kGroupTwo = 1u << 30, kGroupOn = 1u << 31;
 
+__device__ __forceinline__ int pack_cell(int x, int y, int z) { return x | (y << 10) | (z << 20); }
+
+// Values of a record: 96 bytes in FP32, 192 in FP64, read whole with 16-byte
+// loads.
 template <typename T>
 struct DepCon {
-    unsigned int code[3 * kConPerAxis / 4];
     T val[3 * kConPerAxis];
 };
 
 struct DepArgs {
-    const int4 *head;       // [n] start cell (x, y, z) and ncon, in bin order
+    const int4 *head;       // [n] packed start cell and the three axis words, in bin order
     const void *con;        // [n] DepCon<T>, in bin order
     const int *row_start;   // [L^2] first slot of each row
     const int *row_count;   // [L^2]
@@ -81,11 +88,19 @@ struct DepArgs {
 
 constexpr int kDepTZ = 4;  // planes per z-chunk when the deposit is fused
 
+// A regular ion moves less than a along every axis, so each axis of its
+// dimension-split move spans at most two cells (checked on the cell indices
+// too, so that rounding cannot make it three), and starts within one row
+// (in y and z) of the row it was binned in.
 __device__ __forceinline__ bool ion_regular(double a, int L, const double (&u)[3], const double (&du)[3],
                                             int binrow) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < 3; ++d) {
         if (!(fabs(du[d]) < a)) return false;
+        const double u1 = u[d] + du[d];
+        const double lo = u[d] < u1 ? u[d] : u1, hi = u[d] < u1 ? u1 : u[d];
+        if (floor(div_a(hi, a)) - floor(div_a(lo, a)) > 1.0) return false;
+    }
     int cy, cz;
     double f;
     fold(u[1], a, L, cy, f);
@@ -113,6 +128,11 @@ struct LfSmem {
     T sX[2][3][4 * R + 2][66];
     T sB[3][4 * R + 1][65];
 };
+
+// Capacity of the fused deposit's candidate list, which borrows the march's
+// LDS (the last word holds the count).
+template <typename T, int R>
+constexpr int kListCap = (int)(sizeof(LfSmem<T, R>) / sizeof(int)) - 1;
 
 // One workgroup (256 threads) advances the tile (tile_x, tile_y) over the z
 // planes of `chunk`.  Every load wraps periodically; stores are masked to the
@@ -181,6 +201,7 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         // [x0, x0+64), y in [y0, y0+TY), z in [z0, z1)), accumulated in LDS.
         T *accf = &DS->acc[0][0][0][0];
         for (int t = threadIdx.x; t < 3 * kDepTZ * TY * 64; t += blockDim.x) accf[t] = (T)0;
+        if (threadIdx.x == 0) reinterpret_cast<int *>(&S)[kListCap<T, R>] = 0;
         const int nry = TY + 5, nrz = (z1 - z0) + 5, nrows = nry * nrz;
         static_assert((4 * R + 5) * (kDepTZ + 5) <= 128, "candidate rows: two per lane of one wavefront");
         if (wy == 0) {
@@ -219,41 +240,111 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         __syncthreads();
         const int total = DS->rowpre[nrows];
         const DepCon<T> *con = (const DepCon<T> *)dep->con;
-        const int ylim = min(y0 + TY, L), zlim = z1;
-        for (int cidx = threadIdx.x; cidx < total; cidx += blockDim.x) {
-            int lo = 0, hi = nrows - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (DS->rowpre[mid] <= cidx) lo = mid;
-                else hi = mid - 1;
-            }
-            const int slot = DS->rowbase[lo] + cidx;
-            const int4 h = dep->head[slot];
-            if (h.w <= 0) continue;
-            // the links of a regular ion starting in cell c have origins in
-            // [c - 1, c + 2] per axis: skip ions that cannot touch this tile
-            // (periodic; no test along an axis the window covers)
-            const int ex = ((h.x - x0 + 2) % L + L) % L, ey = ((h.y - y0 + 2) % L + L) % L,
-                      ez = ((h.z - z0 + 2) % L + L) % L;
-            if ((L > TX + 4 && ex > TX + 2) || (L > TY + 4 && ey > TY + 2) || (L > (z1 - z0) + 4 && ez > (z1 - z0) + 2))
-                continue;
-            const DepCon<T> &cn = con[slot];
+        const int org[3] = {x0, y0, z0};
+        const int ext[3] = {TX, min(y0 + TY, L) - y0, z1 - z0};
+        int *list = reinterpret_cast<int *>(&S);
+        int *list_n = list + kListCap<T, R>;
+
+        // Adds the values of the record in `slot` that fall on this tile's
+        // links to the LDS accumulator.  Per axis group the two candidate
+        // coordinates along each axis are tested once; each of the (up to)
+        // eight links then needs only those flags.
+        auto deposit_one = [&](int slot, const int4 &h) {
+            constexpr int kWords = (int)sizeof(DepCon<T>) / 16;
+            static_assert(sizeof(DepCon<T>) % 16 == 0, "record of whole 16-byte words");
+            union {
+                uint4 raw[kWords];
+                DepCon<T> rec;
+            } cn;
+            const uint4 *src = reinterpret_cast<const uint4 *>(con + slot);
+#pragma unroll
+            for (int q = 0; q < kWords; ++q) cn.raw[q] = src[q];
+            const unsigned gw[3] = {(unsigned)h.y, (unsigned)h.z, (unsigned)h.w};
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const int nd = (h.w >> (4 * d)) & 15;
-                if (nd == 0) continue;
-                const unsigned int w0 = cn.code[2 * d], w1 = cn.code[2 * d + 1];
-                for (int k = 0; k < nd; ++k) {
-                    const unsigned int code = ((k < 4 ? w0 : w1) >> (8 * (k & 3))) & 255u;
-                    int xx = h.x + (int)(code & 3) - 1, yy = h.y + (int)((code >> 2) & 3) - 1,
-                        zz = h.z + (int)((code >> 4) & 3) - 1;
-                    xx += xx < 0 ? L : (xx >= L ? -L : 0);
-                    yy += yy < 0 ? L : (yy >= L ? -L : 0);
-                    zz += zz < 0 ? L : (zz >= L ? -L : 0);
-                    if (xx < x0 || xx >= x0 + TX || yy < y0 || yy >= ylim || zz < z0 || zz >= zlim) continue;
-                    atomicAdd(&DS->acc[d][zz - z0][yy - y0][xx - x0], cn.val[kConPerAxis * d + k]);
+                const unsigned g = gw[d];
+                if (!(g & kGroupOn)) continue;
+                const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+                int l0[3], l1[3];
+                bool i0[3], i1[3];
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const int v0 = (int)((g >> (10 * e)) & 1023u);
+                    const int v1 = v0 + 1 == L ? 0 : v0 + 1;
+                    l0[e] = v0 - org[e];
+                    l1[e] = v1 - org[e];
+                    i0[e] = (unsigned)l0[e] < (unsigned)ext[e];
+                    i1[e] = (unsigned)l1[e] < (unsigned)ext[e];
+                }
+                const int ncell = (g & kGroupTwo) ? 2 : 1;
+#pragma unroll
+                for (int cell = 0; cell < 2; ++cell) {
+                    if (cell >= ncell) break;
+#pragma unroll
+                    for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                        for (int o1 = 0; o1 < 2; ++o1) {
+                            int sel[3];
+                            sel[d] = cell;
+                            sel[d1] = o1;
+                            sel[d2] = o2;
+                            const bool in = (sel[0] ? i1[0] : i0[0]) && (sel[1] ? i1[1] : i0[1]) &&
+                                            (sel[2] ? i1[2] : i0[2]);
+                            if (!in) continue;
+                            const int lx0 = sel[0] ? l1[0] : l0[0], ly0 = sel[1] ? l1[1] : l0[1],
+                                      lz0 = sel[2] ? l1[2] : l0[2];
+                            atomicAdd(&DS->acc[d][lz0][ly0][lx0], cn.rec.val[kConPerAxis * d + 4 * cell + 2 * o2 + o1]);
+                        }
                 }
             }
+        };
+
+        // Pass 1: heads of the candidates (two per thread in flight), the
+        // ions whose link box can meet this tile go to the list (in the LDS
+        // of the march, unused until its prologue); past the list's capacity
+        // an ion is deposited at once.
+        for (int cbase = 0; cbase < total; cbase += 2 * (int)blockDim.x) {
+            int slot2[2];
+            int4 h2[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int cidx = cbase + j * (int)blockDim.x + (int)threadIdx.x;
+                slot2[j] = -1;
+                if (cidx < total) {
+                    int lo = 0, hi = nrows - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (DS->rowpre[mid] <= cidx) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    slot2[j] = DS->rowbase[lo] + cidx;
+                    h2[j] = dep->head[slot2[j]];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (slot2[j] < 0 || h2[j].x < 0) continue;
+                if (!((h2[j].y | h2[j].z | h2[j].w) & (int)kGroupOn)) continue;  // no move
+                // the links of a regular ion starting in cell c have origins
+                // in [c - 1, c + 2] per axis (periodic; no test along an axis
+                // the window covers)
+                const int cx = h2[j].x & 1023, cy = (h2[j].x >> 10) & 1023, cz = (h2[j].x >> 20) & 1023;
+                const int ex = ((cx - x0 + 2) % L + L) % L, ey = ((cy - y0 + 2) % L + L) % L,
+                          ez = ((cz - z0 + 2) % L + L) % L;
+                if ((L > TX + 4 && ex > TX + 2) || (L > TY + 4 && ey > TY + 2) ||
+                    (L > (z1 - z0) + 4 && ez > (z1 - z0) + 2))
+                    continue;
+                const int pos = atomicAdd(list_n, 1);
+                if (pos < kListCap<T, R>) list[pos] = slot2[j];
+                else deposit_one(slot2[j], h2[j]);
+            }
+        }
+        __syncthreads();
+        // Pass 2: the listed ions, head and values loaded together.
+        const int nlist = min(*list_n, kListCap<T, R>);
+        for (int i = threadIdx.x; i < nlist; i += blockDim.x) {
+            const int slot = list[i];
+            deposit_one(slot, dep->head[slot]);
         }
         __syncthreads();
     }
