@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 METRIC = "MEMD lattice-site updates/s + ion-steps/s; p50/p99 latency for batched replicas"
 HBM_PEAK_GBS = 8000.0
 CADENCE = 50
+PROFILE_EVERY = 10
 
 # Algorithmic bytes (each value read once / written once).
 #   leapfrog, per site: read D[3], B[3], eta[3] (per-link permittivity), write D[3], B[3];
@@ -111,7 +112,9 @@ def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None):
     if warmup:
         memd.memd_step(G.ctx, base, warmup)
     torch.cuda.synchronize()
-    memd.memd_profile_enable(G.ctx, ["leapfrog"])
+    # HIP events ride on one leapfrog launch in PROFILE_EVERY (each timed
+    # launch costs a few microseconds more than an untimed one)
+    memd.memd_profile_enable(G.ctx, ["leapfrog"], PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     memd.memd_step(G.ctx, base + 8 * per * warmup, steps)
@@ -198,8 +201,10 @@ def main():
     ion_steps = w.n * args.steps / r["wall"]
 
     lf_avg_s = r["lf_ms"] / 1e3 / max(r["lf_n"], 1)
-    # the fused kernel also reads each ion's 64-byte record once
-    lf_bytes = leapfrog_bytes_per_site(fp32, True) * sites + (64 * w.n if r["fused"] else 0)
+    # the fused kernel also reads each ion's record once: a 16-byte head and
+    # 24 values in the field type
+    rec_bytes = 16 + 24 * (4 if fp32 else 8)
+    lf_bytes = leapfrog_bytes_per_site(fp32, True) * sites + (rec_bytes * w.n if r["fused"] else 0)
     achieved = lf_bytes / lf_avg_s / 1e9
     traffic = load_traffic(args.precision)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -208,7 +213,7 @@ def main():
             "kernel": ("k_leapfrog_dep (Faraday + Ampere + tile-owned current deposit)" if r["fused"]
                        else "k_leapfrog (Faraday + Ampere)"),
             "algorithmic_bytes_per_launch": lf_bytes, "avg_launch_us": round(lf_avg_s * 1e6, 2),
-            "launches": r["lf_n"],
+            "launches": r["lf_n"], "timed_every": PROFILE_EVERY,
             "tile": {"x": 64, "y": 4 * r["tile"][0], "z_chunk": r["tile"][1],
                      "autotuned_us": r["tile"][2]}}
     if traffic:

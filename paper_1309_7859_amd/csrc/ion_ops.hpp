@@ -220,7 +220,7 @@ __device__ __forceinline__ double force_ion(int L, size_t Ns, double a, double V
     const double pref = qi * qi / (2.0 * eps_cell * a);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double Fself = -pref * dS[d] / a;
+        const double Fself = div_a(-pref * dS[d], a);
         F[d] = Flat[d] - Fself + qi * P[d] / (V * epsh[d]);
     }
     return pref * S;

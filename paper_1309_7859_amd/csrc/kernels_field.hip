@@ -3,6 +3,8 @@
 // reductions, permittivity maps, the salt-dependent permittivity.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "device_util.hpp"
 #include "leapfrog_tile.hpp"
 #include "memd_internal.hpp"
@@ -19,14 +21,14 @@ __global__ __launch_bounds__(256) void k_leapfrog(LfArgs<T> A) {
 }
 
 // The leapfrog with the deposit of the regular ions fused in (leapfrog_tile.hpp).
-template <typename T, int EM, int R>
+template <typename T, int EM, int R, int TZ>
 __global__ __launch_bounds__(256) void k_leapfrog_dep(LfArgs<T> A, DepArgs P) {
     __shared__ LfSmem<T, R> S;
-    __shared__ DepSmem<T, R> DS;
+    __shared__ DepSmem<T, R, TZ> DS;
     const int logical = xcd_logical(blockIdx.x, gridDim.x);
     const int tile_x = logical % A.ntx;
     const int rest = logical / A.ntx;
-    leapfrog_tile<T, EM, R, true>(A, tile_x, rest % A.nty, rest / A.nty, S, &P, &DS);
+    leapfrog_tile<T, EM, R, true, TZ>(A, tile_x, rest % A.nty, rest / A.nty, S, &P, &DS);
 }
 
 template <typename T, int EM>
@@ -52,12 +54,19 @@ static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, voi
     const int nz = (c->L + A.tz - 1) / A.tz;
     const int nblk = A.ntx * A.nty * nz;
     if (dep) {
+        if constexpr (std::is_same<T, float>::value) {
+            if (R == 1 && A.tz > kDepTZ) {
+                hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 1, kDepTZWide>), dim3(nblk), dim3(256), 0, c->stream,
+                                      e0, e1, 0, A, *dep);
+                return hipGetLastError();
+            }
+        }
         if (R == 1)
-            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 1>), dim3(nblk), dim3(256), 0, c->stream, e0, e1, 0, A,
-                                  *dep);
+            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 1, kDepTZ>), dim3(nblk), dim3(256), 0, c->stream, e0, e1,
+                                  0, A, *dep);
         else
-            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 2>), dim3(nblk), dim3(256), 0, c->stream, e0, e1, 0, A,
-                                  *dep);
+            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 2, kDepTZ>), dim3(nblk), dim3(256), 0, c->stream, e0, e1,
+                                  0, A, *dep);
         return hipGetLastError();
     }
     if (R == 1)
@@ -70,7 +79,8 @@ static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, voi
 }
 
 bool fused_deposit_ok(const memd_ctx *c) {
-    return c->fuse_deposit && c->n > 0 && c->L >= 16 && c->L <= 1024 && c->lf_tz <= kDepTZ &&
+    const int tz_max = c->fp32 && c->lf_rows == 1 ? kDepTZWide : kDepTZ;
+    return c->fuse_deposit && c->n > 0 && c->L >= 16 && c->L <= 1024 && c->lf_tz <= tz_max &&
            c->lf_rows <= (c->fp32 ? 2 : 1);
 }
 

@@ -87,21 +87,19 @@ hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_
 }
 
 // Records of the ions in bin order for the fused deposit (leapfrog_tile.hpp,
-// DepCon): ions are read in index order (coalesced), four lanes per ion, and
-// ion i's record goes to its slot slot_of[i].  Lane d < 3 takes axis d of the
-// dimension-split move from the position the earlier axes left (the
-// arithmetic of deposit_ion, bit for bit) and writes its box corner and the
-// values -q (ub - ua)/a w w / a^2 (in the field type); lane 3 writes the
-// head.  An irregular ion gets the head -1.
+// DepCon): ions are read in index order (coalesced), one lane per ion, and
+// ion i's record goes to its slot slot_of[i].  The axes of the
+// dimension-split move are taken in turn with the arithmetic of deposit_ion
+// (bit for bit); for each the box corner and the values -q (ub - ua)/a w w /
+// a^2 (in the field type) are stored.  An irregular ion gets the head -1.
 template <typename T>
 __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const double *__restrict__ q,
                                                    const double *__restrict__ r, const double *__restrict__ disp,
                                                    const int *__restrict__ slot_of, const int *__restrict__ binrow,
                                                    int4 *__restrict__ head, DepCon<T> *__restrict__ con,
                                                    uint64_t seed, uint32_t t, double sigma) {
-    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
-    const int lane = threadIdx.x & 3;
-    if (i >= n) return;  // whole groups of four leave together
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
     const int s = slot_of[i];
     double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
     double du[3];
@@ -110,9 +108,7 @@ __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const
         du[1] = disp[3 * i + 1];
         du[2] = disp[3 * i + 2];
     } else {
-        if (lane == 0) philox_displacement(seed, t, (uint32_t)i, sigma, du);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) du[d] = __shfl(du[d], 0, 4);
+        philox_displacement(seed, t, (uint32_t)i, sigma, du);
     }
     sanitize_move(du, a, L, nullptr);
     int c0[3];
@@ -121,19 +117,18 @@ __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const
 #pragma unroll
         for (int d = 0; d < 3; ++d) fold(u[d], a, L, c0[d], f);
     }
-    const bool regular = ion_regular(a, L, u, du, binrow[i]);
-    unsigned int g = 0u;
-    if (regular && lane < 3) {
-        const int d = lane;
-        const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-        // the position after the moves of the axes before d
+    if (!ion_regular(a, L, u, du, binrow[i])) {
+        head[s] = make_int4(-1, 0, 0, 0);
+        return;
+    }
+    const double qi = q[i], a2 = a * a;
+    DepCon<T> &o = con[s];
+    unsigned int g[3] = {0u, 0u, 0u};
 #pragma unroll
-        for (int e = 0; e < 3; ++e)
-            if (e < d) u[e] = u[e] + du[e];
+    for (int d = 0; d < 3; ++d) {
+        const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
         const double u0 = u[d], u1 = u0 + du[d];
         if (u1 != u0) {
-            DepCon<T> &o = con[s];
-            const double qi = q[i], a2 = a * a;
             int c1, c2;
             double f1, f2;
             fold(u[d1], a, L, c1, f1);
@@ -145,7 +140,7 @@ __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const
             corner[d] = mod_cell(klo, L);
             corner[d1] = c1;
             corner[d2] = c2;
-            g = (unsigned)pack_cell(corner[0], corner[1], corner[2]) | kGroupOn | (khi > klo ? kGroupTwo : 0u);
+            g[d] = (unsigned)pack_cell(corner[0], corner[1], corner[2]) | kGroupOn | (khi > klo ? kGroupTwo : 0u);
             // a regular move spans at most two cells along the axis
 #pragma unroll
             for (int cell = 0; cell < 2; ++cell) {
@@ -154,7 +149,8 @@ __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const
                 const double sa = lo > s0 ? lo : s0;
                 const double sb = hi < s1 ? hi : s1;
                 const double len = sb - sa;
-                const double amount = (cell == 0 || khi > klo) && len > 0.0 ? div_a(qi * sgn * div_a(len, a), a2) : 0.0;
+                const double amount =
+                    (cell == 0 || khi > klo) && len > 0.0 ? div_a(qi * sgn * div_a(len, a), a2) : 0.0;
 #pragma unroll
                 for (int o2 = 0; o2 < 2; ++o2)
 #pragma unroll
@@ -163,15 +159,14 @@ __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const
                             (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
             }
         }
+        u[d] = u1;
     }
-    const unsigned g0 = __shfl(g, 0, 4), g1 = __shfl(g, 1, 4), g2 = __shfl(g, 2, 4);
-    if (lane == 3)
-        head[s] = make_int4(regular ? pack_cell(c0[0], c0[1], c0[2]) : -1, (int)g0, (int)g1, (int)g2);
+    head[s] = make_int4(pack_cell(c0[0], c0[1], c0[2]), (int)g[0], (int)g[1], (int)g[2]);
 }
 
 hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma) {
     if (c->n == 0) return hipSuccess;
-    const int nb = (int)(((size_t)c->n * 4 + kThreads - 1) / kThreads);
+    const int nb = ion_blocks(c->n);
     if (c->fp32)
         hipLaunchKernelGGL(k_pack_ions<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L,
                            c->a, c->q, c->r, disp, c->slot, c->binrow, (int4 *)c->ionrec,
@@ -308,73 +303,55 @@ struct ForceArgs {
     int dip_nblk;
 };
 
-// Forces on every ion, four lanes per ion following `order`: lane d < 3
-// gathers E_d on the 4 d-links of the cell; the 12 eta of the cell (its
-// permittivity for the self-energy correction) are summed across the lanes.
-// Lattice part, self force and dipole correction as in force_ion.
+// Forces on every ion, one lane per ion following `order` (force_ion: the
+// lattice part from the 12 links of the cell, self force, dipole
+// correction).  With dip_partials set, wavefront 0 of every block sums the
+// deposit's per-block q r partials into P (in a fixed order; block 0 also
+// stores it) while the other lanes' loads are in flight.
 template <typename T>
 __global__ __launch_bounds__(256) void k_forces(ForceArgs<T> A) {
     __shared__ double Psh[3];
-    if (A.dip_partials) {
-        double s[3] = {0.0, 0.0, 0.0};
-        for (int b = threadIdx.x; b < A.dip_nblk; b += blockDim.x)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) s[d] += A.dip_partials[3 * b + d];
-        block_sum<3>(s);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                Psh[d] = s[d];
-                if (blockIdx.x == 0) A.scal[S_P + d] = s[d];
-            }
-        }
-    } else if (threadIdx.x < 3) {
-        Psh[threadIdx.x] = A.scal[S_P + threadIdx.x];
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 3;
-    const int slot = (xcd_logical(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 2;
-    double us = 0.0;
+    const int slot = xcd_logical(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const bool live = slot < A.n;
     const int i = live ? (A.order ? A.order[slot] : slot) : 0;
-    int c[3];
-    double f[3];
-    double s = 0.0, esum = 0.0;
-    const double qi = live ? A.q[i] : 0.0;
+    double u[3] = {0.0, 0.0, 0.0}, qi = 0.0;
     if (live) {
-        const int L = A.L;
+        u[0] = A.r[3 * i];
+        u[1] = A.r[3 * i + 1];
+        u[2] = A.r[3 * i + 2];
+        qi = A.q[i];
+    }
+    // lattice part and self force first (their gathers overlap the dipole
+    // sum); the dipole term is added once P is known: x + 0 + y rounds as x + y
+    double us = 0.0, F[3] = {0.0, 0.0, 0.0};
+    if (live) {
+        const EtaView<T> ev{A.mode, A.eta_uni, A.eta_prof, A.eta_link};
+        const double zero[3] = {0.0, 0.0, 0.0};
+        us = force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.D, ev, A.scal + S_G, zero, A.scal + S_EPSH, F);
+    }
+    if (threadIdx.x < 64) {
+        if (A.dip_partials) {
+            double s[3] = {0.0, 0.0, 0.0};
+            for (int b = threadIdx.x; b < A.dip_nblk; b += 64)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) fold(A.r[3 * i + d], A.a, L, c[d], f[d]);
-        if (lane < 3) {
-            const int d = lane, d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-            EtaView<T> ev{A.mode, A.eta_uni, A.eta_prof, A.eta_link};
+                for (int d = 0; d < 3; ++d) s[d] += A.dip_partials[3 * b + d];
 #pragma unroll
-            for (int o2 = 0; o2 < 2; ++o2)
+            for (int d = 0; d < 3; ++d) s[d] = wave_sum(s[d]);
+            if (threadIdx.x == 0) {
 #pragma unroll
-                for (int o1 = 0; o1 < 2; ++o1) {
-                    int x[3] = {c[0], c[1], c[2]};
-                    x[d1] = o1 ? (c[d1] + 1 == L ? 0 : c[d1] + 1) : c[d1];
-                    x[d2] = o2 ? (c[d2] + 1 == L ? 0 : c[d2] + 1) : c[d2];
-                    const size_t off = site_index(x[0], x[1], x[2], L);
-                    const double e = ev.at(d, x[2], off, L, A.Ns);
-                    esum += e;
-                    s += lin_w(o1, f[d1]) * lin_w(o2, f[d2]) * (e * (double)A.D[(size_t)d * A.Ns + off]);
+                for (int d = 0; d < 3; ++d) {
+                    Psh[d] = s[d];
+                    if (blockIdx.x == 0) A.scal[S_P + d] = s[d];
                 }
+            }
+        } else if (threadIdx.x < 3) {
+            Psh[threadIdx.x] = A.scal[S_P + threadIdx.x];
         }
     }
-    esum += __shfl_xor(esum, 1, 4);
-    esum += __shfl_xor(esum, 2, 4);
+    __syncthreads();
     if (live) {
-        const double eps_cell = 12.0 / esum;
-        double S, dS[3];
-        self_sum(A.scal + S_G, f, S, dS);
-        const double pref = qi * qi / (2.0 * eps_cell * A.a);
-        if (lane < 3) {
-            const int d = lane;
-            const double Fself = -pref * dS[d] / A.a;
-            A.F[3 * i + d] = qi * s - Fself + qi * Psh[d] / (A.V * A.scal[S_EPSH + d]);
-        }
-        if (lane == 0) us = pref * S;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) A.F[3 * i + d] = F[d] + qi * Psh[d] / (A.V * A.scal[S_EPSH + d]);
     }
     if (A.uself_partials) {
         double v[1] = {us};
@@ -409,7 +386,7 @@ static ForceArgs<T> force_args(memd_ctx *c, const void *D) {
 
 hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk) {
     if (c->n == 0) return hipSuccess;
-    const int nb = ion_blocks_x8(c->n, 4);
+    const int nb = ion_blocks_x8(c->n, 1);
     if (c->fp32) {
         auto A = force_args<float>(c, D);
         A.dip_partials = dip_partials;
@@ -534,7 +511,7 @@ hipError_t launch_bin_ions(memd_ctx *c) {
 
 // Self energies (through the force kernel, writing the same forces again).
 hipError_t launch_uself(memd_ctx *c, double *partials, int *nblk) {
-    const int nb = ion_blocks_x8(c->n, 4);
+    const int nb = ion_blocks_x8(c->n, 1);
     *nblk = nb;
     const void *D = c->D[c->cur];
     if (c->fp32) {

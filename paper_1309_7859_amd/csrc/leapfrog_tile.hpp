@@ -86,7 +86,10 @@ struct DepArgs {
     double a;
 };
 
-constexpr int kDepTZ = 4;  // planes per z-chunk when the deposit is fused
+// Planes per z-chunk when the deposit is fused: up to 4, or up to 8 for the
+// FP32 tile of 64 x 4 sites (the accumulator is 3 x TZ x TY x 64 values).
+constexpr int kDepTZ = 4;
+constexpr int kDepTZWide = 8;
 
 // A regular ion moves less than a along every axis, so each axis of its
 // dimension-split move spans at most two cells (checked on the cell indices
@@ -114,11 +117,11 @@ __device__ __forceinline__ bool ion_regular(double a, int L, const double (&u)[3
 }
 
 
-template <typename T, int R>
+template <typename T, int R, int TZ = kDepTZ>
 struct DepSmem {
-    T acc[3][kDepTZ][4 * R][64];
-    int rowpre[(4 * R + 5) * (kDepTZ + 5) + 1];
-    int rowbase[(4 * R + 5) * (kDepTZ + 5)];  // first slot of each candidate row minus rowpre
+    T acc[3][TZ][4 * R][64];
+    int rowpre[(4 * R + 5) * (TZ + 5) + 1];
+    int rowbase[(4 * R + 5) * (TZ + 5)];  // first slot of each candidate row minus rowpre
 };
 
 // LDS of one tile: eta*D of two planes with a one-site halo, new B of one
@@ -137,10 +140,10 @@ constexpr int kListCap = (int)(sizeof(LfSmem<T, R>) / sizeof(int)) - 1;
 // One workgroup (256 threads) advances the tile (tile_x, tile_y) over the z
 // planes of `chunk`.  Every load wraps periodically; stores are masked to the
 // lattice, so any L >= 2 works with any tile shape.
-template <typename T, int EM, int R, bool DEP = false>
+template <typename T, int EM, int R, bool DEP = false, int DTZ = kDepTZ>
 __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, int tile_y, int chunk,
                                               LfSmem<T, R> &S, const DepArgs *dep = nullptr,
-                                              DepSmem<T, R> *DS = nullptr) {
+                                              DepSmem<T, R, DTZ> *DS = nullptr) {
     constexpr int TX = 64, TY = 4 * R;
     auto &sX = S.sX;
     auto &sB = S.sB;
@@ -200,10 +203,10 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         // Deposit of the regular ions on the links this tile owns (x in
         // [x0, x0+64), y in [y0, y0+TY), z in [z0, z1)), accumulated in LDS.
         T *accf = &DS->acc[0][0][0][0];
-        for (int t = threadIdx.x; t < 3 * kDepTZ * TY * 64; t += blockDim.x) accf[t] = (T)0;
+        for (int t = threadIdx.x; t < 3 * DTZ * TY * 64; t += blockDim.x) accf[t] = (T)0;
         if (threadIdx.x == 0) reinterpret_cast<int *>(&S)[kListCap<T, R>] = 0;
         const int nry = TY + 5, nrz = (z1 - z0) + 5, nrows = nry * nrz;
-        static_assert((4 * R + 5) * (kDepTZ + 5) <= 128, "candidate rows: two per lane of one wavefront");
+        static_assert((4 * R + 5) * (DTZ + 5) <= 128, "candidate rows: two per lane of one wavefront");
         if (wy == 0) {
             // wavefront 0: counts and starts of the candidate rows, two rows
             // per lane, prefix sums with cross-lane shifts

@@ -330,11 +330,14 @@ def _mixed_moves(rng, steps, n, big_frac=0.05):
     return d
 
 
-@pytest.mark.parametrize("prec", [memd.FP64, memd.FP32_MIXED])
-def test_fused_deposit_matches_atomic_path_and_oracle(prec):
+@pytest.mark.parametrize("prec,tile,L", [(memd.FP64, None, 32), (memd.FP32_MIXED, None, 32),
+                                         (memd.FP32_MIXED, (1, 8), 44), (memd.FP32_MIXED, (2, 4), 44),
+                                         (memd.FP64, (1, 2), 44)])
+def test_fused_deposit_matches_atomic_path_and_oracle(prec, tile, L):
     """The deposit fused into the leapfrog (tile-owned links) and the global
-    atomic deposit give the oracle's result, with jumps of up to 2.5 a mixed in."""
-    L, n = 32, 600
+    atomic deposit give the oracle's result, with jumps of up to 2.5 a mixed
+    in, for several fused tile shapes (ragged tiles and z-chunks at L = 44)."""
+    n = 600
     rng = np.random.default_rng(21)
     r = rng.uniform(0, L, size=(n, 3))
     q = np.tile([1.0, -1.0, 2.0, -2.0], n // 4)
@@ -348,6 +351,8 @@ def test_fused_deposit_matches_atomic_path_and_oracle(prec):
     S.initial_solve(1e-13)
     share_state(S, G)
     H.set_state(*S.state())
+    if tile:
+        memd.memd_set_tiling(G.ctx, *tile)
     assert memd.memd_counters(G.ctx)[1] == 1 and memd.memd_counters(H.ctx)[1] == 0
     disp = _mixed_moves(rng, 12, n)
     ftol, gtol = (1e-10, 1e-12) if prec == memd.FP64 else (1e-4, 1e-5 * 2)
