@@ -78,25 +78,37 @@ static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, voi
     return hipGetLastError();
 }
 
+int bucket_tiles(const memd_ctx *c) {
+    const int TY = 4 * c->lf_rows;
+    return ((c->L + 63) / 64) * ((c->L + TY - 1) / TY) * ((c->L + c->lf_tz - 1) / c->lf_tz);
+}
+
+int bucket_cap(const memd_ctx *c) {
+    const int nt = bucket_tiles(c);
+    const size_t cap = c->bk_entries / (size_t)(nt > 0 ? nt : 1);
+    return cap > (size_t)INT32_MAX ? INT32_MAX : (int)cap;
+}
+
 bool fused_deposit_ok(const memd_ctx *c) {
     const int tz_max = c->fp32 && c->lf_rows == 1 ? kDepTZWide : kDepTZ;
-    return c->fuse_deposit && c->n > 0 && c->L >= 16 && c->L <= 1024 && c->lf_tz <= tz_max &&
-           c->lf_rows <= (c->fp32 ? 2 : 1);
+    return c->fuse_deposit && c->n > 0 && c->bk_head && c->L >= 16 && c->L <= 1024 && c->lf_tz <= tz_max &&
+           c->lf_rows <= (c->fp32 ? 2 : 1) && bucket_tiles(c) <= c->bk_tiles_max && bucket_cap(c) >= 16;
 }
 
 hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout, hipEvent_t e0,
                            hipEvent_t e1, const double *disp, uint64_t seed, uint32_t t, double sigma,
-                           bool with_deposit) {
+                           bool with_deposit, bool need_pack) {
     DepArgs P;
     const DepArgs *dp = nullptr;
     if (with_deposit) {
-        hipError_t e = launch_pack_ions(c, disp, seed, t, sigma);
-        if (e != hipSuccess) return e;
-        P.head = (const int4 *)c->ionrec;
-        P.con = (const int4 *)c->ionrec + c->n;
-        P.row_count = c->bins;
-        P.row_start = c->bins + (size_t)c->L * c->L;
-        P.a = c->a;
+        if (need_pack) {
+            hipError_t e = launch_pack_ions(c, disp, seed, t, sigma);
+            if (e != hipSuccess) return e;
+        }
+        P.head = c->bk_head;
+        P.con = c->bk_con;
+        P.count = c->bk_count;
+        P.cap = bucket_cap(c);
         dp = &P;
     }
     if (c->fp32) {

@@ -1,6 +1,8 @@
 // kernels_ions.hip -- per-ion kernels for gfx950: current deposition, charge
 // assignment, dipole moment, corrected forces; deterministic finalisers of
 // the per-block partial sums; the lattice Green's function table.
+#include <utility>
+
 #include "device_util.hpp"
 #include "ion_ops.hpp"
 #include "leapfrog_tile.hpp"
@@ -22,7 +24,7 @@ __global__ __launch_bounds__(256) void k_deposit(int n, int L, size_t Ns, double
                                                  const double *__restrict__ q, double *__restrict__ r,
                                                  const double *__restrict__ disp, T *__restrict__ D,
                                                  int spread_rho, double *__restrict__ rho,
-                                                 const int *__restrict__ order,
+                                                 const int *__restrict__ order, const int *__restrict__ perm,
                                                  double *__restrict__ partials, unsigned int *bad,
                                                  uint64_t seed, uint32_t t, double sigma) {
     const int lane = threadIdx.x & 15;
@@ -31,15 +33,16 @@ __global__ __launch_bounds__(256) void k_deposit(int n, int L, size_t Ns, double
     double P[3] = {0.0, 0.0, 0.0};
     if (slot < n) {
         const int i = order ? order[slot] : slot;
+        const int ci = perm ? perm[i] : i;  // the caller's index of the ion
         const double qi = q[i];
         double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
         double du[3];
         if (disp) {
-            du[0] = disp[3 * i];
-            du[1] = disp[3 * i + 1];
-            du[2] = disp[3 * i + 2];
+            du[0] = disp[3 * ci];
+            du[1] = disp[3 * ci + 1];
+            du[2] = disp[3 * ci + 2];
         } else {
-            if (lane == 0) philox_displacement(seed, t, (uint32_t)i, sigma, du);
+            if (lane == 0) philox_displacement(seed, t, (uint32_t)ci, sigma, du);
 #pragma unroll
             for (int d = 0; d < 3; ++d) du[d] = __shfl(du[d], 0, 16);
         }
@@ -77,166 +80,431 @@ hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_
     *nblk = nb;
     if (c->fp32)
         hipLaunchKernelGGL(k_deposit<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
-                           c->q, c->r, disp, (float *)D, spread_rho ? 1 : 0, c->rho, c->order, partials,
+                           c->q, c->r, disp, (float *)D, spread_rho ? 1 : 0, c->rho, c->order, c->perm, partials,
                            c->bad_moves, seed, t, sigma);
     else
         hipLaunchKernelGGL(k_deposit<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
-                           c->q, c->r, disp, (double *)D, spread_rho ? 1 : 0, c->rho, c->order, partials,
+                           c->q, c->r, disp, (double *)D, spread_rho ? 1 : 0, c->rho, c->order, c->perm, partials,
                            c->bad_moves, seed, t, sigma);
     return hipGetLastError();
 }
 
-// Records of the ions in bin order for the fused deposit (leapfrog_tile.hpp,
-// DepCon): ions are read in index order (coalesced), one lane per ion, and
-// ion i's record goes to its slot slot_of[i].  The axes of the
-// dimension-split move are taken in turn with the arithmetic of deposit_ion
-// (bit for bit); for each the box corner and the values -q (ub - ua)/a w w /
-// a^2 (in the field type) are stored.  An irregular ion gets the head -1.
+__global__ void k_fill_int(int *dst, int v, size_t count);
+
+// Where the records of the fused deposit go: the tile buckets of the next
+// leapfrog launch (leapfrog_tile.hpp, DepArgs) and its tile shape.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const double *__restrict__ q,
-                                                   const double *__restrict__ r, const double *__restrict__ disp,
-                                                   const int *__restrict__ slot_of, const int *__restrict__ binrow,
-                                                   int4 *__restrict__ head, DepCon<T> *__restrict__ con,
-                                                   uint64_t seed, uint32_t t, double sigma) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int s = slot_of[i];
-    double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
-    double du[3];
-    if (disp) {
-        du[0] = disp[3 * i];
-        du[1] = disp[3 * i + 1];
-        du[2] = disp[3 * i + 2];
-    } else {
-        philox_displacement(seed, t, (uint32_t)i, sigma, du);
-    }
-    sanitize_move(du, a, L, nullptr);
+struct Buckets {
+    int4 *head;
+    DepCon<T> *con;
+    int *count;
+    int cap;
+    int TY, TZ, ntx, nty, nz;
+};
+
+// The record of one ion for the fused deposit (du already sanitised): the
+// axes of the dimension-split move are taken in turn with the arithmetic of
+// deposit_ion (bit for bit), giving per axis the link-box corner and the
+// values -q (ub - ua)/a w w / a^2 (in the field type), and the tiles that
+// own a link of the ion's boxes (at most two along each axis).  Returns the
+// number of those tiles, or -1 when the ion is left to the atomic path
+// (irregular, or more than two tiles along an axis); 0 when it does not move.
+template <typename T>
+__device__ __forceinline__ int make_record(int L, double a, double qi, const double (&u_in)[3],
+                                           const double (&du)[3], const Buckets<T> &B, int4 &h,
+                                           T (&val)[3 * kConPerAxis], int (&ids)[8]) {
+    if (!ion_regular(a, u_in, du)) return -1;
+    double u[3] = {u_in[0], u_in[1], u_in[2]};
     int c0[3];
     {
         double f;
 #pragma unroll
         for (int d = 0; d < 3; ++d) fold(u[d], a, L, c0[d], f);
     }
-    if (!ion_regular(a, L, u, du, binrow[i])) {
-        head[s] = make_int4(-1, 0, 0, 0);
-        return;
-    }
-    const double qi = q[i], a2 = a * a;
-    DepCon<T> &o = con[s];
+    const double a2 = a * a;
     unsigned int g[3] = {0u, 0u, 0u};
+    int lo[3] = {3, 3, 3}, hi[3] = {-2, -2, -2};  // link-origin offsets from c0 touched, per axis
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
         const double u0 = u[d], u1 = u0 + du[d];
+#pragma unroll
+        for (int k = 0; k < kConPerAxis; ++k) val[kConPerAxis * d + k] = (T)0;
         if (u1 != u0) {
             int c1, c2;
             double f1, f2;
             fold(u[d1], a, L, c1, f1);
             fold(u[d2], a, L, c2, f2);
-            const double lo = u0 < u1 ? u0 : u1, hi = u0 < u1 ? u1 : u0;
+            const double lo_u = u0 < u1 ? u0 : u1, hi_u = u0 < u1 ? u1 : u0;
             const double sgn = u1 > u0 ? 1.0 : -1.0;
-            const double klo = floor(div_a(lo, a)), khi = floor(div_a(hi, a));
+            const double klo = floor(div_a(lo_u, a)), khi = floor(div_a(hi_u, a));
             int corner[3];
             corner[d] = mod_cell(klo, L);
             corner[d1] = c1;
             corner[d2] = c2;
-            g[d] = (unsigned)pack_cell(corner[0], corner[1], corner[2]) | kGroupOn | (khi > klo ? kGroupTwo : 0u);
+            const bool two = khi > klo;
+            g[d] = (unsigned)pack_cell(corner[0], corner[1], corner[2]) | kGroupOn | (two ? kGroupTwo : 0u);
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                // offset in [-1, 2] of the corner from the start cell
+                int off = corner[e] - c0[e] + 1;
+                off += off < 0 ? L : (off >= L ? -L : 0);
+                off -= 1;
+                const int top = off + (e == d ? (two ? 1 : 0) : 1);
+                lo[e] = off < lo[e] ? off : lo[e];
+                hi[e] = top > hi[e] ? top : hi[e];
+            }
             // a regular move spans at most two cells along the axis
 #pragma unroll
             for (int cell = 0; cell < 2; ++cell) {
                 const double kc = cell ? khi : klo;
                 const double s0 = kc * a, s1 = (kc + 1.0) * a;
-                const double sa = lo > s0 ? lo : s0;
-                const double sb = hi < s1 ? hi : s1;
+                const double sa = lo_u > s0 ? lo_u : s0;
+                const double sb = hi_u < s1 ? hi_u : s1;
                 const double len = sb - sa;
                 const double amount =
-                    (cell == 0 || khi > klo) && len > 0.0 ? div_a(qi * sgn * div_a(len, a), a2) : 0.0;
+                    (cell == 0 || two) && len > 0.0 ? div_a(qi * sgn * div_a(len, a), a2) : 0.0;
 #pragma unroll
                 for (int o2 = 0; o2 < 2; ++o2)
 #pragma unroll
                     for (int o1 = 0; o1 < 2; ++o1)
-                        o.val[kConPerAxis * d + 4 * cell + 2 * o2 + o1] =
-                            (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
+                        val[kConPerAxis * d + 4 * cell + 2 * o2 + o1] = (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
             }
         }
         u[d] = u1;
     }
-    head[s] = make_int4(pack_cell(c0[0], c0[1], c0[2]), (int)g[0], (int)g[1], (int)g[2]);
+    if (!((g[0] | g[1] | g[2]) & kGroupOn)) return 0;  // no move, nothing to deposit
+    h = make_int4(pack_cell(c0[0], c0[1], c0[2]), (int)g[0], (int)g[1], (int)g[2]);
+    const int ext[3] = {64, B.TY, B.TZ};
+    int tid[3][2], nt[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        nt[e] = 0;
+        for (int off = lo[e]; off <= hi[e]; ++off) {
+            int cell = c0[e] + off;
+            cell += cell < 0 ? L : (cell >= L ? -L : 0);
+            const int tt = cell / ext[e];
+            bool seen = false;
+            for (int k = 0; k < nt[e]; ++k) seen = seen || tid[e][k] == tt;
+            if (seen) continue;
+            if (nt[e] == 2) return -1;
+            tid[e][nt[e]++] = tt;
+        }
+    }
+    const int nres = nt[0] * nt[1] * nt[2];
+    for (int k = 0; k < nres; ++k) {
+        const int kx = k % nt[0], ky = (k / nt[0]) % nt[1], kz = k / (nt[0] * nt[1]);
+        ids[k] = tid[0][kx] + B.ntx * (tid[1][ky] + B.nty * tid[2][kz]);
+    }
+    return nres;
+}
+
+// Bucket positions for the records of a wavefront, all lanes converged
+// (lanes without a record pass nres <= 0): per reservation round the lanes
+// that share a tile are counted with ballots and one lane of each group
+// adds the group's size to the tile's count, so a wavefront issues one
+// atomic per distinct tile and round (sorted ions share tiles; adding per
+// lane made the same counters the bottleneck).  Then the record goes to every
+// reserved entry, or, when a bucket was full, the reserved entries are
+// blanked and the ion is left to the atomic path.  Returns whether the
+// lane's ion goes to the atomic path.
+template <typename T>
+__device__ __forceinline__ bool place_record(int nres, const int4 &h, const T (&val)[3 * kConPerAxis],
+                                             const int (&ids)[8], const Buckets<T> &B) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int pos[8];
+    bool ok = true;
+    for (int k = 0; k < 8; ++k) {
+        const int my = k < nres ? ids[k] : -1;
+        unsigned long long rem = __ballot(my >= 0);
+        if (rem == 0ull) break;  // the same for every lane
+        int lead = lane, rank = 0, take = 0;
+        while (rem) {
+            const int l = __ffsll((long long)rem) - 1;
+            const int idl = __shfl(my, l, 64);
+            const unsigned long long same = __ballot(my == idl);
+            if (my == idl) {
+                lead = l;
+                rank = __popcll(same & below);
+            }
+            if (lane == l) take = __popcll(same);
+            rem &= ~same;
+        }
+        int base = 0;
+        if (take > 0) base = atomicAdd(&B.count[(size_t)my * kCountStride], take);
+        base = __shfl(base, lead, 64);
+        if (my >= 0) {
+            pos[k] = base + rank;
+            ok = ok && pos[k] < B.cap;
+        }
+    }
+    if (nres <= 0) return nres < 0;
+    for (int k = 0; k < nres; ++k) {
+        if (pos[k] >= B.cap) continue;
+        const size_t at = (size_t)ids[k] * B.cap + pos[k];
+        if (!ok) {
+            B.head[at] = make_int4(-1, 0, 0, 0);
+            continue;
+        }
+        B.head[at] = h;
+        DepCon<T> &o = B.con[at];
+#pragma unroll
+        for (int q = 0; q < 3 * kConPerAxis; ++q) o.val[q] = val[q];
+    }
+    return !ok;
+}
+
+// Records for the step about to run, ions read in storage order
+// (coalesced), one lane per ion; the bucket counts were zeroed before.
+// dep_atomic[slot_of[i]] marks an ion left to the atomic path.
+// Displacements are indexed by the caller's index perm[i].
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const double *__restrict__ q,
+                                                   const double *__restrict__ r, const double *__restrict__ disp,
+                                                   const int *__restrict__ slot_of, const int *__restrict__ perm,
+                                                   int *__restrict__ dep_atomic, Buckets<T> B, uint64_t seed,
+                                                   uint32_t t, double sigma) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int4 h = make_int4(-1, 0, 0, 0);
+    T val[3 * kConPerAxis];
+    int ids[8];
+    int nres = 0;
+    if (i < n) {
+        const int ci = perm ? perm[i] : i;
+        const double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
+        double du[3];
+        if (disp) {
+            du[0] = disp[3 * ci];
+            du[1] = disp[3 * ci + 1];
+            du[2] = disp[3 * ci + 2];
+        } else {
+            philox_displacement(seed, t, (uint32_t)ci, sigma, du);
+        }
+        sanitize_move(du, a, L, nullptr);
+        nres = make_record<T>(L, a, q[i], u, du, B, h, val, ids);
+    }
+    const bool atomic_path = place_record<T>(nres, h, val, ids, B);  // every lane of the wavefront takes part
+    if (i < n) dep_atomic[slot_of[i]] = atomic_path ? 1 : 0;
+}
+
+template <typename T>
+static Buckets<T> buckets(memd_ctx *c) {
+    Buckets<T> B;
+    B.head = c->bk_head;
+    B.con = (DepCon<T> *)c->bk_con;
+    B.count = c->bk_count;
+    B.TY = 4 * c->lf_rows;
+    B.TZ = c->lf_tz;
+    B.ntx = (c->L + 63) / 64;
+    B.nty = (c->L + B.TY - 1) / B.TY;
+    B.nz = (c->L + B.TZ - 1) / B.TZ;
+    B.cap = bucket_cap(c);
+    return B;
 }
 
 hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma) {
     if (c->n == 0) return hipSuccess;
+    const size_t nc = (size_t)bucket_tiles(c) * kCountStride;
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((nc + kThreads - 1) / kThreads)), dim3(kThreads), 0, c->stream,
+                       c->bk_count, 0, nc);
     const int nb = ion_blocks(c->n);
     if (c->fp32)
-        hipLaunchKernelGGL(k_pack_ions<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L,
-                           c->a, c->q, c->r, disp, c->slot, c->binrow, (int4 *)c->ionrec,
-                           (DepCon<float> *)((int4 *)c->ionrec + c->n), seed, t, sigma);
+        hipLaunchKernelGGL(k_pack_ions<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->q,
+                           c->r, disp, c->slot, c->perm, c->dep_atomic, buckets<float>(c), seed, t, sigma);
     else
-        hipLaunchKernelGGL(k_pack_ions<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L,
-                           c->a, c->q, c->r, disp, c->slot, c->binrow, (int4 *)c->ionrec,
-                           (DepCon<double> *)((int4 *)c->ionrec + c->n), seed, t, sigma);
+        hipLaunchKernelGGL(k_pack_ions<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->q,
+                           c->r, disp, c->slot, c->perm, c->dep_atomic, buckets<double>(c), seed, t, sigma);
     return hipGetLastError();
 }
 
-// Ion update after the leapfrog with the fused deposit: ions in index order
-// (so the dipole's block sums are in a fixed order), the regularity test of
-// the fused deposit repeated on the same bits; irregular ions deposit their
-// whole move here with global atomics, every ion is moved, and block sums of
-// q r^{n+1} go to partials (plus rho for the audit when spread_rho is set).
+// The ion side of one step after the leapfrog with the fused deposit, in bin
+// order (neighbouring lanes gather neighbouring links).  A block takes 128
+// ions; its wavefronts 0-1 and 2-3 run two independent chains on them:
+//   - wavefronts 0-1: the forces of the state the step started from
+//     (force_ion on D^n, which the leapfrog left intact; P^n from the
+//     previous step's dipole partials, summed by wavefront 0), when
+//     dip_prev is set;
+//   - wavefronts 2-3: irregular ions deposit their whole move into D^{n+1}
+//     with global atomics; every ion moves to r^{n+1} (written to r_out, so
+//     the force lanes still read r^n); per-block sums of q r^{n+1}
+//     (dip_out; rho for the audit when asked); the deposit records of the
+//     next step (from r^{n+1} and its displacement), when head is set.
+constexpr int kIonStepIons = 128;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_ion_update(int n, int L, size_t Ns, double a,
-                                                    const double *__restrict__ q, double *__restrict__ r,
-                                                    const double *__restrict__ disp, T *__restrict__ D,
-                                                    const int *__restrict__ binrow, int spread_rho,
-                                                    double *__restrict__ rho, double *__restrict__ partials,
-                                                    unsigned int *bad, uint64_t seed, uint32_t t, double sigma) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double P[3] = {0.0, 0.0, 0.0};
-    if (i < n) {
-        double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
-        double du[3];
-        if (disp) {
-            du[0] = disp[3 * i];
-            du[1] = disp[3 * i + 1];
-            du[2] = disp[3 * i + 2];
-        } else {
-            philox_displacement(seed, t, (uint32_t)i, sigma, du);
+struct IonStepArgs {
+    int n, L;
+    size_t Ns;
+    double a, V;
+    const double *q;
+    const double *r;
+    double *r_out;
+    const int *order;
+    const int *perm;                 // storage index -> caller index (displacements), null: identity
+    const double *disp, *disp_next;  // null: Philox displacements of steps t and t + 1
+    uint64_t seed;
+    uint32_t t;
+    double sigma;
+    const T *Dcur;
+    T *Dnext;
+    int eta_mode;
+    double eta_uni;
+    const T *eta_prof, *eta_link;
+    double *scal, *F;
+    const double *dip_prev;  // null: no forces in this launch
+    int dip_prev_nblk;
+    double *dip_out;
+    int *dep_atomic;  // [n] by slot: this step's ion left to the atomic path (read), the next step's (written)
+    int pack;         // write the next step's records
+    Buckets<T> bk;
+    double *rho;  // null: no charge spreading
+    unsigned int *bad;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
+    __shared__ double Psh[3];
+    const bool mover = threadIdx.x >= kIonStepIons;
+    const int s = xcd_logical(blockIdx.x, gridDim.x) * kIonStepIons + (threadIdx.x & (kIonStepIons - 1));
+    const bool live = s < A.n;
+    const int i = live ? A.order[s] : 0;
+    const bool forces = A.dip_prev != nullptr;
+    double F[3] = {0.0, 0.0, 0.0}, P[3] = {0.0, 0.0, 0.0}, qi = 0.0;
+    int4 h = make_int4(-1, 0, 0, 0);
+    T val[3 * kConPerAxis];
+    int ids[8];
+    int nres = 0;
+    if (!mover) {
+        // lattice part and self force of r^n on D^n; the dipole term is added
+        // at the end (x + 0 + y rounds as x + y)
+        if (live && forces) {
+            const double u[3] = {A.r[3 * i], A.r[3 * i + 1], A.r[3 * i + 2]};
+            qi = A.q[i];
+            const EtaView<T> ev{A.eta_mode, A.eta_uni, A.eta_prof, A.eta_link};
+            const double zero[3] = {0.0, 0.0, 0.0};
+            force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.Dcur, ev, A.scal + S_G, zero, A.scal + S_EPSH, F);
         }
-        sanitize_move(du, a, L, bad);
-        const double qi = q[i];
-        if (ion_regular(a, L, u, du, binrow[i])) {
+        if (forces && threadIdx.x < 64) {
+            double ps[3] = {0.0, 0.0, 0.0};
+            for (int b = threadIdx.x; b < A.dip_prev_nblk; b += 64)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) ps[d] += A.dip_prev[3 * b + d];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ps[d] = wave_sum(ps[d]);
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    Psh[d] = ps[d];
+                    if (blockIdx.x == 0) A.scal[S_P + d] = ps[d];
+                }
+            }
+        }
+    } else if (live) {
+        const int ci = A.perm ? A.perm[i] : i;
+        double u[3] = {A.r[3 * i], A.r[3 * i + 1], A.r[3 * i + 2]};
+        qi = A.q[i];
+        double du[3], dn[3] = {0.0, 0.0, 0.0};
+        if (A.disp) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) du[d] = A.disp[3 * ci + d];
+        } else {
+            philox_displacement(A.seed, A.t, (uint32_t)ci, A.sigma, du);
+        }
+        if (A.pack) {
+            if (A.disp_next) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) dn[d] = A.disp_next[3 * ci + d];
+            } else {
+                philox_displacement(A.seed, A.t + 1u, (uint32_t)ci, A.sigma, dn);
+            }
+        }
+        sanitize_move(du, A.a, A.L, A.bad);
+        if (!A.dep_atomic[s]) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) u[d] = u[d] + du[d];
         } else {
-            deposit_ion<T>(L, Ns, a, qi, u, du, D);
+            deposit_ion<T>(A.L, A.Ns, A.a, qi, u, du, A.Dnext);
         }
-        r[3 * i] = u[0];
-        r[3 * i + 1] = u[1];
-        r[3 * i + 2] = u[2];
+        A.r_out[3 * i] = u[0];
+        A.r_out[3 * i + 1] = u[1];
+        A.r_out[3 * i + 2] = u[2];
 #pragma unroll
         for (int d = 0; d < 3; ++d) P[d] = qi * u[d];
-        if (spread_rho) spread_ion(L, a, qi, u, rho);
+        if (A.rho) spread_ion(A.L, A.a, qi, u, A.rho);
+        if (A.pack) {
+            sanitize_move(dn, A.a, A.L, nullptr);
+            nres = make_record<T>(A.L, A.a, qi, u, dn, A.bk, h, val, ids);
+        }
     }
-    block_sum<3>(P);
+    if (mover && A.pack) {
+        // every lane of the two mover wavefronts takes part
+        const bool atomic_path = place_record<T>(nres, h, val, ids, A.bk);
+        if (live) A.dep_atomic[s] = atomic_path ? 1 : 0;
+    }
+    block_sum<3>(P);  // its barriers also publish Psh
     if (threadIdx.x == 0) {
-        partials[3 * blockIdx.x] = P[0];
-        partials[3 * blockIdx.x + 1] = P[1];
-        partials[3 * blockIdx.x + 2] = P[2];
+        A.dip_out[3 * blockIdx.x] = P[0];
+        A.dip_out[3 * blockIdx.x + 1] = P[1];
+        A.dip_out[3 * blockIdx.x + 2] = P[2];
+    }
+    if (!mover && live && forces) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) A.F[3 * i + d] = F[d] + qi * Psh[d] / (A.V * A.scal[S_EPSH + d]);
     }
 }
 
-hipError_t launch_ion_update(memd_ctx *c, void *D, const double *disp, bool spread_rho, double *partials,
-                             int *nblk, uint64_t seed, uint32_t t, double sigma) {
-    const int nb = ion_blocks(c->n);
+hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const double *disp, const double *disp_next,
+                           uint64_t seed, uint32_t t, double sigma, const double *dip_prev, int dip_prev_nblk,
+                           double *dip_out, int *nblk, bool pack_next, bool spread_rho) {
+    const int nb = ion_blocks_x8(c->n, kThreads / kIonStepIons);
     *nblk = nb;
-    if (c->fp32)
-        hipLaunchKernelGGL(k_ion_update<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
-                           c->q, c->r, disp, (float *)D, c->binrow, spread_rho ? 1 : 0, c->rho, partials,
-                           c->bad_moves, seed, t, sigma);
-    else
-        hipLaunchKernelGGL(k_ion_update<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
-                           c->q, c->r, disp, (double *)D, c->binrow, spread_rho ? 1 : 0, c->rho, partials,
-                           c->bad_moves, seed, t, sigma);
+    auto fill = [&](auto &A, auto *Dc, auto *Dn) {
+        A.n = c->n;
+        A.L = c->L;
+        A.Ns = c->Ns;
+        A.a = c->a;
+        A.V = c->V;
+        A.q = c->q;
+        A.r = c->r;
+        A.r_out = c->r_alt;
+        A.order = c->order;
+        A.perm = c->perm;
+        A.disp = disp;
+        A.disp_next = disp_next;
+        A.seed = seed;
+        A.t = t;
+        A.sigma = sigma;
+        A.Dcur = Dc;
+        A.Dnext = Dn;
+        A.eta_mode = c->eta_mode;
+        A.eta_uni = c->eta_uni;
+        A.scal = c->scal;
+        A.F = c->F;
+        A.dip_prev = dip_prev;
+        A.dip_prev_nblk = dip_prev_nblk;
+        A.dip_out = dip_out;
+        A.dep_atomic = c->dep_atomic;
+        A.pack = pack_next ? 1 : 0;
+        A.rho = spread_rho ? c->rho : nullptr;
+        A.bad = c->bad_moves;
+    };
+    if (c->fp32) {
+        IonStepArgs<float> A;
+        fill(A, (const float *)Dcur, (float *)Dnext);
+        A.bk = buckets<float>(c);
+        A.eta_prof = (const float *)c->eta_prof;
+        A.eta_link = (const float *)c->eta_link;
+        hipLaunchKernelGGL(k_ion_step<float>, dim3(nb), dim3(kThreads), 0, c->stream, A);
+    } else {
+        IonStepArgs<double> A;
+        fill(A, (const double *)Dcur, (double *)Dnext);
+        A.bk = buckets<double>(c);
+        A.eta_prof = (const double *)c->eta_prof;
+        A.eta_link = (const double *)c->eta_link;
+        hipLaunchKernelGGL(k_ion_step<double>, dim3(nb), dim3(kThreads), 0, c->stream, A);
+    }
+    std::swap(c->r, c->r_alt);  // the new positions are now the current ones
     return hipGetLastError();
 }
 
@@ -490,12 +758,68 @@ __global__ void k_bin_scatter(int n, int L, double a, const double *__restrict__
     binrow[i] = row;
 }
 
+// Binning with the ion arrays moved into bin order: storage index j goes to
+// its slot (r, q, F and the caller index perm), after which order and
+// slot_of are the identity and neighbouring storage indices are
+// neighbouring ions.
+__global__ void k_bin_reorder(int n, int L, double a, const double *__restrict__ r, const double *__restrict__ q,
+                              const double *__restrict__ F, const int *__restrict__ perm, int *__restrict__ cursor,
+                              double *__restrict__ r2, double *__restrict__ q2, double *__restrict__ F2,
+                              int *__restrict__ perm2, int *__restrict__ order, int *__restrict__ slot_of,
+                              int *__restrict__ binrow) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int cy, cz;
+    double f;
+    fold(r[3 * j + 1], a, L, cy, f);
+    fold(r[3 * j + 2], a, L, cz, f);
+    const int row = cy + L * cz;
+    const int s = atomicAdd(&cursor[row], 1);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        r2[3 * s + d] = r[3 * j + d];
+        F2[3 * s + d] = F[3 * j + d];
+    }
+    q2[s] = q[j];
+    perm2[s] = perm[j];
+    order[s] = s;
+    slot_of[s] = s;
+    binrow[s] = row;
+}
+
+__global__ void k_iota(int *dst, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = i;
+}
+
+// out[perm[s] * w + k] = in[s * w + k]: storage order back to the caller's.
+__global__ void k_unpermute(int n, int w, const int *__restrict__ perm, const double *__restrict__ in,
+                            double *__restrict__ out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int ci = perm[s];
+    for (int k = 0; k < w; ++k) out[(size_t)ci * w + k] = in[(size_t)s * w + k];
+}
+
+hipError_t launch_iota(hipStream_t st, int *dst, int n) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, st, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpermute(memd_ctx *c, int w, const double *in, double *out) {
+    if (c->n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unpermute, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, w, c->perm, in,
+                       out);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_int(int *dst, int v, size_t count) {
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < count; t += (size_t)gridDim.x * blockDim.x)
         dst[t] = v;
 }
 
-hipError_t launch_bin_ions(memd_ctx *c) {
+hipError_t launch_bin_ions(memd_ctx *c, bool reorder) {
     if (c->n == 0 || !c->order) return hipSuccess;
     const int nb = c->L * c->L;
     const int g = (int)((nb + kThreads - 1) / kThreads) < 4096 ? (nb + kThreads - 1) / kThreads : 4096;
@@ -504,8 +828,19 @@ hipError_t launch_bin_ions(memd_ctx *c) {
     hipLaunchKernelGGL(k_bin_count, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->r,
                        count);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, count, nb, start, cursor);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
-                       c->r, cursor, c->order, c->slot, c->binrow);
+    if (reorder) {
+        hipLaunchKernelGGL(k_bin_reorder, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
+                           c->r, c->q, c->F, c->perm, cursor, c->r_alt, c->q_alt, c->F_alt, c->perm_alt, c->order,
+                           c->slot, c->binrow);
+        std::swap(c->r, c->r_alt);
+        std::swap(c->q, c->q_alt);
+        std::swap(c->F, c->F_alt);
+        std::swap(c->perm, c->perm_alt);
+        c->sorted = true;
+    } else {
+        hipLaunchKernelGGL(k_bin_scatter, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
+                           c->r, cursor, c->order, c->slot, c->binrow);
+    }
     return hipGetLastError();
 }
 

@@ -47,25 +47,24 @@ __device__ __forceinline__ T eta_at(const LfArgs<T> &A, int d, int gz, size_t of
     }
 }
 
-// Ions for the deposit fused into the leapfrog.  Ions are binned by lattice
-// row (y, z) of their position at the last sort; an ion is "regular" when
-// every displacement component is shorter than a and its current row is
-// within one row (y and z) of its bin row.  A regular ion starting in cell c
-// deposits only on links whose origin lies in [c - 1, c + 2] per axis, so a
-// tile finds every regular ion touching its links in the bin rows
-// [y0 - 3, y0 + TY + 1] x [z0 - 3, z0 + TZ + 1].  Other ions are deposited
-// by the follow-up ion kernel with global atomics.
+// Ions for the deposit fused into the leapfrog.  An ion is "regular" when
+// every displacement component is shorter than a (so each axis of its
+// dimension-split move spans at most two cells); it then deposits only on
+// links whose origin lies within [c - 1, c + 2] per axis of its start cell
+// c.  The kernel that writes an ion's record (k_pack_ions or, one step
+// ahead, k_ion_step) appends it to the bucket of every leapfrog tile that
+// owns one of those links; a tile reads exactly its bucket.  Other ions
+// (irregular ones, and any whose bucket is full) are deposited by the ion
+// step after the leapfrog with global atomics.
 //
-// Records of the ions in bin order, written each step by k_pack_ions, in two
-// arrays.  The head: the start cell packed as x | y << 10 | z << 20 (-1 for
-// an ion left to the atomic path), then one word per axis d of the
-// dimension-split move: the corner of the 2 x 2 x 2 box of links it touches
-// (the first cell along d, the perpendicular cells c_d1, c_d2 of the
-// position it moves from), packed the same way, bit 30 set when the move
-// crosses into a second cell along d, bit 31 set when there is a move.  The
-// values: slot 8d + 4 cell + 2 o2 + o1 holds what is added to D_d at cell
-// `cell` along d and c_d1 + o1, c_d2 + o2 (each wrapped).  Lattices up to
-// 1024 per side.
+// A record: the head, with the start cell packed as x | y << 10 | z << 20
+// (-1 for an empty bucket entry), then one word per axis d of the move: the
+// corner of the 2 x 2 x 2 box of links it touches (the first cell along d,
+// the perpendicular cells c_d1, c_d2 of the position it moves from), packed
+// the same way, bit 30 set when the move crosses into a second cell along
+// d, bit 31 set when there is a move.  The values: slot 8d + 4 cell + 2 o2 +
+// o1 holds what is added to D_d at cell `cell` along d and c_d1 + o1,
+// c_d2 + o2 (each wrapped).  Lattices up to 1024 per side.
 constexpr int kConPerAxis = 8;
 constexpr unsigned kGroupTwo = 1u << 30, kGroupOn = 1u << 31;
 
@@ -78,12 +77,18 @@ struct DepCon {
     T val[3 * kConPerAxis];
 };
 
+// The tile buckets: tile b (b = tile_x + ntx (tile_y + nty chunk)) owns
+// entries [b cap, b cap + min(count[b kCountStride], cap)); a tile resets
+// its count after reading it, so the next writer starts from zero.  Each
+// count sits in a 128-byte line of its own (writers add to them with
+// atomics).
+constexpr int kCountStride = 32;
+
 struct DepArgs {
-    const int4 *head;       // [n] packed start cell and the three axis words, in bin order
-    const void *con;        // [n] DepCon<T>, in bin order
-    const int *row_start;   // [L^2] first slot of each row
-    const int *row_count;   // [L^2]
-    double a;
+    const int4 *head;  // [tiles * cap]
+    const void *con;   // [tiles * cap] DepCon<T>
+    int *count;        // [tiles * kCountStride]
+    int cap;
 };
 
 // Planes per z-chunk when the deposit is fused: up to 4, or up to 8 for the
@@ -93,10 +98,8 @@ constexpr int kDepTZWide = 8;
 
 // A regular ion moves less than a along every axis, so each axis of its
 // dimension-split move spans at most two cells (checked on the cell indices
-// too, so that rounding cannot make it three), and starts within one row
-// (in y and z) of the row it was binned in.
-__device__ __forceinline__ bool ion_regular(double a, int L, const double (&u)[3], const double (&du)[3],
-                                            int binrow) {
+// too, so that rounding cannot make it three).
+__device__ __forceinline__ bool ion_regular(double a, const double (&u)[3], const double (&du)[3]) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         if (!(fabs(du[d]) < a)) return false;
@@ -104,24 +107,12 @@ __device__ __forceinline__ bool ion_regular(double a, int L, const double (&u)[3
         const double lo = u[d] < u1 ? u[d] : u1, hi = u[d] < u1 ? u1 : u[d];
         if (floor(div_a(hi, a)) - floor(div_a(lo, a)) > 1.0) return false;
     }
-    int cy, cz;
-    double f;
-    fold(u[1], a, L, cy, f);
-    fold(u[2], a, L, cz, f);
-    int dy = cy - binrow % L, dz = cz - binrow / L;
-    if (dy > L / 2) dy -= L;
-    if (dy < -L / 2) dy += L;
-    if (dz > L / 2) dz -= L;
-    if (dz < -L / 2) dz += L;
-    return dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+    return true;
 }
-
 
 template <typename T, int R, int TZ = kDepTZ>
 struct DepSmem {
     T acc[3][TZ][4 * R][64];
-    int rowpre[(4 * R + 5) * (TZ + 5) + 1];
-    int rowbase[(4 * R + 5) * (TZ + 5)];  // first slot of each candidate row minus rowpre
 };
 
 // LDS of one tile: eta*D of two planes with a one-site halo, new B of one
@@ -132,10 +123,6 @@ struct LfSmem {
     T sB[3][4 * R + 1][65];
 };
 
-// Capacity of the fused deposit's candidate list, which borrows the march's
-// LDS (the last word holds the count).
-template <typename T, int R>
-constexpr int kListCap = (int)(sizeof(LfSmem<T, R>) / sizeof(int)) - 1;
 
 // One workgroup (256 threads) advances the tile (tile_x, tile_y) over the z
 // planes of `chunk`.  Every load wraps periodically; stores are masked to the
@@ -201,65 +188,30 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
 
     if constexpr (DEP) {
         // Deposit of the regular ions on the links this tile owns (x in
-        // [x0, x0+64), y in [y0, y0+TY), z in [z0, z1)), accumulated in LDS.
+        // [x0, x0+64), y in [y0, y0+TY), z in [z0, z1)), accumulated in LDS
+        // from the tile's bucket.
+        const int bucket = tile_x + A.ntx * (tile_y + A.nty * chunk);
+        const size_t base = (size_t)bucket * dep->cap;
+        const int cnt = min(dep->count[(size_t)bucket * kCountStride], dep->cap);
         T *accf = &DS->acc[0][0][0][0];
         for (int t = threadIdx.x; t < 3 * DTZ * TY * 64; t += blockDim.x) accf[t] = (T)0;
-        if (threadIdx.x == 0) reinterpret_cast<int *>(&S)[kListCap<T, R>] = 0;
-        const int nry = TY + 5, nrz = (z1 - z0) + 5, nrows = nry * nrz;
-        static_assert((4 * R + 5) * (DTZ + 5) <= 128, "candidate rows: two per lane of one wavefront");
-        if (wy == 0) {
-            // wavefront 0: counts and starts of the candidate rows, two rows
-            // per lane, prefix sums with cross-lane shifts
-            int cnt[2], st[2];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int t = 2 * lx + j;
-                cnt[j] = 0;
-                st[j] = 0;
-                if (t < nrows) {
-                    const int by = wrapc(y0 - 3 + t % nry + L, L), bz = wrapc(z0 - 3 + t / nry + L, L);
-                    cnt[j] = dep->row_count[by + L * bz];
-                    st[j] = dep->row_start[by + L * bz];
-                }
-            }
-            const int pair = cnt[0] + cnt[1];
-            int incl = pair;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(incl, o, 64);
-                if (lx >= o) incl += y;
-            }
-            const int excl = incl - pair;
-            if (lx == 0) DS->rowpre[0] = 0;
-            if (2 * lx < nrows) {
-                DS->rowpre[2 * lx + 1] = excl + cnt[0];
-                DS->rowbase[2 * lx] = st[0] - excl;
-            }
-            if (2 * lx + 1 < nrows) {
-                DS->rowpre[2 * lx + 2] = incl;
-                DS->rowbase[2 * lx + 1] = st[1] - (excl + cnt[0]);
-            }
-        }
-        __syncthreads();
-        const int total = DS->rowpre[nrows];
         const DepCon<T> *con = (const DepCon<T> *)dep->con;
         const int org[3] = {x0, y0, z0};
         const int ext[3] = {TX, min(y0 + TY, L) - y0, z1 - z0};
-        int *list = reinterpret_cast<int *>(&S);
-        int *list_n = list + kListCap<T, R>;
-
-        // Adds the values of the record in `slot` that fall on this tile's
-        // links to the LDS accumulator.  Per axis group the two candidate
-        // coordinates along each axis are tested once; each of the (up to)
-        // eight links then needs only those flags.
-        auto deposit_one = [&](int slot, const int4 &h) {
+        __syncthreads();
+        // Per axis group the two candidate coordinates along each axis are
+        // tested once; each of the (up to) eight links then needs only those
+        // flags.
+        for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+            const int4 h = dep->head[base + e];
+            if (h.x < 0) continue;
             constexpr int kWords = (int)sizeof(DepCon<T>) / 16;
             static_assert(sizeof(DepCon<T>) % 16 == 0, "record of whole 16-byte words");
             union {
                 uint4 raw[kWords];
                 DepCon<T> rec;
             } cn;
-            const uint4 *src = reinterpret_cast<const uint4 *>(con + slot);
+            const uint4 *src = reinterpret_cast<const uint4 *>(con + base + e);
 #pragma unroll
             for (int q = 0; q < kWords; ++q) cn.raw[q] = src[q];
             const unsigned gw[3] = {(unsigned)h.y, (unsigned)h.z, (unsigned)h.w};
@@ -271,13 +223,13 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
                 int l0[3], l1[3];
                 bool i0[3], i1[3];
 #pragma unroll
-                for (int e = 0; e < 3; ++e) {
-                    const int v0 = (int)((g >> (10 * e)) & 1023u);
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int v0 = (int)((g >> (10 * ax)) & 1023u);
                     const int v1 = v0 + 1 == L ? 0 : v0 + 1;
-                    l0[e] = v0 - org[e];
-                    l1[e] = v1 - org[e];
-                    i0[e] = (unsigned)l0[e] < (unsigned)ext[e];
-                    i1[e] = (unsigned)l1[e] < (unsigned)ext[e];
+                    l0[ax] = v0 - org[ax];
+                    l1[ax] = v1 - org[ax];
+                    i0[ax] = (unsigned)l0[ax] < (unsigned)ext[ax];
+                    i1[ax] = (unsigned)l1[ax] < (unsigned)ext[ax];
                 }
                 const int ncell = (g & kGroupTwo) ? 2 : 1;
 #pragma unroll
@@ -294,62 +246,15 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
                             const bool in = (sel[0] ? i1[0] : i0[0]) && (sel[1] ? i1[1] : i0[1]) &&
                                             (sel[2] ? i1[2] : i0[2]);
                             if (!in) continue;
-                            const int lx0 = sel[0] ? l1[0] : l0[0], ly0 = sel[1] ? l1[1] : l0[1],
-                                      lz0 = sel[2] ? l1[2] : l0[2];
-                            atomicAdd(&DS->acc[d][lz0][ly0][lx0], cn.rec.val[kConPerAxis * d + 4 * cell + 2 * o2 + o1]);
+                            const int lxx = sel[0] ? l1[0] : l0[0], lyy = sel[1] ? l1[1] : l0[1],
+                                      lzz = sel[2] ? l1[2] : l0[2];
+                            atomicAdd(&DS->acc[d][lzz][lyy][lxx], cn.rec.val[kConPerAxis * d + 4 * cell + 2 * o2 + o1]);
                         }
                 }
             }
-        };
-
-        // Pass 1: heads of the candidates (two per thread in flight), the
-        // ions whose link box can meet this tile go to the list (in the LDS
-        // of the march, unused until its prologue); past the list's capacity
-        // an ion is deposited at once.
-        for (int cbase = 0; cbase < total; cbase += 2 * (int)blockDim.x) {
-            int slot2[2];
-            int4 h2[2];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int cidx = cbase + j * (int)blockDim.x + (int)threadIdx.x;
-                slot2[j] = -1;
-                if (cidx < total) {
-                    int lo = 0, hi = nrows - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (DS->rowpre[mid] <= cidx) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    slot2[j] = DS->rowbase[lo] + cidx;
-                    h2[j] = dep->head[slot2[j]];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                if (slot2[j] < 0 || h2[j].x < 0) continue;
-                if (!((h2[j].y | h2[j].z | h2[j].w) & (int)kGroupOn)) continue;  // no move
-                // the links of a regular ion starting in cell c have origins
-                // in [c - 1, c + 2] per axis (periodic; no test along an axis
-                // the window covers)
-                const int cx = h2[j].x & 1023, cy = (h2[j].x >> 10) & 1023, cz = (h2[j].x >> 20) & 1023;
-                const int ex = ((cx - x0 + 2) % L + L) % L, ey = ((cy - y0 + 2) % L + L) % L,
-                          ez = ((cz - z0 + 2) % L + L) % L;
-                if ((L > TX + 4 && ex > TX + 2) || (L > TY + 4 && ey > TY + 2) ||
-                    (L > (z1 - z0) + 4 && ez > (z1 - z0) + 2))
-                    continue;
-                const int pos = atomicAdd(list_n, 1);
-                if (pos < kListCap<T, R>) list[pos] = slot2[j];
-                else deposit_one(slot2[j], h2[j]);
-            }
         }
         __syncthreads();
-        // Pass 2: the listed ions, head and values loaded together.
-        const int nlist = min(*list_n, kListCap<T, R>);
-        for (int i = threadIdx.x; i < nlist; i += blockDim.x) {
-            const int slot = list[i];
-            deposit_one(slot, dep->head[slot]);
-        }
-        __syncthreads();
+        if (threadIdx.x == 0) dep->count[(size_t)bucket * kCountStride] = 0;  // read by every lane before the barrier
     }
 
     T Dc[R][3], Dn[R][3], prevB[R][2];

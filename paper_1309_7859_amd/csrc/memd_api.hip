@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "leapfrog_tile.hpp"
@@ -247,7 +248,9 @@ void memd_destroy(memd_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     prof_clear(c);
     void *bufs[] = {c->D[0], c->D[1], c->B[0], c->B[1], c->eta_prof, c->eta_link, c->q, c->r, c->F,
-                    c->order, c->slot, c->bins, c->binrow, c->bad_moves, c->ionrec,
+                    c->order, c->slot, c->bins, c->binrow, c->bad_moves, c->dep_atomic, c->bk_head, c->bk_con, c->bk_count,
+                    c->dip[0], c->dip[1],
+                    c->perm, c->perm_alt, c->r_alt, c->q_alt, c->F_alt,
                     c->stage, c->rho, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt,
                     c->salt_nbar};
     for (void *b : bufs)
@@ -331,18 +334,39 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
         hipMalloc((void **)&c->F, 3 * nn * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->order, nn * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->slot, nn * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&c->perm, nn * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&c->perm_alt, nn * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&c->r_alt, 3 * nn * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->q_alt, nn * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->F_alt, 3 * nn * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->bins, 3 * (size_t)p->L * p->L * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->binrow, nn * sizeof(int)) != hipSuccess ||
-        hipMalloc(&c->ionrec, nn * (sizeof(int4) + (c->fp32 ? sizeof(DepCon<float>) : sizeof(DepCon<double>)))) !=
-            hipSuccess ||
+        hipMalloc((void **)&c->dep_atomic, nn * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->bad_moves, sizeof(unsigned int)) != hipSuccess ||
         hipMalloc((void **)&c->rho, Ns * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->partials, partial_doubles(n) * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->dip[0], 3 * (nn / 128 + 16) * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->dip[1], 3 * (nn / 128 + 16) * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->scal, S_COUNT * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->hist_audit, 2 * (size_t)kHistCap * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->hist_energy, 5 * (size_t)kHistCap * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(MEMD_ENOMEM);
+    }
+    // Tile buckets of the fused deposit, sized for the smallest fused tile
+    // shape (64 x 4 x 2): four entries per ion plus 64 per tile.
+    if (n > 0 && p->L >= 16 && p->L <= 1024) {
+        const size_t L = (size_t)p->L;
+        const size_t tiles = ((L + 63) / 64) * ((L + 3) / 4) * ((L + 1) / 2);
+        c->bk_tiles_max = (int)tiles;
+        c->bk_entries = 4 * nn + 64 * tiles;
+        const size_t rec = c->fp32 ? sizeof(DepCon<float>) : sizeof(DepCon<double>);
+        if (hipMalloc((void **)&c->bk_head, c->bk_entries * sizeof(int4)) != hipSuccess ||
+            hipMalloc(&c->bk_con, c->bk_entries * rec) != hipSuccess ||
+            hipMalloc((void **)&c->bk_count, tiles * kCountStride * sizeof(int)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MEMD_ENOMEM);
+        }
     }
     hipStream_t s = c->stream;
     for (int b = 0; b < 2; ++b) {
@@ -353,6 +377,8 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     hipMemsetAsync(c->bad_moves, 0, sizeof(unsigned int), s);
     hipMemsetAsync(c->scal, 0, S_COUNT * sizeof(double), s);
     hipMemsetAsync(c->F, 0, 3 * nn * sizeof(double), s);
+    c->sorted = false;
+    if (launch_iota(s, c->perm, n) != hipSuccess) return fail(MEMD_EDEVICE);
     if (n > 0) {
         if (copy_in(c, c->q, q, (size_t)n * sizeof(double)) != hipSuccess ||
             copy_in(c, c->r, r0, 3 * (size_t)n * sizeof(double)) != hipSuccess) {
@@ -479,8 +505,20 @@ namespace {
 
 // The per-step launch sequence (displacements from disp, or from the Philox
 // stream of `seed` when disp is null).
+//
+// With the fused deposit a step is two kernels: the leapfrog (with the
+// tile-owned deposit of the regular ions) and the ion step, which also
+// computes the forces of the state the step started from and writes the
+// next step's deposit records.  The first step of a call skips those forces
+// (the previous call, or the solve or set_state, left them in F), and after
+// the last step one force launch gives the forces of the final state, so
+// each state's forces are computed once.  Otherwise: leapfrog, the atomic
+// deposit, forces.
 memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, double sigma) {
     const size_t per = 3 * (size_t)c->n;
+    bool recs_ready = false;  // the deposit records of this step were written by the previous ion step
+    const double *dip_prev = nullptr;
+    int dip_nb = 0;
     for (int t = 0; t < nsteps; ++t) {
         if (c->salt_every > 0 && c->step_index % c->salt_every == 0) {
             prof_begin(c, F_SALT);
@@ -494,24 +532,44 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
         const double *dstep = dd ? dd + per * t : nullptr;
         const uint32_t tstep = (uint32_t)c->step_index;
         int nb = 0;
-        if (c->sort_every > 0 && c->step_index % c->sort_every == 0) CK(launch_bin_ions(c));
+        if (c->sort_every > 0 && c->step_index % c->sort_every == 0) {
+            CK(launch_bin_ions(c, true));
+            recs_ready = false;
+        }
         const bool fused = fused_deposit_ok(c);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         prof_pair(c, F_LEAPFROG, &e0, &e1);
         CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx], e0, e1, dstep, seed, tstep, sigma,
-                           fused));
-        prof_begin(c, F_DEPOSIT);
-        if (fused)
-            CK(launch_ion_update(c, c->D[nx], dstep, audit_now, c->partials, &nb, seed, tstep, sigma));
-        else
+                           fused, !recs_ready));
+        if (fused) {
+            // records for the next step only when it exists in this call and
+            // does not re-bin first
+            const bool pack_next =
+                t + 1 < nsteps && !(c->sort_every > 0 && next % c->sort_every == 0);
+            double *dip_out = c->dip[c->step_index & 1];
+            prof_begin(c, F_DEPOSIT);
+            CK(launch_ion_step(c, c->D[c->cur], c->D[nx], dstep, dd && pack_next ? dd + per * (t + 1) : nullptr,
+                               seed, tstep, sigma, t > 0 ? dip_prev : nullptr, dip_nb, dip_out, &nb, pack_next,
+                               audit_now));
+            prof_end(c, F_DEPOSIT);
+            recs_ready = pack_next;
+            dip_prev = dip_out;
+            dip_nb = nb;
+            c->cur = nx;
+            if (energy_now)  // U_dip and the self-energy pass read P of this state
+                CK(launch_finalize_dipole(c->stream, dip_prev, dip_nb, c->scal + S_P));
+        } else {
+            prof_begin(c, F_DEPOSIT);
             CK(launch_deposit(c, c->D[nx], dstep, audit_now, c->partials, &nb, seed, tstep, sigma));
-        prof_end(c, F_DEPOSIT);
-        c->cur = nx;
-        prof_begin(c, F_FORCES);
-        // every force block sums the deposit's per-block q r partials into P
-        // (block 0 also stores it)
-        CK(launch_forces(c, c->D[c->cur], c->partials, nb));
-        prof_end(c, F_FORCES);
+            prof_end(c, F_DEPOSIT);
+            c->cur = nx;
+            prof_begin(c, F_FORCES);
+            // every force block sums the deposit's per-block q r partials into
+            // P (block 0 also stores it)
+            CK(launch_forces(c, c->D[c->cur], c->partials, nb));
+            prof_end(c, F_FORCES);
+            dip_prev = nullptr;
+        }
         if (audit_now) {
             const int slot = c->hist_audit_n < c->hist_cap ? c->hist_audit_n : c->hist_cap - 1;
             CK(enqueue_audit(c, c->hist_audit + 2 * (size_t)slot));
@@ -523,6 +581,12 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
             if (c->hist_energy_n < c->hist_cap) ++c->hist_energy_n;
         }
         c->step_index = next;
+    }
+    if (dip_prev) {
+        // forces (and P) of the final state
+        prof_begin(c, F_FORCES);
+        CK(launch_forces(c, c->D[c->cur], dip_prev, dip_nb));
+        prof_end(c, F_FORCES);
     }
     return MEMD_OK;
 }
@@ -574,7 +638,14 @@ memd_status memd_forces(memd_ctx *c, double *F_out) {
     CHECK_CTX(c);
     if (!F_out && c->n > 0) return MEMD_EINVAL;
     if (!c->ready) return MEMD_ESTATE;
-    CK(copy_out(c, F_out, c->F, 3 * (size_t)c->n * sizeof(double)));
+    const size_t bytes = 3 * (size_t)c->n * sizeof(double);
+    if (c->sorted) {
+        CK(ensure_stage(c, bytes));
+        CK(launch_unpermute(c, 3, c->F, c->stage));
+        CK(copy_out(c, F_out, c->stage, bytes));
+    } else {
+        CK(copy_out(c, F_out, c->F, bytes));
+    }
     return MEMD_OK;
 }
 
@@ -646,7 +717,16 @@ memd_status memd_get_state(memd_ctx *c, double *D, double *B, double *r) {
         CK(launch_uncast(c->stream, c->B[c->cur], c->stage, M, c->fp32));
         CK(copy_out(c, B, c->stage, M * sizeof(double)));
     }
-    if (r) CK(copy_out(c, r, c->r, 3 * (size_t)c->n * sizeof(double)));
+    if (r) {
+        const size_t bytes = 3 * (size_t)c->n * sizeof(double);
+        if (c->sorted) {
+            CK(ensure_stage(c, bytes));
+            CK(launch_unpermute(c, 3, c->r, c->stage));
+            CK(copy_out(c, r, c->stage, bytes));
+        } else {
+            CK(copy_out(c, r, c->r, bytes));
+        }
+    }
     return MEMD_OK;
 }
 
@@ -664,6 +744,13 @@ memd_status memd_set_state(memd_ctx *c, const double *D, const double *B, const 
         CK(launch_cast(c->stream, c->stage, c->B[c->cur], M, c->fp32));
     }
     if (r) {
+        if (c->sorted) {
+            // back to the caller's order: q moves, perm becomes the identity
+            CK(launch_unpermute(c, 1, c->q, c->q_alt));
+            std::swap(c->q, c->q_alt);
+            CK(launch_iota(c->stream, c->perm, c->n));
+            c->sorted = false;
+        }
         CK(copy_in(c, c->r, r, 3 * (size_t)c->n * sizeof(double)));
         CK(launch_bin_ions(c));
     }

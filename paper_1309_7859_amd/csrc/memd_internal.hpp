@@ -87,9 +87,25 @@ struct memd_ctx {
     double *F;     // [3n]
     int *order;    // [n] ion visiting order (binned by lattice row), refreshed every sort_every steps
     int *slot;     // [n] inverse of order: the slot of ion i
+    // Storage order of the ion arrays r, q, F: the caller's order until the
+    // first re-binning of a step loop, which moves them into bin order; perm
+    // maps a storage index to the caller's index (identity while !sorted).
+    int *perm;
+    bool sorted;
+    double *r_alt, *q_alt, *F_alt;  // targets of the re-binning's move
+    int *perm_alt;
     int *bins;     // [3 L^2] bin counts, row starts, cursors
     int *binrow;   // [n] bin row of each ion at the last sort
-    void *ionrec;  // ion records in bin order for the fused deposit: [n] int4 heads, then [n] contributions
+    // Tile buckets of the fused deposit (leapfrog_tile.hpp, DepArgs): bk_entries
+    // records (int4 head + values), shared by the tiles of the current tile
+    // shape, and a count per tile; dep_atomic[slot] marks an ion left to the
+    // atomic path for the step its record was written for.
+    int4 *bk_head;
+    void *bk_con;
+    int *bk_count;
+    size_t bk_entries;
+    int bk_tiles_max;
+    int *dep_atomic;
     unsigned int *bad_moves;  // rejected displacement components (not finite or > L a)
     bool fuse_deposit;
     int sort_every;
@@ -99,6 +115,7 @@ struct memd_ctx {
     // reductions and audit
     double *rho;       // FP64 [Ns], kept all-zero between uses
     double *partials;  // FP64 [kRedBlocks * 8]
+    double *dip[2];    // FP64 per-block q r sums of the ion step, alternating by step
     double *scal;      // FP64 [S_COUNT]
     double *hist_audit;   // FP64 [2*hist_cap]
     double *hist_energy;  // FP64 [5*hist_cap]
@@ -126,15 +143,26 @@ namespace memd {
 // ev0/ev1 (optional): events recorded at the kernel's start and end.
 // with_deposit: the regular ions' deposit is fused in (displacements from disp,
 // or from the Philox stream when disp is null); requires fused_deposit_ok(c).
+// need_pack: write the deposit records first (false when the previous step's
+// ion kernel already wrote them for this step).
 hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout,
                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, const double *disp = nullptr,
-                           uint64_t seed = 0, uint32_t t = 0, double sigma = 0.0, bool with_deposit = false);
+                           uint64_t seed = 0, uint32_t t = 0, double sigma = 0.0, bool with_deposit = false,
+                           bool need_pack = true);
 bool fused_deposit_ok(const memd_ctx *c);
+// Tiles of the current leapfrog tile shape, and the bucket capacity per tile.
+int bucket_tiles(const memd_ctx *c);
+int bucket_cap(const memd_ctx *c);
 hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma);
-// Ion update after the fused leapfrog: irregular ions deposited with global
-// atomics, every position advanced, dipole partials (and rho for the audit).
-hipError_t launch_ion_update(memd_ctx *c, void *D, const double *disp, bool spread_rho, double *partials,
-                             int *nblk, uint64_t seed, uint32_t t, double sigma);
+// The ion side of a step after the fused leapfrog (k_ion_step): forces of the
+// state the step started from (when dip_prev is set: the previous step's
+// dipole partials), irregular ions deposited into Dnext with global atomics,
+// every position advanced, dipole partials into dip_out (nblk blocks), the
+// next step's deposit records (pack_next; displacements disp_next or the
+// Philox stream at t + 1) and rho for the audit (spread_rho).
+hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const double *disp, const double *disp_next,
+                           uint64_t seed, uint32_t t, double sigma, const double *dip_prev, int dip_prev_nblk,
+                           double *dip_out, int *nblk, bool pack_next, bool spread_rho);
 hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
                                int *nblk);
 hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk);
@@ -155,7 +183,12 @@ hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_
 hipError_t launch_spread(memd_ctx *c, const double *charges_or_null, double *dst);
 hipError_t launch_dipole(memd_ctx *c, double *partials, int *nblk);
 hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk);
-hipError_t launch_bin_ions(memd_ctx *c);
+// Row binning of the ions (order, slot, binrow, row counts/starts); with
+// reorder the ion arrays themselves move into bin order (see sorted).
+hipError_t launch_bin_ions(memd_ctx *c, bool reorder = false);
+hipError_t launch_iota(hipStream_t s, int *dst, int n);
+// out[perm[s] * w + k] = in[s * w + k] on the context's stream.
+hipError_t launch_unpermute(memd_ctx *c, int w, const double *in, double *out);
 hipError_t launch_uself(memd_ctx *c, double *partials, int *nblk);
 
 // ---- launchers (reductions / finalisers) ----

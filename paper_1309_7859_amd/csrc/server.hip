@@ -61,12 +61,17 @@ struct Request {
 size_t resident_bytes(int L, int n) {
     const size_t Ns = (size_t)L * L * L;
     const size_t nn = (size_t)(n > 0 ? n : 1);
-    return 4 * 3 * Ns * sizeof(float)            // D, B ping-pong
-           + Ns * sizeof(double)                 // rho
-           + 2 * (size_t)L * L * sizeof(int)     // bins
-           + nn * (7 * sizeof(double) + sizeof(int))
-           + (2 + 5) * 4096 * sizeof(double)     // histories
-           + 3 * (size_t)L * sizeof(float) + (1 << 16);
+    size_t b = 4 * 3 * Ns * sizeof(float)            // D, B ping-pong
+               + Ns * sizeof(double)                 // rho
+               + 3 * (size_t)L * L * sizeof(int)     // bins
+               + nn * (14 * sizeof(double) + 6 * sizeof(int))  // ion arrays and their re-binning targets
+               + (2 + 5) * 4096 * sizeof(double)     // histories
+               + 3 * (size_t)L * sizeof(float) + (1 << 16);
+    if (n > 0 && L >= 16 && L <= 1024) {  // tile buckets of the fused deposit (FP32 records)
+        const size_t tiles = (((size_t)L + 63) / 64) * (((size_t)L + 3) / 4) * (((size_t)L + 1) / 2);
+        b += (4 * nn + 64 * tiles) * (16 + 24 * sizeof(float)) + tiles * 128;
+    }
+    return b;
 }
 
 size_t solve_bytes(int L) {

@@ -120,6 +120,33 @@ def test_c2_parity(prec):
         run_parity(S, G, s["disp"], {1, 10, 100}, 1e-4, 1e-5, 1e-4)
 
 
+def test_c2_fp32_all_1000_steps():
+    """32^3, 1000 ions, eps = 80 in FP32 over the workload's full 1000 steps,
+    taken in calls of 250 steps (the multi-step pipeline: forces in the ion
+    step, deposit records one step ahead, re-binning every 16 steps): the
+    FP32 Gauss residual stays bounded and forces and energies stay within
+    the FP32 tolerance of the FP64 oracle."""
+    w = W.WORKLOADS["c2"]
+    s = W.make_system(w)
+    assert s["disp"].shape[0] == 1000
+    S, G = pair(w.L, s["q"], s["r0"], eps_min=80.0, precision=memd.FP32_MIXED)
+    apply_eps(S, G, "uniform", 80.0)
+    S.initial_solve(1e-13)
+    share_state(S, G)
+    for seg in range(4):
+        d = s["disp"][250 * seg:250 * (seg + 1)]
+        G.step(d, 250)
+        for t in range(250):
+            S.step(d[t])
+        m, _ = G.gauss_residual()
+        assert m <= 1e-5 * 1.0, (seg, m)
+        Fo, _ = S.forces()
+        assert force_err(G.forces(), Fo) <= 1e-4, seg
+        errs = energy_err(G.energy(), S.energy())
+        assert max(errs.values()) <= 1e-4, (seg, errs)
+    assert np.max(np.abs(G.state()[2] - S.r)) <= 1e-12 * np.max(np.abs(S.r))
+
+
 def test_c3_fp32_slab():
     """64^3, 10^4 ions, tanh slab 2 -> 80 (site profile per plane), FP32 fields."""
     w = W.WORKLOADS["c3"]
