@@ -78,21 +78,21 @@ static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, voi
     return hipGetLastError();
 }
 
-int bucket_tiles(const memd_ctx *c) {
+int list_tiles(const memd_ctx *c) {
     const int TY = 4 * c->lf_rows;
     return ((c->L + 63) / 64) * ((c->L + TY - 1) / TY) * ((c->L + c->lf_tz - 1) / c->lf_tz);
 }
 
-int bucket_cap(const memd_ctx *c) {
-    const int nt = bucket_tiles(c);
-    const size_t cap = c->bk_entries / (size_t)(nt > 0 ? nt : 1);
+int list_cap(const memd_ctx *c) {
+    const int nt = list_tiles(c);
+    const size_t cap = c->list_entries / (size_t)(nt > 0 ? nt : 1);
     return cap > (size_t)INT32_MAX ? INT32_MAX : (int)cap;
 }
 
 bool fused_deposit_ok(const memd_ctx *c) {
     const int tz_max = c->fp32 && c->lf_rows == 1 ? kDepTZWide : kDepTZ;
-    return c->fuse_deposit && c->n > 0 && c->bk_head && c->L >= 16 && c->L <= 1024 && c->lf_tz <= tz_max &&
-           c->lf_rows <= (c->fp32 ? 2 : 1) && bucket_tiles(c) <= c->bk_tiles_max && bucket_cap(c) >= 16;
+    return c->fuse_deposit && c->n > 0 && c->list && c->L >= 16 && c->L <= 1024 && c->lf_tz <= tz_max &&
+           c->lf_rows <= (c->fp32 ? 2 : 1) && list_tiles(c) <= c->list_tiles_max && list_cap(c) >= 16;
 }
 
 hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout, hipEvent_t e0,
@@ -101,14 +101,22 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
     DepArgs P;
     const DepArgs *dp = nullptr;
     if (with_deposit) {
-        if (need_pack) {
+        // the lists first (records read each ion's list cell), then the
+        // records unless the previous ion step wrote them against these lists
+        const bool rebuild = c->lists_key != c->lf_rows * 4096 + c->lf_tz;
+        if (rebuild) {
+            hipError_t e = launch_build_lists(c);
+            if (e != hipSuccess) return e;
+        }
+        if (need_pack || rebuild) {
             hipError_t e = launch_pack_ions(c, disp, seed, t, sigma);
             if (e != hipSuccess) return e;
         }
-        P.head = c->bk_head;
-        P.con = c->bk_con;
-        P.count = c->bk_count;
-        P.cap = bucket_cap(c);
+        P.head = c->rec_head;
+        P.con = c->rec_con;
+        P.list = c->list;
+        P.count = c->list_count;
+        P.cap = list_cap(c);
         dp = &P;
     }
     if (c->fp32) {

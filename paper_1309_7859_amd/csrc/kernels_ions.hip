@@ -91,29 +91,27 @@ hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_
 
 __global__ void k_fill_int(int *dst, int v, size_t count);
 
-// Where the records of the fused deposit go: the tile buckets of the next
-// leapfrog launch (leapfrog_tile.hpp, DepArgs) and its tile shape.
+// The records of the fused deposit (leapfrog_tile.hpp), one per slot, and
+// what decides whether an ion stays with the tiles: its cell at the last
+// list build (cbin, packed) and whether it fitted the lists (list_fail).
 template <typename T>
-struct Buckets {
+struct DepOut {
     int4 *head;
     DepCon<T> *con;
-    int *count;
-    int cap;
-    int TY, TZ, ntx, nty, nz;
+    const int *cbin;
+    const int *list_fail;
 };
 
-// The record of one ion for the fused deposit (du already sanitised): the
-// axes of the dimension-split move are taken in turn with the arithmetic of
-// deposit_ion (bit for bit), giving per axis the link-box corner and the
-// values -q (ub - ua)/a w w / a^2 (in the field type), and the tiles that
-// own a link of the ion's boxes (at most two along each axis).  Returns the
-// number of those tiles, or -1 when the ion is left to the atomic path
-// (irregular, or more than two tiles along an axis); 0 when it does not move.
+// The record of one ion in slot s for the fused deposit (du already
+// sanitised): the axes of the dimension-split move are taken in turn with
+// the arithmetic of deposit_ion (bit for bit), giving per axis the link-box
+// corner and the values -q (ub - ua)/a w w / a^2 (in the field type).
+// Returns true, and writes a head of -1, when the ion is left to the atomic
+// path: irregular, drifted more than one cell from its list cell along an
+// axis, or missing from a list.
 template <typename T>
-__device__ __forceinline__ int make_record(int L, double a, double qi, const double (&u_in)[3],
-                                           const double (&du)[3], const Buckets<T> &B, int4 &h,
-                                           T (&val)[3 * kConPerAxis], int (&ids)[8]) {
-    if (!ion_regular(a, u_in, du)) return -1;
+__device__ __forceinline__ bool write_record(int L, double a, double qi, const double (&u_in)[3],
+                                             const double (&du)[3], int s, const DepOut<T> &O) {
     double u[3] = {u_in[0], u_in[1], u_in[2]};
     int c0[3];
     {
@@ -121,15 +119,25 @@ __device__ __forceinline__ int make_record(int L, double a, double qi, const dou
 #pragma unroll
         for (int d = 0; d < 3; ++d) fold(u[d], a, L, c0[d], f);
     }
+    bool atomic_path = O.list_fail[s] != 0 || !ion_regular(a, u_in, du);
+    const int cb = O.cbin[s];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        int off = c0[e] - ((cb >> (10 * e)) & 1023) + 1;
+        off += off < 0 ? L : (off >= L ? -L : 0);
+        atomic_path = atomic_path || off > 2;  // start cell within one cell of the list cell
+    }
+    if (atomic_path) {
+        O.head[s] = make_int4(-1, 0, 0, 0);
+        return true;
+    }
     const double a2 = a * a;
+    DepCon<T> &o = O.con[s];
     unsigned int g[3] = {0u, 0u, 0u};
-    int lo[3] = {3, 3, 3}, hi[3] = {-2, -2, -2};  // link-origin offsets from c0 touched, per axis
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
         const double u0 = u[d], u1 = u0 + du[d];
-#pragma unroll
-        for (int k = 0; k < kConPerAxis; ++k) val[kConPerAxis * d + k] = (T)0;
         if (u1 != u0) {
             int c1, c2;
             double f1, f2;
@@ -144,16 +152,6 @@ __device__ __forceinline__ int make_record(int L, double a, double qi, const dou
             corner[d2] = c2;
             const bool two = khi > klo;
             g[d] = (unsigned)pack_cell(corner[0], corner[1], corner[2]) | kGroupOn | (two ? kGroupTwo : 0u);
-#pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                // offset in [-1, 2] of the corner from the start cell
-                int off = corner[e] - c0[e] + 1;
-                off += off < 0 ? L : (off >= L ? -L : 0);
-                off -= 1;
-                const int top = off + (e == d ? (two ? 1 : 0) : 1);
-                lo[e] = off < lo[e] ? off : lo[e];
-                hi[e] = top > hi[e] ? top : hi[e];
-            }
             // a regular move spans at most two cells along the axis
 #pragma unroll
             for (int cell = 0; cell < 2; ++cell) {
@@ -168,61 +166,113 @@ __device__ __forceinline__ int make_record(int L, double a, double qi, const dou
                 for (int o2 = 0; o2 < 2; ++o2)
 #pragma unroll
                     for (int o1 = 0; o1 < 2; ++o1)
-                        val[kConPerAxis * d + 4 * cell + 2 * o2 + o1] = (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
+                        o.val[kConPerAxis * d + 4 * cell + 2 * o2 + o1] = (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
             }
         }
         u[d] = u1;
     }
-    if (!((g[0] | g[1] | g[2]) & kGroupOn)) return 0;  // no move, nothing to deposit
-    h = make_int4(pack_cell(c0[0], c0[1], c0[2]), (int)g[0], (int)g[1], (int)g[2]);
-    const int ext[3] = {64, B.TY, B.TZ};
-    int tid[3][2], nt[3];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-        nt[e] = 0;
-        for (int off = lo[e]; off <= hi[e]; ++off) {
-            int cell = c0[e] + off;
-            cell += cell < 0 ? L : (cell >= L ? -L : 0);
-            const int tt = cell / ext[e];
-            bool seen = false;
-            for (int k = 0; k < nt[e]; ++k) seen = seen || tid[e][k] == tt;
-            if (seen) continue;
-            if (nt[e] == 2) return -1;
-            tid[e][nt[e]++] = tt;
-        }
-    }
-    const int nres = nt[0] * nt[1] * nt[2];
-    for (int k = 0; k < nres; ++k) {
-        const int kx = k % nt[0], ky = (k / nt[0]) % nt[1], kz = k / (nt[0] * nt[1]);
-        ids[k] = tid[0][kx] + B.ntx * (tid[1][ky] + B.nty * tid[2][kz]);
-    }
-    return nres;
+    O.head[s] = make_int4(pack_cell(c0[0], c0[1], c0[2]), (int)g[0], (int)g[1], (int)g[2]);
+    return false;
 }
 
-// Bucket positions for the records of a wavefront, all lanes converged
-// (lanes without a record pass nres <= 0): per reservation round the lanes
-// that share a tile are counted with ballots and one lane of each group
-// adds the group's size to the tile's count, so a wavefront issues one
-// atomic per distinct tile and round (sorted ions share tiles; adding per
-// lane made the same counters the bottleneck).  Then the record goes to every
-// reserved entry, or, when a bucket was full, the reserved entries are
-// blanked and the ion is left to the atomic path.  Returns whether the
-// lane's ion goes to the atomic path.
+// Records for the step about to run, ions read in storage order
+// (coalesced), one lane per ion, ion i's record going to its slot
+// slot_of[i]; displacements are indexed by the caller's index perm[i].
 template <typename T>
-__device__ __forceinline__ bool place_record(int nres, const int4 &h, const T (&val)[3 * kConPerAxis],
-                                             const int (&ids)[8], const Buckets<T> &B) {
+__global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const double *__restrict__ q,
+                                                   const double *__restrict__ r, const double *__restrict__ disp,
+                                                   const int *__restrict__ slot_of, const int *__restrict__ perm,
+                                                   int *__restrict__ dep_atomic, DepOut<T> O, uint64_t seed,
+                                                   uint32_t t, double sigma) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ci = perm ? perm[i] : i;
+    const double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
+    double du[3];
+    if (disp) {
+        du[0] = disp[3 * ci];
+        du[1] = disp[3 * ci + 1];
+        du[2] = disp[3 * ci + 2];
+    } else {
+        philox_displacement(seed, t, (uint32_t)ci, sigma, du);
+    }
+    sanitize_move(du, a, L, nullptr);
+    const int s = slot_of[i];
+    dep_atomic[s] = write_record<T>(L, a, q[i], u, du, s, O) ? 1 : 0;
+}
+
+template <typename T>
+static DepOut<T> dep_out(memd_ctx *c) {
+    DepOut<T> O;
+    O.head = c->rec_head;
+    O.con = (DepCon<T> *)c->rec_con;
+    O.cbin = c->cbin;
+    O.list_fail = c->list_fail;
+    return O;
+}
+
+// Tile lists, built at a re-binning for the current tile shape: storage
+// index j (slot slot_of[j]) records its cell c_b and joins the list of every
+// tile that owns a link with origin in [c_b - 2, c_b + 3] along each axis.
+// Lanes of a wavefront that join the same tile in the same round reserve
+// their entries with one atomic (sorted ions share tiles).  An ion that
+// would need more than 4 tiles along an axis or finds a list full is
+// marked list_fail: its record head is then -1 at every step, so tiles that
+// do list it skip it, and it is deposited with atomics.
+struct TileLists {
+    int *list, *count;
+    int cap, TY, TZ, ntx, nty;
+};
+
+__global__ __launch_bounds__(256) void k_build_lists(int n, int L, double a, const double *__restrict__ r,
+                                                     const int *__restrict__ slot_of, int *__restrict__ cbin,
+                                                     int *__restrict__ list_fail, TileLists T) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
-    int pos[8];
-    bool ok = true;
-    for (int k = 0; k < 8; ++k) {
-        const int my = k < nres ? ids[k] : -1;
+    int nres = 0, s = 0;
+    int tid[3][4], nt[3] = {0, 0, 0};
+    bool fail = false;
+    if (j < n) {
+        s = slot_of[j];
+        int c[3];
+        double f;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) fold(r[3 * j + e], a, L, c[e], f);
+        cbin[s] = pack_cell(c[0], c[1], c[2]);
+        const int ext[3] = {64, T.TY, T.TZ};
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            for (int off = -2; off <= 3; ++off) {
+                int cell = c[e] + off;
+                cell += cell < 0 ? L : (cell >= L ? -L : 0);
+                const int tt = cell / ext[e];
+                bool seen = false;
+                for (int k = 0; k < nt[e]; ++k) seen = seen || tid[e][k] == tt;
+                if (seen) continue;
+                if (nt[e] == 4) {
+                    fail = true;
+                    break;
+                }
+                tid[e][nt[e]++] = tt;
+            }
+        }
+        nres = fail ? 0 : nt[0] * nt[1] * nt[2];
+    }
+    // every lane of the wavefront takes part in the reservation rounds
+    bool ok = !fail;
+    for (int k = 0; k < 64; ++k) {
+        int my = -1;
+        if (k < nres) {
+            const int kx = k % nt[0], ky = (k / nt[0]) % nt[1], kz = k / (nt[0] * nt[1]);
+            my = tid[0][kx] + T.ntx * (tid[1][ky] + T.nty * tid[2][kz]);
+        }
         unsigned long long rem = __ballot(my >= 0);
         if (rem == 0ull) break;  // the same for every lane
         int lead = lane, rank = 0, take = 0;
         while (rem) {
             const int l = __ffsll((long long)rem) - 1;
-            const int idl = __shfl(my, l, 64);
+            const int idl = __builtin_amdgcn_readlane(my, l);
             const unsigned long long same = __ballot(my == idl);
             if (my == idl) {
                 lead = l;
@@ -232,89 +282,45 @@ __device__ __forceinline__ bool place_record(int nres, const int4 &h, const T (&
             rem &= ~same;
         }
         int base = 0;
-        if (take > 0) base = atomicAdd(&B.count[(size_t)my * kCountStride], take);
+        if (take > 0) base = atomicAdd(&T.count[(size_t)my * kCountStride], take);
         base = __shfl(base, lead, 64);
         if (my >= 0) {
-            pos[k] = base + rank;
-            ok = ok && pos[k] < B.cap;
+            const int pos = base + rank;
+            if (pos >= T.cap) ok = false;
+            else T.list[(size_t)my * T.cap + pos] = s;
         }
     }
-    if (nres <= 0) return nres < 0;
-    for (int k = 0; k < nres; ++k) {
-        if (pos[k] >= B.cap) continue;
-        const size_t at = (size_t)ids[k] * B.cap + pos[k];
-        if (!ok) {
-            B.head[at] = make_int4(-1, 0, 0, 0);
-            continue;
-        }
-        B.head[at] = h;
-        DepCon<T> &o = B.con[at];
-#pragma unroll
-        for (int q = 0; q < 3 * kConPerAxis; ++q) o.val[q] = val[q];
-    }
-    return !ok;
+    if (j < n) list_fail[s] = ok ? 0 : 1;
 }
 
-// Records for the step about to run, ions read in storage order
-// (coalesced), one lane per ion; the bucket counts were zeroed before.
-// dep_atomic[slot_of[i]] marks an ion left to the atomic path.
-// Displacements are indexed by the caller's index perm[i].
-template <typename T>
-__global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const double *__restrict__ q,
-                                                   const double *__restrict__ r, const double *__restrict__ disp,
-                                                   const int *__restrict__ slot_of, const int *__restrict__ perm,
-                                                   int *__restrict__ dep_atomic, Buckets<T> B, uint64_t seed,
-                                                   uint32_t t, double sigma) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int4 h = make_int4(-1, 0, 0, 0);
-    T val[3 * kConPerAxis];
-    int ids[8];
-    int nres = 0;
-    if (i < n) {
-        const int ci = perm ? perm[i] : i;
-        const double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
-        double du[3];
-        if (disp) {
-            du[0] = disp[3 * ci];
-            du[1] = disp[3 * ci + 1];
-            du[2] = disp[3 * ci + 2];
-        } else {
-            philox_displacement(seed, t, (uint32_t)ci, sigma, du);
-        }
-        sanitize_move(du, a, L, nullptr);
-        nres = make_record<T>(L, a, q[i], u, du, B, h, val, ids);
-    }
-    const bool atomic_path = place_record<T>(nres, h, val, ids, B);  // every lane of the wavefront takes part
-    if (i < n) dep_atomic[slot_of[i]] = atomic_path ? 1 : 0;
-}
-
-template <typename T>
-static Buckets<T> buckets(memd_ctx *c) {
-    Buckets<T> B;
-    B.head = c->bk_head;
-    B.con = (DepCon<T> *)c->bk_con;
-    B.count = c->bk_count;
-    B.TY = 4 * c->lf_rows;
-    B.TZ = c->lf_tz;
-    B.ntx = (c->L + 63) / 64;
-    B.nty = (c->L + B.TY - 1) / B.TY;
-    B.nz = (c->L + B.TZ - 1) / B.TZ;
-    B.cap = bucket_cap(c);
-    return B;
+hipError_t launch_build_lists(memd_ctx *c) {
+    if (c->n == 0 || !c->list) return hipSuccess;
+    TileLists T;
+    T.list = c->list;
+    T.count = c->list_count;
+    T.TY = 4 * c->lf_rows;
+    T.TZ = c->lf_tz;
+    T.ntx = (c->L + 63) / 64;
+    T.nty = (c->L + T.TY - 1) / T.TY;
+    T.cap = list_cap(c);
+    const size_t nc = (size_t)list_tiles(c) * kCountStride;
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((nc + kThreads - 1) / kThreads)), dim3(kThreads), 0, c->stream,
+                       c->list_count, 0, nc);
+    hipLaunchKernelGGL(k_build_lists, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->r,
+                       c->slot, c->cbin, c->list_fail, T);
+    c->lists_key = c->lf_rows * 4096 + c->lf_tz;
+    return hipGetLastError();
 }
 
 hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma) {
     if (c->n == 0) return hipSuccess;
-    const size_t nc = (size_t)bucket_tiles(c) * kCountStride;
-    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((nc + kThreads - 1) / kThreads)), dim3(kThreads), 0, c->stream,
-                       c->bk_count, 0, nc);
     const int nb = ion_blocks(c->n);
     if (c->fp32)
         hipLaunchKernelGGL(k_pack_ions<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->q,
-                           c->r, disp, c->slot, c->perm, c->dep_atomic, buckets<float>(c), seed, t, sigma);
+                           c->r, disp, c->slot, c->perm, c->dep_atomic, dep_out<float>(c), seed, t, sigma);
     else
         hipLaunchKernelGGL(k_pack_ions<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->q,
-                           c->r, disp, c->slot, c->perm, c->dep_atomic, buckets<double>(c), seed, t, sigma);
+                           c->r, disp, c->slot, c->perm, c->dep_atomic, dep_out<double>(c), seed, t, sigma);
     return hipGetLastError();
 }
 
@@ -357,7 +363,7 @@ struct IonStepArgs {
     double *dip_out;
     int *dep_atomic;  // [n] by slot: this step's ion left to the atomic path (read), the next step's (written)
     int pack;         // write the next step's records
-    Buckets<T> bk;
+    DepOut<T> out;
     double *rho;  // null: no charge spreading
     unsigned int *bad;
 };
@@ -371,10 +377,6 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
     const int i = live ? A.order[s] : 0;
     const bool forces = A.dip_prev != nullptr;
     double F[3] = {0.0, 0.0, 0.0}, P[3] = {0.0, 0.0, 0.0}, qi = 0.0;
-    int4 h = make_int4(-1, 0, 0, 0);
-    T val[3 * kConPerAxis];
-    int ids[8];
-    int nres = 0;
     if (!mover) {
         // lattice part and self force of r^n on D^n; the dipole term is added
         // at the end (x + 0 + y rounds as x + y)
@@ -434,13 +436,8 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
         if (A.rho) spread_ion(A.L, A.a, qi, u, A.rho);
         if (A.pack) {
             sanitize_move(dn, A.a, A.L, nullptr);
-            nres = make_record<T>(A.L, A.a, qi, u, dn, A.bk, h, val, ids);
+            A.dep_atomic[s] = write_record<T>(A.L, A.a, qi, u, dn, s, A.out) ? 1 : 0;
         }
-    }
-    if (mover && A.pack) {
-        // every lane of the two mover wavefronts takes part
-        const bool atomic_path = place_record<T>(nres, h, val, ids, A.bk);
-        if (live) A.dep_atomic[s] = atomic_path ? 1 : 0;
     }
     block_sum<3>(P);  // its barriers also publish Psh
     if (threadIdx.x == 0) {
@@ -492,14 +489,14 @@ hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const dou
     if (c->fp32) {
         IonStepArgs<float> A;
         fill(A, (const float *)Dcur, (float *)Dnext);
-        A.bk = buckets<float>(c);
+        A.out = dep_out<float>(c);
         A.eta_prof = (const float *)c->eta_prof;
         A.eta_link = (const float *)c->eta_link;
         hipLaunchKernelGGL(k_ion_step<float>, dim3(nb), dim3(kThreads), 0, c->stream, A);
     } else {
         IonStepArgs<double> A;
         fill(A, (const double *)Dcur, (double *)Dnext);
-        A.bk = buckets<double>(c);
+        A.out = dep_out<double>(c);
         A.eta_prof = (const double *)c->eta_prof;
         A.eta_link = (const double *)c->eta_link;
         hipLaunchKernelGGL(k_ion_step<double>, dim3(nb), dim3(kThreads), 0, c->stream, A);
@@ -821,6 +818,7 @@ __global__ void k_fill_int(int *dst, int v, size_t count) {
 
 hipError_t launch_bin_ions(memd_ctx *c, bool reorder) {
     if (c->n == 0 || !c->order) return hipSuccess;
+    c->lists_key = -1;  // slots and cells change: the fused deposit's lists are rebuilt before use
     const int nb = c->L * c->L;
     const int g = (int)((nb + kThreads - 1) / kThreads) < 4096 ? (nb + kThreads - 1) / kThreads : 4096;
     int *count = c->bins, *start = c->bins + nb, *cursor = c->bins + 2 * (size_t)nb;

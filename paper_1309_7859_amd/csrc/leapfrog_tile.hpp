@@ -47,24 +47,26 @@ __device__ __forceinline__ T eta_at(const LfArgs<T> &A, int d, int gz, size_t of
     }
 }
 
-// Ions for the deposit fused into the leapfrog.  An ion is "regular" when
-// every displacement component is shorter than a (so each axis of its
-// dimension-split move spans at most two cells); it then deposits only on
-// links whose origin lies within [c - 1, c + 2] per axis of its start cell
-// c.  The kernel that writes an ion's record (k_pack_ions or, one step
-// ahead, k_ion_step) appends it to the bucket of every leapfrog tile that
-// owns one of those links; a tile reads exactly its bucket.  Other ions
-// (irregular ones, and any whose bucket is full) are deposited by the ion
-// step after the leapfrog with global atomics.
+// Ions for the deposit fused into the leapfrog.  At every re-binning each
+// leapfrog tile gets the list of the ions whose cell c_b at that time lies
+// within two cells of a link it owns along each axis ([c_b - 2, c_b + 3]).
+// At each step an ion is "regular" when every displacement component is
+// shorter than a (so each axis of its dimension-split move spans at most
+// two cells) and its start cell c is within one cell of c_b along each axis:
+// then all its links have origins in [c - 1, c + 2], inside the boxes the
+// lists were built from, and the tiles listing it deposit it.  Other ions
+// (irregular ones, drifted ones, and any that did not fit a list) are
+// deposited by the ion step after the leapfrog with global atomics.
 //
-// A record: the head, with the start cell packed as x | y << 10 | z << 20
-// (-1 for an empty bucket entry), then one word per axis d of the move: the
-// corner of the 2 x 2 x 2 box of links it touches (the first cell along d,
-// the perpendicular cells c_d1, c_d2 of the position it moves from), packed
-// the same way, bit 30 set when the move crosses into a second cell along
-// d, bit 31 set when there is a move.  The values: slot 8d + 4 cell + 2 o2 +
-// o1 holds what is added to D_d at cell `cell` along d and c_d1 + o1,
-// c_d2 + o2 (each wrapped).  Lattices up to 1024 per side.
+// A record (one per ion, in slot order): the head, with the start cell
+// packed as x | y << 10 | z << 20 (-1: nothing for the tiles), then one word
+// per axis d of the move: the corner of the 2 x 2 x 2 box of links it
+// touches (the first cell along d, the perpendicular cells c_d1, c_d2 of
+// the position it moves from), packed the same way, bit 30 set when the
+// move crosses into a second cell along d, bit 31 set when there is a move.
+// The values: slot 8d + 4 cell + 2 o2 + o1 holds what is added to D_d at
+// cell `cell` along d and c_d1 + o1, c_d2 + o2 (each wrapped).  Lattices up
+// to 1024 per side.
 constexpr int kConPerAxis = 8;
 constexpr unsigned kGroupTwo = 1u << 30, kGroupOn = 1u << 31;
 
@@ -77,17 +79,17 @@ struct DepCon {
     T val[3 * kConPerAxis];
 };
 
-// The tile buckets: tile b (b = tile_x + ntx (tile_y + nty chunk)) owns
-// entries [b cap, b cap + min(count[b kCountStride], cap)); a tile resets
-// its count after reading it, so the next writer starts from zero.  Each
-// count sits in a 128-byte line of its own (writers add to them with
-// atomics).
+// The tile lists: tile b (b = tile_x + ntx (tile_y + nty chunk)) lists
+// the slots list[b cap, b cap + min(count[b kCountStride], cap)) (-1: an
+// entry to skip).  Each count sits in a 128-byte line of its own (the list
+// builder adds to them with atomics).
 constexpr int kCountStride = 32;
 
 struct DepArgs {
-    const int4 *head;  // [tiles * cap]
-    const void *con;   // [tiles * cap] DepCon<T>
-    int *count;        // [tiles * kCountStride]
+    const int4 *head;  // [n] by slot
+    const void *con;   // [n] DepCon<T> by slot
+    const int *list;   // [tiles * cap]
+    const int *count;  // [tiles * kCountStride]
     int cap;
 };
 
@@ -189,10 +191,10 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
     if constexpr (DEP) {
         // Deposit of the regular ions on the links this tile owns (x in
         // [x0, x0+64), y in [y0, y0+TY), z in [z0, z1)), accumulated in LDS
-        // from the tile's bucket.
-        const int bucket = tile_x + A.ntx * (tile_y + A.nty * chunk);
-        const size_t base = (size_t)bucket * dep->cap;
-        const int cnt = min(dep->count[(size_t)bucket * kCountStride], dep->cap);
+        // from the records of the ions on the tile's list.
+        const int tile = tile_x + A.ntx * (tile_y + A.nty * chunk);
+        const size_t base = (size_t)tile * dep->cap;
+        const int cnt = min(dep->count[(size_t)tile * kCountStride], dep->cap);
         T *accf = &DS->acc[0][0][0][0];
         for (int t = threadIdx.x; t < 3 * DTZ * TY * 64; t += blockDim.x) accf[t] = (T)0;
         const DepCon<T> *con = (const DepCon<T> *)dep->con;
@@ -203,7 +205,9 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         // tested once; each of the (up to) eight links then needs only those
         // flags.
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-            const int4 h = dep->head[base + e];
+            const int slot = dep->list[base + e];
+            if (slot < 0) continue;
+            const int4 h = dep->head[slot];
             if (h.x < 0) continue;
             constexpr int kWords = (int)sizeof(DepCon<T>) / 16;
             static_assert(sizeof(DepCon<T>) % 16 == 0, "record of whole 16-byte words");
@@ -211,7 +215,7 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
                 uint4 raw[kWords];
                 DepCon<T> rec;
             } cn;
-            const uint4 *src = reinterpret_cast<const uint4 *>(con + base + e);
+            const uint4 *src = reinterpret_cast<const uint4 *>(con + slot);
 #pragma unroll
             for (int q = 0; q < kWords; ++q) cn.raw[q] = src[q];
             const unsigned gw[3] = {(unsigned)h.y, (unsigned)h.z, (unsigned)h.w};
@@ -254,7 +258,6 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0) dep->count[(size_t)bucket * kCountStride] = 0;  // read by every lane before the barrier
     }
 
     T Dc[R][3], Dn[R][3], prevB[R][2];

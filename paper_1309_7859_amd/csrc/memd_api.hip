@@ -248,7 +248,8 @@ void memd_destroy(memd_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     prof_clear(c);
     void *bufs[] = {c->D[0], c->D[1], c->B[0], c->B[1], c->eta_prof, c->eta_link, c->q, c->r, c->F,
-                    c->order, c->slot, c->bins, c->binrow, c->bad_moves, c->dep_atomic, c->bk_head, c->bk_con, c->bk_count,
+                    c->order, c->slot, c->bins, c->binrow, c->bad_moves, c->dep_atomic, c->rec_head, c->rec_con, c->list,
+                    c->list_count, c->cbin, c->list_fail,
                     c->dip[0], c->dip[1],
                     c->perm, c->perm_alt, c->r_alt, c->q_alt, c->F_alt,
                     c->stage, c->rho, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt,
@@ -353,17 +354,21 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
         (void)hipGetLastError();
         return fail(MEMD_ENOMEM);
     }
-    // Tile buckets of the fused deposit, sized for the smallest fused tile
-    // shape (64 x 4 x 2): four entries per ion plus 64 per tile.
+    // Fused deposit: records by slot, and tile lists sized for the smallest
+    // fused tile shape (64 x 4 x 2): twelve entries per ion plus 64 per tile.
+    c->lists_key = -1;
     if (n > 0 && p->L >= 16 && p->L <= 1024) {
         const size_t L = (size_t)p->L;
         const size_t tiles = ((L + 63) / 64) * ((L + 3) / 4) * ((L + 1) / 2);
-        c->bk_tiles_max = (int)tiles;
-        c->bk_entries = 4 * nn + 64 * tiles;
+        c->list_tiles_max = (int)tiles;
+        c->list_entries = 12 * nn + 64 * tiles;
         const size_t rec = c->fp32 ? sizeof(DepCon<float>) : sizeof(DepCon<double>);
-        if (hipMalloc((void **)&c->bk_head, c->bk_entries * sizeof(int4)) != hipSuccess ||
-            hipMalloc(&c->bk_con, c->bk_entries * rec) != hipSuccess ||
-            hipMalloc((void **)&c->bk_count, tiles * kCountStride * sizeof(int)) != hipSuccess) {
+        if (hipMalloc((void **)&c->rec_head, nn * sizeof(int4)) != hipSuccess ||
+            hipMalloc(&c->rec_con, nn * rec) != hipSuccess ||
+            hipMalloc((void **)&c->list, c->list_entries * sizeof(int)) != hipSuccess ||
+            hipMalloc((void **)&c->list_count, tiles * kCountStride * sizeof(int)) != hipSuccess ||
+            hipMalloc((void **)&c->cbin, nn * sizeof(int)) != hipSuccess ||
+            hipMalloc((void **)&c->list_fail, nn * sizeof(int)) != hipSuccess) {
             (void)hipGetLastError();
             return fail(MEMD_ENOMEM);
         }

@@ -96,15 +96,16 @@ struct memd_ctx {
     int *perm_alt;
     int *bins;     // [3 L^2] bin counts, row starts, cursors
     int *binrow;   // [n] bin row of each ion at the last sort
-    // Tile buckets of the fused deposit (leapfrog_tile.hpp, DepArgs): bk_entries
-    // records (int4 head + values), shared by the tiles of the current tile
-    // shape, and a count per tile; dep_atomic[slot] marks an ion left to the
-    // atomic path for the step its record was written for.
-    int4 *bk_head;
-    void *bk_con;
-    int *bk_count;
-    size_t bk_entries;
-    int bk_tiles_max;
+    // Fused deposit (leapfrog_tile.hpp): records by slot (rec_head, rec_con),
+    // the tile lists built at re-binning for the tile shape lists_key
+    // (rows * 4096 + planes; -1: none), list_entries entries shared by the
+    // tiles, and per slot the cell at the build (cbin) and list_fail.
+    int4 *rec_head;
+    void *rec_con;
+    int *list, *list_count, *cbin, *list_fail;
+    size_t list_entries;
+    int list_tiles_max;
+    int lists_key;
     int *dep_atomic;
     unsigned int *bad_moves;  // rejected displacement components (not finite or > L a)
     bool fuse_deposit;
@@ -150,9 +151,11 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
                            uint64_t seed = 0, uint32_t t = 0, double sigma = 0.0, bool with_deposit = false,
                            bool need_pack = true);
 bool fused_deposit_ok(const memd_ctx *c);
-// Tiles of the current leapfrog tile shape, and the bucket capacity per tile.
-int bucket_tiles(const memd_ctx *c);
-int bucket_cap(const memd_ctx *c);
+// Tiles of the current leapfrog tile shape, and the list capacity per tile.
+int list_tiles(const memd_ctx *c);
+int list_cap(const memd_ctx *c);
+// Tile lists of the fused deposit for the current tile shape and positions.
+hipError_t launch_build_lists(memd_ctx *c);
 hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma);
 // The ion side of a step after the fused leapfrog (k_ion_step): forces of the
 // state the step started from (when dip_prev is set: the previous step's
