@@ -202,8 +202,9 @@ def main():
 
     lf_avg_s = r["lf_ms"] / 1e3 / max(r["lf_n"], 1)
     # the fused kernel also reads each ion's record once: a 16-byte head and
-    # 24 values in the field type
-    rec_bytes = 16 + 24 * (4 if fp32 else 8)
+    # the 12 first-cell values in the field type (the second cell's 12 only
+    # for a move that crosses a face)
+    rec_bytes = 16 + 12 * (4 if fp32 else 8)
     lf_bytes = leapfrog_bytes_per_site(fp32, True) * sites + (rec_bytes * w.n if r["fused"] else 0)
     achieved = lf_bytes / lf_avg_s / 1e9
     traffic = load_traffic(args.precision)

@@ -155,18 +155,18 @@ __device__ __forceinline__ bool write_record(int L, double a, double qi, const d
             // a regular move spans at most two cells along the axis
 #pragma unroll
             for (int cell = 0; cell < 2; ++cell) {
+                if (cell == 1 && !two) break;  // the second cell's values are only read when it is used
                 const double kc = cell ? khi : klo;
                 const double s0 = kc * a, s1 = (kc + 1.0) * a;
                 const double sa = lo_u > s0 ? lo_u : s0;
                 const double sb = hi_u < s1 ? hi_u : s1;
                 const double len = sb - sa;
-                const double amount =
-                    (cell == 0 || two) && len > 0.0 ? div_a(qi * sgn * div_a(len, a), a2) : 0.0;
+                const double amount = len > 0.0 ? div_a(qi * sgn * div_a(len, a), a2) : 0.0;
 #pragma unroll
                 for (int o2 = 0; o2 < 2; ++o2)
 #pragma unroll
                     for (int o1 = 0; o1 < 2; ++o1)
-                        o.val[kConPerAxis * d + 4 * cell + 2 * o2 + o1] = (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
+                        o.v[cell][4 * d + 2 * o2 + o1] = (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
             }
         }
         u[d] = u1;

@@ -64,20 +64,22 @@ __device__ __forceinline__ T eta_at(const LfArgs<T> &A, int d, int gz, size_t of
 // touches (the first cell along d, the perpendicular cells c_d1, c_d2 of
 // the position it moves from), packed the same way, bit 30 set when the
 // move crosses into a second cell along d, bit 31 set when there is a move.
-// The values: slot 8d + 4 cell + 2 o2 + o1 holds what is added to D_d at
-// cell `cell` along d and c_d1 + o1, c_d2 + o2 (each wrapped).  Lattices up
-// to 1024 per side.
-constexpr int kConPerAxis = 8;
+// The values: v[cell][4d + 2 o2 + o1] is what is added to D_d at cell
+// `cell` along d and c_d1 + o1, c_d2 + o2 (each wrapped).  Lattices up to
+// 1024 per side.
 constexpr unsigned kGroupTwo = 1u << 30, kGroupOn = 1u << 31;
 
 __device__ __forceinline__ int pack_cell(int x, int y, int z) { return x | (y << 10) | (z << 20); }
 
-// Values of a record: 96 bytes in FP32, 192 in FP64, read whole with 16-byte
-// loads.
+// Values of a record, read with 16-byte loads: those of the first cell of
+// every axis (48 bytes in FP32, 96 in FP64), and those of the second cell,
+// read only when a move crosses into one (bit 30 of an axis word).
 template <typename T>
 struct DepCon {
-    T val[3 * kConPerAxis];
+    T v[2][12];
 };
+template <typename T>
+constexpr int kCellWords = (int)(12 * sizeof(T) / 16);
 
 // The tile lists: tile b (b = tile_x + ntx (tile_y + nty chunk)) lists
 // the slots list[b cap, b cap + min(count[b kCountStride], cap)) (-1: an
@@ -188,77 +190,107 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         }
     };
 
+    // Deposit of the regular ions on the links this tile owns (x in
+    // [x0, x0+64), y in [y0, y0+TY), z in [z0, z1)), accumulated in LDS from
+    // the records of the ions on the tile's list.  Its two dependent memory
+    // round trips (list entries, then the listed records) are issued before
+    // and during the march prologue, whose plane loads and barriers they
+    // overlap; the records are decoded after the prologue, before the first
+    // plane's Ampere update reads the accumulator.
+    constexpr int kWords = kCellWords<T>;
+    static_assert(12 * sizeof(T) % 16 == 0, "values of a cell in whole 16-byte words");
+    constexpr int kPF = sizeof(T) == 4 ? 2 : 1;  // entries per thread prefetched
+    union RecRegs {
+        uint4 raw[kWords];
+        T v[12];
+    };
+    int pf_slot[kPF];
+    int4 pf_head[kPF];
+    RecRegs pf_con[kPF];
+    int dep_cnt = 0;
+    size_t dep_base = 0;
     if constexpr (DEP) {
-        // Deposit of the regular ions on the links this tile owns (x in
-        // [x0, x0+64), y in [y0, y0+TY), z in [z0, z1)), accumulated in LDS
-        // from the records of the ions on the tile's list.
         const int tile = tile_x + A.ntx * (tile_y + A.nty * chunk);
-        const size_t base = (size_t)tile * dep->cap;
-        const int cnt = min(dep->count[(size_t)tile * kCountStride], dep->cap);
+        dep_base = (size_t)tile * dep->cap;
+        dep_cnt = min(dep->count[(size_t)tile * kCountStride], dep->cap);
         T *accf = &DS->acc[0][0][0][0];
         for (int t = threadIdx.x; t < 3 * DTZ * TY * 64; t += blockDim.x) accf[t] = (T)0;
-        const DepCon<T> *con = (const DepCon<T> *)dep->con;
+        // list entries e < cap belong to this tile: read before the count is known
+#pragma unroll
+        for (int j = 0; j < kPF; ++j) {
+            const int e = (int)threadIdx.x + j * (int)blockDim.x;
+            pf_slot[j] = e < dep->cap ? dep->list[dep_base + e] : -1;
+        }
+    }
+    // Adds a record's values that fall on this tile's links to the
+    // accumulator.  Per axis group the two candidate coordinates along each
+    // axis are tested once; each of the (up to) eight links then needs only
+    // those flags.
+    // The second cell's values are loaded here when a move crosses a face.
+    auto deposit_rec = [&](const int4 &h, const RecRegs &c0v, int slot) {
+        // the links of an ion starting in cell c have origins in [c - 1,
+        // c + 2] per axis: skip a listed ion whose box misses the tile now
+        {
+            const int org3[3] = {x0, y0, z0};
+            const int ext3[3] = {TX, min(y0 + TY, L) - y0, z1 - z0};
+            bool meets = true;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                int off = ((h.x >> (10 * ax)) & 1023) - 1 - org3[ax];
+                off += off < 0 ? L : 0;
+                off -= off >= L ? L : 0;
+                meets = meets && (off < ext3[ax] || off + 3 >= L);
+            }
+            if (!meets) return;
+        }
+        const bool two = ((unsigned)h.y | (unsigned)h.z | (unsigned)h.w) & kGroupTwo;
+        RecRegs c1v;
+        if (two) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(&((const DepCon<T> *)dep->con)[slot].v[1][0]);
+#pragma unroll
+            for (int q = 0; q < kWords; ++q) c1v.raw[q] = src[q];
+        }
         const int org[3] = {x0, y0, z0};
         const int ext[3] = {TX, min(y0 + TY, L) - y0, z1 - z0};
-        __syncthreads();
-        // Per axis group the two candidate coordinates along each axis are
-        // tested once; each of the (up to) eight links then needs only those
-        // flags.
-        for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-            const int slot = dep->list[base + e];
-            if (slot < 0) continue;
-            const int4 h = dep->head[slot];
-            if (h.x < 0) continue;
-            constexpr int kWords = (int)sizeof(DepCon<T>) / 16;
-            static_assert(sizeof(DepCon<T>) % 16 == 0, "record of whole 16-byte words");
-            union {
-                uint4 raw[kWords];
-                DepCon<T> rec;
-            } cn;
-            const uint4 *src = reinterpret_cast<const uint4 *>(con + slot);
+        const unsigned gw[3] = {(unsigned)h.y, (unsigned)h.z, (unsigned)h.w};
 #pragma unroll
-            for (int q = 0; q < kWords; ++q) cn.raw[q] = src[q];
-            const unsigned gw[3] = {(unsigned)h.y, (unsigned)h.z, (unsigned)h.w};
+        for (int d = 0; d < 3; ++d) {
+            const unsigned g = gw[d];
+            if (!(g & kGroupOn)) continue;
+            const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+            int l0[3], l1[3];
+            bool i0[3], i1[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const unsigned g = gw[d];
-                if (!(g & kGroupOn)) continue;
-                const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-                int l0[3], l1[3];
-                bool i0[3], i1[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                const int v0 = (int)((g >> (10 * ax)) & 1023u);
+                const int v1 = v0 + 1 == L ? 0 : v0 + 1;
+                l0[ax] = v0 - org[ax];
+                l1[ax] = v1 - org[ax];
+                i0[ax] = (unsigned)l0[ax] < (unsigned)ext[ax];
+                i1[ax] = (unsigned)l1[ax] < (unsigned)ext[ax];
+            }
+            const int ncell = (g & kGroupTwo) ? 2 : 1;
 #pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    const int v0 = (int)((g >> (10 * ax)) & 1023u);
-                    const int v1 = v0 + 1 == L ? 0 : v0 + 1;
-                    l0[ax] = v0 - org[ax];
-                    l1[ax] = v1 - org[ax];
-                    i0[ax] = (unsigned)l0[ax] < (unsigned)ext[ax];
-                    i1[ax] = (unsigned)l1[ax] < (unsigned)ext[ax];
-                }
-                const int ncell = (g & kGroupTwo) ? 2 : 1;
+            for (int cell = 0; cell < 2; ++cell) {
+                if (cell >= ncell) break;
 #pragma unroll
-                for (int cell = 0; cell < 2; ++cell) {
-                    if (cell >= ncell) break;
+                for (int o2 = 0; o2 < 2; ++o2)
 #pragma unroll
-                    for (int o2 = 0; o2 < 2; ++o2)
-#pragma unroll
-                        for (int o1 = 0; o1 < 2; ++o1) {
-                            int sel[3];
-                            sel[d] = cell;
-                            sel[d1] = o1;
-                            sel[d2] = o2;
-                            const bool in = (sel[0] ? i1[0] : i0[0]) && (sel[1] ? i1[1] : i0[1]) &&
-                                            (sel[2] ? i1[2] : i0[2]);
-                            if (!in) continue;
-                            const int lxx = sel[0] ? l1[0] : l0[0], lyy = sel[1] ? l1[1] : l0[1],
-                                      lzz = sel[2] ? l1[2] : l0[2];
-                            atomicAdd(&DS->acc[d][lzz][lyy][lxx], cn.rec.val[kConPerAxis * d + 4 * cell + 2 * o2 + o1]);
-                        }
-                }
+                    for (int o1 = 0; o1 < 2; ++o1) {
+                        int sel[3];
+                        sel[d] = cell;
+                        sel[d1] = o1;
+                        sel[d2] = o2;
+                        const bool in = (sel[0] ? i1[0] : i0[0]) && (sel[1] ? i1[1] : i0[1]) &&
+                                        (sel[2] ? i1[2] : i0[2]);
+                        if (!in) continue;
+                        const int lxx = sel[0] ? l1[0] : l0[0], lyy = sel[1] ? l1[1] : l0[1],
+                                  lzz = sel[2] ? l1[2] : l0[2];
+                        atomicAdd(&DS->acc[d][lzz][lyy][lxx], (cell ? c1v.v : c0v.v)[4 * d + 2 * o2 + o1]);
+                    }
             }
         }
-        __syncthreads();
-    }
+    };
 
     T Dc[R][3], Dn[R][3], prevB[R][2];
 
@@ -268,6 +300,22 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         T dummy[R][3];
         load_plane(0, gzp, dummy);
         load_plane(1, z0, Dc);
+        if constexpr (DEP) {
+            // the list entries have arrived with the planes: issue the records
+            const DepCon<T> *con = (const DepCon<T> *)dep->con;
+#pragma unroll
+            for (int j = 0; j < kPF; ++j) {
+                const int e = (int)threadIdx.x + j * (int)blockDim.x;
+                if (e >= dep_cnt || pf_slot[j] < 0) {
+                    pf_slot[j] = -1;
+                    continue;
+                }
+                pf_head[j] = dep->head[pf_slot[j]];
+                const uint4 *src = reinterpret_cast<const uint4 *>(&con[pf_slot[j]].v[0][0]);
+#pragma unroll
+                for (int q = 0; q < kWords; ++q) pf_con[j].raw[q] = src[q];
+            }
+        }
         T bo[R][2];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -283,6 +331,25 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
                                            sX[1][1][yy][xx] + sX[0][1][yy][xx]);
             prevB[r][1] = bo[r][1] - kB * (sX[1][0][yy][xx] - sX[0][0][yy][xx] -
                                            sX[0][2][yy][xx + 1] + sX[0][2][yy][xx]);
+        }
+        if constexpr (DEP) {
+            // (the accumulator was cleared before the barrier above)
+#pragma unroll
+            for (int j = 0; j < kPF; ++j)
+                if (pf_slot[j] >= 0 && pf_head[j].x >= 0) deposit_rec(pf_head[j], pf_con[j], pf_slot[j]);
+            // entries beyond the prefetched ones, if any
+            const DepCon<T> *con = (const DepCon<T> *)dep->con;
+            for (int e = (int)threadIdx.x + kPF * (int)blockDim.x; e < dep_cnt; e += blockDim.x) {
+                const int slot = dep->list[dep_base + e];
+                if (slot < 0) continue;
+                const int4 h = dep->head[slot];
+                if (h.x < 0) continue;
+                RecRegs cn;
+                const uint4 *src = reinterpret_cast<const uint4 *>(&con[slot].v[0][0]);
+#pragma unroll
+                for (int q = 0; q < kWords; ++q) cn.raw[q] = src[q];
+                deposit_rec(h, cn, slot);
+            }
         }
         __syncthreads();
     }
