@@ -100,6 +100,7 @@ struct DepOut {
     DepCon<T> *con;
     const int *cbin;
     const int *list_fail;
+    double *du;  // [3n] by slot: the (sanitised) displacement the record was made for
 };
 
 // The record of one ion in slot s for the fused deposit (du already
@@ -112,6 +113,8 @@ struct DepOut {
 template <typename T>
 __device__ __forceinline__ bool write_record(int L, double a, double qi, const double (&u_in)[3],
                                              const double (&du)[3], int s, const DepOut<T> &O) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) O.du[3 * s + d] = du[d];
     double u[3] = {u_in[0], u_in[1], u_in[2]};
     int c0[3];
     {
@@ -177,13 +180,15 @@ __device__ __forceinline__ bool write_record(int L, double a, double qi, const d
 
 // Records for the step about to run, ions read in storage order
 // (coalesced), one lane per ion, ion i's record going to its slot
-// slot_of[i]; displacements are indexed by the caller's index perm[i].
+// slot_of[i]; displacements are indexed by the caller's index perm[i], and
+// rejected components are counted here (the ion step reads the sanitised
+// displacement back from the record's slot).
 template <typename T>
 __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const double *__restrict__ q,
                                                    const double *__restrict__ r, const double *__restrict__ disp,
                                                    const int *__restrict__ slot_of, const int *__restrict__ perm,
-                                                   int *__restrict__ dep_atomic, DepOut<T> O, uint64_t seed,
-                                                   uint32_t t, double sigma) {
+                                                   int *__restrict__ dep_atomic, DepOut<T> O, unsigned int *bad,
+                                                   uint64_t seed, uint32_t t, double sigma) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int ci = perm ? perm[i] : i;
@@ -196,7 +201,7 @@ __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const
     } else {
         philox_displacement(seed, t, (uint32_t)ci, sigma, du);
     }
-    sanitize_move(du, a, L, nullptr);
+    sanitize_move(du, a, L, bad);
     const int s = slot_of[i];
     dep_atomic[s] = write_record<T>(L, a, q[i], u, du, s, O) ? 1 : 0;
 }
@@ -208,6 +213,7 @@ static DepOut<T> dep_out(memd_ctx *c) {
     O.con = (DepCon<T> *)c->rec_con;
     O.cbin = c->cbin;
     O.list_fail = c->list_fail;
+    O.du = c->du_slot;
     return O;
 }
 
@@ -317,10 +323,12 @@ hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint
     const int nb = ion_blocks(c->n);
     if (c->fp32)
         hipLaunchKernelGGL(k_pack_ions<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->q,
-                           c->r, disp, c->slot, c->perm, c->dep_atomic, dep_out<float>(c), seed, t, sigma);
+                           c->r, disp, c->slot, c->perm, c->dep_atomic, dep_out<float>(c), c->bad_moves, seed, t,
+                           sigma);
     else
         hipLaunchKernelGGL(k_pack_ions<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->q,
-                           c->r, disp, c->slot, c->perm, c->dep_atomic, dep_out<double>(c), seed, t, sigma);
+                           c->r, disp, c->slot, c->perm, c->dep_atomic, dep_out<double>(c), c->bad_moves, seed, t,
+                           sigma);
     return hipGetLastError();
 }
 
@@ -348,7 +356,7 @@ struct IonStepArgs {
     double *r_out;
     const int *order;
     const int *perm;                 // storage index -> caller index (displacements), null: identity
-    const double *disp, *disp_next;  // null: Philox displacements of steps t and t + 1
+    const double *disp_next;  // null: the Philox displacements of step t + 1
     uint64_t seed;
     uint32_t t;
     double sigma;
@@ -406,13 +414,10 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
         const int ci = A.perm ? A.perm[i] : i;
         double u[3] = {A.r[3 * i], A.r[3 * i + 1], A.r[3 * i + 2]};
         qi = A.q[i];
-        double du[3], dn[3] = {0.0, 0.0, 0.0};
-        if (A.disp) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) du[d] = A.disp[3 * ci + d];
-        } else {
-            philox_displacement(A.seed, A.t, (uint32_t)ci, A.sigma, du);
-        }
+        // this step's displacement, sanitised and counted when its record was
+        // written; the next step's is gathered from the caller's order
+        double du[3] = {A.out.du[3 * s], A.out.du[3 * s + 1], A.out.du[3 * s + 2]};
+        double dn[3] = {0.0, 0.0, 0.0};
         if (A.pack) {
             if (A.disp_next) {
 #pragma unroll
@@ -421,7 +426,6 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
                 philox_displacement(A.seed, A.t + 1u, (uint32_t)ci, A.sigma, dn);
             }
         }
-        sanitize_move(du, A.a, A.L, A.bad);
         if (!A.dep_atomic[s]) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) u[d] = u[d] + du[d];
@@ -435,7 +439,7 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
         for (int d = 0; d < 3; ++d) P[d] = qi * u[d];
         if (A.rho) spread_ion(A.L, A.a, qi, u, A.rho);
         if (A.pack) {
-            sanitize_move(dn, A.a, A.L, nullptr);
+            sanitize_move(dn, A.a, A.L, A.bad);
             A.dep_atomic[s] = write_record<T>(A.L, A.a, qi, u, dn, s, A.out) ? 1 : 0;
         }
     }
@@ -451,7 +455,7 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
     }
 }
 
-hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const double *disp, const double *disp_next,
+hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const double *disp_next,
                            uint64_t seed, uint32_t t, double sigma, const double *dip_prev, int dip_prev_nblk,
                            double *dip_out, int *nblk, bool pack_next, bool spread_rho) {
     const int nb = ion_blocks_x8(c->n, kThreads / kIonStepIons);
@@ -467,7 +471,6 @@ hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const dou
         A.r_out = c->r_alt;
         A.order = c->order;
         A.perm = c->perm;
-        A.disp = disp;
         A.disp_next = disp_next;
         A.seed = seed;
         A.t = t;

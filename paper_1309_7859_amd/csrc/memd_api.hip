@@ -249,7 +249,7 @@ void memd_destroy(memd_ctx *c) {
     prof_clear(c);
     void *bufs[] = {c->D[0], c->D[1], c->B[0], c->B[1], c->eta_prof, c->eta_link, c->q, c->r, c->F,
                     c->order, c->slot, c->bins, c->binrow, c->bad_moves, c->dep_atomic, c->rec_head, c->rec_con, c->list,
-                    c->list_count, c->cbin, c->list_fail,
+                    c->list_count, c->cbin, c->list_fail, c->du_slot,
                     c->dip[0], c->dip[1],
                     c->perm, c->perm_alt, c->r_alt, c->q_alt, c->F_alt,
                     c->stage, c->rho, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt,
@@ -368,7 +368,8 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
             hipMalloc((void **)&c->list, c->list_entries * sizeof(int)) != hipSuccess ||
             hipMalloc((void **)&c->list_count, tiles * kCountStride * sizeof(int)) != hipSuccess ||
             hipMalloc((void **)&c->cbin, nn * sizeof(int)) != hipSuccess ||
-            hipMalloc((void **)&c->list_fail, nn * sizeof(int)) != hipSuccess) {
+            hipMalloc((void **)&c->list_fail, nn * sizeof(int)) != hipSuccess ||
+            hipMalloc((void **)&c->du_slot, 3 * nn * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             return fail(MEMD_ENOMEM);
         }
@@ -553,7 +554,7 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
                 t + 1 < nsteps && !(c->sort_every > 0 && next % c->sort_every == 0);
             double *dip_out = c->dip[c->step_index & 1];
             prof_begin(c, F_DEPOSIT);
-            CK(launch_ion_step(c, c->D[c->cur], c->D[nx], dstep, dd && pack_next ? dd + per * (t + 1) : nullptr,
+            CK(launch_ion_step(c, c->D[c->cur], c->D[nx], dd && pack_next ? dd + per * (t + 1) : nullptr,
                                seed, tstep, sigma, t > 0 ? dip_prev : nullptr, dip_nb, dip_out, &nb, pack_next,
                                audit_now));
             prof_end(c, F_DEPOSIT);

@@ -103,6 +103,7 @@ struct memd_ctx {
     int4 *rec_head;
     void *rec_con;
     int *list, *list_count, *cbin, *list_fail;
+    double *du_slot;  // [3n] by slot: the displacement each record was made for
     size_t list_entries;
     int list_tiles_max;
     int lists_key;
@@ -160,10 +161,11 @@ hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint
 // The ion side of a step after the fused leapfrog (k_ion_step): forces of the
 // state the step started from (when dip_prev is set: the previous step's
 // dipole partials), irregular ions deposited into Dnext with global atomics,
-// every position advanced, dipole partials into dip_out (nblk blocks), the
-// next step's deposit records (pack_next; displacements disp_next or the
-// Philox stream at t + 1) and rho for the audit (spread_rho).
-hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const double *disp, const double *disp_next,
+// every position advanced by the displacement stored with its record, dipole
+// partials into dip_out (nblk blocks), the next step's deposit records
+// (pack_next; displacements disp_next or the Philox stream at t + 1) and rho
+// for the audit (spread_rho).
+hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const double *disp_next,
                            uint64_t seed, uint32_t t, double sigma, const double *dip_prev, int dip_prev_nblk,
                            double *dip_out, int *nblk, bool pack_next, bool spread_rho);
 hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
