@@ -744,7 +744,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const int *__restrict__ count
 }
 
 __global__ void k_bin_scatter(int n, int L, double a, const double *__restrict__ r, int *__restrict__ cursor,
-                              int *__restrict__ order, int *__restrict__ slot_of, int *__restrict__ binrow) {
+                              int *__restrict__ order, int *__restrict__ slot_of) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int cy, cz;
@@ -755,7 +755,6 @@ __global__ void k_bin_scatter(int n, int L, double a, const double *__restrict__
     const int slot = atomicAdd(&cursor[row], 1);
     order[slot] = i;
     slot_of[i] = slot;
-    binrow[i] = row;
 }
 
 // Binning with the ion arrays moved into bin order: storage index j goes to
@@ -765,8 +764,7 @@ __global__ void k_bin_scatter(int n, int L, double a, const double *__restrict__
 __global__ void k_bin_reorder(int n, int L, double a, const double *__restrict__ r, const double *__restrict__ q,
                               const double *__restrict__ F, const int *__restrict__ perm, int *__restrict__ cursor,
                               double *__restrict__ r2, double *__restrict__ q2, double *__restrict__ F2,
-                              int *__restrict__ perm2, int *__restrict__ order, int *__restrict__ slot_of,
-                              int *__restrict__ binrow) {
+                              int *__restrict__ perm2, int *__restrict__ order, int *__restrict__ slot_of) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     int cy, cz;
@@ -784,7 +782,6 @@ __global__ void k_bin_reorder(int n, int L, double a, const double *__restrict__
     perm2[s] = perm[j];
     order[s] = s;
     slot_of[s] = s;
-    binrow[s] = row;
 }
 
 __global__ void k_iota(int *dst, int n) {
@@ -832,7 +829,7 @@ hipError_t launch_bin_ions(memd_ctx *c, bool reorder) {
     if (reorder) {
         hipLaunchKernelGGL(k_bin_reorder, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
                            c->r, c->q, c->F, c->perm, cursor, c->r_alt, c->q_alt, c->F_alt, c->perm_alt, c->order,
-                           c->slot, c->binrow);
+                           c->slot);
         std::swap(c->r, c->r_alt);
         std::swap(c->q, c->q_alt);
         std::swap(c->F, c->F_alt);
@@ -840,7 +837,7 @@ hipError_t launch_bin_ions(memd_ctx *c, bool reorder) {
         c->sorted = true;
     } else {
         hipLaunchKernelGGL(k_bin_scatter, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
-                           c->r, cursor, c->order, c->slot, c->binrow);
+                           c->r, cursor, c->order, c->slot);
     }
     return hipGetLastError();
 }

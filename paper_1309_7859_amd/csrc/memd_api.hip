@@ -248,7 +248,7 @@ void memd_destroy(memd_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     prof_clear(c);
     void *bufs[] = {c->D[0], c->D[1], c->B[0], c->B[1], c->eta_prof, c->eta_link, c->q, c->r, c->F,
-                    c->order, c->slot, c->bins, c->binrow, c->bad_moves, c->dep_atomic, c->rec_head, c->rec_con, c->list,
+                    c->order, c->slot, c->bins, c->bad_moves, c->dep_atomic, c->rec_head, c->rec_con, c->list,
                     c->list_count, c->cbin, c->list_fail, c->du_slot,
                     c->dip[0], c->dip[1],
                     c->perm, c->perm_alt, c->r_alt, c->q_alt, c->F_alt,
@@ -341,7 +341,6 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
         hipMalloc((void **)&c->q_alt, nn * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->F_alt, 3 * nn * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->bins, 3 * (size_t)p->L * p->L * sizeof(int)) != hipSuccess ||
-        hipMalloc((void **)&c->binrow, nn * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->dep_atomic, nn * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->bad_moves, sizeof(unsigned int)) != hipSuccess ||
         hipMalloc((void **)&c->rho, Ns * sizeof(double)) != hipSuccess ||

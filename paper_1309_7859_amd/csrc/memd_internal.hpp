@@ -95,7 +95,6 @@ struct memd_ctx {
     double *r_alt, *q_alt, *F_alt;  // targets of the re-binning's move
     int *perm_alt;
     int *bins;     // [3 L^2] bin counts, row starts, cursors
-    int *binrow;   // [n] bin row of each ion at the last sort
     // Fused deposit (leapfrog_tile.hpp): records by slot (rec_head, rec_con),
     // the tile lists built at re-binning for the tile shape lists_key
     // (rows * 4096 + planes; -1: none), list_entries entries shared by the
@@ -188,7 +187,7 @@ hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_
 hipError_t launch_spread(memd_ctx *c, const double *charges_or_null, double *dst);
 hipError_t launch_dipole(memd_ctx *c, double *partials, int *nblk);
 hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk);
-// Row binning of the ions (order, slot, binrow, row counts/starts); with
+// Row binning of the ions (order, slot, row counts/starts); with
 // reorder the ion arrays themselves move into bin order (see sorted).
 hipError_t launch_bin_ions(memd_ctx *c, bool reorder = false);
 hipError_t launch_iota(hipStream_t s, int *dst, int n);

@@ -410,6 +410,32 @@ def test_fused_deposit_with_stale_bins():
     run_parity(S, G, disp, {5, 25}, 1e-10, 1e-12, 1e-10, audit_each=True)
 
 
+@pytest.mark.parametrize("prec", [memd.FP32_MIXED, memd.FP64])
+def test_fused_deposit_list_overflow(prec):
+    """2000 ions packed into a 3 x 3 x 3 cell corner of a 32^3 lattice: the
+    tile lists there overflow their capacity, the ions that did not fit are
+    deposited by the atomic path, and the run still matches the oracle."""
+    L, n = 32, 2000
+    rng = np.random.default_rng(31)
+    r = 30.5 + rng.uniform(0, 3.0, size=(n, 3))  # wraps across the periodic corner
+    q = np.tile([1.0, -1.0], n // 2)
+    S, G = pair(L, q, r, dt=0.01, eps_min=10.0, precision=prec)
+    apply_eps(S, G, "uniform", 10.0)
+    S.initial_solve(1e-13)
+    share_state(S, G)
+    memd.memd_set_tiling(G.ctx, 1, 8 if prec == memd.FP32_MIXED else 4)
+    assert memd.memd_counters(G.ctx)[1] == 1
+    disp = rng.normal(0, 0.05, size=(40, n, 3))
+    ftol, gtol = (1e-10, 1e-12) if prec == memd.FP64 else (1e-4, 1e-5)
+    G.step(disp, 40)
+    for t in range(40):
+        S.step(disp[t])
+    assert G.gauss_residual()[0] <= gtol
+    Fo, _ = S.forces()
+    assert force_err(G.forces(), Fo) <= ftol
+    assert np.max(np.abs(G.state()[2] - S.r)) <= 1e-12 * np.max(np.abs(S.r))
+
+
 def test_rejected_moves_are_counted_and_taken_as_zero():
     L, n = 16, 40
     rng = np.random.default_rng(23)
