@@ -6,6 +6,7 @@
 #include <type_traits>
 
 #include "device_util.hpp"
+#include "ion_ops.hpp"
 #include "leapfrog_tile.hpp"
 #include "memd_internal.hpp"
 
@@ -117,6 +118,14 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
         P.list = c->list;
         P.count = c->list_count;
         P.cap = list_cap(c);
+        P.fq = c->fq;
+        P.ecell = c->ecell;
+        P.Ft = c->Ft;
+        P.fdone = c->fdone;
+        if (++c->force_tag == 0) c->force_tag = 1;  // 0 never marks a result
+        P.tag = c->force_tag;
+        P.G = c->scal + S_G;
+        P.a = c->a;
         dp = &P;
     }
     if (c->fp32) {
@@ -473,6 +482,46 @@ __global__ void k_salt_link(const double *__restrict__ nbar, int L, size_t Ns, d
     }
 }
 
+// ecell[c] = 12 / (sum of eta over the 12 edges of cell c): the d-links at
+// c + o1 e_d1 + o2 e_d2, summed in the order force_ion sums them.
+template <typename T>
+__global__ void k_ecell(int L, size_t Ns, EtaView<T> ev, T *__restrict__ out) {
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns; v += (size_t)gridDim.x * blockDim.x) {
+        const int c[3] = {(int)(v % L), (int)((v / L) % L), (int)(v / ((size_t)L * L))};
+        const int cp[3] = {c[0] + 1 == L ? 0 : c[0] + 1, c[1] + 1 == L ? 0 : c[1] + 1, c[2] + 1 == L ? 0 : c[2] + 1};
+        double sum = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+#pragma unroll
+            for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                for (int o1 = 0; o1 < 2; ++o1) {
+                    int x[3] = {c[0], c[1], c[2]};
+                    x[d1] = o1 ? cp[d1] : c[d1];
+                    x[d2] = o2 ? cp[d2] : c[d2];
+                    sum += ev.at(d, x[2], site_index(x[0], x[1], x[2], L), L, Ns);
+                }
+        }
+        out[v] = (T)(12.0 / sum);
+    }
+}
+
+hipError_t launch_ecell(memd_ctx *c) {
+    if (!c->ecell) return hipSuccess;
+    const int g = grid_for(c->Ns);
+    if (c->fp32) {
+        const EtaView<float> ev{c->eta_mode, c->eta_uni, (const float *)c->eta_prof, (const float *)c->eta_link};
+        hipLaunchKernelGGL(k_ecell<float>, dim3(g), dim3(kThreads), 0, c->stream, c->L, c->Ns, ev,
+                           (float *)c->ecell);
+    } else {
+        const EtaView<double> ev{c->eta_mode, c->eta_uni, (const double *)c->eta_prof, (const double *)c->eta_link};
+        hipLaunchKernelGGL(k_ecell<double>, dim3(g), dim3(kThreads), 0, c->stream, c->L, c->Ns, ev,
+                           (double *)c->ecell);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_salt(memd_ctx *c) {
     hipError_t e;
     const int g = grid_for(c->Ns);
@@ -491,6 +540,7 @@ hipError_t launch_salt(memd_ctx *c) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int nb = 0;
     if ((e = launch_eta_sums(c, c->partials, &nb)) != hipSuccess) return e;
+    if ((e = launch_ecell(c)) != hipSuccess) return e;
     return launch_finalize_epsh(c->stream, c->partials, nb, (double)c->Ns, c->scal + S_EPSH,
                                 c->scal + S_ETAMAX);
 }

@@ -101,6 +101,7 @@ struct DepOut {
     const int *cbin;
     const int *list_fail;
     double *du;  // [3n] by slot: the (sanitised) displacement the record was made for
+    IonFQ<T> *fq;  // [n] by slot: fractional position in the start cell and charge
 };
 
 // The record of one ion in slot s for the fused deposit (du already
@@ -117,11 +118,9 @@ __device__ __forceinline__ bool write_record(int L, double a, double qi, const d
     for (int d = 0; d < 3; ++d) O.du[3 * s + d] = du[d];
     double u[3] = {u_in[0], u_in[1], u_in[2]};
     int c0[3];
-    {
-        double f;
+    double f0[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) fold(u[d], a, L, c0[d], f);
-    }
+    for (int d = 0; d < 3; ++d) fold(u[d], a, L, c0[d], f0[d]);
     bool atomic_path = O.list_fail[s] != 0 || !ion_regular(a, u_in, du);
     const int cb = O.cbin[s];
 #pragma unroll
@@ -175,6 +174,12 @@ __device__ __forceinline__ bool write_record(int L, double a, double qi, const d
         u[d] = u1;
     }
     O.head[s] = make_int4(pack_cell(c0[0], c0[1], c0[2]), (int)g[0], (int)g[1], (int)g[2]);
+    IonFQ<T> fq;
+    fq.f[0] = (T)f0[0];
+    fq.f[1] = (T)f0[1];
+    fq.f[2] = (T)f0[2];
+    fq.q = (T)qi;
+    O.fq[s] = fq;
     return false;
 }
 
@@ -214,6 +219,7 @@ static DepOut<T> dep_out(memd_ctx *c) {
     O.cbin = c->cbin;
     O.list_fail = c->list_fail;
     O.du = c->du_slot;
+    O.fq = (IonFQ<T> *)c->fq;
     return O;
 }
 
@@ -366,8 +372,11 @@ struct IonStepArgs {
     double eta_uni;
     const T *eta_prof, *eta_link;
     double *scal, *F;
-    const double *dip_prev;  // null: no forces in this launch
+    const double *dip_prev;  // the previous ion step's dipole partials; null: P from the scalars
     int dip_prev_nblk;
+    const double *Ft;           // [3n] by slot: lattice part + self force from the leapfrog tiles
+    const unsigned int *fdone;  // [n] by slot: == tag when the tiles computed Ft
+    unsigned int tag;
     double *dip_out;
     int *dep_atomic;  // [n] by slot: this step's ion left to the atomic path (read), the next step's (written)
     int pack;         // write the next step's records
@@ -383,31 +392,41 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
     const int s = xcd_logical(blockIdx.x, gridDim.x) * kIonStepIons + (threadIdx.x & (kIonStepIons - 1));
     const bool live = s < A.n;
     const int i = live ? A.order[s] : 0;
-    const bool forces = A.dip_prev != nullptr;
     double F[3] = {0.0, 0.0, 0.0}, P[3] = {0.0, 0.0, 0.0}, qi = 0.0;
     if (!mover) {
-        // lattice part and self force of r^n on D^n; the dipole term is added
-        // at the end (x + 0 + y rounds as x + y)
-        if (live && forces) {
-            const double u[3] = {A.r[3 * i], A.r[3 * i + 1], A.r[3 * i + 2]};
+        // lattice part and self force of r^n on D^n (from the leapfrog tile
+        // that owns the ion's cell, else gathered here); the dipole term is
+        // added at the end (x + 0 + y rounds as x + y)
+        if (live) {
             qi = A.q[i];
-            const EtaView<T> ev{A.eta_mode, A.eta_uni, A.eta_prof, A.eta_link};
-            const double zero[3] = {0.0, 0.0, 0.0};
-            force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.Dcur, ev, A.scal + S_G, zero, A.scal + S_EPSH, F);
+            if (A.fdone[s] == A.tag) {
+                F[0] = A.Ft[3 * s];
+                F[1] = A.Ft[3 * s + 1];
+                F[2] = A.Ft[3 * s + 2];
+            } else {
+                const double u[3] = {A.r[3 * i], A.r[3 * i + 1], A.r[3 * i + 2]};
+                const EtaView<T> ev{A.eta_mode, A.eta_uni, A.eta_prof, A.eta_link};
+                const double zero[3] = {0.0, 0.0, 0.0};
+                force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.Dcur, ev, A.scal + S_G, zero, A.scal + S_EPSH, F);
+            }
         }
-        if (forces && threadIdx.x < 64) {
-            double ps[3] = {0.0, 0.0, 0.0};
-            for (int b = threadIdx.x; b < A.dip_prev_nblk; b += 64)
+        if (threadIdx.x < 64) {
+            if (A.dip_prev) {
+                double ps[3] = {0.0, 0.0, 0.0};
+                for (int b = threadIdx.x; b < A.dip_prev_nblk; b += 64)
 #pragma unroll
-                for (int d = 0; d < 3; ++d) ps[d] += A.dip_prev[3 * b + d];
+                    for (int d = 0; d < 3; ++d) ps[d] += A.dip_prev[3 * b + d];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) ps[d] = wave_sum(ps[d]);
-            if (threadIdx.x == 0) {
+                for (int d = 0; d < 3; ++d) ps[d] = wave_sum(ps[d]);
+                if (threadIdx.x == 0) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    Psh[d] = ps[d];
-                    if (blockIdx.x == 0) A.scal[S_P + d] = ps[d];
+                    for (int d = 0; d < 3; ++d) {
+                        Psh[d] = ps[d];
+                        if (blockIdx.x == 0) A.scal[S_P + d] = ps[d];
+                    }
                 }
+            } else if (threadIdx.x < 3) {
+                Psh[threadIdx.x] = A.scal[S_P + threadIdx.x];
             }
         }
     } else if (live) {
@@ -449,7 +468,7 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
         A.dip_out[3 * blockIdx.x + 1] = P[1];
         A.dip_out[3 * blockIdx.x + 2] = P[2];
     }
-    if (!mover && live && forces) {
+    if (!mover && live) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) A.F[3 * i + d] = F[d] + qi * Psh[d] / (A.V * A.scal[S_EPSH + d]);
     }
@@ -483,6 +502,9 @@ hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const dou
         A.F = c->F;
         A.dip_prev = dip_prev;
         A.dip_prev_nblk = dip_prev_nblk;
+        A.Ft = c->Ft;
+        A.fdone = c->fdone;
+        A.tag = c->force_tag;
         A.dip_out = dip_out;
         A.dep_atomic = c->dep_atomic;
         A.pack = pack_next ? 1 : 0;

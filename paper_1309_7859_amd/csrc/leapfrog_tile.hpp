@@ -87,12 +87,30 @@ constexpr int kCellWords = (int)(12 * sizeof(T) / 16);
 // builder adds to them with atomics).
 constexpr int kCountStride = 32;
 
+// Per slot: the fractional position of the ion in its start cell and its
+// charge, for the forces the tiles compute (field type).
+template <typename T>
+struct IonFQ {
+    T f[3];
+    T q;
+};
+
 struct DepArgs {
     const int4 *head;  // [n] by slot
     const void *con;   // [n] DepCon<T> by slot
     const int *list;   // [tiles * cap]
     const int *count;  // [tiles * kCountStride]
     int cap;
+    // forces of the state the step starts from, for the regular ions whose
+    // start cell the tile owns: lattice part and self force into Ft[slot],
+    // fdone[slot] = tag (the dipole term is added by the ion step)
+    const void *fq;     // [n] IonFQ<T> by slot
+    const void *ecell;  // [Ns] T: 12 / (sum of eta over the cell's 12 edges)
+    double *Ft;         // [3n] by slot
+    unsigned int *fdone;
+    unsigned int tag;
+    const double *G;    // lattice Green's-function table G(0..3)
+    double a;
 };
 
 // Planes per z-chunk when the deposit is fused: up to 4, or up to 8 for the
@@ -114,9 +132,16 @@ __device__ __forceinline__ bool ion_regular(double a, const double (&u)[3], cons
     return true;
 }
 
+// Tile LDS of the fused deposit: the accumulator, and the ions whose start
+// cell the tile owns (slot, and the cell packed as lx | ly << 8 | lz << 16),
+// one per thread at most (ions past 256 get their forces in the ion step).
+constexpr int kOwnCap = 256;
+
 template <typename T, int R, int TZ = kDepTZ>
 struct DepSmem {
     T acc[3][TZ][4 * R][64];
+    int own_n;
+    int2 own[kOwnCap];
 };
 
 // LDS of one tile: eta*D of two planes with a one-site halo, new B of one
@@ -215,6 +240,7 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         dep_cnt = min(dep->count[(size_t)tile * kCountStride], dep->cap);
         T *accf = &DS->acc[0][0][0][0];
         for (int t = threadIdx.x; t < 3 * DTZ * TY * 64; t += blockDim.x) accf[t] = (T)0;
+        if (threadIdx.x == 0) DS->own_n = 0;
         // list entries e < cap belong to this tile: read before the count is known
 #pragma unroll
         for (int j = 0; j < kPF; ++j) {
@@ -228,6 +254,14 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
     // those flags.
     // The second cell's values are loaded here when a move crosses a face.
     auto deposit_rec = [&](const int4 &h, const RecRegs &c0v, int slot) {
+        {
+            // an ion whose start cell lies in the tile gets its force here
+            const int lxo = (h.x & 1023) - x0, lyo = ((h.x >> 10) & 1023) - y0, lzo = ((h.x >> 20) & 1023) - z0;
+            if (lxo >= 0 && lxo < TX && lyo >= 0 && lyo < min(y0 + TY, L) - y0 && lzo >= 0 && lzo < z1 - z0) {
+                const int pos = atomicAdd(&DS->own_n, 1);
+                if (pos < kOwnCap) DS->own[pos] = make_int2(slot, lxo | (lyo << 8) | (lzo << 16));
+            }
+        }
         // the links of an ion starting in cell c have origins in [c - 1,
         // c + 2] per axis: skip a listed ion whose box misses the tile now
         {
@@ -354,6 +388,25 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         __syncthreads();
     }
 
+    // The force of the owned ion this thread takes (loaded now, computed when
+    // the march has the planes of its cell in LDS).
+    int own_slot = -1, own_cell = 0, own_lz = -1;
+    IonFQ<T> own_fq{};
+    T own_ec = (T)1;
+    T own_X[12];
+    if constexpr (DEP) {
+        if ((int)threadIdx.x < min(DS->own_n, kOwnCap)) {
+            const int2 o = DS->own[threadIdx.x];
+            own_slot = o.x;
+            own_cell = o.y;
+            own_lz = o.y >> 16;
+            own_fq = ((const IonFQ<T> *)dep->fq)[own_slot];
+            const size_t site = (size_t)(x0 + (o.y & 255)) +
+                                (size_t)L * ((size_t)(y0 + ((o.y >> 8) & 255)) + (size_t)L * (z0 + own_lz));
+            own_ec = ((const T *)dep->ecell)[site];
+        }
+    }
+
     int cur = 1;
     for (int k = z0; k < z1; ++k) {
         const int nxt = cur ^ 1;
@@ -413,6 +466,27 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             sB[2][yy][0] = hb1 - kB * (sX[cur][1][yy][1] - sX[cur][1][yy][0] -
                                        sX[cur][0][yy + 1][0] + sX[cur][0][yy][0]);
         }
+        if constexpr (DEP) {
+            // The owned ion in plane k: capture E = eta D on its cell's 12
+            // links (planes k and k+1, rows and columns with the +1 halo, in
+            // force_ion's order); its force is computed after the march.
+            if (own_lz == k - z0) {
+                const int rr = ((own_cell >> 8) & 255) + 1, cc = (own_cell & 255) + 1;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+#pragma unroll
+                    for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                        for (int o1 = 0; o1 < 2; ++o1) {
+                            int ox[3] = {0, 0, 0};
+                            ox[d1] = o1;
+                            ox[d2] = o2;
+                            own_X[4 * d + 2 * o2 + o1] = sX[ox[2] ? nxt : cur][d][rr + ox[1]][cc + ox[0]];
+                        }
+                }
+            }
+        }
         __syncthreads();
 
         // Ampere: new D on the own sites
@@ -441,6 +515,34 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             for (int d = 0; d < 3; ++d) Dc[r][d] = Dn[r][d];
         }
         cur = nxt;
+    }
+
+    if constexpr (DEP) {
+        // Force of the owned ion: lattice part from the captured E, as
+        // force_ion sums it, then the self force (the dipole term is added by
+        // the ion step).
+        if (own_slot >= 0) {
+            const double f[3] = {(double)own_fq.f[0], (double)own_fq.f[1], (double)own_fq.f[2]};
+            const double q = (double)own_fq.q;
+            double Fl[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+                double sum = 0.0;
+#pragma unroll
+                for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                    for (int o1 = 0; o1 < 2; ++o1)
+                        sum += lin_w(o1, f[d1]) * lin_w(o2, f[d2]) * (double)own_X[4 * d + 2 * o2 + o1];
+                Fl[d] = q * sum;
+            }
+            double S, dS[3];
+            self_sum(dep->G, f, S, dS);
+            const double pref = q * q / (2.0 * (double)own_ec * dep->a);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) dep->Ft[3 * (size_t)own_slot + d] = Fl[d] - div_a(-pref * dS[d], dep->a);
+            dep->fdone[own_slot] = dep->tag;
+        }
     }
 }
 

@@ -176,6 +176,7 @@ memd_status finish_permittivity(memd_ctx *c) {
 memd_status refresh_eta(memd_ctx *c) {
     int nb = 0;
     CK(launch_eta_sums(c, c->partials, &nb));
+    CK(launch_ecell(c));
     CK(launch_finalize_epsh(c->stream, c->partials, nb, (double)c->Ns, c->scal + S_EPSH, c->scal + S_ETAMAX));
     return finish_permittivity(c);
 }
@@ -249,7 +250,7 @@ void memd_destroy(memd_ctx *c) {
     prof_clear(c);
     void *bufs[] = {c->D[0], c->D[1], c->B[0], c->B[1], c->eta_prof, c->eta_link, c->q, c->r, c->F,
                     c->order, c->slot, c->bins, c->bad_moves, c->dep_atomic, c->rec_head, c->rec_con, c->list,
-                    c->list_count, c->cbin, c->list_fail, c->du_slot,
+                    c->list_count, c->cbin, c->list_fail, c->du_slot, c->fq, c->ecell, c->Ft, c->fdone,
                     c->dip[0], c->dip[1],
                     c->perm, c->perm_alt, c->r_alt, c->q_alt, c->F_alt,
                     c->stage, c->rho, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt,
@@ -368,12 +369,17 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
             hipMalloc((void **)&c->list_count, tiles * kCountStride * sizeof(int)) != hipSuccess ||
             hipMalloc((void **)&c->cbin, nn * sizeof(int)) != hipSuccess ||
             hipMalloc((void **)&c->list_fail, nn * sizeof(int)) != hipSuccess ||
-            hipMalloc((void **)&c->du_slot, 3 * nn * sizeof(double)) != hipSuccess) {
+            hipMalloc((void **)&c->du_slot, 3 * nn * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->fq, nn * (c->fp32 ? sizeof(IonFQ<float>) : sizeof(IonFQ<double>))) != hipSuccess ||
+            hipMalloc(&c->ecell, Ns * c->tsize) != hipSuccess ||
+            hipMalloc((void **)&c->Ft, 3 * nn * sizeof(double)) != hipSuccess ||
+            hipMalloc((void **)&c->fdone, nn * sizeof(unsigned int)) != hipSuccess) {
             (void)hipGetLastError();
             return fail(MEMD_ENOMEM);
         }
     }
     hipStream_t s = c->stream;
+    if (c->fdone) hipMemsetAsync(c->fdone, 0, nn * sizeof(unsigned int), s);  // no launch is stamped 0
     for (int b = 0; b < 2; ++b) {
         hipMemsetAsync(c->D[b], 0, fb, s);
         hipMemsetAsync(c->B[b], 0, fb, s);

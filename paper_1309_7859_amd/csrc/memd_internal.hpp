@@ -103,6 +103,14 @@ struct memd_ctx {
     void *rec_con;
     int *list, *list_count, *cbin, *list_fail;
     double *du_slot;  // [3n] by slot: the displacement each record was made for
+    // Forces computed by the leapfrog tiles (DepArgs): fractional positions
+    // and charges by slot (fq), 12 / (sum of the cell's 12 eta) per site
+    // (ecell), the tile results by slot (Ft) with their launch stamp (fdone,
+    // compared with force_tag, which every fused leapfrog launch advances).
+    void *fq, *ecell;
+    double *Ft;
+    unsigned int *fdone;
+    unsigned int force_tag;
     size_t list_entries;
     int list_tiles_max;
     int lists_key;
@@ -156,6 +164,9 @@ int list_tiles(const memd_ctx *c);
 int list_cap(const memd_ctx *c);
 // Tile lists of the fused deposit for the current tile shape and positions.
 hipError_t launch_build_lists(memd_ctx *c);
+// 12 / (sum of eta over each cell's 12 edges), after any permittivity change
+// (no-op when the context has no fused deposit).
+hipError_t launch_ecell(memd_ctx *c);
 hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma);
 // The ion side of a step after the fused leapfrog (k_ion_step): forces of the
 // state the step started from (when dip_prev is set: the previous step's
