@@ -203,8 +203,11 @@ def main():
     lf_avg_s = r["lf_ms"] / 1e3 / max(r["lf_n"], 1)
     # the fused kernel also reads each ion's record once: a 16-byte head and
     # the 12 first-cell values in the field type (the second cell's 12 only
-    # for a move that crosses a face)
-    rec_bytes = 16 + 12 * (4 if fp32 else 8)
+    # for a move that crosses a face); for the forces it computes it reads the
+    # fractional position and charge (4 values) and 12/sum(eta) of the cell,
+    # and writes three FP64 force components and a 4-byte stamp
+    tsz = 4 if fp32 else 8
+    rec_bytes = 16 + 12 * tsz + 5 * tsz + 24 + 4
     lf_bytes = leapfrog_bytes_per_site(fp32, True) * sites + (rec_bytes * w.n if r["fused"] else 0)
     achieved = lf_bytes / lf_avg_s / 1e9
     traffic = load_traffic(args.precision)
