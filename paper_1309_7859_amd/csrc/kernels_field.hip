@@ -98,7 +98,7 @@ bool fused_deposit_ok(const memd_ctx *c) {
 
 hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout, hipEvent_t e0,
                            hipEvent_t e1, const double *disp, uint64_t seed, uint32_t t, double sigma,
-                           bool with_deposit, bool need_pack) {
+                           bool with_deposit, bool need_pack, const double *dip_prev, int dip_nparts) {
     DepArgs P;
     const DepArgs *dp = nullptr;
     if (with_deposit) {
@@ -126,6 +126,9 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
         P.tag = c->force_tag;
         P.G = c->scal + S_G;
         P.a = c->a;
+        P.dip_prev = dip_prev;
+        P.dip_nparts = dip_nparts;
+        P.P = c->scal + S_P;
         dp = &P;
     }
     if (c->fp32) {

