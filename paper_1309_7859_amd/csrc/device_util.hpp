@@ -65,6 +65,29 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// Per-thread sums of W-vectors p[W b .. W b + W) over b = first, first +
+// stride, ... < n, in increasing b (eight vectors' loads in flight per pass).
+template <int W>
+__device__ __forceinline__ void strided_sum(const double *__restrict__ p, int n, int first, int stride,
+                                            double (&s)[W]) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) s[w] = 0.0;
+    for (int b0 = first; b0 < n; b0 += 8 * stride) {
+        double v[8][W];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + u * stride;
+#pragma unroll
+            for (int w = 0; w < W; ++w) v[u][w] = b < n ? p[W * b + w] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                if (b0 + u * stride < n) s[w] += v[u][w];
+    }
+}
+
 // Block-wide sums of N values (blockDim.x a multiple of 64, <= 1024).  The
 // result is returned to every thread; the summation order is fixed.
 template <int N>

@@ -114,7 +114,8 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
             if (e != hipSuccess) return e;
         }
         P.head = c->rec_head;
-        P.con = c->rec_con;
+        P.con0 = c->rec_con;
+        P.con1 = c->rec_con1;
         P.list = c->list;
         P.count = c->list_count;
         P.cap = list_cap(c);

@@ -97,7 +97,7 @@ __global__ void k_fill_int(int *dst, int v, size_t count);
 template <typename T>
 struct DepOut {
     int4 *head;
-    DepCon<T> *con;
+    DepCell<T> *con0, *con1;
     const int *cbin;
     const int *list_fail;
     double *du;  // [3n] by slot: the (sanitised) displacement the record was made for
@@ -134,7 +134,6 @@ __device__ __forceinline__ bool write_record(int L, double a, double qi, const d
         return true;
     }
     const double a2 = a * a;
-    DepCon<T> &o = O.con[s];
     unsigned int g[3] = {0u, 0u, 0u};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -168,7 +167,8 @@ __device__ __forceinline__ bool write_record(int L, double a, double qi, const d
                 for (int o2 = 0; o2 < 2; ++o2)
 #pragma unroll
                     for (int o1 = 0; o1 < 2; ++o1)
-                        o.v[cell][4 * d + 2 * o2 + o1] = (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
+                        (cell ? O.con1 : O.con0)[s].v[4 * d + 2 * o2 + o1] =
+                            (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
             }
         }
         u[d] = u1;
@@ -215,7 +215,8 @@ template <typename T>
 static DepOut<T> dep_out(memd_ctx *c) {
     DepOut<T> O;
     O.head = c->rec_head;
-    O.con = (DepCon<T> *)c->rec_con;
+    O.con0 = (DepCell<T> *)c->rec_con;
+    O.con1 = (DepCell<T> *)c->rec_con1;
     O.cbin = c->cbin;
     O.list_fail = c->list_fail;
     O.du = c->du_slot;
@@ -579,9 +580,9 @@ struct ForceArgs {
 
 // Forces on every ion, one lane per ion following `order` (force_ion: the
 // lattice part from the 12 links of the cell, self force, dipole
-// correction).  With dip_partials set, wavefront 0 of every block sums the
-// deposit's per-block q r partials into P (in a fixed order; block 0 also
-// stores it) while the other lanes' loads are in flight.
+// correction).  With dip_partials set, every block sums the per-wavefront
+// q r partials of the last ion step into P (in the dipole finaliser's order;
+// block 0 also stores it) while its force gathers are in flight.
 template <typename T>
 __global__ __launch_bounds__(256) void k_forces(ForceArgs<T> A) {
     __shared__ double Psh[3];
@@ -603,24 +604,17 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs<T> A) {
         const double zero[3] = {0.0, 0.0, 0.0};
         us = force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.D, ev, A.scal + S_G, zero, A.scal + S_EPSH, F);
     }
-    if (threadIdx.x < 64) {
-        if (A.dip_partials) {
-            double s[3] = {0.0, 0.0, 0.0};
-            for (int b = threadIdx.x; b < A.dip_nblk; b += 64)
-#pragma unroll
-                for (int d = 0; d < 3; ++d) s[d] += A.dip_partials[3 * b + d];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) s[d] = wave_sum(s[d]);
-            if (threadIdx.x == 0) {
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    Psh[d] = s[d];
-                    if (blockIdx.x == 0) A.scal[S_P + d] = s[d];
-                }
-            }
-        } else if (threadIdx.x < 3) {
-            Psh[threadIdx.x] = A.scal[S_P + threadIdx.x];
+    if (A.dip_partials) {
+        // P summed as the dipole finaliser sums it (fin_sum)
+        double s[3];
+        strided_sum<3>(A.dip_partials, A.dip_nblk, threadIdx.x, blockDim.x, s);
+        block_sum<3>(s);
+        if (threadIdx.x < 3) {
+            Psh[threadIdx.x] = s[threadIdx.x];
+            if (blockIdx.x == 0) A.scal[S_P + threadIdx.x] = s[threadIdx.x];
         }
+    } else if (threadIdx.x < 3) {
+        Psh[threadIdx.x] = A.scal[S_P + threadIdx.x];
     }
     __syncthreads();
     if (live) {
@@ -874,11 +868,7 @@ hipError_t launch_uself(memd_ctx *c, double *partials, int *nblk) {
 // order is fixed, so results repeat bit for bit.
 template <int W>
 __device__ void fin_sum(const double *partials, int nblk, double (&out)[W]) {
-#pragma unroll
-    for (int w = 0; w < W; ++w) out[w] = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-#pragma unroll
-        for (int w = 0; w < W; ++w) out[w] += partials[W * b + w];
+    strided_sum<W>(partials, nblk, threadIdx.x, blockDim.x, out);
     block_sum<W>(out);
 }
 

@@ -18,6 +18,8 @@
 #include "memd_internal.hpp"
 #include "philox.hpp"
 
+#include <type_traits>
+
 namespace memd {
 
 template <typename T>
@@ -64,19 +66,21 @@ __device__ __forceinline__ T eta_at(const LfArgs<T> &A, int d, int gz, size_t of
 // touches (the first cell along d, the perpendicular cells c_d1, c_d2 of
 // the position it moves from), packed the same way, bit 30 set when the
 // move crosses into a second cell along d, bit 31 set when there is a move.
-// The values: v[cell][4d + 2 o2 + o1] is what is added to D_d at cell
-// `cell` along d and c_d1 + o1, c_d2 + o2 (each wrapped).  Lattices up to
+// The values, one array per cell along d: v[4d + 2 o2 + o1] of slot s in
+// the first (second) array is what is added to D_d at the first (second)
+// cell along d and c_d1 + o1, c_d2 + o2 (each wrapped).  Lattices up to
 // 1024 per side.
 constexpr unsigned kGroupTwo = 1u << 30, kGroupOn = 1u << 31;
 
 __device__ __forceinline__ int pack_cell(int x, int y, int z) { return x | (y << 10) | (z << 20); }
 
-// Values of a record, read with 16-byte loads: those of the first cell of
-// every axis (48 bytes in FP32, 96 in FP64), and those of the second cell,
-// read only when a move crosses into one (bit 30 of an axis word).
+// Values of one cell of a record, read with 16-byte loads (48 bytes in FP32,
+// 96 in FP64).  The first cells of consecutive slots are contiguous; the
+// second cells sit in an array of their own, read only when a move crosses
+// into one (bit 30 of an axis word).
 template <typename T>
-struct DepCon {
-    T v[2][12];
+struct DepCell {
+    T v[12];
 };
 template <typename T>
 constexpr int kCellWords = (int)(12 * sizeof(T) / 16);
@@ -97,7 +101,8 @@ struct IonFQ {
 
 struct DepArgs {
     const int4 *head;  // [n] by slot
-    const void *con;   // [n] DepCon<T> by slot
+    const void *con0;  // [n] DepCell<T> by slot: first cells
+    const void *con1;  // [n] DepCell<T> by slot: second cells
     const int *list;   // [tiles * cap]
     const int *count;  // [tiles * kCountStride]
     int cap;
@@ -112,7 +117,7 @@ struct DepArgs {
     const double *G;    // lattice Green's-function table G(0..3)
     double a;
     // the previous ion step's dipole partials (nparts x 3; null: none), summed
-    // in a fixed order by wavefront 0 of block 0 into P (the scalars)
+    // by block 0 into P (the scalars) in the dipole finaliser's order
     const double *dip_prev;
     int dip_nparts;
     double *P;
@@ -144,7 +149,8 @@ constexpr int kOwnCap = 256;
 
 template <typename T, int R, int TZ = kDepTZ>
 struct DepSmem {
-    T acc[3][TZ][4 * R][64];
+    alignas(16) T acc[3][TZ][4 * R][64];
+    double psum[3][4];  // block 0: wavefront sums of the dipole partials
     int own_n;
     int2 own[kOwnCap];
 };
@@ -187,46 +193,65 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         act[r] = xact && (y0 + wy + 4 * r) < L;
     }
 
-    // Stage eta*D of plane gz into sX[buf] (own sites, halo rows and columns);
-    // own D values go to Dreg.
-    auto load_plane = [&](int buf, int gz, T (&Dreg)[R][3]) {
+    // A plane of eta*D in flight: the own sites' D and eta, and the one halo
+    // site this thread stages (rows y0-1 and y0+TY on waves 0-1, columns
+    // x0-1 and x0+64 on waves 2-3).  Fetching only issues the loads;
+    // storing waits for them and writes eta*D into sX[buf].
+    struct PlaneRegs {
+        T d[R][3], e[R][3], hd[3], he[3];
+    };
+    auto fetch_plane = [&](int gz, PlaneRegs &p) {
         const size_t zoff = (size_t)gz * LL;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const size_t off = zoff + (size_t)gyo[r] * L + gx;
-            const int yy = wy + 4 * r + 1;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const T v = A.Din[(size_t)d * Ns + off];
-                Dreg[r][d] = v;
-                sX[buf][d][yy][xx] = eta_at<T, EM>(A, d, gz, off) * v;
+                p.d[r][d] = A.Din[(size_t)d * Ns + off];
+                p.e[r][d] = eta_at<T, EM>(A, d, gz, off);
             }
+        }
+        size_t off = 0;
+        bool halo = true;
+        if (wy < 2) {
+            off = zoff + (size_t)wrapc(y0 - 1 + (wy ? TY + 1 : 0), L) * L + gx;
+        } else if (lx < TY + 2) {
+            off = zoff + (size_t)wrapc(y0 - 1 + lx, L) * L + wrapc(x0 - 1 + ((wy == 2) ? 0 : TX + 1), L);
+        } else {
+            halo = false;
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            p.hd[d] = halo ? A.Din[(size_t)d * Ns + off] : (T)0;
+            p.he[d] = halo ? eta_at<T, EM>(A, d, gz, off) : (T)0;
+        }
+    };
+    auto store_plane = [&](int buf, const PlaneRegs &p) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int yy = wy + 4 * r + 1;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sX[buf][d][yy][xx] = p.e[r][d] * p.d[r][d];
         }
         if (wy < 2) {
             const int yy = wy ? TY + 1 : 0;
-            const int gy = wrapc(y0 - 1 + yy, L);
-            const size_t off = zoff + (size_t)gy * L + gx;
 #pragma unroll
-            for (int d = 0; d < 3; ++d)
-                sX[buf][d][yy][xx] = eta_at<T, EM>(A, d, gz, off) * A.Din[(size_t)d * Ns + off];
+            for (int d = 0; d < 3; ++d) sX[buf][d][yy][xx] = p.he[d] * p.hd[d];
         } else if (lx < TY + 2) {
             const int xc = (wy == 2) ? 0 : TX + 1;
-            const int gxx = wrapc(x0 - 1 + xc, L);
-            const int gy = wrapc(y0 - 1 + lx, L);
-            const size_t off = zoff + (size_t)gy * L + gxx;
 #pragma unroll
-            for (int d = 0; d < 3; ++d)
-                sX[buf][d][lx][xc] = eta_at<T, EM>(A, d, gz, off) * A.Din[(size_t)d * Ns + off];
+            for (int d = 0; d < 3; ++d) sX[buf][d][lx][xc] = p.he[d] * p.hd[d];
         }
     };
 
     // Deposit of the regular ions on the links this tile owns (x in
     // [x0, x0+64), y in [y0, y0+TY), z in [z0, z1)), accumulated in LDS from
-    // the records of the ions on the tile's list.  Its two dependent memory
-    // round trips (list entries, then the listed records) are issued before
-    // and during the march prologue, whose plane loads and barriers they
-    // overlap; the records are decoded after the prologue, before the first
-    // plane's Ampere update reads the accumulator.
+    // the records of the ions on the tile's list.  The list entries are read
+    // first, then the records' heads, both under the prologue's plane loads.
+    // The heads decide which ions the tile owns (their forces) and which
+    // records have a link on the tile; only those records' values are read,
+    // and they are decoded in the first plane's step, while the next plane is
+    // in flight, before its Ampere update reads the accumulator.
     constexpr int kWords = kCellWords<T>;
     static_assert(12 * sizeof(T) % 16 == 0, "values of a cell in whole 16-byte words");
     constexpr int kPF = sizeof(T) == 4 ? 2 : 1;  // entries per thread prefetched
@@ -235,75 +260,86 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         T v[12];
     };
     int pf_slot[kPF];
+    bool pf_dec[kPF];
     int4 pf_head[kPF];
     RecRegs pf_con[kPF];
     int dep_cnt = 0;
     size_t dep_base = 0;
+    const int org[3] = {x0, y0, z0};
+    const int ext[3] = {TX, min(y0 + TY, L) - y0, z1 - z0};
     if constexpr (DEP) {
         const int tile = tile_x + A.ntx * (tile_y + A.nty * chunk);
         dep_base = (size_t)tile * dep->cap;
         dep_cnt = min(dep->count[(size_t)tile * kCountStride], dep->cap);
-        T *accf = &DS->acc[0][0][0][0];
-        for (int t = threadIdx.x; t < 3 * DTZ * TY * 64; t += blockDim.x) accf[t] = (T)0;
+        // (the kernel runs 256 threads per tile)
+        constexpr int kAccWords = 3 * DTZ * TY * 64 * (int)sizeof(T) / 16;
+        static_assert(kAccWords % 256 == 0, "accumulator in whole 16-byte words per thread");
+        uint4 *accw = reinterpret_cast<uint4 *>(&DS->acc[0][0][0][0]);
+#pragma unroll
+        for (int t = 0; t < kAccWords / 256; ++t) accw[threadIdx.x + 256 * t] = make_uint4(0u, 0u, 0u, 0u);
         if (threadIdx.x == 0) DS->own_n = 0;
-        if (dep->dip_prev && blockIdx.x == 0 && threadIdx.x < 64) {
-            double ps[3] = {0.0, 0.0, 0.0};
-            for (int b = threadIdx.x; b < dep->dip_nparts; b += 64)
-#pragma unroll
-                for (int d = 0; d < 3; ++d) ps[d] += dep->dip_prev[3 * b + d];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) ps[d] = wave_sum(ps[d]);
-            if (threadIdx.x == 0) {
-                dep->P[0] = ps[0];
-                dep->P[1] = ps[1];
-                dep->P[2] = ps[2];
-            }
-        }
         // list entries e < cap belong to this tile: read before the count is known
 #pragma unroll
         for (int j = 0; j < kPF; ++j) {
             const int e = (int)threadIdx.x + j * (int)blockDim.x;
             pf_slot[j] = e < dep->cap ? dep->list[dep_base + e] : -1;
         }
+        if (dep->dip_prev && blockIdx.x == 0) {
+            // wavefront sums of the dipole partials now, their sum after the
+            // prologue's first barrier (the order of the dipole finaliser)
+            double ps[3];
+            strided_sum<3>(dep->dip_prev, dep->dip_nparts, threadIdx.x, blockDim.x, ps);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ps[d] = wave_sum(ps[d]);
+            if ((threadIdx.x & 63) == 0)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) DS->psum[d][threadIdx.x >> 6] = ps[d];
+        }
     }
+    // An ion whose start cell lies in the tile gets its force here.
+    auto own_rec = [&](const int4 &h, int slot) {
+        const int lxo = (h.x & 1023) - x0, lyo = ((h.x >> 10) & 1023) - y0, lzo = ((h.x >> 20) & 1023) - z0;
+        if (lxo >= 0 && lxo < TX && lyo >= 0 && lyo < ext[1] && lzo >= 0 && lzo < ext[2]) {
+            const int pos = atomicAdd(&DS->own_n, 1);
+            if (pos < kOwnCap) DS->own[pos] = make_int2(slot, lxo | (lyo << 8) | (lzo << 16));
+        }
+    };
+    // Whether one of the record's links lies on the tile: per axis group,
+    // the box of links is the group's corner and the next cell along each
+    // perpendicular axis, and along d the next cell only when the move
+    // crosses into it.
+    auto meets_tile = [&](const int4 &h) -> bool {
+        const unsigned gw[3] = {(unsigned)h.y, (unsigned)h.z, (unsigned)h.w};
+        bool any = false;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const unsigned g = gw[d];
+            bool all = (g & kGroupOn) != 0;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const int v0 = (int)((g >> (10 * ax)) & 1023u);
+                const int v1 = v0 + 1 == L ? 0 : v0 + 1;
+                const bool span = ax != d || (g & kGroupTwo);
+                all = all && ((unsigned)(v0 - org[ax]) < (unsigned)ext[ax] ||
+                              (span && (unsigned)(v1 - org[ax]) < (unsigned)ext[ax]));
+            }
+            any = any || all;
+        }
+        return any;
+    };
     // Adds a record's values that fall on this tile's links to the
     // accumulator.  Per axis group the two candidate coordinates along each
     // axis are tested once; each of the (up to) eight links then needs only
     // those flags.
     // The second cell's values are loaded here when a move crosses a face.
     auto deposit_rec = [&](const int4 &h, const RecRegs &c0v, int slot) {
-        {
-            // an ion whose start cell lies in the tile gets its force here
-            const int lxo = (h.x & 1023) - x0, lyo = ((h.x >> 10) & 1023) - y0, lzo = ((h.x >> 20) & 1023) - z0;
-            if (lxo >= 0 && lxo < TX && lyo >= 0 && lyo < min(y0 + TY, L) - y0 && lzo >= 0 && lzo < z1 - z0) {
-                const int pos = atomicAdd(&DS->own_n, 1);
-                if (pos < kOwnCap) DS->own[pos] = make_int2(slot, lxo | (lyo << 8) | (lzo << 16));
-            }
-        }
-        // the links of an ion starting in cell c have origins in [c - 1,
-        // c + 2] per axis: skip a listed ion whose box misses the tile now
-        {
-            const int org3[3] = {x0, y0, z0};
-            const int ext3[3] = {TX, min(y0 + TY, L) - y0, z1 - z0};
-            bool meets = true;
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                int off = ((h.x >> (10 * ax)) & 1023) - 1 - org3[ax];
-                off += off < 0 ? L : 0;
-                off -= off >= L ? L : 0;
-                meets = meets && (off < ext3[ax] || off + 3 >= L);
-            }
-            if (!meets) return;
-        }
         const bool two = ((unsigned)h.y | (unsigned)h.z | (unsigned)h.w) & kGroupTwo;
         RecRegs c1v;
         if (two) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(&((const DepCon<T> *)dep->con)[slot].v[1][0]);
+            const uint4 *src = reinterpret_cast<const uint4 *>(&((const DepCell<T> *)dep->con1)[slot].v[0]);
 #pragma unroll
             for (int q = 0; q < kWords; ++q) c1v.raw[q] = src[q];
         }
-        const int org[3] = {x0, y0, z0};
-        const int ext[3] = {TX, min(y0 + TY, L) - y0, z1 - z0};
         const unsigned gw[3] = {(unsigned)h.y, (unsigned)h.z, (unsigned)h.w};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -344,17 +380,18 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         }
     };
 
-    T Dc[R][3], Dn[R][3], prevB[R][2];
+    T Dc[R][3], prevB[R][2];
 
     // Prologue: new B_x, B_y of the plane below the chunk, for the own sites.
     {
         const int gzp = wrapc(z0 - 1, L);
-        T dummy[R][3];
-        load_plane(0, gzp, dummy);
-        load_plane(1, z0, Dc);
+        {
+            PlaneRegs p0;
+            fetch_plane(gzp, p0);
+            store_plane(0, p0);
+        }
         if constexpr (DEP) {
-            // the list entries have arrived with the planes: issue the records
-            const DepCon<T> *con = (const DepCon<T> *)dep->con;
+            // the list entries have arrived with the plane: issue the heads
 #pragma unroll
             for (int j = 0; j < kPF; ++j) {
                 const int e = (int)threadIdx.x + j * (int)blockDim.x;
@@ -363,11 +400,10 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
                     continue;
                 }
                 pf_head[j] = dep->head[pf_slot[j]];
-                const uint4 *src = reinterpret_cast<const uint4 *>(&con[pf_slot[j]].v[0][0]);
-#pragma unroll
-                for (int q = 0; q < kWords; ++q) pf_con[j].raw[q] = src[q];
             }
         }
+        PlaneRegs p1;
+        fetch_plane(z0, p1);
         T bo[R][2];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -375,6 +411,24 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             bo[r][0] = A.Bin[off];
             bo[r][1] = A.Bin[Ns + off];
         }
+        if constexpr (DEP) {
+            // the heads: read the values of the records with a link on the tile
+            const DepCell<T> *con = (const DepCell<T> *)dep->con0;
+#pragma unroll
+            for (int j = 0; j < kPF; ++j) {
+                if (pf_slot[j] >= 0 && pf_head[j].x < 0) pf_slot[j] = -1;
+                pf_dec[j] = pf_slot[j] >= 0 && meets_tile(pf_head[j]);
+                if (!pf_dec[j]) continue;
+                const uint4 *src = reinterpret_cast<const uint4 *>(&con[pf_slot[j]].v[0]);
+#pragma unroll
+                for (int q = 0; q < kWords; ++q) pf_con[j].raw[q] = src[q];
+            }
+        }
+        store_plane(1, p1);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Dc[r][d] = p1.d[r][d];
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -385,19 +439,28 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
                                            sX[0][2][yy][xx + 1] + sX[0][2][yy][xx]);
         }
         if constexpr (DEP) {
-            // (the accumulator was cleared before the barrier above)
+            if (dep->dip_prev && blockIdx.x == 0 && threadIdx.x < 3) {
+                double p = 0.0;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) p += DS->psum[threadIdx.x][w];
+                dep->P[threadIdx.x] = p;
+            }
+            // (the accumulator and the owned count were cleared before the
+            // barrier above)
 #pragma unroll
             for (int j = 0; j < kPF; ++j)
-                if (pf_slot[j] >= 0 && pf_head[j].x >= 0) deposit_rec(pf_head[j], pf_con[j], pf_slot[j]);
+                if (pf_slot[j] >= 0) own_rec(pf_head[j], pf_slot[j]);
             // entries beyond the prefetched ones, if any
-            const DepCon<T> *con = (const DepCon<T> *)dep->con;
+            const DepCell<T> *con = (const DepCell<T> *)dep->con0;
             for (int e = (int)threadIdx.x + kPF * (int)blockDim.x; e < dep_cnt; e += blockDim.x) {
                 const int slot = dep->list[dep_base + e];
                 if (slot < 0) continue;
                 const int4 h = dep->head[slot];
                 if (h.x < 0) continue;
+                own_rec(h, slot);
+                if (!meets_tile(h)) continue;
                 RecRegs cn;
-                const uint4 *src = reinterpret_cast<const uint4 *>(&con[slot].v[0][0]);
+                const uint4 *src = reinterpret_cast<const uint4 *>(&con[slot].v[0]);
 #pragma unroll
                 for (int q = 0; q < kWords; ++q) cn.raw[q] = src[q];
                 deposit_rec(h, cn, slot);
@@ -425,12 +488,15 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         }
     }
 
+    // One plane k of the march.  The first one also decodes the prefetched
+    // records, between issuing the next plane's loads and storing it.
     int cur = 1;
-    for (int k = z0; k < z1; ++k) {
+    auto march = [&](int k, auto first) {
         const int nxt = cur ^ 1;
         const int gzn = wrapc(k + 1, L);
         const size_t zoff = (size_t)k * LL;
-        load_plane(nxt, gzn, Dn);
+        PlaneRegs pn;
+        fetch_plane(gzn, pn);
 
         T Bo[R][3];
 #pragma unroll
@@ -450,6 +516,12 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             hb0 = A.Bin[Ns + off];
             hb1 = A.Bin[2 * Ns + off];
         }
+        if constexpr (DEP && decltype(first)::value) {
+#pragma unroll
+            for (int j = 0; j < kPF; ++j)
+                if (pf_dec[j]) deposit_rec(pf_head[j], pf_con[j], pf_slot[j]);
+        }
+        store_plane(nxt, pn);
         __syncthreads();
 
         // Faraday: new B on the own sites
@@ -530,10 +602,12 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             prevB[r][0] = Bn[r][0];
             prevB[r][1] = Bn[r][1];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) Dc[r][d] = Dn[r][d];
+            for (int d = 0; d < 3; ++d) Dc[r][d] = pn.d[r][d];
         }
         cur = nxt;
-    }
+    };
+    march(z0, std::true_type{});
+    for (int k = z0 + 1; k < z1; ++k) march(k, std::false_type{});
 
     if constexpr (DEP) {
         // Force of the owned ion: lattice part from the captured E, as

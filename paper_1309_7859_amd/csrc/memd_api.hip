@@ -362,7 +362,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
         const size_t tiles = ((L + 63) / 64) * ((L + 3) / 4) * ((L + 1) / 2);
         c->list_tiles_max = (int)tiles;
         c->list_entries = 12 * nn + 64 * tiles;
-        const size_t rec = c->fp32 ? sizeof(DepCon<float>) : sizeof(DepCon<double>);
+        const size_t rec = 2 * (c->fp32 ? sizeof(DepCell<float>) : sizeof(DepCell<double>));
         if (hipMalloc((void **)&c->rec_head, nn * sizeof(int4)) != hipSuccess ||
             hipMalloc(&c->rec_con, nn * rec) != hipSuccess ||
             hipMalloc((void **)&c->list, c->list_entries * sizeof(int)) != hipSuccess ||
@@ -377,6 +377,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
             (void)hipGetLastError();
             return fail(MEMD_ENOMEM);
         }
+        c->rec_con1 = (char *)c->rec_con + nn * (rec / 2);
     }
     hipStream_t s = c->stream;
     if (c->fdone) hipMemsetAsync(c->fdone, 0, nn * sizeof(unsigned int), s);  // no launch is stamped 0

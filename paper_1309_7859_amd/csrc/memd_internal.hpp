@@ -100,7 +100,7 @@ struct memd_ctx {
     // (rows * 4096 + planes; -1: none), list_entries entries shared by the
     // tiles, and per slot the cell at the build (cbin) and list_fail.
     int4 *rec_head;
-    void *rec_con;
+    void *rec_con, *rec_con1;  // the records' first cells, second cells (one allocation)
     int *list, *list_count, *cbin, *list_fail;
     double *du_slot;  // [3n] by slot: the displacement each record was made for
     // Forces computed by the leapfrog tiles (DepArgs): fractional positions
