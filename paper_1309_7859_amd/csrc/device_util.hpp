@@ -65,11 +65,12 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Per-thread sums of W-vectors p[W b .. W b + W) over b = first, first +
-// stride, ... < n, in increasing b (eight vectors' loads in flight per pass).
+// Per-thread folds of W-vectors p[W b .. W b + W) over b = first, first +
+// stride, ... < n, in increasing b (eight vectors' loads in flight per
+// pass): column w is summed, or (bit w of maxmask) its maximum taken, from 0.
 template <int W>
-__device__ __forceinline__ void strided_sum(const double *__restrict__ p, int n, int first, int stride,
-                                            double (&s)[W]) {
+__device__ __forceinline__ void strided_fold(const double *__restrict__ p, int n, int first, int stride,
+                                             unsigned maxmask, double (&s)[W]) {
 #pragma unroll
     for (int w = 0; w < W; ++w) s[w] = 0.0;
     for (int b0 = first; b0 < n; b0 += 8 * stride) {
@@ -84,8 +85,14 @@ __device__ __forceinline__ void strided_sum(const double *__restrict__ p, int n,
         for (int u = 0; u < 8; ++u)
 #pragma unroll
             for (int w = 0; w < W; ++w)
-                if (b0 + u * stride < n) s[w] += v[u][w];
+                if (b0 + u * stride < n) s[w] = ((maxmask >> w) & 1u) ? fmax(s[w], v[u][w]) : s[w] + v[u][w];
     }
+}
+
+template <int W>
+__device__ __forceinline__ void strided_sum(const double *__restrict__ p, int n, int first, int stride,
+                                            double (&s)[W]) {
+    strided_fold<W>(p, n, first, stride, 0u, s);
 }
 
 // Block-wide sums of N values (blockDim.x a multiple of 64, <= 1024).  The

@@ -106,10 +106,9 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
         // records unless the previous ion step wrote them against these lists
         const bool rebuild = c->lists_key != c->lf_rows * 4096 + c->lf_tz;
         if (rebuild) {
-            hipError_t e = launch_build_lists(c);
+            hipError_t e = launch_build_lists(c, true, disp, seed, t, sigma);
             if (e != hipSuccess) return e;
-        }
-        if (need_pack || rebuild) {
+        } else if (need_pack) {
             hipError_t e = launch_pack_ions(c, disp, seed, t, sigma);
             if (e != hipSuccess) return e;
         }
@@ -148,6 +147,35 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
 
 // ------------------------------------------------------------------ energy
 
+// The site-loop kernels (energy, audit) walk the lattice by row chunks
+// (64 sites along x at one (y, z)), one wavefront per chunk of a 256-thread
+// block: chunk k has x0 = 64 (k mod nxc),
+// y = (k / nxc) mod L, z = k / (nxc L), nxc = ceil(L / 64).
+struct RowChunk {
+    int x, y, z;
+    bool live;
+};
+__device__ __forceinline__ RowChunk row_chunk(int k, int L) {
+    const int nxc = (L + 63) >> 6;
+    const int yz = k / nxc;
+    RowChunk r;
+    r.x = (k - yz * nxc) * 64 + (int)(threadIdx.x & 63);
+    r.y = yz % L;
+    r.z = yz / L;
+    r.live = r.x < L;
+    return r;
+}
+
+template <typename F>
+__device__ __forceinline__ void for_row_chunks(int L, F &&body) {
+    const int nch = ((L + 63) >> 6) * L * L;
+    for (int k = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6))); k < nch;
+         k += gridDim.x * 4) {
+        const RowChunk rc = row_chunk(k, L);
+        if (rc.live) body(rc);
+    }
+}
+
 template <typename T>
 struct FieldView {
     const T *D;
@@ -178,9 +206,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_energy_field(FieldView<T> V, double kB, double *partials) {
     const int L = V.L;
     double we = 0.0, wb = 0.0;
-    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < V.Ns;
-         v += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(v % L), j = (int)((v / L) % L), k = (int)(v / ((size_t)L * L));
+    for_row_chunks(L, [&](const RowChunk &rc) {
+        const int i = rc.x, j = rc.y, k = rc.z;
+        const size_t v = ((size_t)k * L + j) * L + i;
         const int ip = (i + 1 == L) ? 0 : i + 1, jp = (j + 1 == L) ? 0 : j + 1,
                   kp = (k + 1 == L) ? 0 : k + 1;
         double X[3];
@@ -195,7 +223,7 @@ __global__ __launch_bounds__(256) void k_energy_field(FieldView<T> V, double kB,
         const double cz = X_at(V, 1, ip, j, k) - X[1] - X_at(V, 0, i, jp, k) + X[0];
         const double bx = (double)V.B[v], by = (double)V.B[V.Ns + v], bz = (double)V.B[2 * V.Ns + v];
         wb += bx * (bx - kB * cx) + by * (by - kB * cy) + bz * (bz - kB * cz);
-    }
+    });
     double s[2] = {we, wb};
     block_sum<2>(s);
     if (threadIdx.x == 0) {
@@ -220,7 +248,7 @@ static FieldView<T> make_view(memd_ctx *c, const void *D, const void *B) {
 
 static int site_blocks(size_t Ns) {
     size_t b = (Ns + kThreads - 1) / kThreads;
-    return (int)(b < (size_t)kRedBlocks ? b : (size_t)kRedBlocks);
+    return (int)(b < (size_t)kSiteBlocks ? b : (size_t)kSiteBlocks);
 }
 
 hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
@@ -239,25 +267,23 @@ hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double
 
 // ------------------------------------------------------------------- audit
 
-// R_v = a^2 sum_d [D_d(v) - D_d(v-e_d)] - rho_v in FP64; rho is cleared after
-// reading so that it is all-zero for the next charge assignment.
+// R_v = a^2 sum_d [D_d(v) - D_d(v-e_d)] - rho_v in FP64.
 template <typename T>
-__global__ __launch_bounds__(256) void k_audit(const T *__restrict__ D, double *__restrict__ rho,
+__global__ __launch_bounds__(256) void k_audit(const T *__restrict__ D, const double *__restrict__ rho,
                                                int L, size_t Ns, double a2, double *partials) {
     double mx = 0.0, ss = 0.0;
-    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns;
-         v += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(v % L), j = (int)((v / L) % L), k = (int)(v / ((size_t)L * L));
+    for_row_chunks(L, [&](const RowChunk &rc) {
+        const int i = rc.x, j = rc.y, k = rc.z;
+        const size_t v = ((size_t)k * L + j) * L + i;
         const size_t vx = site_index(i == 0 ? L - 1 : i - 1, j, k, L);
         const size_t vy = site_index(i, j == 0 ? L - 1 : j - 1, k, L);
         const size_t vz = site_index(i, j, k == 0 ? L - 1 : k - 1, L);
         const double dv = ((double)D[v] - (double)D[vx]) + ((double)D[Ns + v] - (double)D[Ns + vy]) +
                           ((double)D[2 * Ns + v] - (double)D[2 * Ns + vz]);
         const double R = a2 * dv - rho[v];
-        rho[v] = 0.0;
         mx = fmax(mx, fabs(R));
         ss += R * R;
-    }
+    });
     double s[1] = {ss};
     block_sum<1>(s);
     const double m = block_max(mx);
@@ -451,38 +477,99 @@ hipError_t launch_eta_sums(memd_ctx *c, double *partials, int *nblk) {
 
 // ---------------------------------------------------- salt permittivity
 
-// nbar_v = (1/27) sum over the periodic 3x3x3 vertex box of cnt / a^3
-__global__ void k_box_mean(const double *__restrict__ cnt, int L, size_t Ns, double inv_cell,
-                           double *__restrict__ nbar) {
-    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns;
-         v += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(v % L), j = (int)((v / L) % L), k = (int)(v / ((size_t)L * L));
-        double s = 0.0;
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx)
-                    s += cnt[site_index(wrapc(i + dx, L), wrapc(j + dy, L), wrapc(k + dz, L), L)] * inv_cell;
-        nbar[v] = s / 27.0;
-    }
-}
+// Salt permittivity from the ion counts cnt (CIC number of ions per vertex):
+//   nbar_v = (1/27) sum over the periodic 3x3x3 vertex box of cnt / a^3,
+//   eps of a link = eps_w - slope * (mean of nbar at its two ends), at least
+//   eps_floor; eta = 1 / eps stored per link; per site 12 / (sum of eta over
+//   the 12 edges of its cell), as force_ion sums the stored values; per
+//   block the sums of eta_d and the largest eta (4 partials).
+// A workgroup takes tiles of 64 x 4 sites and marches through a chunk of
+// kSaltTZ planes.  Per plane R it stages cnt with a one-site halo in LDS,
+// forms the 3 x 3 sums over (x, y) for the 65 x 5 corners its cells need,
+// keeps three such planes, and from them nbar of planes R-1 (two kept); the
+// outputs of plane R-2 then need nothing outside LDS.
+constexpr int kSaltTZ = 8;
 
 template <typename T>
-__global__ void k_salt_link(const double *__restrict__ nbar, int L, size_t Ns, double eps_w,
-                            double slope, double eps_floor, T *__restrict__ eta) {
-    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns;
-         v += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(v % L), j = (int)((v / L) % L), k = (int)(v / ((size_t)L * L));
-        const double n0 = nbar[v];
-        const double nb[3] = {nbar[site_index(i + 1 == L ? 0 : i + 1, j, k, L)],
-                              nbar[site_index(i, j + 1 == L ? 0 : j + 1, k, L)],
-                              nbar[site_index(i, j, k + 1 == L ? 0 : k + 1, L)]};
+__global__ __launch_bounds__(256) void k_salt_tile(const double *__restrict__ cnt, int L, size_t Ns, double inv27, double eps_w, double slope,
+                                                   double eps_floor, T *__restrict__ eta, T *__restrict__ ecell,
+                                                   double *__restrict__ partials) {
+    __shared__ double sc[7][67];      // cnt of plane R, x0-1 .. x0+65, y0-1 .. y0+5
+    __shared__ double sS[3][5][65];   // (x, y) box sums of planes R, R-1, R-2 (ring by plane)
+    __shared__ double sN[2][5][65];   // nbar of two planes (ring by plane)
+    const int lx = threadIdx.x & 63, wy = threadIdx.x >> 6;
+    const int ntx = (L + 63) >> 6, nty = (L + 3) >> 2, ntz = (L + kSaltTZ - 1) / kSaltTZ;
+    const int tiles = ntx * nty * ntz;
+    double s[3] = {0.0, 0.0, 0.0}, mx = 0.0;
+    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int x0 = (tile % ntx) * 64, y0 = ((tile / ntx) % nty) * 4, z0 = (tile / (ntx * nty)) * kSaltTZ;
+        const int z1 = min(z0 + kSaltTZ, L);
+        for (int R = z0 - 1; R <= z1 + 1; ++R) {
+            const size_t zoff = (size_t)wrapc(R, L) * L * L;
+            for (int t = threadIdx.x; t < 7 * 67; t += 256) {
+                const int iy = t / 67, ix = t - iy * 67;
+                sc[iy][ix] = cnt[zoff + (size_t)wrapc(y0 - 1 + iy, L) * L + wrapc(x0 - 1 + ix, L)];
+            }
+            __syncthreads();
+            const int rs = (R + 3) % 3;
+            for (int t = threadIdx.x; t < 5 * 65; t += 256) {
+                const int iy = t / 65, ix = t - iy * 65;
+                double b = 0.0;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double cl = 0.5 * (n0 + nb[d]);
-            double e = eps_w - slope * cl;
-            e = e < eps_floor ? eps_floor : e;
-            eta[(size_t)d * Ns + v] = (T)(1.0 / e);
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) b += sc[iy + dy][ix + dx];
+                sS[rs][iy][ix] = b;
+            }
+            __syncthreads();
+            const int Q = R - 1;  // nbar of plane Q from the box sums of Q-1, Q, Q+1
+            if (Q >= z0) {
+                for (int t = threadIdx.x; t < 5 * 65; t += 256) {
+                    const int iy = t / 65, ix = t - iy * 65;
+                    sN[(Q + 2) & 1][iy][ix] =
+                        (sS[(Q + 2) % 3][iy][ix] + sS[(Q + 3) % 3][iy][ix] + sS[rs][iy][ix]) * inv27;
+                }
+            }
+            __syncthreads();
+            const int P = Q - 1;  // outputs of plane P from nbar of P and P + 1
+            if (P >= z0 && P < z1) {
+                const int x = x0 + lx, y = y0 + wy;
+                if (x < L && y < L) {
+                    double n[8];
+#pragma unroll
+                    for (int o = 0; o < 8; ++o) n[o] = sN[(P + 2 + (o >> 2)) & 1][wy + ((o >> 1) & 1)][lx + (o & 1)];
+                    auto eta_edge = [&](int d, int o) -> T {
+                        const double cl = 0.5 * (n[o] + n[o | (1 << d)]);
+                        double e = eps_w - slope * cl;
+                        e = e < eps_floor ? eps_floor : e;
+                        return (T)(1.0 / e);
+                    };
+                    const size_t v = ((size_t)P * L + y) * L + x;
+                    double sum = 0.0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+                        const T own = eta_edge(d, 0);
+                        eta[(size_t)d * Ns + v] = own;
+                        s[d] += (double)own;
+                        mx = fmax(mx, (double)own);
+#pragma unroll
+                        for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                            for (int o1 = 0; o1 < 2; ++o1) sum += (double)eta_edge(d, (o1 << d1) | (o2 << d2));
+                    }
+                    if (ecell) ecell[v] = (T)(12.0 / sum);
+                }
+            }
         }
+    }
+    block_sum<3>(s);
+    const double m = block_max(mx);
+    if (threadIdx.x == 0) {
+        partials[4 * blockIdx.x] = s[0];
+        partials[4 * blockIdx.x + 1] = s[1];
+        partials[4 * blockIdx.x + 2] = s[2];
+        partials[4 * blockIdx.x + 3] = m;
     }
 }
 
@@ -528,23 +615,21 @@ hipError_t launch_ecell(memd_ctx *c) {
 
 hipError_t launch_salt(memd_ctx *c) {
     hipError_t e;
-    const int g = grid_for(c->Ns);
-    if ((e = launch_fill(c->stream, c->salt_cnt, 0.0, c->Ns)) != hipSuccess) return e;
-    if ((e = launch_spread(c, nullptr, c->salt_cnt)) != hipSuccess) return e;
+    double *cnt = c->salt_cnt;
+    if ((e = launch_spread_dense(c, false, cnt)) != hipSuccess) return e;
     const double a3 = c->a * c->a * c->a;
-    hipLaunchKernelGGL(k_box_mean, dim3(g), dim3(kThreads), 0, c->stream, c->salt_cnt, c->L, c->Ns,
-                       1.0 / a3, c->salt_nbar);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int L = c->L;
+    const int tiles = ((L + 63) / 64) * ((L + 3) / 4) * ((L + kSaltTZ - 1) / kSaltTZ);
+    const int nb = tiles < kSiteBlocks ? tiles : kSiteBlocks;
     if (c->fp32)
-        hipLaunchKernelGGL(k_salt_link<float>, dim3(g), dim3(kThreads), 0, c->stream, c->salt_nbar, c->L, c->Ns,
-                           c->salt_w, c->salt_slope, c->salt_floor, (float *)c->eta_link);
+        hipLaunchKernelGGL(k_salt_tile<float>, dim3(nb), dim3(kThreads), 0, c->stream, cnt, L, c->Ns,
+                           1.0 / (27.0 * a3), c->salt_w, c->salt_slope, c->salt_floor, (float *)c->eta_link,
+                           (float *)c->ecell, c->partials);
     else
-        hipLaunchKernelGGL(k_salt_link<double>, dim3(g), dim3(kThreads), 0, c->stream, c->salt_nbar, c->L,
-                           c->Ns, c->salt_w, c->salt_slope, c->salt_floor, (double *)c->eta_link);
+        hipLaunchKernelGGL(k_salt_tile<double>, dim3(nb), dim3(kThreads), 0, c->stream, cnt, L, c->Ns,
+                           1.0 / (27.0 * a3), c->salt_w, c->salt_slope, c->salt_floor, (double *)c->eta_link,
+                           (double *)c->ecell, c->partials);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    int nb = 0;
-    if ((e = launch_eta_sums(c, c->partials, &nb)) != hipSuccess) return e;
-    if ((e = launch_ecell(c)) != hipSuccess) return e;
     return launch_finalize_epsh(c->stream, c->partials, nb, (double)c->Ns, c->scal + S_EPSH,
                                 c->scal + S_ETAMAX);
 }

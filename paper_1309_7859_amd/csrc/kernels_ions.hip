@@ -16,14 +16,12 @@ namespace memd {
 // The deposit kernel: sixteen lanes per ion (one per axis and transverse
 // corner, deposit_ion_part), ions taken in the order of `order` (binned by
 // lattice row, so that neighbouring lanes update neighbouring links).  Lane 0
-// of each ion writes the new position and, when spread_rho is set, adds the
-// new charge assignment to rho (FP64) for the Gauss audit.  Block sums of
-// q r^{n+1} go to partials (summed in block order by k_fin_dipole).
+// of each ion writes the new position.  Block sums of q r^{n+1} go to
+// partials (summed in block order by k_fin_dipole).
 template <typename T>
 __global__ __launch_bounds__(256) void k_deposit(int n, int L, size_t Ns, double a,
                                                  const double *__restrict__ q, double *__restrict__ r,
                                                  const double *__restrict__ disp, T *__restrict__ D,
-                                                 int spread_rho, double *__restrict__ rho,
                                                  const int *__restrict__ order, const int *__restrict__ perm,
                                                  double *__restrict__ partials, unsigned int *bad,
                                                  uint64_t seed, uint32_t t, double sigma) {
@@ -54,7 +52,6 @@ __global__ __launch_bounds__(256) void k_deposit(int n, int L, size_t Ns, double
             r[3 * i + 2] = u[2];
 #pragma unroll
             for (int d = 0; d < 3; ++d) P[d] = qi * u[d];
-            if (spread_rho) spread_ion(L, a, qi, u, rho);
         }
     }
     block_sum<3>(P);
@@ -74,17 +71,17 @@ static int ion_blocks_x8(int n, int lanes_per_ion = 1) {
     return (b + 7) / 8 * 8;
 }
 
-hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_rho,
-                          double *partials, int *nblk, uint64_t seed, uint32_t t, double sigma) {
+hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, double *partials, int *nblk, uint64_t seed,
+                          uint32_t t, double sigma) {
     const int nb = ion_blocks_x8(c->n, 16);
     *nblk = nb;
     if (c->fp32)
         hipLaunchKernelGGL(k_deposit<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
-                           c->q, c->r, disp, (float *)D, spread_rho ? 1 : 0, c->rho, c->order, c->perm, partials,
+                           c->q, c->r, disp, (float *)D, c->order, c->perm, partials,
                            c->bad_moves, seed, t, sigma);
     else
         hipLaunchKernelGGL(k_deposit<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a,
-                           c->q, c->r, disp, (double *)D, spread_rho ? 1 : 0, c->rho, c->order, c->perm, partials,
+                           c->q, c->r, disp, (double *)D, c->order, c->perm, partials,
                            c->bad_moves, seed, t, sigma);
     return hipGetLastError();
 }
@@ -111,9 +108,11 @@ struct DepOut {
 // Returns true, and writes a head of -1, when the ion is left to the atomic
 // path: irregular, drifted more than one cell from its list cell along an
 // axis, or missing from a list.
+// (list_fail and cb: the slot's entries of O.list_fail and O.cbin.)
 template <typename T>
-__device__ __forceinline__ bool write_record(int L, double a, double qi, const double (&u_in)[3],
-                                             const double (&du)[3], int s, const DepOut<T> &O) {
+__device__ __forceinline__ bool write_record_at(int L, double a, double qi, const double (&u_in)[3],
+                                                const double (&du)[3], int s, const DepOut<T> &O, int list_fail,
+                                                int cb) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) O.du[3 * s + d] = du[d];
     double u[3] = {u_in[0], u_in[1], u_in[2]};
@@ -121,8 +120,7 @@ __device__ __forceinline__ bool write_record(int L, double a, double qi, const d
     double f0[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) fold(u[d], a, L, c0[d], f0[d]);
-    bool atomic_path = O.list_fail[s] != 0 || !ion_regular(a, u_in, du);
-    const int cb = O.cbin[s];
+    bool atomic_path = list_fail != 0 || !ion_regular(a, u_in, du);
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         int off = c0[e] - ((cb >> (10 * e)) & 1023) + 1;
@@ -183,6 +181,28 @@ __device__ __forceinline__ bool write_record(int L, double a, double qi, const d
     return false;
 }
 
+template <typename T>
+__device__ __forceinline__ bool write_record(int L, double a, double qi, const double (&u_in)[3],
+                                             const double (&du)[3], int s, const DepOut<T> &O) {
+    return write_record_at<T>(L, a, qi, u_in, du, s, O, O.list_fail[s], O.cbin[s]);
+}
+
+// The displacement of storage index i for the step (the caller's index
+// perm[i]), sanitised and counted.
+__device__ __forceinline__ void step_displacement(int i, int L, double a, const double *__restrict__ disp,
+                                                  const int *__restrict__ perm, unsigned int *bad, uint64_t seed,
+                                                  uint32_t t, double sigma, double (&du)[3]) {
+    const int ci = perm ? perm[i] : i;
+    if (disp) {
+        du[0] = disp[3 * ci];
+        du[1] = disp[3 * ci + 1];
+        du[2] = disp[3 * ci + 2];
+    } else {
+        philox_displacement(seed, t, (uint32_t)ci, sigma, du);
+    }
+    sanitize_move(du, a, L, bad);
+}
+
 // Records for the step about to run, ions read in storage order
 // (coalesced), one lane per ion, ion i's record going to its slot
 // slot_of[i]; displacements are indexed by the caller's index perm[i], and
@@ -196,17 +216,9 @@ __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const
                                                    uint64_t seed, uint32_t t, double sigma) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int ci = perm ? perm[i] : i;
     const double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
     double du[3];
-    if (disp) {
-        du[0] = disp[3 * ci];
-        du[1] = disp[3 * ci + 1];
-        du[2] = disp[3 * ci + 2];
-    } else {
-        philox_displacement(seed, t, (uint32_t)ci, sigma, du);
-    }
-    sanitize_move(du, a, L, bad);
+    step_displacement(i, L, a, disp, perm, bad, seed, t, sigma, du);
     const int s = slot_of[i];
     dep_atomic[s] = write_record<T>(L, a, q[i], u, du, s, O) ? 1 : 0;
 }
@@ -237,13 +249,36 @@ struct TileLists {
     int cap, TY, TZ, ntx, nty;
 };
 
+// What the list builder needs to write the records too (the pack right
+// after a re-binning).
+template <typename T>
+struct PackArgs {
+    const double *q, *disp;
+    const int *perm;
+    int *dep_atomic;
+    DepOut<T> O;
+    unsigned int *bad;
+    uint64_t seed;
+    uint32_t t;
+    double sigma;
+};
+
+// Lists of the fused deposit, one lane per ion in storage order: the ion's
+// cell c goes to cbin, and its slot to every tile owning a link with origin
+// in [c - 2, c + 3] along each axis.  A wavefront reserves list places in
+// rounds (one per tile of each lane's box), with one atomic per distinct
+// tile and round; eight rounds' atomics are issued before their places are
+// written.  An ion that would need more than four tiles along an axis, or
+// finds a list full, is marked in list_fail.  With PACK the lane then writes
+// the ion's record for the step about to run (as k_pack_ions).
+template <typename T, bool PACK>
 __global__ __launch_bounds__(256) void k_build_lists(int n, int L, double a, const double *__restrict__ r,
                                                      const int *__restrict__ slot_of, int *__restrict__ cbin,
-                                                     int *__restrict__ list_fail, TileLists T) {
+                                                     int *__restrict__ list_fail, TileLists TL, PackArgs<T> PA) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
-    int nres = 0, s = 0;
+    int nres = 0, s = 0, cb = 0;
     int tid[3][4], nt[3] = {0, 0, 0};
     bool fail = false;
     if (j < n) {
@@ -252,8 +287,9 @@ __global__ __launch_bounds__(256) void k_build_lists(int n, int L, double a, con
         double f;
 #pragma unroll
         for (int e = 0; e < 3; ++e) fold(r[3 * j + e], a, L, c[e], f);
-        cbin[s] = pack_cell(c[0], c[1], c[2]);
-        const int ext[3] = {64, T.TY, T.TZ};
+        cb = pack_cell(c[0], c[1], c[2]);
+        cbin[s] = cb;
+        const int ext[3] = {64, TL.TY, TL.TZ};
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
             for (int off = -2; off <= 3; ++off) {
@@ -273,55 +309,93 @@ __global__ __launch_bounds__(256) void k_build_lists(int n, int L, double a, con
         nres = fail ? 0 : nt[0] * nt[1] * nt[2];
     }
     // every lane of the wavefront takes part in the reservation rounds
+    constexpr int kBatch = 8;
     bool ok = !fail;
-    for (int k = 0; k < 64; ++k) {
-        int my = -1;
-        if (k < nres) {
-            const int kx = k % nt[0], ky = (k / nt[0]) % nt[1], kz = k / (nt[0] * nt[1]);
-            my = tid[0][kx] + T.ntx * (tid[1][ky] + T.nty * tid[2][kz]);
-        }
-        unsigned long long rem = __ballot(my >= 0);
-        if (rem == 0ull) break;  // the same for every lane
-        int lead = lane, rank = 0, take = 0;
-        while (rem) {
-            const int l = __ffsll((long long)rem) - 1;
-            const int idl = __builtin_amdgcn_readlane(my, l);
-            const unsigned long long same = __ballot(my == idl);
-            if (my == idl) {
-                lead = l;
-                rank = __popcll(same & below);
+    for (int k0 = 0; __ballot(k0 < nres) != 0ull; k0 += kBatch) {
+        int my[kBatch], lead[kBatch], rank[kBatch], base[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int k = k0 + u;
+            my[u] = -1;
+            if (k < nres) {
+                const int kx = k % nt[0], ky = (k / nt[0]) % nt[1], kz = k / (nt[0] * nt[1]);
+                my[u] = tid[0][kx] + TL.ntx * (tid[1][ky] + TL.nty * tid[2][kz]);
             }
-            if (lane == l) take = __popcll(same);
-            rem &= ~same;
+            unsigned long long rem = __ballot(my[u] >= 0);
+            lead[u] = lane;
+            rank[u] = 0;
+            int take = 0;
+            while (rem) {
+                const int l = __ffsll((long long)rem) - 1;
+                const int idl = __builtin_amdgcn_readlane(my[u], l);
+                const unsigned long long same = __ballot(my[u] == idl);
+                if (my[u] == idl) {
+                    lead[u] = l;
+                    rank[u] = __popcll(same & below);
+                }
+                if (lane == l) take = __popcll(same);
+                rem &= ~same;
+            }
+            base[u] = 0;
+            if (take > 0) base[u] = atomicAdd(&TL.count[(size_t)my[u] * kCountStride], take);
         }
-        int base = 0;
-        if (take > 0) base = atomicAdd(&T.count[(size_t)my * kCountStride], take);
-        base = __shfl(base, lead, 64);
-        if (my >= 0) {
-            const int pos = base + rank;
-            if (pos >= T.cap) ok = false;
-            else T.list[(size_t)my * T.cap + pos] = s;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int b = __shfl(base[u], lead[u], 64);
+            if (my[u] >= 0) {
+                const int pos = b + rank[u];
+                if (pos >= TL.cap) ok = false;
+                else TL.list[(size_t)my[u] * TL.cap + pos] = s;
+            }
         }
     }
-    if (j < n) list_fail[s] = ok ? 0 : 1;
+    if (j < n) {
+        list_fail[s] = ok ? 0 : 1;
+        if constexpr (PACK) {
+            const double u[3] = {r[3 * j], r[3 * j + 1], r[3 * j + 2]};
+            double du[3];
+            step_displacement(j, L, a, PA.disp, PA.perm, PA.bad, PA.seed, PA.t, PA.sigma, du);
+            PA.dep_atomic[s] = write_record_at<T>(L, a, PA.q[j], u, du, s, PA.O, ok ? 0 : 1, cb) ? 1 : 0;
+        }
+    }
 }
 
-hipError_t launch_build_lists(memd_ctx *c) {
+// Builds the lists for the current tile shape; with pack, also the records
+// for the step about to run.  The counts start from zero: cleared by the
+// re-binning's scan for this shape (list_zero_key), else here.
+hipError_t launch_build_lists(memd_ctx *c, bool pack, const double *disp, uint64_t seed, uint32_t t,
+                              double sigma) {
     if (c->n == 0 || !c->list) return hipSuccess;
-    TileLists T;
-    T.list = c->list;
-    T.count = c->list_count;
-    T.TY = 4 * c->lf_rows;
-    T.TZ = c->lf_tz;
-    T.ntx = (c->L + 63) / 64;
-    T.nty = (c->L + T.TY - 1) / T.TY;
-    T.cap = list_cap(c);
-    const size_t nc = (size_t)list_tiles(c) * kCountStride;
-    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((nc + kThreads - 1) / kThreads)), dim3(kThreads), 0, c->stream,
-                       c->list_count, 0, nc);
-    hipLaunchKernelGGL(k_build_lists, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->r,
-                       c->slot, c->cbin, c->list_fail, T);
-    c->lists_key = c->lf_rows * 4096 + c->lf_tz;
+    TileLists TL;
+    TL.list = c->list;
+    TL.count = c->list_count;
+    TL.TY = 4 * c->lf_rows;
+    TL.TZ = c->lf_tz;
+    TL.ntx = (c->L + 63) / 64;
+    TL.nty = (c->L + TL.TY - 1) / TL.TY;
+    TL.cap = list_cap(c);
+    const int key = c->lf_rows * 4096 + c->lf_tz;
+    if (c->list_zero_key != key) {
+        const size_t nc = (size_t)list_tiles(c) * kCountStride;
+        hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((nc + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                           c->stream, c->list_count, 0, nc);
+    }
+    c->list_zero_key = -1;  // the counts are in use from here on
+    const int nb = ion_blocks(c->n);
+    if (pack && c->fp32) {
+        PackArgs<float> PA{c->q, disp, c->perm, c->dep_atomic, dep_out<float>(c), c->bad_moves, seed, t, sigma};
+        hipLaunchKernelGGL((k_build_lists<float, true>), dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
+                           c->r, c->slot, c->cbin, c->list_fail, TL, PA);
+    } else if (pack) {
+        PackArgs<double> PA{c->q, disp, c->perm, c->dep_atomic, dep_out<double>(c), c->bad_moves, seed, t, sigma};
+        hipLaunchKernelGGL((k_build_lists<double, true>), dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
+                           c->r, c->slot, c->cbin, c->list_fail, TL, PA);
+    } else {
+        PackArgs<float> PA{};
+        hipLaunchKernelGGL((k_build_lists<float, false>), dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
+                           c->r, c->slot, c->cbin, c->list_fail, TL, PA);
+    }
+    c->lists_key = key;
     return hipGetLastError();
 }
 
@@ -351,7 +425,7 @@ hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint
 //   - wavefronts 2-3: irregular ions deposit their whole move into D^{n+1}
 //     with global atomics; every ion moves to r^{n+1} (written to r_out, so
 //     the force lanes still read r^n); one partial of q r^{n+1} per
-//     wavefront (dip_out; rho for the audit when asked); the deposit records
+//     wavefront (dip_out); the deposit records
 //     of the next step (from r^{n+1} and its displacement), when pack is set.
 constexpr int kIonStepIons = 128;
 
@@ -382,7 +456,6 @@ struct IonStepArgs {
     int *dep_atomic;  // [n] by slot: this step's ion left to the atomic path (read), the next step's (written)
     int pack;         // write the next step's records
     DepOut<T> out;
-    double *rho;  // null: no charge spreading
     unsigned int *bad;
 };
 
@@ -437,7 +510,6 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
         A.r_out[3 * i + 2] = u[2];
 #pragma unroll
         for (int d = 0; d < 3; ++d) P[d] = qi * u[d];
-        if (A.rho) spread_ion(A.L, A.a, qi, u, A.rho);
         if (A.pack) {
             sanitize_move(dn, A.a, A.L, A.bad);
             A.dep_atomic[s] = write_record<T>(A.L, A.a, qi, u, dn, s, A.out) ? 1 : 0;
@@ -462,8 +534,7 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
 }
 
 hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const double *disp_next,
-                           uint64_t seed, uint32_t t, double sigma, double *dip_out, int *nparts, bool pack_next,
-                           bool spread_rho) {
+                           uint64_t seed, uint32_t t, double sigma, double *dip_out, int *nparts, bool pack_next) {
     const int nb = ion_blocks_x8(c->n, kThreads / kIonStepIons);
     *nparts = 2 * nb;  // one dipole partial per mover wavefront
     auto fill = [&](auto &A, auto *Dc, auto *Dn) {
@@ -493,7 +564,6 @@ hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const dou
         A.dip_out = dip_out;
         A.dep_atomic = c->dep_atomic;
         A.pack = pack_next ? 1 : 0;
-        A.rho = spread_rho ? c->rho : nullptr;
         A.bad = c->bad_moves;
     };
     if (c->fp32) {
@@ -532,6 +602,114 @@ hipError_t launch_spread(memd_ctx *c, const double *charges_or_null, double *dst
     hipLaunchKernelGGL(k_spread, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
                        charges_or_null ? c->q : nullptr, c->r, dst);
     return hipGetLastError();
+}
+
+// The same assignment without global atomics, for ions stored in bin order
+// (the storage indices start[row] .. start[row + 1] of bin row row = y + L z
+// are the ions whose cell lay in that lattice row at the last re-binning).
+// A workgroup owns a tile of 64 x 4 x 8 vertices.  Its vertices draw from
+// cells one below them along each axis, so it reads the ions of the bin
+// rows y0 - 2 .. y0 + 4 and z0 - 2 .. z0 + 8 (every x), keeps those whose
+// cell is still within one row of their bin row along y and z, adds their
+// weights on its vertices in LDS, and stores every vertex of the tile.  The
+// workgroup with x0 = 0 whose rows contain an ion's bin row marks, in
+// drifted, whether that ion moved further (k_spread_drifted adds those).
+constexpr int kSpTY = 4, kSpTZ = 8;
+constexpr int kSpRows = (kSpTY + 3) * (kSpTZ + 3);
+
+__global__ __launch_bounds__(256) void k_spread_tile(int n, int L, double a, const double *__restrict__ q,
+                                                     const double *__restrict__ r, const int *__restrict__ start,
+                                                     int *__restrict__ drifted, double *__restrict__ dst) {
+    __shared__ double acc[kSpTZ][kSpTY][64];
+    __shared__ int row_beg[kSpRows], row_off[kSpRows + 1];
+    const int ntx = (L + 63) >> 6, nty = (L + kSpTY - 1) / kSpTY;
+    const int tile = blockIdx.x;
+    const int x0 = (tile % ntx) * 64, y0 = ((tile / ntx) % nty) * kSpTY, z0 = (tile / (ntx * nty)) * kSpTZ;
+    double *accf = &acc[0][0][0];
+    for (int t = threadIdx.x; t < kSpTZ * kSpTY * 64; t += blockDim.x) accf[t] = 0.0;
+    if (threadIdx.x < kSpRows) {
+        const int iy = threadIdx.x % (kSpTY + 3), iz = threadIdx.x / (kSpTY + 3);
+        const int row = wrapc(y0 - 2 + iy, L) + L * wrapc(z0 - 2 + iz, L);
+        const int b = start[row], e = row + 1 < L * L ? start[row + 1] : n;
+        row_beg[threadIdx.x] = b;
+        row_off[threadIdx.x + 1] = e - b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        row_off[0] = 0;
+        for (int k = 0; k < kSpRows; ++k) row_off[k + 1] += row_off[k];
+    }
+    __syncthreads();
+    const int total = row_off[kSpRows];
+    const int own_ny = min(kSpTY, L - y0), own_nz = min(kSpTZ, L - z0);
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        int lo = 0, hi = kSpRows - 1;  // the candidate row holding entry e
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (row_off[mid] <= e) lo = mid;
+            else hi = mid - 1;
+        }
+        const int i = row_beg[lo] + (e - row_off[lo]);
+        const int iy = lo % (kSpTY + 3), iz = lo / (kSpTY + 3);
+        const double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
+        int cc[3];
+        double ff[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fold(u[d], a, L, cc[d], ff[d]);
+        // cell rows relative to the bin row, periodic, in 0 .. L-1
+        int dy = cc[1] - wrapc(y0 - 2 + iy, L), dz = cc[2] - wrapc(z0 - 2 + iz, L);
+        dy += dy < 0 ? L : 0;
+        dz += dz < 0 ? L : 0;
+        const bool near = (dy <= 1 || dy >= L - 1) && (dz <= 1 || dz >= L - 1);
+        if (x0 == 0 && (unsigned)(iy - 2) < (unsigned)own_ny && (unsigned)(iz - 2) < (unsigned)own_nz)
+            drifted[i] = near ? 0 : 1;
+        if (!near) continue;
+        const double qi = q ? q[i] : 1.0;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+            const int lx = (ox ? (cc[0] + 1 == L ? 0 : cc[0] + 1) : cc[0]) - x0;
+            const int ly = (oy ? (cc[1] + 1 == L ? 0 : cc[1] + 1) : cc[1]) - y0;
+            const int lz = (oz ? (cc[2] + 1 == L ? 0 : cc[2] + 1) : cc[2]) - z0;
+            if ((unsigned)lx < 64u && (unsigned)ly < (unsigned)kSpTY && (unsigned)lz < (unsigned)kSpTZ) {
+                const double w = lin_w(ox, ff[0]) * lin_w(oy, ff[1]) * lin_w(oz, ff[2]);
+                atomicAdd(&acc[lz][ly][lx], qi * w);
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kSpTZ * kSpTY * 64; t += blockDim.x) {
+        const int lx = t & 63, ly = (t >> 6) % kSpTY, lz = t / (64 * kSpTY);
+        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+        if (x < L && y < L && z < L) dst[((size_t)z * L + y) * L + x] = acc[lz][ly][lx];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_spread_drifted(int n, int L, double a, const double *__restrict__ q,
+                                                        const double *__restrict__ r,
+                                                        const int *__restrict__ drifted, double *__restrict__ dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !drifted[i]) return;
+    const double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
+    spread_ion(L, a, q ? q[i] : 1.0, u, dst);
+}
+
+// dst <- linear assignment of the ions (charges q, or 1 each without
+// `weighted`) onto the vertices; every vertex is written.
+hipError_t launch_spread_dense(memd_ctx *c, bool weighted, double *dst) {
+    const double *q = weighted ? c->q : nullptr;
+    if (c->n > 0 && c->sorted && c->L >= 16) {
+        const int L = c->L, nb = L * L;
+        const int tiles = ((L + 63) / 64) * ((L + kSpTY - 1) / kSpTY) * ((L + kSpTZ - 1) / kSpTZ);
+        hipLaunchKernelGGL(k_spread_tile, dim3(tiles), dim3(kThreads), 0, c->stream, c->n, L, c->a, q, c->r,
+                           c->bins + nb, c->drift, dst);
+        hipLaunchKernelGGL(k_spread_drifted, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, L, c->a,
+                           q, c->r, c->drift, dst);
+        return hipGetLastError();
+    }
+    hipError_t e = launch_fill(c->stream, dst, 0.0, c->Ns);
+    if (e != hipSuccess) return e;
+    return launch_spread(c, q, dst);
 }
 
 // ------------------------------------------------------------------ dipole
@@ -673,8 +851,12 @@ hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials,
 
 // Counting sort of the ions by lattice row (y, z cell of the position): the
 // deposit and force kernels then visit neighbouring ions together.
-__global__ void k_bin_count(int n, int L, double a, const double *__restrict__ r, int *__restrict__ count) {
+// Row counts of the ions (count all zero on entry); also clears the nlc list
+// counts lc (the lists are rebuilt after every binning).
+__global__ void k_bin_count(int n, int L, double a, const double *__restrict__ r, int *__restrict__ count,
+                            int *__restrict__ lc, int nlc) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int k = i; k < nlc; k += gridDim.x * blockDim.x) lc[k] = 0;
     if (i >= n) return;
     int cy, cz;
     double f;
@@ -683,12 +865,13 @@ __global__ void k_bin_count(int n, int L, double a, const double *__restrict__ r
     atomicAdd(&count[cy + L * cz], 1);
 }
 
-// Exclusive scan of count[0..nb) into start and cursor (one block of 1024).
+// Exclusive scan of count[0..nb) into start and cursor (one block of 1024),
+// leaving count all zero for the next binning.
 // The bins are taken in super-tiles of 16384: every thread loads its four
 // runs of four bins (bins base + 4096 j + 4t .. +3) at once, then the four
 // tiles of 4096 are scanned in turn (sums of four, wavefront prefix sums,
 // the 16 wavefront totals in LDS) with a running carry.
-__global__ __launch_bounds__(1024) void k_bin_scan(const int *__restrict__ count, int nb, int *__restrict__ start,
+__global__ __launch_bounds__(1024) void k_bin_scan(int *__restrict__ count, int nb, int *__restrict__ start,
                                                    int *__restrict__ cursor) {
     __shared__ int wsum[16];
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
@@ -708,6 +891,13 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const int *__restrict__ count
 #pragma unroll
                 for (int e = 0; e < 4; ++e) v[j][e] = idx + e < nb ? count[idx + e] : 0;
             }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int idx = base + 4096 * j + 4 * t;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (idx + e < nb) count[idx + e] = 0;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -820,12 +1010,13 @@ hipError_t launch_bin_ions(memd_ctx *c, bool reorder) {
     if (c->n == 0 || !c->order) return hipSuccess;
     c->lists_key = -1;  // slots and cells change: the fused deposit's lists are rebuilt before use
     const int nb = c->L * c->L;
-    const int g = (int)((nb + kThreads - 1) / kThreads) < 4096 ? (nb + kThreads - 1) / kThreads : 4096;
+    // count is all zero here (cleared at allocation and by every scan)
     int *count = c->bins, *start = c->bins + nb, *cursor = c->bins + 2 * (size_t)nb;
-    hipLaunchKernelGGL(k_fill_int, dim3(g), dim3(kThreads), 0, c->stream, count, 0, (size_t)nb);
+    const int nlc = c->list ? list_tiles(c) * kCountStride : 0;
     hipLaunchKernelGGL(k_bin_count, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->r,
-                       count);
+                       count, c->list_count, nlc);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, count, nb, start, cursor);
+    c->list_zero_key = c->list ? c->lf_rows * 4096 + c->lf_tz : -1;
     if (reorder) {
         hipLaunchKernelGGL(k_bin_reorder, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
                            c->r, c->q, c->F, c->perm, cursor, c->r_alt, c->q_alt, c->F_alt, c->perm_alt, c->order,
@@ -890,7 +1081,17 @@ hipError_t launch_finalize_dipole(hipStream_t s, const double *partials, int nbl
 __global__ void k_fin_sum(const double *partials, int nblk, int width, double *dst) {
     for (int w = 0; w < width; ++w) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += partials[width * b + w];
+        for (int b0 = threadIdx.x; b0 < nblk; b0 += 8 * blockDim.x) {
+            double v8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = b0 + u * (int)blockDim.x;
+                v8[u] = b < nblk ? partials[width * b + w] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (b0 + u * (int)blockDim.x < nblk) s += v8[u];
+        }
         double v[1] = {s};
         block_sum<1>(v);
         if (threadIdx.x == 0) dst[w] = v[0];
@@ -903,14 +1104,11 @@ hipError_t launch_finalize_sum(hipStream_t s, const double *partials, int nblk, 
 }
 
 __global__ void k_fin_audit(const double *partials, int nblk, double Ns, double *dst, double *hist) {
-    double mx = 0.0, ss = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-        mx = fmax(mx, partials[2 * b]);
-        ss += partials[2 * b + 1];
-    }
-    double v[1] = {ss};
+    double f[2];
+    strided_fold<2>(partials, nblk, threadIdx.x, blockDim.x, 1u, f);  // max |R|, sum R^2
+    double v[1] = {f[1]};
     block_sum<1>(v);
-    const double m = block_max(mx);
+    const double m = block_max(f[0]);
     if (threadIdx.x == 0) {
         dst[0] = m;
         dst[1] = sqrt(v[0] / Ns);
@@ -955,16 +1153,11 @@ hipError_t launch_finalize_energy(memd_ctx *c, const double *fpart, int fblk, co
 }
 
 __global__ void k_fin_epsh4(const double *partials, int nblk, double Ns, double *epsh, double *etamax) {
-    double s[3] = {0.0, 0.0, 0.0};
-    double mx = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-        s[0] += partials[4 * b];
-        s[1] += partials[4 * b + 1];
-        s[2] += partials[4 * b + 2];
-        mx = fmax(mx, partials[4 * b + 3]);
-    }
+    double f[4];
+    strided_fold<4>(partials, nblk, threadIdx.x, blockDim.x, 8u, f);  // sums of eta_d, max eta
+    double s[3] = {f[0], f[1], f[2]};
     block_sum<3>(s);
-    const double m = block_max(mx);
+    const double m = block_max(f[3]);
     if (threadIdx.x == 0) {
         epsh[0] = Ns / s[0];
         epsh[1] = Ns / s[1];

@@ -85,8 +85,8 @@ hipError_t solve_recursion(memd_ctx *c, double *D) {
     hipError_t e;
     const int L = c->L;
     const double a2 = c->a * c->a;
-    // rho <- charge assignment of the ions (rho is all-zero on entry)
-    if ((e = launch_spread(c, c->q, c->rho)) != hipSuccess) return e;
+    // rho <- charge assignment of the ions
+    if ((e = launch_spread_dense(c, true, c->rho)) != hipSuccess) return e;
     double *w = nullptr;
     const size_t LL = (size_t)L * L;
     if ((e = hipMallocAsync((void **)&w, (3 * L + 2 * LL) * sizeof(double), c->stream)) != hipSuccess) return e;

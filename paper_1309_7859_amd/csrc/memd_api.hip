@@ -140,20 +140,21 @@ double courant(const memd_ctx *c) {
     return c->c * c->dt * std::sqrt(3.0) / (c->a * std::sqrt(c->eps_min));
 }
 
-// Reduction scratch: site-loop partials (<= 4 per block of kRedBlocks), the
-// deposit's dipole partials (3 per block of 16 ions), the self-energy
-// partials (1 per block of 64 ions, from offset kRedBlocks * 4).
+// Reduction scratch: the solver's partials (<= 8 per block of kRedBlocks),
+// site-loop partials (<= 4 per block of kSiteBlocks), the deposit's dipole
+// partials (3 per block of 16 ions), the self-energy partials (1 per block
+// of 64 ions, from offset kSiteBlocks * 4).
 size_t partial_doubles(int n) {
     const size_t nn = (size_t)(n > 0 ? n : 1);
     const size_t dep = 3 * (nn / 16 + 16);
-    const size_t us = (size_t)kRedBlocks * 4 + nn / 64 + 16;
+    const size_t us = (size_t)kSiteBlocks * 4 + nn / 64 + 16;
     size_t m = (size_t)kRedBlocks * 8;
     if (dep > m) m = dep;
     if (us > m) m = us;
     return m + 64;
 }
 
-double *ion_partials(memd_ctx *c) { return c->partials + (size_t)kRedBlocks * 4; }
+double *ion_partials(memd_ctx *c) { return c->partials + (size_t)kSiteBlocks * 4; }
 
 // Read eps_h and the largest eta back, fix c on first use, check Courant.
 memd_status finish_permittivity(memd_ctx *c) {
@@ -199,11 +200,13 @@ hipError_t enqueue_energy(memd_ctx *c, double *dst, double *hist) {
     return e;
 }
 
-// Gauss audit of the current state (rho must already hold the assignment).
+// Gauss audit of the current state (rho <- the charge assignment, then the
+// residual).
 hipError_t enqueue_audit(memd_ctx *c, double *hist) {
     hipError_t e;
     int nb = 0;
     prof_begin(c, F_AUDIT);
+    if ((e = launch_spread_dense(c, true, c->rho)) != hipSuccess) return e;
     if ((e = launch_audit(c, c->D[c->cur], c->partials, &nb)) != hipSuccess) return e;
     e = launch_finalize_audit(c->stream, c->partials, nb, (double)c->Ns, c->scal + S_AUDIT, hist);
     prof_end(c, F_AUDIT);
@@ -253,8 +256,7 @@ void memd_destroy(memd_ctx *c) {
                     c->list_count, c->cbin, c->list_fail, c->du_slot, c->fq, c->ecell, c->Ft, c->fdone,
                     c->dip[0], c->dip[1],
                     c->perm, c->perm_alt, c->r_alt, c->q_alt, c->F_alt,
-                    c->stage, c->rho, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt,
-                    c->salt_nbar};
+                    c->stage, c->rho, c->drift, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -345,6 +347,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
         hipMalloc((void **)&c->dep_atomic, nn * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->bad_moves, sizeof(unsigned int)) != hipSuccess ||
         hipMalloc((void **)&c->rho, Ns * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->drift, nn * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->partials, partial_doubles(n) * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->dip[0], 3 * (nn / 64 + 32) * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->dip[1], 3 * (nn / 64 + 32) * sizeof(double)) != hipSuccess ||
@@ -357,6 +360,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     // Fused deposit: records by slot, and tile lists sized for the smallest
     // fused tile shape (64 x 4 x 2): twelve entries per ion plus 64 per tile.
     c->lists_key = -1;
+    c->list_zero_key = -1;
     if (n > 0 && p->L >= 16 && p->L <= 1024) {
         const size_t L = (size_t)p->L;
         const size_t tiles = ((L + 63) / 64) * ((L + 3) / 4) * ((L + 1) / 2);
@@ -387,6 +391,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     }
     hipMemsetAsync(c->rho, 0, Ns * sizeof(double), s);
     hipMemsetAsync(c->bad_moves, 0, sizeof(unsigned int), s);
+    hipMemsetAsync(c->bins, 0, (size_t)c->L * c->L * sizeof(int), s);  // bin counts: kept zero between binnings
     hipMemsetAsync(c->scal, 0, S_COUNT * sizeof(double), s);
     hipMemsetAsync(c->F, 0, 3 * nn * sizeof(double), s);
     c->sorted = false;
@@ -464,7 +469,6 @@ memd_status memd_set_salt_permittivity(memd_ctx *c, double eps_w, double slope, 
     if (st != MEMD_OK) return st;
     if (!c->salt_cnt) {
         CK(hipMalloc((void **)&c->salt_cnt, c->Ns * sizeof(double)));
-        CK(hipMalloc((void **)&c->salt_nbar, c->Ns * sizeof(double)));
     }
     c->salt_w = eps_w;
     c->salt_slope = slope;
@@ -561,7 +565,7 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
             double *dip_out = c->dip[c->step_index & 1];
             prof_begin(c, F_DEPOSIT);
             CK(launch_ion_step(c, c->D[c->cur], c->D[nx], dd && pack_next ? dd + per * (t + 1) : nullptr,
-                               seed, tstep, sigma, dip_out, &nb, pack_next, audit_now));
+                               seed, tstep, sigma, dip_out, &nb, pack_next));
             prof_end(c, F_DEPOSIT);
             recs_ready = pack_next;
             dip_prev = dip_out;
@@ -571,7 +575,7 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
                 CK(launch_finalize_dipole(c->stream, dip_prev, dip_nb, c->scal + S_P));
         } else {
             prof_begin(c, F_DEPOSIT);
-            CK(launch_deposit(c, c->D[nx], dstep, audit_now, c->partials, &nb, seed, tstep, sigma));
+            CK(launch_deposit(c, c->D[nx], dstep, c->partials, &nb, seed, tstep, sigma));
             prof_end(c, F_DEPOSIT);
             c->cur = nx;
             prof_begin(c, F_FORCES);
@@ -676,7 +680,6 @@ memd_status memd_energy(memd_ctx *c, memd_energy_t *out) {
 
 memd_status memd_gauss_residual(memd_ctx *c, double *max_abs, double *rms) {
     CHECK_CTX(c);
-    CK(launch_spread(c, c->q, c->rho));
     CK(enqueue_audit(c, nullptr));
     double h[2];
     CK(copy_out(c, h, c->scal + S_AUDIT, 2 * sizeof(double)));

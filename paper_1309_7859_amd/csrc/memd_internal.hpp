@@ -32,7 +32,8 @@ enum Family : int {
     F_SALT = 6, F_NFAM = 7
 };
 
-constexpr int kRedBlocks = 1024;   // grid of the site-loop reductions
+constexpr int kRedBlocks = 1024;   // grid of the solver's reductions
+constexpr int kSiteBlocks = 8192;  // grid of the field site-loop reductions (energy, audit, permittivity)
 constexpr int kThreads = 256;      // threads per block of the plain kernels
 
 struct EtaDesc {
@@ -73,8 +74,7 @@ struct memd_ctx {
     bool c_fixed;
     int salt_every;
     double salt_w, salt_slope, salt_floor;
-    double *salt_cnt;   // FP64 [Ns] work for the salt permittivity
-    double *salt_nbar;  // FP64 [Ns]
+    double *salt_cnt;  // FP64 [Ns]: ion counts of the salt permittivity
 
     // fields: ping-pong buffers, cur holds the live state
     void *D[2];
@@ -114,6 +114,7 @@ struct memd_ctx {
     size_t list_entries;
     int list_tiles_max;
     int lists_key;
+    int list_zero_key;  // shape whose list counts are all zero (-1: none)
     int *dep_atomic;
     unsigned int *bad_moves;  // rejected displacement components (not finite or > L a)
     bool fuse_deposit;
@@ -122,8 +123,9 @@ struct memd_ctx {
     size_t stage_bytes;
 
     // reductions and audit
-    double *rho;       // FP64 [Ns], kept all-zero between uses
-    double *partials;  // FP64 [kRedBlocks * 8]
+    double *rho;       // FP64 [Ns]: the charge assignment of the last audit
+    int *drift;        // [n] by storage index: ion left to the atomic pass of the spread
+    double *partials;  // FP64 reduction scratch (partial_doubles)
     double *dip[2];    // FP64 per-block q r sums of the ion step, alternating by step
     double *scal;      // FP64 [S_COUNT]
     double *hist_audit;   // FP64 [2*hist_cap]
@@ -165,7 +167,8 @@ bool fused_deposit_ok(const memd_ctx *c);
 int list_tiles(const memd_ctx *c);
 int list_cap(const memd_ctx *c);
 // Tile lists of the fused deposit for the current tile shape and positions.
-hipError_t launch_build_lists(memd_ctx *c);
+hipError_t launch_build_lists(memd_ctx *c, bool pack, const double *disp, uint64_t seed, uint32_t t,
+                              double sigma);
 // 12 / (sum of eta over each cell's 12 edges), after any permittivity change
 // (no-op when the context has no fused deposit).
 hipError_t launch_ecell(memd_ctx *c);
@@ -175,11 +178,9 @@ hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint
 // scalars' P), irregular ions deposited into Dnext with global atomics,
 // every position advanced by the displacement stored with its record,
 // dipole partials into dip_out (nparts of them), the next step's deposit
-// records (pack_next; displacements disp_next or the Philox stream at t + 1)
-// and rho for the audit (spread_rho).
+// records (pack_next; displacements disp_next or the Philox stream at t + 1).
 hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const double *disp_next,
-                           uint64_t seed, uint32_t t, double sigma, double *dip_out, int *nparts, bool pack_next,
-                           bool spread_rho);
+                           uint64_t seed, uint32_t t, double sigma, double *dip_out, int *nparts, bool pack_next);
 hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
                                int *nblk);
 hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk);
@@ -194,10 +195,12 @@ hipError_t launch_fill(hipStream_t s, double *dst, double v, size_t count);
 
 // ---- launchers (ion kernels) ----
 // disp == nullptr: displacements from the Philox stream (seed, step t, sigma)
-hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, bool spread_rho,
-                          double *partials, int *nblk, uint64_t seed = 0, uint32_t t = 0,
-                          double sigma = 0.0);
+hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, double *partials, int *nblk,
+                          uint64_t seed = 0, uint32_t t = 0, double sigma = 0.0);
 hipError_t launch_spread(memd_ctx *c, const double *charges_or_null, double *dst);
+// dst <- the assignment of every ion (charges, or 1 each without weighted);
+// writes every vertex (no global atomics once the ions are in bin order).
+hipError_t launch_spread_dense(memd_ctx *c, bool weighted, double *dst);
 hipError_t launch_dipole(memd_ctx *c, double *partials, int *nblk);
 hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk);
 // Row binning of the ions (order, slot, row counts/starts); with

@@ -64,9 +64,10 @@ size_t resident_bytes(int L, int n) {
     size_t b = 4 * 3 * Ns * sizeof(float)            // D, B ping-pong
                + Ns * sizeof(double)                 // rho
                + 3 * (size_t)L * L * sizeof(int)     // bins
-               + nn * (14 * sizeof(double) + 6 * sizeof(int))  // ion arrays and their re-binning targets
+               + nn * (14 * sizeof(double) + 7 * sizeof(int))  // ion arrays and their re-binning targets
                + (2 + 5) * 4096 * sizeof(double)     // histories
-               + 3 * (size_t)L * sizeof(float) + (1 << 16);
+               + 3 * (size_t)L * sizeof(float) + (1 << 16)
+               + ((size_t)kSiteBlocks * 4 + nn / 16 * 3 + 4096) * sizeof(double);  // reduction scratch
     if (n > 0 && L >= 16 && L <= 1024) {  // tile buckets of the fused deposit (FP32 records)
         const size_t tiles = (((size_t)L + 63) / 64) * (((size_t)L + 3) / 4) * (((size_t)L + 1) / 2);
         b += (4 * nn + 64 * tiles) * (16 + 24 * sizeof(float)) + tiles * 128;

@@ -412,6 +412,41 @@ def test_fused_deposit_with_stale_bins():
     run_parity(S, G, disp, {5, 25}, 1e-10, 1e-12, 1e-10, audit_each=True)
 
 
+@pytest.mark.parametrize("prec", [memd.FP64, memd.FP32_MIXED])
+def test_dense_spread_with_drifted_ions(prec):
+    """Ions stay in the bin order of the first step (re-binning every 1000
+    steps) while they drift several rows: the charge assignment of every
+    audit and the ion counts of the salt permittivity (every 3 steps) take
+    the ions that left their bin rows through the atomic pass, and stay
+    exact."""
+    L, n = 24, 300
+    rng = np.random.default_rng(23)
+    r = rng.uniform(0, L, size=(n, 3))
+    q = np.tile([1.0, -1.0, 2.0, -2.0], n // 4)
+    S, G = pair(L, q, r, dt=0.01, eps_min=70.0, precision=prec)
+    S.set_eps_salt()
+    G.set_salt(80.0, 15.0, 1.0, every=3)
+    memd.memd_set_options(G.ctx, 1, 1000)
+    S.initial_solve(1e-13)
+    share_state(S, G)
+    fp32 = prec == memd.FP32_MIXED
+    disp = rng.normal(0, 0.4, size=(24, n, 3))
+    for t in range(24):
+        if t % 3 == 0:
+            S.set_eps_salt()
+        S.step(disp[t])
+        G.step(disp[t], 1)
+        m, _ = G.gauss_residual()
+        assert m <= (1e-5 * 2.0 if fp32 else 1e-12), (t, m)
+    drift = np.abs(G.state()[2].reshape(-1, 3) - r).max()
+    assert drift > 2.0  # ions left their bin rows
+    Fo, _ = S.forces()
+    assert force_err(G.forces(), Fo) <= (1e-4 if fp32 else 1e-10)
+    if not fp32:
+        errs = energy_err(G.energy(), S.energy())
+        assert max(errs.values()) <= 1e-10, errs
+
+
 @pytest.mark.parametrize("prec", [memd.FP32_MIXED, memd.FP64])
 def test_fused_deposit_list_overflow(prec):
     """2000 ions packed into a 3 x 3 x 3 cell corner of a 32^3 lattice: the
