@@ -504,12 +504,26 @@ __global__ __launch_bounds__(256) void k_salt_tile(const double *__restrict__ cn
     for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int x0 = (tile % ntx) * 64, y0 = ((tile / ntx) % nty) * 4, z0 = (tile / (ntx * nty)) * kSaltTZ;
         const int z1 = min(z0 + kSaltTZ, L);
-        for (int R = z0 - 1; R <= z1 + 1; ++R) {
+        // this thread's (up to) two entries of a staged plane, the next plane
+        // in flight while the current one is processed
+        auto fetch = [&](int R, double (&v)[2]) {
             const size_t zoff = (size_t)wrapc(R, L) * L * L;
-            for (int t = threadIdx.x; t < 7 * 67; t += 256) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int t = threadIdx.x + 256 * j;
                 const int iy = t / 67, ix = t - iy * 67;
-                sc[iy][ix] = cnt[zoff + (size_t)wrapc(y0 - 1 + iy, L) * L + wrapc(x0 - 1 + ix, L)];
+                v[j] = t < 7 * 67 ? cnt[zoff + (size_t)wrapc(y0 - 1 + iy, L) * L + wrapc(x0 - 1 + ix, L)] : 0.0;
             }
+        };
+        double pl[2];
+        fetch(z0 - 1, pl);
+        for (int R = z0 - 1; R <= z1 + 1; ++R) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int t = threadIdx.x + 256 * j;
+                if (t < 7 * 67) (&sc[0][0])[t] = pl[j];
+            }
+            if (R <= z1) fetch(R + 1, pl);
             __syncthreads();
             const int rs = (R + 3) % 3;
             for (int t = threadIdx.x; t < 5 * 65; t += 256) {

@@ -437,7 +437,7 @@ struct IonStepArgs {
     const double *q;
     const double *r;
     double *r_out;
-    const int *order;
+    const int *order;  // null: the identity (ions stored in bin order)
     const int *perm;                 // storage index -> caller index (displacements), null: identity
     const double *disp_next;  // null: the Philox displacements of step t + 1
     uint64_t seed;
@@ -464,18 +464,20 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
     const bool mover = threadIdx.x >= kIonStepIons;
     const int s = xcd_logical(blockIdx.x, gridDim.x) * kIonStepIons + (threadIdx.x & (kIonStepIons - 1));
     const bool live = s < A.n;
-    const int i = live ? A.order[s] : 0;
+    const int i = live ? (A.order ? A.order[s] : s) : 0;
     double F[3] = {0.0, 0.0, 0.0}, P[3] = {0.0, 0.0, 0.0}, qi = 0.0;
     if (!mover) {
         // lattice part and self force of r^n on D^n (from the leapfrog tile
         // that owns the ion's cell, else gathered here); the dipole term is
-        // added at the end (x + 0 + y rounds as x + y)
+        // added at the end (x + 0 + y rounds as x + y).  The tile result is
+        // read with its stamp, not after it.
         if (live) {
             qi = A.q[i];
+            const double ft[3] = {A.Ft[3 * s], A.Ft[3 * s + 1], A.Ft[3 * s + 2]};
             if (A.fdone[s] == A.tag) {
-                F[0] = A.Ft[3 * s];
-                F[1] = A.Ft[3 * s + 1];
-                F[2] = A.Ft[3 * s + 2];
+                F[0] = ft[0];
+                F[1] = ft[1];
+                F[2] = ft[2];
             } else {
                 const double u[3] = {A.r[3 * i], A.r[3 * i + 1], A.r[3 * i + 2]};
                 const EtaView<T> ev{A.eta_mode, A.eta_uni, A.eta_prof, A.eta_link};
@@ -491,7 +493,10 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
         // written; the next step's is gathered from the caller's order
         double du[3] = {A.out.du[3 * s], A.out.du[3 * s + 1], A.out.du[3 * s + 2]};
         double dn[3] = {0.0, 0.0, 0.0};
+        int lfail = 0, lcell = 0;  // the slot's list state, for the next record
         if (A.pack) {
+            lfail = A.out.list_fail[s];
+            lcell = A.out.cbin[s];
             if (A.disp_next) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) dn[d] = A.disp_next[3 * ci + d];
@@ -512,7 +517,7 @@ __global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
         for (int d = 0; d < 3; ++d) P[d] = qi * u[d];
         if (A.pack) {
             sanitize_move(dn, A.a, A.L, A.bad);
-            A.dep_atomic[s] = write_record<T>(A.L, A.a, qi, u, dn, s, A.out) ? 1 : 0;
+            A.dep_atomic[s] = write_record_at<T>(A.L, A.a, qi, u, dn, s, A.out, lfail, lcell) ? 1 : 0;
         }
     }
     if (mover) {
@@ -546,7 +551,7 @@ hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const dou
         A.q = c->q;
         A.r = c->r;
         A.r_out = c->r_alt;
-        A.order = c->order;
+        A.order = c->sorted ? nullptr : c->order;
         A.perm = c->perm;
         A.disp_next = disp_next;
         A.seed = seed;
@@ -824,7 +829,7 @@ static ForceArgs<T> force_args(memd_ctx *c, const void *D) {
     A.scal = c->scal;
     A.F = c->F;
     A.uself_partials = nullptr;
-    A.order = c->order;
+    A.order = c->sorted ? nullptr : c->order;  // identity once the ions are stored in bin order
     A.dip_partials = nullptr;
     A.dip_nblk = 0;
     return A;
