@@ -3,8 +3,10 @@
 // (section "Periodicity"), and the relaxation to curl E = 0 by minimising the
 // field energy over D + C^T theta (conjugate gradients on C eta C^T theta =
 // -C eta D with a Jacobi preconditioner; D is updated in place of theta).
-// Also the periodic lattice Green's function used by the self-energy
-// correction (eq. greens and the Brillouin-zone sum that follows it).
+// For a uniform or planar permittivity the same minimiser is computed
+// directly (a 2-D DFT and one tridiagonal solve per mode).  Also the
+// periodic lattice Green's function used by the self-energy correction
+// (eq. greens and the Brillouin-zone sum that follows it).
 #include "device_util.hpp"
 #include "memd_internal.hpp"
 
@@ -467,6 +469,204 @@ memd_status solve_relax(memd_ctx *c, double *D, double tol, int max_iter, int *i
     if (res_out) *res_out = res;
     if (st == MEMD_OK && !converged) st = MEMD_ENOCONV;
     return st;
+}
+
+// ------------------------------------------------ direct planar solution
+//
+// When eta is uniform or depends only on the plane (eta_d(k)), the field the
+// relaxation converges to is reached directly.  Its non-uniform part is
+// E = -grad phi with phi periodic: Gauss's law, with D_d = -eps_d (phi(v+e_d)
+// - phi(v)) / a, reads
+//   a sum_d [eps_d(v) (phi(v+e_d) - phi(v)) - eps_d(v-e_d) (phi(v) - phi(v-e_d))] = -q_v,
+// which a 2-D DFT over (x, y) turns into one cyclic tridiagonal system along
+// z per mode (mx, my) != (0, 0):
+//   eps_z(k-1) phi_{k-1} + [eps_x(k) lx + eps_y(k) ly - eps_z(k) - eps_z(k-1)] phi_k
+//   + eps_z(k) phi_{k+1} = -q_k / a,   l = 2 cos(2 pi m / L) - 2.
+// The plane means (mode (0, 0)) are fixed by the constraints the relaxation
+// keeps: mean D = -P/V (section "Periodicity") and no circulation on any
+// plaquette, so E_x and E_y are one constant across planes (D_x(k) =
+// eps_x(k) E0_x), and D_z(k) follows the plane charges by Gauss's law up to
+// the constant that sets its mean.  Everything is FP64.
+
+// eps_d(k) = 1 / eta_d(k) of the stored permittivity (uniform or per plane)
+template <typename T>
+__global__ void k_planar_eps(int mode, double eta_uni, const T *__restrict__ prof, int L, double *__restrict__ eps) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * L) return;
+    eps[t] = 1.0 / (mode == ETA_UNIFORM ? eta_uni : (double)prof[t]);
+}
+
+__global__ void k_to_complex(const double *__restrict__ x, size_t n, double2 *__restrict__ out) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        out[t] = make_double2(x[t], 0.0);
+}
+
+// One DFT of length L (<= 256) along x (axis 0) or y (axis 1) per workgroup:
+// out[m] = sum_n in[n] exp(sign 2 pi i m n / L), the twiddles from a table
+// of the L angles 2 pi t / L (t = m n mod L).
+__global__ __launch_bounds__(256) void k_dft_line(const double2 *__restrict__ in, double2 *__restrict__ out, int L,
+                                                  int axis, double sign) {
+    __shared__ double2 line[256];
+    __shared__ double2 tw[256];
+    const int b = blockIdx.x;  // line: (j, k) along x, (i, k) along y
+    const size_t LL = (size_t)L * L;
+    const size_t base = axis == 0 ? (size_t)b * L : (size_t)(b % L) + (size_t)(b / L) * LL;
+    const size_t stride = axis == 0 ? 1 : (size_t)L;
+    const int t = threadIdx.x;
+    if (t < L) {
+        line[t] = in[base + t * stride];
+        double sn, cs;
+        sincospi(2.0 * t / L, &sn, &cs);
+        tw[t] = make_double2(cs, sign * sn);
+    }
+    __syncthreads();
+    if (t < L) {
+        double re = 0.0, im = 0.0;
+        int idx = 0;
+        for (int n = 0; n < L; ++n) {
+            const double2 x = line[n], w = tw[idx];
+            re += x.x * w.x - x.y * w.y;
+            im += x.x * w.y + x.y * w.x;
+            idx += t;
+            idx -= idx >= L ? L : 0;
+        }
+        out[base + t * stride] = make_double2(re, im);
+    }
+}
+
+// Plane means: from the plane charges q_k (the (0,0) coefficients of the
+// forward transform), D_z(k) - D_z(k-1) = q_k / (a^2 L^2) shifted to mean
+// -P_z/V, and E0_{x,y} = -P_{x,y} / (V mean_k eps_{x,y}(k)).  One thread.
+__global__ void k_planar_means(const double2 *__restrict__ A, const double *__restrict__ eps, int L, double a,
+                               double V, const double *__restrict__ P, double *__restrict__ dz, double *__restrict__ e0) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const size_t LL = (size_t)L * L;
+    const double scale = 1.0 / (a * a * (double)LL);
+    double run = 0.0, sum = 0.0;
+    for (int k = 0; k < L; ++k) {
+        run += A[(size_t)k * LL].x * scale;
+        dz[k] = run;
+        sum += run;
+    }
+    const double shift = -P[2] / V - sum / L;
+    for (int k = 0; k < L; ++k) dz[k] += shift;
+    double mx = 0.0, my = 0.0;
+    for (int k = 0; k < L; ++k) {
+        mx += eps[k];
+        my += eps[L + k];
+    }
+    e0[0] = -P[0] / (V * (mx / L));
+    e0[1] = -P[1] / (V * (my / L));
+}
+
+// The cyclic tridiagonal system of each mode (mx, my) != (0, 0), in place on
+// A (right-hand side -q_k / a in, phi_k out), by the Sherman-Morrison form of
+// the Thomas algorithm; w holds 4 L doubles per mode.
+__global__ void k_planar_tridiag(double2 *__restrict__ A, const double *__restrict__ eps, int L, double a,
+                                 double *__restrict__ w) {
+    const int mode = blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t LL = (size_t)L * L;
+    if (mode >= (int)LL) return;
+    double2 *x = A + mode;  // element k at x[k LL]
+    if (mode == 0) {
+        for (int k = 0; k < L; ++k) x[(size_t)k * LL] = make_double2(0.0, 0.0);
+        return;
+    }
+    const int mx = mode % L, my = mode / L;
+    const double lx = 2.0 * cospi(2.0 * mx / L) - 2.0, ly = 2.0 * cospi(2.0 * my / L) - 2.0;
+    const double *ex = eps, *ey = eps + L, *ez = eps + 2 * L;
+    double *cp = w + (size_t)mode * 4 * L, *yr = cp + L, *yi = cp + 2 * L, *zz = cp + 3 * L;
+    auto diag = [&](int k) { return ex[k] * lx + ey[k] * ly - ez[k] - ez[k == 0 ? L - 1 : k - 1]; };
+    const double a0 = ez[L - 1];   // row 0, column L-1
+    const double cl = ez[L - 1];   // row L-1, column 0
+    const double gam = -diag(0);
+    // forward elimination of T (corners removed, b_0 - gam, b_{L-1} - a0 cl / gam) for the
+    // right-hand sides d (real, imaginary) and u = (gam, 0, ..., 0, cl)
+    double bp = diag(0) - gam;
+    double2 d0 = x[0];
+    cp[0] = ez[0] / bp;
+    yr[0] = (-d0.x / a) / bp;
+    yi[0] = (-d0.y / a) / bp;
+    zz[0] = gam / bp;
+    for (int k = 1; k < L; ++k) {
+        const double lo = ez[k - 1];
+        double bk = diag(k);
+        if (k == L - 1) bk -= a0 * cl / gam;
+        const double m = bk - lo * cp[k - 1];
+        const double2 dk = x[(size_t)k * LL];
+        cp[k] = ez[k] / m;
+        yr[k] = (-dk.x / a - lo * yr[k - 1]) / m;
+        yi[k] = (-dk.y / a - lo * yi[k - 1]) / m;
+        zz[k] = ((k == L - 1 ? cl : 0.0) - lo * zz[k - 1]) / m;
+    }
+    for (int k = L - 2; k >= 0; --k) {
+        yr[k] -= cp[k] * yr[k + 1];
+        yi[k] -= cp[k] * yi[k + 1];
+        zz[k] -= cp[k] * zz[k + 1];
+    }
+    const double vf = a0 / gam;
+    const double den = 1.0 + zz[0] + vf * zz[L - 1];
+    const double fr = (yr[0] + vf * yr[L - 1]) / den, fi = (yi[0] + vf * yi[L - 1]) / den;
+    for (int k = 0; k < L; ++k) x[(size_t)k * LL] = make_double2(yr[k] - zz[k] * fr, yi[k] - zz[k] * fi);
+}
+
+// D from phi (the inverse transform, not yet divided by L^2) and the plane
+// means.
+__global__ void k_planar_field(const double2 *__restrict__ A, const double *__restrict__ eps,
+                               const double *__restrict__ dz, const double *__restrict__ e0, int L, double a,
+                               double *__restrict__ D) {
+    const size_t Ns = (size_t)L * L * L, LL = (size_t)L * L;
+    const double inv = 1.0 / ((double)LL * a);
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns; v += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(v % L), j = (int)((v / L) % L), k = (int)(v / LL);
+        const size_t row = v - (size_t)i, plane = v - (size_t)j * L - (size_t)i;
+        const size_t vx = row + (i + 1 == L ? 0 : i + 1);
+        const size_t vy = plane + (size_t)(j + 1 == L ? 0 : j + 1) * L + i;
+        const size_t vz = (size_t)(k + 1 == L ? 0 : k + 1) * LL + (size_t)j * L + i;
+        const double ph = A[v].x;
+        D[v] = -eps[k] * (A[vx].x - ph) * inv + eps[k] * e0[0];
+        D[Ns + v] = -eps[L + k] * (A[vy].x - ph) * inv + eps[L + k] * e0[1];
+        D[2 * Ns + v] = -eps[2 * L + k] * (A[vz].x - ph) * inv + dz[k];
+    }
+}
+
+bool planar_solve_ok(const memd_ctx *c) {
+    return (c->eta_mode == ETA_UNIFORM || c->eta_mode == ETA_ZPROF) && c->L >= 4 && c->L <= 128;
+}
+
+hipError_t solve_planar(memd_ctx *c, double *D) {
+    hipError_t e;
+    const int L = c->L;
+    const size_t Ns = c->Ns, LL = (size_t)L * L;
+    hipStream_t s = c->stream;
+    // the dipole of the ions (their mean field) and their charge assignment
+    int nb = 0;
+    if ((e = launch_dipole(c, c->partials, &nb)) != hipSuccess) return e;
+    if ((e = launch_finalize_dipole(s, c->partials, nb, c->scal + S_P)) != hipSuccess) return e;
+    if ((e = launch_spread_dense(c, true, c->rho)) != hipSuccess) return e;
+    double *buf = nullptr;
+    const size_t nbytes = 2 * Ns * sizeof(double2) + (4 * LL * L + 6 * L + 2) * sizeof(double);
+    if ((e = hipMallocAsync((void **)&buf, nbytes, s)) != hipSuccess) return e;
+    double2 *A = (double2 *)buf, *Bt = A + Ns;
+    double *w = (double *)(Bt + Ns), *eps = w + 4 * LL * L, *dz = eps + 3 * L, *e0 = dz + L;
+    if (c->fp32)
+        hipLaunchKernelGGL(k_planar_eps<float>, dim3((3 * L + 255) / 256), dim3(256), 0, s, c->eta_mode, c->eta_uni,
+                           (const float *)c->eta_prof, L, eps);
+    else
+        hipLaunchKernelGGL(k_planar_eps<double>, dim3((3 * L + 255) / 256), dim3(256), 0, s, c->eta_mode,
+                           c->eta_uni, (const double *)c->eta_prof, L, eps);
+    const int gs = grid_m(Ns);
+    hipLaunchKernelGGL(k_to_complex, dim3(gs), dim3(kThreads), 0, s, c->rho, Ns, A);
+    const int lines = (int)LL;  // L^2 lines along each axis
+    hipLaunchKernelGGL(k_dft_line, dim3(lines), dim3(256), 0, s, A, Bt, L, 0, -1.0);
+    hipLaunchKernelGGL(k_dft_line, dim3(lines), dim3(256), 0, s, Bt, A, L, 1, -1.0);
+    hipLaunchKernelGGL(k_planar_means, dim3(1), dim3(64), 0, s, A, eps, L, c->a, c->V, c->scal + S_P, dz, e0);
+    hipLaunchKernelGGL(k_planar_tridiag, dim3((unsigned)((LL + 255) / 256)), dim3(256), 0, s, A, eps, L, c->a, w);
+    hipLaunchKernelGGL(k_dft_line, dim3(lines), dim3(256), 0, s, A, Bt, L, 1, 1.0);
+    hipLaunchKernelGGL(k_dft_line, dim3(lines), dim3(256), 0, s, Bt, A, L, 0, 1.0);
+    hipLaunchKernelGGL(k_planar_field, dim3(gs), dim3(kThreads), 0, s, A, eps, dz, e0, L, c->a, D);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipFreeAsync(buf, s);
 }
 
 // ------------------------------------------------------- Green's function

@@ -496,8 +496,13 @@ memd_status memd_initial_gauss_solve(memd_ctx *c, double tol, int max_iter, int 
     } else {
         Dw = (double *)c->D[c->cur];
     }
-    CK(solve_recursion(c, Dw));
-    CK(solve_mean_shift(c, Dw));
+    if (planar_solve_ok(c)) {
+        // the minimiser itself; the relaxation then only checks it
+        CK(solve_planar(c, Dw));
+    } else {
+        CK(solve_recursion(c, Dw));
+        CK(solve_mean_shift(c, Dw));
+    }
     memd_status st = solve_relax(c, Dw, tol, max_iter, iters_out, res_out);
     if (st == MEMD_EDEVICE || st == MEMD_ENOMEM) {
         if (st == MEMD_EDEVICE) c->poisoned = true;

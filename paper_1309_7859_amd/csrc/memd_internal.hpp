@@ -234,6 +234,9 @@ memd_status autotune_leapfrog(memd_ctx *c, int reps, const char *cache_path, int
 // ---- initial solve (FP64) ----
 hipError_t solve_recursion(memd_ctx *c, double *D);
 hipError_t solve_mean_shift(memd_ctx *c, double *D);
+// uniform or planar permittivity, 4 <= L <= 128: the relaxed field directly
+bool planar_solve_ok(const memd_ctx *c);
+hipError_t solve_planar(memd_ctx *c, double *D);
 memd_status solve_relax(memd_ctx *c, double *D, double tol, int max_iter, int *iters,
                         double *res);
 

@@ -98,6 +98,7 @@ struct memd_server {
     bool stopping = false;
     std::vector<std::thread> workers;
     std::deque<Request *> init_queue;   // admitted, waiting for a worker
+    std::deque<Request *> retire_queue; // finished, results to be taken out by a worker
     std::deque<Request *> pending;      // waiting for admission
     std::vector<Request *> ready;       // initialised, waiting to join the table
     std::map<uint64_t, std::unique_ptr<Request>> all;
@@ -127,16 +128,26 @@ struct memd_server {
 
 namespace {
 
+void finish_request(memd_server *s, Request *rq);
+
 void worker_main(memd_server *s) {
     hipSetDevice(s->device);
     for (;;) {
         Request *rq = nullptr;
+        bool retiring = false;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv.wait(lk, [&] { return s->stopping || !s->init_queue.empty(); });
+            s->cv.wait(lk, [&] { return s->stopping || !s->init_queue.empty() || !s->retire_queue.empty(); });
             if (s->stopping) return;
-            rq = s->init_queue.front();
-            s->init_queue.pop_front();
+            // finished replicas first: their memory admits the next requests
+            retiring = !s->retire_queue.empty();
+            std::deque<Request *> &q = retiring ? s->retire_queue : s->init_queue;
+            rq = q.front();
+            q.pop_front();
+        }
+        if (retiring) {
+            finish_request(s, rq);
+            continue;
         }
         memd_status st = memd_init_lattice(&rq->ctx, &rq->p, rq->n, rq->q.data(), rq->r0.data(), nullptr);
         if (st == MEMD_OK) st = memd_set_permittivity(rq->ctx, rq->eps_mode, rq->eps.data(), 4.0);
@@ -284,43 +295,54 @@ hipError_t join_ready(memd_server *s) {
     return hipSuccess;
 }
 
-// Retire finished replicas: results out, context destroyed, memory and slot freed.
+// Retire finished replicas: out of the table (their slot is free for the
+// next one to join); a worker takes their results out and frees their
+// memory, off this thread, so the step graph keeps its queue.
 hipError_t retire(memd_server *s) {
     std::vector<Request *> keep;
+    bool any = false;
     for (Request *rq : s->active) {
         const int st = s->h_steps[rq->slot];
         if (st < rq->nsteps) {
             keep.push_back(rq);
             continue;
         }
-        memd_ctx *c = rq->ctx;
-        c->cur = rq->nsteps & 1;
-        c->step_index = rq->nsteps;
-        rq->F.assign(3 * (size_t)rq->n, 0.0);
-        memd_status ms = memd_forces(c, rq->F.data());
-        if (ms == MEMD_OK) ms = memd_energy(c, &rq->E);
-        if (ms == MEMD_OK) ms = memd_gauss_residual(c, &rq->gauss, nullptr);
-        bool finite = std::isfinite(rq->E.E_corrected);
-        for (double f : rq->F) finite = finite && std::isfinite(f);
-        rq->t_done = s->now();
-        rq->state = (ms == MEMD_OK && finite) ? Q_DONE : Q_FAILED;
-        rq->error = ms != MEMD_OK ? ms : (finite ? MEMD_OK : MEMD_EDEVICE);
-        memd_destroy(c);
-        rq->ctx = nullptr;
-        hipFree(rq->dip);
-        rq->dip = nullptr;
         s->free_slots.push_back(rq->slot);
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->used -= rq->bytes_resident;
-            --s->slots_used;
-            if (rq->state == Q_DONE) ++s->done_count;
-            else ++s->failed_count;
-        }
         s->table_dirty = true;
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->retire_queue.push_back(rq);
+        any = true;
     }
     s->active.swap(keep);
+    if (any) s->cv.notify_all();
     return hipSuccess;
+}
+
+// Results of a finished replica (forces, energy, Gauss audit of its final
+// state, on its context's own stream), then its context destroyed and its
+// memory returned to the budget.
+void finish_request(memd_server *s, Request *rq) {
+    memd_ctx *c = rq->ctx;
+    c->cur = rq->nsteps & 1;
+    c->step_index = rq->nsteps;
+    rq->F.assign(3 * (size_t)rq->n, 0.0);
+    memd_status ms = memd_forces(c, rq->F.data());
+    if (ms == MEMD_OK) ms = memd_energy(c, &rq->E);
+    if (ms == MEMD_OK) ms = memd_gauss_residual(c, &rq->gauss, nullptr);
+    bool finite = std::isfinite(rq->E.E_corrected);
+    for (double f : rq->F) finite = finite && std::isfinite(f);
+    memd_destroy(c);
+    hipFree(rq->dip);
+    std::lock_guard<std::mutex> lk(s->mu);
+    rq->ctx = nullptr;
+    rq->dip = nullptr;
+    rq->t_done = s->now();
+    rq->state = (ms == MEMD_OK && finite) ? Q_DONE : Q_FAILED;
+    rq->error = ms != MEMD_OK ? ms : (finite ? MEMD_OK : MEMD_EDEVICE);
+    s->used -= rq->bytes_resident;
+    --s->slots_used;
+    if (rq->state == Q_DONE) ++s->done_count;
+    else ++s->failed_count;
 }
 
 }  // namespace
