@@ -35,8 +35,13 @@ def _rng_system(seed, n, L, valence2=False):
 
 # ------------------------------------------------------------ initial solve
 
-@pytest.mark.parametrize("case", ["c1", "site12", "zsite16", "link10"])
+@pytest.mark.parametrize("case", ["c1", "site12", "zsite16", "link10", "uniform12", "zsite24"])
 def test_initial_solve_parity(case):
+    """The GPU initial solution against the oracle's relaxation.  Uniform and
+    planar permittivities (c1, zsite16, uniform12, zsite24: lattice sides
+    that are and are not powers of two) are solved directly (a 2-D DFT and a
+    tridiagonal solve per mode), so the relaxation that follows has nothing
+    left to do; per-site and per-link ones are relaxed."""
     if case == "c1":
         w = W.WORKLOADS["c1"]
         s = W.make_system(w, steps=0)
@@ -55,6 +60,17 @@ def test_initial_solve_parity(case):
         ez = W.tanh_slab(L, 1.0)
         S, G = pair(L, q, r, eps_min=ez.min())
         apply_eps(S, G, "zsite", eps_z=ez)
+    elif case == "uniform12":
+        L = 12
+        rng, q, r = _rng_system(8, 14, L, True)
+        S, G = pair(L, q, r, eps_min=5.0)
+        apply_eps(S, G, "uniform", 5.0)
+    elif case == "zsite24":
+        L = 24
+        rng, q, r = _rng_system(9, 40, L, True)
+        ez = W.tanh_slab(L, 1.0)
+        S, G = pair(L, q, r, eps_min=ez.min())
+        apply_eps(S, G, "zsite", eps_z=ez)
     else:
         L = 10
         rng, q, r = _rng_system(7, 8, L)
@@ -65,6 +81,8 @@ def test_initial_solve_parity(case):
     assert rc == 0
     st, git, gres = G.solve(1e-13)
     assert st == memd.OK and gres <= 1e-13
+    if case in ("c1", "zsite16", "uniform12", "zsite24"):
+        assert git == 0  # the direct solution is the minimiser already
     D, B, rr = G.state()
     E = S.eta * D
     Eref = S.eta * S.D
