@@ -16,28 +16,37 @@
 
 namespace memd {
 
-__device__ __forceinline__ int find_rep(const RepDesc *__restrict__ tab, int count, int item, bool by_tiles) {
+// The owner of a work item: the last entry whose first item is at most the
+// item, by binary search over the entries' offsets, staged in LDS (dynamic,
+// max_slots ints) from the header's compact copy once per workgroup.
+extern __shared__ int s_off[];
+
+__device__ __forceinline__ int stage_index(const int *__restrict__ hdr, bool by_tiles) {
+    const int count = hdr[0], max_slots = hdr[3];
+    const int *src = hdr + kHdrInts + (by_tiles ? 0 : max_slots);
+    for (int t = threadIdx.x; t < count; t += blockDim.x) s_off[t] = src[t];
+    __syncthreads();
+    return count;
+}
+
+__device__ __forceinline__ int find_rep(int count, int item) {
     int lo = 0, hi = count - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const int off = by_tiles ? tab[mid].tile_off : tab[mid].ion_off;
-        if (off <= item) lo = mid;
+        if (s_off[mid] <= item) lo = mid;
         else hi = mid - 1;
     }
     return lo;
 }
 
-union BatchSmem {
-    LfSmem<float, 1> s1;
-    LfSmem<float, 2> s2;
-};
 
 __global__ __launch_bounds__(256) void k_batch_leapfrog(const RepDesc *__restrict__ tab,
                                                         const int *__restrict__ hdr) {
-    __shared__ BatchSmem U;
-    const int count = hdr[0], total = hdr[1];
+    __shared__ LfSmem<float, 1> U;
+    const int total = hdr[1];
+    const int count = stage_index(hdr, true);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int ri = find_rep(tab, count, item, true);
+        const int ri = find_rep(count, item);
         const RepDesc &R = tab[ri];
         const int step = *R.step;
         if (step >= R.nsteps) continue;
@@ -60,26 +69,20 @@ __global__ __launch_bounds__(256) void k_batch_leapfrog(const RepDesc *__restric
         A.ntx = R.ntx;
         A.nty = R.nty;
         A.tz = R.tz;
-        __syncthreads();  // the previous item may have used another LDS layout
-        if (R.rows == 1) {
-            if (R.eta_mode == ETA_UNIFORM)
-                leapfrog_tile<float, ETA_UNIFORM, 1>(A, tile_x, rest % R.nty, rest / R.nty, U.s1);
-            else
-                leapfrog_tile<float, ETA_ZPROF, 1>(A, tile_x, rest % R.nty, rest / R.nty, U.s1);
-        } else {
-            if (R.eta_mode == ETA_UNIFORM)
-                leapfrog_tile<float, ETA_UNIFORM, 2>(A, tile_x, rest % R.nty, rest / R.nty, U.s2);
-            else
-                leapfrog_tile<float, ETA_ZPROF, 2>(A, tile_x, rest % R.nty, rest / R.nty, U.s2);
-        }
+        __syncthreads();  // the previous item's LDS use is over
+        if (R.eta_mode == ETA_UNIFORM)
+            leapfrog_tile<float, ETA_UNIFORM, 1>(A, tile_x, rest % R.nty, rest / R.nty, U);
+        else
+            leapfrog_tile<float, ETA_ZPROF, 1>(A, tile_x, rest % R.nty, rest / R.nty, U);
     }
 }
 
 __global__ __launch_bounds__(256) void k_batch_deposit(const RepDesc *__restrict__ tab,
                                                        const int *__restrict__ hdr) {
-    const int count = hdr[0], total = hdr[2];
+    const int total = hdr[2];
+    const int count = stage_index(hdr, false);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int ri = find_rep(tab, count, item, false);
+        const int ri = find_rep(count, item);
         const RepDesc &R = tab[ri];
         const int step = *R.step;
         if (step >= R.nsteps) continue;
@@ -113,9 +116,10 @@ __global__ __launch_bounds__(256) void k_batch_deposit(const RepDesc *__restrict
 __global__ __launch_bounds__(256) void k_batch_forces(const RepDesc *__restrict__ tab,
                                                       const int *__restrict__ hdr) {
     __shared__ double Psh[3];
-    const int count = hdr[0], total = hdr[2];
+    const int total = hdr[2];
+    const int count = stage_index(hdr, false);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int ri = find_rep(tab, count, item, false);
+        const int ri = find_rep(count, item);
         const RepDesc &R = tab[ri];
         const int step = *R.step;
         if (step >= R.nsteps) continue;
@@ -157,10 +161,12 @@ __global__ void k_batch_advance(const RepDesc *__restrict__ tab, const int *__re
     }
 }
 
-hipError_t launch_batch_step(hipStream_t s, const RepDesc *tab, const int *hdr, int lf_grid, int ion_grid) {
-    hipLaunchKernelGGL(k_batch_leapfrog, dim3(lf_grid), dim3(256), 0, s, tab, hdr);
-    hipLaunchKernelGGL(k_batch_deposit, dim3(ion_grid), dim3(256), 0, s, tab, hdr);
-    hipLaunchKernelGGL(k_batch_forces, dim3(ion_grid), dim3(256), 0, s, tab, hdr);
+hipError_t launch_batch_step(hipStream_t s, const RepDesc *tab, const int *hdr, int max_slots, int lf_grid,
+                             int ion_grid) {
+    const size_t lds = (size_t)max_slots * sizeof(int);
+    hipLaunchKernelGGL(k_batch_leapfrog, dim3(lf_grid), dim3(256), lds, s, tab, hdr);
+    hipLaunchKernelGGL(k_batch_deposit, dim3(ion_grid), dim3(256), lds, s, tab, hdr);
+    hipLaunchKernelGGL(k_batch_forces, dim3(ion_grid), dim3(256), lds, s, tab, hdr);
     hipLaunchKernelGGL(k_batch_advance, dim3(4), dim3(256), 0, s, tab, hdr);
     return hipGetLastError();
 }

@@ -860,7 +860,7 @@ memd_status memd::autotune_leapfrog(memd_ctx *c, int reps, const char *cache_pat
                     int rr = 0, pp = 0;
                     double uu = 0.0;
                     if (sscanf(line + kl, " rows=%d planes=%d us=%lf", &rr, &pp, &uu) == 3 &&
-                        (rr == 1 || rr == 2 || rr == 4) && pp >= 1) {
+                        (rr == 1 || rr == 2 || rr == 4) && rr <= max_rows && pp >= 1) {
                         br = rr;
                         bp = pp;
                         bu = uu;

@@ -32,10 +32,14 @@ struct RepDesc {
     int *step;     // steps done (device counter)
 };
 
-// table header on the device: {count, total leapfrog tiles, total ion blocks}
+// table header on the device: {count, total leapfrog tiles, total ion blocks,
+// max_slots}, then the entries' tile_off[max_slots] and ion_off[max_slots]
+// (the offsets again, compact, for the kernels' owner search)
 constexpr int kHdrInts = 4;
+__host__ __device__ inline int hdr_ints(int max_slots) { return kHdrInts + 2 * max_slots; }
 
-hipError_t launch_batch_step(hipStream_t s, const RepDesc *tab, const int *hdr, int lf_grid, int ion_grid);
+hipError_t launch_batch_step(hipStream_t s, const RepDesc *tab, const int *hdr, int max_slots, int lf_grid,
+                             int ion_grid);
 hipError_t launch_philox_disp(hipStream_t s, uint64_t seed, uint32_t t, int n, double sigma, double *out);
 
 }  // namespace memd

@@ -154,8 +154,8 @@ void worker_main(memd_server *s) {
         if (st == MEMD_OK) st = memd_initial_gauss_solve(rq->ctx, s->solve_tol, 0, nullptr, nullptr);
         if (st == MEMD_OK) {
             const char *cache = s->tune_cache.empty() ? nullptr : s->tune_cache.c_str();
-            // the batched leapfrog holds tiles of 1 or 2 rows per thread
-            st = autotune_leapfrog(rq->ctx, 5, cache, 2, &rq->rows, &rq->tz, nullptr);
+            // the batched leapfrog holds tiles of one row per thread
+            st = autotune_leapfrog(rq->ctx, 5, cache, 1, &rq->rows, &rq->tz, nullptr);
         }
         if (st == MEMD_OK) {
             const int ib = rq->n > 0 ? (rq->n + 255) / 256 : 1;
@@ -240,19 +240,22 @@ hipError_t upload_table(memd_server *s) {
         fill_desc(rq, rq->slot, s->d_steps, d);
         d.tile_off = toff;
         d.ion_off = ioff;
+        s->h_hdr[kHdrInts + k] = toff;
+        s->h_hdr[kHdrInts + s->max_slots + k] = ioff;
         toff += d.tiles;
         ioff += d.iblocks;
     }
     s->h_hdr[0] = (int)s->active.size();
     s->h_hdr[1] = toff;
     s->h_hdr[2] = ioff;
-    s->h_hdr[3] = 0;
+    s->h_hdr[3] = s->max_slots;
     hipError_t e;
     if (!s->active.empty())
         if ((e = hipMemcpyAsync(s->d_tab, s->h_tab, s->active.size() * sizeof(RepDesc), hipMemcpyHostToDevice,
                                 s->stream)) != hipSuccess)
             return e;
-    if ((e = hipMemcpyAsync(s->d_hdr, s->h_hdr, kHdrInts * sizeof(int), hipMemcpyHostToDevice, s->stream)) !=
+    if ((e = hipMemcpyAsync(s->d_hdr, s->h_hdr, hdr_ints(s->max_slots) * sizeof(int), hipMemcpyHostToDevice,
+                            s->stream)) !=
         hipSuccess)
         return e;
     s->table_dirty = false;
@@ -264,7 +267,7 @@ hipError_t upload_table(memd_server *s) {
 hipError_t capture_graph(memd_server *s) {
     hipError_t e;
     if ((e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
-    launch_batch_step(s->stream, s->d_tab, s->d_hdr, s->lf_grid, s->ion_grid);
+    launch_batch_step(s->stream, s->d_tab, s->d_hdr, s->max_slots, s->lf_grid, s->ion_grid);
     if ((e = hipStreamEndCapture(s->stream, &s->graph)) != hipSuccess) return e;
     return hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0);
 }
@@ -375,15 +378,15 @@ memd_status memd_server_create(memd_server **out, size_t hbm_budget_bytes, int m
         s->own_stream = true;
     }
     if (hipMalloc((void **)&s->d_tab, (size_t)max_slots * sizeof(RepDesc)) != hipSuccess ||
-        hipMalloc((void **)&s->d_hdr, kHdrInts * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&s->d_hdr, hdr_ints(max_slots) * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&s->d_steps, (size_t)max_slots * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void **)&s->h_tab, (size_t)max_slots * sizeof(RepDesc), 0) != hipSuccess ||
-        hipHostMalloc((void **)&s->h_hdr, kHdrInts * sizeof(int), 0) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_hdr, hdr_ints(max_slots) * sizeof(int), 0) != hipSuccess ||
         hipHostMalloc((void **)&s->h_steps, (size_t)max_slots * sizeof(int), 0) != hipSuccess) {
         memd_server_destroy(s);
         return MEMD_ENOMEM;
     }
-    memset(s->h_hdr, 0, kHdrInts * sizeof(int));
+    memset(s->h_hdr, 0, hdr_ints(max_slots) * sizeof(int));
     memset(s->h_steps, 0, (size_t)max_slots * sizeof(int));
     for (int k = max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
     if (upload_table(s) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess ||
