@@ -856,85 +856,126 @@ hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials,
 
 // Counting sort of the ions by lattice row (y, z cell of the position): the
 // deposit and force kernels then visit neighbouring ions together.
+// Wavefront-aggregated add of 1 to ctr[key] per active lane (key < 0: none):
+// one atomic per distinct key, every lane gets its own position (the
+// returned value plus its rank among the lanes with its key, in lane order)
+// when `ret` is set.  Ions in (nearly) bin order share keys within a wavefront.
+__device__ __forceinline__ int wave_add_one(int *ctr, int key, bool ret) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long rem = __ballot(key >= 0);
+    int lead = lane, rank = 0, take = 0;
+    while (rem) {
+        const int l = __ffsll((long long)rem) - 1;
+        const int kl = __builtin_amdgcn_readlane(key, l);
+        const unsigned long long same = __ballot(key == kl);
+        if (key == kl) {
+            lead = l;
+            rank = __popcll(same & below);
+        }
+        if (lane == l) take = __popcll(same);
+        rem &= ~same;
+    }
+    // the leaders' atomics all go out together
+    int base = 0;
+    if (take > 0) {
+        if (ret) base = atomicAdd(&ctr[key], take);
+        else atomicAdd(&ctr[key], take);
+    }
+    if (ret) base = __shfl(base, lead, 64);
+    return base + rank;
+}
+
 // Row counts of the ions (count all zero on entry); also clears the nlc list
 // counts lc (the lists are rebuilt after every binning).
 __global__ void k_bin_count(int n, int L, double a, const double *__restrict__ r, int *__restrict__ count,
                             int *__restrict__ lc, int nlc) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     for (int k = i; k < nlc; k += gridDim.x * blockDim.x) lc[k] = 0;
-    if (i >= n) return;
-    int cy, cz;
-    double f;
-    fold(r[3 * i + 1], a, L, cy, f);
-    fold(r[3 * i + 2], a, L, cz, f);
-    atomicAdd(&count[cy + L * cz], 1);
+    int row = -1;
+    if (i < n) {
+        int cy, cz;
+        double f;
+        fold(r[3 * i + 1], a, L, cy, f);
+        fold(r[3 * i + 2], a, L, cz, f);
+        row = cy + L * cz;
+    }
+    wave_add_one(count, row, false);
 }
 
 // Exclusive scan of count[0..nb) into start and cursor (one block of 1024),
-// leaving count all zero for the next binning.
-// The bins are taken in super-tiles of 16384: every thread loads its four
-// runs of four bins (bins base + 4096 j + 4t .. +3) at once, then the four
-// tiles of 4096 are scanned in turn (sums of four, wavefront prefix sums,
-// the 16 wavefront totals in LDS) with a running carry.
+// leaving count all zero for the next binning.  Per pass of 16384 bins each
+// thread holds 16 consecutive ones (four 16-byte words): a sequential sum,
+// a wavefront prefix sum of the thread totals, the 16 wavefront totals in
+// LDS, then the thread's 16 starts written back as 16-byte words.
 __global__ __launch_bounds__(1024) void k_bin_scan(int *__restrict__ count, int nb, int *__restrict__ start,
                                                    int *__restrict__ cursor) {
     __shared__ int wsum[16];
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const bool vec = (nb & 3) == 0;
     int carry = 0;
     for (int base = 0; base < nb; base += 16384) {
-        int v[4][4];
+        const int b0 = base + 16 * t;
+        int v[16];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int idx = base + 4096 * j + 4 * t;
-            if (idx + 3 < nb && (nb & 3) == 0) {
+        for (int q = 0; q < 4; ++q) {
+            const int idx = b0 + 4 * q;
+            if (vec && idx + 3 < nb) {
                 const int4 w = *reinterpret_cast<const int4 *>(count + idx);
-                v[j][0] = w.x;
-                v[j][1] = w.y;
-                v[j][2] = w.z;
-                v[j][3] = w.w;
+                v[4 * q] = w.x;
+                v[4 * q + 1] = w.y;
+                v[4 * q + 2] = w.z;
+                v[4 * q + 3] = w.w;
             } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[j][e] = idx + e < nb ? count[idx + e] : 0;
+                for (int e = 0; e < 4; ++e) v[4 * q + e] = idx + e < nb ? count[idx + e] : 0;
             }
         }
+        int tot = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int idx = base + 4096 * j + 4 * t;
+        for (int e = 0; e < 16; ++e) tot += v[e];
+        int x = tot;
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (idx + e < nb) count[idx + e] = 0;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
         }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        int before = carry, total = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int idx = base + 4096 * j + 4 * t;
-            const int s4 = v[j][0] + v[j][1] + v[j][2] + v[j][3];
-            int x = s4;
+        for (int w = 0; w < 16; ++w) {
+            const int ws = wsum[w];
+            if (w < wid) before += ws;
+            total += ws;
+        }
+        int run = before + x - tot;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(x, o, 64);
-                if (lane >= o) x += y;
-            }
-            if (lane == 63) wsum[wid] = x;
-            __syncthreads();
-            int before = carry, total = 0;
-#pragma unroll
-            for (int w = 0; w < 16; ++w) {
-                const int ws = wsum[w];
-                if (w < wid) before += ws;
-                total += ws;
-            }
-            int run = before + x - s4;
+        for (int q = 0; q < 4; ++q) {
+            const int idx = b0 + 4 * q;
+            int st[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                if (idx + e < nb) {
-                    start[idx + e] = run;
-                    cursor[idx + e] = run;
-                }
-                run += v[j][e];
+                st[e] = run;
+                run += v[4 * q + e];
             }
-            carry += total;
-            __syncthreads();
+            if (vec && idx + 3 < nb) {
+                const int4 w = make_int4(st[0], st[1], st[2], st[3]);
+                *reinterpret_cast<int4 *>(start + idx) = w;
+                *reinterpret_cast<int4 *>(cursor + idx) = w;
+                *reinterpret_cast<int4 *>(count + idx) = make_int4(0, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (idx + e < nb) {
+                        start[idx + e] = st[e];
+                        cursor[idx + e] = st[e];
+                        count[idx + e] = 0;
+                    }
+            }
         }
+        carry += total;
+        __syncthreads();
     }
 }
 
@@ -961,13 +1002,16 @@ __global__ void k_bin_reorder(int n, int L, double a, const double *__restrict__
                               double *__restrict__ r2, double *__restrict__ q2, double *__restrict__ F2,
                               int *__restrict__ perm2, int *__restrict__ order, int *__restrict__ slot_of) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    int row = -1;
+    if (j < n) {
+        int cy, cz;
+        double f;
+        fold(r[3 * j + 1], a, L, cy, f);
+        fold(r[3 * j + 2], a, L, cz, f);
+        row = cy + L * cz;
+    }
+    const int s = wave_add_one(cursor, row, true);
     if (j >= n) return;
-    int cy, cz;
-    double f;
-    fold(r[3 * j + 1], a, L, cy, f);
-    fold(r[3 * j + 2], a, L, cz, f);
-    const int row = cy + L * cz;
-    const int s = atomicAdd(&cursor[row], 1);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         r2[3 * s + d] = r[3 * j + d];
