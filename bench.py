@@ -77,7 +77,7 @@ def load_traffic(precision: str):
     return float(m.group(1))
 
 
-def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None):
+def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None, solve_tol=1e-12):
     import torch
     from paper_1309_7859_amd import memd
     from paper_1309_7859_amd import workloads as W
@@ -99,7 +99,7 @@ def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None):
                      audit_every=CADENCE, energy_every=CADENCE)
     G.set_salt(80.0, 15.0, 1.0, every=CADENCE)
     t0 = time.perf_counter()
-    st, iters, res = G.solve(1e-12, check=False)
+    st, iters, res = G.solve(solve_tol, check=False)
     t_solve = time.perf_counter() - t0
     if tile:
         memd.memd_set_tiling(G.ctx, tile[0], tile[1])
@@ -175,6 +175,9 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
     ap.add_argument("--tile", type=str, default="", help="rows,planes of the leapfrog tile")
+    ap.add_argument("--diag256-steps", type=int, default=50,
+                    help="steps of the same workload at 256^3 (8e5 ions), whose fields exceed the "
+                         "256 MB Infinity Cache (0 = skip)")
     ap.add_argument("--serve-count", type=int, default=512,
                     help="replicas in the serving stream (0 = skip the serving measurement)")
     ap.add_argument("--serve-rate", type=float, default=500.0, help="Poisson arrival rate (1/s)")
@@ -251,6 +254,25 @@ def main():
             "ms_per_step": round(r64["wall"] * 1e3 / args.fp64_steps, 5),
             "leapfrog_frac": round(b64 / lf64 / 1e9 / HBM_PEAK_GBS, 4),
             "steps": args.fp64_steps}
+    if fp32 and args.diag256_steps > 0:
+        # the same recipe at 256^3 with 8x the ions (same density): 604 MB of
+        # fields per step, more than the Infinity Cache holds
+        w2 = W.Workload("c4@256", 256, w.a, w.dt, tuple(8 * c for c in w.counts), "salt", 0.0, w.sigma,
+                        args.diag256_steps, 105, salt_every=CADENCE)
+        r2 = gpu_run(w2, args.diag256_steps, 10, "fp32", solve_tol=1e-6)
+        lf2 = r2["lf_ms"] / 1e3 / max(r2["lf_n"], 1)
+        b2 = leapfrog_bytes_per_site(True, True) * w2.sites + (rec_bytes * w2.n if r2["fused"] else 0)
+        out["diag_256"] = {
+            "workload": "c4 recipe at 256^3: 8e5 ions (10% +-2), salt eps every 50 steps, "
+                        "audit+energy every 50 steps, FP32 fields",
+            "value": round(w2.sites * args.diag256_steps / r2["wall"], 1), "unit": "site-updates/s",
+            "ms_per_step": round(r2["wall"] * 1e3 / args.diag256_steps, 5),
+            "steps": args.diag256_steps,
+            "leapfrog": {"avg_launch_us": round(lf2 * 1e6, 2), "algorithmic_bytes_per_launch": b2,
+                         "achieved": round(b2 / lf2 / 1e9, 1),
+                         "frac": round(b2 / lf2 / 1e9 / HBM_PEAK_GBS, 4),
+                         "tile": {"x": 64, "y": 4 * r2["tile"][0], "z_chunk": r2["tile"][1]},
+                         "fused": r2["fused"]}}
     if args.cpu_steps > 0:
         cb = cpu_baseline(w, args.cpu_steps)
         out["cpu_baseline"] = {

@@ -207,7 +207,7 @@ memd_status memd_set_tiling(memd_ctx *ctx, int rows_per_thread, int planes_per_c
  * the leapfrog kernel, each tile adding the contributions to the links it
  * owns; the other ions, and every ion when fuse_deposit = 0, deposit with
  * global atomics.  sort_every: steps between re-binnings of the ions by
- * lattice row (default 32; 0 = never after the first).  Both forms give the
+ * lattice row (default 64; 0 = never after the first).  Both forms give the
  * same result up to the order of floating-point additions. */
 memd_status memd_set_options(memd_ctx *ctx, int fuse_deposit, int sort_every);
 /* bad_moves: displacement components rejected so far (not finite, or longer

@@ -289,7 +289,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     c->tsize = c->fp32 ? sizeof(float) : sizeof(double);
     c->lf_rows = c->fp32 ? 2 : 1;
     c->lf_tz = 4;
-    c->sort_every = 32;
+    c->sort_every = 64;
     c->fuse_deposit = true;
     c->hist_cap = kHistCap;
     if (hipGetDevice(&c->device) != hipSuccess) {

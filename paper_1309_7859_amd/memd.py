@@ -261,7 +261,7 @@ def memd_autotune(ctx: int, reps: int = 10, cache_path: str | None = None):
     return rr.value, pp.value, us.value
 
 
-def memd_set_options(ctx: int, fuse_deposit: int = 1, sort_every: int = 32):
+def memd_set_options(ctx: int, fuse_deposit: int = 1, sort_every: int = 64):
     _check(load().memd_set_options(ctx, int(fuse_deposit), int(sort_every)), "memd_set_options")
 
 
