@@ -55,12 +55,10 @@ static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, voi
     const int nz = (c->L + A.tz - 1) / A.tz;
     const int nblk = A.ntx * A.nty * nz;
     if (dep) {
-        if constexpr (std::is_same<T, float>::value) {
-            if (R == 1 && A.tz > kDepTZ) {
-                hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 1, kDepTZWide>), dim3(nblk), dim3(256), 0, c->stream,
-                                      e0, e1, 0, A, *dep);
-                return hipGetLastError();
-            }
+        if (R == 1 && A.tz > kDepTZ) {
+            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 1, kDepTZWide>), dim3(nblk), dim3(256), 0, c->stream, e0,
+                                  e1, 0, A, *dep);
+            return hipGetLastError();
         }
         if (R == 1)
             hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 1, kDepTZ>), dim3(nblk), dim3(256), 0, c->stream, e0, e1,
@@ -91,7 +89,7 @@ int list_cap(const memd_ctx *c) {
 }
 
 bool fused_deposit_ok(const memd_ctx *c) {
-    const int tz_max = c->fp32 && c->lf_rows == 1 ? kDepTZWide : kDepTZ;
+    const int tz_max = c->lf_rows == 1 ? kDepTZWide : kDepTZ;
     return c->fuse_deposit && c->n > 0 && c->list && c->L >= 16 && c->L <= 1024 && c->lf_tz <= tz_max &&
            c->lf_rows <= (c->fp32 ? 2 : 1) && list_tiles(c) <= c->list_tiles_max && list_cap(c) >= 16;
 }

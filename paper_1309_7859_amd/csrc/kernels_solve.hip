@@ -101,8 +101,6 @@ hipError_t solve_recursion(memd_ctx *c, double *D) {
     hipLaunchKernelGGL(k_row_fill, dim3(nl), dim3(kThreads), 0, c->stream, c->rho, qbar, qline, dz, dy, L,
                        a2, D);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // restore the all-zero invariant of rho
-    if ((e = launch_fill(c->stream, c->rho, 0.0, c->Ns)) != hipSuccess) return e;
     return hipFreeAsync(w, c->stream);
 }
 

@@ -124,7 +124,7 @@ struct DepArgs {
 };
 
 // Planes per z-chunk when the deposit is fused: up to 4, or up to 8 for the
-// FP32 tile of 64 x 4 sites (the accumulator is 3 x TZ x TY x 64 values).
+// tile of 64 x 4 sites (the accumulator is 3 x TZ x TY x 64 values).
 constexpr int kDepTZ = 4;
 constexpr int kDepTZWide = 8;
 

@@ -379,7 +379,7 @@ def _mixed_moves(rng, steps, n, big_frac=0.05):
 
 @pytest.mark.parametrize("prec,tile,L", [(memd.FP64, None, 32), (memd.FP32_MIXED, None, 32),
                                          (memd.FP32_MIXED, (1, 8), 44), (memd.FP32_MIXED, (2, 4), 44),
-                                         (memd.FP64, (1, 2), 44)])
+                                         (memd.FP64, (1, 2), 44), (memd.FP64, (1, 8), 44)])
 def test_fused_deposit_matches_atomic_path_and_oracle(prec, tile, L):
     """The deposit fused into the leapfrog (tile-owned links) and the global
     atomic deposit give the oracle's result, with jumps of up to 2.5 a mixed
