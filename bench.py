@@ -38,14 +38,31 @@ PROFILE_EVERY = 10
 
 # Algorithmic bytes (each value read once / written once).
 #   leapfrog, per site: read D[3], B[3], eta[3] (per-link permittivity), write D[3], B[3];
-#     with the fused deposit also the ion's 64-byte record
-#   ion side, per ion: pack (60 read + 64 write), update (60 read + 24 write),
-#     forces (r, q, 12 D + 12 eta, F write)
+#     with the fused deposit also, per ion, the tiles' share (its record, the
+#     inputs and outputs of the force its tile computes) and the movers' share
+#     (mover_bytes_per_ion)
+#   ion side without the fused deposit, per ion: pack (60 read + 64 write),
+#     update (60 read + 24 write), forces (r, q, 12 D + 12 eta, F write);
+#     with it, the finisher: read the tile force (24), its stamp (4), q (8),
+#     the atomic-path flag (4), write F (24)
 
 
 def leapfrog_bytes_per_site(fp32: bool, per_link_eps: bool) -> int:
     t = 4 if fp32 else 8
     return (15 if per_link_eps else 12) * t
+
+
+def mover_bytes_per_ion(fp32: bool) -> int:
+    """The movers of the fused launch: read r, q, the record's displacement,
+    list_fail, cbin, perm and the next displacement (given by the caller);
+    write r^{n+1} and the next record (16-byte head, the first cell's 12
+    values, the displacement, the fractional position and charge, the
+    atomic-path flag)."""
+    t = 4 if fp32 else 8
+    return (24 + 8 + 24 + 4 + 4 + 4 + 24) + (24 + 16 + 12 * t + 24 + 4 * t + 4)
+
+
+FINISH_BYTES_PER_ION = 24 + 4 + 8 + 4 + 24
 
 
 def ion_bytes_per_step(fp32: bool) -> int:
@@ -58,7 +75,7 @@ def ion_bytes_per_step(fp32: bool) -> int:
 def kernel_source_hash() -> str:
     """Hash of the sources of the leapfrog kernels (plain and with the fused deposit)."""
     h = hashlib.sha256()
-    for f in ("kernels_field.hip", "leapfrog_tile.hpp", "ion_ops.hpp", "device_util.hpp"):
+    for f in ("kernels_field.hip", "leapfrog_tile.hpp", "ion_records.hpp", "ion_ops.hpp", "device_util.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1309_7859_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -208,16 +225,17 @@ def main():
     # the 12 first-cell values in the field type (the second cell's 12 only
     # for a move that crosses a face); for the forces it computes it reads the
     # fractional position and charge (4 values) and 12/sum(eta) of the cell,
-    # and writes three FP64 force components and a 4-byte stamp
+    # and writes three FP64 force components and a 4-byte stamp; its movers
+    # move every ion and write the next step's records
     tsz = 4 if fp32 else 8
-    rec_bytes = 16 + 12 * tsz + 5 * tsz + 24 + 4
+    rec_bytes = 16 + 12 * tsz + 5 * tsz + 24 + 4 + mover_bytes_per_ion(fp32)
     lf_bytes = leapfrog_bytes_per_site(fp32, True) * sites + (rec_bytes * w.n if r["fused"] else 0)
     achieved = lf_bytes / lf_avg_s / 1e9
     traffic = load_traffic(args.precision)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (round(traffic / lf_avg_s / 1e9, 1) if traffic else None),
-            "kernel": ("k_leapfrog_dep (Faraday + Ampere + tile-owned current deposit)" if r["fused"]
+            "kernel": ("k_leapfrog_dep (Faraday + Ampere + tile-owned current deposit + ion movers)" if r["fused"]
                        else "k_leapfrog (Faraday + Ampere)"),
             "algorithmic_bytes_per_launch": lf_bytes, "avg_launch_us": round(lf_avg_s * 1e6, 2),
             "launches": r["lf_n"], "timed_every": PROFILE_EVERY,
@@ -225,7 +243,7 @@ def main():
                      "autotuned_us": r["tile"][2]}}
     if traffic:
         roof["traffic_bytes_per_launch"] = traffic
-    step_bytes = lf_bytes + ion_bytes_per_step(fp32) * w.n
+    step_bytes = lf_bytes + (FINISH_BYTES_PER_ION if r["fused"] else ion_bytes_per_step(fp32)) * w.n
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "site-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -247,7 +265,8 @@ def main():
     if fp32 and args.fp64_steps > 0:
         r64 = gpu_run(w, args.fp64_steps, min(args.warmup, 20), "fp64")
         lf64 = r64["lf_ms"] / 1e3 / max(r64["lf_n"], 1)
-        b64 = leapfrog_bytes_per_site(False, True) * sites
+        rec64 = 16 + 12 * 8 + 5 * 8 + 24 + 4 + mover_bytes_per_ion(False)
+        b64 = leapfrog_bytes_per_site(False, True) * sites + (rec64 * w.n if r64["fused"] else 0)
         out["fp64_variant"] = {
             "value": round(sites * args.fp64_steps / r64["wall"], 1),
             "ion_steps_per_s": round(w.n * args.fp64_steps / r64["wall"], 1),

@@ -1,0 +1,254 @@
+// ion_records.hpp -- the per-slot records of the fused deposit and the ion
+// movers that write them (gfx950).
+//
+// A record holds what the leapfrog tiles need of one ion's move for the
+// step: its start cell, per axis the link box the dimension-split move
+// touches, and the values it adds to those links (the current of the move,
+// assigned so that Gauss's law holds after the move, eq. constraint, with
+// the transverse linear weights).
+#pragma once
+
+#include "device_util.hpp"
+#include "ion_ops.hpp"
+#include "leapfrog_tile.hpp"
+#include "memd_internal.hpp"
+#include "philox.hpp"
+
+namespace memd {
+
+// The records of the fused deposit (leapfrog_tile.hpp), one per slot, and
+// what decides whether an ion stays with the tiles: its cell at the last
+// list build (cbin, packed) and whether it fitted the lists (list_fail).
+template <typename T>
+struct DepOut {
+    int4 *head;
+    DepCell<T> *con0, *con1;
+    const int *cbin;
+    const int *list_fail;
+    double *du;  // [3n] by slot: the (sanitised) displacement the record was made for
+    IonFQ<T> *fq;  // [n] by slot: fractional position in the start cell and charge
+};
+
+// The record of one ion in slot s for the fused deposit (du already
+// sanitised): the axes of the dimension-split move are taken in turn with
+// the arithmetic of deposit_ion (bit for bit), giving per axis the link-box
+// corner and the values -q (ub - ua)/a w w / a^2 (in the field type).
+// Returns true, and writes a head of -1, when the ion is left to the atomic
+// path: irregular, drifted more than one cell from its list cell along an
+// axis, or missing from a list.
+// (list_fail and cb: the slot's entries of O.list_fail and O.cbin.)
+template <typename T>
+__device__ __forceinline__ bool write_record_at(int L, double a, double qi, const double (&u_in)[3],
+                                                const double (&du)[3], int s, const DepOut<T> &O, int list_fail,
+                                                int cb) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) O.du[3 * s + d] = du[d];
+    double u[3] = {u_in[0], u_in[1], u_in[2]};
+    int c0[3];
+    double f0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fold(u[d], a, L, c0[d], f0[d]);
+    bool atomic_path = list_fail != 0 || !ion_regular(a, u_in, du);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        int off = c0[e] - ((cb >> (10 * e)) & 1023) + 1;
+        off += off < 0 ? L : (off >= L ? -L : 0);
+        atomic_path = atomic_path || off > 2;  // start cell within one cell of the list cell
+    }
+    if (atomic_path) {
+        O.head[s] = make_int4(-1, 0, 0, 0);
+        return true;
+    }
+    const double a2 = a * a;
+    unsigned int g[3] = {0u, 0u, 0u};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+        const double u0 = u[d], u1 = u0 + du[d];
+        if (u1 != u0) {
+            int c1, c2;
+            double f1, f2;
+            fold(u[d1], a, L, c1, f1);
+            fold(u[d2], a, L, c2, f2);
+            const double lo_u = u0 < u1 ? u0 : u1, hi_u = u0 < u1 ? u1 : u0;
+            const double sgn = u1 > u0 ? 1.0 : -1.0;
+            const double klo = floor(div_a(lo_u, a)), khi = floor(div_a(hi_u, a));
+            int corner[3];
+            corner[d] = mod_cell(klo, L);
+            corner[d1] = c1;
+            corner[d2] = c2;
+            const bool two = khi > klo;
+            g[d] = (unsigned)pack_cell(corner[0], corner[1], corner[2]) | kGroupOn | (two ? kGroupTwo : 0u);
+            // a regular move spans at most two cells along the axis
+#pragma unroll
+            for (int cell = 0; cell < 2; ++cell) {
+                if (cell == 1 && !two) break;  // the second cell's values are only read when it is used
+                const double kc = cell ? khi : klo;
+                const double s0 = kc * a, s1 = (kc + 1.0) * a;
+                const double sa = lo_u > s0 ? lo_u : s0;
+                const double sb = hi_u < s1 ? hi_u : s1;
+                const double len = sb - sa;
+                const double amount = len > 0.0 ? div_a(qi * sgn * div_a(len, a), a2) : 0.0;
+#pragma unroll
+                for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                    for (int o1 = 0; o1 < 2; ++o1)
+                        (cell ? O.con1 : O.con0)[s].v[4 * d + 2 * o2 + o1] =
+                            (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
+            }
+        }
+        u[d] = u1;
+    }
+    O.head[s] = make_int4(pack_cell(c0[0], c0[1], c0[2]), (int)g[0], (int)g[1], (int)g[2]);
+    IonFQ<T> fq;
+    fq.f[0] = (T)f0[0];
+    fq.f[1] = (T)f0[1];
+    fq.f[2] = (T)f0[2];
+    fq.q = (T)qi;
+    O.fq[s] = fq;
+    return false;
+}
+
+template <typename T>
+__device__ __forceinline__ bool write_record(int L, double a, double qi, const double (&u_in)[3],
+                                             const double (&du)[3], int s, const DepOut<T> &O) {
+    return write_record_at<T>(L, a, qi, u_in, du, s, O, O.list_fail[s], O.cbin[s]);
+}
+
+// The displacement of storage index i for the step (the caller's index
+// perm[i]), sanitised and counted.
+__device__ __forceinline__ void step_displacement(int i, int L, double a, const double *__restrict__ disp,
+                                                  const int *__restrict__ perm, unsigned int *bad, uint64_t seed,
+                                                  uint32_t t, double sigma, double (&du)[3]) {
+    const int ci = perm ? perm[i] : i;
+    if (disp) {
+        du[0] = disp[3 * ci];
+        du[1] = disp[3 * ci + 1];
+        du[2] = disp[3 * ci + 2];
+    } else {
+        philox_displacement(seed, t, (uint32_t)ci, sigma, du);
+    }
+    sanitize_move(du, a, L, bad);
+}
+
+// The ion movers: workgroups of the fused leapfrog launch beside its tiles.
+// Nothing they read or write is touched by the tiles of the same launch:
+// they move every
+// ion to r^{n+1} = r^n + du (into r_out; r^n stays for the forces and the
+// irregular ions' deposit that follow the launch), write one partial of
+// q r^{n+1} per wavefront, and, with pack set, the next step's records into
+// the second record set (the tiles read the first).
+constexpr int kMoverPerThread = 1;
+constexpr int kMoverIons = 256 * kMoverPerThread;  // ions per mover workgroup (256 threads)
+
+template <typename T>
+struct MoverArgs {
+    int nblocks;  // mover workgroups after the tiles (0: none)
+    int n, L;
+    double a;
+    const double *q, *r;
+    double *r_out;
+    const int *order;  // null: ions stored in bin order
+    const int *perm;   // storage index -> caller index (displacements), null: identity
+    const double *du;  // [3n] by slot: this step's displacements (the current records')
+    double *dip_out;   // 4 partials of q r^{n+1} per mover workgroup
+    int pack;          // write the next step's records
+    const double *disp_next;  // null: the Philox displacements of step t_next
+    uint64_t seed;
+    uint32_t t_next;
+    double sigma;
+    unsigned int *bad;
+    int *atomic_next;  // [n] by slot: the next step's ion left to the atomic path
+    DepOut<T> out;     // the next step's records (cbin, list_fail: the lists' state)
+};
+
+template <typename T>
+__device__ __forceinline__ void move_ions(const MoverArgs<T> &M, int m) {
+    double P[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < kMoverPerThread; ++k) {
+        const int s = m * kMoverIons + 256 * k + (int)threadIdx.x;
+        if (s >= M.n) break;
+        const int i = M.order ? M.order[s] : s;
+        const int ci = M.perm ? M.perm[i] : i;
+        double u[3] = {M.r[3 * i], M.r[3 * i + 1], M.r[3 * i + 2]};
+        const double qi = M.q[i];
+        const double du[3] = {M.du[3 * s], M.du[3 * s + 1], M.du[3 * s + 2]};
+        double dn[3] = {0.0, 0.0, 0.0};
+        int lfail = 0, lcell = 0;
+        if (M.pack) {
+            lfail = M.out.list_fail[s];
+            lcell = M.out.cbin[s];
+            if (M.disp_next) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) dn[d] = M.disp_next[3 * ci + d];
+            } else {
+                philox_displacement(M.seed, M.t_next, (uint32_t)ci, M.sigma, dn);
+            }
+        }
+        // the position deposit_ion leaves, bit for bit
+#pragma unroll
+        for (int d = 0; d < 3; ++d) u[d] = u[d] + du[d];
+        M.r_out[3 * i] = u[0];
+        M.r_out[3 * i + 1] = u[1];
+        M.r_out[3 * i + 2] = u[2];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) P[d] += qi * u[d];
+        if (M.pack) {
+            sanitize_move(dn, M.a, M.L, M.bad);
+            M.atomic_next[s] = write_record_at<T>(M.L, M.a, qi, u, dn, s, M.out, lfail, lcell) ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) P[d] = wave_sum(P[d]);
+    if ((threadIdx.x & 63) == 0) {
+        const int w = 4 * m + (int)(threadIdx.x >> 6);
+        M.dip_out[3 * w] = P[0];
+        M.dip_out[3 * w + 1] = P[1];
+        M.dip_out[3 * w + 2] = P[2];
+    }
+}
+
+// The records of the step about to run (next: the second set, which the
+// movers fill for the step after it).
+template <typename T>
+inline DepOut<T> dep_out(const memd_ctx *c, bool next = false) {
+    DepOut<T> O;
+    O.head = next ? c->rec_head_nx : c->rec_head;
+    O.con0 = (DepCell<T> *)(next ? c->rec_con_nx : c->rec_con);
+    O.con1 = (DepCell<T> *)(next ? c->rec_con1_nx : c->rec_con1);
+    O.cbin = c->cbin;
+    O.list_fail = c->list_fail;
+    O.du = next ? c->du_slot_nx : c->du_slot;
+    O.fq = (IonFQ<T> *)(next ? c->fq_nx : c->fq);
+    return O;
+}
+
+inline int mover_blocks(int n) { return n > 0 ? (n + kMoverIons - 1) / kMoverIons : 0; }
+
+template <typename T>
+inline MoverArgs<T> mover_args(const memd_ctx *c, const IonMoves &mv) {
+    MoverArgs<T> M;
+    M.nblocks = mover_blocks(c->n);
+    M.n = c->n;
+    M.L = c->L;
+    M.a = c->a;
+    M.q = c->q;
+    M.r = c->r;
+    M.r_out = c->r_alt;
+    M.order = c->sorted ? nullptr : c->order;
+    M.perm = c->perm;
+    M.du = c->du_slot;
+    M.dip_out = mv.dip_out;
+    M.pack = mv.pack_next ? 1 : 0;
+    M.disp_next = mv.disp_next;
+    M.seed = mv.seed;
+    M.t_next = mv.t_next;
+    M.sigma = mv.sigma;
+    M.bad = c->bad_moves;
+    M.atomic_next = c->dep_atomic_nx;
+    M.out = dep_out<T>(c, true);
+    return M;
+}
+
+}  // namespace memd

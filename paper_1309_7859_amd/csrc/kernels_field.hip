@@ -7,6 +7,7 @@
 
 #include "device_util.hpp"
 #include "ion_ops.hpp"
+#include "ion_records.hpp"
 #include "leapfrog_tile.hpp"
 #include "memd_internal.hpp"
 
@@ -21,12 +22,19 @@ __global__ __launch_bounds__(256) void k_leapfrog(LfArgs<T> A) {
     leapfrog_tile<T, EM, R>(A, tile_x, rest % A.nty, rest / A.nty, S);
 }
 
-// The leapfrog with the deposit of the regular ions fused in (leapfrog_tile.hpp).
+// The leapfrog with the deposit of the regular ions fused in (leapfrog_tile.hpp),
+// and the ion movers (ion_records.hpp) as the first M.nblocks workgroups: they
+// take CU slots at the start, and the tiles they hold back then fill the
+// slots that tiles free at the end.
 template <typename T, int EM, int R, int TZ>
-__global__ __launch_bounds__(256) void k_leapfrog_dep(LfArgs<T> A, DepArgs P) {
+__global__ __launch_bounds__(256) void k_leapfrog_dep(LfArgs<T> A, DepArgs P, MoverArgs<T> M) {
     __shared__ LfSmem<T, R> S;
     __shared__ DepSmem<T, R, TZ> DS;
-    const int logical = xcd_logical(blockIdx.x, gridDim.x);
+    if ((int)blockIdx.x < M.nblocks) {
+        move_ions<T>(M, (int)blockIdx.x);
+        return;
+    }
+    const int logical = xcd_logical((int)blockIdx.x - M.nblocks, (int)gridDim.x - M.nblocks);
     const int tile_x = logical % A.ntx;
     const int rest = logical / A.ntx;
     leapfrog_tile<T, EM, R, true, TZ>(A, tile_x, rest % A.nty, rest / A.nty, S, &P, &DS);
@@ -34,7 +42,7 @@ __global__ __launch_bounds__(256) void k_leapfrog_dep(LfArgs<T> A, DepArgs P) {
 
 template <typename T, int EM>
 static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout,
-                              hipEvent_t e0, hipEvent_t e1, const DepArgs *dep) {
+                              hipEvent_t e0, hipEvent_t e1, const DepArgs *dep, const MoverArgs<T> *mv) {
     LfArgs<T> A;
     A.Din = (const T *)Din;
     A.Bin = (const T *)Bin;
@@ -55,17 +63,23 @@ static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, voi
     const int nz = (c->L + A.tz - 1) / A.tz;
     const int nblk = A.ntx * A.nty * nz;
     if (dep) {
+        MoverArgs<T> M{};
+        if (mv) M = *mv;
+        DepArgs P = *dep;
+        P.dip_block = M.nblocks;  // the first tile
+        dep = &P;
+        const int ng = nblk + M.nblocks;
         if (R == 1 && A.tz > kDepTZ) {
-            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 1, kDepTZWide>), dim3(nblk), dim3(256), 0, c->stream, e0,
-                                  e1, 0, A, *dep);
+            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 1, kDepTZWide>), dim3(ng), dim3(256), 0, c->stream, e0,
+                                  e1, 0, A, *dep, M);
             return hipGetLastError();
         }
         if (R == 1)
-            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 1, kDepTZ>), dim3(nblk), dim3(256), 0, c->stream, e0, e1,
-                                  0, A, *dep);
+            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 1, kDepTZ>), dim3(ng), dim3(256), 0, c->stream, e0, e1,
+                                  0, A, *dep, M);
         else
-            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 2, kDepTZ>), dim3(nblk), dim3(256), 0, c->stream, e0, e1,
-                                  0, A, *dep);
+            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 2, kDepTZ>), dim3(ng), dim3(256), 0, c->stream, e0, e1,
+                                  0, A, *dep, M);
         return hipGetLastError();
     }
     if (R == 1)
@@ -96,7 +110,8 @@ bool fused_deposit_ok(const memd_ctx *c) {
 
 hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout, hipEvent_t e0,
                            hipEvent_t e1, const double *disp, uint64_t seed, uint32_t t, double sigma,
-                           bool with_deposit, bool need_pack, const double *dip_prev, int dip_nparts) {
+                           bool with_deposit, bool need_pack, const double *dip_prev, int dip_nparts,
+                           IonMoves *moves) {
     DepArgs P;
     const DepArgs *dp = nullptr;
     if (with_deposit) {
@@ -129,17 +144,25 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
         P.P = c->scal + S_P;
         dp = &P;
     }
+    const bool with_moves = dp && moves;
+    if (with_moves) moves->nparts = 4 * mover_blocks(c->n);
     if (c->fp32) {
+        MoverArgs<float> M{};
+        if (with_moves) M = mover_args<float>(c, *moves);
+        const MoverArgs<float> *mp = with_moves ? &M : nullptr;
         switch (c->eta_mode) {
-            case ETA_UNIFORM: return launch_lf_t<float, ETA_UNIFORM>(c, Din, Bin, Dout, Bout, e0, e1, dp);
-            case ETA_ZPROF: return launch_lf_t<float, ETA_ZPROF>(c, Din, Bin, Dout, Bout, e0, e1, dp);
-            default: return launch_lf_t<float, ETA_LINK>(c, Din, Bin, Dout, Bout, e0, e1, dp);
+            case ETA_UNIFORM: return launch_lf_t<float, ETA_UNIFORM>(c, Din, Bin, Dout, Bout, e0, e1, dp, mp);
+            case ETA_ZPROF: return launch_lf_t<float, ETA_ZPROF>(c, Din, Bin, Dout, Bout, e0, e1, dp, mp);
+            default: return launch_lf_t<float, ETA_LINK>(c, Din, Bin, Dout, Bout, e0, e1, dp, mp);
         }
     }
+    MoverArgs<double> M{};
+    if (with_moves) M = mover_args<double>(c, *moves);
+    const MoverArgs<double> *mp = with_moves ? &M : nullptr;
     switch (c->eta_mode) {
-        case ETA_UNIFORM: return launch_lf_t<double, ETA_UNIFORM>(c, Din, Bin, Dout, Bout, e0, e1, dp);
-        case ETA_ZPROF: return launch_lf_t<double, ETA_ZPROF>(c, Din, Bin, Dout, Bout, e0, e1, dp);
-        default: return launch_lf_t<double, ETA_LINK>(c, Din, Bin, Dout, Bout, e0, e1, dp);
+        case ETA_UNIFORM: return launch_lf_t<double, ETA_UNIFORM>(c, Din, Bin, Dout, Bout, e0, e1, dp, mp);
+        case ETA_ZPROF: return launch_lf_t<double, ETA_ZPROF>(c, Din, Bin, Dout, Bout, e0, e1, dp, mp);
+        default: return launch_lf_t<double, ETA_LINK>(c, Din, Bin, Dout, Bout, e0, e1, dp, mp);
     }
 }
 

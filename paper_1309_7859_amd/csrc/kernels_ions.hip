@@ -5,6 +5,7 @@
 
 #include "device_util.hpp"
 #include "ion_ops.hpp"
+#include "ion_records.hpp"
 #include "leapfrog_tile.hpp"
 #include "memd_internal.hpp"
 #include "philox.hpp"
@@ -88,121 +89,6 @@ hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, double *part
 
 __global__ void k_fill_int(int *dst, int v, size_t count);
 
-// The records of the fused deposit (leapfrog_tile.hpp), one per slot, and
-// what decides whether an ion stays with the tiles: its cell at the last
-// list build (cbin, packed) and whether it fitted the lists (list_fail).
-template <typename T>
-struct DepOut {
-    int4 *head;
-    DepCell<T> *con0, *con1;
-    const int *cbin;
-    const int *list_fail;
-    double *du;  // [3n] by slot: the (sanitised) displacement the record was made for
-    IonFQ<T> *fq;  // [n] by slot: fractional position in the start cell and charge
-};
-
-// The record of one ion in slot s for the fused deposit (du already
-// sanitised): the axes of the dimension-split move are taken in turn with
-// the arithmetic of deposit_ion (bit for bit), giving per axis the link-box
-// corner and the values -q (ub - ua)/a w w / a^2 (in the field type).
-// Returns true, and writes a head of -1, when the ion is left to the atomic
-// path: irregular, drifted more than one cell from its list cell along an
-// axis, or missing from a list.
-// (list_fail and cb: the slot's entries of O.list_fail and O.cbin.)
-template <typename T>
-__device__ __forceinline__ bool write_record_at(int L, double a, double qi, const double (&u_in)[3],
-                                                const double (&du)[3], int s, const DepOut<T> &O, int list_fail,
-                                                int cb) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) O.du[3 * s + d] = du[d];
-    double u[3] = {u_in[0], u_in[1], u_in[2]};
-    int c0[3];
-    double f0[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) fold(u[d], a, L, c0[d], f0[d]);
-    bool atomic_path = list_fail != 0 || !ion_regular(a, u_in, du);
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-        int off = c0[e] - ((cb >> (10 * e)) & 1023) + 1;
-        off += off < 0 ? L : (off >= L ? -L : 0);
-        atomic_path = atomic_path || off > 2;  // start cell within one cell of the list cell
-    }
-    if (atomic_path) {
-        O.head[s] = make_int4(-1, 0, 0, 0);
-        return true;
-    }
-    const double a2 = a * a;
-    unsigned int g[3] = {0u, 0u, 0u};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-        const double u0 = u[d], u1 = u0 + du[d];
-        if (u1 != u0) {
-            int c1, c2;
-            double f1, f2;
-            fold(u[d1], a, L, c1, f1);
-            fold(u[d2], a, L, c2, f2);
-            const double lo_u = u0 < u1 ? u0 : u1, hi_u = u0 < u1 ? u1 : u0;
-            const double sgn = u1 > u0 ? 1.0 : -1.0;
-            const double klo = floor(div_a(lo_u, a)), khi = floor(div_a(hi_u, a));
-            int corner[3];
-            corner[d] = mod_cell(klo, L);
-            corner[d1] = c1;
-            corner[d2] = c2;
-            const bool two = khi > klo;
-            g[d] = (unsigned)pack_cell(corner[0], corner[1], corner[2]) | kGroupOn | (two ? kGroupTwo : 0u);
-            // a regular move spans at most two cells along the axis
-#pragma unroll
-            for (int cell = 0; cell < 2; ++cell) {
-                if (cell == 1 && !two) break;  // the second cell's values are only read when it is used
-                const double kc = cell ? khi : klo;
-                const double s0 = kc * a, s1 = (kc + 1.0) * a;
-                const double sa = lo_u > s0 ? lo_u : s0;
-                const double sb = hi_u < s1 ? hi_u : s1;
-                const double len = sb - sa;
-                const double amount = len > 0.0 ? div_a(qi * sgn * div_a(len, a), a2) : 0.0;
-#pragma unroll
-                for (int o2 = 0; o2 < 2; ++o2)
-#pragma unroll
-                    for (int o1 = 0; o1 < 2; ++o1)
-                        (cell ? O.con1 : O.con0)[s].v[4 * d + 2 * o2 + o1] =
-                            (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
-            }
-        }
-        u[d] = u1;
-    }
-    O.head[s] = make_int4(pack_cell(c0[0], c0[1], c0[2]), (int)g[0], (int)g[1], (int)g[2]);
-    IonFQ<T> fq;
-    fq.f[0] = (T)f0[0];
-    fq.f[1] = (T)f0[1];
-    fq.f[2] = (T)f0[2];
-    fq.q = (T)qi;
-    O.fq[s] = fq;
-    return false;
-}
-
-template <typename T>
-__device__ __forceinline__ bool write_record(int L, double a, double qi, const double (&u_in)[3],
-                                             const double (&du)[3], int s, const DepOut<T> &O) {
-    return write_record_at<T>(L, a, qi, u_in, du, s, O, O.list_fail[s], O.cbin[s]);
-}
-
-// The displacement of storage index i for the step (the caller's index
-// perm[i]), sanitised and counted.
-__device__ __forceinline__ void step_displacement(int i, int L, double a, const double *__restrict__ disp,
-                                                  const int *__restrict__ perm, unsigned int *bad, uint64_t seed,
-                                                  uint32_t t, double sigma, double (&du)[3]) {
-    const int ci = perm ? perm[i] : i;
-    if (disp) {
-        du[0] = disp[3 * ci];
-        du[1] = disp[3 * ci + 1];
-        du[2] = disp[3 * ci + 2];
-    } else {
-        philox_displacement(seed, t, (uint32_t)ci, sigma, du);
-    }
-    sanitize_move(du, a, L, bad);
-}
-
 // Records for the step about to run, ions read in storage order
 // (coalesced), one lane per ion, ion i's record going to its slot
 // slot_of[i]; displacements are indexed by the caller's index perm[i], and
@@ -221,19 +107,6 @@ __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const
     step_displacement(i, L, a, disp, perm, bad, seed, t, sigma, du);
     const int s = slot_of[i];
     dep_atomic[s] = write_record<T>(L, a, q[i], u, du, s, O) ? 1 : 0;
-}
-
-template <typename T>
-static DepOut<T> dep_out(memd_ctx *c) {
-    DepOut<T> O;
-    O.head = c->rec_head;
-    O.con0 = (DepCell<T> *)c->rec_con;
-    O.con1 = (DepCell<T> *)c->rec_con1;
-    O.cbin = c->cbin;
-    O.list_fail = c->list_fail;
-    O.du = c->du_slot;
-    O.fq = (IonFQ<T> *)c->fq;
-    return O;
 }
 
 // Tile lists, built at a re-binning for the current tile shape: storage
@@ -413,136 +286,70 @@ hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint
     return hipGetLastError();
 }
 
-// The ion side of one step after the leapfrog with the fused deposit, in bin
-// order.  A block takes 128 ions; its wavefronts 0-1 and 2-3 run two
-// independent chains on them, with no block barrier:
-//   - wavefronts 0-1: the forces of the state the step started from: the
-//     lattice part and self force from the leapfrog tile that owns the
-//     ion's cell (stamped with this step's tag), or gathered here (force_ion
-//     on D^n, which the leapfrog left intact) for an ion no tile took; plus
-//     the dipole term with P^n, which the leapfrog summed from the previous
+// The ion side of one step after the fused leapfrog and its movers, one
+// ion per thread in bin order:
+//   - the forces of the state the step started from: the lattice part and
+//     self force from the leapfrog tile that owns the ion's start cell
+//     (stamped with that launch's tag), or gathered here (force_ion on D^n,
+//     which the leapfrog left intact) for an ion no tile took; plus the
+//     dipole term with P^n, which the leapfrog summed from the previous
 //     step's partials into the scalars;
-//   - wavefronts 2-3: irregular ions deposit their whole move into D^{n+1}
-//     with global atomics; every ion moves to r^{n+1} (written to r_out, so
-//     the force lanes still read r^n); one partial of q r^{n+1} per
-//     wavefront (dip_out); the deposit records
-//     of the next step (from r^{n+1} and its displacement), when pack is set.
-constexpr int kIonStepIons = 128;
-
+//   - the whole move of each irregular ion of the current records deposited
+//     into D^{n+1} with global atomics, from r^n (the movers wrote r^{n+1}
+//     elsewhere) and the record's displacement.
 template <typename T>
-struct IonStepArgs {
+struct IonFinishArgs {
     int n, L;
     size_t Ns;
     double a, V;
-    const double *q;
-    const double *r;
-    double *r_out;
+    const double *q, *r;
     const int *order;  // null: the identity (ions stored in bin order)
-    const int *perm;                 // storage index -> caller index (displacements), null: identity
-    const double *disp_next;  // null: the Philox displacements of step t + 1
-    uint64_t seed;
-    uint32_t t;
-    double sigma;
     const T *Dcur;
     T *Dnext;
     int eta_mode;
     double eta_uni;
     const T *eta_prof, *eta_link;
-    double *scal, *F;
+    const double *scal;
+    double *F;
     const double *Ft;           // [3n] by slot: lattice part + self force from the leapfrog tiles
     const unsigned int *fdone;  // [n] by slot: == tag when the tiles computed Ft
     unsigned int tag;
-    double *dip_out;
-    int *dep_atomic;  // [n] by slot: this step's ion left to the atomic path (read), the next step's (written)
-    int pack;         // write the next step's records
-    DepOut<T> out;
-    unsigned int *bad;
+    const int *dep_atomic;  // [n] by slot: the ion is left to the atomic path this step
+    const double *du;       // [3n] by slot: this step's displacements
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_ion_step(IonStepArgs<T> A) {
-    const bool mover = threadIdx.x >= kIonStepIons;
-    const int s = xcd_logical(blockIdx.x, gridDim.x) * kIonStepIons + (threadIdx.x & (kIonStepIons - 1));
-    const bool live = s < A.n;
-    const int i = live ? (A.order ? A.order[s] : s) : 0;
-    double F[3] = {0.0, 0.0, 0.0}, P[3] = {0.0, 0.0, 0.0}, qi = 0.0;
-    if (!mover) {
-        // lattice part and self force of r^n on D^n (from the leapfrog tile
-        // that owns the ion's cell, else gathered here); the dipole term is
-        // added at the end (x + 0 + y rounds as x + y).  The tile result is
-        // read with its stamp, not after it.
-        if (live) {
-            qi = A.q[i];
-            const double ft[3] = {A.Ft[3 * s], A.Ft[3 * s + 1], A.Ft[3 * s + 2]};
-            if (A.fdone[s] == A.tag) {
-                F[0] = ft[0];
-                F[1] = ft[1];
-                F[2] = ft[2];
-            } else {
-                const double u[3] = {A.r[3 * i], A.r[3 * i + 1], A.r[3 * i + 2]};
-                const EtaView<T> ev{A.eta_mode, A.eta_uni, A.eta_prof, A.eta_link};
-                const double zero[3] = {0.0, 0.0, 0.0};
-                force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.Dcur, ev, A.scal + S_G, zero, A.scal + S_EPSH, F);
-            }
+__global__ __launch_bounds__(256) void k_ion_finish(IonFinishArgs<T> A) {
+    const int s = xcd_logical(blockIdx.x, gridDim.x) * kThreads + (int)threadIdx.x;
+    if (s >= A.n) return;
+    const int i = A.order ? A.order[s] : s;
+    const double qi = A.q[i];
+    // the tile result is read with its stamp, not after it
+    const double ft[3] = {A.Ft[3 * s], A.Ft[3 * s + 1], A.Ft[3 * s + 2]};
+    const bool tiled = A.fdone[s] == A.tag;
+    const bool atomic_path = A.dep_atomic[s] != 0;
+    double F[3] = {ft[0], ft[1], ft[2]};
+    if (!tiled || atomic_path) {
+        const double u[3] = {A.r[3 * i], A.r[3 * i + 1], A.r[3 * i + 2]};
+        const EtaView<T> ev{A.eta_mode, A.eta_uni, A.eta_prof, A.eta_link};
+        if (!tiled) {
+            // the dipole term is added below (x + 0 + y rounds as x + y)
+            const double zero[3] = {0.0, 0.0, 0.0};
+            force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.Dcur, ev, A.scal + S_G, zero, A.scal + S_EPSH, F);
         }
-    } else if (live) {
-        const int ci = A.perm ? A.perm[i] : i;
-        double u[3] = {A.r[3 * i], A.r[3 * i + 1], A.r[3 * i + 2]};
-        qi = A.q[i];
-        // this step's displacement, sanitised and counted when its record was
-        // written; the next step's is gathered from the caller's order
-        double du[3] = {A.out.du[3 * s], A.out.du[3 * s + 1], A.out.du[3 * s + 2]};
-        double dn[3] = {0.0, 0.0, 0.0};
-        int lfail = 0, lcell = 0;  // the slot's list state, for the next record
-        if (A.pack) {
-            lfail = A.out.list_fail[s];
-            lcell = A.out.cbin[s];
-            if (A.disp_next) {
-#pragma unroll
-                for (int d = 0; d < 3; ++d) dn[d] = A.disp_next[3 * ci + d];
-            } else {
-                philox_displacement(A.seed, A.t + 1u, (uint32_t)ci, A.sigma, dn);
-            }
-        }
-        if (!A.dep_atomic[s]) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) u[d] = u[d] + du[d];
-        } else {
-            deposit_ion<T>(A.L, A.Ns, A.a, qi, u, du, A.Dnext);
-        }
-        A.r_out[3 * i] = u[0];
-        A.r_out[3 * i + 1] = u[1];
-        A.r_out[3 * i + 2] = u[2];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) P[d] = qi * u[d];
-        if (A.pack) {
-            sanitize_move(dn, A.a, A.L, A.bad);
-            A.dep_atomic[s] = write_record_at<T>(A.L, A.a, qi, u, dn, s, A.out, lfail, lcell) ? 1 : 0;
+        if (atomic_path) {
+            double w[3] = {u[0], u[1], u[2]};
+            const double du[3] = {A.du[3 * s], A.du[3 * s + 1], A.du[3 * s + 2]};
+            deposit_ion<T>(A.L, A.Ns, A.a, qi, w, du, A.Dnext);
         }
     }
-    if (mover) {
-        // one partial of q r^{n+1} per mover wavefront (no block barrier)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) P[d] = wave_sum(P[d]);
-        if ((threadIdx.x & 63) == 0) {
-            const int w = 2 * blockIdx.x + ((threadIdx.x - kIonStepIons) >> 6);
-            A.dip_out[3 * w] = P[0];
-            A.dip_out[3 * w + 1] = P[1];
-            A.dip_out[3 * w + 2] = P[2];
-        }
-    } else if (live) {
-        // P^n: summed from the previous step's partials by the leapfrog (or
-        // left by the call before)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) A.F[3 * i + d] = F[d] + qi * A.scal[S_P + d] / (A.V * A.scal[S_EPSH + d]);
-    }
+    for (int d = 0; d < 3; ++d) A.F[3 * i + d] = F[d] + qi * A.scal[S_P + d] / (A.V * A.scal[S_EPSH + d]);
 }
 
-hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const double *disp_next,
-                           uint64_t seed, uint32_t t, double sigma, double *dip_out, int *nparts, bool pack_next) {
-    const int nb = ion_blocks_x8(c->n, kThreads / kIonStepIons);
-    *nparts = 2 * nb;  // one dipole partial per mover wavefront
-    auto fill = [&](auto &A, auto *Dc, auto *Dn) {
+hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext) {
+    const int nb = ion_blocks_x8(c->n);
+    auto fill = [&](auto &A) {
         A.n = c->n;
         A.L = c->L;
         A.Ns = c->Ns;
@@ -550,15 +357,7 @@ hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const dou
         A.V = c->V;
         A.q = c->q;
         A.r = c->r;
-        A.r_out = c->r_alt;
         A.order = c->sorted ? nullptr : c->order;
-        A.perm = c->perm;
-        A.disp_next = disp_next;
-        A.seed = seed;
-        A.t = t;
-        A.sigma = sigma;
-        A.Dcur = Dc;
-        A.Dnext = Dn;
         A.eta_mode = c->eta_mode;
         A.eta_uni = c->eta_uni;
         A.scal = c->scal;
@@ -566,27 +365,26 @@ hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const dou
         A.Ft = c->Ft;
         A.fdone = c->fdone;
         A.tag = c->force_tag;
-        A.dip_out = dip_out;
         A.dep_atomic = c->dep_atomic;
-        A.pack = pack_next ? 1 : 0;
-        A.bad = c->bad_moves;
+        A.du = c->du_slot;
     };
     if (c->fp32) {
-        IonStepArgs<float> A;
-        fill(A, (const float *)Dcur, (float *)Dnext);
-        A.out = dep_out<float>(c);
+        IonFinishArgs<float> A;
+        fill(A);
+        A.Dcur = (const float *)Dcur;
+        A.Dnext = (float *)Dnext;
         A.eta_prof = (const float *)c->eta_prof;
         A.eta_link = (const float *)c->eta_link;
-        hipLaunchKernelGGL(k_ion_step<float>, dim3(nb), dim3(kThreads), 0, c->stream, A);
+        hipLaunchKernelGGL(k_ion_finish<float>, dim3(nb), dim3(kThreads), 0, c->stream, A);
     } else {
-        IonStepArgs<double> A;
-        fill(A, (const double *)Dcur, (double *)Dnext);
-        A.out = dep_out<double>(c);
+        IonFinishArgs<double> A;
+        fill(A);
+        A.Dcur = (const double *)Dcur;
+        A.Dnext = (double *)Dnext;
         A.eta_prof = (const double *)c->eta_prof;
         A.eta_link = (const double *)c->eta_link;
-        hipLaunchKernelGGL(k_ion_step<double>, dim3(nb), dim3(kThreads), 0, c->stream, A);
+        hipLaunchKernelGGL(k_ion_finish<double>, dim3(nb), dim3(kThreads), 0, c->stream, A);
     }
-    std::swap(c->r, c->r_alt);  // the new positions are now the current ones
     return hipGetLastError();
 }
 

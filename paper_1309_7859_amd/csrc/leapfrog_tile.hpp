@@ -116,10 +116,12 @@ struct DepArgs {
     unsigned int tag;
     const double *G;    // lattice Green's-function table G(0..3)
     double a;
-    // the previous ion step's dipole partials (nparts x 3; null: none), summed
-    // by block 0 into P (the scalars) in the dipole finaliser's order
+    // the previous step's dipole partials (nparts x 3; null: none), summed by
+    // workgroup dip_block (a tile) into P (the scalars) in the dipole
+    // finaliser's order
     const double *dip_prev;
     int dip_nparts;
+    int dip_block;
     double *P;
 };
 
@@ -284,7 +286,7 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             const int e = (int)threadIdx.x + j * (int)blockDim.x;
             pf_slot[j] = e < dep->cap ? dep->list[dep_base + e] : -1;
         }
-        if (dep->dip_prev && blockIdx.x == 0) {
+        if (dep->dip_prev && (int)blockIdx.x == dep->dip_block) {
             // wavefront sums of the dipole partials now, their sum after the
             // prologue's first barrier (the order of the dipole finaliser)
             double ps[3];
@@ -439,7 +441,7 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
                                            sX[0][2][yy][xx + 1] + sX[0][2][yy][xx]);
         }
         if constexpr (DEP) {
-            if (dep->dip_prev && blockIdx.x == 0 && threadIdx.x < 3) {
+            if (dep->dip_prev && (int)blockIdx.x == dep->dip_block && threadIdx.x < 3) {
                 double p = 0.0;
 #pragma unroll
                 for (int w = 0; w < 4; ++w) p += DS->psum[threadIdx.x][w];

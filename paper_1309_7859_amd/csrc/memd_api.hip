@@ -77,9 +77,23 @@ hipError_t ensure_stage(memd_ctx *c, size_t bytes) {
 }
 
 // Whether this launch of family fam is one of the timed ones.
+constexpr int kProfPoolPairs = 64;  // event pairs made per family when profiling is enabled
+
 static bool prof_take(memd_ctx *c, int fam) {
     if (!c->prof_on || !(c->prof_mask & (1u << fam))) return false;
     return c->prof[fam].seen++ % c->prof_every == 0;
+}
+
+// An event for a sample: from the pool made when profiling was enabled (so
+// that a sampled launch costs the host no event creation), else a new one.
+static hipError_t prof_event(memd_ctx *c, int fam, hipEvent_t *e) {
+    auto &pool = c->prof[fam].pool;
+    if (!pool.empty()) {
+        *e = pool.back();
+        pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
 }
 
 void prof_begin(memd_ctx *c, int fam) {
@@ -87,7 +101,7 @@ void prof_begin(memd_ctx *c, int fam) {
     P.open = false;
     if (!prof_take(c, fam)) return;
     hipEvent_t e;
-    if (hipEventCreate(&e) == hipSuccess) {
+    if (prof_event(c, fam, &e) == hipSuccess) {
         if (hipEventRecord(e, c->stream) == hipSuccess) {
             P.start.push_back(e);
             P.open = true;
@@ -101,10 +115,11 @@ void prof_end(memd_ctx *c, int fam) {
     auto &P = c->prof[fam];
     if (!P.open) return;
     P.open = false;
-    hipEvent_t e;
-    if (hipEventCreate(&e) == hipSuccess && hipEventRecord(e, c->stream) == hipSuccess) {
+    hipEvent_t e = nullptr;
+    if (prof_event(c, fam, &e) == hipSuccess && hipEventRecord(e, c->stream) == hipSuccess) {
         P.stop.push_back(e);
     } else {
+        if (e) hipEventDestroy(e);
         hipEventDestroy(P.start.back());
         P.start.pop_back();
     }
@@ -115,8 +130,8 @@ void prof_end(memd_ctx *c, int fam) {
 void prof_pair(memd_ctx *c, int fam, hipEvent_t *e0, hipEvent_t *e1) {
     *e0 = *e1 = nullptr;
     if (!prof_take(c, fam)) return;
-    if (hipEventCreate(e0) != hipSuccess) return;
-    if (hipEventCreate(e1) != hipSuccess) {
+    if (prof_event(c, fam, e0) != hipSuccess) return;
+    if (prof_event(c, fam, e1) != hipSuccess) {
         hipEventDestroy(*e0);
         *e0 = nullptr;
         return;
@@ -129,8 +144,10 @@ void prof_clear(memd_ctx *c) {
     for (int f = 0; f < F_NFAM; ++f) {
         for (auto e : c->prof[f].start) hipEventDestroy(e);
         for (auto e : c->prof[f].stop) hipEventDestroy(e);
+        for (auto e : c->prof[f].pool) hipEventDestroy(e);
         c->prof[f].start.clear();
         c->prof[f].stop.clear();
+        c->prof[f].pool.clear();
         c->prof[f].seen = 0;
         c->prof[f].open = false;
     }
@@ -254,6 +271,7 @@ void memd_destroy(memd_ctx *c) {
     void *bufs[] = {c->D[0], c->D[1], c->B[0], c->B[1], c->eta_prof, c->eta_link, c->q, c->r, c->F,
                     c->order, c->slot, c->bins, c->bad_moves, c->dep_atomic, c->rec_head, c->rec_con, c->list,
                     c->list_count, c->cbin, c->list_fail, c->du_slot, c->fq, c->ecell, c->Ft, c->fdone,
+                    c->rec_head_nx, c->rec_con_nx, c->du_slot_nx, c->fq_nx, c->dep_atomic_nx,
                     c->dip[0], c->dip[1],
                     c->perm, c->perm_alt, c->r_alt, c->q_alt, c->F_alt,
                     c->stage, c->rho, c->drift, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt};
@@ -377,11 +395,17 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
             hipMalloc(&c->fq, nn * (c->fp32 ? sizeof(IonFQ<float>) : sizeof(IonFQ<double>))) != hipSuccess ||
             hipMalloc(&c->ecell, Ns * c->tsize) != hipSuccess ||
             hipMalloc((void **)&c->Ft, 3 * nn * sizeof(double)) != hipSuccess ||
-            hipMalloc((void **)&c->fdone, nn * sizeof(unsigned int)) != hipSuccess) {
+            hipMalloc((void **)&c->fdone, nn * sizeof(unsigned int)) != hipSuccess ||
+            hipMalloc((void **)&c->rec_head_nx, nn * sizeof(int4)) != hipSuccess ||
+            hipMalloc(&c->rec_con_nx, nn * rec) != hipSuccess ||
+            hipMalloc((void **)&c->du_slot_nx, 3 * nn * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->fq_nx, nn * (c->fp32 ? sizeof(IonFQ<float>) : sizeof(IonFQ<double>))) != hipSuccess ||
+            hipMalloc((void **)&c->dep_atomic_nx, nn * sizeof(int)) != hipSuccess) {
             (void)hipGetLastError();
             return fail(MEMD_ENOMEM);
         }
         c->rec_con1 = (char *)c->rec_con + nn * (rec / 2);
+        c->rec_con1_nx = (char *)c->rec_con_nx + nn * (rec / 2);
     }
     hipStream_t s = c->stream;
     if (c->fdone) hipMemsetAsync(c->fdone, 0, nn * sizeof(unsigned int), s);  // no launch is stamped 0
@@ -524,13 +548,25 @@ memd_status memd_initial_gauss_solve(memd_ctx *c, double tol, int max_iter, int 
 
 namespace {
 
+// The records the movers wrote for the step after the current one become
+// the current ones.
+void swap_record_sets(memd_ctx *c) {
+    std::swap(c->rec_head, c->rec_head_nx);
+    std::swap(c->rec_con, c->rec_con_nx);
+    std::swap(c->rec_con1, c->rec_con1_nx);
+    std::swap(c->du_slot, c->du_slot_nx);
+    std::swap(c->fq, c->fq_nx);
+    std::swap(c->dep_atomic, c->dep_atomic_nx);
+}
+
 // The per-step launch sequence (displacements from disp, or from the Philox
 // stream of `seed` when disp is null).
 //
 // With the fused deposit a step is two kernels: the leapfrog (with the
-// tile-owned deposit of the regular ions) and the ion step, which also
-// computes the forces of the state the step started from and writes the
-// next step's deposit records.  The first step of a call skips those forces
+// tile-owned deposit of the regular ions, and the ion movers, which also
+// write the next step's deposit records) and the ion finisher, which
+// computes the forces of the state the step started from and deposits the
+// irregular ions.  The first step of a call skips those forces
 // (the previous call, or the solve or set_state, left them in F), and after
 // the last step one force launch gives the forces of the final state, so
 // each state's forces are computed once.  Otherwise: leapfrog, the atomic
@@ -558,23 +594,24 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
             recs_ready = false;
         }
         const bool fused = fused_deposit_ok(c);
+        // with the fused deposit, the movers write the next step's records
+        // only when it exists in this call and does not re-bin first
+        const bool pack_next = fused && t + 1 < nsteps && !(c->sort_every > 0 && next % c->sort_every == 0);
+        IonMoves mv{dd && pack_next ? dd + per * (t + 1) : nullptr, seed, tstep + 1u, sigma, pack_next,
+                    c->dip[c->step_index & 1], 0};
         hipEvent_t e0 = nullptr, e1 = nullptr;
         prof_pair(c, F_LEAPFROG, &e0, &e1);
         CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx], e0, e1, dstep, seed, tstep, sigma,
-                           fused, !recs_ready, fused ? dip_prev : nullptr, dip_nb));
+                           fused, !recs_ready, fused ? dip_prev : nullptr, dip_nb, fused ? &mv : nullptr));
         if (fused) {
-            // records for the next step only when it exists in this call and
-            // does not re-bin first
-            const bool pack_next =
-                t + 1 < nsteps && !(c->sort_every > 0 && next % c->sort_every == 0);
-            double *dip_out = c->dip[c->step_index & 1];
             prof_begin(c, F_DEPOSIT);
-            CK(launch_ion_step(c, c->D[c->cur], c->D[nx], dd && pack_next ? dd + per * (t + 1) : nullptr,
-                               seed, tstep, sigma, dip_out, &nb, pack_next));
+            CK(launch_ion_finish(c, c->D[c->cur], c->D[nx]));
             prof_end(c, F_DEPOSIT);
+            std::swap(c->r, c->r_alt);  // the movers' positions are now the current ones
+            if (pack_next) swap_record_sets(c);
             recs_ready = pack_next;
-            dip_prev = dip_out;
-            dip_nb = nb;
+            dip_prev = mv.dip_out;
+            dip_nb = mv.nparts;
             c->cur = nx;
             if (energy_now)  // U_dip and the self-energy pass read P of this state
                 CK(launch_finalize_dipole(c->stream, dip_prev, dip_nb, c->scal + S_P));
@@ -812,6 +849,17 @@ memd_status memd_profile_enable(memd_ctx *c, int mask, int every) {
     c->prof_on = mask != 0;
     c->prof_mask = (unsigned)mask;
     c->prof_every = every;
+    for (int f = 0; f < F_NFAM; ++f) {
+        if (!(c->prof_mask & (1u << f))) continue;
+        for (int k = 0; k < 2 * kProfPoolPairs; ++k) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                break;
+            }
+            c->prof[f].pool.push_back(e);
+        }
+    }
     return MEMD_OK;
 }
 

@@ -45,6 +45,7 @@ struct EtaDesc {
 
 struct ProfileEvents {
     std::vector<hipEvent_t> start, stop;
+    std::vector<hipEvent_t> pool;  // made in advance, not yet used
     long seen = 0;  // launches of the family since the collection started
     bool open = false;  // a begin event is waiting for its end
 };
@@ -103,6 +104,13 @@ struct memd_ctx {
     void *rec_con, *rec_con1;  // the records' first cells, second cells (one allocation)
     int *list, *list_count, *cbin, *list_fail;
     double *du_slot;  // [3n] by slot: the displacement each record was made for
+    // The second record set (head, values, displacement, fq, dep_atomic):
+    // the ion movers of a fused leapfrog launch fill it for the step after
+    // the current one, and the two sets swap when that step starts.
+    int4 *rec_head_nx;
+    void *rec_con_nx, *rec_con1_nx, *fq_nx;
+    double *du_slot_nx;
+    int *dep_atomic_nx;
     // Forces computed by the leapfrog tiles (DepArgs): fractional positions
     // and charges by slot (fq), 12 / (sum of the cell's 12 eta) per site
     // (ecell), the tile results by slot (Ft) with their launch stamp (fdone,
@@ -150,18 +158,35 @@ struct memd_ctx {
 
 namespace memd {
 
+// The ion movers of a fused leapfrog launch (ion_records.hpp): every ion
+// moved by its record's displacement into r_alt, one dipole partial of
+// q r^{n+1} per mover wavefront into dip_out (nparts, set by the launch),
+// and with pack_next the next step's records (displacements disp_next, or
+// the Philox stream at t_next) into the second record set.
+struct IonMoves {
+    const double *disp_next;
+    uint64_t seed;
+    uint32_t t_next;
+    double sigma;
+    bool pack_next;
+    double *dip_out;
+    int nparts;
+};
+
 // ---- launchers (field kernels) ----
 // ev0/ev1 (optional): events recorded at the kernel's start and end.
 // with_deposit: the regular ions' deposit is fused in (displacements from disp,
 // or from the Philox stream when disp is null); requires fused_deposit_ok(c).
-// need_pack: write the deposit records first (false when the previous step's
-// ion kernel already wrote them for this step).  dip_prev (nparts values of
-// 3): the previous ion step's dipole partials, which the fused kernel sums
-// into the scalars' P (null: P is already there).
+// need_pack: write the deposit records first (false when the previous
+// launch's movers already wrote them for this step).  dip_prev (nparts
+// values of 3): the previous step's dipole partials, which the fused kernel
+// sums into the scalars' P (null: P is already there).  moves (with the
+// deposit only; null: none): the ion movers run in the same launch.
 hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout,
                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, const double *disp = nullptr,
                            uint64_t seed = 0, uint32_t t = 0, double sigma = 0.0, bool with_deposit = false,
-                           bool need_pack = true, const double *dip_prev = nullptr, int dip_nparts = 0);
+                           bool need_pack = true, const double *dip_prev = nullptr, int dip_nparts = 0,
+                           IonMoves *moves = nullptr);
 bool fused_deposit_ok(const memd_ctx *c);
 // Tiles of the current leapfrog tile shape, and the list capacity per tile.
 int list_tiles(const memd_ctx *c);
@@ -173,14 +198,12 @@ hipError_t launch_build_lists(memd_ctx *c, bool pack, const double *disp, uint64
 // (no-op when the context has no fused deposit).
 hipError_t launch_ecell(memd_ctx *c);
 hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma);
-// The ion side of a step after the fused leapfrog (k_ion_step): forces of the
-// state the step started from (tile results plus the dipole term with the
-// scalars' P), irregular ions deposited into Dnext with global atomics,
-// every position advanced by the displacement stored with its record,
-// dipole partials into dip_out (nparts of them), the next step's deposit
-// records (pack_next; displacements disp_next or the Philox stream at t + 1).
-hipError_t launch_ion_step(memd_ctx *c, const void *Dcur, void *Dnext, const double *disp_next,
-                           uint64_t seed, uint32_t t, double sigma, double *dip_out, int *nparts, bool pack_next);
+// The ion side of a step after the fused leapfrog and its movers
+// (k_ion_finish): forces of the state the step started from (tile results,
+// or gathered from Dcur at r^n, plus the dipole term with the scalars' P),
+// and the irregular ions of the current records deposited into Dnext with
+// global atomics (from r^n, still in c->r).
+hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext);
 hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
                                int *nblk);
 hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk);
