@@ -131,19 +131,18 @@ __device__ __forceinline__ void step_displacement(int i, int L, double a, const 
     sanitize_move(du, a, L, bad);
 }
 
-// The ion movers: workgroups of the fused leapfrog launch beside its tiles.
-// Nothing they read or write is touched by the tiles of the same launch:
-// they move every
-// ion to r^{n+1} = r^n + du (into r_out; r^n stays for the forces and the
-// irregular ions' deposit that follow the launch), write one partial of
-// q r^{n+1} per wavefront, and, with pack set, the next step's records into
-// the second record set (the tiles read the first).
-constexpr int kMoverPerThread = 1;
-constexpr int kMoverIons = 256 * kMoverPerThread;  // ions per mover workgroup (256 threads)
+// The ion movers of the fused leapfrog launch.  Nothing they read or write
+// is touched by the tiles of the same launch: they move every ion to
+// r^{n+1} = r^n + du (into r_out; r^n stays for the forces and the irregular
+// ions' deposit that follow the launch), write one partial of q r^{n+1} per
+// wavefront, and, with pack set, the next step's records into the second
+// record set (the tiles read the first).  They run as workgroups of their
+// own ahead of the tiles (nblocks of them, kMoverIons ions each).
+constexpr int kMoverIons = 256;  // ions per mover workgroup, one per thread
 
 template <typename T>
 struct MoverArgs {
-    int nblocks;  // mover workgroups after the tiles (0: none)
+    int nblocks;  // mover workgroups ahead of the tiles (0: none)
     int n, L;
     double a;
     const double *q, *r;
@@ -151,7 +150,7 @@ struct MoverArgs {
     const int *order;  // null: ions stored in bin order
     const int *perm;   // storage index -> caller index (displacements), null: identity
     const double *du;  // [3n] by slot: this step's displacements (the current records')
-    double *dip_out;   // 4 partials of q r^{n+1} per mover workgroup
+    double *dip_out;   // one partial of q r^{n+1} per wavefront: 4 per mover workgroup
     int pack;          // write the next step's records
     const double *disp_next;  // null: the Philox displacements of step t_next
     uint64_t seed;
@@ -162,13 +161,13 @@ struct MoverArgs {
     DepOut<T> out;     // the next step's records (cbin, list_fail: the lists' state)
 };
 
+// Slots [s0, s0 + count) by the workgroup's 256 threads; partials to
+// dip_out[part0 .. part0 + 3] (zero for a wavefront without ions).
 template <typename T>
-__device__ __forceinline__ void move_ions(const MoverArgs<T> &M, int m) {
+__device__ __forceinline__ void move_ions(const MoverArgs<T> &M, int s0, int count, int part0) {
     double P[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int k = 0; k < kMoverPerThread; ++k) {
-        const int s = m * kMoverIons + 256 * k + (int)threadIdx.x;
-        if (s >= M.n) break;
+    const int s1 = min(s0 + count, M.n);
+    for (int s = s0 + (int)threadIdx.x; s < s1; s += 256) {
         const int i = M.order ? M.order[s] : s;
         const int ci = M.perm ? M.perm[i] : i;
         double u[3] = {M.r[3 * i], M.r[3 * i + 1], M.r[3 * i + 2]};
@@ -202,7 +201,7 @@ __device__ __forceinline__ void move_ions(const MoverArgs<T> &M, int m) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) P[d] = wave_sum(P[d]);
     if ((threadIdx.x & 63) == 0) {
-        const int w = 4 * m + (int)(threadIdx.x >> 6);
+        const int w = part0 + (int)(threadIdx.x >> 6);
         M.dip_out[3 * w] = P[0];
         M.dip_out[3 * w + 1] = P[1];
         M.dip_out[3 * w + 2] = P[2];
@@ -225,6 +224,7 @@ inline DepOut<T> dep_out(const memd_ctx *c, bool next = false) {
 }
 
 inline int mover_blocks(int n) { return n > 0 ? (n + kMoverIons - 1) / kMoverIons : 0; }
+
 
 template <typename T>
 inline MoverArgs<T> mover_args(const memd_ctx *c, const IonMoves &mv) {

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_leapfrog_dep(LfArgs<T> A, DepArgs P, Mo
     __shared__ LfSmem<T, R> S;
     __shared__ DepSmem<T, R, TZ> DS;
     if ((int)blockIdx.x < M.nblocks) {
-        move_ions<T>(M, (int)blockIdx.x);
+        move_ions<T>(M, (int)blockIdx.x * kMoverIons, kMoverIons, 4 * (int)blockIdx.x);
         return;
     }
     const int logical = xcd_logical((int)blockIdx.x - M.nblocks, (int)gridDim.x - M.nblocks);
@@ -116,7 +116,7 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
     const DepArgs *dp = nullptr;
     if (with_deposit) {
         // the lists first (records read each ion's list cell), then the
-        // records unless the previous ion step wrote them against these lists
+        // records unless the previous launch's movers wrote them against these lists
         const bool rebuild = c->lists_key != c->lf_rows * 4096 + c->lf_tz;
         if (rebuild) {
             hipError_t e = launch_build_lists(c, true, disp, seed, t, sigma);

@@ -92,8 +92,8 @@ __global__ void k_fill_int(int *dst, int v, size_t count);
 // Records for the step about to run, ions read in storage order
 // (coalesced), one lane per ion, ion i's record going to its slot
 // slot_of[i]; displacements are indexed by the caller's index perm[i], and
-// rejected components are counted here (the ion step reads the sanitised
-// displacement back from the record's slot).
+// rejected components are counted here (the movers and the finisher read
+// the sanitised displacement back from the record's slot).
 template <typename T>
 __global__ __launch_bounds__(256) void k_pack_ions(int n, int L, double a, const double *__restrict__ q,
                                                    const double *__restrict__ r, const double *__restrict__ disp,
@@ -562,7 +562,7 @@ struct ForceArgs {
 // Forces on every ion, one lane per ion following `order` (force_ion: the
 // lattice part from the 12 links of the cell, self force, dipole
 // correction).  With dip_partials set, every block sums the per-wavefront
-// q r partials of the last ion step into P (in the dipole finaliser's order;
+// q r partials of the last step's movers into P (in the dipole finaliser's order;
 // block 0 also stores it) while its force gathers are in flight.
 template <typename T>
 __global__ __launch_bounds__(256) void k_forces(ForceArgs<T> A) {

@@ -348,6 +348,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
 
     const size_t fb = 3 * Ns * c->tsize;
     const size_t nn = (size_t)(n > 0 ? n : 1);
+    const size_t dip_parts = nn / 64 + 32;  // dipole partials: 4 per mover workgroup of 256 ions
     if (hipMalloc(&c->D[0], fb) != hipSuccess || hipMalloc(&c->D[1], fb) != hipSuccess ||
         hipMalloc(&c->B[0], fb) != hipSuccess || hipMalloc(&c->B[1], fb) != hipSuccess ||
         hipMalloc(&c->eta_prof, 3 * (size_t)c->L * c->tsize) != hipSuccess ||
@@ -367,8 +368,8 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
         hipMalloc((void **)&c->rho, Ns * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->drift, nn * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->partials, partial_doubles(n) * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->dip[0], 3 * (nn / 64 + 32) * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->dip[1], 3 * (nn / 64 + 32) * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->dip[0], 3 * dip_parts * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->dip[1], 3 * dip_parts * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->scal, S_COUNT * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->hist_audit, 2 * (size_t)kHistCap * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->hist_energy, 5 * (size_t)kHistCap * sizeof(double)) != hipSuccess) {
@@ -573,7 +574,7 @@ void swap_record_sets(memd_ctx *c) {
 // deposit, forces.
 memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, double sigma) {
     const size_t per = 3 * (size_t)c->n;
-    bool recs_ready = false;  // the deposit records of this step were written by the previous ion step
+    bool recs_ready = false;  // the deposit records of this step were written by the previous step's movers
     const double *dip_prev = nullptr;
     int dip_nb = 0;
     for (int t = 0; t < nsteps; ++t) {
