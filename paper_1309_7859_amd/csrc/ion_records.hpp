@@ -137,12 +137,14 @@ __device__ __forceinline__ void step_displacement(int i, int L, double a, const 
 // ions' deposit that follow the launch), write one partial of q r^{n+1} per
 // wavefront, and, with pack set, the next step's records into the second
 // record set (the tiles read the first).  They run as workgroups of their
-// own ahead of the tiles (nblocks of them, kMoverIons ions each).
+// own beside the tiles (nblocks of them, kMoverIons ions each; ahead: the
+// first workgroups of the launch, else the last).
 constexpr int kMoverIons = 256;  // ions per mover workgroup, one per thread
 
 template <typename T>
 struct MoverArgs {
-    int nblocks;  // mover workgroups ahead of the tiles (0: none)
+    int nblocks;  // mover workgroups (0: none)
+    int ahead;    // the movers are the launch's first workgroups (else its last)
     int n, L;
     double a;
     const double *q, *r;
@@ -230,6 +232,7 @@ template <typename T>
 inline MoverArgs<T> mover_args(const memd_ctx *c, const IonMoves &mv) {
     MoverArgs<T> M;
     M.nblocks = mover_blocks(c->n);
+    M.ahead = 0;  // chosen at the launch
     M.n = c->n;
     M.L = c->L;
     M.a = c->a;

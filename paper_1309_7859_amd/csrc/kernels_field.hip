@@ -23,21 +23,42 @@ __global__ __launch_bounds__(256) void k_leapfrog(LfArgs<T> A) {
 }
 
 // The leapfrog with the deposit of the regular ions fused in (leapfrog_tile.hpp),
-// and the ion movers (ion_records.hpp) as the first M.nblocks workgroups: they
-// take CU slots at the start, and the tiles they hold back then fill the
-// slots that tiles free at the end.
+// and the ion movers (ion_records.hpp) as M.nblocks workgroups of their own:
+// ahead of the tiles when every tile is resident at once (they take CU slots
+// at the start, and the tiles they hold back fill the slots that tiles free
+// at the end), else after them (they fill the last round's free slots).
 template <typename T, int EM, int R, int TZ>
 __global__ __launch_bounds__(256) void k_leapfrog_dep(LfArgs<T> A, DepArgs P, MoverArgs<T> M) {
     __shared__ LfSmem<T, R> S;
     __shared__ DepSmem<T, R, TZ> DS;
-    if ((int)blockIdx.x < M.nblocks) {
-        move_ions<T>(M, (int)blockIdx.x * kMoverIons, kMoverIons, 4 * (int)blockIdx.x);
+    const int b = (int)blockIdx.x, nt = (int)gridDim.x - M.nblocks;
+    const int m = M.ahead ? b : b - nt;  // the mover index, for a mover workgroup
+    if (m >= 0 && m < M.nblocks) {
+        move_ions<T>(M, m * kMoverIons, kMoverIons, 4 * m);
         return;
     }
-    const int logical = xcd_logical((int)blockIdx.x - M.nblocks, (int)gridDim.x - M.nblocks);
+    const int logical = xcd_logical(M.ahead ? b - M.nblocks : b, nt);
     const int tile_x = logical % A.ntx;
     const int rest = logical / A.ntx;
     leapfrog_tile<T, EM, R, true, TZ>(A, tile_x, rest % A.nty, rest / A.nty, S, &P, &DS);
+}
+
+// Workgroups of the kernel the whole device holds at once (0: unknown).
+static int resident_blocks(const void *kernel) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * cus;
+}
+
+template <typename T, int EM, int R, int TZ>
+static int dep_resident() {
+    static const int slots = resident_blocks((const void *)k_leapfrog_dep<T, EM, R, TZ>);
+    return slots;
 }
 
 template <typename T, int EM>
@@ -65,21 +86,22 @@ static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, voi
     if (dep) {
         MoverArgs<T> M{};
         if (mv) M = *mv;
-        DepArgs P = *dep;
-        P.dip_block = M.nblocks;  // the first tile
-        dep = &P;
-        const int ng = nblk + M.nblocks;
+        void (*kern)(LfArgs<T>, DepArgs, MoverArgs<T>) = nullptr;
+        int slots = 0;
         if (R == 1 && A.tz > kDepTZ) {
-            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 1, kDepTZWide>), dim3(ng), dim3(256), 0, c->stream, e0,
-                                  e1, 0, A, *dep, M);
-            return hipGetLastError();
+            kern = k_leapfrog_dep<T, EM, 1, kDepTZWide>;
+            slots = dep_resident<T, EM, 1, kDepTZWide>();
+        } else if (R == 1) {
+            kern = k_leapfrog_dep<T, EM, 1, kDepTZ>;
+            slots = dep_resident<T, EM, 1, kDepTZ>();
+        } else {
+            kern = k_leapfrog_dep<T, EM, 2, kDepTZ>;
+            slots = dep_resident<T, EM, 2, kDepTZ>();
         }
-        if (R == 1)
-            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 1, kDepTZ>), dim3(ng), dim3(256), 0, c->stream, e0, e1,
-                                  0, A, *dep, M);
-        else
-            hipExtLaunchKernelGGL((k_leapfrog_dep<T, EM, 2, kDepTZ>), dim3(ng), dim3(256), 0, c->stream, e0, e1,
-                                  0, A, *dep, M);
+        M.ahead = nblk <= slots ? 1 : 0;
+        DepArgs P = *dep;
+        P.dip_block = M.ahead ? M.nblocks : 0;  // the first tile sums the dipole
+        hipExtLaunchKernelGGL(kern, dim3(nblk + M.nblocks), dim3(256), 0, c->stream, e0, e1, 0, A, P, M);
         return hipGetLastError();
     }
     if (R == 1)
