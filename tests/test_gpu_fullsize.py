@@ -1,9 +1,12 @@
 """Parity at the full size of the timed workload: 128^3 lattice, 10^5 ions,
 salt-dependent permittivity per link recomputed every 50 steps, in the launch
 configuration the bench times (autotuned tile shape, the leapfrog with the
-fused deposit, several steps per call so that the ion step computes the
-forces of the state it starts from and packs the next step's deposit, a
-re-binning of the ions inside the run).
+fused deposit and its ion movers, several steps per call so that the
+finisher computes the forces of the state each step starts from and the
+movers write the next step's records), with the ions re-binned every 8
+steps and the run split over two calls, so that records are built by the
+re-binning, by the pack at a call's start and by the movers, on both
+record sets.
 
 Both sides start from the oracle's recursion solution (its CG relaxation at
 128^3 is a one-off outside the step) and take the same seeded displacements.
@@ -21,6 +24,7 @@ from tests.gpu_helpers import energy_err, force_err, require_gpu
 pytestmark = pytest.mark.gpu
 
 STEPS = 20
+SPLIT = 7  # the first call's steps
 CADENCE = 10
 
 
@@ -45,8 +49,10 @@ def test_c4_full_size_parity(prec):
         G.set_salt(80.0, 15.0, 1.0, every=50)
         G.set_state(D0, B0, r0)
         memd.memd_autotune(G.ctx, 3, None)
+        memd.memd_set_options(G.ctx, 1, 8)
         assert memd.memd_counters(G.ctx)[1] == 1  # the fused path, as in the bench
-        G.step(disp, STEPS)
+        G.step(disp[:SPLIT], SPLIT)
+        G.step(disp[SPLIT:], STEPS - SPLIT)
         gauss = []
         for t in range(STEPS):
             if t % 50 == 0:

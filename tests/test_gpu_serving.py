@@ -51,6 +51,38 @@ def test_seeded_step_matches_oracle():
     assert np.max(np.abs(G.state()[2] - S.r)) <= 1e-12
 
 
+@pytest.mark.parametrize("prec", [memd.FP32_MIXED, memd.FP64])
+def test_seeded_fused_step_matches_oracle(prec):
+    """Device-drawn displacements on the fused path (L >= 16): the movers of
+    each leapfrog launch draw the next step's displacements themselves, over
+    two calls and re-binnings every 4 steps."""
+    L, n, seed, sigma = 24, 400, 2024, 0.05
+    rng = np.random.default_rng(11)
+    q = np.repeat([1.0, -1.0], n // 2)
+    r = rng.uniform(0, L, size=(n, 3))
+    c = W.default_c(1.0, 0.01, 5.0)
+    S = oracle.System(L, 1.0, 0.01, c, q, r)
+    S.set_eps_uniform(5.0)
+    S.initial_solve(1e-13)
+    G = memd.Context(L, q, r, c=c, precision=prec)
+    try:
+        G.set_permittivity(memd.EPS_UNIFORM, [5.0])
+        G.set_state(*S.state())
+        memd.memd_set_options(G.ctx, 1, 4)
+        assert memd.memd_counters(G.ctx)[1] == 1
+        memd.memd_step_seeded(G.ctx, seed, sigma, 6)
+        memd.memd_step_seeded(G.ctx, seed, sigma, 9)
+        for t in range(15):
+            S.step(oracle.seeded_displacements(seed, t, n, sigma))
+        fp32 = prec == memd.FP32_MIXED
+        assert force_err(G.forces(), S.forces()[0]) <= (1e-4 if fp32 else 1e-10)
+        assert np.max(np.abs(G.state()[2] - S.r)) <= 1e-12 * L
+        m, _ = G.gauss_residual()
+        assert m <= (1e-5 if fp32 else 1e-12)
+    finally:
+        G.close()
+
+
 def _served(specs, budget=8 << 30, **kw):
     out = serve.run_stream(specs, budget, max_slots=64, workers=2, poll_steps=3, **kw)
     return out
