@@ -68,9 +68,13 @@ size_t resident_bytes(int L, int n) {
                + (2 + 5) * 4096 * sizeof(double)     // histories
                + 3 * (size_t)L * sizeof(float) + (1 << 16)
                + ((size_t)kSiteBlocks * 4 + nn / 16 * 3 + 4096) * sizeof(double);  // reduction scratch
-    if (n > 0 && L >= 16 && L <= 1024) {  // tile buckets of the fused deposit (FP32 records)
+    if (n > 0 && L >= 16 && L <= 1024) {  // the fused deposit (FP32 fields)
         const size_t tiles = (((size_t)L + 63) / 64) * (((size_t)L + 3) / 4) * (((size_t)L + 1) / 2);
-        b += (4 * nn + 64 * tiles) * (16 + 24 * sizeof(float)) + tiles * 128;
+        // two record sets: head, both cells' values, displacement, fq, flag
+        b += 2 * nn * (16 + 24 * sizeof(float) + 24 + 16 + 4);
+        b += (12 * nn + 64 * tiles) * sizeof(int) + tiles * 128;  // tile lists and their counts
+        b += nn * (2 * sizeof(int) + 24 + 4);                     // cbin, list_fail, Ft, fdone
+        b += Ns * sizeof(float);                                  // 12 / sum(eta) per site
     }
     return b;
 }
