@@ -414,6 +414,36 @@ def test_fused_deposit_matches_atomic_path_and_oracle(prec, tile, L):
     assert np.max(np.abs(G.state()[2] - S.r)) <= 1e-12
 
 
+@pytest.mark.parametrize("prec", [memd.FP64, memd.FP32_MIXED])
+def test_fused_mixed_moves_in_one_call(prec):
+    """The same mixed moves (jumps of up to 2.5 a among small steps) taken in
+    one call, re-binning every 5 steps: the records of most steps are then
+    written by the previous launch's movers into the other record set, and
+    the jumping ions they mark reach D^{n+1} through the finisher's atomic
+    deposit."""
+    L, n, steps = 32, 600, 13
+    rng = np.random.default_rng(24)
+    r = rng.uniform(0, L, size=(n, 3))
+    q = np.tile([1.0, -1.0, 2.0, -2.0], n // 4)
+    el = 2.0 + 20.0 * rng.uniform(size=3 * L ** 3)
+    S, G = pair(L, q, r, dt=0.01, eps_min=el.min(), precision=prec)
+    apply_eps(S, G, "link", eps_link=el)
+    S.initial_solve(1e-13)
+    share_state(S, G)
+    memd.memd_set_options(G.ctx, 1, 5)
+    assert memd.memd_counters(G.ctx)[1] == 1
+    disp = _mixed_moves(rng, steps, n)
+    G.step(disp, steps)
+    for t in range(steps):
+        S.step(disp[t])
+    fp32 = prec == memd.FP32_MIXED
+    assert G.gauss_residual()[0] <= (1e-5 * 2 if fp32 else 1e-12)
+    Fo, _ = S.forces()
+    assert force_err(G.forces(), Fo) <= (1e-4 if fp32 else 1e-10)
+    assert np.max(np.abs(G.state()[2] - S.r)) <= 1e-12 * L
+    assert np.max(np.abs(G.dipole() - S.dipole())) <= 1e-12 * max(1.0, np.max(np.abs(S.dipole())))
+
+
 def test_fused_deposit_with_stale_bins():
     """Bins never refreshed (sort_every = 0) while ions drift several rows: the
     drifted ions fall back to the atomic path and the result stays exact."""
