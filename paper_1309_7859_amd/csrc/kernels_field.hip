@@ -529,8 +529,11 @@ hipError_t launch_eta_sums(memd_ctx *c, double *partials, int *nblk) {
 // A workgroup takes tiles of 64 x 4 sites and marches through a chunk of
 // kSaltTZ planes.  Per plane R it stages cnt with a one-site halo in LDS,
 // forms the 3 x 3 sums over (x, y) for the 65 x 5 corners its cells need,
-// keeps three such planes, and from them nbar of planes R-1 (two kept); the
-// outputs of plane R-2 then need nothing outside LDS.
+// keeps three such planes, and from them nbar of plane R-1 (two planes
+// kept).  From nbar of planes P and P+1 (P = R-2) it computes eta of the own
+// links of plane P's sites, the tile and a +1 halo in x and y, once each
+// (two planes kept in LDS), and stores the tile's; 12 / (sum of eta over the
+// 12 edges of a cell) of plane P-1 then reads them all from LDS.
 constexpr int kSaltTZ = 8;
 
 template <typename T>
@@ -540,6 +543,7 @@ __global__ __launch_bounds__(256) void k_salt_tile(const double *__restrict__ cn
     __shared__ double sc[7][67];      // cnt of plane R, x0-1 .. x0+65, y0-1 .. y0+5
     __shared__ double sS[3][5][65];   // (x, y) box sums of planes R, R-1, R-2 (ring by plane)
     __shared__ double sN[2][5][65];   // nbar of two planes (ring by plane)
+    __shared__ T sE[2][3][5][65];     // eta of the own links of two planes' sites (ring by plane)
     const int lx = threadIdx.x & 63, wy = threadIdx.x >> 6;
     const int ntx = (L + 63) >> 6, nty = (L + 3) >> 2, ntz = (L + kSaltTZ - 1) / kSaltTZ;
     const int tiles = ntx * nty * ntz;
@@ -560,13 +564,13 @@ __global__ __launch_bounds__(256) void k_salt_tile(const double *__restrict__ cn
         };
         double pl[2];
         fetch(z0 - 1, pl);
-        for (int R = z0 - 1; R <= z1 + 1; ++R) {
+        for (int R = z0 - 1; R <= z1 + 2; ++R) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const int t = threadIdx.x + 256 * j;
                 if (t < 7 * 67) (&sc[0][0])[t] = pl[j];
             }
-            if (R <= z1) fetch(R + 1, pl);
+            if (R <= z1 + 1) fetch(R + 1, pl);
             __syncthreads();
             const int rs = (R + 3) % 3;
             for (int t = threadIdx.x; t < 5 * 65; t += 256) {
@@ -588,34 +592,68 @@ __global__ __launch_bounds__(256) void k_salt_tile(const double *__restrict__ cn
                 }
             }
             __syncthreads();
-            const int P = Q - 1;  // outputs of plane P from nbar of P and P + 1
-            if (P >= z0 && P < z1) {
+            const int P = Q - 1;  // eta of plane P's own links from nbar of P and P + 1
+            if (P >= z0 && P <= z1) {
+                const int sp = (P + 2) & 1, sq = (P + 3) & 1;
+                for (int t = threadIdx.x; t < 4 * 64 + 64 + 5; t += 256) {
+                    // the tile's 4 x 64 sites first (t < 256: the thread's own
+                    // site), then the +1 halo: row y0+4 (64 sites), column x0+64 (5)
+                    int iy, ix;
+                    if (t < 256) {
+                        iy = t >> 6;
+                        ix = t & 63;
+                    } else if (t < 320) {
+                        iy = 4;
+                        ix = t - 256;
+                    } else {
+                        iy = t - 320;
+                        ix = 64;
+                    }
+                    const double n0 = sN[sp][iy][ix];
+                    const double nn[3] = {ix < 64 ? sN[sp][iy][ix + 1] : 0.0, iy < 4 ? sN[sp][iy + 1][ix] : 0.0,
+                                          sN[sq][iy][ix]};
+                    T e3[3];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        // the halo's own x-links (y-links) at the +x (+y) edge
+                        // are never read; their partner corner lies outside
+                        double e = eps_w - slope * (0.5 * (n0 + nn[d]));
+                        e = e < eps_floor ? eps_floor : e;
+                        e3[d] = (T)(1.0 / e);
+                        sE[P & 1][d][iy][ix] = e3[d];
+                    }
+                    const int x = x0 + ix, y = y0 + iy;
+                    if (t < 256 && P < z1 && x < L && y < L) {
+                        const size_t v = ((size_t)P * L + y) * L + x;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            eta[(size_t)d * Ns + v] = e3[d];
+                            s[d] += (double)e3[d];
+                            mx = fmax(mx, (double)e3[d]);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            const int O = P - 1;  // 12 / sum of the cell's 12 edges, plane O (own links of O and O + 1)
+            if (ecell && O >= z0 && O < z1) {
                 const int x = x0 + lx, y = y0 + wy;
                 if (x < L && y < L) {
-                    double n[8];
-#pragma unroll
-                    for (int o = 0; o < 8; ++o) n[o] = sN[(P + 2 + (o >> 2)) & 1][wy + ((o >> 1) & 1)][lx + (o & 1)];
-                    auto eta_edge = [&](int d, int o) -> T {
-                        const double cl = 0.5 * (n[o] + n[o | (1 << d)]);
-                        double e = eps_w - slope * cl;
-                        e = e < eps_floor ? eps_floor : e;
-                        return (T)(1.0 / e);
-                    };
-                    const size_t v = ((size_t)P * L + y) * L + x;
                     double sum = 0.0;
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-                        const T own = eta_edge(d, 0);
-                        eta[(size_t)d * Ns + v] = own;
-                        s[d] += (double)own;
-                        mx = fmax(mx, (double)own);
 #pragma unroll
                         for (int o2 = 0; o2 < 2; ++o2)
 #pragma unroll
-                            for (int o1 = 0; o1 < 2; ++o1) sum += (double)eta_edge(d, (o1 << d1) | (o2 << d2));
+                            for (int o1 = 0; o1 < 2; ++o1) {
+                                const int ox = (d1 == 0 ? o1 : 0) + (d2 == 0 ? o2 : 0);
+                                const int oy = (d1 == 1 ? o1 : 0) + (d2 == 1 ? o2 : 0);
+                                const int oz = (d1 == 2 ? o1 : 0) + (d2 == 2 ? o2 : 0);
+                                sum += (double)sE[(O + oz) & 1][d][wy + oy][lx + ox];
+                            }
                     }
-                    if (ecell) ecell[v] = (T)(12.0 / sum);
+                    ecell[((size_t)O * L + y) * L + x] = (T)(12.0 / sum);
                 }
             }
         }
