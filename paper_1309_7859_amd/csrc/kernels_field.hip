@@ -55,6 +55,8 @@ static int resident_blocks(const void *kernel) {
     return per_cu * cus;
 }
 
+// Measured once per kernel, on the first device that launches it (the
+// devices a process drives are taken to be alike).
 template <typename T, int EM, int R, int TZ>
 static int dep_resident() {
     static const int slots = resident_blocks((const void *)k_leapfrog_dep<T, EM, R, TZ>);

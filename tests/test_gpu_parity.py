@@ -444,6 +444,34 @@ def test_fused_mixed_moves_in_one_call(prec):
     assert np.max(np.abs(G.dipole() - S.dipole())) <= 1e-12 * max(1.0, np.max(np.abs(S.dipole())))
 
 
+@pytest.mark.parametrize("prec", [memd.FP64, memd.FP32_MIXED])
+def test_fused_two_ions_smallest_lattice(prec):
+    """Two opposite charges on the smallest lattice with the fused deposit
+    (L = 16), 30 steps in one call, re-binning every 4 steps, moves of up to
+    0.9 a that carry both ions across the periodic faces: one mover
+    workgroup with two live threads, tiles with empty lists."""
+    L = 16
+    q = np.array([1.0, -1.0])
+    r = np.array([[15.6, 0.3, 7.9], [0.2, 15.7, 8.4]])
+    S, G = pair(L, q, r, dt=0.01, eps_min=3.0, precision=prec)
+    apply_eps(S, G, "uniform", 3.0)
+    S.initial_solve(1e-13)
+    share_state(S, G)
+    memd.memd_set_options(G.ctx, 1, 4)
+    assert memd.memd_counters(G.ctx)[1] == 1
+    rng = np.random.default_rng(41)
+    disp = rng.uniform(-0.9, 0.9, size=(30, 2, 3))
+    G.step(disp, 30)
+    for t in range(30):
+        S.step(disp[t])
+    fp32 = prec == memd.FP32_MIXED
+    assert G.gauss_residual()[0] <= (1e-5 if fp32 else 1e-12)
+    Fo, _ = S.forces()
+    assert force_err(G.forces(), Fo) <= (1e-4 if fp32 else 1e-10)
+    assert np.max(np.abs(G.state()[2] - S.r)) <= 1e-12 * L
+    assert np.max(np.abs(S.r.reshape(-1, 3) - r)) > 1.0  # the ions did move
+
+
 def test_fused_deposit_with_stale_bins():
     """Bins never refreshed (sort_every = 0) while ions drift several rows: the
     drifted ions fall back to the atomic path and the result stays exact."""
