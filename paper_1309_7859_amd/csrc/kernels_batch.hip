@@ -21,9 +21,9 @@ namespace memd {
 // max_slots ints) from the header's compact copy once per workgroup.
 extern __shared__ int s_off[];
 
-__device__ __forceinline__ int stage_index(const int *__restrict__ hdr, bool by_tiles) {
+__device__ __forceinline__ int stage_index(const int *__restrict__ hdr, int range) {
     const int count = hdr[0], max_slots = hdr[3];
-    const int *src = hdr + kHdrInts + (by_tiles ? 0 : max_slots);
+    const int *src = hdr + kHdrInts + range * max_slots;
     for (int t = threadIdx.x; t < count; t += blockDim.x) s_off[t] = src[t];
     __syncthreads();
     return count;
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_batch_leapfrog(const RepDesc *__restric
                                                         const int *__restrict__ hdr) {
     __shared__ LfSmem<float, 1> U;
     const int total = hdr[1];
-    const int count = stage_index(hdr, true);
+    const int count = stage_index(hdr, RANGE_TILES);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int ri = find_rep(count, item);
         const RepDesc &R = tab[ri];
@@ -77,31 +77,41 @@ __global__ __launch_bounds__(256) void k_batch_leapfrog(const RepDesc *__restric
     }
 }
 
+// Deposit of every ion's move (its Philox displacement of this step) with
+// global atomics: an item is 16 ions, 16 lanes per ion (deposit_ion_part: one
+// axis and transverse corner each), so that a replica's ions spread over many
+// workgroups; lane 0 of each ion draws the displacement and writes r^{n+1}.
+// One partial of q r^{n+1} per item.
 __global__ __launch_bounds__(256) void k_batch_deposit(const RepDesc *__restrict__ tab,
                                                        const int *__restrict__ hdr) {
-    const int total = hdr[2];
-    const int count = stage_index(hdr, false);
+    const int total = hdr[4];
+    const int count = stage_index(hdr, RANGE_DEP);
+    const int lane = threadIdx.x & 15;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int ri = find_rep(count, item);
         const RepDesc &R = tab[ri];
         const int step = *R.step;
         if (step >= R.nsteps) continue;
-        const int b = item - R.ion_off;
-        const int i = b * blockDim.x + threadIdx.x;
+        const int b = item - R.dep_off;
+        const int i = b * kDepIons + (int)(threadIdx.x >> 4);
         double P[3] = {0.0, 0.0, 0.0};
         if (i < R.n) {
             const size_t Ns = (size_t)R.L * R.L * R.L;
             double u[3] = {R.r[3 * i], R.r[3 * i + 1], R.r[3 * i + 2]};
-            double du[3];
-            philox_displacement(R.seed, (uint32_t)step, (uint32_t)i, R.sigma, du);
+            double du[3] = {0.0, 0.0, 0.0};
+            if (lane == 0) philox_displacement(R.seed, (uint32_t)step, (uint32_t)i, R.sigma, du);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) du[d] = __shfl(du[d], 0, 16);
             sanitize_move(du, R.a, R.L, nullptr);
             const double qi = R.q[i];
-            deposit_ion<float>(R.L, Ns, R.a, qi, u, du, R.D[(step & 1) ^ 1]);
-            R.r[3 * i] = u[0];
-            R.r[3 * i + 1] = u[1];
-            R.r[3 * i + 2] = u[2];
+            deposit_ion_part<float>(R.L, Ns, R.a, qi, u, du, R.D[(step & 1) ^ 1], lane >> 2, lane & 3);
+            if (lane == 0) {
+                R.r[3 * i] = u[0];
+                R.r[3 * i + 1] = u[1];
+                R.r[3 * i + 2] = u[2];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) P[d] = qi * u[d];
+                for (int d = 0; d < 3; ++d) P[d] = qi * u[d];
+            }
         }
         block_sum<3>(P);
         if (threadIdx.x == 0) {
@@ -117,7 +127,7 @@ __global__ __launch_bounds__(256) void k_batch_forces(const RepDesc *__restrict_
                                                       const int *__restrict__ hdr) {
     __shared__ double Psh[3];
     const int total = hdr[2];
-    const int count = stage_index(hdr, false);
+    const int count = stage_index(hdr, RANGE_IONS);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int ri = find_rep(count, item);
         const RepDesc &R = tab[ri];
@@ -125,7 +135,7 @@ __global__ __launch_bounds__(256) void k_batch_forces(const RepDesc *__restrict_
         if (step >= R.nsteps) continue;
         const int b = item - R.ion_off;
         double s[3] = {0.0, 0.0, 0.0};
-        for (int k = threadIdx.x; k < R.iblocks; k += blockDim.x)
+        for (int k = threadIdx.x; k < R.dblocks; k += blockDim.x)
 #pragma unroll
             for (int d = 0; d < 3; ++d) s[d] += R.dip[3 * k + d];
         block_sum<3>(s);
@@ -162,10 +172,10 @@ __global__ void k_batch_advance(const RepDesc *__restrict__ tab, const int *__re
 }
 
 hipError_t launch_batch_step(hipStream_t s, const RepDesc *tab, const int *hdr, int max_slots, int lf_grid,
-                             int ion_grid) {
+                             int ion_grid, int dep_grid) {
     const size_t lds = (size_t)max_slots * sizeof(int);
     hipLaunchKernelGGL(k_batch_leapfrog, dim3(lf_grid), dim3(256), lds, s, tab, hdr);
-    hipLaunchKernelGGL(k_batch_deposit, dim3(ion_grid), dim3(256), lds, s, tab, hdr);
+    hipLaunchKernelGGL(k_batch_deposit, dim3(dep_grid), dim3(256), lds, s, tab, hdr);
     hipLaunchKernelGGL(k_batch_forces, dim3(ion_grid), dim3(256), lds, s, tab, hdr);
     hipLaunchKernelGGL(k_batch_advance, dim3(4), dim3(256), 0, s, tab, hdr);
     return hipGetLastError();

@@ -120,7 +120,7 @@ struct memd_server {
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int lf_grid = 2048, ion_grid = 1024;
+    int lf_grid = 2048, ion_grid = 1024, dep_grid = 2048;
 
     long global_steps = 0, replica_steps = 0, done_count = 0, failed_count = 0;
     char last_error[160] = {0};
@@ -162,8 +162,8 @@ void worker_main(memd_server *s) {
             st = autotune_leapfrog(rq->ctx, 5, cache, 1, &rq->rows, &rq->tz, nullptr);
         }
         if (st == MEMD_OK) {
-            const int ib = rq->n > 0 ? (rq->n + 255) / 256 : 1;
-            if (hipMalloc((void **)&rq->dip, 3 * (size_t)ib * sizeof(double)) != hipSuccess) st = MEMD_ENOMEM;
+            const int db = rq->n > 0 ? (rq->n + kDepIons - 1) / kDepIons : 1;
+            if (hipMalloc((void **)&rq->dip, 3 * (size_t)db * sizeof(double)) != hipSuccess) st = MEMD_ENOMEM;
         }
         std::lock_guard<std::mutex> lk(s->mu);
         rq->t_ready = s->now();
@@ -214,6 +214,7 @@ void fill_desc(const Request *rq, int slot, int *d_steps, RepDesc &d) {
     d.nzc = (c->L + d.tz - 1) / d.tz;
     d.tiles = d.ntx * d.nty * d.nzc;
     d.iblocks = c->n > 0 ? (c->n + 255) / 256 : 1;
+    d.dblocks = c->n > 0 ? (c->n + kDepIons - 1) / kDepIons : 1;
     d.eta_mode = c->eta_mode;
     d.nsteps = rq->nsteps;
     d.eta_uni = (float)c->eta_uni;
@@ -237,22 +238,26 @@ void fill_desc(const Request *rq, int slot, int *d_steps, RepDesc &d) {
 }
 
 hipError_t upload_table(memd_server *s) {
-    int toff = 0, ioff = 0;
+    int toff = 0, ioff = 0, doff = 0;
     for (size_t k = 0; k < s->active.size(); ++k) {
         Request *rq = s->active[k];
         RepDesc &d = s->h_tab[k];
         fill_desc(rq, rq->slot, s->d_steps, d);
         d.tile_off = toff;
         d.ion_off = ioff;
+        d.dep_off = doff;
         s->h_hdr[kHdrInts + k] = toff;
         s->h_hdr[kHdrInts + s->max_slots + k] = ioff;
+        s->h_hdr[kHdrInts + 2 * s->max_slots + k] = doff;
         toff += d.tiles;
         ioff += d.iblocks;
+        doff += d.dblocks;
     }
     s->h_hdr[0] = (int)s->active.size();
     s->h_hdr[1] = toff;
     s->h_hdr[2] = ioff;
     s->h_hdr[3] = s->max_slots;
+    s->h_hdr[4] = doff;
     hipError_t e;
     if (!s->active.empty())
         if ((e = hipMemcpyAsync(s->d_tab, s->h_tab, s->active.size() * sizeof(RepDesc), hipMemcpyHostToDevice,
@@ -271,7 +276,7 @@ hipError_t upload_table(memd_server *s) {
 hipError_t capture_graph(memd_server *s) {
     hipError_t e;
     if ((e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
-    launch_batch_step(s->stream, s->d_tab, s->d_hdr, s->max_slots, s->lf_grid, s->ion_grid);
+    launch_batch_step(s->stream, s->d_tab, s->d_hdr, s->max_slots, s->lf_grid, s->ion_grid, s->dep_grid);
     if ((e = hipStreamEndCapture(s->stream, &s->graph)) != hipSuccess) return e;
     return hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0);
 }
