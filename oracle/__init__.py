@@ -10,7 +10,8 @@ with ctypes and strings the calls together in the order the paper gives:
 charge assignment, permittivity mapping, the initial recursion plus
 relaxation, then per step the leapfrog halves, the current deposit, and the
 observables (forces with self-energy and dipole corrections, energies, Gauss
-residual, dipole moment).
+residual, dipole moment); and the ions' own dynamics driven by those forces
+(velocity Verlet, ``System.md_step``).
 """
 from __future__ import annotations
 
@@ -257,6 +258,24 @@ class System:
         assert d.size == 3 * self.n
         self.lib.orc_step(self.L, self.a, self.dt, self.c, _ptr(self.eta), self.n,
                           _ptr(self.q), _ptr(self.r), _ptr(d), _ptr(self.D), _ptr(self.B))
+
+    def md_step(self, v, m):
+        """One step of the ions' own dynamics (velocity Verlet), the fields
+        following: the ions obey Newton's equation with the MEMD force (the
+        kinetic term of the section "Extension of the algorithm" Lagrangian,
+        and eq. force without the magnetic part, as the paper's implementation
+        omits it), so the move of the step is dt times the half-kicked
+        velocity, and that move is the current of the leapfrog step:
+          v <- v + dt F(state n) / (2 m);  step(dt v);  v <- v + dt F(state n+1) / (2 m).
+        v [n, 3] is updated in place and returned; m [n] are the masses."""
+        v = np.asarray(v)
+        m = _f64(m).reshape(-1, 1)
+        F, _ = self.forces()
+        v += 0.5 * self.dt * F / m
+        self.step(self.dt * v)
+        F, _ = self.forces()
+        v += 0.5 * self.dt * F / m
+        return v
 
     def faraday(self):
         self.lib.orc_faraday(self.L, self.a, self.dt, _ptr(self.eta), _ptr(self.D), _ptr(self.B))

@@ -560,3 +560,56 @@ def test_static_energy_is_lattice_pair_energy(orc, L, eps):
                     s += wi * wj * T[(vi[2] - vj[2]) % L, (vi[1] - vj[1]) % L, (vi[0] - vj[0]) % L]
             pair += q[i] * q[j] / (eps * a) * s
     assert e["E_corrected"] == pytest.approx(pair, rel=1e-10, abs=1e-13)
+
+
+def _md_energies(orc, dt, T, c, seed=3, L=6, n=8):
+    rng = np.random.default_rng(seed)
+    q, r = neutral_ions(rng, n, L, 1.0)
+    S = orc.System(L, 1.0, dt, c, q, r)
+    S.set_eps_site(2.0 + 6.0 * rng.uniform(size=L ** 3))
+    S.initial_solve(1e-13)
+    m = np.full(n, 50.0)
+    v = rng.normal(0, 0.05, size=(n, 3))
+    out = []
+    for _ in range(int(round(T / dt))):
+        S.md_step(v, m)
+        e = S.energy()
+        K = 0.5 * np.sum(m[:, None] * v * v)
+        out.append((K, e["E_corrected"], e["W_E"] + e["W_B"]))
+    return np.array(out).T
+
+
+def test_md_total_energy_conserved(orc):
+    """f1: ions driven by the MEMD force (velocity Verlet, fields following)
+    keep K + E_corrected constant -- the paper's energy conservation with the
+    magnetic force omitted -- to round-off-like levels, with a fluctuation
+    that shrinks with dt; K + W_E + W_B alone is not conserved (the self and
+    dipole corrections are part of the dynamics)."""
+    c = orc.default_c(1.0, 0.02, 2.0)  # one speed of light for both time steps
+    spread = {}
+    for dt in (0.02, 0.01):
+        K, Ec, W = _md_energies(orc, dt, 1.0, c)
+        tot = K + Ec
+        spread[dt] = tot.max() - tot.min()
+        assert spread[dt] <= 2e-8 * abs(tot[0])
+        assert (K.max() - K.min()) > 1e-4 * K[0]  # the ions exchange energy with the field
+        assert ((K + W).max() - (K + W).min()) > 1e3 * spread[dt]
+    assert spread[0.01] <= 0.7 * spread[0.02]
+
+
+def test_md_free_flight(orc):
+    """f1: uncharged ions feel no force: the velocities stay exactly as they
+    are and the positions advance by dt v per step."""
+    L, n, dt = 5, 6, 0.05
+    rng = np.random.default_rng(44)
+    r = rng.uniform(0, L, size=(n, 3))
+    S = orc.System(L, 1.0, dt, 2.0, np.zeros(n), r)
+    S.set_eps_uniform(3.0)
+    S.initial_solve(1e-13)
+    v0 = rng.normal(0, 0.3, size=(n, 3))
+    v = v0.copy()
+    for _ in range(40):
+        S.md_step(v, np.full(n, 2.0))
+    assert np.array_equal(v, v0)
+    assert np.allclose(S.r.reshape(n, 3), r + 40 * dt * v0, rtol=0, atol=1e-12)
+    assert np.max(np.abs(S.D)) == 0.0
