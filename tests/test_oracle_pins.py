@@ -562,39 +562,50 @@ def test_static_energy_is_lattice_pair_energy(orc, L, eps):
     assert e["E_corrected"] == pytest.approx(pair, rel=1e-10, abs=1e-13)
 
 
-def _md_energies(orc, dt, T, c, seed=3, L=6, n=8):
+def _md_energies(orc, dt, T, c, eps_kind, vs, seed=3, L=6, n=8, mass=50.0):
     rng = np.random.default_rng(seed)
     q, r = neutral_ions(rng, n, L, 1.0)
     S = orc.System(L, 1.0, dt, c, q, r)
-    S.set_eps_site(2.0 + 6.0 * rng.uniform(size=L ** 3))
+    if eps_kind == "uniform":
+        S.set_eps_uniform(4.0)
+    else:
+        S.set_eps_site(2.0 + 6.0 * rng.uniform(size=L ** 3))
     S.initial_solve(1e-13)
-    m = np.full(n, 50.0)
-    v = rng.normal(0, 0.05, size=(n, 3))
+    m = np.full(n, mass)
+    v = rng.normal(0, vs, size=(n, 3))
+    r0 = S.r.copy()
     out = []
     for _ in range(int(round(T / dt))):
         S.md_step(v, m)
         e = S.energy()
         K = 0.5 * np.sum(m[:, None] * v * v)
         out.append((K, e["E_corrected"], e["W_E"] + e["W_B"]))
-    return np.array(out).T
+    crossed = bool(np.any(np.floor(S.r) != np.floor(r0)))
+    return np.array(out).T, np.max(np.abs(S.r - r0)), crossed
 
 
 def test_md_total_energy_conserved(orc):
     """f1: ions driven by the MEMD force (velocity Verlet, fields following)
     keep K + E_corrected constant -- the paper's energy conservation with the
-    magnetic force omitted -- to round-off-like levels, with a fluctuation
-    that shrinks with dt; K + W_E + W_B alone is not conserved (the self and
-    dipole corrections are part of the dynamics)."""
+    magnetic force omitted -- with a fluctuation that shrinks with dt, while
+    K + W_E + W_B alone is not conserved (the self and dipole corrections are
+    part of the dynamics).  (a) A varying permittivity, the ions staying in
+    their cells: round-off-like levels.  (b) Uniform permittivity, ions
+    crossing many cell faces."""
     c = orc.default_c(1.0, 0.02, 2.0)  # one speed of light for both time steps
-    spread = {}
-    for dt in (0.02, 0.01):
-        K, Ec, W = _md_energies(orc, dt, 1.0, c)
-        tot = K + Ec
-        spread[dt] = tot.max() - tot.min()
-        assert spread[dt] <= 2e-8 * abs(tot[0])
-        assert (K.max() - K.min()) > 1e-4 * K[0]  # the ions exchange energy with the field
-        assert ((K + W).max() - (K + W).min()) > 1e3 * spread[dt]
-    assert spread[0.01] <= 0.7 * spread[0.02]
+    for kind, vs, T, L, n, mass, tol in [("site", 0.05, 1.0, 6, 8, 50.0, 2e-8),
+                                         ("uniform", 0.3, 3.0, 8, 16, 30.0, 1e-5)]:
+        spread = {}
+        for dt in (0.02, 0.01):
+            (K, Ec, W), moved, crossed = _md_energies(orc, dt, T, c, kind, vs, seed=3 if kind == "site" else 7, L=L,
+                                             n=n, mass=mass)
+            tot = K + Ec
+            spread[dt] = tot.max() - tot.min()
+            assert spread[dt] <= tol * abs(tot[0]), (kind, dt, spread[dt])
+            assert (K.max() - K.min()) > 1e-4 * K[0]  # the ions exchange energy with the field
+            assert ((K + W).max() - (K + W).min()) > 100 * spread[dt]
+            assert crossed == (moved > 1.0) == (kind == "uniform")
+        assert spread[0.01] <= 0.7 * spread[0.02], (kind, spread)
 
 
 def test_md_free_flight(orc):
