@@ -149,6 +149,27 @@ memd_status memd_step(memd_ctx *ctx, const double *disp, int nsteps);
  * numbers for one step into out[3n] (host or device memory).
  * Errors: ESTATE, EINVAL (sigma < 0), EDEVICE. */
 memd_status memd_step_seeded(memd_ctx *ctx, uint64_t seed, double sigma, int nsteps);
+
+/* The ions' own dynamics: nsteps steps in which the ions obey Newton's
+ * equation with the force memd_forces returns (the kinetic term of the
+ * Lagrangian in section "Extension of the algorithm" and eq. force, without
+ * the magnetic v x B part, as the paper's implementation omits it), by
+ * velocity Verlet: a half kick v += (dt/2) F/m with the forces of the current
+ * state, the memd_step step whose move is dt v (the move is the current the
+ * step deposits), a second half kick with the forces of the new state.  The
+ * conserved quantity is the kinetic energy plus E_corrected of memd_energy.
+ * v[3n] (in/out, the ions' velocities, AoS, the caller's order) and mass[n]
+ * (in, > 0) may be host or device memory; host velocities are copied back
+ * before the call returns (device ones are updated in stream order).  The
+ * forces of the current state are recomputed at the start of the call, so
+ * the permittivity may have changed since the last step; with a salt
+ * permittivity, a step's first half kick uses the forces from before that
+ * step's permittivity update.  Audit and energy histories run at their
+ * cadence.  The library keeps 7n doubles of device memory for this call until
+ * the context is destroyed.
+ * Errors: ESTATE, EINVAL (null v or mass with ions, a host mass <= 0 or not
+ * finite), ENOMEM, EDEVICE. */
+memd_status memd_md_step(memd_ctx *ctx, double *v, const double *mass, int nsteps);
 memd_status memd_seeded_displacements(uint64_t seed, int step, int n, double sigma, double *out);
 
 /* Forces F_out[3n] on the ions at the current state (FP64). */

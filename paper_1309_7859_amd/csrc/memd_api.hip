@@ -274,7 +274,8 @@ void memd_destroy(memd_ctx *c) {
                     c->rec_head_nx, c->rec_con_nx, c->du_slot_nx, c->fq_nx, c->dep_atomic_nx,
                     c->dip[0], c->dip[1],
                     c->perm, c->perm_alt, c->r_alt, c->q_alt, c->F_alt,
-                    c->stage, c->rho, c->drift, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt};
+                    c->stage, c->rho, c->drift, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt,
+                    c->md_buf};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -677,6 +678,44 @@ memd_status memd_step_seeded(memd_ctx *c, uint64_t seed, double sigma, int nstep
     if (!c->ready) return MEMD_ESTATE;
     if (nsteps < 0 || !(sigma >= 0.0) || !std::isfinite(sigma)) return MEMD_EINVAL;
     return run_steps(c, nullptr, nsteps, seed, sigma);
+}
+
+memd_status memd_md_step(memd_ctx *c, double *v, const double *mass, int nsteps) {
+    CHECK_CTX(c);
+    if (!c->ready) return MEMD_ESTATE;
+    if (nsteps < 0) return MEMD_EINVAL;
+    if (nsteps == 0) return MEMD_OK;
+    if (c->n == 0) return run_steps(c, nullptr, nsteps, 0, 0.0);
+    if (!v || !mass) return MEMD_EINVAL;
+    const size_t n = (size_t)c->n, per = 3 * n;
+    const bool v_dev = is_device_ptr(v), m_dev = is_device_ptr(mass);
+    if (!m_dev)
+        for (size_t i = 0; i < n; ++i)
+            if (!(mass[i] > 0.0) || !std::isfinite(mass[i])) return MEMD_EINVAL;
+    if (!c->md_buf) {
+        CK(hipStreamSynchronize(c->stream));
+        if (hipMalloc((void **)&c->md_buf, (2 * per + n) * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            c->md_buf = nullptr;
+            return MEMD_ENOMEM;
+        }
+    }
+    double *disp = c->md_buf;
+    double *dv = v_dev ? v : c->md_buf + per;
+    const double *dm = m_dev ? mass : c->md_buf + 2 * per;
+    if (!v_dev) CK(copy_in(c, dv, v, per * sizeof(double)));
+    if (!m_dev) CK(copy_in(c, c->md_buf + 2 * per, mass, n * sizeof(double)));
+    // forces of the current state (the permittivity may have changed since
+    // the last ones were computed)
+    CK(enqueue_dipole_forces(c));
+    for (int t = 0; t < nsteps; ++t) {
+        CK(launch_md_kick(c, dm, dv, disp));
+        const memd_status st = run_steps(c, disp, 1, 0, 0.0);  // ends with the forces of the new state
+        if (st != MEMD_OK) return st;
+        CK(launch_md_kick(c, dm, dv, nullptr));
+    }
+    if (!v_dev) CK(copy_out(c, v, dv, per * sizeof(double)));
+    return MEMD_OK;
 }
 
 memd_status memd_seeded_displacements(uint64_t seed, int step, int n, double sigma, double *out) {

@@ -59,6 +59,7 @@ def load():
         "memd_set_salt_permittivity": [vp, d, d, d, i],
         "memd_initial_gauss_solve": [vp, d, i, C.POINTER(i), dp],
         "memd_step": [vp, vp, i],
+        "memd_md_step": [vp, vp, vp, i],
         "memd_forces": [vp, vp],
         "memd_energy": [vp, C.POINTER(memd_energy_t)],
         "memd_gauss_residual": [vp, dp, dp],
@@ -272,6 +273,12 @@ def memd_counters(ctx: int):
     return b.value, f.value
 
 
+def memd_md_step(ctx: int, v, mass, nsteps: int):
+    """Velocity-Verlet steps of the ions under their MEMD forces; v (3n
+    doubles, host numpy or device tensor) is updated in place."""
+    _check(load().memd_md_step(ctx, _addr(v, writable=True), _addr(mass), int(nsteps)), "memd_md_step")
+
+
 def memd_step_seeded(ctx: int, seed: int, sigma: float, nsteps: int):
     _check(load().memd_step_seeded(ctx, int(seed), float(sigma), int(nsteps)), "memd_step_seeded")
 
@@ -399,6 +406,10 @@ class Context:
         if nsteps is None:
             nsteps = 1 if getattr(disp, "ndim", 1) <= 2 else disp.shape[0]
         memd_step(self.ctx, disp, nsteps)
+
+    def md_step(self, v, mass, nsteps=1):
+        """Velocity-Verlet steps; v ([n, 3] float64, host or device) is updated in place."""
+        memd_md_step(self.ctx, v, mass, nsteps)
 
     def forces(self) -> np.ndarray:
         F = np.zeros(3 * self.n)
