@@ -13,7 +13,9 @@ Inputs (including all displacements) are resident in HBM before timing.
 Prints one JSON line: value = lattice-site updates per second (whole job),
 plus ion-steps/s, the leapfrog kernel's roofline object (HIP-event timing of
 every launch in the timed region) and the FP64 CPU oracle's throughput on a
-bounded sample of the same workload.
+bounded sample of the same workload; beside them the FP64 variant, the same
+recipe at 256^3, the same system moved by its own forces (velocity Verlet)
+and the batched serving stream.
 """
 from __future__ import annotations
 
@@ -149,6 +151,42 @@ def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None, solve_tol=1e-12):
                 energy_last=energies[-1].tolist() if len(energies) else None)
 
 
+def md_run(w, steps, warmup, tile=None):
+    """The c4 system with the ions' own dynamics instead of prescribed moves
+    (memd_md_step: velocity Verlet under the MEMD forces; mass 100 and
+    initial velocities N(0, 2) per component, so that a step moves an ion
+    about as far as the prescribed displacements do).  Per step: a half kick
+    with the move of the step, the step (records, leapfrog with the deposit,
+    finisher), the forces of the new state, the second half kick."""
+    import torch
+    from paper_1309_7859_amd import memd
+    from paper_1309_7859_amd import workloads as W
+
+    s = W.make_system(w, steps=0)
+    G = memd.Context(w.L, s["q"], s["r0"], a=w.a, dt=w.dt, c=0.0, precision=memd.FP32_MIXED,
+                     audit_every=CADENCE, energy_every=CADENCE)
+    G.set_salt(80.0, 15.0, 1.0, every=CADENCE)
+    G.solve(1e-6, check=False)
+    if tile:
+        memd.memd_set_tiling(G.ctx, tile[0], tile[1])
+    else:
+        memd.memd_autotune(G.ctx, 10, None)
+    rng = np.random.default_rng(w.seed + 1)
+    v = torch.from_numpy(rng.normal(0.0, 2.0, size=(w.n, 3))).to("cuda").contiguous()
+    m = torch.full((w.n,), 100.0, dtype=torch.float64, device="cuda")
+    if warmup:
+        G.md_step(v, m, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G.md_step(v, m, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    audits, _ = G.history()
+    gauss_max = float(np.max(audits[:, 0])) if len(audits) else None
+    G.close()
+    return dict(wall=wall, gauss_max=gauss_max)
+
+
 def cpu_baseline(w, sample_steps: int):
     """The FP64 oracle on a bounded sample of the same workload: sample_steps
     steps (leapfrog, deposit, dipole, forces) plus one permittivity recompute,
@@ -192,6 +230,8 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
     ap.add_argument("--tile", type=str, default="", help="rows,planes of the leapfrog tile")
+    ap.add_argument("--md-steps", type=int, default=100,
+                    help="steps of the c4 system under its own dynamics (0 = skip)")
     ap.add_argument("--diag256-steps", type=int, default=50,
                     help="steps of the same workload at 256^3 (8e5 ions), whose fields exceed the "
                          "256 MB Infinity Cache (0 = skip)")
@@ -292,6 +332,15 @@ def main():
                          "frac": round(b2 / lf2 / 1e9 / HBM_PEAK_GBS, 4),
                          "tile": {"x": 64, "y": 4 * r2["tile"][0], "z_chunk": r2["tile"][1]},
                          "fused": r2["fused"]}}
+    if fp32 and args.md_steps > 0:
+        rm = md_run(w, args.md_steps, 10, tile=tile)
+        out["md"] = {
+            "workload": "c4 with the ions' own dynamics (velocity Verlet under the MEMD forces, mass 100, "
+                        "initial velocities N(0, 2)), FP32 fields, salt eps + audit + energy every 50 steps",
+            "value": round(sites * args.md_steps / rm["wall"], 1), "unit": "site-updates/s",
+            "ion_steps_per_s": round(w.n * args.md_steps / rm["wall"], 1),
+            "ms_per_step": round(rm["wall"] * 1e3 / args.md_steps, 5), "steps": args.md_steps,
+            "gauss_residual_max": rm["gauss_max"]}
     if args.cpu_steps > 0:
         cb = cpu_baseline(w, args.cpu_steps)
         out["cpu_baseline"] = {
