@@ -390,29 +390,33 @@ hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext) {
 
 // ------------------------------------------------------- ion dynamics
 
-// Half kick of the ions' velocities with the forces of the current state,
-// v <- v + (dt/2) F / m: F by storage index i, v and the masses by the
-// caller's index perm[i]; with disp set, also the move of the step about to
-// run, disp = dt v (caller order), which is that step's current.
+// Half kicks of the ions' velocities with the forces of the current state,
+// v <- v + (dt/2) F / m, one or two in a row (the closing kick of a step and
+// the opening kick of the next use the same forces): F by storage index i, v
+// and the masses by the caller's index perm[i]; with disp set, also the move
+// of the step about to run, disp = dt v (caller order), which is that step's
+// current.
 __global__ __launch_bounds__(256) void k_md_kick(int n, const int *__restrict__ perm, const double *__restrict__ F,
                                                  const double *__restrict__ mass, double *__restrict__ v,
-                                                 double half_dt, double dt, double *__restrict__ disp) {
+                                                 int kicks, double half_dt, double dt, double *__restrict__ disp) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int ci = perm ? perm[i] : i;
     const double m = mass[ci];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double w = v[3 * ci + d] + half_dt * F[3 * i + d] / m;
+        const double f = F[3 * i + d];
+        double w = v[3 * ci + d] + half_dt * f / m;
+        if (kicks == 2) w = w + half_dt * f / m;
         v[3 * ci + d] = w;
         if (disp) disp[3 * ci + d] = dt * w;
     }
 }
 
-hipError_t launch_md_kick(memd_ctx *c, const double *mass, double *v, double *disp) {
+hipError_t launch_md_kick(memd_ctx *c, const double *mass, double *v, int kicks, double *disp) {
     if (c->n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_md_kick, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->perm, c->F, mass,
-                       v, 0.5 * c->dt, c->dt, disp);
+                       v, kicks, 0.5 * c->dt, c->dt, disp);
     return hipGetLastError();
 }
 

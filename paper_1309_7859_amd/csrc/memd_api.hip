@@ -708,11 +708,13 @@ memd_status memd_md_step(memd_ctx *c, double *v, const double *mass, int nsteps)
     // forces of the current state (the permittivity may have changed since
     // the last ones were computed)
     CK(enqueue_dipole_forces(c));
+    // the closing half kick of a step and the opening one of the next share
+    // one launch (the same forces, applied one after the other)
+    CK(launch_md_kick(c, dm, dv, 1, disp));
     for (int t = 0; t < nsteps; ++t) {
-        CK(launch_md_kick(c, dm, dv, disp));
         const memd_status st = run_steps(c, disp, 1, 0, 0.0);  // ends with the forces of the new state
         if (st != MEMD_OK) return st;
-        CK(launch_md_kick(c, dm, dv, nullptr));
+        CK(launch_md_kick(c, dm, dv, t + 1 < nsteps ? 2 : 1, t + 1 < nsteps ? disp : nullptr));
     }
     if (!v_dev) CK(copy_out(c, v, dv, per * sizeof(double)));
     return MEMD_OK;

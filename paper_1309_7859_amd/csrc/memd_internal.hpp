@@ -205,9 +205,9 @@ hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint
 // and the irregular ions of the current records deposited into Dnext with
 // global atomics (from r^n, still in c->r).
 hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext);
-// Half kick v += (dt/2) F/m (v, mass in the caller's order); with disp, the
-// move dt v of the step about to run.
-hipError_t launch_md_kick(memd_ctx *c, const double *mass, double *v, double *disp);
+// kicks (1 or 2) half kicks v += (dt/2) F/m (v, mass in the caller's
+// order); with disp, the move dt v of the step about to run.
+hipError_t launch_md_kick(memd_ctx *c, const double *mass, double *v, int kicks, double *disp);
 hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
                                int *nblk);
 hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk);
