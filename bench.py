@@ -157,7 +157,9 @@ def md_run(w, steps, warmup, tile=None):
     initial velocities N(0, 2) per component, so that a step moves an ion
     about as far as the prescribed displacements do).  Per step: a half kick
     with the move of the step, the step (records, leapfrog with the deposit,
-    finisher), the forces of the new state, the second half kick."""
+    finisher), the forces of the new state, the second half kick.  The ions
+    move ballistically here, so they are re-binned every 16 steps rather than
+    64 (measured: 0.092 ms per step at 64, 0.083 at 32, 0.080 at 16 and 8)."""
     import torch
     from paper_1309_7859_amd import memd
     from paper_1309_7859_amd import workloads as W
@@ -171,6 +173,7 @@ def md_run(w, steps, warmup, tile=None):
         memd.memd_set_tiling(G.ctx, tile[0], tile[1])
     else:
         memd.memd_autotune(G.ctx, 10, None)
+    memd.memd_set_options(G.ctx, 1, 16)
     rng = np.random.default_rng(w.seed + 1)
     v = torch.from_numpy(rng.normal(0.0, 2.0, size=(w.n, 3))).to("cuda").contiguous()
     m = torch.full((w.n,), 100.0, dtype=torch.float64, device="cuda")
@@ -336,7 +339,8 @@ def main():
         rm = md_run(w, args.md_steps, 10, tile=tile)
         out["md"] = {
             "workload": "c4 with the ions' own dynamics (velocity Verlet under the MEMD forces, mass 100, "
-                        "initial velocities N(0, 2)), FP32 fields, salt eps + audit + energy every 50 steps",
+                        "initial velocities N(0, 2)), FP32 fields, salt eps + audit + energy every 50 steps, "
+                        "re-binning every 16 steps",
             "value": round(sites * args.md_steps / rm["wall"], 1), "unit": "site-updates/s",
             "ion_steps_per_s": round(w.n * args.md_steps / rm["wall"], 1),
             "ms_per_step": round(rm["wall"] * 1e3 / args.md_steps, 5), "steps": args.md_steps,
