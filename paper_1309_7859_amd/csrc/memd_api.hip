@@ -268,14 +268,8 @@ void memd_destroy(memd_ctx *c) {
     hipSetDevice(c->device);
     if (c->stream) hipStreamSynchronize(c->stream);
     prof_clear(c);
-    void *bufs[] = {c->D[0], c->D[1], c->B[0], c->B[1], c->eta_prof, c->eta_link, c->q, c->r, c->F,
-                    c->order, c->slot, c->bins, c->bad_moves, c->dep_atomic, c->rec_head, c->rec_con, c->list,
-                    c->list_count, c->cbin, c->list_fail, c->du_slot, c->fq, c->ecell, c->Ft, c->fdone,
-                    c->rec_head_nx, c->rec_con_nx, c->du_slot_nx, c->fq_nx, c->dep_atomic_nx,
-                    c->dip[0], c->dip[1],
-                    c->perm, c->perm_alt, c->r_alt, c->q_alt, c->F_alt,
-                    c->stage, c->rho, c->drift, c->partials, c->scal, c->hist_audit, c->hist_energy, c->salt_cnt,
-                    c->md_buf};
+    // the arena holds every fixed buffer; the rest were made on demand
+    void *bufs[] = {c->arena, c->eta_link, c->stage, c->salt_cnt, c->md_buf};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -350,62 +344,84 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     const size_t fb = 3 * Ns * c->tsize;
     const size_t nn = (size_t)(n > 0 ? n : 1);
     const size_t dip_parts = nn / 64 + 32;  // dipole partials: 4 per mover workgroup of 256 ions
-    if (hipMalloc(&c->D[0], fb) != hipSuccess || hipMalloc(&c->D[1], fb) != hipSuccess ||
-        hipMalloc(&c->B[0], fb) != hipSuccess || hipMalloc(&c->B[1], fb) != hipSuccess ||
-        hipMalloc(&c->eta_prof, 3 * (size_t)c->L * c->tsize) != hipSuccess ||
-        hipMalloc((void **)&c->q, nn * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->r, 3 * nn * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->F, 3 * nn * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->order, nn * sizeof(int)) != hipSuccess ||
-        hipMalloc((void **)&c->slot, nn * sizeof(int)) != hipSuccess ||
-        hipMalloc((void **)&c->perm, nn * sizeof(int)) != hipSuccess ||
-        hipMalloc((void **)&c->perm_alt, nn * sizeof(int)) != hipSuccess ||
-        hipMalloc((void **)&c->r_alt, 3 * nn * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->q_alt, nn * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->F_alt, 3 * nn * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->bins, 3 * (size_t)p->L * p->L * sizeof(int)) != hipSuccess ||
-        hipMalloc((void **)&c->dep_atomic, nn * sizeof(int)) != hipSuccess ||
-        hipMalloc((void **)&c->bad_moves, sizeof(unsigned int)) != hipSuccess ||
-        hipMalloc((void **)&c->rho, Ns * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->drift, nn * sizeof(int)) != hipSuccess ||
-        hipMalloc((void **)&c->partials, partial_doubles(n) * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->dip[0], 3 * dip_parts * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->dip[1], 3 * dip_parts * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->scal, S_COUNT * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->hist_audit, 2 * (size_t)kHistCap * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->hist_energy, 5 * (size_t)kHistCap * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(MEMD_ENOMEM);
-    }
-    // Fused deposit: records by slot, and tile lists sized for the smallest
-    // fused tile shape (64 x 4 x 2): twelve entries per ion plus 64 per tile.
+    // Every fixed buffer of the context is carved from one allocation (each
+    // piece 256-byte aligned): one hipMalloc here and one hipFree at destroy,
+    // which matters to a server creating and destroying contexts while other
+    // work runs.  The buffers made later on demand (per-link eta, staging,
+    // salt counts, the ion-dynamics buffers) are allocations of their own.
+    std::vector<std::pair<void **, size_t>> pieces;
+    auto piece = [&](auto **ptr, size_t bytes) { pieces.push_back({(void **)ptr, bytes}); };
+    piece(&c->D[0], fb);
+    piece(&c->D[1], fb);
+    piece(&c->B[0], fb);
+    piece(&c->B[1], fb);
+    piece(&c->eta_prof, 3 * (size_t)c->L * c->tsize);
+    piece(&c->q, nn * sizeof(double));
+    piece(&c->r, 3 * nn * sizeof(double));
+    piece(&c->F, 3 * nn * sizeof(double));
+    piece(&c->order, nn * sizeof(int));
+    piece(&c->slot, nn * sizeof(int));
+    piece(&c->perm, nn * sizeof(int));
+    piece(&c->perm_alt, nn * sizeof(int));
+    piece(&c->r_alt, 3 * nn * sizeof(double));
+    piece(&c->q_alt, nn * sizeof(double));
+    piece(&c->F_alt, 3 * nn * sizeof(double));
+    piece(&c->bins, 3 * (size_t)p->L * p->L * sizeof(int));
+    piece(&c->dep_atomic, nn * sizeof(int));
+    piece(&c->bad_moves, sizeof(unsigned int));
+    piece(&c->rho, Ns * sizeof(double));
+    piece(&c->drift, nn * sizeof(int));
+    piece(&c->partials, partial_doubles(n) * sizeof(double));
+    piece(&c->dip[0], 3 * dip_parts * sizeof(double));
+    piece(&c->dip[1], 3 * dip_parts * sizeof(double));
+    piece(&c->scal, S_COUNT * sizeof(double));
+    piece(&c->hist_audit, 2 * (size_t)kHistCap * sizeof(double));
+    piece(&c->hist_energy, 5 * (size_t)kHistCap * sizeof(double));
+    // Fused deposit: records by slot (two sets), and tile lists sized for the
+    // smallest fused tile shape (64 x 4 x 2): twelve entries per ion plus 64
+    // per tile.
     c->lists_key = -1;
     c->list_zero_key = -1;
-    if (n > 0 && p->L >= 16 && p->L <= 1024) {
+    const size_t rec = 2 * (c->fp32 ? sizeof(DepCell<float>) : sizeof(DepCell<double>));
+    const size_t fqb = c->fp32 ? sizeof(IonFQ<float>) : sizeof(IonFQ<double>);
+    const bool fused_bufs = n > 0 && p->L >= 16 && p->L <= 1024;
+    if (fused_bufs) {
         const size_t L = (size_t)p->L;
         const size_t tiles = ((L + 63) / 64) * ((L + 3) / 4) * ((L + 1) / 2);
         c->list_tiles_max = (int)tiles;
         c->list_entries = 12 * nn + 64 * tiles;
-        const size_t rec = 2 * (c->fp32 ? sizeof(DepCell<float>) : sizeof(DepCell<double>));
-        if (hipMalloc((void **)&c->rec_head, nn * sizeof(int4)) != hipSuccess ||
-            hipMalloc(&c->rec_con, nn * rec) != hipSuccess ||
-            hipMalloc((void **)&c->list, c->list_entries * sizeof(int)) != hipSuccess ||
-            hipMalloc((void **)&c->list_count, tiles * kCountStride * sizeof(int)) != hipSuccess ||
-            hipMalloc((void **)&c->cbin, nn * sizeof(int)) != hipSuccess ||
-            hipMalloc((void **)&c->list_fail, nn * sizeof(int)) != hipSuccess ||
-            hipMalloc((void **)&c->du_slot, 3 * nn * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->fq, nn * (c->fp32 ? sizeof(IonFQ<float>) : sizeof(IonFQ<double>))) != hipSuccess ||
-            hipMalloc(&c->ecell, Ns * c->tsize) != hipSuccess ||
-            hipMalloc((void **)&c->Ft, 3 * nn * sizeof(double)) != hipSuccess ||
-            hipMalloc((void **)&c->fdone, nn * sizeof(unsigned int)) != hipSuccess ||
-            hipMalloc((void **)&c->rec_head_nx, nn * sizeof(int4)) != hipSuccess ||
-            hipMalloc(&c->rec_con_nx, nn * rec) != hipSuccess ||
-            hipMalloc((void **)&c->du_slot_nx, 3 * nn * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->fq_nx, nn * (c->fp32 ? sizeof(IonFQ<float>) : sizeof(IonFQ<double>))) != hipSuccess ||
-            hipMalloc((void **)&c->dep_atomic_nx, nn * sizeof(int)) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(MEMD_ENOMEM);
+        piece(&c->rec_head, nn * sizeof(int4));
+        piece(&c->rec_con, nn * rec);
+        piece(&c->list, c->list_entries * sizeof(int));
+        piece(&c->list_count, tiles * kCountStride * sizeof(int));
+        piece(&c->cbin, nn * sizeof(int));
+        piece(&c->list_fail, nn * sizeof(int));
+        piece(&c->du_slot, 3 * nn * sizeof(double));
+        piece(&c->fq, nn * fqb);
+        piece(&c->ecell, Ns * c->tsize);
+        piece(&c->Ft, 3 * nn * sizeof(double));
+        piece(&c->fdone, nn * sizeof(unsigned int));
+        piece(&c->rec_head_nx, nn * sizeof(int4));
+        piece(&c->rec_con_nx, nn * rec);
+        piece(&c->du_slot_nx, 3 * nn * sizeof(double));
+        piece(&c->fq_nx, nn * fqb);
+        piece(&c->dep_atomic_nx, nn * sizeof(int));
+    }
+    size_t arena_bytes = 0;
+    for (const auto &pc : pieces) arena_bytes += (pc.second + 255) / 256 * 256;
+    if (hipMalloc(&c->arena, arena_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        c->arena = nullptr;
+        return fail(MEMD_ENOMEM);
+    }
+    {
+        char *at = (char *)c->arena;
+        for (const auto &pc : pieces) {
+            *pc.first = at;
+            at += (pc.second + 255) / 256 * 256;
         }
+    }
+    if (fused_bufs) {
         c->rec_con1 = (char *)c->rec_con + nn * (rec / 2);
         c->rec_con1_nx = (char *)c->rec_con_nx + nn * (rec / 2);
     }

@@ -53,6 +53,7 @@ struct ProfileEvents {
 }  // namespace memd
 
 struct memd_ctx {
+    void *arena;  // the one device allocation every fixed buffer below is carved from
     memd_params p;
     int n;
     int L;
