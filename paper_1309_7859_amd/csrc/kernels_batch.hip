@@ -80,7 +80,8 @@ __global__ __launch_bounds__(256) void k_batch_leapfrog(const RepDesc *__restric
 // Deposit of every ion's move (its Philox displacement of this step) with
 // global atomics: an item is 16 ions, 16 lanes per ion (deposit_ion_part: one
 // axis and transverse corner each), so that a replica's ions spread over many
-// workgroups; lane 0 of each ion draws the displacement and writes r^{n+1}.
+// workgroups; lanes 0-2 of each ion draw the displacement's components, lane
+// 0 writes r^{n+1}.
 // One partial of q r^{n+1} per item.
 __global__ __launch_bounds__(256) void k_batch_deposit(const RepDesc *__restrict__ tab,
                                                        const int *__restrict__ hdr) {
@@ -98,10 +99,13 @@ __global__ __launch_bounds__(256) void k_batch_deposit(const RepDesc *__restrict
         if (i < R.n) {
             const size_t Ns = (size_t)R.L * R.L * R.L;
             double u[3] = {R.r[3 * i], R.r[3 * i + 1], R.r[3 * i + 2]};
-            double du[3] = {0.0, 0.0, 0.0};
-            if (lane == 0) philox_displacement(R.seed, (uint32_t)step, (uint32_t)i, R.sigma, du);
+            // lanes 0-2 draw one component each
+            const double dc = lane < 3 ? philox_displacement_component(R.seed, (uint32_t)step, (uint32_t)i, R.sigma,
+                                                                       lane)
+                                       : 0.0;
+            double du[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) du[d] = __shfl(du[d], 0, 16);
+            for (int d = 0; d < 3; ++d) du[d] = __shfl(dc, d, 16);
             sanitize_move(du, R.a, R.L, nullptr);
             const double qi = R.q[i];
             deposit_ion_part<float>(R.L, Ns, R.a, qi, u, du, R.D[(step & 1) ^ 1], lane >> 2, lane & 3);
