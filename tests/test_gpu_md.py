@@ -103,3 +103,36 @@ def test_md_device_velocities_and_energy_conservation():
     finally:
         G.close()
         H.close()
+
+
+def test_md_error_codes():
+    """Before a state exists, with missing buffers, non-positive or non-finite
+    host masses, or a negative step count, memd_md_step refuses and leaves the
+    context usable."""
+    L = 8
+    q = np.array([1.0, -1.0])
+    r = np.array([[1.0, 2.0, 3.0], [4.0, 5.0, 6.0]])
+    v = np.zeros((2, 3))
+    G = memd.Context(L, q, r)
+    try:
+        with pytest.raises(memd.MemdError) as e:
+            G.md_step(v, np.ones(2), 1)
+        assert e.value.status == memd.ESTATE
+        G.set_permittivity(memd.EPS_UNIFORM, [2.0])
+        G.solve(1e-12)
+        for mass in (np.array([1.0, 0.0]), np.array([1.0, -2.0]), np.array([1.0, np.nan])):
+            with pytest.raises(memd.MemdError) as e:
+                G.md_step(v, mass, 1)
+            assert e.value.status == memd.EINVAL
+        with pytest.raises(memd.MemdError) as e:
+            memd.memd_md_step(G.ctx, None, np.ones(2), 1)
+        assert e.value.status == memd.EINVAL
+        with pytest.raises(memd.MemdError) as e:
+            G.md_step(v, np.ones(2), -1)
+        assert e.value.status == memd.EINVAL
+        G.md_step(v, np.ones(2), 0)  # nothing to do
+        v[0, 0] = 0.1
+        G.md_step(v, np.ones(2), 3)  # still usable
+        assert G.gauss_residual()[0] <= 1e-12
+    finally:
+        G.close()
