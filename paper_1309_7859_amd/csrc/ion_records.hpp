@@ -139,7 +139,8 @@ __device__ __forceinline__ void step_displacement(int i, int L, double a, const 
 // record set (the tiles read the first).  They run as workgroups of their
 // own beside the tiles (nblocks of them, kMoverIons ions each; ahead: the
 // first workgroups of the launch, else the last).
-constexpr int kMoverIons = 256;  // ions per mover workgroup, one per thread
+constexpr int kMoverPerThread = 1;  // ions per mover thread
+constexpr int kMoverIons = 256 * kMoverPerThread;  // ions per mover workgroup
 
 template <typename T>
 struct MoverArgs {
@@ -163,41 +164,61 @@ struct MoverArgs {
     DepOut<T> out;     // the next step's records (cbin, list_fail: the lists' state)
 };
 
-// Slots [s0, s0 + count) by the workgroup's 256 threads; partials to
-// dip_out[part0 .. part0 + 3] (zero for a wavefront without ions).
+// Slots [s0, s0 + count) by the workgroup's 256 threads, kMoverPerThread
+// per thread (all of a thread's loads issued before any of its arithmetic);
+// partials to dip_out[part0 .. part0 + 3] (zero for a wavefront without
+// ions).
 template <typename T>
 __device__ __forceinline__ void move_ions(const MoverArgs<T> &M, int s0, int count, int part0) {
+    constexpr int K = kMoverPerThread;
     double P[3] = {0.0, 0.0, 0.0};
     const int s1 = min(s0 + count, M.n);
-    for (int s = s0 + (int)threadIdx.x; s < s1; s += 256) {
-        const int i = M.order ? M.order[s] : s;
-        const int ci = M.perm ? M.perm[i] : i;
-        double u[3] = {M.r[3 * i], M.r[3 * i + 1], M.r[3 * i + 2]};
-        const double qi = M.q[i];
-        const double du[3] = {M.du[3 * s], M.du[3 * s + 1], M.du[3 * s + 2]};
-        double dn[3] = {0.0, 0.0, 0.0};
-        int lfail = 0, lcell = 0;
-        if (M.pack) {
-            lfail = M.out.list_fail[s];
-            lcell = M.out.cbin[s];
+    int sk[K], ik[K], ck[K], lfail[K], lcell[K];
+    bool live[K];
+    double u[K][3], du[K][3], dn[K][3], qk[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        sk[k] = s0 + (int)threadIdx.x + 256 * k;
+        live[k] = sk[k] < s1;
+        const int s = live[k] ? sk[k] : s0;
+        ik[k] = M.order ? M.order[s] : s;
+        ck[k] = M.perm ? M.perm[ik[k]] : ik[k];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            u[k][d] = M.r[3 * ik[k] + d];
+            du[k][d] = M.du[3 * s + d];
+            dn[k][d] = 0.0;
+        }
+        qk[k] = M.q[ik[k]];
+        lfail[k] = M.pack ? M.out.list_fail[s] : 0;
+        lcell[k] = M.pack ? M.out.cbin[s] : 0;
+    }
+    if (M.pack) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
             if (M.disp_next) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) dn[d] = M.disp_next[3 * ci + d];
+                for (int d = 0; d < 3; ++d) dn[k][d] = M.disp_next[3 * ck[k] + d];
             } else {
-                philox_displacement(M.seed, M.t_next, (uint32_t)ci, M.sigma, dn);
+                philox_displacement(M.seed, M.t_next, (uint32_t)ck[k], M.sigma, dn[k]);
             }
         }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (!live[k]) continue;
+        const int s = sk[k], i = ik[k];
         // the position deposit_ion leaves, bit for bit
 #pragma unroll
-        for (int d = 0; d < 3; ++d) u[d] = u[d] + du[d];
-        M.r_out[3 * i] = u[0];
-        M.r_out[3 * i + 1] = u[1];
-        M.r_out[3 * i + 2] = u[2];
+        for (int d = 0; d < 3; ++d) u[k][d] = u[k][d] + du[k][d];
+        M.r_out[3 * i] = u[k][0];
+        M.r_out[3 * i + 1] = u[k][1];
+        M.r_out[3 * i + 2] = u[k][2];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) P[d] += qi * u[d];
+        for (int d = 0; d < 3; ++d) P[d] += qk[k] * u[k][d];
         if (M.pack) {
-            sanitize_move(dn, M.a, M.L, M.bad);
-            M.atomic_next[s] = write_record_at<T>(M.L, M.a, qi, u, dn, s, M.out, lfail, lcell) ? 1 : 0;
+            sanitize_move(dn[k], M.a, M.L, M.bad);
+            M.atomic_next[s] = write_record_at<T>(M.L, M.a, qk[k], u[k], dn[k], s, M.out, lfail[k], lcell[k]) ? 1 : 0;
         }
     }
 #pragma unroll
