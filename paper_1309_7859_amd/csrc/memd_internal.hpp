@@ -136,7 +136,7 @@ struct memd_ctx {
     double *rho;       // FP64 [Ns]: the charge assignment of the last audit
     int *drift;        // [n] by storage index: ion left to the atomic pass of the spread
     double *partials;  // FP64 reduction scratch (partial_doubles)
-    double *dip[2];    // FP64 per-block q r sums of the ion step, alternating by step
+    double *dip[2];    // FP64 per-wavefront q r sums of the ion movers, alternating by step
     double *scal;      // FP64 [S_COUNT]
     double *hist_audit;   // FP64 [2*hist_cap]
     double *hist_energy;  // FP64 [5*hist_cap]
