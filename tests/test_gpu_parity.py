@@ -414,14 +414,15 @@ def test_fused_deposit_matches_atomic_path_and_oracle(prec, tile, L):
     assert np.max(np.abs(G.state()[2] - S.r)) <= 1e-12
 
 
-@pytest.mark.parametrize("prec", [memd.FP64, memd.FP32_MIXED])
-def test_fused_mixed_moves_in_one_call(prec):
+@pytest.mark.parametrize("prec,L", [(memd.FP64, 32), (memd.FP32_MIXED, 32), (memd.FP64, 17),
+                                    (memd.FP32_MIXED, 65)])
+def test_fused_mixed_moves_in_one_call(prec, L):
     """The same mixed moves (jumps of up to 2.5 a among small steps) taken in
     one call, re-binning every 5 steps: the records of most steps are then
     written by the previous launch's movers into the other record set, and
     the jumping ions they mark reach D^{n+1} through the finisher's atomic
-    deposit."""
-    L, n, steps = 32, 600, 13
+    deposit.  L = 17 and 65 leave ragged tiles in every direction."""
+    n, steps = 600, 13
     rng = np.random.default_rng(24)
     r = rng.uniform(0, L, size=(n, 3))
     q = np.tile([1.0, -1.0, 2.0, -2.0], n // 4)
