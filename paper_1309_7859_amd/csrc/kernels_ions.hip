@@ -392,16 +392,17 @@ hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext) {
 
 // Half kicks of the ions' velocities with the forces of the current state,
 // v <- v + (dt/2) F / m, one or two in a row (the closing kick of a step and
-// the opening kick of the next use the same forces): F by storage index i, v
-// and the masses by the caller's index perm[i]; with disp set, also the move
-// of the step about to run, disp = dt v (caller order), which is that step's
-// current.
-__global__ __launch_bounds__(256) void k_md_kick(int n, const int *__restrict__ perm, const double *__restrict__ F,
+// the opening kick of the next use the same forces): one thread per ion in
+// the caller's order, so that v, the masses and the move are read and
+// written coalesced and only F is gathered (storage index iperm[ci]); with
+// disp set, also the move of the step about to run, disp = dt v, which is
+// that step's current.
+__global__ __launch_bounds__(256) void k_md_kick(int n, const int *__restrict__ iperm, const double *__restrict__ F,
                                                  const double *__restrict__ mass, double *__restrict__ v,
                                                  int kicks, double half_dt, double dt, double *__restrict__ disp) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int ci = perm ? perm[i] : i;
+    const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ci >= n) return;
+    const int i = iperm[ci];
     const double m = mass[ci];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -413,10 +414,22 @@ __global__ __launch_bounds__(256) void k_md_kick(int n, const int *__restrict__ 
     }
 }
 
-hipError_t launch_md_kick(memd_ctx *c, const double *mass, double *v, int kicks, double *disp) {
+hipError_t launch_md_kick(memd_ctx *c, const int *iperm, const double *mass, double *v, int kicks, double *disp) {
     if (c->n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_md_kick, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->perm, c->F, mass,
-                       v, kicks, 0.5 * c->dt, c->dt, disp);
+    hipLaunchKernelGGL(k_md_kick, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, iperm, c->F, mass, v,
+                       kicks, 0.5 * c->dt, c->dt, disp);
+    return hipGetLastError();
+}
+
+// iperm[perm[i]] = i: the storage index of each caller index.
+__global__ __launch_bounds__(256) void k_invert_perm(int n, const int *__restrict__ perm, int *__restrict__ iperm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) iperm[perm[i]] = i;
+}
+
+hipError_t launch_invert_perm(memd_ctx *c, int *iperm) {
+    if (c->n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_invert_perm, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->perm, iperm);
     return hipGetLastError();
 }
 
@@ -904,6 +917,7 @@ hipError_t launch_bin_ions(memd_ctx *c, bool reorder) {
         std::swap(c->q, c->q_alt);
         std::swap(c->F, c->F_alt);
         std::swap(c->perm, c->perm_alt);
+        ++c->perm_version;
         c->sorted = true;
     } else {
         hipLaunchKernelGGL(k_bin_scatter, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,

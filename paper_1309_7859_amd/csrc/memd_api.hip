@@ -710,15 +710,26 @@ memd_status memd_md_step(memd_ctx *c, double *v, const double *mass, int nsteps)
             if (!(mass[i] > 0.0) || !std::isfinite(mass[i])) return MEMD_EINVAL;
     if (!c->md_buf) {
         CK(hipStreamSynchronize(c->stream));
-        if (hipMalloc((void **)&c->md_buf, (2 * per + n) * sizeof(double)) != hipSuccess) {
+        if (hipMalloc((void **)&c->md_buf, (2 * per + n) * sizeof(double) + n * sizeof(int)) != hipSuccess) {
             (void)hipGetLastError();
             c->md_buf = nullptr;
             return MEMD_ENOMEM;
         }
+        c->iperm_version = c->perm_version - 1;  // not made yet
     }
     double *disp = c->md_buf;
     double *dv = v_dev ? v : c->md_buf + per;
     const double *dm = m_dev ? mass : c->md_buf + 2 * per;
+    int *iperm = (int *)(c->md_buf + 2 * per + n);
+    // the inverse of perm, remade after a re-binning or set_state changed it
+    auto kick = [&](int kicks, double *d) -> hipError_t {
+        if (c->iperm_version != c->perm_version) {
+            hipError_t e = launch_invert_perm(c, iperm);
+            if (e != hipSuccess) return e;
+            c->iperm_version = c->perm_version;
+        }
+        return launch_md_kick(c, iperm, dm, dv, kicks, d);
+    };
     if (!v_dev) CK(copy_in(c, dv, v, per * sizeof(double)));
     if (!m_dev) CK(copy_in(c, c->md_buf + 2 * per, mass, n * sizeof(double)));
     // forces of the current state (the permittivity may have changed since
@@ -726,11 +737,11 @@ memd_status memd_md_step(memd_ctx *c, double *v, const double *mass, int nsteps)
     CK(enqueue_dipole_forces(c));
     // the closing half kick of a step and the opening one of the next share
     // one launch (the same forces, applied one after the other)
-    CK(launch_md_kick(c, dm, dv, 1, disp));
+    CK(kick(1, disp));
     for (int t = 0; t < nsteps; ++t) {
         const memd_status st = run_steps(c, disp, 1, 0, 0.0);  // ends with the forces of the new state
         if (st != MEMD_OK) return st;
-        CK(launch_md_kick(c, dm, dv, t + 1 < nsteps ? 2 : 1, t + 1 < nsteps ? disp : nullptr));
+        CK(kick(t + 1 < nsteps ? 2 : 1, t + 1 < nsteps ? disp : nullptr));
     }
     if (!v_dev) CK(copy_out(c, v, dv, per * sizeof(double)));
     return MEMD_OK;
@@ -863,6 +874,7 @@ memd_status memd_set_state(memd_ctx *c, const double *D, const double *B, const 
             CK(launch_unpermute(c, 1, c->q, c->q_alt));
             std::swap(c->q, c->q_alt);
             CK(launch_iota(c->stream, c->perm, c->n));
+            ++c->perm_version;
             c->sorted = false;
         }
         CK(copy_in(c, c->r, r, 3 * (size_t)c->n * sizeof(double)));

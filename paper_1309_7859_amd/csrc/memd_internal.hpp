@@ -130,7 +130,9 @@ struct memd_ctx {
     int sort_every;
     double *stage;       // FP64 staging buffer for host inputs / FP32 casts
     size_t stage_bytes;
-    double *md_buf;      // ion dynamics: the step's move [3n], staged velocities [3n] and masses [n]
+    double *md_buf;      // ion dynamics: the step's move [3n], staged velocities [3n] and masses [n], iperm [n] ints
+    long perm_version;   // advanced whenever perm changes
+    long iperm_version;  // the perm_version the ion dynamics' inverse of perm was made for
 
     // reductions and audit
     double *rho;       // FP64 [Ns]: the charge assignment of the last audit
@@ -207,8 +209,11 @@ hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint
 // global atomics (from r^n, still in c->r).
 hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext);
 // kicks (1 or 2) half kicks v += (dt/2) F/m (v, mass in the caller's
-// order); with disp, the move dt v of the step about to run.
-hipError_t launch_md_kick(memd_ctx *c, const double *mass, double *v, int kicks, double *disp);
+// order; iperm: the storage index of each caller index); with disp, the
+// move dt v of the step about to run.
+hipError_t launch_md_kick(memd_ctx *c, const int *iperm, const double *mass, double *v, int kicks, double *disp);
+// iperm[perm[i]] = i
+hipError_t launch_invert_perm(memd_ctx *c, int *iperm);
 hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
                                int *nblk);
 hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk);
