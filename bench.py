@@ -6,16 +6,21 @@ at seeded uniform positions, salt-dependent permittivity per link
 density) recomputed every 50 steps, seeded Gaussian prescribed displacements
 (sigma = 0.02 a), FP32 fields with FP64 positions, dipole, Gauss audit and
 energies.  One step = leapfrog (Faraday + Ampere) + ion move and current
-deposit + dipole + corrected forces; the Gauss audit, the energy evaluation
-and the permittivity recompute run every 50 steps inside the timed region.
-Inputs (including all displacements) are resident in HBM before timing.
+deposit + dipole + corrected forces; every 50 steps the permittivity
+recompute, the re-binning of the ions, the Gauss audit and the energy
+evaluation.  The timed window starts on the last step of a 50-step period
+(extra untimed steps after the warm-up align it), so it holds at least one
+of each of these whatever its length.  Inputs (including all displacements)
+are resident in HBM before timing.
 
 Prints one JSON line: value = lattice-site updates per second (whole job),
 plus ion-steps/s, the leapfrog kernel's roofline object (HIP-event timing of
-every launch in the timed region) and the FP64 CPU oracle's throughput on a
-bounded sample of the same workload; beside them the FP64 variant, the same
-recipe at 256^3, the same system moved by its own forces (velocity Verlet)
-and the batched serving stream.
+one launch in ten in the timed region) on the algorithmic bytes per site and
+per ion, an on-box stream-copy ceiling, and the FP64 CPU oracle's throughput
+on a bounded sample of the same workload; beside them the FP64 variant over
+the same trajectory (and the FP32 path's error on each output against it),
+the same recipe at 256^3, the same system moved by its own forces (velocity
+Verlet) and the batched serving stream.
 """
 from __future__ import annotations
 
@@ -38,15 +43,26 @@ HBM_PEAK_GBS = 8000.0
 CADENCE = 50
 PROFILE_EVERY = 10
 
-# Algorithmic bytes (each value read once / written once).
-#   leapfrog, per site: read D[3], B[3], eta[3] (per-link permittivity), write D[3], B[3];
-#     with the fused deposit also, per ion, the tiles' share (its record, the
-#     inputs and outputs of the force its tile computes) and the movers' share
-#     (mover_bytes_per_ion)
-#   ion side without the fused deposit, per ion: pack (60 read + 64 write),
-#     update (60 read + 24 write), forces (r, q, 12 D + 12 eta, F write);
-#     with it, the finisher: read the tile force (24), its stamp (4), q (8),
-#     the atomic-path flag (4), write F (24)
+# Algorithmic bytes of a step (each value read once and written once):
+#   per site: D[3], B[3] read and written, the per-link eta[3] read
+#     (15 values: 60 B FP32, 120 B FP64)
+#   per ion: r and the displacement read, r written, q read, the 12-link
+#     current read-modify-write, the 12-link gather of D (and eta), the force
+#     written: about 250 B FP32, 490 B FP64
+SITE_BYTES = {"fp32": 60, "fp64": 120}
+ION_BYTES = {"fp32": 250, "fp64": 490}
+
+
+def algorithmic_bytes(precision: str, sites: int, ions: int) -> int:
+    return SITE_BYTES[precision] * sites + ION_BYTES[precision] * ions
+
+
+# Bytes this implementation moves per launch of the fused leapfrog, counted
+# the same way (each value once): the algorithmic field bytes, and per ion
+# the tiles' share (its record: a 16-byte head and the 12 first-cell values
+# in the field type; the fractional position, charge and 12/sum(eta) for the
+# force the tile computes, which it writes with a 4-byte stamp) and the
+# movers' share (mover_bytes_per_ion).
 
 
 def leapfrog_bytes_per_site(fp32: bool, per_link_eps: bool) -> int:
@@ -64,14 +80,10 @@ def mover_bytes_per_ion(fp32: bool) -> int:
     return (24 + 8 + 24 + 4 + 4 + 4 + 24) + (24 + 16 + 12 * t + 24 + 4 * t + 4)
 
 
-FINISH_BYTES_PER_ION = 24 + 4 + 8 + 4 + 24
-
-
-def ion_bytes_per_step(fp32: bool) -> int:
+def implementation_bytes(fp32: bool, sites: int, ions: int, fused: bool) -> int:
     t = 4 if fp32 else 8
-    pack_update = (60 + 64) + (60 + 24)
-    forces = 24 + 8 + 24 * t + 24
-    return pack_update + forces
+    rec = 16 + 12 * t + 5 * t + 24 + 4 + mover_bytes_per_ion(fp32)
+    return leapfrog_bytes_per_site(fp32, True) * sites + (rec * ions if fused else 0)
 
 
 def kernel_source_hash() -> str:
@@ -96,15 +108,33 @@ def load_traffic(precision: str):
     return float(m.group(1))
 
 
-def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None, solve_tol=1e-12):
+def align_steps(warmup: int) -> int:
+    """Untimed steps after the warm-up that put the first timed step on the
+    last step of a cadence period (step index -1 mod CADENCE): that step ends
+    with the audit and the energy evaluation, and the next one starts with
+    the permittivity recompute and the re-binning, so a window of two or more
+    steps holds each of them."""
+    return (CADENCE - 1 - warmup) % CADENCE
+
+
+def cadence_counts(first: int, steps: int) -> dict:
+    idx = range(first, first + steps)
+    return {"permittivity_recompute": sum(1 for t in idx if t % CADENCE == 0),
+            "rebinning": sum(1 for t in idx if t % CADENCE == 0),
+            "audit": sum(1 for t in idx if (t + 1) % CADENCE == 0),
+            "energy": sum(1 for t in idx if (t + 1) % CADENCE == 0)}
+
+
+def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None, solve_tol=1e-12, outputs=False):
     import torch
     from paper_1309_7859_amd import memd
     from paper_1309_7859_amd import workloads as W
 
     fp32 = precision == "fp32"
+    pre = warmup + align_steps(warmup)
     s = W.make_system(w, steps=0)
     stream = W.DisplacementStream(w)
-    disp = torch.from_numpy(stream.take(warmup + steps)).to("cuda").contiguous()
+    disp = torch.from_numpy(stream.take(pre + steps)).to("cuda").contiguous()
     torch.cuda.synchronize()
     if copy_mb:
         # a plain copy of known size: calibrates the HBM byte counters under rocprofv3
@@ -125,18 +155,19 @@ def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None, solve_tol=1e-12):
         tile_used = tuple(tile) + (None,)
     else:
         tile_used = memd.memd_autotune(G.ctx, 10, None)
+    memd.memd_set_options(G.ctx, 1, CADENCE)  # re-binning on the permittivity's cadence
     c_used, eps_h, eps_min = G.params_in_use()
     per = 3 * w.n
     base = disp.data_ptr()
-    if warmup:
-        memd.memd_step(G.ctx, base, warmup)
+    if pre:
+        memd.memd_step(G.ctx, base, pre)
     torch.cuda.synchronize()
     # HIP events ride on one leapfrog launch in PROFILE_EVERY (each timed
     # launch costs a few microseconds more than an untimed one)
     memd.memd_profile_enable(G.ctx, ["leapfrog"], PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    memd.memd_step(G.ctx, base + 8 * per * warmup, steps)
+    memd.memd_step(G.ctx, base + 8 * per * pre, steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lf_ms, lf_n = memd.memd_profile_read(G.ctx, "leapfrog")
@@ -144,11 +175,58 @@ def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None, solve_tol=1e-12):
     bad_moves, fused = memd.memd_counters(G.ctx)
     audits, energies = G.history()
     gauss_max = float(np.max(audits[:, 0])) if len(audits) else None
+    gauss_final, _ = G.gauss_residual()  # the state the window ends on, after the timing
+    out = dict(wall=wall, lf_ms=lf_ms, lf_n=lf_n, solve_s=t_solve, solve_iters=iters, tile=tile_used,
+               fused=bool(fused), bad_moves=bad_moves, pre=pre,
+               solve_res=res, solve_status=st, c=c_used, eps_min=eps_min, gauss_max=gauss_max,
+               gauss_final=gauss_final, cadence=cadence_counts(pre, steps),
+               energy_last=energies[-1].tolist() if len(energies) else None)
+    if outputs:
+        out["F"] = G.forces()
+        out["E"] = G.energy()
+        out["P"] = G.dipole()
     G.close()
-    return dict(wall=wall, lf_ms=lf_ms, lf_n=lf_n, solve_s=t_solve, solve_iters=iters, tile=tile_used,
-                fused=bool(fused), bad_moves=bad_moves,
-                solve_res=res, solve_status=st, c=c_used, eps_min=eps_min, gauss_max=gauss_max,
-                energy_last=energies[-1].tolist() if len(energies) else None)
+    return out
+
+
+def output_error(r32, r64) -> dict:
+    """Error of each output of the FP32-field run against the FP64 run of the
+    same trajectory (the FP64 path matches the FP64 oracle to 1e-10)."""
+    F, F64 = r32["F"], r64["F"]
+    rms = float(np.sqrt(np.mean(np.sum(F64 ** 2, axis=1))))
+    e, e64 = r32["E"], r64["E"]
+    out = {"force_max_over_rms": float(np.max(np.abs(F - F64)) / rms)}
+    for k in ("W_E", "W_B", "U_self", "U_dip"):
+        out[k] = abs(e[k] - e64[k]) / max(abs(e64[k]), 1e-300)
+    out["E_corrected_over_W_E"] = abs(e["E_corrected"] - e64["E_corrected"]) / abs(e64["W_E"])
+    out["dipole"] = float(np.max(np.abs(r32["P"] - r64["P"])) / max(1.0, np.max(np.abs(r64["P"]))))
+    out["gauss_max"] = r32["gauss_final"]
+    out["gauss_max_fp64"] = r64["gauss_final"]
+    return {k: float("%.3g" % v) for k, v in out.items()}
+
+
+def stream_copy_gbs(mb: int = 1024, reps: int = 10) -> dict:
+    """On-box bandwidth ceiling: a device-to-device copy of mb MiB (torch's
+    copy kernel), timed with events, median of reps; bytes = read + write."""
+    import torch
+    n = (mb << 20) // 4
+    src = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    t = float(np.median(times))
+    return {"GBps": round(2 * n * 4 / t / 1e9, 1), "bytes_per_copy": 2 * n * 4, "median_s": t,
+            "reps": reps}
 
 
 def md_run(w, steps, warmup, tile=None):
@@ -177,8 +255,9 @@ def md_run(w, steps, warmup, tile=None):
     rng = np.random.default_rng(w.seed + 1)
     v = torch.from_numpy(rng.normal(0.0, 2.0, size=(w.n, 3))).to("cuda").contiguous()
     m = torch.full((w.n,), 100.0, dtype=torch.float64, device="cuda")
-    if warmup:
-        G.md_step(v, m, warmup)
+    pre = warmup + align_steps(warmup)
+    if pre:
+        G.md_step(v, m, pre)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     G.md_step(v, m, steps)
@@ -186,39 +265,71 @@ def md_run(w, steps, warmup, tile=None):
     wall = time.perf_counter() - t0
     audits, _ = G.history()
     gauss_max = float(np.max(audits[:, 0])) if len(audits) else None
+    gauss_final, _ = G.gauss_residual()
     G.close()
-    return dict(wall=wall, gauss_max=gauss_max)
+    return dict(wall=wall, gauss_max=gauss_max, gauss_final=gauss_final)
 
 
-def cpu_baseline(w, sample_steps: int):
-    """The FP64 oracle on a bounded sample of the same workload: sample_steps
-    steps (leapfrog, deposit, dipole, forces) plus one permittivity recompute,
-    one Gauss audit and one energy evaluation, amortised at the GPU cadence
-    of one per 50 steps.  The oracle starts from the recursion solution (its
-    CG relaxation at 128^3 is a one-off that is not part of a step)."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, sample_steps: int, single_steps: int):
+    """The FP64 oracle on a bounded sample of the same workload: per step the
+    leapfrog, the deposit, the dipole and the forces, timed over sample_steps
+    steps three times (the median is taken) with all of the oracle's threads,
+    and over single_steps steps three times with one thread; the permittivity
+    recompute, the Gauss audit and the energy evaluation are timed once at
+    each thread count and amortised at the GPU cadence of one per 50 steps.
+    The oracle starts from the recursion solution (its CG relaxation at 128^3
+    is a one-off that is not part of a step)."""
     import oracle
     from paper_1309_7859_amd import workloads as W
 
     s = W.make_system(w, steps=0)
-    disp = W.DisplacementStream(w).take(sample_steps)
+    disp = W.DisplacementStream(w).take(3 * sample_steps + 3 * single_steps)
     S = oracle.System(w.L, w.a, w.dt, 1.0, s["q"], s["r0"])
-    t0 = time.perf_counter()
     S.set_eps_salt()
-    t_salt = time.perf_counter() - t0
     S.c = W.default_c(w.a, w.dt, float(np.min(1.0 / S.eta)))
     S.recursion_only()
-    t0 = time.perf_counter()
-    for t in range(sample_steps):
-        S.step(disp[t])
-        S.forces()
-    t_steps = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    S.gauss_residual()
-    S.energy()
-    t_obs = time.perf_counter() - t0
-    per_step = t_steps / sample_steps + (t_salt + t_obs) / CADENCE
-    return dict(per_step=per_step, cores=oracle.threads(),
-                total=t_steps + t_salt + t_obs)
+    cursor = [0]
+
+    def steps_time(k):
+        t0 = time.perf_counter()
+        for _ in range(k):
+            S.step(disp[cursor[0]])
+            S.forces()
+            cursor[0] += 1
+        return (time.perf_counter() - t0) / k
+
+    def cadence_time():
+        t0 = time.perf_counter()
+        S.set_eps_salt()
+        S.gauss_residual()
+        S.energy()
+        return time.perf_counter() - t0
+
+    threads = oracle.threads()
+    t_start = time.perf_counter()
+    multi = [steps_time(sample_steps) for _ in range(3)]
+    cad_multi = cadence_time()
+    oracle.set_threads(1)
+    try:
+        single = [steps_time(single_steps) for _ in range(3)]
+        cad_single = cadence_time()
+    finally:
+        oracle.set_threads(threads)
+    total = time.perf_counter() - t_start
+    per_multi = float(np.median(multi)) + cad_multi / CADENCE
+    per_single = float(np.median(single)) + cad_single / CADENCE
+    return dict(per_step=per_multi, per_step_single=per_single, cores=threads, total=total,
+                runs=[round(x * 1e3, 1) for x in multi], runs_single=[round(x * 1e3, 1) for x in single])
 
 
 def main():
@@ -227,11 +338,17 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--fp64-steps", type=int, default=200,
-                    help="steps of the FP64 variant reported beside the main line (0 = skip)")
-    ap.add_argument("--cpu-steps", type=int, default=100, help="oracle sample size (0 = skip)")
+    ap.add_argument("--fp64", type=int, default=1,
+                    help="1: run the FP64 variant over the same trajectory and report the FP32 "
+                         "path's error on each output against it (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=10,
+                    help="oracle sample: steps per timed run with all threads (0 = skip)")
+    ap.add_argument("--cpu-single-steps", type=int, default=1,
+                    help="oracle sample: steps per timed run with one thread")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
+    ap.add_argument("--stream-mb", type=int, default=1024,
+                    help="size of the on-box stream-copy ceiling measurement (0 = skip)")
     ap.add_argument("--tile", type=str, default="", help="rows,planes of the leapfrog tile")
     ap.add_argument("--md-steps", type=int, default=100,
                     help="steps of the c4 system under its own dynamics (0 = skip)")
@@ -258,64 +375,72 @@ def main():
     w = W.WORKLOADS["c4"]
     tile = tuple(int(x) for x in args.tile.split(",")) if args.tile else None
     fp32 = args.precision == "fp32"
-    r = gpu_run(w, args.steps, args.warmup, args.precision, args.copy_mb, tile)
+    copy = stream_copy_gbs(args.stream_mb) if args.stream_mb > 0 else None
+    r = gpu_run(w, args.steps, args.warmup, args.precision, args.copy_mb, tile, outputs=True)
     sites = w.sites
     value = sites * args.steps / r["wall"]
     ion_steps = w.n * args.steps / r["wall"]
 
     lf_avg_s = r["lf_ms"] / 1e3 / max(r["lf_n"], 1)
-    # the fused kernel also reads each ion's record once: a 16-byte head and
-    # the 12 first-cell values in the field type (the second cell's 12 only
-    # for a move that crosses a face); for the forces it computes it reads the
-    # fractional position and charge (4 values) and 12/sum(eta) of the cell,
-    # and writes three FP64 force components and a 4-byte stamp; its movers
-    # move every ion and write the next step's records
-    tsz = 4 if fp32 else 8
-    rec_bytes = 16 + 12 * tsz + 5 * tsz + 24 + 4 + mover_bytes_per_ion(fp32)
-    lf_bytes = leapfrog_bytes_per_site(fp32, True) * sites + (rec_bytes * w.n if r["fused"] else 0)
-    achieved = lf_bytes / lf_avg_s / 1e9
+    alg = algorithmic_bytes(args.precision, sites, w.n)
+    impl = implementation_bytes(fp32, sites, w.n, r["fused"])
+    achieved = alg / lf_avg_s / 1e9
     traffic = load_traffic(args.precision)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (round(traffic / lf_avg_s / 1e9, 1) if traffic else None),
             "kernel": ("k_leapfrog_dep (Faraday + Ampere + tile-owned current deposit + ion movers)" if r["fused"]
                        else "k_leapfrog (Faraday + Ampere)"),
-            "algorithmic_bytes_per_launch": lf_bytes, "avg_launch_us": round(lf_avg_s * 1e6, 2),
+            "algorithmic_bytes_per_launch": alg,
+            "algorithmic_bytes_rule": f"{SITE_BYTES[args.precision]} B/site + {ION_BYTES[args.precision]} B/ion",
+            "avg_launch_us": round(lf_avg_s * 1e6, 2),
             "launches": r["lf_n"], "timed_every": PROFILE_EVERY,
+            "implementation_bytes_per_launch": impl,
+            "implementation_frac": round(impl / lf_avg_s / 1e9 / HBM_PEAK_GBS, 4),
             "tile": {"x": 64, "y": 4 * r["tile"][0], "z_chunk": r["tile"][1],
                      "autotuned_us": r["tile"][2]}}
     if traffic:
         roof["traffic_bytes_per_launch"] = traffic
-    step_bytes = lf_bytes + (FINISH_BYTES_PER_ION if r["fused"] else ion_bytes_per_step(fp32)) * w.n
+    if copy:
+        roof["frac_of_stream_copy"] = round(achieved / copy["GBps"], 4)
+    ms_step = r["wall"] * 1e3 / args.steps
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "site-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(r["wall"] * 1e3 / args.steps, 5),
+        "ms_per_step": round(ms_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 fields, f64 positions/reductions" if fp32 else "f64",
         "data": "synthetic: seeded uniform ions, Gaussian displacements (c4 recipe)",
-        "config": {"workload": "c4: 128^3 lattice, 1e5 ions (10% +-2), salt eps per link every 50 "
-                               "steps, audit+energy every 50 steps",
+        "config": {"workload": "c4: 128^3 lattice, 1e5 ions (10% +-2), salt eps per link, re-binning, "
+                               "audit and energy every 50 steps",
                    "L": w.L, "n_ions": w.n, "precision": args.precision, "c": r["c"],
                    "dt": w.dt, "sigma": w.sigma},
         "ion_steps_per_s": round(ion_steps, 1),
-        "step_hbm_frac": round(step_bytes / (r["wall"] / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_hbm_frac": round(alg / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roof,
+        "timed_window": {"first_step_index": r["pre"], "align_steps": r["pre"] - args.warmup,
+                         "cadence_work_inside": r["cadence"]},
         "gauss_residual_max": r["gauss_max"],
+        "gauss_residual_final": r["gauss_final"],
         "initial_solve": {"seconds": round(r["solve_s"], 3), "iterations": r["solve_iters"],
                           "curl_residual": r["solve_res"], "status": r["solve_status"]},
     }
-    if fp32 and args.fp64_steps > 0:
-        r64 = gpu_run(w, args.fp64_steps, min(args.warmup, 20), "fp64")
+    if copy:
+        out["stream_copy"] = {"GBps": copy["GBps"], "frac_of_peak": round(copy["GBps"] / HBM_PEAK_GBS, 4),
+                              "kind": f"device copy of {args.stream_mb} MiB (torch), median of {copy['reps']}"}
+    if fp32 and args.fp64 > 0:
+        r64 = gpu_run(w, args.steps, args.warmup, "fp64", outputs=True)
         lf64 = r64["lf_ms"] / 1e3 / max(r64["lf_n"], 1)
-        rec64 = 16 + 12 * 8 + 5 * 8 + 24 + 4 + mover_bytes_per_ion(False)
-        b64 = leapfrog_bytes_per_site(False, True) * sites + (rec64 * w.n if r64["fused"] else 0)
+        b64 = algorithmic_bytes("fp64", sites, w.n)
         out["fp64_variant"] = {
-            "value": round(sites * args.fp64_steps / r64["wall"], 1),
-            "ion_steps_per_s": round(w.n * args.fp64_steps / r64["wall"], 1),
-            "ms_per_step": round(r64["wall"] * 1e3 / args.fp64_steps, 5),
+            "value": round(sites * args.steps / r64["wall"], 1),
+            "ion_steps_per_s": round(w.n * args.steps / r64["wall"], 1),
+            "ms_per_step": round(r64["wall"] * 1e3 / args.steps, 5),
+            "leapfrog_avg_us": round(lf64 * 1e6, 2),
             "leapfrog_frac": round(b64 / lf64 / 1e9 / HBM_PEAK_GBS, 4),
-            "steps": args.fp64_steps}
+            "step_hbm_frac": round(b64 / (r64["wall"] / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+            "steps": args.steps, "gauss_residual_final": r64["gauss_final"]}
+        out["fp32_error_vs_fp64"] = dict(steps=r["pre"] + args.steps, **output_error(r, r64))
     if fp32 and args.diag256_steps > 0:
         # the same recipe at 256^3 with 8x the ions (same density): 604 MB of
         # fields per step, more than the Infinity Cache holds
@@ -323,18 +448,21 @@ def main():
                         args.diag256_steps, 105, salt_every=CADENCE)
         r2 = gpu_run(w2, args.diag256_steps, 10, "fp32", solve_tol=1e-6)
         lf2 = r2["lf_ms"] / 1e3 / max(r2["lf_n"], 1)
-        b2 = leapfrog_bytes_per_site(True, True) * w2.sites + (rec_bytes * w2.n if r2["fused"] else 0)
+        b2 = algorithmic_bytes("fp32", w2.sites, w2.n)
         out["diag_256"] = {
-            "workload": "c4 recipe at 256^3: 8e5 ions (10% +-2), salt eps every 50 steps, "
-                        "audit+energy every 50 steps, FP32 fields",
+            "workload": "c4 recipe at 256^3: 8e5 ions (10% +-2), salt eps, re-binning, audit and energy "
+                        "every 50 steps, FP32 fields",
             "value": round(w2.sites * args.diag256_steps / r2["wall"], 1), "unit": "site-updates/s",
             "ms_per_step": round(r2["wall"] * 1e3 / args.diag256_steps, 5),
             "steps": args.diag256_steps,
+            "step_hbm_frac": round(b2 / (r2["wall"] / args.diag256_steps) / 1e9 / HBM_PEAK_GBS, 4),
             "leapfrog": {"avg_launch_us": round(lf2 * 1e6, 2), "algorithmic_bytes_per_launch": b2,
                          "achieved": round(b2 / lf2 / 1e9, 1),
                          "frac": round(b2 / lf2 / 1e9 / HBM_PEAK_GBS, 4),
+                         "implementation_bytes_per_launch": implementation_bytes(True, w2.sites, w2.n, r2["fused"]),
                          "tile": {"x": 64, "y": 4 * r2["tile"][0], "z_chunk": r2["tile"][1]},
-                         "fused": r2["fused"]}}
+                         "fused": r2["fused"]},
+            "gauss_residual_final": r2["gauss_final"]}
     if fp32 and args.md_steps > 0:
         rm = md_run(w, args.md_steps, 10, tile=tile)
         out["md"] = {
@@ -344,16 +472,22 @@ def main():
             "value": round(sites * args.md_steps / rm["wall"], 1), "unit": "site-updates/s",
             "ion_steps_per_s": round(w.n * args.md_steps / rm["wall"], 1),
             "ms_per_step": round(rm["wall"] * 1e3 / args.md_steps, 5), "steps": args.md_steps,
-            "gauss_residual_max": rm["gauss_max"]}
+            "gauss_residual_max": rm["gauss_max"], "gauss_residual_final": rm["gauss_final"]}
     if args.cpu_steps > 0:
-        cb = cpu_baseline(w, args.cpu_steps)
+        cb = cpu_baseline(w, args.cpu_steps, args.cpu_single_steps)
         out["cpu_baseline"] = {
             "value": round(sites / cb["per_step"], 1), "unit": "site-updates/s",
             "cores": cb["cores"], "kind": "oracle",
-            "sample": f"{args.cpu_steps} c4 steps (leapfrog, deposit, dipole, forces) + 1 salt "
-                      f"recompute + 1 audit + 1 energy amortised at 1/50, FP64, from the recursion "
-                      f"solution; {cb['total']:.1f} s of CPU work",
-            "ion_steps_per_s": round(w.n / cb["per_step"], 1)}
+            "sample": f"c4, FP64, from the recursion solution: 3 runs of {args.cpu_steps} steps (leapfrog, "
+                      f"deposit, dipole, forces) with {cb['cores']} threads, median, plus one permittivity "
+                      f"recompute, audit and energy amortised at 1/50; the same with 1 thread over 3 runs "
+                      f"of {args.cpu_single_steps} step(s); {cb['total']:.1f} s of CPU work",
+            "ion_steps_per_s": round(w.n / cb["per_step"], 1),
+            "cpu_model": cpu_model(),
+            "ms_per_step_runs": cb["runs"],
+            "single_thread": {"value": round(sites / cb["per_step_single"], 1),
+                              "ion_steps_per_s": round(w.n / cb["per_step_single"], 1),
+                              "ms_per_step_runs": cb["runs_single"]}}
     if args.serve_count > 0:
         out["serving"] = serving_run(args.serve_count, args.serve_rate, args.serve_fp64_count)
     print(json.dumps(out), flush=True)

@@ -172,15 +172,39 @@ memd_status memd_step_seeded(memd_ctx *ctx, uint64_t seed, double sigma, int nst
 memd_status memd_md_step(memd_ctx *ctx, double *v, const double *mass, int nsteps);
 memd_status memd_seeded_displacements(uint64_t seed, int step, int n, double sigma, double *out);
 
-/* Forces F_out[3n] on the ions at the current state (FP64). */
+/* Forces on the ions at the current state: eq. force (the electric part
+ * q_i E with E = D/eps; the magnetic v x B part is omitted, as the paper's
+ * own implementation omits it), with E interpolated from the 4 links of each
+ * axis of the ion's cell by the transverse linear weights (the partner of the
+ * current assignment of the same cell), minus the lattice self force of
+ * eq. greens (section "Self energy interaction": U = q^2 S(f)/(2 eps_cell a),
+ * eps_cell the harmonic mean of the cell's 12 edges), plus the dipole term
+ * q_i P_d/(V eps_h_d) of section "Periodicity".  F_out[3n] (host or device
+ * memory, FP64, AoS xyz, the caller's ion order) is owned by the caller.
+ * Waits for the context's stream.
+ * Errors: EINVAL (F_out NULL with ions), EDEVICE. */
 memd_status memd_forces(memd_ctx *ctx, double *F_out);
 
-/* Energies of the current state (FP64 accumulation). */
+/* Energies of the current state, accumulated in FP64 on the device: the
+ * field terms of eq. lagrangian, W_E = (1/2) a^3 sum_links D^2/eps (the
+ * weight of eq. finalpartitionfunction) and the magnetic term in the
+ * leapfrog's shadow form (c^2/2) a^3 sum B^{n+1/2} B^{n+3/2} (the later factor
+ * made transiently, the state left unchanged), the lattice self energy
+ * U_self of section "Self energy interaction", the uniform-mode energy U_dip
+ * removed by the dipole correction of section "Periodicity", and
+ * E_corrected = W_E + W_B - U_self - U_dip.  *out is owned by the caller.
+ * Waits for the context's stream.
+ * Errors: EINVAL (out NULL), EDEVICE. */
 memd_status memd_energy(memd_ctx *ctx, memd_energy_t *out);
 
-/* Gauss audit of the current state: R_v = a^2 div D(v) - q_v with q_v the
- * linear assignment of the ions, max_v |R_v| and rms (FP64).  Either output
- * may be NULL. */
+/* Gauss audit of the current state: Gauss's law as the recursion of Fig. 1
+ * establishes it and every later update keeps it (section "Extension of the
+ * algorithm", eq. constraint), R_v = a^2 sum_d [D_d(v) - D_d(v - e_d)] - q_v
+ * with q_v the linear assignment of the ions' charges to the vertices;
+ * returns max_v |R_v| and the rms over the Ns vertices, computed in FP64 on
+ * the device (in FP32 mode from the stored FP32 values).  Either output may
+ * be NULL.  Waits for the context's stream.
+ * Errors: EDEVICE. */
 memd_status memd_gauss_residual(memd_ctx *ctx, double *max_abs, double *rms);
 
 /* Dipole moment of the unfolded positions, P = sum_i q_i r_i (FP64). */

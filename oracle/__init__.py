@@ -40,6 +40,7 @@ def _load():
     sig = {
         "orc_version": (i, []),
         "orc_threads": (i, []),
+        "orc_set_threads": (None, [i]),
         "orc_spread": (None, [i, d, i, _P, _P, _P]),
         "orc_eps_site_to_link": (i, [i, _P, d, _P]),
         "orc_eps_derived": (None, [i, _P, _P, _P, _P]),
@@ -183,6 +184,11 @@ def threads() -> int:
     return _load().orc_threads()
 
 
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (n > 0)."""
+    _load().orc_set_threads(int(n))
+
+
 def default_c(a: float, dt: float, eps_min: float, nu: float = 0.25) -> float:
     """Speed of light for a Courant number nu = c dt sqrt(3) / (a sqrt(eps_min))."""
     return nu * (a / dt) * math.sqrt(eps_min / 3.0)
@@ -206,6 +212,11 @@ class System:
         self.B = np.zeros(3 * self.Ns)
         self.G = greens(self.L)
         self.set_eps_uniform(1.0)
+        # section "Periodicity": with the correction, the force of the uniform
+        # mode of D on each ion, -q_i P/(V eps_h), is removed (metallic
+        # boundaries at infinity) and U_dip leaves the energy; without it, the
+        # plain lattice algorithm holds the dipole moment in a harmonic well
+        self.dipole_correction = True
 
     # -- permittivity
     def set_eps_link(self, eps_link):
@@ -302,10 +313,13 @@ class System:
         self.lib.orc_gauss_residual(self.L, self.a, _ptr(self.D), _ptr(rho), C.byref(m), C.byref(s))
         return m.value, s.value
 
+    def _P_for_correction(self) -> np.ndarray:
+        return self.dipole() if self.dipole_correction else np.zeros(3)
+
     def forces(self, with_self: bool = True):
         F = np.zeros(3 * self.n)
         U = np.zeros(self.n)
-        P = self.dipole()
+        P = self._P_for_correction()
         self.lib.orc_forces(self.L, self.a, self.n, _ptr(self.q), _ptr(self.r), _ptr(self.D),
                             _ptr(self.eta), _ptr(self.eps_cell), _ptr(self.eps_h), _ptr(self.G),
                             _ptr(P), _ptr(F), _ptr(U))
@@ -315,7 +329,7 @@ class System:
     def energy(self) -> dict:
         _, U = self.forces()
         out = np.zeros(5)
-        P = self.dipole()
+        P = self._P_for_correction()
         self.lib.orc_energy(self.L, self.a, self.dt, self.c, _ptr(self.eta), _ptr(self.D),
                             _ptr(self.B), float(U.sum()), _ptr(P), _ptr(self.eps_h), _ptr(out))
         return dict(W_E=out[0], W_B=out[1], U_self=out[2], U_dip=out[3], E_corrected=out[4])

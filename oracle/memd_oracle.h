@@ -22,8 +22,9 @@ extern "C" {
 #endif
 
 int orc_version(void);
-/* OpenMP threads the stencil loops use. */
+/* OpenMP threads the stencil loops use, and a way to set them (n > 0). */
 int orc_threads(void);
+void orc_set_threads(int n);
 
 /* Linear (cloud-in-cell) charge assignment to the 8 corners of the cell
  * (section "Self energy interaction"; section "Error estimates"). */

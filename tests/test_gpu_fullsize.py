@@ -3,15 +3,15 @@ salt-dependent permittivity per link recomputed every 50 steps, in the launch
 configuration the bench times (autotuned tile shape, the leapfrog with the
 fused deposit and its ion movers, several steps per call so that the
 finisher computes the forces of the state each step starts from and the
-movers write the next step's records), with the ions re-binned every 8
-steps and the run split over two calls, so that records are built by the
-re-binning, by the pack at a call's start and by the movers, on both
-record sets.
+movers write the next step's records, re-binning and the permittivity
+recompute every 50 steps, audit and energy at their cadence), over 63 steps
+split into calls of 27 and 36 steps, so that the step-50 permittivity
+recompute and re-binning run inside a call.
 
-Both sides start from the oracle's recursion solution (its CG relaxation at
-128^3 is a one-off outside the step) and take the same seeded displacements.
-Every force, position, the dipole, the energies and the Gauss residual are
-compared, not a sample: the oracle runs these 20 steps in seconds.
+Both precisions start from the oracle's recursion solution (its CG
+relaxation at 128^3 is a one-off outside the step) and take the same seeded
+displacements; the oracle runs once for both.  Every force, position, the
+dipole, the energies and the Gauss residual are compared, not a sample.
 """
 import numpy as np
 import pytest
@@ -19,13 +19,15 @@ import pytest
 import oracle
 from paper_1309_7859_amd import memd
 from paper_1309_7859_amd import workloads as W
-from tests.gpu_helpers import energy_err, force_err, require_gpu
+from tests.gpu_helpers import (energy_err, force_err, fp32_gauss_bar, output_errors, record,
+                               require_gpu)
 
 pytestmark = pytest.mark.gpu
 
-STEPS = 20
-SPLIT = 7  # the first call's steps
-CADENCE = 10
+CALLS = (27, 36)
+STEPS = sum(CALLS)
+CADENCE = 50    # permittivity recompute and re-binning, as in the bench
+AUDIT = 9       # audit and energy histories inside the calls
 
 
 @pytest.fixture(autouse=True)
@@ -33,8 +35,10 @@ def _gpu():
     require_gpu()
 
 
-@pytest.mark.parametrize("prec", [memd.FP32_MIXED, memd.FP64])
-def test_c4_full_size_parity(prec):
+@pytest.fixture(scope="module")
+def c4_oracle():
+    """The oracle's run of the 63 steps: its start state, the displacements,
+    and the finished System with the Gauss residuals at the audit cadence."""
     w = W.WORKLOADS["c4"]
     s = W.make_system(w, steps=0)
     disp = W.DisplacementStream(w).take(STEPS)
@@ -42,39 +46,46 @@ def test_c4_full_size_parity(prec):
     S.set_eps_salt()
     S.c = W.default_c(w.a, w.dt, float(np.min(1.0 / S.eta)))
     S.recursion_only()
-    D0, B0, r0 = S.state()
+    start = S.state()
+    gauss = []
+    for t in range(STEPS):
+        if t % CADENCE == 0:
+            S.set_eps_salt()
+        S.step(disp[t])
+        if (t + 1) % AUDIT == 0:
+            gauss.append(S.gauss_residual()[0])
+    return dict(w=w, s=s, disp=disp, S=S, start=start, gauss=gauss)
+
+
+@pytest.mark.parametrize("prec", [memd.FP32_MIXED, memd.FP64])
+def test_c4_full_size_parity(prec, c4_oracle):
+    w, s, disp, S = c4_oracle["w"], c4_oracle["s"], c4_oracle["disp"], c4_oracle["S"]
+    D0, B0, r0 = c4_oracle["start"]
     G = memd.Context(w.L, s["q"], s["r0"], a=w.a, dt=w.dt, c=S.c, precision=prec,
-                     audit_every=CADENCE, energy_every=CADENCE)
+                     audit_every=AUDIT, energy_every=AUDIT)
     try:
-        G.set_salt(80.0, 15.0, 1.0, every=50)
+        G.set_salt(80.0, 15.0, 1.0, every=CADENCE)
         G.set_state(D0, B0, r0)
         memd.memd_autotune(G.ctx, 3, None)
-        memd.memd_set_options(G.ctx, 1, 8)
+        memd.memd_set_options(G.ctx, 1, CADENCE)
         assert memd.memd_counters(G.ctx)[1] == 1  # the fused path, as in the bench
-        G.step(disp[:SPLIT], SPLIT)
-        G.step(disp[SPLIT:], STEPS - SPLIT)
-        gauss = []
-        for t in range(STEPS):
-            if t % 50 == 0:
-                S.set_eps_salt()
-            S.step(disp[t])
-            if (t + 1) % CADENCE == 0:
-                gauss.append(S.gauss_residual()[0])
-        Fo, _ = S.forces()
-        F = G.forces()
+        G.step(disp[:CALLS[0]], CALLS[0])
+        G.step(disp[CALLS[0]:], CALLS[1])
+        fp32 = prec == memd.FP32_MIXED
+        ftol, etol = (1e-4, 1e-4) if fp32 else (1e-10, 1e-10)
+        gtol = fp32_gauss_bar(w.L, w.a, s["q"], r0, S.r) if fp32 else 1e-12
         D, B, r = G.state()
         audits, energies = G.history()
-        fp32 = prec == memd.FP32_MIXED
-        ftol, gtol, etol = (1e-4, 2e-5, 1e-4) if fp32 else (1e-10, 1e-12, 1e-10)
-        assert np.max(np.abs(r - S.r)) <= 1e-12 * max(1.0, np.max(np.abs(S.r)))
-        assert force_err(F, Fo) <= ftol
-        P, Po = G.dipole(), S.dipole()
-        assert np.max(np.abs(P - Po)) <= 1e-12 * max(1.0, np.max(np.abs(Po)))
-        assert len(audits) == STEPS // CADENCE and len(energies) == STEPS // CADENCE
+        err = output_errors(G, S)
+        record("c4", precision="fp32" if fp32 else "fp64", steps=STEPS, gauss_bar=gtol,
+               audit_history_max=float(np.max(audits[:, 0])), **err)
+        assert err["position"] <= 1e-12
+        assert err["force"] <= ftol, err
+        assert err["dipole"] <= 1e-12
+        assert len(audits) == STEPS // AUDIT and len(energies) == STEPS // AUDIT
         assert np.all(audits[:, 0] <= gtol), audits
-        assert max(gauss) <= 1e-12
-        m, _ = G.gauss_residual()
-        assert m <= gtol
+        assert max(c4_oracle["gauss"]) <= 1e-12
+        assert err["gauss_max"] <= gtol
         errs = energy_err(G.energy(), S.energy())
         assert max(errs.values()) <= etol, errs
         E = S.eta * D
