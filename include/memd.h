@@ -54,7 +54,8 @@ typedef enum {
     MEMD_EUNSTABLE = -4,    /* Courant number c dt sqrt(3) / (a sqrt(eps_min)) >= 1 */
     MEMD_ESTATE = -5,       /* call out of order (e.g. step before the initial solve) */
     MEMD_ENOCONV = -6,      /* the relaxation did not reach the tolerance */
-    MEMD_EDEVICE = -7       /* a HIP call failed; the context is poisoned */
+    MEMD_EDEVICE = -7,      /* a HIP call failed; the context is poisoned */
+    MEMD_ESIZE = -8         /* input larger than the fixed scratch area of an allocation-free call */
 } memd_status;
 
 typedef enum {
@@ -206,6 +207,25 @@ memd_status memd_energy(memd_ctx *ctx, memd_energy_t *out);
  * be NULL.  Waits for the context's stream.
  * Errors: EDEVICE. */
 memd_status memd_gauss_residual(memd_ctx *ctx, double *max_abs, double *rms);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the audit of
+ * memd_gauss_residual on caller-owned buffers, without a context and without
+ * any allocation.  D[3 L^3] (FP64 for MEMD_FP64, FP32 for MEMD_FP32_MIXED,
+ * component-major), q[n] and r[3n] (FP64, unfolded, AoS xyz) must be device
+ * memory of the current device; out[2] receives (max_v |R_v|, rms) and may be
+ * device memory (written in stream order, the call does not wait: usable
+ * under graph capture) or host memory (the call waits for the stream).  Work
+ * runs on hip_stream (NULL: the null stream).  The charge assignment and the
+ * partial sums live in one fixed device array of 16.1 MiB per GPU (held from
+ * the first call on that GPU until the process ends), which limits L to 128.
+ * Every call on a GPU shares that array: calls that overlap on one GPU (on
+ * different streams, or from different threads) race and must be ordered by
+ * the caller.
+ * Errors: EINVAL (L < 2, a <= 0, n < 0, NULL or non-device pointers, bad
+ * precision), ESIZE (L > 128), EDEVICE. */
+memd_status memd_gauss_residual_noalloc(int L, double a, int n, const double *q, const double *r,
+                                        const void *D, int precision, double *out, void *hip_stream);
 
 /* Dipole moment of the unfolded positions, P = sum_i q_i r_i (FP64). */
 memd_status memd_dipole(memd_ctx *ctx, double P[3]);

@@ -338,17 +338,23 @@ __global__ __launch_bounds__(256) void k_audit(const T *__restrict__ D, const do
     }
 }
 
-hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk) {
-    const int nb = site_blocks(c->Ns);
+hipError_t launch_audit_raw(hipStream_t s, const void *D, bool fp32, const double *rho, int L, double a,
+                            double *partials, int *nblk) {
+    const size_t Ns = (size_t)L * L * L;
+    const int nb = site_blocks(Ns);
     *nblk = nb;
-    const double a2 = c->a * c->a;
-    if (c->fp32)
-        hipLaunchKernelGGL(k_audit<float>, dim3(nb), dim3(kThreads), 0, c->stream, (const float *)D,
-                           c->rho, c->L, c->Ns, a2, partials);
+    const double a2 = a * a;
+    if (fp32)
+        hipLaunchKernelGGL(k_audit<float>, dim3(nb), dim3(kThreads), 0, s, (const float *)D, rho, L, Ns, a2,
+                           partials);
     else
-        hipLaunchKernelGGL(k_audit<double>, dim3(nb), dim3(kThreads), 0, c->stream,
-                           (const double *)D, c->rho, c->L, c->Ns, a2, partials);
+        hipLaunchKernelGGL(k_audit<double>, dim3(nb), dim3(kThreads), 0, s, (const double *)D, rho, L, Ns, a2,
+                           partials);
     return hipGetLastError();
+}
+
+hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk) {
+    return launch_audit_raw(c->stream, D, c->fp32, c->rho, c->L, c->a, partials, nblk);
 }
 
 // ------------------------------------------------------------------ casts

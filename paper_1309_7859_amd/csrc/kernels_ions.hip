@@ -445,11 +445,15 @@ __global__ __launch_bounds__(256) void k_spread(int n, int L, double a, const do
     spread_ion(L, a, q ? q[i] : 1.0, u, dst);
 }
 
-hipError_t launch_spread(memd_ctx *c, const double *charges_or_null, double *dst) {
-    if (c->n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spread, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
-                       charges_or_null ? c->q : nullptr, c->r, dst);
+hipError_t launch_spread_raw(hipStream_t s, int n, int L, double a, const double *q, const double *r,
+                             double *dst) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spread, dim3(ion_blocks(n)), dim3(kThreads), 0, s, n, L, a, q, r, dst);
     return hipGetLastError();
+}
+
+hipError_t launch_spread(memd_ctx *c, const double *charges_or_null, double *dst) {
+    return launch_spread_raw(c->stream, c->n, c->L, c->a, charges_or_null ? c->q : nullptr, c->r, dst);
 }
 
 // The same assignment without global atomics, for ions stored in bin order

@@ -259,6 +259,7 @@ const char *memd_strerror(memd_status s) {
         case MEMD_ESTATE: return "call out of order";
         case MEMD_ENOCONV: return "relaxation did not converge";
         case MEMD_EDEVICE: return "HIP device error";
+        case MEMD_ESIZE: return "input larger than the fixed scratch area of an allocation-free call";
     }
     return "unknown status";
 }

@@ -217,6 +217,10 @@ hipError_t launch_invert_perm(memd_ctx *c, int *iperm);
 hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
                                int *nblk);
 hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk);
+// The audit's site pass on any buffers: partials[2 * nblk] (max |R|, sum R^2
+// per block) of R_v = a^2 div D(v) - rho_v; nblk <= kSiteBlocks.
+hipError_t launch_audit_raw(hipStream_t s, const void *D, bool fp32, const double *rho, int L, double a,
+                            double *partials, int *nblk);
 hipError_t launch_cast(hipStream_t s, const double *src, void *dst, size_t count, bool to_fp32);
 hipError_t launch_uncast(hipStream_t s, const void *src, double *dst, size_t count, bool from_fp32);
 hipError_t launch_eta_from_link(memd_ctx *c, const double *eps_link, void *eta_link);
@@ -231,6 +235,9 @@ hipError_t launch_fill(hipStream_t s, double *dst, double v, size_t count);
 hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, double *partials, int *nblk,
                           uint64_t seed = 0, uint32_t t = 0, double sigma = 0.0);
 hipError_t launch_spread(memd_ctx *c, const double *charges_or_null, double *dst);
+// dst += the linear assignment of q[i] (1 when q is null) at r[3i..3i+2], FP64 atomics.
+hipError_t launch_spread_raw(hipStream_t s, int n, int L, double a, const double *q, const double *r,
+                             double *dst);
 // dst <- the assignment of every ion (charges, or 1 each without weighted);
 // writes every vertex (no global atomics once the ions are in bin order).
 hipError_t launch_spread_dense(memd_ctx *c, bool weighted, double *dst);

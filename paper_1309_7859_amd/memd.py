@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmemd.so")
 
-OK, EINVAL, ENOMEM, ENONNEUTRAL, EUNSTABLE, ESTATE, ENOCONV, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, ENONNEUTRAL, EUNSTABLE, ESTATE, ENOCONV, EDEVICE, ESIZE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 FP64, FP32_MIXED = 0, 1
 EPS_UNIFORM, EPS_SITE, EPS_LINK, EPS_ZSITE = 0, 1, 2, 3
 FAMILIES = {"leapfrog": 0, "deposit": 1, "forces": 2, "audit": 3, "energy": 4, "dipole": 5, "salt": 6}
@@ -63,6 +63,7 @@ def load():
         "memd_forces": [vp, vp],
         "memd_energy": [vp, C.POINTER(memd_energy_t)],
         "memd_gauss_residual": [vp, dp, dp],
+        "memd_gauss_residual_noalloc": [i, d, i, vp, vp, vp, i, vp, vp],
         "memd_dipole": [vp, vp],
         "memd_history": [vp, vp, vp, i, C.POINTER(i), C.POINTER(i)],
         "memd_get_state": [vp, vp, vp, vp],
@@ -184,6 +185,21 @@ def memd_gauss_residual(ctx: int):
     s = C.c_double()
     _check(load().memd_gauss_residual(ctx, C.byref(m), C.byref(s)), "memd_gauss_residual")
     return m.value, s.value
+
+
+def memd_gauss_residual_noalloc(L: int, a: float, n: int, q, r, D, precision: int, out,
+                                hip_stream=None):
+    """The allocation-free audit on device buffers.  q, r, D: torch tensors on
+    the current device (D FP64 or FP32 as precision says) or raw addresses;
+    out: a float64 array of 2 on the host or the device."""
+    def dev(x):
+        if x is None or isinstance(x, int):
+            return x
+        return x.data_ptr() if hasattr(x, "data_ptr") else x.ctypes.data
+    o = dev(out) if hasattr(out, "data_ptr") or isinstance(out, int) else _addr(out, writable=True)
+    _check(load().memd_gauss_residual_noalloc(L, a, n, dev(q), dev(r), dev(D), precision, o, hip_stream),
+           "memd_gauss_residual_noalloc")
+    return out
 
 
 def memd_dipole(ctx: int) -> np.ndarray:

@@ -43,6 +43,7 @@ def test_status_codes_match_header():
     assert codes["MEMD_ESTATE"] == memd.ESTATE
     assert codes["MEMD_ENOCONV"] == memd.ENOCONV
     assert codes["MEMD_EDEVICE"] == memd.EDEVICE
+    assert codes["MEMD_ESIZE"] == memd.ESIZE
     for k, v in re.findall(r"(MEMD_EPS_[A-Z]+)\s*=\s*(\d+)", text):
         assert getattr(memd, k[len("MEMD_"):]) == int(v)
     lib = memd.load()
