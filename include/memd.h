@@ -275,6 +275,18 @@ memd_status memd_set_tiling(memd_ctx *ctx, int rows_per_thread, int planes_per_c
  * lattice row (default 64; 0 = never after the first).  Both forms give the
  * same result up to the order of floating-point additions. */
 memd_status memd_set_options(memd_ctx *ctx, int fuse_deposit, int sort_every);
+/* The dipole correction of section "Periodicity" (on = 1, the default): the
+ * uniform mode of D, which follows -P/V with P the dipole moment of the
+ * unfolded positions, exerts -q_i P/(V eps_h) on each ion and holds P in a
+ * harmonic well, the behaviour of a periodic system with eps = 0 at
+ * infinity; the correction adds q_i P_d/(V eps_h_d) to every force (and
+ * subtracts U_dip from E_corrected), the metallic boundary at infinity under
+ * which P performs a free random walk.  on = 0 runs the plain lattice
+ * algorithm: no dipole term in the forces, U_dip reported as 0.  The forces
+ * of the current state are recomputed.  Waits for the context's stream.
+ * Errors: EINVAL (on not 0 or 1), EDEVICE. */
+memd_status memd_set_dipole_correction(memd_ctx *ctx, int on);
+
 /* bad_moves: displacement components rejected so far (not finite, or longer
  * than (L + 1024) a; they are taken as 0).  fused_path: 1 if the next
  * step runs the fused deposit.  Either may be NULL. */

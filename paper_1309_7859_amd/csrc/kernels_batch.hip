@@ -144,9 +144,10 @@ __global__ __launch_bounds__(256) void k_batch_forces(const RepDesc *__restrict_
             for (int d = 0; d < 3; ++d) s[d] += R.dip[3 * k + d];
         block_sum<3>(s);
         if (threadIdx.x == 0) {
+            const double w = R.scal[S_DIPW];  // 1, or 0 without the dipole correction
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                Psh[d] = s[d];
+                Psh[d] = w * s[d];
                 if (b == 0) R.scal[S_P + d] = s[d];
             }
         }

@@ -343,8 +343,9 @@ __global__ __launch_bounds__(256) void k_ion_finish(IonFinishArgs<T> A) {
             deposit_ion<T>(A.L, A.Ns, A.a, qi, w, du, A.Dnext);
         }
     }
+    const double w = A.scal[S_DIPW];  // 1, or 0 without the dipole correction
 #pragma unroll
-    for (int d = 0; d < 3; ++d) A.F[3 * i + d] = F[d] + qi * A.scal[S_P + d] / (A.V * A.scal[S_EPSH + d]);
+    for (int d = 0; d < 3; ++d) A.F[3 * i + d] = F[d] + qi * (w * A.scal[S_P + d]) / (A.V * A.scal[S_EPSH + d]);
 }
 
 hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext) {
@@ -648,8 +649,9 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs<T> A) {
     }
     __syncthreads();
     if (live) {
+        const double w = A.scal[S_DIPW];  // 1, or 0 without the dipole correction
 #pragma unroll
-        for (int d = 0; d < 3; ++d) A.F[3 * i + d] = F[d] + qi * Psh[d] / (A.V * A.scal[S_EPSH + d]);
+        for (int d = 0; d < 3; ++d) A.F[3 * i + d] = F[d] + qi * (w * Psh[d]) / (A.V * A.scal[S_EPSH + d]);
     }
     if (A.uself_partials) {
         double v[1] = {us};
@@ -1031,8 +1033,9 @@ __global__ void k_fin_energy(const double *fpart, int fblk, const double *ipart,
     if (threadIdx.x == 0) {
         const double we = 0.5 * a3 * s[0];
         const double wb = 0.5 * c2 * a3 * s[1];
-        double ud = 0.0;
+        double ud = 0.0;  // U_dip, removed from the energy only with the dipole correction
         for (int d = 0; d < 3; ++d) ud += scal[S_P + d] * scal[S_P + d] / (2.0 * V * scal[S_EPSH + d]);
+        ud *= scal[S_DIPW];
         const double e[5] = {we, wb, u[0], ud, we + wb - u[0] - ud};
         for (int t = 0; t < 5; ++t) {
             dst[t] = e[t];

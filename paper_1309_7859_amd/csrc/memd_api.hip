@@ -304,6 +304,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     c->lf_rows = c->fp32 ? 2 : 1;
     c->lf_tz = 4;
     c->sort_every = 64;
+    c->dipole_correction = true;
     c->fuse_deposit = true;
     c->hist_cap = kHistCap;
     if (hipGetDevice(&c->device) != hipSuccess) {
@@ -436,6 +437,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     hipMemsetAsync(c->bad_moves, 0, sizeof(unsigned int), s);
     hipMemsetAsync(c->bins, 0, (size_t)c->L * c->L * sizeof(int), s);  // bin counts: kept zero between binnings
     hipMemsetAsync(c->scal, 0, S_COUNT * sizeof(double), s);
+    if (launch_fill(s, c->scal + S_DIPW, 1.0, 1) != hipSuccess) return fail(MEMD_EDEVICE);
     hipMemsetAsync(c->F, 0, 3 * nn * sizeof(double), s);
     c->sorted = false;
     if (launch_iota(s, c->perm, n) != hipSuccess) return fail(MEMD_EDEVICE);
@@ -1070,6 +1072,16 @@ memd_status memd_set_options(memd_ctx *c, int fuse_deposit, int sort_every) {
     if (fuse_deposit < 0 || fuse_deposit > 1 || sort_every < 0) return MEMD_EINVAL;
     c->fuse_deposit = fuse_deposit != 0;
     c->sort_every = sort_every;
+    return MEMD_OK;
+}
+
+memd_status memd_set_dipole_correction(memd_ctx *c, int on) {
+    CHECK_CTX(c);
+    if (on < 0 || on > 1) return MEMD_EINVAL;
+    c->dipole_correction = on != 0;
+    CK(launch_fill(c->stream, c->scal + S_DIPW, on ? 1.0 : 0.0, 1));
+    if (c->ready) CK(enqueue_dipole_forces(c));  // the current state's forces under the new setting
+    CK(hipStreamSynchronize(c->stream));
     return MEMD_OK;
 }
 

@@ -22,6 +22,7 @@ enum ScalarSlot : int {
     S_CG = 20,      // conjugate-gradient scalars (20 slots)
     S_MEAN = 40,    // mean of D per direction [3]
     S_ETAMAX = 44,  // maximum eta over the links (1 / eps_min)
+    S_DIPW = 45,    // weight of the dipole correction: 1 (on, the default) or 0 (off)
     S_COUNT = 64
 };
 
@@ -75,6 +76,7 @@ struct memd_ctx {
     double eps_min;
     bool c_fixed;
     int salt_every;
+    bool dipole_correction;  // mirrors scal[S_DIPW]
     double salt_w, salt_slope, salt_floor;
     double *salt_cnt;  // FP64 [Ns]: ion counts of the salt permittivity
 

@@ -76,6 +76,7 @@ def load():
         "memd_autotune": [vp, i, C.c_char_p, C.POINTER(i), C.POINTER(i), dp],
         "memd_step_seeded": [vp, C.c_uint64, d, i],
         "memd_set_options": [vp, i, i],
+        "memd_set_dipole_correction": [vp, i],
         "memd_counters": [vp, C.POINTER(C.c_ulong), C.POINTER(i)],
         "memd_seeded_displacements": [C.c_uint64, i, i, d, vp],
         "memd_server_create": [C.POINTER(vp), C.c_size_t, i, i, d, C.c_char_p, vp],
@@ -282,6 +283,10 @@ def memd_set_options(ctx: int, fuse_deposit: int = 1, sort_every: int = 64):
     _check(load().memd_set_options(ctx, int(fuse_deposit), int(sort_every)), "memd_set_options")
 
 
+def memd_set_dipole_correction(ctx: int, on: bool):
+    _check(load().memd_set_dipole_correction(ctx, 1 if on else 0), "memd_set_dipole_correction")
+
+
 def memd_counters(ctx: int):
     b = C.c_ulong()
     f = C.c_int()
@@ -453,6 +458,9 @@ class Context:
 
     def history(self, max_entries=4096):
         return memd_history(self.ctx, max_entries)
+
+    def set_dipole_correction(self, on: bool):
+        memd_set_dipole_correction(self.ctx, on)
 
     def params_in_use(self):
         return memd_get_params(self.ctx)

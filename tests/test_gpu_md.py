@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_1309_7859_amd import memd
-from tests.gpu_helpers import apply_eps, energy_err, force_err, pair, require_gpu, share_state
+from tests.gpu_helpers import apply_eps, energy_err, force_err, fp32_gauss_bar, pair, require_gpu, share_state
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +51,7 @@ def test_md_matches_oracle(prec, L, fused):
         vrms = np.sqrt(np.mean(vo ** 2))
         assert np.max(np.abs(vg - vo)) <= (1e-5 if fp32 else 1e-11) * vrms
         assert np.max(np.abs(G.state()[2] - S.r)) <= (1e-8 if fp32 else 1e-12 * L)
-        assert G.gauss_residual()[0] <= (1e-5 * 2 if fp32 else 1e-12)
+        assert G.gauss_residual()[0] <= (fp32_gauss_bar(L, 1.0, S.q, S.r) if fp32 else 1e-12)
         if not fp32:
             errs = energy_err(G.energy(), S.energy())
             assert max(errs.values()) <= 1e-10, errs

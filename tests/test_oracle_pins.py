@@ -624,3 +624,114 @@ def test_md_free_flight(orc):
     assert np.array_equal(v, v0)
     assert np.allclose(S.r.reshape(n, 3), r + 40 * dt * v0, rtol=0, atol=1e-12)
     assert np.max(np.abs(S.D)) == 0.0
+
+
+# ------------------------------------------- the dipole correction ("Periodicity")
+
+def test_uncorrected_forces_lack_exactly_the_dipole_term(orc):
+    """Switching the correction off removes q_i P_d/(V eps_h_d) from every
+    force component and U_dip from the energy, and nothing else (the lattice
+    part and the self force are shared)."""
+    L, a = 8, 1.0
+    rng = np.random.default_rng(91)
+    q, r = neutral_ions(rng, 10, L, a, valence2=True)
+    S = orc.System(L, a, 0.01, 8.0, q, r)
+    S.set_eps_link(1.0 + 3.0 * rng.uniform(size=3 * L ** 3))
+    S.initial_solve(1e-13)
+    for _ in range(5):
+        S.step(rng.normal(0, 0.3, size=(10, 3)))
+    F1, _ = S.forces()
+    e1 = S.energy()
+    S.dipole_correction = False
+    F0, _ = S.forces()
+    e0 = S.energy()
+    P, V = S.dipole(), (L * a) ** 3
+    assert np.max(np.abs(P)) > 1.0
+    dip = q[:, None] * P[None, :] / (V * S.eps_h[None, :])
+    assert np.max(np.abs((F1 - F0) - dip)) <= 1e-13 * np.max(np.abs(F1))
+    assert e0["U_dip"] == 0.0 and e1["U_dip"] > 0.0
+    assert e0["E_corrected"] - e1["E_corrected"] == pytest.approx(e1["U_dip"], rel=1e-12)
+    assert e0["W_E"] == e1["W_E"] and e0["U_self"] == e1["U_self"]
+
+
+def _drag(orc, L, corrected, drag_steps, rest_steps):
+    """+1 held still and -1 dragged along +x by one box length L a at constant
+    speed, then held still: the x force on the +1 ion at the start, and its
+    mean and the y, z extremes over the rest period (the undamped lattice
+    waves the drag leaves behind average out)."""
+    a, dt = 1.0, 0.01
+    r = np.array([[2.5, L / 2 + 0.5, L / 2 + 0.5], [5.5, L / 2 + 0.5, L / 2 + 0.5]])
+    S = orc.System(L, a, dt, orc.default_c(a, dt, 1.0), [1.0, -1.0], r)
+    S.dipole_correction = corrected
+    S.initial_solve(1e-13)
+    F0 = S.forces()[0][0]
+    d = np.zeros((2, 3))
+    d[1, 0] = L * a / drag_steps
+    for _ in range(drag_steps):
+        S.step(d)
+    fx, fyz = [], 0.0
+    for _ in range(rest_steps):
+        S.step(np.zeros((2, 3)))
+        F = S.forces()[0][0]
+        fx.append(F[0])
+        fyz = max(fyz, abs(F[1]), abs(F[2]))
+    return F0, float(np.mean(fx)), fyz, S
+
+
+def test_slow_drag_across_the_box(orc):
+    """Section "Periodicity", Fig. 5b: two opposite charges pulled apart by a
+    whole box length end in the configuration they started from, up to the
+    unfolding of one ion.  With the dipole correction the force returns to
+    its start value (within what the drag's retardation leaves, averaged
+    over the rest period); without it the dipole moment has grown by
+    q_2 L a e_x and the force on the other ion is offset by exactly
+    -q_1 q_2 L a/(eps V) along x, larger than the pair force itself."""
+    L = 8
+    V = float(L ** 3)
+    F0c, fc, yzc, _ = _drag(orc, L, True, 800, 400)
+    F0u, fu, yzu, _ = _drag(orc, L, False, 800, 400)
+    offset = -(1.0) * (-1.0) * L / V  # -q1 q2 L a / (eps V)
+    assert F0c[0] > 0  # attraction towards the -1 ion at larger x
+    assert abs(fc - F0c[0]) <= 0.02 * abs(F0c[0]), (fc, F0c)
+    assert abs((fu - F0u[0]) - offset) <= 0.02 * offset, (fu - F0u[0], offset)
+    assert offset > 2 * abs(F0c[0])
+    assert yzc <= 1e-12 and yzu <= 1e-12  # symmetric in y and z throughout
+
+
+def test_dipole_random_walk(orc):
+    """Section "Periodicity", Fig. 5a: an electrolyte of 64 monovalent ions
+    moving under its own forces (velocity Verlet, L = 8, eps = 1, unit
+    masses, velocities N(0, 1)).  Without the correction the uniform mode of
+    D pulls the dipole moment back with -sum_i q_i^2 P/(m V eps): P stays
+    inside the harmonic amplitude A = sqrt(|P0|^2 + |dP/dt(0)|^2 / w^2),
+    w^2 = sum q^2/(m V eps) (the eps = 0 boundary of the figure).  With it P
+    walks freely and leaves that amplitude several times over (the metallic
+    boundary).  Each run conserves its own energy: K + E_corrected, where
+    E_corrected keeps the uniform-mode energy without the correction."""
+    L, n, eps, dt, steps = 8, 64, 1.0, 0.01, 3000
+    rng = np.random.default_rng(5)
+    r = rng.uniform(0, L, size=(n, 3))
+    q = np.tile([1.0, -1.0], n // 2)
+    v0 = rng.normal(0, 1.0, size=(n, 3))
+    m = np.ones(n)
+    V = float(L ** 3)
+    w = math.sqrt(np.sum(q ** 2) / (V * eps))
+    A = math.sqrt(np.sum(orc.dipole(q, r) ** 2) + np.sum((q @ v0) ** 2) / w ** 2)
+    peak = {}
+    for corrected in (False, True):
+        S = orc.System(L, 1.0, dt, orc.default_c(1.0, dt, eps), q, r)
+        S.set_eps_uniform(eps)
+        S.dipole_correction = corrected
+        S.initial_solve(1e-13)
+        v = v0.copy()
+        Pn, tot = [], []
+        for t in range(steps):
+            S.md_step(v, m)
+            if t % 50 == 49:
+                Pn.append(np.linalg.norm(S.dipole()))
+                tot.append(0.5 * np.sum(m[:, None] * v ** 2) + S.energy()["E_corrected"])
+        tot = np.array(tot)
+        assert tot.max() - tot.min() <= 2e-3 * abs(tot[0]), (corrected, tot.max() - tot.min())
+        peak[corrected] = max(Pn)
+    assert peak[False] <= 1.2 * A, (peak, A)
+    assert peak[True] >= 4.0 * A, (peak, A)
