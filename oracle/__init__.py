@@ -341,3 +341,52 @@ class System:
         self.D = _f64(D).reshape(-1).copy()
         self.B = _f64(B).reshape(-1).copy()
         self.r = _f64(r).reshape(-1).copy()
+
+
+# -------------------------------------------- dielectric walls (section "Validation")
+
+def wall_image_force_z(charges, z0: float, z_lo: float, z_hi: float, eps_in: float, eps_out: float,
+                       period: float = 0.0, lateral: int = 0, n_images: int = 60) -> float:
+    """z force on the first of `charges` (a list of (q, x, y), all at height
+    z0 inside a slab z_lo < z < z_hi of permittivity eps_in between two
+    half-spaces of eps_out: the two infinite dielectric walls of the
+    thermodynamic check, Fig. 6), from the images the walls induce.
+
+    Textbook construction by repeated reflection: with Delta = (eps_in -
+    eps_out)/(eps_in + eps_out), d = z_hi - z_lo and s = z0 - z_lo, a charge q
+    has images Delta^|2m-1| q at z_lo - s + 2 m d (every integer m) and
+    Delta^(2|n|) q at z_lo + s + 2 n d (n != 0), the potential inside the slab
+    being the charges' and their images' Coulomb potentials q/(4 pi eps_in r).
+    The charges themselves, all at height z0, exert no z force on each other.
+    With period > 0 every charge repeats at (x + i period, y + j period) for
+    |i|, |j| <= lateral (a laterally periodic box); the sum runs over those
+    copies of every charge's images (for a neutral set the sheet terms of the
+    copies cancel between charges)."""
+    Delta = (eps_in - eps_out) / (eps_in + eps_out)
+    d = z_hi - z_lo
+    s = z0 - z_lo
+    q1, x1, y1 = charges[0]
+    F = 0.0
+    for (qj, xj, yj) in charges:
+        # lateral offsets of the copies of charge j seen from charge 1
+        offs = []
+        for i in range(-lateral, lateral + 1):
+            for j in range(-lateral, lateral + 1):
+                dx = xj + i * period - x1 if period > 0 else xj - x1
+                dy = yj + j * period - y1 if period > 0 else yj - y1
+                offs.append(dx * dx + dy * dy)
+                if period <= 0:
+                    break
+            if period <= 0:
+                break
+        offs = np.array(offs)
+        for m in range(-n_images, n_images + 1):
+            # the reflected images m and 1 - m (mirror pairs about the slab's
+            # centre) are kept or dropped together
+            images = [(-s + 2 * m * d, Delta ** abs(2 * m - 1))] if m > -n_images else []
+            if m != 0:
+                images.append((s + 2 * m * d, Delta ** (2 * abs(m))))
+            for zi, strength in images:
+                h = s - zi
+                F += q1 * qj * strength * h * float(np.sum((offs + h * h) ** -1.5))
+    return F / (4.0 * math.pi * eps_in)

@@ -142,3 +142,23 @@ def ewald_pair_force(box: float, q1: float, q2: float, r1, r2, eps: float = 1.0,
         if nmax > 8:
             break
     return q1 * q2 / (4 * math.pi * eps) * tot
+
+
+def slab_self_force_k_integral(q: float, s: float, d: float, eps_in: float, eps_out: float) -> float:
+    """z force on a charge q at distance s above the lower of two parallel
+    interfaces a distance d apart (eps_in between them, eps_out outside), from
+    the Fourier-Bessel form of its reflected potential: with
+    D = (eps_in - eps_out)/(eps_in + eps_out), the self energy is
+    W(s) = q^2/(8 pi eps_in) int_0^inf dk [D e^{-2ks} + D e^{-2k(d-s)} + 2 D^2 e^{-2kd}]
+           / (1 - D^2 e^{-2kd}),
+    and F = -dW/ds is integrated numerically (scipy quad), independently of any
+    image sum."""
+    from scipy.integrate import quad
+    D = (eps_in - eps_out) / (eps_in + eps_out)
+
+    def integrand(k):
+        den = 1.0 - D * D * math.exp(-2.0 * k * d)
+        return (-2.0 * k * D * math.exp(-2.0 * k * s) + 2.0 * k * D * math.exp(-2.0 * k * (d - s))) / den
+
+    val, _ = quad(integrand, 0.0, math.inf, epsabs=1e-15, epsrel=1e-12, limit=400)
+    return -q * q / (8.0 * math.pi * eps_in) * val
