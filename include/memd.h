@@ -65,6 +65,12 @@ typedef enum {
 } memd_precision;
 
 typedef enum {
+    MEMD_SELF_GREEN = 0,  /* lattice Green's-function self force, eps of the cell = harmonic mean of its
+                             12 edges (the default) */
+    MEMD_SELF_DIRECT = 1  /* direct subtraction of the self field on each of the cell's links */
+} memd_self_scheme;
+
+typedef enum {
     MEMD_EPS_UNIFORM = 0, /* eps[0]: one value everywhere */
     MEMD_EPS_SITE = 1,    /* eps[Ns]: one value per lattice site, mapped to links */
     MEMD_EPS_LINK = 2,    /* eps[3*Ns]: one value per link, component-major */
@@ -286,6 +292,25 @@ memd_status memd_set_options(memd_ctx *ctx, int fuse_deposit, int sort_every);
  * of the current state are recomputed.  Waits for the context's stream.
  * Errors: EINVAL (on not 0 or 1), EDEVICE. */
 memd_status memd_set_dipole_correction(memd_ctx *ctx, int on);
+
+/* Self-energy treatment of the forces (section "Self energy interaction").
+ * MEMD_SELF_GREEN (default): the lattice Green's-function scheme (eq. greens;
+ * phi = q G/(a eps) with one eps per cell, the harmonic mean of its 12
+ * edges): F_self = -grad of U_self = q^2 S(f)/(2 eps_cell a).
+ * MEMD_SELF_DIRECT: the direct subtraction (eq. direct-subtraction, whose
+ * printed form is garbled; reading): the ion's own linearly assigned charges
+ * produce on each link of its cell the displacement field of a homogeneous
+ * lattice (from the same Green's function, independent of eps), that field
+ * divided by the link's own permittivity is interpolated to the ion like the
+ * lattice field, and the result is subtracted.  It equals the Green's-function
+ * self force wherever the cell's 12 edges share one permittivity, and
+ * differs where the permittivity changes inside the cell.  It is not the
+ * gradient of a potential there, so the energy keeps the Green's-function
+ * U_self.  With the direct scheme every force is gathered after the step (the
+ * leapfrog's own force pass uses the Green's function).  The forces of the
+ * current state are recomputed.  Waits for the context's stream.
+ * Errors: EINVAL (unknown scheme), EDEVICE. */
+memd_status memd_set_self_scheme(memd_ctx *ctx, int scheme);
 
 /* bad_moves: displacement components rejected so far (not finite, or longer
  * than (L + 1024) a; they are taken as 0).  fused_path: 1 if the next

@@ -60,7 +60,7 @@ def _load():
         "orc_dipole": (None, [i, _P, _P, _P]),
         "orc_greens": (None, [i, _P]),
         "orc_self_sum": (None, [_P, _P, _P, _P]),
-        "orc_forces": (None, [i, d, i, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+        "orc_forces": (None, [i, d, i, _P, _P, _P, _P, _P, _P, _P, _P, i, _P, _P]),
         "orc_energy": (None, [i, d, d, d, _P, _P, _P, d, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
@@ -217,6 +217,11 @@ class System:
         # boundaries at infinity) and U_dip leaves the energy; without it, the
         # plain lattice algorithm holds the dipole moment in a harmonic well
         self.dipole_correction = True
+        # section "Self energy interaction": "green" subtracts the lattice
+        # Green's-function self force with the cell's harmonic-mean eps,
+        # "direct" the field of the ion's own assigned charges on each of
+        # its cell's links, divided by that link's eps
+        self.self_scheme = "green"
 
     # -- permittivity
     def set_eps_link(self, eps_link):
@@ -322,7 +327,7 @@ class System:
         P = self._P_for_correction()
         self.lib.orc_forces(self.L, self.a, self.n, _ptr(self.q), _ptr(self.r), _ptr(self.D),
                             _ptr(self.eta), _ptr(self.eps_cell), _ptr(self.eps_h), _ptr(self.G),
-                            _ptr(P), _ptr(F), _ptr(U))
+                            _ptr(P), 1 if self.self_scheme == "direct" else 0, _ptr(F), _ptr(U))
         self._uself = U
         return F.reshape(self.n, 3), U
 

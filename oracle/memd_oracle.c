@@ -606,6 +606,58 @@ void orc_self_sum(const double G[4], const double f[3], double *S, double dS[3])
     for (int d = 0; d < 3; ++d) dS[d] = ds[d];
 }
 
+/* Periodic lattice Green's function at an offset n with every component in
+ * {-1, 0, 1}: by cubic symmetry it depends only on how many components are
+ * nonzero (G[0..3] = G(000), G(100), G(110), G(111)). */
+static double green_near(const double G[4], const long n[3]) {
+    int k = 0;
+    for (int d = 0; d < 3; ++d) k += n[d] != 0;
+    return G[k];
+}
+
+/* Direct subtraction of the self influence (section "Self energy
+ * interaction", eq. direct-subtraction, whose printed form is garbled; the
+ * reading): the ion's own linearly assigned charges q w_m at the 8 corners
+ * c + m of its cell produce on each link (u, d) of that cell the displacement
+ * field of a homogeneous lattice,
+ *   D_self_d(u) = -(q/a^2) sum_m w_m [G(u + e_d - c - m) - G(u - c - m)]
+ * (phi = q G/(a eps) of eq. greens, D = -eps grad phi: eps drops out), and its
+ * field there is D_self/eps of that link (the permittivity of the link
+ * between the two vertices, as the equation has it).  The self force is the
+ * force interpolation of that field,
+ *   Fself_d = q sum_{4 d-links} w w eta_link D_self_d(link).
+ * With the same eps on the 12 edges this is the Green's-function self force. */
+static void self_force_direct(int L, double a, double q, const long c[3], const double f[3],
+                              const double *eta, const double G[4], double Fself[3]) {
+    size_t Ns = (size_t)L * L * L;
+    for (int d = 0; d < 3; ++d) {
+        int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+        double s = 0.0;
+        for (int o2 = 0; o2 < 2; ++o2)
+            for (int o1 = 0; o1 < 2; ++o1) {
+                long uo[3] = {0, 0, 0};  /* u - c */
+                uo[d1] = o1;
+                uo[d2] = o2;
+                double Dself = 0.0;
+                for (int m = 0; m < 8; ++m) {
+                    long mb[3] = {m & 1, (m >> 1) & 1, (m >> 2) & 1};
+                    double w = wgt((int)mb[0], f[0]) * wgt((int)mb[1], f[1]) * wgt((int)mb[2], f[2]);
+                    long nA[3], nB[3];
+                    for (int k = 0; k < 3; ++k) {
+                        nB[k] = uo[k] - mb[k];
+                        nA[k] = nB[k] + (k == d);
+                    }
+                    Dself += w * (green_near(G, nA) - green_near(G, nB));
+                }
+                Dself *= -q / (a * a);
+                long x[3] = {c[0] + uo[0], c[1] + uo[1], c[2] + uo[2]};
+                size_t l = (size_t)d * Ns + site(L, x[0], x[1], x[2]);
+                s += wgt(o1, f[d1]) * wgt(o2, f[d2]) * eta[l] * Dself;
+            }
+        Fself[d] = q * s;
+    }
+}
+
 /* Forces on the ions (eq. force without the v x B term, which the paper drops;
  * reading: the sign is F = +q E, from eq. maggs:eq:force with dA/dt = -D/eps).
  *  - lattice part: E_d = eta_d D_d on the 4 d-links of the ion's cell, with the
@@ -615,10 +667,12 @@ void orc_self_sum(const double G[4], const double f[3], double *S, double dS[3])
  *    F_self = -dU_self/dr is subtracted;
  *  - dipole correction (section "Periodicity"): the uniform mode of D equals
  *    -P/V, so the lattice field carries -P/(V eps) on every ion; adding
- *    q P_d/(V eps_h_d) removes it (metallic boundary at infinity). */
+ *    q P_d/(V eps_h_d) removes it (metallic boundary at infinity).
+ * scheme 0: the Green's-function self force; scheme 1: direct subtraction
+ * (self_force_direct).  Uself is the Green's-function self energy in both. */
 void orc_forces(int L, double a, int n, const double *q, const double *r, const double *D,
                 const double *eta, const double *eps_cell, const double eps_h[3],
-                const double G[4], const double P[3], double *F, double *Uself) {
+                const double G[4], const double P[3], int scheme, double *F, double *Uself) {
     size_t Ns = (size_t)L * L * L;
     double V = pow((double)L * a, 3);
     for (int i = 0; i < n; ++i) {
@@ -644,8 +698,10 @@ void orc_forces(int L, double a, int n, const double *q, const double *r, const 
         orc_self_sum(G, f, &S, dS);
         double pref = q[i] * q[i] / (2.0 * ec * a);
         if (Uself) Uself[i] = pref * S;
+        double Fd[3];
+        if (scheme == 1) self_force_direct(L, a, q[i], c, f, eta, G, Fd);
         for (int d = 0; d < 3; ++d) {
-            double Fself = -pref * dS[d] / a;
+            double Fself = scheme == 1 ? Fd[d] : -pref * dS[d] / a;
             F[3 * i + d] = Flat[d] - Fself + q[i] * P[d] / (V * eps_h[d]);
         }
     }

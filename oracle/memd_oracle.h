@@ -83,10 +83,11 @@ void orc_dipole(int n, const double *q, const double *r, double P[3]);
 void orc_greens(int L, double G[4]);
 /* Cell self-energy sum S(f) = sum_{v,v'} w_v w_v' G(v - v') and dS/df. */
 void orc_self_sum(const double G[4], const double f[3], double *S, double dS[3]);
-/* Corrected forces F[3n] and per-ion self energies Uself[n] (may be NULL). */
+/* Corrected forces F[3n] and per-ion self energies Uself[n] (may be NULL);
+ * scheme 0 subtracts the Green's-function self force, 1 the direct one. */
 void orc_forces(int L, double a, int n, const double *q, const double *r, const double *D,
                 const double *eta, const double *eps_cell, const double eps_h[3],
-                const double G[4], const double P[3], double *F, double *Uself);
+                const double G[4], const double P[3], int scheme, double *F, double *Uself);
 /* Energies: out = {W_E, W_B (shadow), U_self, U_dip, E_corrected}. */
 void orc_energy(int L, double a, double dt, double c, const double *eta, const double *D,
                 const double *B, double U_self, const double P[3], const double eps_h[3],

@@ -180,26 +180,33 @@ __device__ __forceinline__ void self_sum(const double *G, const double f[3], dou
 
 // Corrected force on one ion (eq. force without v x B; F = +q E):
 //   q sum_{4 d-links of the cell} w w eta_d D_d
-//   - F_self (lattice Green's-function self force, eps_cell = harmonic mean of
-//     the cell's 12 edges)
+//   - F_self: the lattice Green's-function self force with eps_cell = the
+//     harmonic mean of the cell's 12 edges, or, with direct, the direct
+//     subtraction (section "Self energy interaction"): the ion's own
+//     assigned charges produce on the cell's d-link with transverse corner
+//     offsets (o1, o2) the homogeneous-lattice field
+//       D_self = -(q/a^2) (1 - 2 f_d) X,  X = sum_{k1,k2} p1(k1) p2(k2) (G[k1+k2+1] - G[k1+k2])
+//     (p(0) = w(o; f), the charge on the link's own side of the transverse
+//     axis; p(1) = 1 - w(o; f)), and F_self_d = q sum w w eta_link D_self
 //   + q P_d / (V eps_h_d)   (dipole correction, section "Periodicity").
-// Returns the ion's self energy.
+// Returns the ion's self energy (the Green's-function form in both cases).
 template <typename T>
 __device__ __forceinline__ double force_ion(int L, size_t Ns, double a, double V, double qi,
                                             const double (&u)[3], const T *__restrict__ D,
                                             const EtaView<T> &eta, const double *G, const double *P,
-                                            const double *epsh, double (&F)[3]) {
+                                            const double *epsh, double (&F)[3], bool direct = false) {
     int c[3];
     double f[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) fold(u[d], a, L, c[d], f[d]);
     const int cp[3] = {c[0] + 1 == L ? 0 : c[0] + 1, c[1] + 1 == L ? 0 : c[1] + 1, c[2] + 1 == L ? 0 : c[2] + 1};
-    double Flat[3];
+    double Flat[3], Fdir[3];
     double etasum = 0.0;
+    const double dG0 = G[1] - G[0], dG1 = G[2] - G[1], dG2 = G[3] - G[2];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-        double s = 0.0;
+        double s = 0.0, sd = 0.0;
 #pragma unroll
         for (int o2 = 0; o2 < 2; ++o2)
 #pragma unroll
@@ -210,9 +217,16 @@ __device__ __forceinline__ double force_ion(int L, size_t Ns, double a, double V
                 const size_t off = site_index(x[0], x[1], x[2], L);
                 const double e = eta.at(d, x[2], off, L, Ns);
                 etasum += e;
-                s += lin_w(o1, f[d1]) * lin_w(o2, f[d2]) * (e * (double)D[(size_t)d * Ns + off]);
+                const double w1 = lin_w(o1, f[d1]), w2 = lin_w(o2, f[d2]);
+                s += w1 * w2 * (e * (double)D[(size_t)d * Ns + off]);
+                if (direct) {
+                    const double X = w1 * w2 * dG0 + (w1 * (1.0 - w2) + (1.0 - w1) * w2) * dG1 +
+                                     (1.0 - w1) * (1.0 - w2) * dG2;
+                    sd += w1 * w2 * e * X;
+                }
             }
         Flat[d] = qi * s;
+        Fdir[d] = -div_a(div_a(qi * qi * (1.0 - 2.0 * f[d]) * sd, a), a);
     }
     const double eps_cell = 12.0 / etasum;
     double S, dS[3];
@@ -220,7 +234,7 @@ __device__ __forceinline__ double force_ion(int L, size_t Ns, double a, double V
     const double pref = qi * qi / (2.0 * eps_cell * a);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double Fself = div_a(-pref * dS[d], a);
+        const double Fself = direct ? Fdir[d] : div_a(-pref * dS[d], a);
         F[d] = Flat[d] - Fself + qi * P[d] / (V * epsh[d]);
     }
     return pref * S;

@@ -316,6 +316,7 @@ struct IonFinishArgs {
     unsigned int tag;
     const int *dep_atomic;  // [n] by slot: the ion is left to the atomic path this step
     const double *du;       // [3n] by slot: this step's displacements
+    int self_direct;        // 1: direct self subtraction; the tiles' results (Green's function) are not used
 };
 
 template <typename T>
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(256) void k_ion_finish(IonFinishArgs<T> A) {
     const double qi = A.q[i];
     // the tile result is read with its stamp, not after it
     const double ft[3] = {A.Ft[3 * s], A.Ft[3 * s + 1], A.Ft[3 * s + 2]};
-    const bool tiled = A.fdone[s] == A.tag;
+    const bool tiled = !A.self_direct && A.fdone[s] == A.tag;
     const bool atomic_path = A.dep_atomic[s] != 0;
     double F[3] = {ft[0], ft[1], ft[2]};
     if (!tiled || atomic_path) {
@@ -335,7 +336,8 @@ __global__ __launch_bounds__(256) void k_ion_finish(IonFinishArgs<T> A) {
         if (!tiled) {
             // the dipole term is added below (x + 0 + y rounds as x + y)
             const double zero[3] = {0.0, 0.0, 0.0};
-            force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.Dcur, ev, A.scal + S_G, zero, A.scal + S_EPSH, F);
+            force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.Dcur, ev, A.scal + S_G, zero, A.scal + S_EPSH, F,
+                         A.self_direct != 0);
         }
         if (atomic_path) {
             double w[3] = {u[0], u[1], u[2]};
@@ -368,6 +370,7 @@ hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext) {
         A.tag = c->force_tag;
         A.dep_atomic = c->dep_atomic;
         A.du = c->du_slot;
+        A.self_direct = c->self_scheme == MEMD_SELF_DIRECT;
     };
     if (c->fp32) {
         IonFinishArgs<float> A;
@@ -607,6 +610,7 @@ struct ForceArgs {
     const int *order;        // optional: ion order (binned by lattice row)
     const double *dip_partials;  // optional: deposit's per-block q r sums -> P
     int dip_nblk;
+    int self_direct;  // 1: direct self subtraction
 };
 
 // Forces on every ion, one lane per ion following `order` (force_ion: the
@@ -633,7 +637,8 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs<T> A) {
     if (live) {
         const EtaView<T> ev{A.mode, A.eta_uni, A.eta_prof, A.eta_link};
         const double zero[3] = {0.0, 0.0, 0.0};
-        us = force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.D, ev, A.scal + S_G, zero, A.scal + S_EPSH, F);
+        us = force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.D, ev, A.scal + S_G, zero, A.scal + S_EPSH, F,
+                          A.self_direct != 0);
     }
     if (A.dip_partials) {
         // P summed as the dipole finaliser sums it (fin_sum)
@@ -681,6 +686,7 @@ static ForceArgs<T> force_args(memd_ctx *c, const void *D) {
     A.order = c->sorted ? nullptr : c->order;  // identity once the ions are stored in bin order
     A.dip_partials = nullptr;
     A.dip_nblk = 0;
+    A.self_direct = c->self_scheme == MEMD_SELF_DIRECT;
     return A;
 }
 

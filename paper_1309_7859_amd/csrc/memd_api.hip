@@ -305,6 +305,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     c->lf_tz = 4;
     c->sort_every = 64;
     c->dipole_correction = true;
+    c->self_scheme = MEMD_SELF_GREEN;
     c->fuse_deposit = true;
     c->hist_cap = kHistCap;
     if (hipGetDevice(&c->device) != hipSuccess) {
@@ -1081,6 +1082,15 @@ memd_status memd_set_dipole_correction(memd_ctx *c, int on) {
     c->dipole_correction = on != 0;
     CK(launch_fill(c->stream, c->scal + S_DIPW, on ? 1.0 : 0.0, 1));
     if (c->ready) CK(enqueue_dipole_forces(c));  // the current state's forces under the new setting
+    CK(hipStreamSynchronize(c->stream));
+    return MEMD_OK;
+}
+
+memd_status memd_set_self_scheme(memd_ctx *c, int scheme) {
+    CHECK_CTX(c);
+    if (scheme != MEMD_SELF_GREEN && scheme != MEMD_SELF_DIRECT) return MEMD_EINVAL;
+    c->self_scheme = scheme;
+    if (c->ready) CK(enqueue_dipole_forces(c));  // the current state's forces under the new scheme
     CK(hipStreamSynchronize(c->stream));
     return MEMD_OK;
 }

@@ -77,6 +77,7 @@ struct memd_ctx {
     bool c_fixed;
     int salt_every;
     bool dipole_correction;  // mirrors scal[S_DIPW]
+    int self_scheme;         // memd_self_scheme
     double salt_w, salt_slope, salt_floor;
     double *salt_cnt;  // FP64 [Ns]: ion counts of the salt permittivity
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmemd.so")
 
 OK, EINVAL, ENOMEM, ENONNEUTRAL, EUNSTABLE, ESTATE, ENOCONV, EDEVICE, ESIZE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 FP64, FP32_MIXED = 0, 1
+SELF_GREEN, SELF_DIRECT = 0, 1
 EPS_UNIFORM, EPS_SITE, EPS_LINK, EPS_ZSITE = 0, 1, 2, 3
 FAMILIES = {"leapfrog": 0, "deposit": 1, "forces": 2, "audit": 3, "energy": 4, "dipole": 5, "salt": 6}
 
@@ -77,6 +78,7 @@ def load():
         "memd_step_seeded": [vp, C.c_uint64, d, i],
         "memd_set_options": [vp, i, i],
         "memd_set_dipole_correction": [vp, i],
+        "memd_set_self_scheme": [vp, i],
         "memd_counters": [vp, C.POINTER(C.c_ulong), C.POINTER(i)],
         "memd_seeded_displacements": [C.c_uint64, i, i, d, vp],
         "memd_server_create": [C.POINTER(vp), C.c_size_t, i, i, d, C.c_char_p, vp],
@@ -287,6 +289,10 @@ def memd_set_dipole_correction(ctx: int, on: bool):
     _check(load().memd_set_dipole_correction(ctx, 1 if on else 0), "memd_set_dipole_correction")
 
 
+def memd_set_self_scheme(ctx: int, scheme: int):
+    _check(load().memd_set_self_scheme(ctx, int(scheme)), "memd_set_self_scheme")
+
+
 def memd_counters(ctx: int):
     b = C.c_ulong()
     f = C.c_int()
@@ -461,6 +467,9 @@ class Context:
 
     def set_dipole_correction(self, on: bool):
         memd_set_dipole_correction(self.ctx, on)
+
+    def set_self_scheme(self, scheme: int):
+        memd_set_self_scheme(self.ctx, scheme)
 
     def params_in_use(self):
         return memd_get_params(self.ctx)
