@@ -358,7 +358,7 @@ def main():
     ap.add_argument("--serve-count", type=int, default=512,
                     help="replicas in the serving stream (0 = skip the serving measurement)")
     ap.add_argument("--serve-rate", type=float, default=500.0, help="Poisson arrival rate (1/s)")
-    ap.add_argument("--serve-fp64-count", type=int, default=24,
+    ap.add_argument("--serve-fp64-count", type=int, default=512,
                     help="replicas of the same stream run one by one on the FP64 single-system path")
     args = ap.parse_args()
 

@@ -135,7 +135,7 @@ bool fused_deposit_ok(const memd_ctx *c) {
 hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout, hipEvent_t e0,
                            hipEvent_t e1, const double *disp, uint64_t seed, uint32_t t, double sigma,
                            bool with_deposit, bool need_pack, const double *dip_prev, int dip_nparts,
-                           IonMoves *moves) {
+                           IonMoves *moves, bool own_forces) {
     DepArgs P;
     const DepArgs *dp = nullptr;
     if (with_deposit) {
@@ -155,6 +155,7 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
         P.list = c->list;
         P.count = c->list_count;
         P.cap = list_cap(c);
+        P.own_forces = own_forces ? 1 : 0;
         P.fq = c->fq;
         P.ecell = c->ecell;
         P.Ft = c->Ft;

@@ -317,6 +317,7 @@ struct IonFinishArgs {
     const int *dep_atomic;  // [n] by slot: the ion is left to the atomic path this step
     const double *du;       // [3n] by slot: this step's displacements
     int self_direct;        // 1: direct self subtraction; the tiles' results (Green's function) are not used
+    int no_forces;          // 1: only the irregular deposits (the ions' own dynamics gathers the forces after)
 };
 
 template <typename T>
@@ -325,6 +326,14 @@ __global__ __launch_bounds__(256) void k_ion_finish(IonFinishArgs<T> A) {
     if (s >= A.n) return;
     const int i = A.order ? A.order[s] : s;
     const double qi = A.q[i];
+    if (A.no_forces) {
+        if (A.dep_atomic[s] != 0) {
+            double w[3] = {A.r[3 * i], A.r[3 * i + 1], A.r[3 * i + 2]};
+            const double du[3] = {A.du[3 * s], A.du[3 * s + 1], A.du[3 * s + 2]};
+            deposit_ion<T>(A.L, A.Ns, A.a, qi, w, du, A.Dnext);
+        }
+        return;
+    }
     // the tile result is read with its stamp, not after it
     const double ft[3] = {A.Ft[3 * s], A.Ft[3 * s + 1], A.Ft[3 * s + 2]};
     const bool tiled = !A.self_direct && A.fdone[s] == A.tag;
@@ -350,7 +359,7 @@ __global__ __launch_bounds__(256) void k_ion_finish(IonFinishArgs<T> A) {
     for (int d = 0; d < 3; ++d) A.F[3 * i + d] = F[d] + qi * (w * A.scal[S_P + d]) / (A.V * A.scal[S_EPSH + d]);
 }
 
-hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext) {
+hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext, bool forces) {
     const int nb = ion_blocks_x8(c->n);
     auto fill = [&](auto &A) {
         A.n = c->n;
@@ -371,6 +380,7 @@ hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext) {
         A.dep_atomic = c->dep_atomic;
         A.du = c->du_slot;
         A.self_direct = c->self_scheme == MEMD_SELF_DIRECT;
+        A.no_forces = forces ? 0 : 1;
     };
     if (c->fp32) {
         IonFinishArgs<float> A;
@@ -389,51 +399,6 @@ hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext) {
         A.eta_link = (const double *)c->eta_link;
         hipLaunchKernelGGL(k_ion_finish<double>, dim3(nb), dim3(kThreads), 0, c->stream, A);
     }
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------- ion dynamics
-
-// Half kicks of the ions' velocities with the forces of the current state,
-// v <- v + (dt/2) F / m, one or two in a row (the closing kick of a step and
-// the opening kick of the next use the same forces): one thread per ion in
-// the caller's order, so that v, the masses and the move are read and
-// written coalesced and only F is gathered (storage index iperm[ci]); with
-// disp set, also the move of the step about to run, disp = dt v, which is
-// that step's current.
-__global__ __launch_bounds__(256) void k_md_kick(int n, const int *__restrict__ iperm, const double *__restrict__ F,
-                                                 const double *__restrict__ mass, double *__restrict__ v,
-                                                 int kicks, double half_dt, double dt, double *__restrict__ disp) {
-    const int ci = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ci >= n) return;
-    const int i = iperm[ci];
-    const double m = mass[ci];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const double f = F[3 * i + d];
-        double w = v[3 * ci + d] + half_dt * f / m;
-        if (kicks == 2) w = w + half_dt * f / m;
-        v[3 * ci + d] = w;
-        if (disp) disp[3 * ci + d] = dt * w;
-    }
-}
-
-hipError_t launch_md_kick(memd_ctx *c, const int *iperm, const double *mass, double *v, int kicks, double *disp) {
-    if (c->n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_md_kick, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, iperm, c->F, mass, v,
-                       kicks, 0.5 * c->dt, c->dt, disp);
-    return hipGetLastError();
-}
-
-// iperm[perm[i]] = i: the storage index of each caller index.
-__global__ __launch_bounds__(256) void k_invert_perm(int n, const int *__restrict__ perm, int *__restrict__ iperm) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) iperm[perm[i]] = i;
-}
-
-hipError_t launch_invert_perm(memd_ctx *c, int *iperm) {
-    if (c->n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_invert_perm, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->perm, iperm);
     return hipGetLastError();
 }
 
@@ -703,6 +668,142 @@ hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials,
         A.dip_partials = dip_partials;
         A.dip_nblk = dip_nblk;
         hipLaunchKernelGGL(k_forces<double>, dim3(nb), dim3(kThreads), 0, c->stream, A);
+    }
+    return hipGetLastError();
+}
+
+// The ion side of one step of the ions' own dynamics, after the leapfrog
+// (and the finisher's irregular deposits) produced the new state: one thread
+// per ion in storage order (in bin order once binned, so the gathers of
+// neighbouring lanes share lines), caller index ci = perm[i]:
+//   - with gather, the forces of the new state (force_ion on D: lattice part,
+//     self force, dipole term with P summed, as k_forces does, from the
+//     movers' per-wavefront partials), into F; else F as it stands;
+//   - `kicks` half kicks v <- v + (dt/2) F/m (the closing kick of the step and
+//     the opening one of the next use the same forces);
+//   - with pack, the move of the next step, dt v, into disp (caller order:
+//     the plain path's deposit and a re-binning's list builder read it), and
+//     with records also, sanitised, into the ion's record of the current
+//     record set (as k_pack_ions writes it).
+template <typename T>
+struct MdIonArgs {
+    ForceArgs<T> fa;  // D, permittivity, scalars, F, order, dipole partials, scheme
+    int gather;
+    const int *perm;
+    const int *slot_of;
+    const double *mass;
+    double *v;
+    int kicks;
+    double half_dt, dt;
+    double *disp;
+    int pack;
+    int records;
+    int *dep_atomic;
+    DepOut<T> O;
+    unsigned int *bad;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_md_ions(MdIonArgs<T> M) {
+    const ForceArgs<T> &A = M.fa;
+    __shared__ double Psh[3];
+    const int slot = xcd_logical(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const bool live = slot < A.n;
+    const int i = live ? (A.order ? A.order[slot] : slot) : 0;
+    double u[3] = {0.0, 0.0, 0.0}, qi = 0.0;
+    if (live) {
+        u[0] = A.r[3 * i];
+        u[1] = A.r[3 * i + 1];
+        u[2] = A.r[3 * i + 2];
+        qi = A.q[i];
+    }
+    double F[3] = {0.0, 0.0, 0.0};
+    if (M.gather) {
+        if (live) {
+            const EtaView<T> ev{A.mode, A.eta_uni, A.eta_prof, A.eta_link};
+            const double zero[3] = {0.0, 0.0, 0.0};
+            force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.D, ev, A.scal + S_G, zero, A.scal + S_EPSH, F,
+                         A.self_direct != 0);
+        }
+        if (A.dip_partials) {
+            double s[3];
+            strided_sum<3>(A.dip_partials, A.dip_nblk, threadIdx.x, blockDim.x, s);
+            block_sum<3>(s);
+            if (threadIdx.x < 3) {
+                Psh[threadIdx.x] = s[threadIdx.x];
+                if (blockIdx.x == 0) A.scal[S_P + threadIdx.x] = s[threadIdx.x];
+            }
+        } else if (threadIdx.x < 3) {
+            Psh[threadIdx.x] = A.scal[S_P + threadIdx.x];
+        }
+        __syncthreads();
+        if (live) {
+            const double w = A.scal[S_DIPW];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                F[d] = F[d] + qi * (w * Psh[d]) / (A.V * A.scal[S_EPSH + d]);
+                A.F[3 * i + d] = F[d];
+            }
+        }
+    } else if (live) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[d] = A.F[3 * i + d];
+    }
+    if (!live) return;
+    const int ci = M.perm[i];
+    const double m = M.mass[ci];
+    double du[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double w = M.v[3 * ci + d] + M.half_dt * F[d] / m;
+        if (M.kicks == 2) w = w + M.half_dt * F[d] / m;
+        M.v[3 * ci + d] = w;
+        du[d] = M.dt * w;
+    }
+    if (M.pack) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) M.disp[3 * ci + d] = du[d];
+    }
+    if (M.records) {
+        sanitize_move(du, A.a, A.L, M.bad);
+        const int s = M.slot_of[i];
+        M.dep_atomic[s] = write_record<T>(A.L, A.a, qi, u, du, s, M.O) ? 1 : 0;
+    }
+}
+
+hipError_t launch_md_ions(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk, bool gather,
+                          const double *mass, double *v, int kicks, double *disp, bool pack, bool records) {
+    if (c->n == 0) return hipSuccess;
+    const int nb = ion_blocks_x8(c->n, 1);
+    auto fill = [&](auto &M) {
+        M.gather = gather ? 1 : 0;
+        M.fa.dip_partials = dip_partials;
+        M.fa.dip_nblk = dip_nblk;
+        M.perm = c->perm;
+        M.slot_of = c->slot;
+        M.mass = mass;
+        M.v = v;
+        M.kicks = kicks;
+        M.half_dt = 0.5 * c->dt;
+        M.dt = c->dt;
+        M.disp = disp;
+        M.pack = pack ? 1 : 0;
+        M.records = records ? 1 : 0;
+        M.dep_atomic = c->dep_atomic;
+        M.bad = c->bad_moves;
+    };
+    if (c->fp32) {
+        MdIonArgs<float> M;
+        M.fa = force_args<float>(c, D);
+        fill(M);
+        M.O = dep_out<float>(c);
+        hipLaunchKernelGGL(k_md_ions<float>, dim3(nb), dim3(kThreads), 0, c->stream, M);
+    } else {
+        MdIonArgs<double> M;
+        M.fa = force_args<double>(c, D);
+        fill(M);
+        M.O = dep_out<double>(c);
+        hipLaunchKernelGGL(k_md_ions<double>, dim3(nb), dim3(kThreads), 0, c->stream, M);
     }
     return hipGetLastError();
 }

@@ -109,6 +109,7 @@ struct DepArgs {
     // forces of the state the step starts from, for the regular ions whose
     // start cell the tile owns: lattice part and self force into Ft[slot],
     // fdone[slot] = tag (the dipole term is added by the ion finisher)
+    int own_forces;     // 0: the tiles compute no forces (the ions' own dynamics gathers them)
     const void *fq;     // [n] IonFQ<T> by slot
     const void *ecell;  // [Ns] T: 12 / (sum of eta over the cell's 12 edges)
     double *Ft;         // [3n] by slot
@@ -300,6 +301,7 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
     }
     // An ion whose start cell lies in the tile gets its force here.
     auto own_rec = [&](const int4 &h, int slot) {
+        if (!dep->own_forces) return;
         const int lxo = (h.x & 1023) - x0, lyo = ((h.x >> 10) & 1023) - y0, lzo = ((h.x >> 20) & 1023) - z0;
         if (lxo >= 0 && lxo < TX && lyo >= 0 && lyo < ext[1] && lzo >= 0 && lzo < ext[2]) {
             const int pos = atomicAdd(&DS->own_n, 1);

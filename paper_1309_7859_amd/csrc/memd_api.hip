@@ -593,9 +593,23 @@ void swap_record_sets(memd_ctx *c) {
 // the last step one force launch gives the forces of the final state, so
 // each state's forces are computed once.  Otherwise: leapfrog, the atomic
 // deposit, forces.
-memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, double sigma) {
+// One step of the ions' own dynamics hands its end over to the caller:
+// recs_ready (in): the caller wrote this step's records (k_md_ions); out:
+// whether the forces of the new state were gathered here (the plain path),
+// else the movers' dipole partials the caller's gather sums into P.
+struct MdHandoff {
+    bool recs_ready;
+    bool gathered;
+    const double *dip;
+    int nb;
+};
+
+memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, double sigma,
+                      MdHandoff *md = nullptr) {
     const size_t per = 3 * (size_t)c->n;
-    bool recs_ready = false;  // the deposit records of this step were written by the previous step's movers
+    // the deposit records of this step were written by the previous step's
+    // movers (or, for the ions' own dynamics, by the caller)
+    bool recs_ready = md && md->recs_ready;
     const double *dip_prev = nullptr;
     int dip_nb = 0;
     for (int t = 0; t < nsteps; ++t) {
@@ -624,10 +638,10 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
         hipEvent_t e0 = nullptr, e1 = nullptr;
         prof_pair(c, F_LEAPFROG, &e0, &e1);
         CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx], e0, e1, dstep, seed, tstep, sigma,
-                           fused, !recs_ready, fused ? dip_prev : nullptr, dip_nb, fused ? &mv : nullptr));
+                           fused, !recs_ready, fused ? dip_prev : nullptr, dip_nb, fused ? &mv : nullptr, !md));
         if (fused) {
             prof_begin(c, F_DEPOSIT);
-            CK(launch_ion_finish(c, c->D[c->cur], c->D[nx]));
+            CK(launch_ion_finish(c, c->D[c->cur], c->D[nx], !md));
             prof_end(c, F_DEPOSIT);
             std::swap(c->r, c->r_alt);  // the movers' positions are now the current ones
             if (pack_next) swap_record_sets(c);
@@ -661,7 +675,11 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
         }
         c->step_index = next;
     }
-    if (dip_prev) {
+    if (md) {
+        md->gathered = dip_prev == nullptr;  // the plain path gathered them after its deposit
+        md->dip = dip_prev;
+        md->nb = dip_nb;
+    } else if (dip_prev) {
         // forces (and P) of the final state
         prof_begin(c, F_FORCES);
         CK(launch_forces(c, c->D[c->cur], dip_prev, dip_nb));
@@ -714,38 +732,36 @@ memd_status memd_md_step(memd_ctx *c, double *v, const double *mass, int nsteps)
             if (!(mass[i] > 0.0) || !std::isfinite(mass[i])) return MEMD_EINVAL;
     if (!c->md_buf) {
         CK(hipStreamSynchronize(c->stream));
-        if (hipMalloc((void **)&c->md_buf, (2 * per + n) * sizeof(double) + n * sizeof(int)) != hipSuccess) {
+        if (hipMalloc((void **)&c->md_buf, (2 * per + n) * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             c->md_buf = nullptr;
             return MEMD_ENOMEM;
         }
-        c->iperm_version = c->perm_version - 1;  // not made yet
     }
     double *disp = c->md_buf;
     double *dv = v_dev ? v : c->md_buf + per;
     const double *dm = m_dev ? mass : c->md_buf + 2 * per;
-    int *iperm = (int *)(c->md_buf + 2 * per + n);
-    // the inverse of perm, remade after a re-binning or set_state changed it
-    auto kick = [&](int kicks, double *d) -> hipError_t {
-        if (c->iperm_version != c->perm_version) {
-            hipError_t e = launch_invert_perm(c, iperm);
-            if (e != hipSuccess) return e;
-            c->iperm_version = c->perm_version;
-        }
-        return launch_md_kick(c, iperm, dm, dv, kicks, d);
-    };
     if (!v_dev) CK(copy_in(c, dv, v, per * sizeof(double)));
     if (!m_dev) CK(copy_in(c, c->md_buf + 2 * per, mass, n * sizeof(double)));
+    // With the fused deposit the records of a step are written by the ion
+    // kernel that ends the step before (k_md_ions: forces of the new state,
+    // the closing half kick of the step and the opening one of the next with
+    // the same forces, the next move and its records); the step itself then
+    // runs the leapfrog (its tiles compute no forces) and the irregular
+    // deposits.  The plain path gathers the forces in the step, and the ion
+    // kernel only kicks and writes the move.
+    const bool records = fused_deposit_ok(c);
     // forces of the current state (the permittivity may have changed since
-    // the last ones were computed)
+    // the last ones were computed), the opening half kick, the first move
     CK(enqueue_dipole_forces(c));
-    // the closing half kick of a step and the opening one of the next share
-    // one launch (the same forces, applied one after the other)
-    CK(kick(1, disp));
+    CK(launch_md_ions(c, c->D[c->cur], nullptr, 0, false, dm, dv, 1, disp, true, records));
     for (int t = 0; t < nsteps; ++t) {
-        const memd_status st = run_steps(c, disp, 1, 0, 0.0);  // ends with the forces of the new state
+        MdHandoff h{records, false, nullptr, 0};
+        const memd_status st = run_steps(c, disp, 1, 0, 0.0, &h);
         if (st != MEMD_OK) return st;
-        CK(kick(t + 1 < nsteps ? 2 : 1, t + 1 < nsteps ? disp : nullptr));
+        const bool last = t + 1 == nsteps;
+        CK(launch_md_ions(c, c->D[c->cur], h.dip, h.nb, !h.gathered, dm, dv, last ? 1 : 2, disp, !last,
+                          records && !last));
     }
     if (!v_dev) CK(copy_out(c, v, dv, per * sizeof(double)));
     return MEMD_OK;

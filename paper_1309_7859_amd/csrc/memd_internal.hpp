@@ -133,9 +133,8 @@ struct memd_ctx {
     int sort_every;
     double *stage;       // FP64 staging buffer for host inputs / FP32 casts
     size_t stage_bytes;
-    double *md_buf;      // ion dynamics: the step's move [3n], staged velocities [3n] and masses [n], iperm [n] ints
+    double *md_buf;      // ion dynamics: the step's move [3n], staged velocities [3n] and masses [n]
     long perm_version;   // advanced whenever perm changes
-    long iperm_version;  // the perm_version the ion dynamics' inverse of perm was made for
 
     // reductions and audit
     double *rho;       // FP64 [Ns]: the charge assignment of the last audit
@@ -189,11 +188,13 @@ struct IonMoves {
 // values of 3): the previous step's dipole partials, which the fused kernel
 // sums into the scalars' P (null: P is already there).  moves (with the
 // deposit only; null: none): the ion movers run in the same launch.
+// own_forces: the tiles compute the forces of the ions whose start cell they
+// own (off for the ions' own dynamics, which gathers forces after the step).
 hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *Dout, void *Bout,
                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, const double *disp = nullptr,
                            uint64_t seed = 0, uint32_t t = 0, double sigma = 0.0, bool with_deposit = false,
                            bool need_pack = true, const double *dip_prev = nullptr, int dip_nparts = 0,
-                           IonMoves *moves = nullptr);
+                           IonMoves *moves = nullptr, bool own_forces = true);
 bool fused_deposit_ok(const memd_ctx *c);
 // Tiles of the current leapfrog tile shape, and the list capacity per tile.
 int list_tiles(const memd_ctx *c);
@@ -210,13 +211,16 @@ hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint
 // or gathered from Dcur at r^n, plus the dipole term with the scalars' P),
 // and the irregular ions of the current records deposited into Dnext with
 // global atomics (from r^n, still in c->r).
-hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext);
-// kicks (1 or 2) half kicks v += (dt/2) F/m (v, mass in the caller's
-// order; iperm: the storage index of each caller index); with disp, the
-// move dt v of the step about to run.
-hipError_t launch_md_kick(memd_ctx *c, const int *iperm, const double *mass, double *v, int kicks, double *disp);
-// iperm[perm[i]] = i
-hipError_t launch_invert_perm(memd_ctx *c, int *iperm);
+// forces = false: only the irregular deposits (the ions' own dynamics gathers
+// the new state's forces after the step).
+hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext, bool forces = true);
+// The ion side of a step of the ions' own dynamics (k_md_ions): the forces of
+// the state in D (gather; else c->F as it is, dip_partials unused), `kicks`
+// half kicks of v (caller order, masses too), with pack the next move dt v
+// into disp (caller order), with records also its deposit records (the
+// current set; the fused deposit only).
+hipError_t launch_md_ions(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk, bool gather,
+                          const double *mass, double *v, int kicks, double *disp, bool pack, bool records);
 hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
                                int *nblk);
 hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk);

@@ -93,3 +93,37 @@ def test_c4_full_size_parity(prec, c4_oracle):
         assert np.max(np.abs(E - Eo)) <= (1e-4 if fp32 else 1e-10) * np.max(np.abs(Eo))
     finally:
         G.close()
+
+
+def test_c4_initial_solve_at_full_size():
+    """The FP64 initial solve at 128^3 with 10^5 ions and the salt
+    permittivity (CG relaxation, 600+ iterations), checked with the oracle's
+    operators: the relaxed field is the unique minimiser of the field energy
+    over the fields that obey Gauss's law with mean D = -P/V (the paragraph
+    after the recursion; section "Periodicity"), so it is pinned at any size by
+    those three properties: the Gauss residual at round-off, the mean, and a
+    curl-free E = eta D (a max|C(eta D)| / max|eta D| within the solve's
+    tolerance, measured by the oracle)."""
+    w = W.WORKLOADS["c4"]
+    s = W.make_system(w, steps=0)
+    S = oracle.System(w.L, w.a, w.dt, 1.0, s["q"], s["r0"])
+    S.set_eps_salt()
+    S.c = W.default_c(w.a, w.dt, float(np.min(1.0 / S.eta)))
+    G = memd.Context(w.L, s["q"], s["r0"], a=w.a, dt=w.dt, c=S.c, precision=memd.FP64)
+    try:
+        G.set_salt(80.0, 15.0, 1.0, every=0)
+        st, iters, res = G.solve(1e-12)
+        assert st == memd.OK and iters > 0 and res <= 1e-12
+        D, B, r = G.state()
+        assert np.max(np.abs(B)) == 0.0
+        S.set_state(D, B, r)
+        curl = S.curl_measure()
+        gmax, _ = S.gauss_residual()
+        P = S.dipole()
+        mean = D.reshape(3, -1).mean(axis=1)
+        record("c4_solve", iterations=iters, gpu_curl=res, oracle_curl=curl, gauss=gmax)
+        assert curl <= 1.01e-12, curl
+        assert gmax <= 1e-12, gmax
+        assert np.max(np.abs(mean + P / S.V)) <= 1e-12 * max(1.0, np.max(np.abs(P / S.V)))
+    finally:
+        G.close()
