@@ -247,37 +247,6 @@ __device__ __forceinline__ double X_at(const FieldView<T> &V, int d, int i, int 
     return eta_fv(V, d, k, off) * (double)V.D[(size_t)d * V.Ns + off];
 }
 
-// W_E = 1/2 a^3 sum eta D^2 and W_B = (c^2/2) a^3 sum B (B - dt C(eta D)), per block.
-template <typename T>
-__global__ __launch_bounds__(256) void k_energy_field(FieldView<T> V, double kB, double *partials) {
-    const int L = V.L;
-    double we = 0.0, wb = 0.0;
-    for_row_chunks(L, [&](const RowChunk &rc) {
-        const int i = rc.x, j = rc.y, k = rc.z;
-        const size_t v = ((size_t)k * L + j) * L + i;
-        const int ip = (i + 1 == L) ? 0 : i + 1, jp = (j + 1 == L) ? 0 : j + 1,
-                  kp = (k + 1 == L) ? 0 : k + 1;
-        double X[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double Dd = (double)V.D[(size_t)d * V.Ns + v];
-            X[d] = eta_fv(V, d, k, v) * Dd;
-            we += X[d] * Dd;
-        }
-        const double cx = X_at(V, 2, i, jp, k) - X[2] - X_at(V, 1, i, j, kp) + X[1];
-        const double cy = X_at(V, 0, i, j, kp) - X[0] - X_at(V, 2, ip, j, k) + X[2];
-        const double cz = X_at(V, 1, ip, j, k) - X[1] - X_at(V, 0, i, jp, k) + X[0];
-        const double bx = (double)V.B[v], by = (double)V.B[V.Ns + v], bz = (double)V.B[2 * V.Ns + v];
-        wb += bx * (bx - kB * cx) + by * (by - kB * cy) + bz * (bz - kB * cz);
-    });
-    double s[2] = {we, wb};
-    block_sum<2>(s);
-    if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = s[0];
-        partials[2 * blockIdx.x + 1] = s[1];
-    }
-}
-
 template <typename T>
 static FieldView<T> make_view(memd_ctx *c, const void *D, const void *B) {
     FieldView<T> V;
@@ -295,20 +264,6 @@ static FieldView<T> make_view(memd_ctx *c, const void *D, const void *B) {
 static int site_blocks(size_t Ns) {
     size_t b = (Ns + kThreads - 1) / kThreads;
     return (int)(b < (size_t)kSiteBlocks ? b : (size_t)kSiteBlocks);
-}
-
-hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
-                               int *nblk) {
-    const int nb = site_blocks(c->Ns);
-    *nblk = nb;
-    const double kB = c->dt / c->a;
-    if (c->fp32)
-        hipLaunchKernelGGL(k_energy_field<float>, dim3(nb), dim3(kThreads), 0, c->stream,
-                           make_view<float>(c, D, B), kB, partials);
-    else
-        hipLaunchKernelGGL(k_energy_field<double>, dim3(nb), dim3(kThreads), 0, c->stream,
-                           make_view<double>(c, D, B), kB, partials);
-    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------- audit
@@ -354,8 +309,90 @@ hipError_t launch_audit_raw(hipStream_t s, const void *D, bool fp32, const doubl
     return hipGetLastError();
 }
 
-hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk) {
-    return launch_audit_raw(c->stream, D, c->fp32, c->rho, c->L, c->a, partials, nblk);
+// The observables of the current state in one pass over the lattice, per
+// block: with ENG, sum eta D^2 and sum B (B - (dt/a) C(eta D)) (W_E = 1/2 a^3
+// of the first, W_B = (c^2/2) a^3 of the second: the leapfrog's shadow form
+// B^{n+1/2} B^{n+3/2}, the later factor made here); with AUD, max |R| and
+// sum R^2 of R_v = a^2 sum_d [D_d(v) - D_d(v-e_d)] - rho_v, the audit k_audit
+// also forms.  Four partials per block (we, wb, max, sum).
+template <typename T, bool AUD, bool ENG>
+__global__ __launch_bounds__(256) void k_field_obs(FieldView<T> V, double kB, double a2, const double *__restrict__ rho,
+                                                   double *partials) {
+    const int L = V.L;
+    const size_t Ns = V.Ns;
+    double we = 0.0, wb = 0.0, mx = 0.0, ss = 0.0;
+    for_row_chunks(L, [&](const RowChunk &rc) {
+        const int i = rc.x, j = rc.y, k = rc.z;
+        const size_t v = ((size_t)k * L + j) * L + i;
+        double Dv[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Dv[d] = (double)V.D[(size_t)d * Ns + v];
+        if constexpr (ENG) {
+            const int ip = (i + 1 == L) ? 0 : i + 1, jp = (j + 1 == L) ? 0 : j + 1,
+                      kp = (k + 1 == L) ? 0 : k + 1;
+            double X[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                X[d] = eta_fv(V, d, k, v) * Dv[d];
+                we += X[d] * Dv[d];
+            }
+            const double cx = X_at(V, 2, i, jp, k) - X[2] - X_at(V, 1, i, j, kp) + X[1];
+            const double cy = X_at(V, 0, i, j, kp) - X[0] - X_at(V, 2, ip, j, k) + X[2];
+            const double cz = X_at(V, 1, ip, j, k) - X[1] - X_at(V, 0, i, jp, k) + X[0];
+            const double bx = (double)V.B[v], by = (double)V.B[Ns + v], bz = (double)V.B[2 * Ns + v];
+            wb += bx * (bx - kB * cx) + by * (by - kB * cy) + bz * (bz - kB * cz);
+        }
+        if constexpr (AUD) {
+            const size_t vx = site_index(i == 0 ? L - 1 : i - 1, j, k, L);
+            const size_t vy = site_index(i, j == 0 ? L - 1 : j - 1, k, L);
+            const size_t vz = site_index(i, j, k == 0 ? L - 1 : k - 1, L);
+            const double dv = (Dv[0] - (double)V.D[vx]) + (Dv[1] - (double)V.D[Ns + vy]) +
+                              (Dv[2] - (double)V.D[2 * Ns + vz]);
+            const double R = a2 * dv - rho[v];
+            mx = fmax(mx, fabs(R));
+            ss += R * R;
+        }
+    });
+    double s[3] = {we, wb, ss};
+    block_sum<3>(s);
+    const double m = block_max(mx);
+    if (threadIdx.x == 0) {
+        partials[4 * blockIdx.x] = s[0];
+        partials[4 * blockIdx.x + 1] = s[1];
+        partials[4 * blockIdx.x + 2] = m;
+        partials[4 * blockIdx.x + 3] = s[2];
+    }
+}
+
+hipError_t launch_field_obs(memd_ctx *c, bool audit, bool energy, double *partials, int *nblk) {
+    const int nb = site_blocks(c->Ns);
+    *nblk = nb;
+    const double kB = c->dt / c->a, a2 = c->a * c->a;
+    const void *D = c->D[c->cur], *B = c->B[c->cur];
+    if (c->fp32) {
+        const auto V = make_view<float>(c, D, B);
+        if (audit && energy)
+            hipLaunchKernelGGL((k_field_obs<float, true, true>), dim3(nb), dim3(kThreads), 0, c->stream, V, kB, a2,
+                               c->rho, partials);
+        else if (audit)
+            hipLaunchKernelGGL((k_field_obs<float, true, false>), dim3(nb), dim3(kThreads), 0, c->stream, V, kB, a2,
+                               c->rho, partials);
+        else
+            hipLaunchKernelGGL((k_field_obs<float, false, true>), dim3(nb), dim3(kThreads), 0, c->stream, V, kB, a2,
+                               c->rho, partials);
+    } else {
+        const auto V = make_view<double>(c, D, B);
+        if (audit && energy)
+            hipLaunchKernelGGL((k_field_obs<double, true, true>), dim3(nb), dim3(kThreads), 0, c->stream, V, kB, a2,
+                               c->rho, partials);
+        else if (audit)
+            hipLaunchKernelGGL((k_field_obs<double, true, false>), dim3(nb), dim3(kThreads), 0, c->stream, V, kB, a2,
+                               c->rho, partials);
+        else
+            hipLaunchKernelGGL((k_field_obs<double, false, true>), dim3(nb), dim3(kThreads), 0, c->stream, V, kB, a2,
+                               c->rho, partials);
+    }
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ casts

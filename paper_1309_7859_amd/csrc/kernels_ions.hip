@@ -1039,22 +1039,62 @@ hipError_t launch_bin_ions(memd_ctx *c, bool reorder) {
     return hipGetLastError();
 }
 
-// Self energies (through the force kernel, writing the same forces again).
+// Self energies U_i = q_i^2 S(f_i) / (2 eps_cell a) (section "Self energy
+// interaction"), eps_cell = 12 / (sum of eta over the cell's 12 edges), with
+// the arithmetic of force_ion but no field read; one partial per block, the
+// ions of a block as k_forces groups them in index order (so the sum is
+// deterministic).
+template <typename T>
+__global__ __launch_bounds__(256) void k_uself(int n, int L, size_t Ns, double a, const double *__restrict__ q,
+                                               const double *__restrict__ r, EtaView<T> eta, const double *G,
+                                               double *partials) {
+    const int i = xcd_logical(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    double us = 0.0;
+    if (i < n) {
+        const double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
+        const double qi = q[i];
+        int c[3];
+        double f[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fold(u[d], a, L, c[d], f[d]);
+        const int cp[3] = {c[0] + 1 == L ? 0 : c[0] + 1, c[1] + 1 == L ? 0 : c[1] + 1, c[2] + 1 == L ? 0 : c[2] + 1};
+        double etasum = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+#pragma unroll
+            for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                for (int o1 = 0; o1 < 2; ++o1) {
+                    int x[3] = {c[0], c[1], c[2]};
+                    x[d1] = o1 ? cp[d1] : c[d1];
+                    x[d2] = o2 ? cp[d2] : c[d2];
+                    etasum += eta.at(d, x[2], site_index(x[0], x[1], x[2], L), L, Ns);
+                }
+        }
+        const double eps_cell = 12.0 / etasum;
+        double S, dS[3];
+        self_sum(G, f, S, dS);
+        us = qi * qi / (2.0 * eps_cell * a) * S;
+    }
+    double v[1] = {us};
+    block_sum<1>(v);
+    if (threadIdx.x == 0) partials[blockIdx.x] = v[0];
+}
+
 hipError_t launch_uself(memd_ctx *c, double *partials, int *nblk) {
     const int nb = ion_blocks_x8(c->n, 1);
     *nblk = nb;
-    const void *D = c->D[c->cur];
-    if (c->fp32) {
-        auto A = force_args<float>(c, D);
-        A.uself_partials = partials;
-        A.order = nullptr;  // index order: the self-energy sum is then deterministic
-        hipLaunchKernelGGL(k_forces<float>, dim3(nb), dim3(kThreads), 0, c->stream, A);
-    } else {
-        auto A = force_args<double>(c, D);
-        A.uself_partials = partials;
-        A.order = nullptr;
-        hipLaunchKernelGGL(k_forces<double>, dim3(nb), dim3(kThreads), 0, c->stream, A);
-    }
+    if (c->fp32)
+        hipLaunchKernelGGL(k_uself<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a, c->q,
+                           c->r, EtaView<float>{c->eta_mode, c->eta_uni, (const float *)c->eta_prof,
+                                                (const float *)c->eta_link},
+                           c->scal + S_G, partials);
+    else
+        hipLaunchKernelGGL(k_uself<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a, c->q,
+                           c->r, EtaView<double>{c->eta_mode, c->eta_uni, (const double *)c->eta_prof,
+                                                 (const double *)c->eta_link},
+                           c->scal + S_G, partials);
     return hipGetLastError();
 }
 
@@ -1131,31 +1171,64 @@ hipError_t launch_finalize_audit(hipStream_t s, const double *partials, int nblk
     return hipGetLastError();
 }
 
-__global__ void k_fin_energy(const double *fpart, int fblk, const double *ipart, int iblk, double a3,
-                             double c2, double V, const double *scal, double *dst, double *hist) {
-    double s[2];
-    fin_sum<2>(fpart, fblk, s);
-    double u[1];
-    fin_sum<1>(ipart, iblk, u);
-    if (threadIdx.x == 0) {
+// Finaliser of the observables (one block): from the field pass's partials
+// (we, wb, max|R|, sum R^2 per block), the self-energy partials and, when
+// given, the movers' dipole partials (P is then stored too): the audit
+// (max, rms) and the five energies, each into the scalars and its history
+// slot when asked for.  The sums run in a fixed order (that of k_fin_audit
+// for the audit), so results repeat bit for bit.
+__global__ void k_fin_obs(const double *fpart, int fblk, const double *ipart, int iblk, const double *dip, int dipn,
+                          int audit, int energy, double Ns, double a3, double c2, double V, double *scal,
+                          double *audit_hist, double *energy_hist) {
+    double f[4];
+    strided_fold<4>(fpart, fblk, threadIdx.x, blockDim.x, 4u, f);  // sums, max of column 2
+    double s[3] = {f[0], f[1], f[3]};
+    block_sum<3>(s);
+    const double m = block_max(f[2]);
+    double u[1] = {0.0}, P[3] = {0.0, 0.0, 0.0};
+    if (energy) {
+        fin_sum<1>(ipart, iblk, u);
+        if (dip) fin_sum<3>(dip, dipn, P);
+    }
+    if (threadIdx.x != 0) return;
+    if (audit) {
+        scal[S_AUDIT] = m;
+        scal[S_AUDIT + 1] = sqrt(s[2] / Ns);
+        if (audit_hist) {
+            audit_hist[0] = m;
+            audit_hist[1] = scal[S_AUDIT + 1];
+        }
+    }
+    if (energy) {
+        if (dip) {
+            scal[S_P] = P[0];
+            scal[S_P + 1] = P[1];
+            scal[S_P + 2] = P[2];
+        } else {
+            P[0] = scal[S_P];
+            P[1] = scal[S_P + 1];
+            P[2] = scal[S_P + 2];
+        }
         const double we = 0.5 * a3 * s[0];
         const double wb = 0.5 * c2 * a3 * s[1];
         double ud = 0.0;  // U_dip, removed from the energy only with the dipole correction
-        for (int d = 0; d < 3; ++d) ud += scal[S_P + d] * scal[S_P + d] / (2.0 * V * scal[S_EPSH + d]);
+        for (int d = 0; d < 3; ++d) ud += P[d] * P[d] / (2.0 * V * scal[S_EPSH + d]);
         ud *= scal[S_DIPW];
         const double e[5] = {we, wb, u[0], ud, we + wb - u[0] - ud};
         for (int t = 0; t < 5; ++t) {
-            dst[t] = e[t];
-            if (hist) hist[t] = e[t];
+            scal[S_ENERGY + t] = e[t];
+            if (energy_hist) energy_hist[t] = e[t];
         }
     }
 }
 
-hipError_t launch_finalize_energy(memd_ctx *c, const double *fpart, int fblk, const double *ipart, int iblk,
-                                  double *dst, double *hist) {
+hipError_t launch_finalize_obs(memd_ctx *c, const double *fpart, int fblk, const double *ipart, int iblk,
+                               const double *dip, int dipn, bool audit, bool energy, double *audit_hist,
+                               double *energy_hist) {
     const double a3 = c->a * c->a * c->a;
-    hipLaunchKernelGGL(k_fin_energy, dim3(1), dim3(kThreads), 0, c->stream, fpart, fblk, ipart, iblk, a3,
-                       c->c * c->c, c->V, c->scal, dst, hist);
+    hipLaunchKernelGGL(k_fin_obs, dim3(1), dim3(kThreads), 0, c->stream, fpart, fblk, ipart, iblk, dip, dipn,
+                       audit ? 1 : 0, energy ? 1 : 0, (double)c->Ns, a3, c->c * c->c, c->V, c->scal, audit_hist,
+                       energy_hist);
     return hipGetLastError();
 }
 

@@ -206,27 +206,23 @@ memd_status ensure_eta_link(memd_ctx *c) {
 }
 
 // Energy of the current state into dst (and hist when given).
-hipError_t enqueue_energy(memd_ctx *c, double *dst, double *hist) {
+// The Gauss audit and/or the energies of the current state: the charge
+// assignment (for the audit), one pass over the lattice for both, the self
+// energies (for the energy), one finaliser; results in the scalars (S_AUDIT,
+// S_ENERGY) and in the history slots when given.  dip (nparts partials):
+// the movers' dipole partials of the state, summed into P by the finaliser;
+// null: P is in the scalars already.
+hipError_t enqueue_observables(memd_ctx *c, bool audit, bool energy, double *audit_hist, double *energy_hist,
+                               const double *dip = nullptr, int dipn = 0) {
     hipError_t e;
     int fb = 0, ib = 0;
-    prof_begin(c, F_ENERGY);
-    if ((e = launch_energy_field(c, c->D[c->cur], c->B[c->cur], c->partials, &fb)) != hipSuccess) return e;
-    if ((e = launch_uself(c, ion_partials(c), &ib)) != hipSuccess) return e;
-    e = launch_finalize_energy(c, c->partials, fb, ion_partials(c), ib, dst, hist);
-    prof_end(c, F_ENERGY);
-    return e;
-}
-
-// Gauss audit of the current state (rho <- the charge assignment, then the
-// residual).
-hipError_t enqueue_audit(memd_ctx *c, double *hist) {
-    hipError_t e;
-    int nb = 0;
-    prof_begin(c, F_AUDIT);
-    if ((e = launch_spread_dense(c, true, c->rho)) != hipSuccess) return e;
-    if ((e = launch_audit(c, c->D[c->cur], c->partials, &nb)) != hipSuccess) return e;
-    e = launch_finalize_audit(c->stream, c->partials, nb, (double)c->Ns, c->scal + S_AUDIT, hist);
-    prof_end(c, F_AUDIT);
+    prof_begin(c, audit ? F_AUDIT : F_ENERGY);
+    if (audit && (e = launch_spread_dense(c, true, c->rho)) != hipSuccess) return e;
+    if ((e = launch_field_obs(c, audit, energy, c->partials, &fb)) != hipSuccess) return e;
+    if (energy && (e = launch_uself(c, ion_partials(c), &ib)) != hipSuccess) return e;
+    e = launch_finalize_obs(c, c->partials, fb, ion_partials(c), ib, dip, dipn, audit, energy, audit_hist,
+                            energy_hist);
+    prof_end(c, audit ? F_AUDIT : F_ENERGY);
     return e;
 }
 
@@ -649,8 +645,6 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
             dip_prev = mv.dip_out;
             dip_nb = mv.nparts;
             c->cur = nx;
-            if (energy_now)  // U_dip and the self-energy pass read P of this state
-                CK(launch_finalize_dipole(c->stream, dip_prev, dip_nb, c->scal + S_P));
         } else {
             prof_begin(c, F_DEPOSIT);
             CK(launch_deposit(c, c->D[nx], dstep, c->partials, &nb, seed, tstep, sigma));
@@ -663,15 +657,21 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
             prof_end(c, F_FORCES);
             dip_prev = nullptr;
         }
-        if (audit_now) {
-            const int slot = c->hist_audit_n < c->hist_cap ? c->hist_audit_n : c->hist_cap - 1;
-            CK(enqueue_audit(c, c->hist_audit + 2 * (size_t)slot));
-            if (c->hist_audit_n < c->hist_cap) ++c->hist_audit_n;
-        }
-        if (energy_now) {
-            const int slot = c->hist_energy_n < c->hist_cap ? c->hist_energy_n : c->hist_cap - 1;
-            CK(enqueue_energy(c, c->scal + S_ENERGY, c->hist_energy + 5 * (size_t)slot));
-            if (c->hist_energy_n < c->hist_cap) ++c->hist_energy_n;
+        if (audit_now || energy_now) {
+            double *ah = nullptr, *eh = nullptr;
+            if (audit_now) {
+                const int slot = c->hist_audit_n < c->hist_cap ? c->hist_audit_n : c->hist_cap - 1;
+                ah = c->hist_audit + 2 * (size_t)slot;
+                if (c->hist_audit_n < c->hist_cap) ++c->hist_audit_n;
+            }
+            if (energy_now) {
+                const int slot = c->hist_energy_n < c->hist_cap ? c->hist_energy_n : c->hist_cap - 1;
+                eh = c->hist_energy + 5 * (size_t)slot;
+                if (c->hist_energy_n < c->hist_cap) ++c->hist_energy_n;
+            }
+            // with the fused deposit, P of this state is in the movers' partials
+            CK(enqueue_observables(c, audit_now, energy_now, ah, eh, energy_now ? dip_prev : nullptr,
+                                   energy_now ? dip_nb : 0));
         }
         c->step_index = next;
     }
@@ -798,7 +798,7 @@ memd_status memd_forces(memd_ctx *c, double *F_out) {
 memd_status memd_energy(memd_ctx *c, memd_energy_t *out) {
     CHECK_CTX(c);
     if (!out) return MEMD_EINVAL;
-    CK(enqueue_energy(c, c->scal + S_ENERGY, nullptr));
+    CK(enqueue_observables(c, false, true, nullptr, nullptr));
     double h[5];
     CK(copy_out(c, h, c->scal + S_ENERGY, 5 * sizeof(double)));
     out->W_E = h[0];
@@ -811,7 +811,7 @@ memd_status memd_energy(memd_ctx *c, memd_energy_t *out) {
 
 memd_status memd_gauss_residual(memd_ctx *c, double *max_abs, double *rms) {
     CHECK_CTX(c);
-    CK(enqueue_audit(c, nullptr));
+    CK(enqueue_observables(c, true, false, nullptr, nullptr));
     double h[2];
     CK(copy_out(c, h, c->scal + S_AUDIT, 2 * sizeof(double)));
     if (max_abs) *max_abs = h[0];

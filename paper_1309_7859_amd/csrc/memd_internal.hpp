@@ -221,9 +221,9 @@ hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext, bool fo
 // current set; the fused deposit only).
 hipError_t launch_md_ions(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk, bool gather,
                           const double *mass, double *v, int kicks, double *disp, bool pack, bool records);
-hipError_t launch_energy_field(memd_ctx *c, const void *D, const void *B, double *partials,
-                               int *nblk);
-hipError_t launch_audit(memd_ctx *c, const void *D, double *partials, int *nblk);
+// Energy and/or audit of the current state in one pass over the lattice
+// (the audit reads c->rho): partials[4 nblk] = (we, wb, max |R|, sum R^2).
+hipError_t launch_field_obs(memd_ctx *c, bool audit, bool energy, double *partials, int *nblk);
 // The audit's site pass on any buffers: partials[2 * nblk] (max |R|, sum R^2
 // per block) of R_v = a^2 div D(v) - rho_v; nblk <= kSiteBlocks.
 hipError_t launch_audit_raw(hipStream_t s, const void *D, bool fp32, const double *rho, int L, double a,
@@ -265,11 +265,15 @@ hipError_t launch_finalize_sum(hipStream_t s, const double *partials, int nblk, 
 // Audit finaliser: partials hold (max, sumsq) per block -> dst = (max, rms); also appends.
 hipError_t launch_finalize_audit(hipStream_t s, const double *partials, int nblk, double Ns,
                                  double *dst, double *hist);
-// Energy finaliser: field partials (we, wb) + ion partials (uself) -> 5 energies.
-hipError_t launch_finalize_energy(memd_ctx *c, const double *fpart, int fblk,
-                                  const double *ipart, int iblk, double *dst, double *hist);
 hipError_t launch_finalize_dipole(hipStream_t s, const double *partials, int nblk,
                                   double *P);
+// Audit and/or energy from launch_field_obs's partials (4 per block), the
+// self-energy partials and (null: P in the scalars) the movers' dipole
+// partials; results into the scalars (S_AUDIT, S_ENERGY, S_P) and the
+// history slots when given.
+hipError_t launch_finalize_obs(memd_ctx *c, const double *fpart, int fblk, const double *ipart, int iblk,
+                               const double *dip, int dipn, bool audit, bool energy, double *audit_hist,
+                               double *energy_hist);
 hipError_t launch_finalize_epsh(hipStream_t s, const double *partials, int nblk, double Ns,
                                 double *epsh, double *etamax);
 hipError_t launch_greens(memd_ctx *c, double *G);
