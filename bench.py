@@ -341,9 +341,9 @@ def main():
     ap.add_argument("--fp64", type=int, default=1,
                     help="1: run the FP64 variant over the same trajectory and report the FP32 "
                          "path's error on each output against it (0 = skip)")
-    ap.add_argument("--cpu-steps", type=int, default=10,
+    ap.add_argument("--cpu-steps", type=int, default=30,
                     help="oracle sample: steps per timed run with all threads (0 = skip)")
-    ap.add_argument("--cpu-single-steps", type=int, default=1,
+    ap.add_argument("--cpu-single-steps", type=int, default=2,
                     help="oracle sample: steps per timed run with one thread")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
