@@ -102,7 +102,8 @@ typedef struct {
  * solution of Gauss's law, then its propagation).  q[n] charges, r0[3n]
  * unfolded positions.  hip_stream: a hipStream_t, or NULL for a stream of the
  * library's own.  The permittivity starts uniform, eps = 1.
- * Errors: EINVAL (bad params or pointers, n < 0), ENONNEUTRAL, ENOMEM, EDEVICE. */
+ * Errors: EINVAL (bad params or pointers, n < 0, a position not finite or
+ * beyond 2^40 L a in magnitude), ENONNEUTRAL, ENOMEM, EDEVICE. */
 memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n_ions,
                               const double *q, const double *r0, void *hip_stream);
 
@@ -246,7 +247,9 @@ memd_status memd_history(memd_ctx *ctx, double *audit, double *energy, int max_e
 
 /* Copy the state out / in: D[3*Ns], B[3*Ns] (B at the last half step), r[3n].
  * memd_set_state also marks the context ready to step (it replaces the
- * initial solve).  Any of the three may be NULL to skip it. */
+ * initial solve).  Any of the three may be NULL to skip it.  memd_set_state
+ * returns EINVAL, changing nothing, when a position is not finite or beyond
+ * 2^40 L a in magnitude. */
 memd_status memd_get_state(memd_ctx *ctx, double *D, double *B, double *r);
 memd_status memd_set_state(memd_ctx *ctx, const double *D, const double *B, const double *r);
 
@@ -337,13 +340,16 @@ int memd_version(void);
  * memd_server_progress admits queued requests while the device-memory budget
  * (resident buffers plus the FP64 solver's work vectors) and the slot count
  * allow, initialises them on worker threads (own streams: context,
- * permittivity, FP64 initial solve to solve_tol, leapfrog tile autotune with
- * the cache file tune_cache), joins initialised replicas to the device-resident
- * replica table, replays the captured step graph `global_steps` times (every
- * resident replica advances one step per replay), and retires finished
- * replicas (forces, energies and Gauss residual kept for memd_server_poll;
- * device memory returned).  Times are seconds since memd_server_create.
- * Not thread-safe: one caller drives a server. */
+ * permittivity, FP64 initial solve to solve_tol), joins initialised replicas
+ * to the device-resident replica table, replays the captured step graph
+ * `global_steps` times (every resident replica advances one step per replay:
+ * two launches, the batched leapfrog and the batched deposit), and retires
+ * finished replicas (forces, energies and Gauss residual of the final state
+ * kept for memd_server_poll; device memory returned).  Times are seconds since
+ * memd_server_create.  memd_server_create tunes the batched leapfrog's tile
+ * depth on a synthetic batch of up to 16 lattices of 64^3 sites (about 200 MB
+ * for a moment, fewer lattices under a smaller budget), or reads it from the
+ * cache file tune_cache.  Not thread-safe: one caller drives a server. */
 typedef struct memd_server memd_server;
 
 typedef enum {

@@ -27,8 +27,10 @@ __device__ __forceinline__ double div_a(double x, double a) {
 // k mod L in [0, L) for an integer-valued double k with |k| < 2^51 L: the
 // quotient's floor comes from k * (1/L), is off by at most one, and one
 // correction fixes it; k - L q is then exact.  (No 64-bit integer division,
-// which is a long software sequence on the GPU.)  The final clamp never
-// changes a correct result.
+// which is a long software sequence on the GPU.)  The bound on |k| holds by
+// construction: positions are rejected at entry beyond 2^40 box lengths and
+// displacements beyond one box length per step.  The final clamp only keeps
+// an index in bounds and never changes a result inside that range.
 __device__ __forceinline__ int mod_cell(double k, int L) {
     const double Ld = (double)L;
     double m = k - Ld * floor(k * (1.0 / Ld));

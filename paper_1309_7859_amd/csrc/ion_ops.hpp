@@ -107,7 +107,6 @@ __device__ __forceinline__ void deposit_ion_part(int L, size_t Ns, double a, dou
             double f1, f2;
             fold(u[d1], a, L, c1, f1);
             fold(u[d2], a, L, c2, f2);
-            const double w = lin_w(o1, f1) * lin_w(o2, f2);
             const int x1 = o1 ? (c1 + 1 == L ? 0 : c1 + 1) : c1;
             const int x2 = o2 ? (c2 + 1 == L ? 0 : c2 + 1) : c2;
             const double lo = u0 < u1 ? u0 : u1, hi = u0 < u1 ? u1 : u0;
@@ -126,7 +125,6 @@ __device__ __forceinline__ void deposit_ion_part(int L, size_t Ns, double a, dou
                 x[d1] = x1;
                 x[d2] = x2;
                 const double val = amount * lin_w(o1, f1) * lin_w(o2, f2);
-                (void)w;
                 unsafeAtomicAdd(&D[(size_t)d * Ns + site_index(x[0], x[1], x[2], L)], (T)(-val));
             }
         }

@@ -1,5 +1,5 @@
 // kernels_batch.hip -- one global step of many independent MEMD replicas
-// (different L, ion counts, permittivity profiles) in four launches with
+// (different L, ion counts, permittivity profiles) in two launches with
 // fixed grids.  The replica table lives in device memory and may change
 // between launches (replicas join and leave) without re-capturing the graph
 // that holds the launches: every workgroup walks the work items (leapfrog
@@ -7,6 +7,13 @@
 // owner replica by binary search over the item offsets, and skips replicas
 // that have finished.  Fields are FP32; positions, dipole and the ion
 // arithmetic are FP64; displacements come from the replica's Philox stream.
+//
+// Step counters (two ints per replica, no launch of their own): the deposit
+// launch writes done = s + 1 after the step s it deposits; the leapfrog
+// launch reads done and copies it to seen, which the deposit launch reads
+// (it cannot read the counter it writes: its workgroups run in any order).
+// The forces and energy of a replica's final state are computed when it
+// leaves the batch, on its own context's stream.
 #include "device_util.hpp"
 #include "ion_ops.hpp"
 #include "leapfrog_tile.hpp"
@@ -22,7 +29,7 @@ namespace memd {
 extern __shared__ int s_off[];
 
 __device__ __forceinline__ int stage_index(const int *__restrict__ hdr, int range) {
-    const int count = hdr[0], max_slots = hdr[3];
+    const int count = hdr[0], max_slots = hdr[2];
     const int *src = hdr + kHdrInts + range * max_slots;
     for (int t = threadIdx.x; t < count; t += blockDim.x) s_off[t] = src[t];
     __syncthreads();
@@ -39,7 +46,6 @@ __device__ __forceinline__ int find_rep(int count, int item) {
     return lo;
 }
 
-
 __global__ __launch_bounds__(256) void k_batch_leapfrog(const RepDesc *__restrict__ tab,
                                                         const int *__restrict__ hdr) {
     __shared__ LfSmem<float, 1> U;
@@ -48,7 +54,8 @@ __global__ __launch_bounds__(256) void k_batch_leapfrog(const RepDesc *__restric
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int ri = find_rep(count, item);
         const RepDesc &R = tab[ri];
-        const int step = *R.step;
+        const int step = R.steps[1];
+        if (threadIdx.x == 0) R.steps[0] = step;  // every item of the replica stores the same value
         if (step >= R.nsteps) continue;
         const int local = item - R.tile_off;
         const int tile_x = local % R.ntx;
@@ -81,108 +88,50 @@ __global__ __launch_bounds__(256) void k_batch_leapfrog(const RepDesc *__restric
 // global atomics: an item is 16 ions, 16 lanes per ion (deposit_ion_part: one
 // axis and transverse corner each), so that a replica's ions spread over many
 // workgroups; lanes 0-2 of each ion draw the displacement's components, lane
-// 0 writes r^{n+1}.
-// One partial of q r^{n+1} per item.
+// 0 writes r^{n+1}.  Every item of a replica then stores the replica's new
+// step count.
 __global__ __launch_bounds__(256) void k_batch_deposit(const RepDesc *__restrict__ tab,
                                                        const int *__restrict__ hdr) {
-    const int total = hdr[4];
+    const int total = hdr[3];
     const int count = stage_index(hdr, RANGE_DEP);
     const int lane = threadIdx.x & 15;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int ri = find_rep(count, item);
         const RepDesc &R = tab[ri];
-        const int step = *R.step;
+        const int step = R.steps[0];
         if (step >= R.nsteps) continue;
-        const int b = item - R.dep_off;
-        const int i = b * kDepIons + (int)(threadIdx.x >> 4);
-        double P[3] = {0.0, 0.0, 0.0};
+        const int i = (item - R.dep_off) * kDepIons + (int)(threadIdx.x >> 4);
         if (i < R.n) {
             const size_t Ns = (size_t)R.L * R.L * R.L;
             double u[3] = {R.r[3 * i], R.r[3 * i + 1], R.r[3 * i + 2]};
             // lanes 0-2 draw one component each
-            const double dc = lane < 3 ? philox_displacement_component(R.seed, (uint32_t)step, (uint32_t)i, R.sigma,
-                                                                       lane)
-                                       : 0.0;
+            const double dc =
+                lane < 3 ? philox_displacement_component(R.seed, (uint32_t)step, (uint32_t)i, R.sigma, lane) : 0.0;
             double du[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) du[d] = __shfl(dc, d, 16);
             sanitize_move(du, R.a, R.L, nullptr);
-            const double qi = R.q[i];
-            deposit_ion_part<float>(R.L, Ns, R.a, qi, u, du, R.D[(step & 1) ^ 1], lane >> 2, lane & 3);
+            deposit_ion_part<float>(R.L, Ns, R.a, R.q[i], u, du, R.D[(step & 1) ^ 1], lane >> 2, lane & 3);
             if (lane == 0) {
                 R.r[3 * i] = u[0];
                 R.r[3 * i + 1] = u[1];
                 R.r[3 * i + 2] = u[2];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) P[d] = qi * u[d];
             }
         }
-        block_sum<3>(P);
-        if (threadIdx.x == 0) {
-            R.dip[3 * b] = P[0];
-            R.dip[3 * b + 1] = P[1];
-            R.dip[3 * b + 2] = P[2];
-        }
-        __syncthreads();
+        if (threadIdx.x == 0) R.steps[1] = step + 1;
     }
 }
 
-__global__ __launch_bounds__(256) void k_batch_forces(const RepDesc *__restrict__ tab,
-                                                      const int *__restrict__ hdr) {
-    __shared__ double Psh[3];
-    const int total = hdr[2];
-    const int count = stage_index(hdr, RANGE_IONS);
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int ri = find_rep(count, item);
-        const RepDesc &R = tab[ri];
-        const int step = *R.step;
-        if (step >= R.nsteps) continue;
-        const int b = item - R.ion_off;
-        double s[3] = {0.0, 0.0, 0.0};
-        for (int k = threadIdx.x; k < R.dblocks; k += blockDim.x)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) s[d] += R.dip[3 * k + d];
-        block_sum<3>(s);
-        if (threadIdx.x == 0) {
-            const double w = R.scal[S_DIPW];  // 1, or 0 without the dipole correction
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                Psh[d] = w * s[d];
-                if (b == 0) R.scal[S_P + d] = s[d];
-            }
-        }
-        __syncthreads();
-        const int i = b * blockDim.x + threadIdx.x;
-        if (i < R.n) {
-            const size_t Ns = (size_t)R.L * R.L * R.L;
-            const double u[3] = {R.r[3 * i], R.r[3 * i + 1], R.r[3 * i + 2]};
-            EtaView<float> ev{R.eta_mode, (double)R.eta_uni, R.eta_prof, nullptr};
-            double F[3];
-            force_ion<float>(R.L, Ns, R.a, R.V, R.q[i], u, R.D[(step & 1) ^ 1], ev, R.scal + S_G, Psh,
-                             R.scal + S_EPSH, F);
-            R.F[3 * i] = F[0];
-            R.F[3 * i + 1] = F[1];
-            R.F[3 * i + 2] = F[2];
-        }
-        __syncthreads();
-    }
-}
-
-__global__ void k_batch_advance(const RepDesc *__restrict__ tab, const int *__restrict__ hdr) {
-    const int count = hdr[0];
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < count; r += gridDim.x * blockDim.x) {
-        int *st = tab[r].step;
-        if (*st < tab[r].nsteps) *st += 1;
-    }
+hipError_t launch_batch_leapfrog(hipStream_t s, const RepDesc *tab, const int *hdr, int max_slots, int grid) {
+    hipLaunchKernelGGL(k_batch_leapfrog, dim3(grid), dim3(256), (size_t)max_slots * sizeof(int), s, tab, hdr);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_step(hipStream_t s, const RepDesc *tab, const int *hdr, int max_slots, int lf_grid,
-                             int ion_grid, int dep_grid) {
+                             int dep_grid) {
     const size_t lds = (size_t)max_slots * sizeof(int);
     hipLaunchKernelGGL(k_batch_leapfrog, dim3(lf_grid), dim3(256), lds, s, tab, hdr);
     hipLaunchKernelGGL(k_batch_deposit, dim3(dep_grid), dim3(256), lds, s, tab, hdr);
-    hipLaunchKernelGGL(k_batch_forces, dim3(ion_grid), dim3(256), lds, s, tab, hdr);
-    hipLaunchKernelGGL(k_batch_advance, dim3(4), dim3(256), 0, s, tab, hdr);
     return hipGetLastError();
 }
 

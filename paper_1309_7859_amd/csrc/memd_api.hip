@@ -21,6 +21,25 @@ namespace {
 
 constexpr int kHistCap = 4096;
 
+// Positions enter finite and within 2^40 box lengths of the origin; every
+// accepted displacement component is at most one box length, so a cell index
+// floor(u / a) stays below 2^51 L (where the device's fold is exact) for
+// 2^50 steps.  r may be host or device memory.
+constexpr double kPosBoxes = 1099511627776.0;  // 2^40
+
+bool positions_ok(const double *r, size_t n, int L, double a) {
+    if (n == 0) return true;
+    std::vector<double> h(3 * n);
+    if (hipMemcpy(h.data(), r, 3 * n * sizeof(double), hipMemcpyDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const double lim = kPosBoxes * (double)L * a;
+    for (double x : h)
+        if (!(std::fabs(x) <= lim)) return false;
+    return true;
+}
+
 #define CK(expr)                                  \
     do {                                          \
         hipError_t _e = (expr);                   \
@@ -241,6 +260,15 @@ hipError_t enqueue_dipole_forces(memd_ctx *c) {
 
 }  // namespace
 
+namespace memd {
+
+hipError_t refresh_forces(memd_ctx *c) {
+    const hipError_t e = hipSetDevice(c->device);
+    return e != hipSuccess ? e : enqueue_dipole_forces(c);
+}
+
+}  // namespace memd
+
 extern "C" {
 
 int memd_version(void) { return 1; }
@@ -338,6 +366,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
             sa += std::fabs(x);
         }
         if (std::fabs(s) > 1e-12 * sa) return fail(MEMD_ENONNEUTRAL);
+        if (!positions_ok(r0, (size_t)n, p->L, p->a)) return fail(MEMD_EINVAL);
     }
 
     const size_t fb = 3 * Ns * c->tsize;
@@ -888,6 +917,7 @@ memd_status memd_set_state(memd_ctx *c, const double *D, const double *B, const 
         CK(copy_in(c, c->stage, B, M * sizeof(double)));
         CK(launch_cast(c->stream, c->stage, c->B[c->cur], M, c->fp32));
     }
+    if (r && !positions_ok(r, (size_t)c->n, c->L, c->a)) return MEMD_EINVAL;
     if (r) {
         if (c->sorted) {
             // back to the caller's order: q moves, perm becomes the identity

@@ -214,6 +214,10 @@ hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint
 // forces = false: only the irregular deposits (the ions' own dynamics gathers
 // the new state's forces after the step).
 hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext, bool forces = true);
+// The dipole moment and the forces of the context's current state (D[cur],
+// r), recomputed on its stream (the server, for a replica the batched kernels
+// advanced).
+hipError_t refresh_forces(memd_ctx *c);
 // The ion side of a step of the ions' own dynamics (k_md_ions): the forces of
 // the state in D (gather; else c->F as it is, dip_partials unused), `kicks`
 // half kicks of v (caller order, masses too), with pack the next move dt v

@@ -13,9 +13,9 @@ struct RepDesc {
     int L, n;
     int rows, tz;          // leapfrog tile: 64 x (4 rows) sites, tz planes per chunk
     int ntx, nty, nzc;
-    int tiles, iblocks;    // leapfrog work items, ion blocks of 256 (forces)
+    int tiles;             // leapfrog work items
     int dblocks;           // deposit work items: 16 ions each, 16 lanes per ion
-    int tile_off, ion_off, dep_off; // first item of this replica in the global item ranges
+    int tile_off, dep_off; // first item of this replica in the global item ranges
     int eta_mode;          // ETA_UNIFORM or ETA_ZPROF
     int nsteps;
     float eta_uni, kB, kD; // 1/eps, dt/a, dt c^2/a
@@ -27,24 +27,22 @@ struct RepDesc {
     const float *eta_prof;
     const double *q;
     double *r;
-    double *F;
-    double *scal;  // P, eps_h, G of the replica
-    double *dip;   // [3 * dblocks] partial sums of q r (one per deposit item)
-    int *step;     // steps done (device counter)
+    int *steps;    // [2] device counters: steps[0] the count the leapfrog launch saw (read by
+                   // the deposit launch), steps[1] steps done
 };
 
-// table header on the device: {count, total leapfrog tiles, total ion blocks,
-// max_slots, total deposit items}, then the entries' tile_off[max_slots],
-// ion_off[max_slots] and dep_off[max_slots] (the offsets again, compact, for
-// the kernels' owner search)
-constexpr int kHdrInts = 5;
-__host__ __device__ inline int hdr_ints(int max_slots) { return kHdrInts + 3 * max_slots; }
+// table header on the device: {count, total leapfrog tiles, max_slots, total
+// deposit items}, then the entries' tile_off[max_slots] and dep_off[max_slots]
+// (the offsets again, compact, for the kernels' owner search)
+constexpr int kHdrInts = 4;
+__host__ __device__ inline int hdr_ints(int max_slots) { return kHdrInts + 2 * max_slots; }
 constexpr int kDepIons = 16;  // ions per deposit item (16 lanes each)
 // the item ranges of the header
-enum ItemRange : int { RANGE_TILES = 0, RANGE_IONS = 1, RANGE_DEP = 2 };
+enum ItemRange : int { RANGE_TILES = 0, RANGE_DEP = 1 };
 
 hipError_t launch_batch_step(hipStream_t s, const RepDesc *tab, const int *hdr, int max_slots, int lf_grid,
-                             int ion_grid, int dep_grid);
+                             int dep_grid);
+hipError_t launch_batch_leapfrog(hipStream_t s, const RepDesc *tab, const int *hdr, int max_slots, int grid);
 hipError_t launch_philox_disp(hipStream_t s, uint64_t seed, uint32_t t, int n, double sigma, double *out);
 
 }  // namespace memd

@@ -6,17 +6,20 @@
 // on a stream of its own (context, permittivity, FP64 initial solve, tile
 // autotune), which overlaps with the batched steps of the resident replicas.
 // Each global step advances every resident replica by one time step with one
-// replay of a captured HIP graph (batched leapfrog, deposit, forces, counter
-// advance); the replica table the graph reads lives in device memory and is
-// rewritten between replays when replicas join or leave.  Finished replicas
-// are retired (forces, energy, Gauss audit copied out, memory returned) and
-// their slots reused.
+// replay of a captured HIP graph of two launches (batched leapfrog, then the
+// batched deposit, which also advances the step counters); the replica table
+// the graph reads lives in device memory and is rewritten between replays
+// when replicas join or leave.  Finished replicas are retired on a worker
+// thread (forces, energy and Gauss audit of the final state computed on the
+// replica's own stream and copied out, memory returned) and their slots
+// reused.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -50,8 +53,6 @@ struct Request {
     memd_status error = MEMD_OK;
     memd_ctx *ctx = nullptr;
     size_t bytes_resident = 0, bytes_peak = 0;
-    int rows = 2, tz = 8;
-    double *dip = nullptr;
     int slot = -1;
     std::vector<double> F;
     memd_energy_t E{};
@@ -111,7 +112,7 @@ struct memd_server {
 
     RepDesc *d_tab = nullptr;
     int *d_hdr = nullptr;
-    int *d_steps = nullptr;       // one counter per slot
+    int *d_steps = nullptr;       // two counters per slot (RepDesc::steps)
     RepDesc *h_tab = nullptr;     // pinned mirrors
     int *h_hdr = nullptr;
     int *h_steps = nullptr;
@@ -120,7 +121,8 @@ struct memd_server {
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int lf_grid = 2048, ion_grid = 1024, dep_grid = 2048;
+    int lf_grid = 2048, dep_grid = 2048;
+    int batch_tz = 8;  // planes per z-chunk of every replica's leapfrog tiles (tune_batch_depth)
 
     long global_steps = 0, replica_steps = 0, done_count = 0, failed_count = 0;
     char last_error[160] = {0};
@@ -156,15 +158,6 @@ void worker_main(memd_server *s) {
         memd_status st = memd_init_lattice(&rq->ctx, &rq->p, rq->n, rq->q.data(), rq->r0.data(), nullptr);
         if (st == MEMD_OK) st = memd_set_permittivity(rq->ctx, rq->eps_mode, rq->eps.data(), 4.0);
         if (st == MEMD_OK) st = memd_initial_gauss_solve(rq->ctx, s->solve_tol, 0, nullptr, nullptr);
-        if (st == MEMD_OK) {
-            const char *cache = s->tune_cache.empty() ? nullptr : s->tune_cache.c_str();
-            // the batched leapfrog holds tiles of one row per thread
-            st = autotune_leapfrog(rq->ctx, 5, cache, 1, &rq->rows, &rq->tz, nullptr);
-        }
-        if (st == MEMD_OK) {
-            const int db = rq->n > 0 ? (rq->n + kDepIons - 1) / kDepIons : 1;
-            if (hipMalloc((void **)&rq->dip, 3 * (size_t)db * sizeof(double)) != hipSuccess) st = MEMD_ENOMEM;
-        }
         std::lock_guard<std::mutex> lk(s->mu);
         rq->t_ready = s->now();
         if (st == MEMD_OK) {
@@ -203,17 +196,16 @@ void admit(memd_server *s) {
     s->cv.notify_all();
 }
 
-void fill_desc(const Request *rq, int slot, int *d_steps, RepDesc &d) {
+void fill_desc(const Request *rq, int slot, int *d_steps, int tz, RepDesc &d) {
     memd_ctx *c = rq->ctx;
     d.L = c->L;
     d.n = c->n;
-    d.rows = rq->rows;
-    d.tz = rq->tz;
+    d.rows = 1;  // the batched leapfrog holds tiles of one row per thread
+    d.tz = std::min(tz, c->L);
     d.ntx = (c->L + 63) / 64;
     d.nty = (c->L + 4 * d.rows - 1) / (4 * d.rows);
     d.nzc = (c->L + d.tz - 1) / d.tz;
     d.tiles = d.ntx * d.nty * d.nzc;
-    d.iblocks = c->n > 0 ? (c->n + 255) / 256 : 1;
     d.dblocks = c->n > 0 ? (c->n + kDepIons - 1) / kDepIons : 1;
     d.eta_mode = c->eta_mode;
     d.nsteps = rq->nsteps;
@@ -231,33 +223,26 @@ void fill_desc(const Request *rq, int slot, int *d_steps, RepDesc &d) {
     d.eta_prof = (const float *)c->eta_prof;
     d.q = c->q;
     d.r = c->r;
-    d.F = c->F;
-    d.scal = c->scal;
-    d.dip = rq->dip;
-    d.step = d_steps + slot;
+    d.steps = d_steps + 2 * slot;
 }
 
 hipError_t upload_table(memd_server *s) {
-    int toff = 0, ioff = 0, doff = 0;
+    int toff = 0, doff = 0;
     for (size_t k = 0; k < s->active.size(); ++k) {
         Request *rq = s->active[k];
         RepDesc &d = s->h_tab[k];
-        fill_desc(rq, rq->slot, s->d_steps, d);
+        fill_desc(rq, rq->slot, s->d_steps, s->batch_tz, d);
         d.tile_off = toff;
-        d.ion_off = ioff;
         d.dep_off = doff;
-        s->h_hdr[kHdrInts + k] = toff;
-        s->h_hdr[kHdrInts + s->max_slots + k] = ioff;
-        s->h_hdr[kHdrInts + 2 * s->max_slots + k] = doff;
+        s->h_hdr[kHdrInts + RANGE_TILES * s->max_slots + k] = toff;
+        s->h_hdr[kHdrInts + RANGE_DEP * s->max_slots + k] = doff;
         toff += d.tiles;
-        ioff += d.iblocks;
         doff += d.dblocks;
     }
     s->h_hdr[0] = (int)s->active.size();
     s->h_hdr[1] = toff;
-    s->h_hdr[2] = ioff;
-    s->h_hdr[3] = s->max_slots;
-    s->h_hdr[4] = doff;
+    s->h_hdr[2] = s->max_slots;
+    s->h_hdr[3] = doff;
     hipError_t e;
     if (!s->active.empty())
         if ((e = hipMemcpyAsync(s->d_tab, s->h_tab, s->active.size() * sizeof(RepDesc), hipMemcpyHostToDevice,
@@ -276,9 +261,121 @@ hipError_t upload_table(memd_server *s) {
 hipError_t capture_graph(memd_server *s) {
     hipError_t e;
     if ((e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
-    launch_batch_step(s->stream, s->d_tab, s->d_hdr, s->max_slots, s->lf_grid, s->ion_grid, s->dep_grid);
+    launch_batch_step(s->stream, s->d_tab, s->d_hdr, s->max_slots, s->lf_grid, s->dep_grid);
     if ((e = hipStreamEndCapture(s->stream, &s->graph)) != hipSuccess) return e;
     return hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0);
+}
+
+// The tile depth of the batched leapfrog (planes per z-chunk), one for every
+// replica, picked by timing the batched kernel itself on a synthetic batch
+// that fills the device as a live one does: up to 16 lattices of 64^3 sites
+// (4.2M sites, fewer under a small budget), zero fields (the kernel's time
+// does not depend on the values), uniform permittivity.  Depths 2..32, ten
+// launches each after two untimed ones; the pick is cached in tune_cache.
+// Tuning replicas one at a time, alone on the device, favours shallow tiles
+// (more of them to fill the device) where the full batch is faster with
+// deeper ones, whose z halo costs less.
+hipError_t tune_batch_depth(memd_server *s) {
+    const char *key = "batch_leapfrog fp32";
+    if (!s->tune_cache.empty()) {
+        if (FILE *f = fopen(s->tune_cache.c_str(), "r")) {
+            char line[256];
+            int tz = 0;
+            while (fgets(line, sizeof(line), f)) {
+                int t = 0;
+                if (strncmp(line, key, strlen(key)) == 0 && sscanf(line + strlen(key), " planes=%d", &t) == 1 &&
+                    t >= 1)
+                    tz = t;
+            }
+            fclose(f);
+            if (tz > 0) {
+                s->batch_tz = tz;
+                return hipSuccess;
+            }
+        }
+    }
+    constexpr int L = 64;
+    const size_t Ns = (size_t)L * L * L, per = 12 * Ns * sizeof(float);  // D, B and their next values
+    const int M = (int)std::max<size_t>(1, std::min<size_t>(16, s->budget / per));
+    float *fields = nullptr;
+    RepDesc *d_tab = nullptr;
+    int *d_hdr = nullptr, *d_cnt = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<RepDesc> tab(M);
+    std::vector<int> hdr(hdr_ints(M), 0);
+    hipError_t e = hipMalloc((void **)&fields, M * per);
+    if (e == hipSuccess) e = hipMalloc((void **)&d_tab, M * sizeof(RepDesc));
+    if (e == hipSuccess) e = hipMalloc((void **)&d_hdr, hdr.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void **)&d_cnt, 2 * (size_t)M * sizeof(int));
+    if (e == hipSuccess) e = hipMemsetAsync(fields, 0, M * per, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d_cnt, 0, 2 * (size_t)M * sizeof(int), s->stream);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    double best_us = HUGE_VAL;
+    for (int tz = 2; tz <= 32 && e == hipSuccess; tz *= 2) {
+        int toff = 0;
+        for (int k = 0; k < M; ++k) {
+            RepDesc &d = tab[k];
+            memset(&d, 0, sizeof(d));
+            d.L = L;
+            d.rows = 1;
+            d.tz = tz;
+            d.ntx = 1;
+            d.nty = L / 4;
+            d.nzc = L / tz;
+            d.tiles = d.ntx * d.nty * d.nzc;
+            d.dblocks = 1;
+            d.tile_off = toff;
+            d.dep_off = k;
+            d.eta_mode = ETA_UNIFORM;
+            d.nsteps = 1 << 30;
+            d.eta_uni = 1.0f;
+            d.kB = 0.01f;
+            d.kD = 0.01f;
+            d.a = 1.0;
+            d.V = (double)Ns;
+            float *f = fields + 12 * Ns * k;
+            d.D[0] = f;
+            d.D[1] = f + 3 * Ns;
+            d.B[0] = f + 6 * Ns;
+            d.B[1] = f + 9 * Ns;
+            d.steps = d_cnt + 2 * k;
+            hdr[kHdrInts + RANGE_TILES * M + k] = toff;
+            hdr[kHdrInts + RANGE_DEP * M + k] = k;
+            toff += d.tiles;
+        }
+        hdr[0] = M;
+        hdr[1] = toff;
+        hdr[2] = M;
+        hdr[3] = M;
+        e = hipMemcpyAsync(d_tab, tab.data(), M * sizeof(RepDesc), hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_hdr, hdr.data(), hdr.size() * sizeof(int), hipMemcpyHostToDevice, s->stream);
+        for (int t = 0; t < 12 && e == hipSuccess; ++t) {
+            if (t == 2) e = hipEventRecord(e0, s->stream);
+            if (e == hipSuccess) e = launch_batch_leapfrog(s->stream, d_tab, d_hdr, M, s->lf_grid);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);  // the host copies above are reused next round
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && 100.0 * ms < best_us) {
+            best_us = 100.0 * ms;  // us per launch
+            s->batch_tz = tz;
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(fields);
+    hipFree(d_tab);
+    hipFree(d_hdr);
+    hipFree(d_cnt);
+    if (e == hipSuccess && !s->tune_cache.empty())
+        if (FILE *f = fopen(s->tune_cache.c_str(), "a")) {
+            fprintf(f, "%s planes=%d us=%.3f\n", key, s->batch_tz, best_us);
+            fclose(f);
+        }
+    return e;
 }
 
 memd_status fail_dev(memd_server *s, const char *what, hipError_t e) {
@@ -286,7 +383,7 @@ memd_status fail_dev(memd_server *s, const char *what, hipError_t e) {
     return MEMD_EDEVICE;
 }
 
-// Join initialised replicas (slot, zeroed step counter).
+// Join initialised replicas (slot, zeroed step counters).
 hipError_t join_ready(memd_server *s) {
     std::vector<Request *> joining;
     {
@@ -296,9 +393,11 @@ hipError_t join_ready(memd_server *s) {
     for (Request *rq : joining) {
         rq->slot = s->free_slots.back();
         s->free_slots.pop_back();
-        s->h_steps[rq->slot] = 0;
-        hipError_t e = hipMemcpyAsync(s->d_steps + rq->slot, s->h_steps + rq->slot, sizeof(int),
-                                      hipMemcpyHostToDevice, s->stream);
+        int *hs = s->h_steps + 2 * rq->slot;
+        hs[0] = 0;
+        hs[1] = 0;
+        hipError_t e = hipMemcpyAsync(s->d_steps + 2 * rq->slot, hs, 2 * sizeof(int), hipMemcpyHostToDevice,
+                                      s->stream);
         if (e != hipSuccess) return e;
         rq->state = Q_ACTIVE;
         s->active.push_back(rq);
@@ -314,8 +413,7 @@ hipError_t retire(memd_server *s) {
     std::vector<Request *> keep;
     bool any = false;
     for (Request *rq : s->active) {
-        const int st = s->h_steps[rq->slot];
-        if (st < rq->nsteps) {
+        if (s->h_steps[2 * rq->slot + 1] < rq->nsteps) {
             keep.push_back(rq);
             continue;
         }
@@ -338,16 +436,15 @@ void finish_request(memd_server *s, Request *rq) {
     c->cur = rq->nsteps & 1;
     c->step_index = rq->nsteps;
     rq->F.assign(3 * (size_t)rq->n, 0.0);
-    memd_status ms = memd_forces(c, rq->F.data());
+    memd_status ms = refresh_forces(c) == hipSuccess ? MEMD_OK : MEMD_EDEVICE;
+    if (ms == MEMD_OK) ms = memd_forces(c, rq->F.data());
     if (ms == MEMD_OK) ms = memd_energy(c, &rq->E);
     if (ms == MEMD_OK) ms = memd_gauss_residual(c, &rq->gauss, nullptr);
     bool finite = std::isfinite(rq->E.E_corrected);
     for (double f : rq->F) finite = finite && std::isfinite(f);
     memd_destroy(c);
-    hipFree(rq->dip);
     std::lock_guard<std::mutex> lk(s->mu);
     rq->ctx = nullptr;
-    rq->dip = nullptr;
     rq->t_done = s->now();
     rq->state = (ms == MEMD_OK && finite) ? Q_DONE : Q_FAILED;
     rq->error = ms != MEMD_OK ? ms : (finite ? MEMD_OK : MEMD_EDEVICE);
@@ -388,18 +485,18 @@ memd_status memd_server_create(memd_server **out, size_t hbm_budget_bytes, int m
     }
     if (hipMalloc((void **)&s->d_tab, (size_t)max_slots * sizeof(RepDesc)) != hipSuccess ||
         hipMalloc((void **)&s->d_hdr, hdr_ints(max_slots) * sizeof(int)) != hipSuccess ||
-        hipMalloc((void **)&s->d_steps, (size_t)max_slots * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&s->d_steps, 2 * (size_t)max_slots * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void **)&s->h_tab, (size_t)max_slots * sizeof(RepDesc), 0) != hipSuccess ||
         hipHostMalloc((void **)&s->h_hdr, hdr_ints(max_slots) * sizeof(int), 0) != hipSuccess ||
-        hipHostMalloc((void **)&s->h_steps, (size_t)max_slots * sizeof(int), 0) != hipSuccess) {
+        hipHostMalloc((void **)&s->h_steps, 2 * (size_t)max_slots * sizeof(int), 0) != hipSuccess) {
         memd_server_destroy(s);
         return MEMD_ENOMEM;
     }
     memset(s->h_hdr, 0, hdr_ints(max_slots) * sizeof(int));
-    memset(s->h_steps, 0, (size_t)max_slots * sizeof(int));
+    memset(s->h_steps, 0, 2 * (size_t)max_slots * sizeof(int));
     for (int k = max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
-    if (upload_table(s) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess ||
-        capture_graph(s) != hipSuccess) {
+    if (tune_batch_depth(s) != hipSuccess || upload_table(s) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess || capture_graph(s) != hipSuccess) {
         memd_server_destroy(s);
         return MEMD_EDEVICE;
     }
@@ -462,7 +559,7 @@ memd_status memd_server_progress(memd_server *s, int global_steps, int *active, 
         for (int t = 0; t < global_steps; ++t)
             if ((e = hipGraphLaunch(s->exec, s->stream)) != hipSuccess) return fail_dev(s, "hipGraphLaunch", e);
         s->global_steps += global_steps;
-        if ((e = hipMemcpyAsync(s->h_steps, s->d_steps, (size_t)s->max_slots * sizeof(int),
+        if ((e = hipMemcpyAsync(s->h_steps, s->d_steps, 2 * (size_t)s->max_slots * sizeof(int),
                                 hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
             return fail_dev(s, "step counters", e);
         if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return fail_dev(s, "step sync", e);
@@ -526,7 +623,6 @@ memd_status memd_server_destroy(memd_server *s) {
     for (auto &kv : s->all) {
         Request *rq = kv.second.get();
         if (rq->ctx) memd_destroy(rq->ctx);
-        if (rq->dip) hipFree(rq->dip);
     }
     if (s->exec) hipGraphExecDestroy(s->exec);
     if (s->graph) hipGraphDestroy(s->graph);

@@ -351,7 +351,18 @@ def test_error_codes():
     with pytest.raises(memd.MemdError) as e:
         memd.Context(1, q, r)
     assert e.value.status == memd.EINVAL
+    for bad in (np.nan, np.inf, 2.0 ** 41 * L):  # positions: finite, within 2^40 L a
+        rb = r.copy()
+        rb[1, 2] = bad
+        with pytest.raises(memd.MemdError) as e:
+            memd.Context(L, q, rb)
+        assert e.value.status == memd.EINVAL
     G = memd.Context(L, q, r)
+    rb = r.copy()
+    rb[0, 0] = -np.inf
+    with pytest.raises(memd.MemdError) as e:
+        G.set_state(None, None, rb)
+    assert e.value.status == memd.EINVAL
     with pytest.raises(memd.MemdError) as e:
         G.step(np.zeros((2, 3)), 1)
     assert e.value.status == memd.ESTATE
@@ -365,6 +376,8 @@ def test_error_codes():
     with pytest.raises(memd.MemdError) as e:
         memd.memd_set_tiling(G.ctx, 3, 0)
     assert e.value.status == memd.EINVAL
+    G.set_state(None, None, r + 2.0 ** 39 * L)  # far from the origin, but inside the bound
+    G.step(np.zeros((2, 3)), 1)
 
 
 def test_autotune_keeps_state_and_caches(tmp_path):

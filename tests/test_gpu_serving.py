@@ -182,3 +182,44 @@ def test_served_equals_single_system_fp32():
         memd.memd_step_seeded(G.ctx, sp.seed, 0.02, sp.steps)
         F = G.forces()
     assert force_err(res["F"], F) <= 1e-5
+
+
+def test_short_replicas_match_oracle():
+    """Replicas of 0, 1 and 2 steps in one mix (their final forces come from
+    the leapfrog launch after their last deposit, or from the initial solve
+    for no steps) against the oracle."""
+    specs = [spec(k, L, n, steps, "zsite" if k % 2 else "uniform", 15.0, 0.0, seed=900 + k)
+             for k, (L, n, steps) in enumerate([(16, 60, 0), (24, 90, 1), (16, 120, 2), (32, 40, 1)])]
+    out = _served(specs, solve_tol=1e-12)
+    assert out["done"] == len(specs) and out["failed"] == 0
+    for k, sp in enumerate(specs):
+        q, r0 = W.replica_inputs(sp)
+        eps_min = 15.0 if sp.eps_kind == "uniform" else float(np.min(sp.eps_z))
+        S = oracle.System(sp.L, 1.0, W.DT, W.default_c(1.0, W.DT, eps_min), q, r0)
+        if sp.eps_kind == "uniform":
+            S.set_eps_uniform(15.0)
+        else:
+            S.set_eps_zsite(sp.eps_z)
+        S.initial_solve(1e-12)
+        for t in range(sp.steps):
+            S.step(oracle.seeded_displacements(sp.seed, t, sp.n, 0.02))
+        res = out["results"][k]
+        assert force_err(res["F"], S.forces()[0]) <= 1e-4, (k, sp.steps)
+        errs = energy_err(res["E"], S.energy())
+        assert max(errs.values()) <= 1e-4, (k, errs)
+
+
+def test_batch_depth_tuned_and_cached(tmp_path):
+    """memd_server_create times the batched leapfrog for each tile depth on a
+    synthetic batch and caches the pick; a second server reads it back (no
+    new line) and serves a replica with it."""
+    cache = str(tmp_path / "tune.txt")
+    srv = memd.memd_server_create(1 << 30, 8, 1, 1e-8, cache)
+    memd.memd_server_destroy(srv)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("batch_leapfrog fp32 planes=")
+    assert int(lines[0].split("planes=")[1].split()[0]) in (2, 4, 8, 16, 32)
+    sp = spec(0, 24, 100, 10, "uniform", 20.0, 0.0)
+    out = serve.run_stream([sp], 1 << 30, max_slots=8, workers=1, poll_steps=2, tune_cache=cache)
+    assert out["done"] == 1
+    assert open(cache).read().splitlines() == lines
