@@ -2,7 +2,9 @@
 // plane -> line -> vertex recursion (Fig. 1), the uniform mode set to -P/V
 // (section "Periodicity"), and the relaxation to curl E = 0 by minimising the
 // field energy over D + C^T theta (conjugate gradients on C eta C^T theta =
-// -C eta D with a Jacobi preconditioner; D is updated in place of theta).
+// -C eta D; D is updated in place of theta), preconditioned by the inverse
+// lattice Laplacian through 3-D FFTs when L is a power of two up to 1024,
+// else by the diagonal.
 // For a uniform or planar permittivity the same minimiser is computed
 // directly (a 2-D DFT and one tridiagonal solve per mode).  Also the
 // periodic lattice Green's function used by the self-energy correction
@@ -10,6 +12,7 @@
 #include "device_util.hpp"
 #include "memd_internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace memd {
@@ -263,6 +266,136 @@ __global__ __launch_bounds__(256) void k_precond(const double *__restrict__ dinv
     if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
 }
 
+// ---------------------------------------------- spectral preconditioner
+//
+// On plaquette fields in the range of C (the only ones the iteration sees:
+// the right-hand side and every C eta w are curls), C C^T is the lattice
+// Laplacian -Delta acting on each component alike: in Fourier space its
+// symbol is |kappa|^2 = sum_d 4 sin^2(pi m_d / L) / a^2.  z = (-Delta)^{-1} r
+// is therefore the exact inverse of C eta C^T for a uniform eta (up to the
+// scale, which conjugate gradients do not see), and for a varying eta the
+// preconditioned operator's condition number is at most max eta / min eta.
+// The three components go through two complex transforms: r_x + i r_y
+// (the symbol is real and even, so real and imaginary parts stay apart) and
+// r_z.
+
+// z (complex, batch of two L^3 arrays) = (r_x + i r_y, r_z + 0 i)
+__global__ __launch_bounds__(256) void k_spec_pack(const double *__restrict__ r, size_t Ns,
+                                                   double2 *__restrict__ Z, const int *stop) {
+    if (stop && *stop) return;
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns; v += (size_t)gridDim.x * blockDim.x) {
+        Z[v] = make_double2(r[v], r[Ns + v]);
+        Z[Ns + v] = make_double2(r[2 * Ns + v], 0.0);
+    }
+}
+
+// In-place radix-2 FFT of lines along `axis` of `batch` complex L^3 arrays
+// (L = 2^lg <= 1024), exp(sign 2 pi i m n / L), unnormalised.  A workgroup
+// takes G = min(L, 2048 / L) lines that are neighbours along the fastest
+// other axis (so that its loads along y and z are coalesced across lines):
+// bit-reversed into LDS, lg butterfly stages, stored back.
+__global__ __launch_bounds__(256) void k_fft_lines(double2 *__restrict__ data, int L, int lg, int axis, double sign,
+                                                   const int *stop) {
+    if (stop && *stop) return;
+    extern __shared__ double2 fsh[];
+    const int G = min(L, 2048 / L);
+    double2 *tw = fsh + (size_t)G * L;
+    const size_t LL = (size_t)L * L, Ns = LL * L;
+    const int groups = L / G;
+    const int a0 = (int)(blockIdx.x % groups) * G;
+    const size_t rest = blockIdx.x / groups;
+    const int b = (int)(rest % L);
+    double2 *base = data + (rest / L) * Ns;
+    for (int k = threadIdx.x; k < L / 2; k += blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * k / L, &sn, &cs);
+        tw[k] = make_double2(cs, sign * sn);
+    }
+    auto addr = [&](int g, int j) -> size_t {
+        const int a = a0 + g;
+        if (axis == 0) return (size_t)j + (size_t)L * a + LL * b;
+        if (axis == 1) return (size_t)a + (size_t)L * j + LL * b;
+        return (size_t)a + (size_t)L * b + LL * j;
+    };
+    for (int t = threadIdx.x; t < G * L; t += blockDim.x) {
+        const int g = axis == 0 ? t / L : t % G, j = axis == 0 ? t % L : t / G;
+        fsh[g * L + (int)(__brev((unsigned)j) >> (32 - lg))] = base[addr(g, j)];
+    }
+    for (int h = 1; h < L; h *= 2) {
+        __syncthreads();
+        const int stride = L / (2 * h);
+        for (int bt = threadIdx.x; bt < G * L / 2; bt += blockDim.x) {
+            const int g = bt / (L / 2), bb = bt % (L / 2);
+            const int j = (bb / h) * 2 * h + bb % h;
+            const double2 w = tw[(bb % h) * stride];
+            const double2 u = fsh[g * L + j], x = fsh[g * L + j + h];
+            const double2 v = make_double2(x.x * w.x - x.y * w.y, x.x * w.y + x.y * w.x);
+            fsh[g * L + j] = make_double2(u.x + v.x, u.y + v.y);
+            fsh[g * L + j + h] = make_double2(u.x - v.x, u.y - v.y);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < G * L; t += blockDim.x) {
+        const int g = axis == 0 ? t / L : t % G, j = axis == 0 ? t % L : t / G;
+        base[addr(g, j)] = fsh[g * L + j];
+    }
+}
+
+// Z(m) *= 1 / sum_d 4 sin^2(pi m_d / L) (the mean, m = 0, to zero), batch of two.
+__global__ __launch_bounds__(256) void k_spec_scale(double2 *__restrict__ Z, int L, size_t Ns, const int *stop) {
+    if (stop && *stop) return;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < 2 * Ns; t += (size_t)gridDim.x * blockDim.x) {
+        const size_t v = t % Ns;
+        int i, j, k;
+        site_ijk(v, L, i, j, k);
+        const double si = sinpi((double)i / L), sj = sinpi((double)j / L), sk = sinpi((double)k / L);
+        const double lam = 4.0 * (si * si + sj * sj + sk * sk);
+        const double f = v == 0 ? 0.0 : 1.0 / lam;
+        Z[t] = make_double2(Z[t].x * f, Z[t].y * f);
+    }
+}
+
+// z = (Re Z0, Im Z0, Re Z1) / Ns; partial <r, z> of this block into
+// partials[stride * block].
+__global__ __launch_bounds__(256) void k_spec_unpack(const double2 *__restrict__ Z, const double *__restrict__ r,
+                                                     double *__restrict__ z, size_t Ns, double *partials, int stride,
+                                                     const int *stop) {
+    if (stop && *stop) return;
+    const double inv = 1.0 / (double)Ns;
+    double s[1] = {0.0};
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < Ns; v += (size_t)gridDim.x * blockDim.x) {
+        const double2 a = Z[v], c = Z[Ns + v];
+        const double z0 = a.x * inv, z1 = a.y * inv, z2 = c.x * inv;
+        z[v] = z0;
+        z[Ns + v] = z1;
+        z[2 * Ns + v] = z2;
+        s[0] += r[v] * z0 + r[Ns + v] * z1 + r[2 * Ns + v] * z2;
+    }
+    block_sum<1>(s);
+    if (threadIdx.x == 0) partials[(size_t)stride * blockIdx.x] = s[0];
+}
+
+static bool spectral_ok(int L) { return L >= 2 && L <= 1024 && (L & (L - 1)) == 0; }
+
+// z = (-Delta)^{-1} r on the three components, partial <r, z> per block of
+// `blocks` into partials[stride * b]; Z holds 2 L^3 complex values.
+static void launch_spectral(hipStream_t s, int L, const double *r, double *z, double2 *Z, int blocks,
+                            double *partials, int stride, const int *stop) {
+    const size_t Ns = (size_t)L * L * L;
+    int lg = 0;
+    while ((1 << lg) < L) ++lg;
+    const int G = std::min(L, 2048 / L);
+    const int wgs = 2 * (L / G) * L;
+    const size_t lds = ((size_t)G * L + L / 2) * sizeof(double2);
+    hipLaunchKernelGGL(k_spec_pack, dim3(blocks), dim3(kThreads), 0, s, r, Ns, Z, stop);
+    for (int ax = 0; ax < 3; ++ax)
+        hipLaunchKernelGGL(k_fft_lines, dim3(wgs), dim3(kThreads), lds, s, Z, L, lg, ax, -1.0, stop);
+    hipLaunchKernelGGL(k_spec_scale, dim3(blocks), dim3(kThreads), 0, s, Z, L, Ns, stop);
+    for (int ax = 0; ax < 3; ++ax)
+        hipLaunchKernelGGL(k_fft_lines, dim3(wgs), dim3(kThreads), lds, s, Z, L, lg, ax, 1.0, stop);
+    hipLaunchKernelGGL(k_spec_unpack, dim3(blocks), dim3(kThreads), 0, s, Z, r, z, Ns, partials, stride, stop);
+}
+
 // CG scalar slots (relative to S_CG)
 enum { CG_RZ = 0, CG_ALPHA = 1, CG_BETA = 2, CG_RMAX = 3, CG_DEN = 4, CG_TOL = 5, CG_AINV = 6 };
 
@@ -281,7 +414,9 @@ __global__ void k_cg_alpha(const double *partials, int nblk, double *cg, int *fl
     }
 }
 
-// D += alpha w; r -= alpha q; z = dinv r; partials: <r,z>, max|r|
+// D += alpha w; r -= alpha q; z = dinv r; partials: <r,z>, max|r| (with
+// dinv null, z and <r,z> are left to the spectral preconditioner, which
+// writes partials[2 b] after this kernel)
 __global__ __launch_bounds__(256) void k_cg_update(double *__restrict__ D, double *__restrict__ r,
                                                    double *__restrict__ z, const double *__restrict__ w,
                                                    const double *__restrict__ q,
@@ -295,15 +430,17 @@ __global__ __launch_bounds__(256) void k_cg_update(double *__restrict__ D, doubl
         D[t] += alpha * w[t];
         const double rr = r[t] - alpha * q[t];
         r[t] = rr;
-        const double zz = dinv[t] * rr;
-        z[t] = zz;
-        s[0] += rr * zz;
+        if (dinv) {
+            const double zz = dinv[t] * rr;
+            z[t] = zz;
+            s[0] += rr * zz;
+        }
         mx = fmax(mx, fabs(rr));
     }
     block_sum<1>(s);
     const double m = block_max(mx);
     if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = s[0];
+        if (dinv) partials[2 * blockIdx.x] = s[0];
         partials[2 * blockIdx.x + 1] = m;
     }
 }
@@ -377,11 +514,15 @@ static int grid_m(size_t M) {
 memd_status solve_relax(memd_ctx *c, double *D, double tol, int max_iter, int *iters_out, double *res_out) {
     const size_t Ns = c->Ns, M = 3 * Ns;
     hipStream_t s = c->stream;
+    const bool spectral = spectral_ok(c->L);
     double *buf = nullptr;
-    // eta, dinv, r, z, p, w, q, Dbest
-    if (hipMallocAsync((void **)&buf, 8 * M * sizeof(double), s) != hipSuccess) return MEMD_ENOMEM;
-    double *eta = buf, *dinv = buf + M, *r = buf + 2 * M, *z = buf + 3 * M, *p = buf + 4 * M,
-           *w = buf + 5 * M, *q = buf + 6 * M, *Dbest = buf + 7 * M;
+    // eta, dinv (the spectral preconditioner's complex work array in its
+    // place, 4 Ns doubles), r, z, p, w, q, Dbest
+    if (hipMallocAsync((void **)&buf, (8 * M + (spectral ? Ns : 0)) * sizeof(double), s) != hipSuccess)
+        return MEMD_ENOMEM;
+    double *eta = buf, *dinv = buf + M, *r = buf + 2 * M + (spectral ? Ns : 0);
+    double *z = r + M, *p = r + 2 * M, *w = r + 3 * M, *q = r + 4 * M, *Dbest = r + 5 * M;
+    double2 *Z = reinterpret_cast<double2 *>(dinv);
     int *flags = nullptr;
     if (hipMallocAsync((void **)&flags, 4 * sizeof(int), s) != hipSuccess) {
         hipFreeAsync(buf, s);
@@ -396,7 +537,7 @@ memd_status solve_relax(memd_ctx *c, double *D, double tol, int max_iter, int *i
         hipLaunchKernelGGL(k_eta_expand<double>, dim3(gm), dim3(kThreads), 0, s, (const double *)c->eta_link,
                            (const double *)c->eta_prof, c->eta_uni, c->eta_mode, c->L, Ns, eta);
     CgArgs A{c->L, Ns, 1.0 / c->a, eta};
-    hipLaunchKernelGGL(k_dinv, dim3(g), dim3(kThreads), 0, s, A, c->a * c->a, dinv);
+    if (!spectral) hipLaunchKernelGGL(k_dinv, dim3(g), dim3(kThreads), 0, s, A, c->a * c->a, dinv);
     double *cg = c->scal + S_CG;
     double *part = c->partials;
 
@@ -438,7 +579,10 @@ memd_status solve_relax(memd_ctx *c, double *D, double tol, int max_iter, int *i
             res = best;
             break;
         }
-        hipLaunchKernelGGL(k_precond, dim3(gm), dim3(kThreads), 0, s, dinv, r, z, M, part);
+        if (spectral)
+            launch_spectral(s, c->L, r, z, Z, gm, part, 1, nullptr);
+        else
+            hipLaunchKernelGGL(k_precond, dim3(gm), dim3(kThreads), 0, s, dinv, r, z, M, part);
         launch_finalize_sum(s, part, gm, 1, cg + CG_RZ);
         if (first || hf[0] == 2) {
             hipLaunchKernelGGL(k_copy, dim3(gm), dim3(kThreads), 0, s, z, p, M);
@@ -450,8 +594,9 @@ memd_status solve_relax(memd_ctx *c, double *D, double tol, int max_iter, int *i
             hipLaunchKernelGGL((k_curl_eta<false, true>), dim3(g), dim3(kThreads), 0, s, A, w, 1.0, q, p, part,
                                flags);
             hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kThreads), 0, s, part, g, cg, flags);
-            hipLaunchKernelGGL(k_cg_update, dim3(gm), dim3(kThreads), 0, s, D, r, z, w, q, dinv, M, cg, part,
-                               flags);
+            hipLaunchKernelGGL(k_cg_update, dim3(gm), dim3(kThreads), 0, s, D, r, z, w, q,
+                               spectral ? nullptr : dinv, M, cg, part, flags);
+            if (spectral) launch_spectral(s, c->L, r, z, Z, gm, part, 2, flags);
             hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(kThreads), 0, s, part, gm, c->a, cg, flags, flags + 1);
             hipLaunchKernelGGL(k_cg_p, dim3(gm), dim3(kThreads), 0, s, p, z, M, cg, flags, it_total + t + 1);
         }

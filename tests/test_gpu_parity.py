@@ -37,13 +37,17 @@ def _rng_system(seed, n, L, valence2=False):
 
 # ------------------------------------------------------------ initial solve
 
-@pytest.mark.parametrize("case", ["c1", "site12", "zsite16", "link10", "uniform12", "zsite24"])
+@pytest.mark.parametrize("case", ["c1", "site12", "zsite16", "link10", "uniform12", "zsite24", "link16", "site32",
+                                  "link8_contrast"])
 def test_initial_solve_parity(case):
     """The GPU initial solution against the oracle's relaxation.  Uniform and
     planar permittivities (c1, zsite16, uniform12, zsite24: lattice sides
     that are and are not powers of two) are solved directly (a 2-D DFT and a
     tridiagonal solve per mode), so the relaxation that follows has nothing
-    left to do; per-site and per-link ones are relaxed."""
+    left to do; per-site and per-link ones are relaxed: with the diagonal
+    preconditioner on sides that are not powers of two (site12, link10), with
+    the spectral one (FFT of the inverse lattice Laplacian) on the others
+    (link16, site32, and link8_contrast with a permittivity contrast of 1000)."""
     if case == "c1":
         w = W.WORKLOADS["c1"]
         s = W.make_system(w, steps=0)
@@ -73,6 +77,24 @@ def test_initial_solve_parity(case):
         ez = W.tanh_slab(L, 1.0)
         S, G = pair(L, q, r, eps_min=ez.min())
         apply_eps(S, G, "zsite", eps_z=ez)
+    elif case == "link16":
+        L = 16
+        rng, q, r = _rng_system(17, 30, L, True)
+        el = 1.0 + 9.0 * rng.uniform(size=3 * L ** 3)
+        S, G = pair(L, q, r, eps_min=el.min())
+        apply_eps(S, G, "link", eps_link=el)
+    elif case == "site32":
+        L = 32
+        rng, q, r = _rng_system(18, 60, L, True)
+        eps = 20.0 + 60.0 * rng.uniform(size=L ** 3)
+        S, G = pair(L, q, r, eps_min=eps.min())
+        apply_eps(S, G, "site", eps_site=eps)
+    elif case == "link8_contrast":
+        L = 8
+        rng, q, r = _rng_system(19, 6, L)
+        el = np.exp(np.log(1000.0) * rng.uniform(size=3 * L ** 3))
+        S, G = pair(L, q, r, eps_min=el.min())
+        apply_eps(S, G, "link", eps_link=el)
     else:
         L = 10
         rng, q, r = _rng_system(7, 8, L)
@@ -85,6 +107,7 @@ def test_initial_solve_parity(case):
     assert st == memd.OK and gres <= 1e-13
     if case in ("c1", "zsite16", "uniform12", "zsite24"):
         assert git == 0  # the direct solution is the minimiser already
+    record("initial_solve", label=case, L=L, gpu_iterations=git, oracle_iterations=it)
     D, B, rr = G.state()
     E = S.eta * D
     Eref = S.eta * S.D
