@@ -329,6 +329,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     c->lf_tz = 4;
     c->sort_every = 64;
     c->dipole_correction = true;
+    c->final_forces = true;
     c->self_scheme = MEMD_SELF_GREEN;
     c->fuse_deposit = true;
     c->hist_cap = kHistCap;
@@ -708,7 +709,7 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
         md->gathered = dip_prev == nullptr;  // the plain path gathered them after its deposit
         md->dip = dip_prev;
         md->nb = dip_nb;
-    } else if (dip_prev) {
+    } else if (dip_prev && c->final_forces) {
         // forces (and P) of the final state
         prof_begin(c, F_FORCES);
         CK(launch_forces(c, c->D[c->cur], dip_prev, dip_nb));
@@ -1119,6 +1120,13 @@ memd_status memd_set_options(memd_ctx *c, int fuse_deposit, int sort_every) {
     if (fuse_deposit < 0 || fuse_deposit > 1 || sort_every < 0) return MEMD_EINVAL;
     c->fuse_deposit = fuse_deposit != 0;
     c->sort_every = sort_every;
+    return MEMD_OK;
+}
+
+memd_status memd_set_final_forces(memd_ctx *c, int on) {
+    CHECK_CTX(c);
+    if (on < 0 || on > 1) return MEMD_EINVAL;
+    c->final_forces = on != 0;
     return MEMD_OK;
 }
 

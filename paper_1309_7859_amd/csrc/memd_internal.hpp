@@ -128,6 +128,7 @@ struct memd_ctx {
     int lists_key;
     int list_zero_key;  // shape whose list counts are all zero (-1: none)
     int *dep_atomic;
+    bool final_forces;        // a call ends with the forces of its final state (memd_set_final_forces)
     unsigned int *bad_moves;  // rejected displacement components (not finite or > L a)
     bool fuse_deposit;
     int sort_every;

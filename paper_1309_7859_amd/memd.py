@@ -78,6 +78,7 @@ def load():
         "memd_step_seeded": [vp, C.c_uint64, d, i],
         "memd_set_options": [vp, i, i],
         "memd_set_dipole_correction": [vp, i],
+        "memd_set_final_forces": [vp, i],
         "memd_set_self_scheme": [vp, i],
         "memd_counters": [vp, C.POINTER(C.c_ulong), C.POINTER(i)],
         "memd_seeded_displacements": [C.c_uint64, i, i, d, vp],
@@ -285,6 +286,10 @@ def memd_set_options(ctx: int, fuse_deposit: int = 1, sort_every: int = 64):
     _check(load().memd_set_options(ctx, int(fuse_deposit), int(sort_every)), "memd_set_options")
 
 
+def memd_set_final_forces(ctx: int, on: bool):
+    _check(load().memd_set_final_forces(ctx, 1 if on else 0), "memd_set_final_forces")
+
+
 def memd_set_dipole_correction(ctx: int, on: bool):
     _check(load().memd_set_dipole_correction(ctx, 1 if on else 0), "memd_set_dipole_correction")
 
@@ -467,6 +472,9 @@ class Context:
 
     def set_dipole_correction(self, on: bool):
         memd_set_dipole_correction(self.ctx, on)
+
+    def set_final_forces(self, on: bool):
+        memd_set_final_forces(self.ctx, on)
 
     def set_self_scheme(self, scheme: int):
         memd_set_self_scheme(self.ctx, scheme)
