@@ -150,6 +150,57 @@ __device__ __forceinline__ void spread_ion(int L, double a, double qi, const dou
     }
 }
 
+// The current of one ion's move (deposit_ion's arithmetic, every axis and
+// transverse corner) restricted to the links whose site lies in the box
+// org + [0, ext), which does not wrap, added into acc[d][z][y][x] (relative
+// to org) with LDS atomics.  u is moved in place.
+template <typename T, int NZ, int NY>
+__device__ __forceinline__ void deposit_ion_box(int L, double a, double qi, double (&u)[3], const double (&du)[3],
+                                                const int (&org)[3], const int (&ext)[3], T (*acc)[NZ][NY][64]) {
+    const double a2 = a * a;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double u0 = u[d];
+        const double u1 = u0 + du[d];
+        if (u1 != u0) {
+            const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+            int c1, c2;
+            double f1, f2;
+            fold(u[d1], a, L, c1, f1);
+            fold(u[d2], a, L, c2, f2);
+            const double lo = u0 < u1 ? u0 : u1, hi = u0 < u1 ? u1 : u0;
+            const double sgn = u1 > u0 ? 1.0 : -1.0;
+            const double klo = floor(div_a(lo, a)), khi = floor(div_a(hi, a));
+#pragma unroll
+            for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                for (int o1 = 0; o1 < 2; ++o1) {
+                    const int x1 = o1 ? (c1 + 1 == L ? 0 : c1 + 1) : c1;
+                    const int x2 = o2 ? (c2 + 1 == L ? 0 : c2 + 1) : c2;
+                    const int l1 = x1 - org[d1], l2 = x2 - org[d2];
+                    if ((unsigned)l1 >= (unsigned)ext[d1] || (unsigned)l2 >= (unsigned)ext[d2]) continue;
+                    for (double kc = klo; kc <= khi; kc += 1.0) {
+                        const int ld = mod_cell(kc, L) - org[d];
+                        if ((unsigned)ld >= (unsigned)ext[d]) continue;
+                        const double s0 = kc * a, s1 = (kc + 1.0) * a;
+                        const double sa = lo > s0 ? lo : s0;
+                        const double sb = hi < s1 ? hi : s1;
+                        const double len = sb - sa;
+                        if (!(len > 0.0)) continue;
+                        const double amount = div_a(qi * sgn * div_a(len, a), a2);
+                        const double val = amount * lin_w(o1, f1) * lin_w(o2, f2);
+                        int l[3];
+                        l[d] = ld;
+                        l[d1] = l1;
+                        l[d2] = l2;
+                        atomicAdd(&acc[d][l[2]][l[1]][l[0]], (T)(-val));
+                    }
+                }
+        }
+        u[d] = u1;
+    }
+}
+
 // Cell self-energy sum S(f) = sum_{o,o'} w_o w_o' G(o - o') and its gradient:
 // per axis, equal corners weigh alpha = 1 - beta, different corners
 // beta = 2 f (1 - f); G depends on the number of differing axes.

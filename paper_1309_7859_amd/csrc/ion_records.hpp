@@ -27,6 +27,8 @@ struct DepOut {
     const int *list_fail;
     double *du;  // [3n] by slot: the (sanitised) displacement the record was made for
     IonFQ<T> *fq;  // [n] by slot: fractional position in the start cell and charge
+    int *icnt;     // non-null: the atomic-path ions of the records' step are appended here
+    int *ilist;    // (their slots; irr_count)
 };
 
 // The record of one ion in slot s for the fused deposit (du already
@@ -57,6 +59,7 @@ __device__ __forceinline__ bool write_record_at(int L, double a, double qi, cons
     }
     if (atomic_path) {
         O.head[s] = make_int4(-1, 0, 0, 0);
+        if (O.icnt) O.ilist[atomicAdd(O.icnt, 1)] = s;
         return true;
     }
     const double a2 = a * a;
@@ -243,6 +246,8 @@ inline DepOut<T> dep_out(const memd_ctx *c, bool next = false) {
     O.list_fail = c->list_fail;
     O.du = next ? c->du_slot_nx : c->du_slot;
     O.fq = (IonFQ<T> *)(next ? c->fq_nx : c->fq);
+    O.icnt = c->tile_irregular ? irr_count(c, c->step_index + (next ? 1 : 0)) : nullptr;
+    O.ilist = O.icnt ? O.icnt + kIrrHead : nullptr;
     return O;
 }
 

@@ -167,6 +167,12 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
         P.dip_prev = dip_prev;
         P.dip_nparts = dip_nparts;
         P.P = c->scal + S_P;
+        P.irr_cnt = c->tile_irregular ? irr_count(c, c->step_index) : nullptr;
+        P.irr_zero = c->tile_irregular ? irr_count(c, c->step_index + 2) : nullptr;
+        P.irr_r = c->r;
+        P.irr_du = c->du_slot;
+        P.irr_q = c->q;
+        P.irr_order = c->sorted ? nullptr : c->order;
         dp = &P;
     }
     const bool with_moves = dp && moves;

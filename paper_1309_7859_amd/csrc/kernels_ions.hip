@@ -254,6 +254,7 @@ hipError_t launch_build_lists(memd_ctx *c, bool pack, const double *disp, uint64
                            c->stream, c->list_count, 0, nc);
     }
     c->list_zero_key = -1;  // the counts are in use from here on
+    if (pack && c->tile_irregular) launch_clear_irregular(c);
     const int nb = ion_blocks(c->n);
     if (pack && c->fp32) {
         PackArgs<float> PA{c->q, disp, c->perm, c->dep_atomic, dep_out<float>(c), c->bad_moves, seed, t, sigma};
@@ -272,8 +273,18 @@ hipError_t launch_build_lists(memd_ctx *c, bool pack, const double *disp, uint64
     return hipGetLastError();
 }
 
+// The count of the atomic-path ions of the step whose records are about to
+// be written whole, cleared first (a fill kernel, so that a captured stream
+// records no memset).
+hipError_t launch_clear_irregular(memd_ctx *c) {
+    if (int *cnt = irr_count(c, c->step_index))
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, cnt, 0, (size_t)1);
+    return hipGetLastError();
+}
+
 hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma) {
     if (c->n == 0) return hipSuccess;
+    if (c->tile_irregular) launch_clear_irregular(c);
     const int nb = ion_blocks(c->n);
     if (c->fp32)
         hipLaunchKernelGGL(k_pack_ions<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->q,
@@ -318,6 +329,7 @@ struct IonFinishArgs {
     const double *du;       // [3n] by slot: this step's displacements
     int self_direct;        // 1: direct self subtraction; the tiles' results (Green's function) are not used
     int no_forces;          // 1: only the irregular deposits (the ions' own dynamics gathers the forces after)
+    int tiles_deposit;      // 1: the leapfrog tiles deposited the atomic-path ions (none here)
 };
 
 template <typename T>
@@ -327,7 +339,7 @@ __global__ __launch_bounds__(256) void k_ion_finish(IonFinishArgs<T> A) {
     const int i = A.order ? A.order[s] : s;
     const double qi = A.q[i];
     if (A.no_forces) {
-        if (A.dep_atomic[s] != 0) {
+        if (A.dep_atomic[s] != 0 && !A.tiles_deposit) {
             double w[3] = {A.r[3 * i], A.r[3 * i + 1], A.r[3 * i + 2]};
             const double du[3] = {A.du[3 * s], A.du[3 * s + 1], A.du[3 * s + 2]};
             deposit_ion<T>(A.L, A.Ns, A.a, qi, w, du, A.Dnext);
@@ -348,7 +360,7 @@ __global__ __launch_bounds__(256) void k_ion_finish(IonFinishArgs<T> A) {
             force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.Dcur, ev, A.scal + S_G, zero, A.scal + S_EPSH, F,
                          A.self_direct != 0);
         }
-        if (atomic_path) {
+        if (atomic_path && !A.tiles_deposit) {
             double w[3] = {u[0], u[1], u[2]};
             const double du[3] = {A.du[3 * s], A.du[3 * s + 1], A.du[3 * s + 2]};
             deposit_ion<T>(A.L, A.Ns, A.a, qi, w, du, A.Dnext);
@@ -381,6 +393,7 @@ hipError_t launch_ion_finish(memd_ctx *c, const void *Dcur, void *Dnext, bool fo
         A.du = c->du_slot;
         A.self_direct = c->self_scheme == MEMD_SELF_DIRECT;
         A.no_forces = forces ? 0 : 1;
+        A.tiles_deposit = c->tile_irregular ? 1 : 0;
     };
     if (c->fp32) {
         IonFinishArgs<float> A;

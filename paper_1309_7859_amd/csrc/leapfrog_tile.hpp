@@ -124,6 +124,14 @@ struct DepArgs {
     int dip_nparts;
     int dip_block;
     double *P;
+    // the ions the atomic path holds this step (irr_count; null: the
+    // finisher deposits them): each tile deposits their moves on the links
+    // it owns, from r, the record's displacement and q; tile 0 clears the
+    // count of the step after next
+    const int *irr_cnt;
+    int *irr_zero;
+    const double *irr_r, *irr_du, *irr_q;
+    const int *irr_order;
 };
 
 // Planes per z-chunk when the deposit is fused: up to 4, or up to 8 for the
@@ -280,7 +288,10 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         uint4 *accw = reinterpret_cast<uint4 *>(&DS->acc[0][0][0][0]);
 #pragma unroll
         for (int t = 0; t < kAccWords / 256; ++t) accw[threadIdx.x + 256 * t] = make_uint4(0u, 0u, 0u, 0u);
-        if (threadIdx.x == 0) DS->own_n = 0;
+        if (threadIdx.x == 0) {
+            DS->own_n = 0;
+            if (dep->irr_zero && tile == 0) *dep->irr_zero = 0;
+        }
         // list entries e < cap belong to this tile: read before the count is known
 #pragma unroll
         for (int j = 0; j < kPF; ++j) {
@@ -468,6 +479,19 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
 #pragma unroll
                 for (int q = 0; q < kWords; ++q) cn.raw[q] = src[q];
                 deposit_rec(h, cn, slot);
+            }
+            // the atomic-path ions' moves, on this tile's links
+            if (dep->irr_cnt) {
+                const int ni = *dep->irr_cnt;
+                const int *il = dep->irr_cnt + kIrrHead;
+                const int ex[3] = {min(TX, L - x0), ext[1], ext[2]};
+                for (int e = (int)threadIdx.x; e < ni; e += blockDim.x) {
+                    const int s = il[e];
+                    const int i = dep->irr_order ? dep->irr_order[s] : s;
+                    double u[3] = {dep->irr_r[3 * i], dep->irr_r[3 * i + 1], dep->irr_r[3 * i + 2]};
+                    const double du[3] = {dep->irr_du[3 * s], dep->irr_du[3 * s + 1], dep->irr_du[3 * s + 2]};
+                    deposit_ion_box<T, DTZ, TY>(L, dep->a, dep->irr_q[i], u, du, org, ex, DS->acc);
+                }
             }
         }
         __syncthreads();

@@ -330,6 +330,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     c->sort_every = 64;
     c->dipole_correction = true;
     c->final_forces = true;
+    c->irr = nullptr;
     c->self_scheme = MEMD_SELF_GREEN;
     c->fuse_deposit = true;
     c->hist_cap = kHistCap;
@@ -435,6 +436,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
         piece(&c->du_slot_nx, 3 * nn * sizeof(double));
         piece(&c->fq_nx, nn * fqb);
         piece(&c->dep_atomic_nx, nn * sizeof(int));
+        piece(&c->irr, 3 * (kIrrHead + nn) * sizeof(int));
     }
     size_t arena_bytes = 0;
     for (const auto &pc : pieces) arena_bytes += (pc.second + 255) / 256 * 256;
@@ -456,6 +458,8 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     }
     hipStream_t s = c->stream;
     if (c->fdone) hipMemsetAsync(c->fdone, 0, nn * sizeof(unsigned int), s);  // no launch is stamped 0
+    c->tile_irregular = c->irr != nullptr;
+    if (c->irr) hipMemsetAsync(c->irr, 0, 3 * (kIrrHead + nn) * sizeof(int), s);
     for (int b = 0; b < 2; ++b) {
         hipMemsetAsync(c->D[b], 0, fb, s);
         hipMemsetAsync(c->B[b], 0, fb, s);
@@ -666,9 +670,12 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
         CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx], e0, e1, dstep, seed, tstep, sigma,
                            fused, !recs_ready, fused ? dip_prev : nullptr, dip_nb, fused ? &mv : nullptr, !md));
         if (fused) {
-            prof_begin(c, F_DEPOSIT);
-            CK(launch_ion_finish(c, c->D[c->cur], c->D[nx], !md));
-            prof_end(c, F_DEPOSIT);
+            // (the ions' own dynamics needs no finisher once the tiles deposit the atomic path)
+            if (!md || !c->tile_irregular) {
+                prof_begin(c, F_DEPOSIT);
+                CK(launch_ion_finish(c, c->D[c->cur], c->D[nx], !md));
+                prof_end(c, F_DEPOSIT);
+            }
             std::swap(c->r, c->r_alt);  // the movers' positions are now the current ones
             if (pack_next) swap_record_sets(c);
             recs_ready = pack_next;
@@ -784,6 +791,7 @@ memd_status memd_md_step(memd_ctx *c, double *v, const double *mass, int nsteps)
     // forces of the current state (the permittivity may have changed since
     // the last ones were computed), the opening half kick, the first move
     CK(enqueue_dipole_forces(c));
+    if (records && c->tile_irregular) CK(launch_clear_irregular(c));
     CK(launch_md_ions(c, c->D[c->cur], nullptr, 0, false, dm, dv, 1, disp, true, records));
     for (int t = 0; t < nsteps; ++t) {
         MdHandoff h{records, false, nullptr, 0};

@@ -128,6 +128,13 @@ struct memd_ctx {
     int lists_key;
     int list_zero_key;  // shape whose list counts are all zero (-1: none)
     int *dep_atomic;
+    // The ions the atomic path holds, per step (index step mod 3): a count in
+    // a 128-byte line of its own, then their slots (irr_list).  Whatever
+    // writes a step's records appends its atomic-path ions; the leapfrog
+    // tiles of that step deposit their moves on the links they own; the
+    // leapfrog launch of step t clears the count of step t + 2.
+    int *irr;
+    bool tile_irregular;      // the tiles, not the finisher, deposit those ions' moves
     bool final_forces;        // a call ends with the forces of its final state (memd_set_final_forces)
     unsigned int *bad_moves;  // rejected displacement components (not finite or > L a)
     bool fuse_deposit;
@@ -170,6 +177,12 @@ namespace memd {
 // q r^{n+1} per mover wavefront into dip_out (nparts, set by the launch),
 // and with pack_next the next step's records (displacements disp_next, or
 // the Philox stream at t_next) into the second record set.
+// The count of the atomic-path ions of step `step` (its slots follow at +32).
+constexpr int kIrrHead = 32;
+inline int *irr_count(const memd_ctx *c, long step) {
+    return c->irr ? c->irr + (step % 3) * (kIrrHead + (size_t)(c->n > 0 ? c->n : 1)) : nullptr;
+}
+
 struct IonMoves {
     const double *disp_next;
     uint64_t seed;
@@ -207,6 +220,9 @@ hipError_t launch_build_lists(memd_ctx *c, bool pack, const double *disp, uint64
 // (no-op when the context has no fused deposit).
 hipError_t launch_ecell(memd_ctx *c);
 hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma);
+// Clears the count of the atomic-path ions of the current step (before its
+// records are written whole).
+hipError_t launch_clear_irregular(memd_ctx *c);
 // The ion side of a step after the fused leapfrog and its movers
 // (k_ion_finish): forces of the state the step started from (tile results,
 // or gathered from Dcur at r^n, plus the dipole term with the scalars' P),
