@@ -287,14 +287,16 @@ memd_status memd_set_options(memd_ctx *ctx, int fuse_deposit, int sort_every);
 /* Whether memd_step ends with the forces of the final state (on = 1, the
  * default).  With the fused deposit every step computes the forces of the
  * state it starts from inside the step (eq. force: the tiles gather the
- * lattice part and the self force while they hold E in LDS, the finisher
- * adds the dipole term and gathers the ions no tile took), and one more
- * force launch after the last step gives the final state's.  With on = 0
- * that launch is skipped, and memd_forces returns what the last step
- * computed: the forces of the state it started from (on the plain path,
- * which computes each new state's forces in its step, those of the final
- * state).  This exposes the in-step force computation to checks.
- * Errors: EINVAL (on not 0 or 1). */
+ * lattice part and the self force of the ions whose start cell they own
+ * while they hold E in LDS; the movers of the next step's launch add the
+ * dipole term, or, with the direct self subtraction, a finisher after the
+ * leapfrog computes them), and one more force launch after the last step
+ * gives the final state's.  With on = 0 that launch is skipped, and
+ * memd_forces returns the newest forces a step completed: those of the
+ * state two steps before the end (calls of three steps or more; one step
+ * before with the direct subtraction; on the plain path, which computes each
+ * new state's forces in its step, those of the final state).  This exposes
+ * the in-step force computation to checks.  Errors: EINVAL (on not 0 or 1). */
 memd_status memd_set_final_forces(memd_ctx *ctx, int on);
 /* The dipole correction of section "Periodicity" (on = 1, the default): the
  * uniform mode of D, which follows -P/V with P the dipole moment of the

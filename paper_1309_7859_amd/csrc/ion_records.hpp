@@ -59,7 +59,16 @@ __device__ __forceinline__ bool write_record_at(int L, double a, double qi, cons
     }
     if (atomic_path) {
         O.head[s] = make_int4(-1, 0, 0, 0);
-        if (O.icnt) O.ilist[atomicAdd(O.icnt, 1)] = s;
+        if (O.icnt) {
+            // the tiles take these ions' moves and forces from the atomic-path list
+            O.ilist[atomicAdd(O.icnt, 1)] = s;
+            IonFQ<T> fq;
+            fq.f[0] = (T)f0[0];
+            fq.f[1] = (T)f0[1];
+            fq.f[2] = (T)f0[2];
+            fq.q = (T)qi;
+            O.fq[s] = fq;
+        }
         return true;
     }
     const double a2 = a * a;
@@ -165,6 +174,17 @@ struct MoverArgs {
     unsigned int *bad;
     int *atomic_next;  // [n] by slot: the next step's ion left to the atomic path
     DepOut<T> out;     // the next step's records (cbin, list_fail: the lists' state)
+    // The forces of the state the previous launch started from, completed
+    // here (Ft_prev null: not): lattice part and self force from that
+    // launch's tiles (stamped fdone_prev == tag_prev), plus the dipole term
+    // with P_prev, into F by storage index (the finisher's arithmetic).
+    const double *Ft_prev;
+    const unsigned int *fdone_prev;
+    unsigned int tag_prev;
+    const double *P_prev;
+    const double *scal;
+    double V;
+    double *F;
 };
 
 // Slots [s0, s0 + count) by the workgroup's 256 threads, kMoverPerThread
@@ -179,6 +199,8 @@ __device__ __forceinline__ void move_ions(const MoverArgs<T> &M, int s0, int cou
     int sk[K], ik[K], ck[K], lfail[K], lcell[K];
     bool live[K];
     double u[K][3], du[K][3], dn[K][3], qk[K];
+    unsigned int fdp[K];  // the previous state's force stamp and result (Ft_prev)
+    double ftp[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         sk[k] = s0 + (int)threadIdx.x + 256 * k;
@@ -195,6 +217,9 @@ __device__ __forceinline__ void move_ions(const MoverArgs<T> &M, int s0, int cou
         qk[k] = M.q[ik[k]];
         lfail[k] = M.pack ? M.out.list_fail[s] : 0;
         lcell[k] = M.pack ? M.out.cbin[s] : 0;
+        fdp[k] = M.Ft_prev ? M.fdone_prev[s] : 0u;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ftp[k][d] = M.Ft_prev ? M.Ft_prev[3 * s + d] : 0.0;
     }
     if (M.pack) {
 #pragma unroll
@@ -222,6 +247,16 @@ __device__ __forceinline__ void move_ions(const MoverArgs<T> &M, int s0, int cou
         if (M.pack) {
             sanitize_move(dn[k], M.a, M.L, M.bad);
             M.atomic_next[s] = write_record_at<T>(M.L, M.a, qk[k], u[k], dn[k], s, M.out, lfail[k], lcell[k]) ? 1 : 0;
+        }
+    }
+    if (M.Ft_prev) {
+        const double w = M.scal[S_DIPW];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!live[k] || fdp[k] != M.tag_prev) continue;
+            double *F = M.F + 3 * (size_t)ik[k];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) F[d] = ftp[k][d] + qk[k] * (w * M.P_prev[d]) / (M.V * M.scal[S_EPSH + d]);
         }
     }
 #pragma unroll
@@ -277,6 +312,13 @@ inline MoverArgs<T> mover_args(const memd_ctx *c, const IonMoves &mv) {
     M.bad = c->bad_moves;
     M.atomic_next = c->dep_atomic_nx;
     M.out = dep_out<T>(c, true);
+    M.Ft_prev = nullptr;  // set by the launch when it completes the previous state's forces
+    M.fdone_prev = nullptr;
+    M.tag_prev = 0;
+    M.P_prev = nullptr;
+    M.scal = nullptr;
+    M.V = 0.0;
+    M.F = nullptr;
     return M;
 }
 

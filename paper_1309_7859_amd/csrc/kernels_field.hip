@@ -138,6 +138,7 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
                            IonMoves *moves, bool own_forces) {
     DepArgs P;
     const DepArgs *dp = nullptr;
+    unsigned int tag_prev = 0;
     if (with_deposit) {
         // the lists first (records read each ion's list cell), then the
         // records unless the previous launch's movers wrote them against these lists
@@ -158,15 +159,21 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
         P.own_forces = own_forces ? 1 : 0;
         P.fq = c->fq;
         P.ecell = c->ecell;
-        P.Ft = c->Ft;
-        P.fdone = c->fdone;
+        const bool odd = (c->step_index & 1) != 0;
+        P.Ft = c->fold_step && odd ? c->Ft_alt : c->Ft;
+        P.fdone = c->fold_step && odd ? c->fdone_alt : c->fdone;
+        tag_prev = c->force_tag;
         if (++c->force_tag == 0) c->force_tag = 1;  // 0 never marks a result
         P.tag = c->force_tag;
         P.G = c->scal + S_G;
         P.a = c->a;
         P.dip_prev = dip_prev;
         P.dip_nparts = dip_nparts;
-        P.P = c->scal + S_P;
+        P.P = c->scal + (c->fold_step ? S_PB + 3 * (int)(c->step_index & 1) : S_P);
+        P.ovf_mark = c->fold_step ? c->ovf_mark : nullptr;
+        P.V = c->V;
+        P.eta_uni = c->eta_uni;
+        P.epsh = c->scal + S_EPSH;
         P.irr_cnt = c->tile_irregular ? irr_count(c, c->step_index) : nullptr;
         P.irr_zero = c->tile_irregular ? irr_count(c, c->step_index + 2) : nullptr;
         P.irr_r = c->r;
@@ -177,9 +184,22 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
     }
     const bool with_moves = dp && moves;
     if (with_moves) moves->nparts = 4 * mover_blocks(c->n);
+    // the movers complete the forces of the state the previous launch started from
+    auto assemble = [&](auto &M) {
+        if (!(with_moves && c->fold_step && moves->assemble)) return;
+        const bool prev_odd = ((c->step_index - 1) & 1) != 0;
+        M.Ft_prev = prev_odd ? c->Ft_alt : c->Ft;
+        M.fdone_prev = prev_odd ? c->fdone_alt : c->fdone;
+        M.tag_prev = tag_prev;
+        M.P_prev = c->scal + S_PB + 3 * (prev_odd ? 1 : 0);
+        M.scal = c->scal;
+        M.V = c->V;
+        M.F = c->F;
+    };
     if (c->fp32) {
         MoverArgs<float> M{};
         if (with_moves) M = mover_args<float>(c, *moves);
+        assemble(M);
         const MoverArgs<float> *mp = with_moves ? &M : nullptr;
         switch (c->eta_mode) {
             case ETA_UNIFORM: return launch_lf_t<float, ETA_UNIFORM>(c, Din, Bin, Dout, Bout, e0, e1, dp, mp);
@@ -189,6 +209,7 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
     }
     MoverArgs<double> M{};
     if (with_moves) M = mover_args<double>(c, *moves);
+    assemble(M);
     const MoverArgs<double> *mp = with_moves ? &M : nullptr;
     switch (c->eta_mode) {
         case ETA_UNIFORM: return launch_lf_t<double, ETA_UNIFORM>(c, Din, Bin, Dout, Bout, e0, e1, dp, mp);

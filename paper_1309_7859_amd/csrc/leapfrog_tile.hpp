@@ -132,6 +132,13 @@ struct DepArgs {
     int *irr_zero;
     const double *irr_r, *irr_du, *irr_q;
     const int *irr_order;
+    // non-null: every ion whose start cell the tile owns gets its force here
+    // (the atomic-path ones too, from the list above); the owned ions beyond
+    // the LDS list are marked (ovf_mark[slot] = tag) and gathered from D^n
+    // after the march, with the permittivity of the launch, V and eps_h
+    unsigned int *ovf_mark;
+    double V, eta_uni;
+    const double *epsh;
 };
 
 // Planes per z-chunk when the deposit is fused: up to 4, or up to 8 for the
@@ -317,6 +324,7 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         if (lxo >= 0 && lxo < TX && lyo >= 0 && lyo < ext[1] && lzo >= 0 && lzo < ext[2]) {
             const int pos = atomicAdd(&DS->own_n, 1);
             if (pos < kOwnCap) DS->own[pos] = make_int2(slot, lxo | (lyo << 8) | (lzo << 16));
+            else if (dep->ovf_mark) dep->ovf_mark[slot] = dep->tag;
         }
     };
     // Whether one of the record's links lies on the tile: per axis group,
@@ -490,6 +498,13 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
                     const int i = dep->irr_order ? dep->irr_order[s] : s;
                     double u[3] = {dep->irr_r[3 * i], dep->irr_r[3 * i + 1], dep->irr_r[3 * i + 2]};
                     const double du[3] = {dep->irr_du[3 * s], dep->irr_du[3 * s + 1], dep->irr_du[3 * s + 2]};
+                    if (dep->ovf_mark) {
+                        int cc[3];
+                        double ff;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) fold(u[d], dep->a, L, cc[d], ff);
+                        own_rec(make_int4(pack_cell(cc[0], cc[1], cc[2]), 0, 0, 0), s);
+                    }
                     deposit_ion_box<T, DTZ, TY>(L, dep->a, dep->irr_q[i], u, du, org, ex, DS->acc);
                 }
             }
@@ -662,6 +677,31 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
 #pragma unroll
             for (int d = 0; d < 3; ++d) dep->Ft[3 * (size_t)own_slot + d] = Fl[d] - div_a(-pref * dS[d], dep->a);
             dep->fdone[own_slot] = dep->tag;
+        }
+        // owned ions beyond the LDS list (marked by own_rec): gathered from
+        // D^n, which this launch only reads, as the finisher would
+        if (dep->ovf_mark && dep->own_forces && DS->own_n > kOwnCap) {
+            const int ni = dep->irr_cnt ? *dep->irr_cnt : 0;
+            const EtaView<T> ev{EM, dep->eta_uni, A.eta_prof, A.eta_link};
+            const double zero[3] = {0.0, 0.0, 0.0};
+            for (int e = (int)threadIdx.x; e < dep_cnt + ni; e += blockDim.x) {
+                const int slot = e < dep_cnt ? dep->list[dep_base + e] : dep->irr_cnt[kIrrHead + e - dep_cnt];
+                if (slot < 0 || dep->ovf_mark[slot] != dep->tag) continue;
+                const int i = dep->irr_order ? dep->irr_order[slot] : slot;
+                const double u[3] = {dep->irr_r[3 * i], dep->irr_r[3 * i + 1], dep->irr_r[3 * i + 2]};
+                int cc[3];
+                double ff;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) fold(u[d], dep->a, L, cc[d], ff);
+                if ((unsigned)(cc[0] - x0) >= (unsigned)TX || (unsigned)(cc[1] - y0) >= (unsigned)ext[1] ||
+                    (unsigned)(cc[2] - z0) >= (unsigned)ext[2])
+                    continue;  // another tile's
+                double F[3];
+                force_ion<T>(L, Ns, dep->a, dep->V, dep->irr_q[i], u, A.Din, ev, dep->G, zero, dep->epsh, F);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) dep->Ft[3 * (size_t)slot + d] = F[d];
+                dep->fdone[slot] = dep->tag;
+            }
         }
     }
 }

@@ -331,6 +331,10 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     c->dipole_correction = true;
     c->final_forces = true;
     c->irr = nullptr;
+    c->Ft_alt = nullptr;
+    c->fdone_alt = nullptr;
+    c->ovf_mark = nullptr;
+    c->fold_step = false;
     c->self_scheme = MEMD_SELF_GREEN;
     c->fuse_deposit = true;
     c->hist_cap = kHistCap;
@@ -437,6 +441,9 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
         piece(&c->fq_nx, nn * fqb);
         piece(&c->dep_atomic_nx, nn * sizeof(int));
         piece(&c->irr, 3 * (kIrrHead + nn) * sizeof(int));
+        piece(&c->Ft_alt, 3 * nn * sizeof(double));
+        piece(&c->fdone_alt, nn * sizeof(unsigned int));
+        piece(&c->ovf_mark, nn * sizeof(unsigned int));
     }
     size_t arena_bytes = 0;
     for (const auto &pc : pieces) arena_bytes += (pc.second + 255) / 256 * 256;
@@ -460,6 +467,8 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     if (c->fdone) hipMemsetAsync(c->fdone, 0, nn * sizeof(unsigned int), s);  // no launch is stamped 0
     c->tile_irregular = c->irr != nullptr;
     if (c->irr) hipMemsetAsync(c->irr, 0, 3 * (kIrrHead + nn) * sizeof(int), s);
+    if (c->fdone_alt) hipMemsetAsync(c->fdone_alt, 0, nn * sizeof(unsigned int), s);
+    if (c->ovf_mark) hipMemsetAsync(c->ovf_mark, 0, nn * sizeof(unsigned int), s);
     for (int b = 0; b < 2; ++b) {
         hipMemsetAsync(c->D[b], 0, fb, s);
         hipMemsetAsync(c->B[b], 0, fb, s);
@@ -663,15 +672,27 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
         // with the fused deposit, the movers write the next step's records
         // only when it exists in this call and does not re-bin first
         const bool pack_next = fused && t + 1 < nsteps && !(c->sort_every > 0 && next % c->sort_every == 0);
+        // One launch per step: the tiles deposit every ion's move and compute
+        // every owned ion's lattice and self force, the movers of the next
+        // launch add the dipole term (from the third step of a call on: the
+        // first launch of a call has no dipole of its start state).  The
+        // direct self subtraction and the ions' own dynamics keep their own
+        // force paths.
+        const bool fold = fused && !md && c->tile_irregular && c->self_scheme == MEMD_SELF_GREEN;
         IonMoves mv{dd && pack_next ? dd + per * (t + 1) : nullptr, seed, tstep + 1u, sigma, pack_next,
-                    c->dip[c->step_index & 1], 0};
+                    c->dip[c->step_index & 1], 0, fold && t >= 2};
         hipEvent_t e0 = nullptr, e1 = nullptr;
         prof_pair(c, F_LEAPFROG, &e0, &e1);
-        CK(launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx], e0, e1, dstep, seed, tstep, sigma,
-                           fused, !recs_ready, fused ? dip_prev : nullptr, dip_nb, fused ? &mv : nullptr, !md));
+        c->fold_step = fold;
+        const hipError_t lf = launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx], e0, e1, dstep,
+                                              seed, tstep, sigma, fused, !recs_ready, fused ? dip_prev : nullptr,
+                                              dip_nb, fused ? &mv : nullptr, !md);
+        c->fold_step = false;
+        CK(lf);
         if (fused) {
-            // (the ions' own dynamics needs no finisher once the tiles deposit the atomic path)
-            if (!md || !c->tile_irregular) {
+            // (with the tiles depositing the atomic path, only the direct self
+            // subtraction's forces need the finisher)
+            if (!fold && (!md || !c->tile_irregular)) {
                 prof_begin(c, F_DEPOSIT);
                 CK(launch_ion_finish(c, c->D[c->cur], c->D[nx], !md));
                 prof_end(c, F_DEPOSIT);

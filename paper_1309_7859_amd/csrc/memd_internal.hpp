@@ -23,6 +23,7 @@ enum ScalarSlot : int {
     S_MEAN = 40,    // mean of D per direction [3]
     S_ETAMAX = 44,  // maximum eta over the links (1 / eps_min)
     S_DIPW = 45,    // weight of the dipole correction: 1 (on, the default) or 0 (off)
+    S_PB = 46,      // P of the state a fused launch starts from, by the step's parity [2][3]
     S_COUNT = 64
 };
 
@@ -123,6 +124,14 @@ struct memd_ctx {
     double *Ft;
     unsigned int *fdone;
     unsigned int force_tag;
+    // One launch per step (fold_step, set for each launch): the tile results
+    // of state t go to the buffers of t's parity (Ft and fdone for even t,
+    // Ft_alt and fdone_alt for odd), and the movers of the next launch
+    // complete them into F; ovf_mark: the owned ions a tile gathers itself.
+    double *Ft_alt;
+    unsigned int *fdone_alt;
+    unsigned int *ovf_mark;
+    bool fold_step;
     size_t list_entries;
     int list_tiles_max;
     int lists_key;
@@ -191,6 +200,7 @@ struct IonMoves {
     bool pack_next;
     double *dip_out;
     int nparts;
+    bool assemble;  // (one launch per step) complete the previous state's forces
 };
 
 // ---- launchers (field kernels) ----

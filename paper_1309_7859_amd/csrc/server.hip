@@ -75,6 +75,7 @@ size_t resident_bytes(int L, int n) {
         b += 2 * nn * (16 + 24 * sizeof(float) + 24 + 16 + 4);
         b += (12 * nn + 64 * tiles) * sizeof(int) + tiles * 128;  // tile lists and their counts
         b += nn * (2 * sizeof(int) + 24 + 4);                     // cbin, list_fail, Ft, fdone
+        b += nn * (24 + 2 * 4 + 3 * 4) + 3 * 32 * 4;              // Ft_alt, fdone_alt, ovf_mark, atomic-path lists
         b += Ns * sizeof(float);                                  // 12 / sum(eta) per site
     }
     return b;

@@ -1,9 +1,13 @@
-"""The forces each step computes inside itself on the fused path (eq. force:
-the tiles' lattice part and self force, the finisher's dipole term and its
-gathers for the ions no tile took) against the oracle.  memd_step normally
-ends with one more force launch for the final state, which hides them;
-memd_set_final_forces(0) skips it, so that memd_forces returns the forces of
-the state the last step started from."""
+"""The forces each step computes inside itself on the fused path (eq. force)
+against the oracle.  With the Green's-function self energy a step is one
+launch: its tiles compute the lattice part and the self force of every ion
+whose start cell they own (the atomic-path ions and those beyond a tile's
+LDS list gathered from D^n), and the movers of the next launch add the
+dipole term; with the direct subtraction the finisher computes them after
+the leapfrog.  memd_step normally ends with one more force launch for the
+final state, which hides them; memd_set_final_forces(0) skips it, so that
+memd_forces returns the newest forces a step completed: those of the state
+two steps before the end (one step before, with the direct subtraction)."""
 import numpy as np
 import pytest
 
@@ -18,17 +22,18 @@ def _gpu():
     require_gpu()
 
 
-def _check(S, G, disp, ftol, label, prec):
+def _check(S, G, disp, ftol, label, prec, lag=2):
     """Steps both sides through disp; the GPU with its final force launch
-    off must hold the oracle's forces of the state before the last step."""
+    off must hold the oracle's forces of the state `lag` steps before the end."""
     k = disp.shape[0]
     G.set_final_forces(False)
     G.step(disp, k)
-    for t in range(k - 1):
+    for t in range(k - lag):
         S.step(disp[t])
     F_before = S.forces()[0]
     err = force_err(G.forces(), F_before)
-    S.step(disp[k - 1])
+    for t in range(k - lag, k):
+        S.step(disp[t])
     G.set_final_forces(True)
     record("instep_forces", label=label, precision="fp32" if prec == memd.FP32_MIXED else "fp64", force_err=err)
     assert err <= ftol, (label, err)
@@ -79,13 +84,13 @@ def test_instep_forces_irregular_and_crowded(prec):
     S.self_scheme = "direct"
     G.set_self_scheme(memd.SELF_DIRECT)
     disp = rng.normal(0, 0.05, size=(4, n, 3))
-    _check(S, G, disp, ftol, "crowded_direct", prec)
+    _check(S, G, disp, ftol, "crowded_direct", prec, lag=1)
 
 
 def test_instep_forces_first_step_of_a_call():
-    """A call of one step computes no forces inside it (the previous call left
-    them): with the final launch off, the forces stay those of the state the
-    step started from, which the previous call computed."""
+    """A call of one step completes no forces inside it: with the final
+    launch off, the forces stay those the previous call (here the state's
+    upload) left, of the state the step started from."""
     L, n = 16, 40
     rng = np.random.default_rng(83)
     r = rng.uniform(0, L, size=(n, 3))
