@@ -75,9 +75,12 @@ def mover_bytes_per_ion(fp32: bool) -> int:
     list_fail, cbin, perm and the next displacement (given by the caller);
     write r^{n+1} and the next record (16-byte head, the first cell's 12
     values, the displacement, the fractional position and charge, the
-    atomic-path flag)."""
+    atomic-path flag); and, completing the force of the state the previous
+    launch started from, read that launch's tile force with its stamp and
+    write the whole force."""
     t = 4 if fp32 else 8
-    return (24 + 8 + 24 + 4 + 4 + 4 + 24) + (24 + 16 + 12 * t + 24 + 4 * t + 4)
+    return ((24 + 8 + 24 + 4 + 4 + 4 + 24) + (24 + 16 + 12 * t + 24 + 4 * t + 4)
+            + (24 + 4) + 24)
 
 
 def implementation_bytes(fp32: bool, sites: int, ions: int, fused: bool) -> int:
@@ -389,7 +392,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (round(traffic / lf_avg_s / 1e9, 1) if traffic else None),
-            "kernel": ("k_leapfrog_dep (Faraday + Ampere + tile-owned current deposit + ion movers)" if r["fused"]
+            "kernel": ("k_leapfrog_dep (Faraday + Ampere + tile-owned current deposit + forces + ion movers)" if r["fused"]
                        else "k_leapfrog (Faraday + Ampere)"),
             "algorithmic_bytes_per_launch": alg,
             "algorithmic_bytes_rule": f"{SITE_BYTES[args.precision]} B/site + {ION_BYTES[args.precision]} B/ion",
