@@ -57,8 +57,10 @@ __device__ __forceinline__ T eta_at(const LfArgs<T> &A, int d, int gz, size_t of
 // two cells) and its start cell c is within one cell of c_b along each axis:
 // then all its links have origins in [c - 1, c + 2], inside the boxes the
 // lists were built from, and the tiles listing it deposit it.  Other ions
-// (irregular ones, drifted ones, and any that did not fit a list) are
-// deposited by the ion finisher after the leapfrog with global atomics.
+// (irregular ones, drifted ones, and any that did not fit a list) take the
+// atomic path: every tile deposits the part of their moves on its own links
+// from the step's list of them (irr_cnt), or, without that list, the ion
+// finisher deposits them after the leapfrog with global atomics.
 //
 // A record (one per ion, in slot order): the head, with the start cell
 // packed as x | y << 10 | z << 20 (-1: nothing for the tiles), then one word
@@ -108,7 +110,8 @@ struct DepArgs {
     int cap;
     // forces of the state the step starts from, for the regular ions whose
     // start cell the tile owns: lattice part and self force into Ft[slot],
-    // fdone[slot] = tag (the dipole term is added by the ion finisher)
+    // fdone[slot] = tag (the dipole term is added by the ion finisher, or
+    // by the movers of the next launch)
     int own_forces;     // 0: the tiles compute no forces (the ions' own dynamics gathers them)
     const void *fq;     // [n] IonFQ<T> by slot
     const void *ecell;  // [Ns] T: 12 / (sum of eta over the cell's 12 edges)
@@ -162,7 +165,8 @@ __device__ __forceinline__ bool ion_regular(double a, const double (&u)[3], cons
 
 // Tile LDS of the fused deposit: the accumulator, and the ions whose start
 // cell the tile owns (slot, and the cell packed as lx | ly << 8 | lz << 16),
-// one per thread at most (ions past 256 get their forces in the ion finisher).
+// one per thread at most (ions past 256 are gathered after the march, or get
+// their forces in the ion finisher).
 constexpr int kOwnCap = 256;
 
 template <typename T, int R, int TZ = kDepTZ>
@@ -655,7 +659,7 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
     if constexpr (DEP) {
         // Force of the owned ion: lattice part from the captured E, as
         // force_ion sums it, then the self force (the dipole term is added by
-        // the ion finisher).
+        // the ion finisher, or by the movers of the next launch).
         if (own_slot >= 0) {
             const double f[3] = {(double)own_fq.f[0], (double)own_fq.f[1], (double)own_fq.f[2]};
             const double q = (double)own_fq.q;
