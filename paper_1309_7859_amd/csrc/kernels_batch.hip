@@ -46,9 +46,16 @@ __device__ __forceinline__ int find_rep(int count, int item) {
     return lo;
 }
 
-__global__ __launch_bounds__(256) void k_batch_leapfrog(const RepDesc *__restrict__ tab,
+// LDS of a leapfrog work item: a 64-site row tile, or whole rows of a narrow
+// lattice (RepDesc::xrows)
+union BatchSmem {
+    LfSmem<float, 1> tile;
+    RowSmem<float> rows;
+};
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_batch_leapfrog(const RepDesc *__restrict__ tab,
                                                         const int *__restrict__ hdr) {
-    __shared__ LfSmem<float, 1> U;
+    __shared__ BatchSmem U;
     const int total = hdr[1];
     const int count = stage_index(hdr, RANGE_TILES);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
@@ -77,10 +84,16 @@ __global__ __launch_bounds__(256) void k_batch_leapfrog(const RepDesc *__restric
         A.nty = R.nty;
         A.tz = R.tz;
         __syncthreads();  // the previous item's LDS use is over
-        if (R.eta_mode == ETA_UNIFORM)
-            leapfrog_tile<float, ETA_UNIFORM, 1>(A, tile_x, rest % R.nty, rest / R.nty, U);
-        else
-            leapfrog_tile<float, ETA_ZPROF, 1>(A, tile_x, rest % R.nty, rest / R.nty, U);
+        if (R.xrows > 0) {
+            if (R.eta_mode == ETA_UNIFORM)
+                leapfrog_rows<float, ETA_UNIFORM>(A, R.xrows, rest % R.nty, rest / R.nty, U.rows);
+            else
+                leapfrog_rows<float, ETA_ZPROF>(A, R.xrows, rest % R.nty, rest / R.nty, U.rows);
+        } else if (R.eta_mode == ETA_UNIFORM) {
+            leapfrog_tile<float, ETA_UNIFORM, 1>(A, tile_x, rest % R.nty, rest / R.nty, U.tile);
+        } else {
+            leapfrog_tile<float, ETA_ZPROF, 1>(A, tile_x, rest % R.nty, rest / R.nty, U.tile);
+        }
     }
 }
 

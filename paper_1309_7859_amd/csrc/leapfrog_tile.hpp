@@ -711,4 +711,160 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
 }
 
 
+// Lattices narrower than a wavefront (L < 64), where a 64-site row tile
+// would leave 64 - L lanes of every wavefront idle: a workgroup holds whole
+// rows of L sites, thread t on site x = t mod L of row t / L, xrows = 256 / L
+// rows (threads past xrows L idle), and marches through a z-chunk as
+// leapfrog_tile does, with the same arithmetic.  Along x the tile is the
+// whole lattice, so the stencil's x neighbours wrap inside it: no x halo.
+// (kRowSites: memd_internal.hpp)
+
+template <typename T>
+struct RowSmem {
+    T sX[2][3][kRowSites + 128];  // eta*D of two planes, rows y0 - 1 .. y0 + xrows: (xrows + 2) L values
+    T sB[3][kRowSites + 64];      // new B of the plane, rows y0 - 1 .. y0 + xrows - 1
+};
+
+template <typename T, int EM>
+__device__ __forceinline__ void leapfrog_rows(const LfArgs<T> &A, int xrows, int tile_y, int chunk,
+                                              RowSmem<T> &S) {
+    auto &sX = S.sX;
+    auto &sB = S.sB;
+    const int L = A.L;
+    const size_t Ns = A.Ns, LL = (size_t)L * L;
+    const int y0 = tile_y * xrows, z0 = chunk * A.tz;
+    const int z1 = min(z0 + A.tz, L);
+    const int t = (int)threadIdx.x;
+    const int r = t / L, x = t - r * L;
+    const bool live = r < xrows;           // the thread holds a site of the tile
+    const bool act = live && y0 + r < L;   // and stores it (rows past L wrap, as in leapfrog_tile)
+    const int gy = wrapc(y0 + r, L);
+    const int xp = x + 1 == L ? 0 : x + 1, xm = x == 0 ? L - 1 : x - 1;
+    const int yy = r + 1;
+    const T kB = A.kB, kD = A.kD;
+    // the halo row this thread stages: y0 - 1 (row 0) for r == 0, y0 + xrows
+    // (row xrows + 1) for r == 1
+    const bool halo = live && r < 2;
+    const int hrow = r == 0 ? 0 : xrows + 1;
+    const int hy = wrapc(r == 0 ? y0 - 1 : y0 + xrows, L);
+
+    struct PlaneRegs {
+        T d[3], e[3], hd[3], he[3];
+    };
+    auto fetch_plane = [&](int gz, PlaneRegs &p) {
+        if (!live) return;
+        const size_t off = (size_t)gz * LL + (size_t)gy * L + x;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            p.d[d] = A.Din[(size_t)d * Ns + off];
+            p.e[d] = eta_at<T, EM>(A, d, gz, off);
+        }
+        const size_t ho = (size_t)gz * LL + (size_t)hy * L + x;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            p.hd[d] = halo ? A.Din[(size_t)d * Ns + ho] : (T)0;
+            p.he[d] = halo ? eta_at<T, EM>(A, d, gz, ho) : (T)0;
+        }
+    };
+    auto store_plane = [&](int buf, const PlaneRegs &p) {
+        if (!live) return;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sX[buf][d][yy * L + x] = p.e[d] * p.d[d];
+        if (halo)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sX[buf][d][hrow * L + x] = p.he[d] * p.hd[d];
+    };
+
+    T Dc[3] = {(T)0, (T)0, (T)0}, prevB[2] = {(T)0, (T)0};
+    const int c0 = yy * L + x;  // the thread's own site in the LDS rows
+    // Prologue: new B_x, B_y of the plane below the chunk, for the own sites.
+    {
+        const int gzp = wrapc(z0 - 1, L);
+        {
+            PlaneRegs p0;
+            fetch_plane(gzp, p0);
+            store_plane(0, p0);
+        }
+        PlaneRegs p1;
+        fetch_plane(z0, p1);
+        T bo[2] = {(T)0, (T)0};
+        if (live) {
+            const size_t off = (size_t)gzp * LL + (size_t)gy * L + x;
+            bo[0] = A.Bin[off];
+            bo[1] = A.Bin[Ns + off];
+        }
+        store_plane(1, p1);
+        if (live)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Dc[d] = p1.d[d];
+        __syncthreads();
+        if (live) {
+            prevB[0] = bo[0] - kB * (sX[0][2][c0 + L] - sX[0][2][c0] - sX[1][1][c0] + sX[0][1][c0]);
+            prevB[1] = bo[1] - kB * (sX[1][0][c0] - sX[0][0][c0] - sX[0][2][yy * L + xp] + sX[0][2][c0]);
+        }
+        __syncthreads();
+    }
+
+    int cur = 1;
+    for (int k = z0; k < z1; ++k) {
+        const int nxt = cur ^ 1;
+        const size_t zoff = (size_t)k * LL;
+        PlaneRegs pn;
+        fetch_plane(wrapc(k + 1, L), pn);
+        T Bo[3] = {(T)0, (T)0, (T)0};
+        T hb0 = 0, hb1 = 0;
+        if (live) {
+            const size_t off = zoff + (size_t)gy * L + x;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Bo[d] = A.Bin[(size_t)d * Ns + off];
+            if (r == 0) {
+                // halo B^{n-1/2} of row y0 - 1: B_x, B_z
+                const size_t ho = zoff + (size_t)hy * L + x;
+                hb0 = A.Bin[ho];
+                hb1 = A.Bin[2 * Ns + ho];
+            }
+        }
+        store_plane(nxt, pn);
+        __syncthreads();
+
+        // Faraday: new B on the own sites, and B_x, B_z on the row y0 - 1
+        T Bn[3] = {(T)0, (T)0, (T)0};
+        if (live) {
+            Bn[0] = Bo[0] - kB * (sX[cur][2][c0 + L] - sX[cur][2][c0] - sX[nxt][1][c0] + sX[cur][1][c0]);
+            Bn[1] = Bo[1] - kB * (sX[nxt][0][c0] - sX[cur][0][c0] - sX[cur][2][yy * L + xp] + sX[cur][2][c0]);
+            Bn[2] = Bo[2] - kB * (sX[cur][1][yy * L + xp] - sX[cur][1][c0] - sX[cur][0][c0 + L] + sX[cur][0][c0]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sB[d][c0] = Bn[d];
+            if (act) {
+                const size_t off = zoff + (size_t)gy * L + x;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) A.Bout[(size_t)d * Ns + off] = Bn[d];
+            }
+            if (r == 0) {
+                sB[0][x] = hb0 - kB * (sX[cur][2][L + x] - sX[cur][2][x] - sX[nxt][1][x] + sX[cur][1][x]);
+                sB[2][x] = hb1 - kB * (sX[cur][1][xp] - sX[cur][1][x] - sX[cur][0][L + x] + sX[cur][0][x]);
+            }
+        }
+        __syncthreads();
+
+        // Ampere: new D on the own sites
+        if (live) {
+            const T dx = Dc[0] + kD * (Bn[2] - sB[2][c0 - L] - Bn[1] + prevB[1]);
+            const T dy = Dc[1] + kD * (Bn[0] - prevB[0] - Bn[2] + sB[2][yy * L + xm]);
+            const T dz = Dc[2] + kD * (Bn[1] - sB[1][yy * L + xm] - Bn[0] + sB[0][c0 - L]);
+            if (act) {
+                const size_t off = zoff + (size_t)gy * L + x;
+                A.Dout[off] = dx;
+                A.Dout[Ns + off] = dy;
+                A.Dout[2 * Ns + off] = dz;
+            }
+            prevB[0] = Bn[0];
+            prevB[1] = Bn[1];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Dc[d] = pn.d[d];
+        }
+        cur = nxt;
+    }
+}
+
 }  // namespace memd

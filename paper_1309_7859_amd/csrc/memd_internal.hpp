@@ -192,6 +192,10 @@ inline int *irr_count(const memd_ctx *c, long step) {
     return c->irr ? c->irr + (step % 3) * (kIrrHead + (size_t)(c->n > 0 ? c->n : 1)) : nullptr;
 }
 
+// Sites per leapfrog work item of a lattice narrower than a wavefront (the
+// batched leapfrog's tiles of whole rows: 256 / L rows of L < 64 sites).
+constexpr int kRowSites = 256;
+
 struct IonMoves {
     const double *disp_next;
     uint64_t seed;

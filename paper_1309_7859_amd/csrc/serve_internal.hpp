@@ -12,6 +12,7 @@ struct RepDesc {
     // geometry and tiling
     int L, n;
     int rows, tz;          // leapfrog tile: 64 x (4 rows) sites, tz planes per chunk
+    int xrows;             // > 0 (L < 64): tiles of xrows whole rows of L sites instead
     int ntx, nty, nzc;
     int tiles;             // leapfrog work items
     int dblocks;           // deposit work items: 16 ions each, 16 lanes per ion

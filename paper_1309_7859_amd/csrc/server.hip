@@ -203,8 +203,10 @@ void fill_desc(const Request *rq, int slot, int *d_steps, int tz, RepDesc &d) {
     d.n = c->n;
     d.rows = 1;  // the batched leapfrog holds tiles of one row per thread
     d.tz = std::min(tz, c->L);
-    d.ntx = (c->L + 63) / 64;
-    d.nty = (c->L + 4 * d.rows - 1) / (4 * d.rows);
+    // a lattice narrower than a wavefront: tiles of whole rows, 256 / L of them
+    d.xrows = c->L < 64 ? kRowSites / c->L : 0;
+    d.ntx = d.xrows > 0 ? 1 : (c->L + 63) / 64;
+    d.nty = d.xrows > 0 ? (c->L + d.xrows - 1) / d.xrows : (c->L + 4 * d.rows - 1) / (4 * d.rows);
     d.nzc = (c->L + d.tz - 1) / d.tz;
     d.tiles = d.ntx * d.nty * d.nzc;
     d.dblocks = c->n > 0 ? (c->n + kDepIons - 1) / kDepIons : 1;
@@ -320,6 +322,7 @@ hipError_t tune_batch_depth(memd_server *s) {
             memset(&d, 0, sizeof(d));
             d.L = L;
             d.rows = 1;
+            d.xrows = 0;
             d.tz = tz;
             d.ntx = 1;
             d.nty = L / 4;

@@ -190,6 +190,12 @@ def test_short_replicas_match_oracle():
     for no steps) against the oracle."""
     specs = [spec(k, L, n, steps, "zsite" if k % 2 else "uniform", 15.0, 0.0, seed=900 + k)
              for k, (L, n, steps) in enumerate([(16, 60, 0), (24, 90, 1), (16, 120, 2), (32, 40, 1)])]
+    _check_against_oracle(specs)
+
+
+def _check_against_oracle(specs):
+    """Serves the replicas in one mix and compares each with the oracle fed
+    the same seeded displacements (FP32 tolerances)."""
     out = _served(specs, solve_tol=1e-12)
     assert out["done"] == len(specs) and out["failed"] == 0
     for k, sp in enumerate(specs):
@@ -207,6 +213,16 @@ def test_short_replicas_match_oracle():
         assert force_err(res["F"], S.forces()[0]) <= 1e-4, (k, sp.steps)
         errs = energy_err(res["E"], S.energy())
         assert max(errs.values()) <= 1e-4, (k, errs)
+
+
+def test_narrow_row_tiles_match_oracle():
+    """Lattices narrower than a wavefront run as tiles of 256 // L whole rows:
+    L = 8 (one tile holds every row), 20 and 40 (a shorter last tile), 63
+    (four rows per tile, three in the last), in one mix with both
+    permittivity kinds, against the oracle."""
+    specs = [spec(k, L, n, steps, "zsite" if k % 2 else "uniform", 15.0, 0.0, seed=950 + k)
+             for k, (L, n, steps) in enumerate([(8, 30, 12), (20, 80, 10), (40, 300, 8), (63, 500, 6)])]
+    _check_against_oracle(specs)
 
 
 def test_batch_depth_tuned_and_cached(tmp_path):
