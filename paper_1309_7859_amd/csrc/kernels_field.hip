@@ -784,7 +784,9 @@ hipError_t launch_ecell(memd_ctx *c) {
 hipError_t launch_salt(memd_ctx *c) {
     hipError_t e;
     double *cnt = c->salt_cnt;
-    if ((e = launch_spread_dense(c, false, cnt)) != hipSuccess) return e;
+    // (the audit that ended the previous step may have written the counts)
+    if (c->salt_cnt_step != c->step_index && (e = launch_spread_dense(c, false, cnt)) != hipSuccess) return e;
+    c->salt_cnt_step = -1;
     const double a3 = c->a * c->a * c->a;
     const int L = c->L;
     const int tiles = ((L + 63) / 64) * ((L + 3) / 4) * ((L + kSaltTZ - 1) / kSaltTZ);

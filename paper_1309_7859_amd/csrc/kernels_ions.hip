@@ -451,16 +451,24 @@ hipError_t launch_spread(memd_ctx *c, const double *charges_or_null, double *dst
 constexpr int kSpTY = 4, kSpTZ = 8;
 constexpr int kSpRows = (kSpTY + 3) * (kSpTZ + 3);
 
+// With TWO, the same pass also assigns unit weights into dst2 (the ion
+// counts of the salt permittivity beside the charge density of the audit).
+template <bool TWO>
 __global__ __launch_bounds__(256) void k_spread_tile(int n, int L, double a, const double *__restrict__ q,
                                                      const double *__restrict__ r, const int *__restrict__ start,
-                                                     int *__restrict__ drifted, double *__restrict__ dst) {
+                                                     int *__restrict__ drifted, double *__restrict__ dst,
+                                                     double *__restrict__ dst2) {
     __shared__ double acc[kSpTZ][kSpTY][64];
+    __shared__ double acc2[TWO ? kSpTZ : 1][TWO ? kSpTY : 1][TWO ? 64 : 1];
     __shared__ int row_beg[kSpRows], row_off[kSpRows + 1];
     const int ntx = (L + 63) >> 6, nty = (L + kSpTY - 1) / kSpTY;
     const int tile = blockIdx.x;
     const int x0 = (tile % ntx) * 64, y0 = ((tile / ntx) % nty) * kSpTY, z0 = (tile / (ntx * nty)) * kSpTZ;
     double *accf = &acc[0][0][0];
-    for (int t = threadIdx.x; t < kSpTZ * kSpTY * 64; t += blockDim.x) accf[t] = 0.0;
+    for (int t = threadIdx.x; t < kSpTZ * kSpTY * 64; t += blockDim.x) {
+        accf[t] = 0.0;
+        if constexpr (TWO) (&acc2[0][0][0])[t] = 0.0;
+    }
     if (threadIdx.x < kSpRows) {
         const int iy = threadIdx.x % (kSpTY + 3), iz = threadIdx.x / (kSpTY + 3);
         const int row = wrapc(y0 - 2 + iy, L) + L * wrapc(z0 - 2 + iz, L);
@@ -508,6 +516,7 @@ __global__ __launch_bounds__(256) void k_spread_tile(int n, int L, double a, con
             if ((unsigned)lx < 64u && (unsigned)ly < (unsigned)kSpTY && (unsigned)lz < (unsigned)kSpTZ) {
                 const double w = lin_w(ox, ff[0]) * lin_w(oy, ff[1]) * lin_w(oz, ff[2]);
                 atomicAdd(&acc[lz][ly][lx], qi * w);
+                if constexpr (TWO) atomicAdd(&acc2[lz][ly][lx], w);
             }
         }
     }
@@ -515,35 +524,49 @@ __global__ __launch_bounds__(256) void k_spread_tile(int n, int L, double a, con
     for (int t = threadIdx.x; t < kSpTZ * kSpTY * 64; t += blockDim.x) {
         const int lx = t & 63, ly = (t >> 6) % kSpTY, lz = t / (64 * kSpTY);
         const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-        if (x < L && y < L && z < L) dst[((size_t)z * L + y) * L + x] = acc[lz][ly][lx];
+        if (x < L && y < L && z < L) {
+            dst[((size_t)z * L + y) * L + x] = acc[lz][ly][lx];
+            if constexpr (TWO) dst2[((size_t)z * L + y) * L + x] = acc2[lz][ly][lx];
+        }
     }
 }
 
 __global__ __launch_bounds__(256) void k_spread_drifted(int n, int L, double a, const double *__restrict__ q,
                                                         const double *__restrict__ r,
-                                                        const int *__restrict__ drifted, double *__restrict__ dst) {
+                                                        const int *__restrict__ drifted, double *__restrict__ dst,
+                                                        double *__restrict__ dst2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !drifted[i]) return;
     const double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
     spread_ion(L, a, q ? q[i] : 1.0, u, dst);
+    if (dst2) spread_ion(L, a, 1.0, u, dst2);
 }
 
 // dst <- linear assignment of the ions (charges q, or 1 each without
-// `weighted`) onto the vertices; every vertex is written.
-hipError_t launch_spread_dense(memd_ctx *c, bool weighted, double *dst) {
+// `weighted`) onto the vertices; every vertex is written.  With dst2 (and
+// `weighted`), the same pass also writes the unit-weight assignment (ion
+// counts) into dst2.
+hipError_t launch_spread_dense(memd_ctx *c, bool weighted, double *dst, double *dst2) {
     const double *q = weighted ? c->q : nullptr;
     if (c->n > 0 && c->sorted && c->L >= 16) {
         const int L = c->L, nb = L * L;
         const int tiles = ((L + 63) / 64) * ((L + kSpTY - 1) / kSpTY) * ((L + kSpTZ - 1) / kSpTZ);
-        hipLaunchKernelGGL(k_spread_tile, dim3(tiles), dim3(kThreads), 0, c->stream, c->n, L, c->a, q, c->r,
-                           c->bins + nb, c->drift, dst);
+        if (dst2)
+            hipLaunchKernelGGL(k_spread_tile<true>, dim3(tiles), dim3(kThreads), 0, c->stream, c->n, L, c->a, q,
+                               c->r, c->bins + nb, c->drift, dst, dst2);
+        else
+            hipLaunchKernelGGL(k_spread_tile<false>, dim3(tiles), dim3(kThreads), 0, c->stream, c->n, L, c->a, q,
+                               c->r, c->bins + nb, c->drift, dst, nullptr);
         hipLaunchKernelGGL(k_spread_drifted, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, L, c->a,
-                           q, c->r, c->drift, dst);
+                           q, c->r, c->drift, dst, dst2);
         return hipGetLastError();
     }
     hipError_t e = launch_fill(c->stream, dst, 0.0, c->Ns);
     if (e != hipSuccess) return e;
-    return launch_spread(c, q, dst);
+    if ((e = launch_spread(c, q, dst)) != hipSuccess) return e;
+    if (!dst2) return hipSuccess;
+    if ((e = launch_fill(c->stream, dst2, 0.0, c->Ns)) != hipSuccess) return e;
+    return launch_spread(c, nullptr, dst2);
 }
 
 // ------------------------------------------------------------------ dipole
@@ -1121,7 +1144,6 @@ __device__ void fin_sum(const double *partials, int nblk, double (&out)[W]) {
     strided_sum<W>(partials, nblk, threadIdx.x, blockDim.x, out);
     block_sum<W>(out);
 }
-
 __global__ void k_fin_dipole(const double *partials, int nblk, double *P) {
     double s[3];
     fin_sum<3>(partials, nblk, s);

@@ -231,12 +231,15 @@ memd_status ensure_eta_link(memd_ctx *c) {
 // S_ENERGY) and in the history slots when given.  dip (nparts partials):
 // the movers' dipole partials of the state, summed into P by the finaliser;
 // null: P is in the scalars already.
+// cnt (with audit): the same charge-assignment pass also writes the ion
+// counts of the salt permittivity there (for a recompute that follows on
+// the same positions).
 hipError_t enqueue_observables(memd_ctx *c, bool audit, bool energy, double *audit_hist, double *energy_hist,
-                               const double *dip = nullptr, int dipn = 0) {
+                               const double *dip = nullptr, int dipn = 0, double *cnt = nullptr) {
     hipError_t e;
     int fb = 0, ib = 0;
     prof_begin(c, audit ? F_AUDIT : F_ENERGY);
-    if (audit && (e = launch_spread_dense(c, true, c->rho)) != hipSuccess) return e;
+    if (audit && (e = launch_spread_dense(c, true, c->rho, cnt)) != hipSuccess) return e;
     if ((e = launch_field_obs(c, audit, energy, c->partials, &fb)) != hipSuccess) return e;
     if (energy && (e = launch_uself(c, ion_partials(c), &ib)) != hipSuccess) return e;
     e = launch_finalize_obs(c, c->partials, fb, ion_partials(c), ib, dip, dipn, audit, energy, audit_hist,
@@ -330,6 +333,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     c->sort_every = 64;
     c->dipole_correction = true;
     c->final_forces = true;
+    c->salt_cnt_step = -1;
     c->irr = nullptr;
     c->Ft_alt = nullptr;
     c->fdone_alt = nullptr;
@@ -602,6 +606,7 @@ memd_status memd_initial_gauss_solve(memd_ctx *c, double tol, int max_iter, int 
     CK(hipStreamSynchronize(c->stream));
     c->ready = true;
     c->step_index = 0;
+    c->salt_cnt_step = -1;
     return st;
 }
 
@@ -727,9 +732,15 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
                 eh = c->hist_energy + 5 * (size_t)slot;
                 if (c->hist_energy_n < c->hist_cap) ++c->hist_energy_n;
             }
-            // with the fused deposit, P of this state is in the movers' partials
+            // with the fused deposit, P of this state is in the movers' partials;
+            // when the next step starts with the salt permittivity, the audit's
+            // charge assignment also gives its ion counts (same positions)
+            double *cnt = audit_now && c->salt_cnt && c->salt_every > 0 && next % c->salt_every == 0
+                              ? c->salt_cnt
+                              : nullptr;
             CK(enqueue_observables(c, audit_now, energy_now, ah, eh, energy_now ? dip_prev : nullptr,
-                                   energy_now ? dip_nb : 0));
+                                   energy_now ? dip_nb : 0, cnt));
+            c->salt_cnt_step = cnt ? next : -1;
         }
         c->step_index = next;
     }
@@ -959,6 +970,7 @@ memd_status memd_set_state(memd_ctx *c, const double *D, const double *B, const 
         }
         CK(copy_in(c, c->r, r, 3 * (size_t)c->n * sizeof(double)));
         CK(launch_bin_ions(c));
+        c->salt_cnt_step = -1;  // counts of the old positions
     }
     if (!c->c_fixed) {
         c->c = 0.25 * (c->a / c->dt) * std::sqrt(c->eps_min / 3.0);

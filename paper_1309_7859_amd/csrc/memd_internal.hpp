@@ -81,6 +81,7 @@ struct memd_ctx {
     int self_scheme;         // memd_self_scheme
     double salt_w, salt_slope, salt_floor;
     double *salt_cnt;  // FP64 [Ns]: ion counts of the salt permittivity
+    long salt_cnt_step;  // salt_cnt already holds the counts of the positions at this step (-1: none)
 
     // fields: ping-pong buffers, cur holds the live state
     void *D[2];
@@ -282,7 +283,7 @@ hipError_t launch_spread_raw(hipStream_t s, int n, int L, double a, const double
                              double *dst);
 // dst <- the assignment of every ion (charges, or 1 each without weighted);
 // writes every vertex (no global atomics once the ions are in bin order).
-hipError_t launch_spread_dense(memd_ctx *c, bool weighted, double *dst);
+hipError_t launch_spread_dense(memd_ctx *c, bool weighted, double *dst, double *dst2 = nullptr);
 hipError_t launch_dipole(memd_ctx *c, double *partials, int *nblk);
 hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk);
 // Row binning of the ions (order, slot, row counts/starts); with

@@ -269,6 +269,52 @@ def test_salt_permittivity_parity():
     assert max(errs.values()) <= 1e-10
 
 
+@pytest.mark.parametrize("prec", [memd.FP64, memd.FP32_MIXED])
+def test_salt_counts_from_the_audit(prec):
+    """When an audit inside a call ends the step before a salt recompute, its
+    charge-assignment pass also writes the ion counts that the recompute then
+    uses: within a call (salt every 4 steps, audit every 2), across a call
+    boundary, and not after memd_set_state has moved ions in between (the
+    recompute then assigns the new positions itself)."""
+    L, n = 16, 400
+    rng = np.random.default_rng(19)
+    r = rng.uniform(0, L, size=(n, 3))
+    q = np.repeat([1.0, -1.0, 2.0, -2.0], n // 4)
+    S, G = pair(L, q, r, eps_min=70.0, precision=prec, audit_every=2)
+    S.set_eps_salt()
+    G.set_salt(80.0, 15.0, 1.0, every=4)
+    S.initial_solve(1e-13)
+    share_state(S, G)
+    fp32 = prec == memd.FP32_MIXED
+    disp = rng.normal(0, 0.05, size=(16, n, 3))
+
+    def oracle_steps(t0, t1):
+        for t in range(t0, t1):
+            if t % 4 == 0:
+                S.set_eps_salt()
+            S.step(disp[t])
+
+    G.step(disp[:8], 8)
+    oracle_steps(0, 8)
+    G.step(disp[8:12], 4)
+    oracle_steps(8, 12)
+    # move a quarter of the ions by half a spacing: the counts the last
+    # audit wrote are stale
+    D, B, rr = S.state()
+    rr = rr.reshape(-1, 3).copy()
+    rr[::4, 0] += 0.5
+    S.set_state(D, B, rr)
+    share_state(S, G)
+    G.step(disp[12:], 4)
+    oracle_steps(12, 16)
+    Fo, _ = S.forces()
+    assert force_err(G.forces(), Fo) <= (1e-4 if fp32 else 1e-10)
+    errs = energy_err(G.energy(), S.energy())
+    assert max(errs.values()) <= (1e-4 if fp32 else 1e-10), errs
+    E = S.eta * G.state()[0]
+    assert np.max(np.abs(E - S.eta * S.D)) <= (1e-4 if fp32 else 1e-10) * np.max(np.abs(S.eta * S.D))
+
+
 @pytest.mark.parametrize("L", [2, 3, 4, 5])
 def test_large_moves_wraparound(L):
     """Face crossings of several cells per axis, wrap-around, unfolded positions."""
