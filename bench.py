@@ -456,8 +456,8 @@ def main():
         lf2 = r2["lf_ms"] / 1e3 / max(r2["lf_n"], 1)
         b2 = algorithmic_bytes("fp32", w2.sites, w2.n)
         out["diag_256"] = {
-            "workload": "c4 recipe at 256^3: 8e5 ions (10% +-2), salt eps, re-binning, audit and energy "
-                        "every 50 steps, FP32 fields",
+            "workload": f"c4 recipe at 256^3: 8e5 ions (10% +-2), salt eps, audit and energy every {CADENCE} "
+                        f"steps, re-binning every {REBIN_EVERY}, FP32 fields",
             "value": round(w2.sites * args.diag256_steps / r2["wall"], 1), "unit": "site-updates/s",
             "ms_per_step": round(r2["wall"] * 1e3 / args.diag256_steps, 5),
             "steps": args.diag256_steps,
