@@ -44,6 +44,9 @@ CADENCE = 50
 # the ions are re-binned (and the tile lists rebuilt) every REBIN_EVERY steps,
 # a multiple of the cadence, so that re-binnings fall on cadence steps
 REBIN_EVERY = 2 * CADENCE
+# under their own dynamics the ions move ballistically and leave the tile
+# lists' one-cell margin sooner: re-binned every MD_REBIN_EVERY steps
+MD_REBIN_EVERY = 16
 PROFILE_EVERY = 10
 
 # Algorithmic bytes of a step (each value read once and written once):
@@ -239,11 +242,12 @@ def md_run(w, steps, warmup, tile=None):
     """The c4 system with the ions' own dynamics instead of prescribed moves
     (memd_md_step: velocity Verlet under the MEMD forces; mass 100 and
     initial velocities N(0, 2) per component, so that a step moves an ion
-    about as far as the prescribed displacements do).  Per step: a half kick
-    with the move of the step, the step (records, leapfrog with the deposit,
-    finisher), the forces of the new state, the second half kick.  The ions
-    move ballistically here, so they are re-binned every 16 steps rather than
-    64 (measured: 0.092 ms per step at 64, 0.083 at 32, 0.080 at 16 and 8)."""
+    about as far as the prescribed displacements do).  Per step: the
+    leapfrog with the deposit of the step's move, then the forces of the new
+    state with both half kicks and the next move's records.  The ions move
+    ballistically here, so they are re-binned every MD_REBIN_EVERY = 16
+    steps (measured: 0.0647 ms per step at 8, 0.0624-0.0625 at 16, 0.0651-0.0653
+    at 24, 0.0813 at 32)."""
     import torch
     from paper_1309_7859_amd import memd
     from paper_1309_7859_amd import workloads as W
@@ -257,7 +261,7 @@ def md_run(w, steps, warmup, tile=None):
         memd.memd_set_tiling(G.ctx, tile[0], tile[1])
     else:
         memd.memd_autotune(G.ctx, 10, None)
-    memd.memd_set_options(G.ctx, 1, 16)
+    memd.memd_set_options(G.ctx, 1, MD_REBIN_EVERY)
     rng = np.random.default_rng(w.seed + 1)
     v = torch.from_numpy(rng.normal(0.0, 2.0, size=(w.n, 3))).to("cuda").contiguous()
     m = torch.full((w.n,), 100.0, dtype=torch.float64, device="cuda")
