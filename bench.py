@@ -14,8 +14,8 @@ holds at least one of each of these whatever its length.  Inputs (including all 
 are resident in HBM before timing.
 
 Prints one JSON line: value = lattice-site updates per second (whole job),
-plus ion-steps/s, the leapfrog kernel's roofline object (HIP-event timing of
-one launch in ten in the timed region) on the algorithmic bytes per site and
+plus ion-steps/s, the leapfrog kernel's roofline object (HIP events over the
+runs of one-launch steps in the timed region) on the algorithmic bytes per site and
 per ion, an on-box stream-copy ceiling, and the FP64 CPU oracle's throughput
 on a bounded sample of the same workload; beside them the FP64 variant over
 the same trajectory (and the FP32 path's error on each output against it),
@@ -171,8 +171,10 @@ def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None, solve_tol=1e-12, 
     if pre:
         memd.memd_step(G.ctx, base, pre)
     torch.cuda.synchronize()
-    # HIP events ride on one leapfrog launch in PROFILE_EVERY (each timed
-    # launch costs a few microseconds more than an untimed one)
+    # The steps that are one leapfrog launch and nothing else are timed in
+    # runs (an event pair around each run of them, every launch counted);
+    # one in PROFILE_EVERY of the other leapfrog launches (those beside the
+    # cadence work) carries events of its own, the first of the call excepted
     memd.memd_profile_enable(G.ctx, ["leapfrog"], PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -404,7 +406,9 @@ def main():
             "algorithmic_bytes_per_launch": alg,
             "algorithmic_bytes_rule": f"{SITE_BYTES[args.precision]} B/site + {ION_BYTES[args.precision]} B/ion",
             "avg_launch_us": round(lf_avg_s * 1e6, 2),
-            "launches": r["lf_n"], "timed_every": PROFILE_EVERY,
+            "launches": r["lf_n"],
+            "timing": "HIP events around each run of one-launch steps in the timed window (all their "
+                      f"launches), plus one in {PROFILE_EVERY} of the launches beside cadence work",
             "implementation_bytes_per_launch": impl,
             "implementation_frac": round(impl / lf_avg_s / 1e9 / HBM_PEAK_GBS, 4),
             "tile": {"x": 64, "y": 4 * r["tile"][0], "z_chunk": r["tile"][1],

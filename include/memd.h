@@ -262,11 +262,14 @@ memd_status memd_get_params(memd_ctx *ctx, double *c, double eps_h[3], double *e
  * launches of the kernel families (0 leapfrog, 1 deposit, 2 forces, 3 audit,
  * 4 energy, 5 dipole, 6 salt).  mask is a bit mask (1 << family) of the
  * families to time, -1 all of them, 0 stops timing; every >= 1 times one
- * launch in `every` of each family (the leapfrog's events ride on its own
- * launch; the other families use marker events, which cost several
- * microseconds each).  Each call starts a fresh collection.
- * memd_profile_read waits for the stream and returns the total milliseconds
- * and the number of timed launches of one family. */
+ * launch in `every` of each family (the other families use marker events,
+ * which cost several microseconds each).  The leapfrog family is timed in
+ * runs: consecutive steps that are one fused launch and nothing else are
+ * bracketed by one marker pair per run, and every launch of the run counts;
+ * a leapfrog launch outside such runs gets events riding on its own launch,
+ * one in `every`, except the first launch of a call.  Each call starts a
+ * fresh collection.  memd_profile_read waits for the stream and returns the
+ * total milliseconds and the number of timed launches of one family. */
 memd_status memd_profile_enable(memd_ctx *ctx, int mask, int every);
 memd_status memd_profile_read(memd_ctx *ctx, int family, double *total_ms, long *launches);
 

@@ -115,19 +115,27 @@ static hipError_t prof_event(memd_ctx *c, int fam, hipEvent_t *e) {
     return hipEventCreate(e);
 }
 
-void prof_begin(memd_ctx *c, int fam) {
+// A marker event opening a timed interval of family fam on the stream.
+static void prof_open(memd_ctx *c, int fam) {
     auto &P = c->prof[fam];
-    P.open = false;
-    if (!prof_take(c, fam)) return;
     hipEvent_t e;
     if (prof_event(c, fam, &e) == hipSuccess) {
         if (hipEventRecord(e, c->stream) == hipSuccess) {
             P.start.push_back(e);
+            P.count.push_back(0);
             P.open = true;
         } else {
             hipEventDestroy(e);
         }
     }
+}
+
+void prof_begin(memd_ctx *c, int fam) {
+    auto &P = c->prof[fam];
+    P.open = false;
+    if (!prof_take(c, fam)) return;
+    prof_open(c, fam);
+    if (P.open) P.count.back() = 1;
 }
 
 void prof_end(memd_ctx *c, int fam) {
@@ -141,7 +149,23 @@ void prof_end(memd_ctx *c, int fam) {
         if (e) hipEventDestroy(e);
         hipEventDestroy(P.start.back());
         P.start.pop_back();
+        P.count.pop_back();
     }
+}
+
+// Runs of leapfrog launches with no other launch between them (steps that
+// do nothing but the one fused launch) are timed whole: a marker before the
+// first launch of the run and one after its last, so that the interval holds
+// those launches back to back and nothing else.  Only the launches of such
+// runs are counted.
+static void prof_run_enter(memd_ctx *c) {
+    if (!c->prof_on || !(c->prof_mask & (1u << F_LEAPFROG))) return;
+    if (!c->prof[F_LEAPFROG].open) prof_open(c, F_LEAPFROG);
+    if (c->prof[F_LEAPFROG].open) ++c->prof[F_LEAPFROG].count.back();
+}
+
+static void prof_run_close(memd_ctx *c) {
+    if (c->prof[F_LEAPFROG].open) prof_end(c, F_LEAPFROG);
 }
 
 // A start/stop event pair attached to one launch (hipExtLaunchKernelGGL
@@ -157,6 +181,7 @@ void prof_pair(memd_ctx *c, int fam, hipEvent_t *e0, hipEvent_t *e1) {
     }
     c->prof[fam].start.push_back(*e0);
     c->prof[fam].stop.push_back(*e1);
+    c->prof[fam].count.push_back(1);
 }
 
 void prof_clear(memd_ctx *c) {
@@ -166,6 +191,7 @@ void prof_clear(memd_ctx *c) {
         for (auto e : c->prof[f].pool) hipEventDestroy(e);
         c->prof[f].start.clear();
         c->prof[f].stop.clear();
+        c->prof[f].count.clear();
         c->prof[f].pool.clear();
         c->prof[f].seen = 0;
         c->prof[f].open = false;
@@ -656,7 +682,20 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
     bool recs_ready = md && md->recs_ready;
     const double *dip_prev = nullptr;
     int dip_nb = 0;
+    bool alone = false;
     for (int t = 0; t < nsteps; ++t) {
+        {
+            // a step that is its one fused launch and nothing else continues
+            // the current timed run of leapfrog launches; any other ends it
+            const long nx_i = c->step_index + 1;
+            const bool fold0 = fused_deposit_ok(c) && !md && c->tile_irregular && c->self_scheme == MEMD_SELF_GREEN;
+            alone = fold0 && recs_ready && c->lists_key == c->lf_rows * 4096 + c->lf_tz &&
+                    !(c->salt_every > 0 && c->step_index % c->salt_every == 0) &&
+                    !(c->sort_every > 0 && c->step_index % c->sort_every == 0) &&
+                    !(c->p.audit_every > 0 && nx_i % c->p.audit_every == 0) &&
+                    !(c->p.energy_every > 0 && nx_i % c->p.energy_every == 0);
+            if (!alone) prof_run_close(c);
+        }
         if (c->salt_every > 0 && c->step_index % c->salt_every == 0) {
             prof_begin(c, F_SALT);
             CK(launch_salt(c));
@@ -687,7 +726,13 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
         IonMoves mv{dd && pack_next ? dd + per * (t + 1) : nullptr, seed, tstep + 1u, sigma, pack_next,
                     c->dip[c->step_index & 1], 0, fold && t >= 2};
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        prof_pair(c, F_LEAPFROG, &e0, &e1);
+        if (alone) {
+            prof_run_enter(c);
+        } else if (t > 0) {
+            // (the first launch of a call is not sampled: the GPU may be idle
+            // and its start event taken before the host has issued the kernel)
+            prof_pair(c, F_LEAPFROG, &e0, &e1);
+        }
         c->fold_step = fold;
         const hipError_t lf = launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx], e0, e1, dstep,
                                               seed, tstep, sigma, fused, !recs_ready, fused ? dip_prev : nullptr,
@@ -744,6 +789,7 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
         }
         c->step_index = next;
     }
+    prof_run_close(c);
     if (md) {
         md->gathered = dip_prev == nullptr;  // the plain path gathered them after its deposit
         md->dip = dip_prev;
@@ -1032,13 +1078,15 @@ memd_status memd_profile_read(memd_ctx *c, int family, double *total_ms, long *l
     const auto &P = c->prof[family];
     const size_t m = P.start.size() < P.stop.size() ? P.start.size() : P.stop.size();
     double tot = 0.0;
+    long cnt = 0;
     for (size_t t = 0; t < m; ++t) {
         float ms = 0.0f;
         CK(hipEventElapsedTime(&ms, P.start[t], P.stop[t]));
         tot += ms;
+        cnt += P.count[t];
     }
     if (total_ms) *total_ms = tot;
-    if (launches) *launches = (long)m;
+    if (launches) *launches = cnt;
     return MEMD_OK;
 }
 

@@ -47,6 +47,7 @@ struct EtaDesc {
 
 struct ProfileEvents {
     std::vector<hipEvent_t> start, stop;
+    std::vector<long> count;  // launches between start[k] and stop[k]
     std::vector<hipEvent_t> pool;  // made in advance, not yet used
     long seen = 0;  // launches of the family since the collection started
     bool open = false;  // a begin event is waiting for its end
