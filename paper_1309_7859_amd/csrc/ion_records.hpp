@@ -29,6 +29,7 @@ struct DepOut {
     IonFQ<T> *fq;  // [n] by slot: fractional position in the start cell and charge
     int *icnt;     // non-null: the atomic-path ions of the records' step are appended here
     int *ilist;    // (their slots; irr_count)
+    int *endc;     // non-null: [n] by slot, the cell the move ends in (packed)
 };
 
 // The record of one ion in slot s for the fused deposit (du already
@@ -50,6 +51,13 @@ __device__ __forceinline__ bool write_record_at(int L, double a, double qi, cons
     double f0[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) fold(u[d], a, L, c0[d], f0[d]);
+    if (O.endc) {
+        int ce[3];
+        double fe;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fold(u_in[d] + du[d], a, L, ce[d], fe);
+        O.endc[s] = pack_cell(ce[0], ce[1], ce[2]);
+    }
     bool atomic_path = list_fail != 0 || !ion_regular(a, u_in, du);
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
@@ -283,6 +291,7 @@ inline DepOut<T> dep_out(const memd_ctx *c, bool next = false) {
     O.fq = (IonFQ<T> *)(next ? c->fq_nx : c->fq);
     O.icnt = c->tile_irregular ? irr_count(c, c->step_index + (next ? 1 : 0)) : nullptr;
     O.ilist = O.icnt ? O.icnt + kIrrHead : nullptr;
+    O.endc = c->endc;
     return O;
 }
 

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_leapfrog(LfArgs<T> A) {
 // ahead of the tiles when every tile is resident at once (they take CU slots
 // at the start, and the tiles they hold back fill the slots that tiles free
 // at the end), else after them (they fill the last round's free slots).
-template <typename T, int EM, int R, int TZ>
+template <typename T, int EM, int R, int TZ, bool CAP = false>
 __global__ __launch_bounds__(256) void k_leapfrog_dep(LfArgs<T> A, DepArgs P, MoverArgs<T> M) {
     __shared__ LfSmem<T, R> S;
     __shared__ DepSmem<T, R, TZ> DS;
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_leapfrog_dep(LfArgs<T> A, DepArgs P, Mo
     const int logical = xcd_logical(M.ahead ? b - M.nblocks : b, nt);
     const int tile_x = logical % A.ntx;
     const int rest = logical / A.ntx;
-    leapfrog_tile<T, EM, R, true, TZ>(A, tile_x, rest % A.nty, rest / A.nty, S, &P, &DS);
+    leapfrog_tile<T, EM, R, true, TZ, CAP>(A, tile_x, rest % A.nty, rest / A.nty, S, &P, &DS);
 }
 
 // Workgroups of the kernel the whole device holds at once (0: unknown).
@@ -57,9 +57,9 @@ static int resident_blocks(const void *kernel) {
 
 // Measured once per kernel, on the first device that launches it (the
 // devices a process drives are taken to be alike).
-template <typename T, int EM, int R, int TZ>
+template <typename T, int EM, int R, int TZ, bool CAP = false>
 static int dep_resident() {
-    static const int slots = resident_blocks((const void *)k_leapfrog_dep<T, EM, R, TZ>);
+    static const int slots = resident_blocks((const void *)k_leapfrog_dep<T, EM, R, TZ, CAP>);
     return slots;
 }
 
@@ -90,12 +90,21 @@ static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, voi
         if (mv) M = *mv;
         void (*kern)(LfArgs<T>, DepArgs, MoverArgs<T>) = nullptr;
         int slots = 0;
-        if (R == 1 && A.tz > kDepTZ) {
+        if (dep->ecap && R == 1 && A.tz > kDepTZ) {
+            kern = k_leapfrog_dep<T, EM, 1, kDepTZWide, true>;
+            slots = dep_resident<T, EM, 1, kDepTZWide, true>();
+        } else if (dep->ecap && R == 1) {
+            kern = k_leapfrog_dep<T, EM, 1, kDepTZ, true>;
+            slots = dep_resident<T, EM, 1, kDepTZ, true>();
+        } else if (R == 1 && A.tz > kDepTZ) {
             kern = k_leapfrog_dep<T, EM, 1, kDepTZWide>;
             slots = dep_resident<T, EM, 1, kDepTZWide>();
         } else if (R == 1) {
             kern = k_leapfrog_dep<T, EM, 1, kDepTZ>;
             slots = dep_resident<T, EM, 1, kDepTZ>();
+        } else if (dep->ecap) {
+            kern = k_leapfrog_dep<T, EM, 2, kDepTZ, true>;
+            slots = dep_resident<T, EM, 2, kDepTZ, true>();
         } else {
             kern = k_leapfrog_dep<T, EM, 2, kDepTZ>;
             slots = dep_resident<T, EM, 2, kDepTZ>();
@@ -139,6 +148,7 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
     DepArgs P;
     const DepArgs *dp = nullptr;
     unsigned int tag_prev = 0;
+    c->ecap_tag = 0u;
     if (with_deposit) {
         // the lists first (records read each ion's list cell), then the
         // records unless the previous launch's movers wrote them against these lists
@@ -180,6 +190,14 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
         P.irr_du = c->du_slot;
         P.irr_q = c->q;
         P.irr_order = c->sorted ? nullptr : c->order;
+        // the ions' own dynamics capture the new state's field for the ion
+        // kernel that follows (with the atomic path on the tiles' list and
+        // the Green's-function self energy)
+        const bool cap = !own_forces && c->ecap && c->tile_irregular && c->self_scheme == MEMD_SELF_GREEN;
+        P.endc = cap ? c->endc : nullptr;
+        P.ecap = cap ? c->ecap : nullptr;
+        P.ecap_bad = cap ? c->ecap_bad : nullptr;
+        c->ecap_tag = cap ? P.tag : 0u;
         dp = &P;
     }
     const bool with_moves = dp && moves;

@@ -714,7 +714,12 @@ hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials,
 // neighbouring lanes share lines), caller index ci = perm[i]:
 //   - with gather, the forces of the new state (force_ion on D: lattice part,
 //     self force, dipole term with P summed, as k_forces does, from the
-//     movers' per-wavefront partials), into F; else F as it stands;
+//     movers' per-wavefront partials), into F; else F as it stands.  When
+//     the leapfrog tiles captured E = eta D on the 12 links of the ion's cell
+//     (ecap, by slot: every ion but those stamped with cap_tag in ecap_bad),
+//     the lattice part comes from those values and the self force from the
+//     cell's 12 / sum(eta) (ecell), the arithmetic of force_ion without its
+//     gather;
 //   - `kicks` half kicks v <- v + (dt/2) F/m (the closing kick of the step and
 //     the opening one of the next use the same forces);
 //   - with pack, the move of the next step, dt v, into disp (caller order:
@@ -737,7 +742,40 @@ struct MdIonArgs {
     int *dep_atomic;
     DepOut<T> O;
     unsigned int *bad;
+    const T *ecap;  // null: gather
+    const unsigned int *ecap_bad;
+    unsigned int cap_tag;
+    const T *ecell;
 };
+
+// force_ion's lattice part and Green's-function self force from the field
+// already interpolated to the cell's 12 links (E[4 d + 2 o2 + o1]) and the
+// cell's 12 / sum(eta); the dipole term is added by the caller.
+template <typename T>
+__device__ __forceinline__ void force_from_links(int L, double a, double qi, const double (&u)[3], const T (&e)[12],
+                                                 const T *ecell, const double *G, double (&F)[3]) {
+    int c[3];
+    double f[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fold(u[d], a, L, c[d], f[d]);
+    const double eps_cell = (double)ecell[site_index(c[0], c[1], c[2], L)];
+    double Flat[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+        double s = 0.0;
+#pragma unroll
+        for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+            for (int o1 = 0; o1 < 2; ++o1) s += lin_w(o1, f[d1]) * lin_w(o2, f[d2]) * (double)e[4 * d + 2 * o2 + o1];
+        Flat[d] = qi * s;
+    }
+    double S, dS[3];
+    self_sum(G, f, S, dS);
+    const double pref = qi * qi / (2.0 * eps_cell * a);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F[d] = Flat[d] - div_a(-pref * dS[d], a);
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_md_ions(MdIonArgs<T> M) {
@@ -746,28 +784,62 @@ __global__ __launch_bounds__(256) void k_md_ions(MdIonArgs<T> M) {
     const int slot = xcd_logical(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const bool live = slot < A.n;
     const int i = live ? (A.order ? A.order[slot] : slot) : 0;
+    // Every load that needs only the slot is issued first (position, charge,
+    // caller index, record slot, the captured field and its stamp, the
+    // dipole partials), then those that depend on them.
     double u[3] = {0.0, 0.0, 0.0}, qi = 0.0;
+    int ci = 0, rs = 0;
     if (live) {
         u[0] = A.r[3 * i];
         u[1] = A.r[3 * i + 1];
         u[2] = A.r[3 * i + 2];
         qi = A.q[i];
+        ci = M.perm[i];
+        if (M.records) rs = M.slot_of[i];
+    }
+    const bool cap = M.gather && M.ecap != nullptr;
+    unsigned int bad = 0u;
+    union {
+        T v[12];
+        uint4 w[kCellWords<T>];
+    } E;
+    if (cap && live) {
+        bad = M.ecap_bad[slot];
+        const uint4 *src = reinterpret_cast<const uint4 *>(M.ecap + 12 * (size_t)slot);
+#pragma unroll
+        for (int q = 0; q < kCellWords<T>; ++q) E.w[q] = src[q];
+    }
+    const bool psum = M.gather && A.dip_partials != nullptr;
+    double Ps[3] = {0.0, 0.0, 0.0};
+    if (psum) strided_sum<3>(A.dip_partials, A.dip_nblk, threadIdx.x, blockDim.x, Ps);
+    double m = 1.0, vv[3] = {0.0, 0.0, 0.0};
+    int lfail = 0, lcell = 0;
+    if (live) {
+        m = M.mass[ci];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) vv[d] = M.v[3 * ci + d];
+        if (M.records) {
+            lfail = M.O.list_fail[rs];
+            lcell = M.O.cbin[rs];
+        }
     }
     double F[3] = {0.0, 0.0, 0.0};
     if (M.gather) {
         if (live) {
-            const EtaView<T> ev{A.mode, A.eta_uni, A.eta_prof, A.eta_link};
-            const double zero[3] = {0.0, 0.0, 0.0};
-            force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.D, ev, A.scal + S_G, zero, A.scal + S_EPSH, F,
-                         A.self_direct != 0);
+            if (cap && bad != M.cap_tag) {
+                force_from_links<T>(A.L, A.a, qi, u, E.v, M.ecell, A.scal + S_G, F);
+            } else {
+                const EtaView<T> ev{A.mode, A.eta_uni, A.eta_prof, A.eta_link};
+                const double zero[3] = {0.0, 0.0, 0.0};
+                force_ion<T>(A.L, A.Ns, A.a, A.V, qi, u, A.D, ev, A.scal + S_G, zero, A.scal + S_EPSH, F,
+                             A.self_direct != 0);
+            }
         }
-        if (A.dip_partials) {
-            double s[3];
-            strided_sum<3>(A.dip_partials, A.dip_nblk, threadIdx.x, blockDim.x, s);
-            block_sum<3>(s);
+        if (psum) {
+            block_sum<3>(Ps);
             if (threadIdx.x < 3) {
-                Psh[threadIdx.x] = s[threadIdx.x];
-                if (blockIdx.x == 0) A.scal[S_P + threadIdx.x] = s[threadIdx.x];
+                Psh[threadIdx.x] = Ps[threadIdx.x];
+                if (blockIdx.x == 0) A.scal[S_P + threadIdx.x] = Ps[threadIdx.x];
             }
         } else if (threadIdx.x < 3) {
             Psh[threadIdx.x] = A.scal[S_P + threadIdx.x];
@@ -786,12 +858,10 @@ __global__ __launch_bounds__(256) void k_md_ions(MdIonArgs<T> M) {
         for (int d = 0; d < 3; ++d) F[d] = A.F[3 * i + d];
     }
     if (!live) return;
-    const int ci = M.perm[i];
-    const double m = M.mass[ci];
     double du[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        double w = M.v[3 * ci + d] + M.half_dt * F[d] / m;
+        double w = vv[d] + M.half_dt * F[d] / m;
         if (M.kicks == 2) w = w + M.half_dt * F[d] / m;
         M.v[3 * ci + d] = w;
         du[d] = M.dt * w;
@@ -802,8 +872,7 @@ __global__ __launch_bounds__(256) void k_md_ions(MdIonArgs<T> M) {
     }
     if (M.records) {
         sanitize_move(du, A.a, A.L, M.bad);
-        const int s = M.slot_of[i];
-        M.dep_atomic[s] = write_record<T>(A.L, A.a, qi, u, du, s, M.O) ? 1 : 0;
+        M.dep_atomic[rs] = write_record_at<T>(A.L, A.a, qi, u, du, rs, M.O, lfail, lcell) ? 1 : 0;
     }
 }
 
@@ -827,17 +896,25 @@ hipError_t launch_md_ions(memd_ctx *c, const void *D, const double *dip_partials
         M.records = records ? 1 : 0;
         M.dep_atomic = c->dep_atomic;
         M.bad = c->bad_moves;
+        // the field the leapfrog tiles captured for the state just made
+        const bool cap = gather && c->ecap_tag != 0u;
+        M.ecap_bad = cap ? c->ecap_bad : nullptr;
+        M.cap_tag = c->ecap_tag;
     };
     if (c->fp32) {
         MdIonArgs<float> M;
         M.fa = force_args<float>(c, D);
         fill(M);
+        M.ecap = M.ecap_bad ? (const float *)c->ecap : nullptr;
+        M.ecell = (const float *)c->ecell;
         M.O = dep_out<float>(c);
         hipLaunchKernelGGL(k_md_ions<float>, dim3(nb), dim3(kThreads), 0, c->stream, M);
     } else {
         MdIonArgs<double> M;
         M.fa = force_args<double>(c, D);
         fill(M);
+        M.ecap = M.ecap_bad ? (const double *)c->ecap : nullptr;
+        M.ecell = (const double *)c->ecell;
         M.O = dep_out<double>(c);
         hipLaunchKernelGGL(k_md_ions<double>, dim3(nb), dim3(kThreads), 0, c->stream, M);
     }

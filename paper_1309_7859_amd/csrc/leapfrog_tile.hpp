@@ -142,6 +142,13 @@ struct DepArgs {
     unsigned int *ovf_mark;
     double V, eta_uni;
     const double *epsh;
+    // the ions' own dynamics (the capturing kernel): E = eta D^{n+1} on the
+    // 12 links of the cell each move ends in (endc[slot], packed) is written
+    // to ecap[12 slot + 4 d + 2 o2 + o1] (field type) by the tile owning the
+    // link's site; an ion a tile had no room to list gets ecap_bad[slot] = tag
+    const int *endc;
+    void *ecap;
+    unsigned int *ecap_bad;
 };
 
 // Planes per z-chunk when the deposit is fused: up to 4, or up to 8 for the
@@ -188,11 +195,14 @@ struct LfSmem {
 
 // One workgroup (256 threads) advances the tile (tile_x, tile_y) over the z
 // planes of `chunk`.  Every load wraps periodically; stores are masked to the
-// lattice, so any L >= 2 works with any tile shape.
-template <typename T, int EM, int R, bool DEP = false, int DTZ = kDepTZ>
+// lattice, so any L >= 2 works with any tile shape.  With CAP (the ions' own
+// dynamics: the tiles compute no forces) the tile instead captures the new
+// field on the links of the cells the moves end in.
+template <typename T, int EM, int R, bool DEP = false, int DTZ = kDepTZ, bool CAP = false>
 __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, int tile_y, int chunk,
                                               LfSmem<T, R> &S, const DepArgs *dep = nullptr,
                                               DepSmem<T, R, DTZ> *DS = nullptr) {
+    static_assert(!CAP || DEP, "the capture rides on the fused deposit");
     constexpr int TX = 64, TY = 4 * R;
     auto &sX = S.sX;
     auto &sB = S.sB;
@@ -284,6 +294,7 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
     int pf_slot[kPF];
     bool pf_dec[kPF];
     int4 pf_head[kPF];
+    int pf_endc[kPF];
     RecRegs pf_con[kPF];
     int dep_cnt = 0;
     size_t dep_base = 0;
@@ -330,6 +341,24 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             if (pos < kOwnCap) DS->own[pos] = make_int2(slot, lxo | (lyo << 8) | (lzo << 16));
             else if (dep->ovf_mark) dep->ovf_mark[slot] = dep->tag;
         }
+    };
+    // With CAP: an ion whose end cell has a link with its site on the tile
+    // (cell or cell + 1 along every axis within the tile's real sites) joins
+    // the tile's capture list (the LDS list of owned ions, unused then).
+    const int exc0 = min(TX, L - x0);
+    auto cap_rec = [&](int ec, int slot) {
+        const int exr[3] = {exc0, ext[1], ext[2]};
+        bool in = true;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const int v0 = (ec >> (10 * ax)) & 1023;
+            const int v1 = v0 + 1 == L ? 0 : v0 + 1;
+            in = in && ((unsigned)(v0 - org[ax]) < (unsigned)exr[ax] || (unsigned)(v1 - org[ax]) < (unsigned)exr[ax]);
+        }
+        if (!in) return;
+        const int pos = atomicAdd(&DS->own_n, 1);
+        if (pos < kOwnCap) DS->own[pos] = make_int2(slot, ec);
+        else dep->ecap_bad[slot] = dep->tag;
     };
     // Whether one of the record's links lies on the tile: per axis group,
     // the box of links is the group's corner and the next cell along each
@@ -408,6 +437,7 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
     };
 
     T Dc[R][3], prevB[R][2];
+    T Ec[CAP ? R : 1][3];  // with CAP: eta of the own sites of the plane being updated
 
     // Prologue: new B_x, B_y of the plane below the chunk, for the own sites.
     {
@@ -427,6 +457,7 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
                     continue;
                 }
                 pf_head[j] = dep->head[pf_slot[j]];
+                if constexpr (CAP) pf_endc[j] = dep->endc[pf_slot[j]];
             }
         }
         PlaneRegs p1;
@@ -456,6 +487,11 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int d = 0; d < 3; ++d) Dc[r][d] = p1.d[r][d];
+        if constexpr (CAP)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) Ec[r][d] = p1.e[r][d];
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -475,8 +511,11 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             // (the accumulator and the owned count were cleared before the
             // barrier above)
 #pragma unroll
-            for (int j = 0; j < kPF; ++j)
-                if (pf_slot[j] >= 0) own_rec(pf_head[j], pf_slot[j]);
+            for (int j = 0; j < kPF; ++j) {
+                if (pf_slot[j] < 0) continue;
+                if constexpr (CAP) cap_rec(pf_endc[j], pf_slot[j]);
+                else own_rec(pf_head[j], pf_slot[j]);
+            }
             // entries beyond the prefetched ones, if any
             const DepCell<T> *con = (const DepCell<T> *)dep->con0;
             for (int e = (int)threadIdx.x + kPF * (int)blockDim.x; e < dep_cnt; e += blockDim.x) {
@@ -484,7 +523,8 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
                 if (slot < 0) continue;
                 const int4 h = dep->head[slot];
                 if (h.x < 0) continue;
-                own_rec(h, slot);
+                if constexpr (CAP) cap_rec(dep->endc[slot], slot);
+                else own_rec(h, slot);
                 if (!meets_tile(h)) continue;
                 RecRegs cn;
                 const uint4 *src = reinterpret_cast<const uint4 *>(&con[slot].v[0]);
@@ -510,6 +550,14 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
                         own_rec(make_int4(pack_cell(cc[0], cc[1], cc[2]), 0, 0, 0), s);
                     }
                     deposit_ion_box<T, DTZ, TY>(L, dep->a, dep->irr_q[i], u, du, org, ex, DS->acc);
+                    if constexpr (CAP) {
+                        // u has moved to where the move ends
+                        int ce[3];
+                        double ff;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) fold(u[d], dep->a, L, ce[d], ff);
+                        cap_rec(pack_cell(ce[0], ce[1], ce[2]), s);
+                    }
                 }
             }
         }
@@ -522,7 +570,7 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
     IonFQ<T> own_fq{};
     T own_ec = (T)1;
     T own_X[12];
-    if constexpr (DEP) {
+    if constexpr (DEP && !CAP) {
         if ((int)threadIdx.x < min(DS->own_n, kOwnCap)) {
             const int2 o = DS->own[threadIdx.x];
             own_slot = o.x;
@@ -534,6 +582,60 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             own_ec = ((const T *)dep->ecell)[site];
         }
     }
+
+    // With CAP, after the march: the links of the listed end cells whose
+    // site lies on the tile, from E of the tile's planes (the Ampere update
+    // leaves E = eta D^{n+1} of each site in its accumulator entry, which is
+    // not read again), to the capture array: all 12 LDS reads first, then the
+    // values, with three 16-byte stores (FP32; six in FP64) when the tile
+    // owns every link of the cell.
+    auto cap_links = [&]() {
+        if constexpr (CAP) {
+            const int ncap = min(DS->own_n, kOwnCap);
+            for (int e = (int)threadIdx.x; e < ncap; e += blockDim.x) {
+                const int2 o = DS->own[e];
+                int c0[3], c1[3];
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    c0[ax] = (o.y >> (10 * ax)) & 1023;
+                    c1[ax] = c0[ax] + 1 == L ? 0 : c0[ax] + 1;
+                }
+                union {
+                    T v[12];
+                    uint4 w[kCellWords<T>];
+                } E;
+                unsigned own = 0u;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+#pragma unroll
+                    for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                        for (int o1 = 0; o1 < 2; ++o1) {
+                            int x[3] = {c0[0], c0[1], c0[2]};
+                            x[d1] = o1 ? c1[d1] : c0[d1];
+                            x[d2] = o2 ? c1[d2] : c0[d2];
+                            const int lxx = x[0] - x0, lyy = x[1] - y0, lzz = x[2] - z0;
+                            const bool in = (unsigned)lxx < (unsigned)exc0 && (unsigned)lyy < (unsigned)ext[1] &&
+                                            (unsigned)lzz < (unsigned)ext[2];
+                            const int t = 4 * d + 2 * o2 + o1;
+                            own |= in ? 1u << t : 0u;
+                            E.v[t] = DS->acc[d][in ? lzz : 0][in ? lyy : 0][in ? lxx : 0];
+                        }
+                }
+                T *dst = (T *)dep->ecap + 12 * (size_t)o.x;
+                if (own == 0xFFFu) {
+                    uint4 *dw = reinterpret_cast<uint4 *>(dst);
+#pragma unroll
+                    for (int q = 0; q < kCellWords<T>; ++q) dw[q] = E.w[q];
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 12; ++t)
+                        if (own & (1u << t)) dst[t] = E.v[t];
+                }
+            }
+        }
+    };
 
     // One plane k of the march.  The first one also decodes the prefetched
     // records, between issuing the next plane's loads and storing it.
@@ -603,7 +705,7 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             sB[2][yy][0] = hb1 - kB * (sX[cur][1][yy][1] - sX[cur][1][yy][0] -
                                        sX[cur][0][yy + 1][0] + sX[cur][0][yy][0]);
         }
-        if constexpr (DEP) {
+        if constexpr (DEP && !CAP) {
             // The owned ion in plane k: capture E = eta D on its cell's 12
             // links (planes k and k+1, rows and columns with the +1 halo, in
             // force_ion's order); its force is computed after the march.
@@ -633,7 +735,20 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             const T dx = Dc[r][0] + kD * (Bn[r][2] - sB[2][yy - 1][xx] - Bn[r][1] + prevB[r][1]);
             const T dy = Dc[r][1] + kD * (Bn[r][0] - prevB[r][0] - Bn[r][2] + sB[2][yy][xx - 1]);
             const T dz = Dc[r][2] + kD * (Bn[r][1] - sB[1][yy][xx - 1] - Bn[r][0] + sB[0][yy - 1][xx]);
-            if (act[r]) {
+            if constexpr (CAP) {
+                const int kz = k - z0, ky = wy + 4 * r;
+                const T n3[3] = {dx + DS->acc[0][kz][ky][lx], dy + DS->acc[1][kz][ky][lx],
+                                 dz + DS->acc[2][kz][ky][lx]};
+                // (this thread's own entry: nothing reads it again in the march)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) DS->acc[d][kz][ky][lx] = Ec[r][d] * n3[d];
+                if (act[r]) {
+                    const size_t off = zoff + (size_t)gyo[r] * L + gx;
+                    A.Dout[off] = n3[0];
+                    A.Dout[Ns + off] = n3[1];
+                    A.Dout[2 * Ns + off] = n3[2];
+                }
+            } else if (act[r]) {
                 const size_t off = zoff + (size_t)gyo[r] * L + gx;
                 if constexpr (DEP) {
                     const int kz = k - z0, ky = wy + 4 * r;
@@ -650,13 +765,20 @@ __device__ __forceinline__ void leapfrog_tile(const LfArgs<T> &A, int tile_x, in
             prevB[r][1] = Bn[r][1];
 #pragma unroll
             for (int d = 0; d < 3; ++d) Dc[r][d] = pn.d[r][d];
+            if constexpr (CAP)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) Ec[r][d] = pn.e[r][d];
         }
         cur = nxt;
     };
     march(z0, std::true_type{});
     for (int k = z0 + 1; k < z1; ++k) march(k, std::false_type{});
 
-    if constexpr (DEP) {
+    if constexpr (CAP) {
+        __syncthreads();
+        cap_links();
+    }
+    if constexpr (DEP && !CAP) {
         // Force of the owned ion: lattice part from the captured E, as
         // force_ion sums it, then the self force (the dipole term is added by
         // the ion finisher, or by the movers of the next launch).

@@ -323,7 +323,7 @@ void memd_destroy(memd_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     prof_clear(c);
     // the arena holds every fixed buffer; the rest were made on demand
-    void *bufs[] = {c->arena, c->eta_link, c->stage, c->salt_cnt, c->md_buf};
+    void *bufs[] = {c->arena, c->eta_link, c->stage, c->salt_cnt, c->md_buf, c->md_cap};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -866,6 +866,23 @@ memd_status memd_md_step(memd_ctx *c, double *v, const double *mass, int nsteps)
     // deposits.  The plain path gathers the forces in the step, and the ion
     // kernel only kicks and writes the move.
     const bool records = fused_deposit_ok(c);
+    if (records && !c->md_cap) {
+        // the capture buffers of the fused path: E on the 12 links of each
+        // ion's end cell (field type), the incomplete-capture stamps (0 marks
+        // none), the end cells
+        const size_t eb = (12 * n * c->tsize + 255) / 256 * 256;
+        const size_t bytes = eb + 2 * n * sizeof(int);
+        CK(hipStreamSynchronize(c->stream));
+        if (hipMalloc(&c->md_cap, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            c->md_cap = nullptr;
+            return MEMD_ENOMEM;
+        }
+        CK(hipMemsetAsync(c->md_cap, 0, bytes, c->stream));
+        c->ecap = c->md_cap;
+        c->ecap_bad = (unsigned int *)((char *)c->md_cap + eb);
+        c->endc = (int *)(c->ecap_bad + n);
+    }
     // forces of the current state (the permittivity may have changed since
     // the last ones were computed), the opening half kick, the first move
     CK(enqueue_dipole_forces(c));

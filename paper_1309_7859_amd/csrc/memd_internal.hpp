@@ -153,6 +153,16 @@ struct memd_ctx {
     double *stage;       // FP64 staging buffer for host inputs / FP32 casts
     size_t stage_bytes;
     double *md_buf;      // ion dynamics: the step's move [3n], staged velocities [3n] and masses [n]
+    // ion dynamics with the fused deposit: the field E = eta D of the new
+    // state on the 12 links of each ion's end cell, captured by the leapfrog
+    // tiles ([12n] field type, by slot), the launch tag of the ions whose
+    // capture was incomplete ([n]), the end cell of each record's move ([n]);
+    // one allocation (md_cap), made by the first memd_md_step
+    void *md_cap;
+    void *ecap;
+    unsigned int *ecap_bad;
+    int *endc;
+    unsigned int ecap_tag;  // tag of the leapfrog launch that captured (0: none)
     long perm_version;   // advanced whenever perm changes
 
     // reductions and audit
