@@ -173,7 +173,7 @@ struct MoverArgs {
     const int *order;  // null: ions stored in bin order
     const int *perm;   // storage index -> caller index (displacements), null: identity
     const double *du;  // [3n] by slot: this step's displacements (the current records')
-    double *dip_out;   // one partial of q r^{n+1} per wavefront: 4 per mover workgroup
+    double *dip_out;   // one partial of q r^{n+1} per mover workgroup
     int pack;          // write the next step's records
     const double *disp_next;  // null: the Philox displacements of step t_next
     uint64_t seed;
@@ -197,10 +197,10 @@ struct MoverArgs {
 
 // Slots [s0, s0 + count) by the workgroup's 256 threads, kMoverPerThread
 // per thread (all of a thread's loads issued before any of its arithmetic);
-// partials to dip_out[part0 .. part0 + 3] (zero for a wavefront without
-// ions).
+// the workgroup's dipole partial to dip_out[part] (its four wavefront sums
+// added in order through psum; zero for a workgroup without ions).
 template <typename T>
-__device__ __forceinline__ void move_ions(const MoverArgs<T> &M, int s0, int count, int part0) {
+__device__ __forceinline__ void move_ions(const MoverArgs<T> &M, int s0, int count, int part, double (*psum)[4]) {
     constexpr int K = kMoverPerThread;
     double P[3] = {0.0, 0.0, 0.0};
     const int s1 = min(s0 + count, M.n);
@@ -269,11 +269,13 @@ __device__ __forceinline__ void move_ions(const MoverArgs<T> &M, int s0, int cou
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) P[d] = wave_sum(P[d]);
-    if ((threadIdx.x & 63) == 0) {
-        const int w = part0 + (int)(threadIdx.x >> 6);
-        M.dip_out[3 * w] = P[0];
-        M.dip_out[3 * w + 1] = P[1];
-        M.dip_out[3 * w + 2] = P[2];
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) psum[d][threadIdx.x >> 6] = P[d];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int d = (int)threadIdx.x;
+        M.dip_out[3 * part + d] = ((psum[d][0] + psum[d][1]) + psum[d][2]) + psum[d][3];
     }
 }
 

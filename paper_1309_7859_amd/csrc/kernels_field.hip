@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256) void k_leapfrog_dep(LfArgs<T> A, DepArgs P, Mo
     const int b = (int)blockIdx.x, nt = (int)gridDim.x - M.nblocks;
     const int m = M.ahead ? b : b - nt;  // the mover index, for a mover workgroup
     if (m >= 0 && m < M.nblocks) {
-        move_ions<T>(M, m * kMoverIons, kMoverIons, 4 * m);
+        move_ions<T>(M, m * kMoverIons, kMoverIons, m, DS.psum);
         return;
     }
     const int logical = xcd_logical(M.ahead ? b - M.nblocks : b, nt);
@@ -201,7 +201,7 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
         dp = &P;
     }
     const bool with_moves = dp && moves;
-    if (with_moves) moves->nparts = 4 * mover_blocks(c->n);
+    if (with_moves) moves->nparts = mover_blocks(c->n);
     // the movers complete the forces of the state the previous launch started from
     auto assemble = [&](auto &M) {
         if (!(with_moves && c->fold_step && moves->assemble)) return;
@@ -409,8 +409,14 @@ __global__ __launch_bounds__(256) void k_field_obs(FieldView<T> V, double kB, do
     }
 }
 
+// The observables pass runs 2048 blocks at most (four row chunks per
+// wavefront at 128^3): at c4 it took 35.3 us on 8192 blocks (one chunk per
+// wavefront, each block's reduction for 256 sites), 30.9 on 4096 and 27.7 on
+// 2048, and its finaliser 13.2, 10.4 and 9.1 us over those partials.
+constexpr int kObsBlocks = 2048;
+
 hipError_t launch_field_obs(memd_ctx *c, bool audit, bool energy, double *partials, int *nblk) {
-    const int nb = site_blocks(c->Ns);
+    const int nb = site_blocks(c->Ns) < kObsBlocks ? site_blocks(c->Ns) : kObsBlocks;
     *nblk = nb;
     const double kB = c->dt / c->a, a2 = c->a * c->a;
     const void *D = c->D[c->cur], *B = c->B[c->cur];

@@ -254,7 +254,8 @@ hipError_t launch_build_lists(memd_ctx *c, bool pack, const double *disp, uint64
                            c->stream, c->list_count, 0, nc);
     }
     c->list_zero_key = -1;  // the counts are in use from here on
-    if (pack && c->tile_irregular) launch_clear_irregular(c);
+    if (pack && c->tile_irregular && c->irr_zeroed != c->step_index) launch_clear_irregular(c);
+    c->irr_zeroed = -1;
     const int nb = ion_blocks(c->n);
     if (pack && c->fp32) {
         PackArgs<float> PA{c->q, disp, c->perm, c->dep_atomic, dep_out<float>(c), c->bad_moves, seed, t, sigma};
@@ -616,7 +617,7 @@ struct ForceArgs {
 
 // Forces on every ion, one lane per ion following `order` (force_ion: the
 // lattice part from the 12 links of the cell, self force, dipole
-// correction).  With dip_partials set, every block sums the per-wavefront
+// correction).  With dip_partials set, every block sums the per-workgroup
 // q r partials of the last step's movers into P (in the dipole finaliser's order;
 // block 0 also stores it) while its force gathers are in flight.
 template <typename T>
@@ -714,7 +715,7 @@ hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials,
 // neighbouring lanes share lines), caller index ci = perm[i]:
 //   - with gather, the forces of the new state (force_ion on D: lattice part,
 //     self force, dipole term with P summed, as k_forces does, from the
-//     movers' per-wavefront partials), into F; else F as it stands.  When
+//     movers' per-workgroup partials), into F; else F as it stands.  When
 //     the leapfrog tiles captured E = eta D on the 12 links of the ion's cell
 //     (ecap, by slot: every ion but those stamped with cap_tag in ecap_bad),
 //     the lattice part comes from those values and the self force from the
@@ -978,9 +979,10 @@ __global__ void k_bin_count(int n, int L, double a, const double *__restrict__ r
 // a wavefront prefix sum of the thread totals, the 16 wavefront totals in
 // LDS, then the thread's 16 starts written back as 16-byte words.
 __global__ __launch_bounds__(1024) void k_bin_scan(int *__restrict__ count, int nb, int *__restrict__ start,
-                                                   int *__restrict__ cursor) {
+                                                   int *__restrict__ cursor, int *__restrict__ zero) {
     __shared__ int wsum[16];
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    if (zero && t == 0) *zero = 0;
     const bool vec = (nb & 3) == 0;
     int carry = 0;
     for (int base = 0; base < nb; base += 16384) {
@@ -1124,7 +1126,7 @@ __global__ void k_fill_int(int *dst, int v, size_t count) {
         dst[t] = v;
 }
 
-hipError_t launch_bin_ions(memd_ctx *c, bool reorder) {
+hipError_t launch_bin_ions(memd_ctx *c, bool reorder, bool zero_irr) {
     if (c->n == 0 || !c->order) return hipSuccess;
     c->lists_key = -1;  // slots and cells change: the fused deposit's lists are rebuilt before use
     const int nb = c->L * c->L;
@@ -1133,7 +1135,9 @@ hipError_t launch_bin_ions(memd_ctx *c, bool reorder) {
     const int nlc = c->list ? list_tiles(c) * kCountStride : 0;
     hipLaunchKernelGGL(k_bin_count, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->r,
                        count, c->list_count, nlc);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, count, nb, start, cursor);
+    int *zero = zero_irr && c->tile_irregular ? irr_count(c, c->step_index) : nullptr;
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, count, nb, start, cursor, zero);
+    c->irr_zeroed = zero ? c->step_index : -1;
     c->list_zero_key = c->list ? c->lf_rows * 4096 + c->lf_tz : -1;
     if (reorder) {
         hipLaunchKernelGGL(k_bin_reorder, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,

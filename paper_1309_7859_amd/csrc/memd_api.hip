@@ -347,6 +347,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
     c->p = *p;
     c->n = n;
     c->prof_every = 1;
+    c->irr_zeroed = -1;
     c->L = p->L;
     c->Ns = Ns;
     c->a = p->a;
@@ -407,7 +408,7 @@ memd_status memd_init_lattice(memd_ctx **out, const memd_params *p, int n, const
 
     const size_t fb = 3 * Ns * c->tsize;
     const size_t nn = (size_t)(n > 0 ? n : 1);
-    const size_t dip_parts = nn / 64 + 32;  // dipole partials: 4 per mover workgroup of 256 ions
+    const size_t dip_parts = nn / 64 + 32;  // dipole partials: one per mover workgroup of 256 ions (room for 4)
     // Every fixed buffer of the context is carved from one allocation (each
     // piece 256-byte aligned): one hipMalloc here and one hipFree at destroy,
     // which matters to a server creating and destroying contexts while other
@@ -709,7 +710,7 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
         const uint32_t tstep = (uint32_t)c->step_index;
         int nb = 0;
         if (c->sort_every > 0 && c->step_index % c->sort_every == 0) {
-            CK(launch_bin_ions(c, true));
+            CK(launch_bin_ions(c, true, true));
             recs_ready = false;
         }
         const bool fused = fused_deposit_ok(c);

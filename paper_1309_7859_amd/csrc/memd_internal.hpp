@@ -163,13 +163,14 @@ struct memd_ctx {
     unsigned int *ecap_bad;
     int *endc;
     unsigned int ecap_tag;  // tag of the leapfrog launch that captured (0: none)
+    long irr_zeroed;        // step whose atomic-path count the last re-binning cleared (-1: none)
     long perm_version;   // advanced whenever perm changes
 
     // reductions and audit
     double *rho;       // FP64 [Ns]: the charge assignment of the last audit
     int *drift;        // [n] by storage index: ion left to the atomic pass of the spread
     double *partials;  // FP64 reduction scratch (partial_doubles)
-    double *dip[2];    // FP64 per-wavefront q r sums of the ion movers, alternating by step
+    double *dip[2];    // FP64 per-workgroup q r sums of the ion movers, alternating by step
     double *scal;      // FP64 [S_COUNT]
     double *hist_audit;   // FP64 [2*hist_cap]
     double *hist_energy;  // FP64 [5*hist_cap]
@@ -195,7 +196,7 @@ namespace memd {
 
 // The ion movers of a fused leapfrog launch (ion_records.hpp): every ion
 // moved by its record's displacement into r_alt, one dipole partial of
-// q r^{n+1} per mover wavefront into dip_out (nparts, set by the launch),
+// q r^{n+1} per mover workgroup into dip_out (nparts, set by the launch),
 // and with pack_next the next step's records (displacements disp_next, or
 // the Philox stream at t_next) into the second record set.
 // The count of the atomic-path ions of step `step` (its slots follow at +32).
@@ -299,7 +300,9 @@ hipError_t launch_dipole(memd_ctx *c, double *partials, int *nblk);
 hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk);
 // Row binning of the ions (order, slot, row counts/starts); with
 // reorder the ion arrays themselves move into bin order (see sorted).
-hipError_t launch_bin_ions(memd_ctx *c, bool reorder = false);
+// zero_irr: the re-binning's scan also clears the count of this step's
+// atomic-path ions (the list build that follows it in the step then need not)
+hipError_t launch_bin_ions(memd_ctx *c, bool reorder = false, bool zero_irr = false);
 hipError_t launch_iota(hipStream_t s, int *dst, int n);
 // out[perm[s] * w + k] = in[s * w + k] on the context's stream.
 hipError_t launch_unpermute(memd_ctx *c, int w, const double *in, double *out);
