@@ -289,4 +289,53 @@ __device__ __forceinline__ double force_ion(int L, size_t Ns, double a, double V
     return pref * S;
 }
 
+// Self energies U_i = q_i^2 S(f_i) / (2 eps_cell a) (section "Self energy
+// interaction"), eps_cell = 12 / (sum of eta over the cell's 12 edges), with
+// the arithmetic of force_ion but no field read: the partial of block b of
+// nb (256 threads; the ions of the block as k_forces groups them, so the sum
+// is deterministic) into partials[b].
+struct SelfEnergyArgs {
+    int n, nb;
+    double a;
+    const double *q, *r, *G;
+    double *partials;
+};
+
+template <typename T>
+__device__ __forceinline__ void self_energy_block(int b, const SelfEnergyArgs &U, int L, size_t Ns,
+                                                  const EtaView<T> &eta) {
+    const int i = xcd_logical(b, U.nb) * blockDim.x + threadIdx.x;
+    double us = 0.0;
+    if (i < U.n) {
+        const double u[3] = {U.r[3 * i], U.r[3 * i + 1], U.r[3 * i + 2]};
+        const double qi = U.q[i];
+        int c[3];
+        double f[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fold(u[d], U.a, L, c[d], f[d]);
+        const int cp[3] = {c[0] + 1 == L ? 0 : c[0] + 1, c[1] + 1 == L ? 0 : c[1] + 1, c[2] + 1 == L ? 0 : c[2] + 1};
+        double etasum = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+#pragma unroll
+            for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+                for (int o1 = 0; o1 < 2; ++o1) {
+                    int x[3] = {c[0], c[1], c[2]};
+                    x[d1] = o1 ? cp[d1] : c[d1];
+                    x[d2] = o2 ? cp[d2] : c[d2];
+                    etasum += eta.at(d, x[2], site_index(x[0], x[1], x[2], L), L, Ns);
+                }
+        }
+        const double eps_cell = 12.0 / etasum;
+        double S, dS[3];
+        self_sum(U.G, f, S, dS);
+        us = qi * qi / (2.0 * eps_cell * U.a) * S;
+    }
+    double v[1] = {us};
+    block_sum<1>(v);
+    if (threadIdx.x == 0) U.partials[b] = v[0];
+}
+
 }  // namespace memd

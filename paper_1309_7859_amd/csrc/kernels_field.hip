@@ -257,11 +257,12 @@ __device__ __forceinline__ RowChunk row_chunk(int k, int L) {
     return r;
 }
 
+// (over the first nblk blocks of the grid)
 template <typename F>
-__device__ __forceinline__ void for_row_chunks(int L, F &&body) {
+__device__ __forceinline__ void for_row_chunks(int L, int nblk, F &&body) {
     const int nch = ((L + 63) >> 6) * L * L;
     for (int k = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6))); k < nch;
-         k += gridDim.x * 4) {
+         k += nblk * 4) {
         const RowChunk rc = row_chunk(k, L);
         if (rc.live) body(rc);
     }
@@ -318,7 +319,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_audit(const T *__restrict__ D, const double *__restrict__ rho,
                                                int L, size_t Ns, double a2, double *partials) {
     double mx = 0.0, ss = 0.0;
-    for_row_chunks(L, [&](const RowChunk &rc) {
+    for_row_chunks(L, (int)gridDim.x, [&](const RowChunk &rc) {
         const int i = rc.x, j = rc.y, k = rc.z;
         const size_t v = ((size_t)k * L + j) * L + i;
         const size_t vx = site_index(i == 0 ? L - 1 : i - 1, j, k, L);
@@ -359,14 +360,22 @@ hipError_t launch_audit_raw(hipStream_t s, const void *D, bool fp32, const doubl
 // of the first, W_B = (c^2/2) a^3 of the second: the leapfrog's shadow form
 // B^{n+1/2} B^{n+3/2}, the later factor made here); with AUD, max |R| and
 // sum R^2 of R_v = a^2 sum_d [D_d(v) - D_d(v-e_d)] - rho_v, the audit k_audit
-// also forms.  Four partials per block (we, wb, max, sum).
+// also forms.  Four partials per block (we, wb, max, sum).  With ENG the
+// launch's last U.nb blocks compute the self-energy partials instead
+// (self_energy_block), beside the field blocks.
 template <typename T, bool AUD, bool ENG>
 __global__ __launch_bounds__(256) void k_field_obs(FieldView<T> V, double kB, double a2, const double *__restrict__ rho,
-                                                   double *partials) {
+                                                   double *partials, SelfEnergyArgs U) {
     const int L = V.L;
     const size_t Ns = V.Ns;
+    const int nf = (int)gridDim.x - (ENG ? U.nb : 0);  // field blocks
+    if (ENG && (int)blockIdx.x >= nf) {
+        const EtaView<T> ev{V.mode, V.eta_uni, V.eta_prof, V.eta_link};
+        self_energy_block<T>((int)blockIdx.x - nf, U, L, Ns, ev);
+        return;
+    }
     double we = 0.0, wb = 0.0, mx = 0.0, ss = 0.0;
-    for_row_chunks(L, [&](const RowChunk &rc) {
+    for_row_chunks(L, nf, [&](const RowChunk &rc) {
         const int i = rc.x, j = rc.y, k = rc.z;
         const size_t v = ((size_t)k * L + j) * L + i;
         double Dv[3];
@@ -415,33 +424,38 @@ __global__ __launch_bounds__(256) void k_field_obs(FieldView<T> V, double kB, do
 // 2048, and its finaliser 13.2, 10.4 and 9.1 us over those partials.
 constexpr int kObsBlocks = 2048;
 
-hipError_t launch_field_obs(memd_ctx *c, bool audit, bool energy, double *partials, int *nblk) {
+hipError_t launch_field_obs(memd_ctx *c, bool audit, bool energy, double *partials, int *nblk, double *ipart,
+                            int *iblk) {
     const int nb = site_blocks(c->Ns) < kObsBlocks ? site_blocks(c->Ns) : kObsBlocks;
     *nblk = nb;
+    // the self energies ride on the energy launch as blocks of their own
+    SelfEnergyArgs U{c->n, energy ? ion_blocks_x8(c->n, 1) : 0, c->a, c->q, c->r, c->scal + S_G, ipart};
+    *iblk = U.nb;
+    const int grid = nb + U.nb;
     const double kB = c->dt / c->a, a2 = c->a * c->a;
     const void *D = c->D[c->cur], *B = c->B[c->cur];
     if (c->fp32) {
         const auto V = make_view<float>(c, D, B);
         if (audit && energy)
-            hipLaunchKernelGGL((k_field_obs<float, true, true>), dim3(nb), dim3(kThreads), 0, c->stream, V, kB, a2,
-                               c->rho, partials);
+            hipLaunchKernelGGL((k_field_obs<float, true, true>), dim3(grid), dim3(kThreads), 0, c->stream, V, kB, a2,
+                               c->rho, partials, U);
         else if (audit)
-            hipLaunchKernelGGL((k_field_obs<float, true, false>), dim3(nb), dim3(kThreads), 0, c->stream, V, kB, a2,
-                               c->rho, partials);
+            hipLaunchKernelGGL((k_field_obs<float, true, false>), dim3(grid), dim3(kThreads), 0, c->stream, V, kB, a2,
+                               c->rho, partials, U);
         else
-            hipLaunchKernelGGL((k_field_obs<float, false, true>), dim3(nb), dim3(kThreads), 0, c->stream, V, kB, a2,
-                               c->rho, partials);
+            hipLaunchKernelGGL((k_field_obs<float, false, true>), dim3(grid), dim3(kThreads), 0, c->stream, V, kB, a2,
+                               c->rho, partials, U);
     } else {
         const auto V = make_view<double>(c, D, B);
         if (audit && energy)
-            hipLaunchKernelGGL((k_field_obs<double, true, true>), dim3(nb), dim3(kThreads), 0, c->stream, V, kB, a2,
-                               c->rho, partials);
+            hipLaunchKernelGGL((k_field_obs<double, true, true>), dim3(grid), dim3(kThreads), 0, c->stream, V, kB, a2,
+                               c->rho, partials, U);
         else if (audit)
-            hipLaunchKernelGGL((k_field_obs<double, true, false>), dim3(nb), dim3(kThreads), 0, c->stream, V, kB, a2,
-                               c->rho, partials);
+            hipLaunchKernelGGL((k_field_obs<double, true, false>), dim3(grid), dim3(kThreads), 0, c->stream, V, kB, a2,
+                               c->rho, partials, U);
         else
-            hipLaunchKernelGGL((k_field_obs<double, false, true>), dim3(nb), dim3(kThreads), 0, c->stream, V, kB, a2,
-                               c->rho, partials);
+            hipLaunchKernelGGL((k_field_obs<double, false, true>), dim3(grid), dim3(kThreads), 0, c->stream, V, kB, a2,
+                               c->rho, partials, U);
     }
     return hipGetLastError();
 }

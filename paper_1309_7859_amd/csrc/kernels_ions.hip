@@ -64,13 +64,6 @@ __global__ __launch_bounds__(256) void k_deposit(int n, int L, size_t Ns, double
 }
 
 static int ion_blocks(int n) { return n > 0 ? (n + kThreads - 1) / kThreads : 1; }
-// grid of the sorted-order ion kernels (lanes_per_ion lanes per ion): a
-// multiple of the 8 XCDs
-static int ion_blocks_x8(int n, int lanes_per_ion = 1) {
-    const long long t = (long long)(n > 0 ? n : 1) * lanes_per_ion;
-    const int b = (int)((t + kThreads - 1) / kThreads);
-    return (b + 7) / 8 * 8;
-}
 
 hipError_t launch_deposit(memd_ctx *c, void *D, const double *disp, double *partials, int *nblk, uint64_t seed,
                           uint32_t t, double sigma) {
@@ -1153,65 +1146,6 @@ hipError_t launch_bin_ions(memd_ctx *c, bool reorder, bool zero_irr) {
         hipLaunchKernelGGL(k_bin_scatter, dim3(ion_blocks(c->n)), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
                            c->r, cursor, c->order, c->slot);
     }
-    return hipGetLastError();
-}
-
-// Self energies U_i = q_i^2 S(f_i) / (2 eps_cell a) (section "Self energy
-// interaction"), eps_cell = 12 / (sum of eta over the cell's 12 edges), with
-// the arithmetic of force_ion but no field read; one partial per block, the
-// ions of a block as k_forces groups them in index order (so the sum is
-// deterministic).
-template <typename T>
-__global__ __launch_bounds__(256) void k_uself(int n, int L, size_t Ns, double a, const double *__restrict__ q,
-                                               const double *__restrict__ r, EtaView<T> eta, const double *G,
-                                               double *partials) {
-    const int i = xcd_logical(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    double us = 0.0;
-    if (i < n) {
-        const double u[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
-        const double qi = q[i];
-        int c[3];
-        double f[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) fold(u[d], a, L, c[d], f[d]);
-        const int cp[3] = {c[0] + 1 == L ? 0 : c[0] + 1, c[1] + 1 == L ? 0 : c[1] + 1, c[2] + 1 == L ? 0 : c[2] + 1};
-        double etasum = 0.0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-#pragma unroll
-            for (int o2 = 0; o2 < 2; ++o2)
-#pragma unroll
-                for (int o1 = 0; o1 < 2; ++o1) {
-                    int x[3] = {c[0], c[1], c[2]};
-                    x[d1] = o1 ? cp[d1] : c[d1];
-                    x[d2] = o2 ? cp[d2] : c[d2];
-                    etasum += eta.at(d, x[2], site_index(x[0], x[1], x[2], L), L, Ns);
-                }
-        }
-        const double eps_cell = 12.0 / etasum;
-        double S, dS[3];
-        self_sum(G, f, S, dS);
-        us = qi * qi / (2.0 * eps_cell * a) * S;
-    }
-    double v[1] = {us};
-    block_sum<1>(v);
-    if (threadIdx.x == 0) partials[blockIdx.x] = v[0];
-}
-
-hipError_t launch_uself(memd_ctx *c, double *partials, int *nblk) {
-    const int nb = ion_blocks_x8(c->n, 1);
-    *nblk = nb;
-    if (c->fp32)
-        hipLaunchKernelGGL(k_uself<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a, c->q,
-                           c->r, EtaView<float>{c->eta_mode, c->eta_uni, (const float *)c->eta_prof,
-                                                (const float *)c->eta_link},
-                           c->scal + S_G, partials);
-    else
-        hipLaunchKernelGGL(k_uself<double>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->Ns, c->a, c->q,
-                           c->r, EtaView<double>{c->eta_mode, c->eta_uni, (const double *)c->eta_prof,
-                                                 (const double *)c->eta_link},
-                           c->scal + S_G, partials);
     return hipGetLastError();
 }
 

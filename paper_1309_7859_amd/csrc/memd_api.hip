@@ -266,8 +266,7 @@ hipError_t enqueue_observables(memd_ctx *c, bool audit, bool energy, double *aud
     int fb = 0, ib = 0;
     prof_begin(c, audit ? F_AUDIT : F_ENERGY);
     if (audit && (e = launch_spread_dense(c, true, c->rho, cnt)) != hipSuccess) return e;
-    if ((e = launch_field_obs(c, audit, energy, c->partials, &fb)) != hipSuccess) return e;
-    if (energy && (e = launch_uself(c, ion_partials(c), &ib)) != hipSuccess) return e;
+    if ((e = launch_field_obs(c, audit, energy, c->partials, &fb, ion_partials(c), &ib)) != hipSuccess) return e;
     e = launch_finalize_obs(c, c->partials, fb, ion_partials(c), ib, dip, dipn, audit, energy, audit_hist,
                             energy_hist);
     prof_end(c, audit ? F_AUDIT : F_ENERGY);

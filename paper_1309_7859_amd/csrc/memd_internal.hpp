@@ -269,9 +269,18 @@ hipError_t refresh_forces(memd_ctx *c);
 // current set; the fused deposit only).
 hipError_t launch_md_ions(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk, bool gather,
                           const double *mass, double *v, int kicks, double *disp, bool pack, bool records);
+// grid of the sorted-order ion kernels (lanes_per_ion lanes per ion): a
+// multiple of the 8 XCDs
+inline int ion_blocks_x8(int n, int lanes_per_ion = 1) {
+    const long long t = (long long)(n > 0 ? n : 1) * lanes_per_ion;
+    const int b = (int)((t + kThreads - 1) / kThreads);
+    return (b + 7) / 8 * 8;
+}
 // Energy and/or audit of the current state in one pass over the lattice
 // (the audit reads c->rho): partials[4 nblk] = (we, wb, max |R|, sum R^2).
-hipError_t launch_field_obs(memd_ctx *c, bool audit, bool energy, double *partials, int *nblk);
+// (with energy also the self-energy partials into ipart, iblk of them)
+hipError_t launch_field_obs(memd_ctx *c, bool audit, bool energy, double *partials, int *nblk, double *ipart,
+                            int *iblk);
 // The audit's site pass on any buffers: partials[2 * nblk] (max |R|, sum R^2
 // per block) of R_v = a^2 div D(v) - rho_v; nblk <= kSiteBlocks.
 hipError_t launch_audit_raw(hipStream_t s, const void *D, bool fp32, const double *rho, int L, double a,
@@ -306,7 +315,6 @@ hipError_t launch_bin_ions(memd_ctx *c, bool reorder = false, bool zero_irr = fa
 hipError_t launch_iota(hipStream_t s, int *dst, int n);
 // out[perm[s] * w + k] = in[s * w + k] on the context's stream.
 hipError_t launch_unpermute(memd_ctx *c, int w, const double *in, double *out);
-hipError_t launch_uself(memd_ctx *c, double *partials, int *nblk);
 
 // ---- launchers (reductions / finalisers) ----
 // Sum `width` doubles per block over nblk partial blocks into dst[width] (fixed order).
