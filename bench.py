@@ -393,29 +393,33 @@ def main():
     value = sites * args.steps / r["wall"]
     ion_steps = w.n * args.steps / r["wall"]
 
-    lf_avg_s = r["lf_ms"] / 1e3 / max(r["lf_n"], 1)
+    # (a one-step window times no leapfrog launch: the first of a call is never sampled)
+    lf_avg_s = r["lf_ms"] / 1e3 / r["lf_n"] if r["lf_n"] else None
     alg = algorithmic_bytes(args.precision, sites, w.n)
     impl = implementation_bytes(fp32, sites, w.n, r["fused"])
-    achieved = alg / lf_avg_s / 1e9
+    achieved = alg / lf_avg_s / 1e9 if lf_avg_s else None
     traffic = load_traffic(args.precision)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (round(traffic / lf_avg_s / 1e9, 1) if traffic else None),
+
+    def per_launch(x, nd):
+        return round(x, nd) if lf_avg_s else None
+    roof = {"bound": "hbm", "achieved": per_launch(achieved or 0.0, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": per_launch((achieved or 0.0) / HBM_PEAK_GBS, 4),
+            "traffic": (round(traffic / lf_avg_s / 1e9, 1) if traffic and lf_avg_s else None),
             "kernel": ("k_leapfrog_dep (Faraday + Ampere + tile-owned current deposit + forces + ion movers)" if r["fused"]
                        else "k_leapfrog (Faraday + Ampere)"),
             "algorithmic_bytes_per_launch": alg,
             "algorithmic_bytes_rule": f"{SITE_BYTES[args.precision]} B/site + {ION_BYTES[args.precision]} B/ion",
-            "avg_launch_us": round(lf_avg_s * 1e6, 2),
+            "avg_launch_us": per_launch((lf_avg_s or 0.0) * 1e6, 2),
             "launches": r["lf_n"],
             "timing": "HIP events around each run of one-launch steps in the timed window (all their "
                       f"launches), plus one in {PROFILE_EVERY} of the launches beside cadence work",
             "implementation_bytes_per_launch": impl,
-            "implementation_frac": round(impl / lf_avg_s / 1e9 / HBM_PEAK_GBS, 4),
+            "implementation_frac": per_launch(impl / (lf_avg_s or 1.0) / 1e9 / HBM_PEAK_GBS, 4),
             "tile": {"x": 64, "y": 4 * r["tile"][0], "z_chunk": r["tile"][1],
                      "autotuned_us": r["tile"][2]}}
     if traffic:
         roof["traffic_bytes_per_launch"] = traffic
-    if copy:
+    if copy and achieved:
         roof["frac_of_stream_copy"] = round(achieved / copy["GBps"], 4)
     ms_step = r["wall"] * 1e3 / args.steps
     out = {
@@ -444,7 +448,7 @@ def main():
                               "kind": f"device copy of {args.stream_mb} MiB (torch), median of {copy['reps']}"}
     if fp32 and args.fp64 > 0:
         r64 = gpu_run(w, args.steps, args.warmup, "fp64", outputs=True)
-        lf64 = r64["lf_ms"] / 1e3 / max(r64["lf_n"], 1)
+        lf64 = r64["lf_ms"] / 1e3 / r64["lf_n"] if r64["lf_n"] else float("nan")
         b64 = algorithmic_bytes("fp64", sites, w.n)
         out["fp64_variant"] = {
             "value": round(sites * args.steps / r64["wall"], 1),
@@ -461,7 +465,7 @@ def main():
         w2 = W.Workload("c4@256", 256, w.a, w.dt, tuple(8 * c for c in w.counts), "salt", 0.0, w.sigma,
                         args.diag256_steps, 105, salt_every=CADENCE)
         r2 = gpu_run(w2, args.diag256_steps, 10, "fp32", solve_tol=1e-6)
-        lf2 = r2["lf_ms"] / 1e3 / max(r2["lf_n"], 1)
+        lf2 = r2["lf_ms"] / 1e3 / r2["lf_n"] if r2["lf_n"] else float("nan")
         b2 = algorithmic_bytes("fp32", w2.sites, w2.n)
         out["diag_256"] = {
             "workload": f"c4 recipe at 256^3: 8e5 ions (10% +-2), salt eps, audit and energy every {CADENCE} "
