@@ -178,7 +178,9 @@ hipError_t launch_leapfrog(memd_ctx *c, const void *Din, const void *Bin, void *
         P.G = c->scal + S_G;
         P.a = c->a;
         P.dip_prev = dip_prev;
-        P.dip_nparts = dip_nparts;
+        // (a list build just now may have rewritten the ions' own dynamics'
+        // position partials, with its own count)
+        P.dip_nparts = c->md_pos && dip_prev ? c->pos_nb : dip_nparts;
         P.P = c->scal + (c->fold_step ? S_PB + 3 * (int)(c->step_index & 1) : S_P);
         P.ovf_mark = c->fold_step ? c->ovf_mark : nullptr;
         P.V = c->V;

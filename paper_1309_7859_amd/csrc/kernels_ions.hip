@@ -127,6 +127,11 @@ struct PackArgs {
     uint64_t seed;
     uint32_t t;
     double sigma;
+    // non-null: the position each move ends at (by storage index) and one
+    // partial of q r per block (the ions' own dynamics, whose leapfrog then
+    // runs no movers)
+    double *r_next;
+    double *pos_dip;
 };
 
 // Lists of the fused deposit, one lane per ion in storage order: the ion's
@@ -215,6 +220,7 @@ __global__ __launch_bounds__(256) void k_build_lists(int n, int L, double a, con
             }
         }
     }
+    double pn[3] = {0.0, 0.0, 0.0};
     if (j < n) {
         list_fail[s] = ok ? 0 : 1;
         if constexpr (PACK) {
@@ -222,6 +228,20 @@ __global__ __launch_bounds__(256) void k_build_lists(int n, int L, double a, con
             double du[3];
             step_displacement(j, L, a, PA.disp, PA.perm, PA.bad, PA.seed, PA.t, PA.sigma, du);
             PA.dep_atomic[s] = write_record_at<T>(L, a, PA.q[j], u, du, s, PA.O, ok ? 0 : 1, cb) ? 1 : 0;
+            if (PA.r_next) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double un = u[d] + du[d];  // the movers' arithmetic
+                    PA.r_next[3 * j + d] = un;
+                    pn[d] = PA.q[j] * un;
+                }
+            }
+        }
+    }
+    if constexpr (PACK) {
+        if (PA.r_next) {
+            block_sum<3>(pn);
+            if (threadIdx.x < 3) PA.pos_dip[3 * blockIdx.x + threadIdx.x] = pn[threadIdx.x];
         }
     }
 }
@@ -250,12 +270,19 @@ hipError_t launch_build_lists(memd_ctx *c, bool pack, const double *disp, uint64
     if (pack && c->tile_irregular && c->irr_zeroed != c->step_index) launch_clear_irregular(c);
     c->irr_zeroed = -1;
     const int nb = ion_blocks(c->n);
+    // the ions' own dynamics without movers: the end positions of the moves
+    // packed here and their dipole partials come from this kernel too
+    double *rn = pack && c->md_pos ? c->r_alt : nullptr;
+    double *pd = rn ? c->dip[c->step_index & 1] : nullptr;
+    if (rn) c->pos_nb = nb;
     if (pack && c->fp32) {
-        PackArgs<float> PA{c->q, disp, c->perm, c->dep_atomic, dep_out<float>(c), c->bad_moves, seed, t, sigma};
+        PackArgs<float> PA{c->q,  disp, c->perm, c->dep_atomic, dep_out<float>(c), c->bad_moves, seed, t, sigma,
+                           rn,    pd};
         hipLaunchKernelGGL((k_build_lists<float, true>), dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
                            c->r, c->slot, c->cbin, c->list_fail, TL, PA);
     } else if (pack) {
-        PackArgs<double> PA{c->q, disp, c->perm, c->dep_atomic, dep_out<double>(c), c->bad_moves, seed, t, sigma};
+        PackArgs<double> PA{c->q,  disp, c->perm, c->dep_atomic, dep_out<double>(c), c->bad_moves, seed, t, sigma,
+                            rn,    pd};
         hipLaunchKernelGGL((k_build_lists<double, true>), dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->a,
                            c->r, c->slot, c->cbin, c->list_fail, TL, PA);
     } else {
@@ -740,6 +767,11 @@ struct MdIonArgs {
     const unsigned int *ecap_bad;
     unsigned int cap_tag;
     const T *ecell;
+    // non-null (with records): the position the next move ends at (by
+    // storage index) and one partial of q r of those per block, for the
+    // leapfrog of the next step, which then runs no movers
+    double *r_next;
+    double *pos_dip;
 };
 
 // force_ion's lattice part and Green's-function self force from the field
@@ -851,29 +883,46 @@ __global__ __launch_bounds__(256) void k_md_ions(MdIonArgs<T> M) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) F[d] = A.F[3 * i + d];
     }
-    if (!live) return;
-    double du[3];
+    double pn[3] = {0.0, 0.0, 0.0};
+    if (live) {
+        double du[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        double w = vv[d] + M.half_dt * F[d] / m;
-        if (M.kicks == 2) w = w + M.half_dt * F[d] / m;
-        M.v[3 * ci + d] = w;
-        du[d] = M.dt * w;
-    }
-    if (M.pack) {
+        for (int d = 0; d < 3; ++d) {
+            double w = vv[d] + M.half_dt * F[d] / m;
+            if (M.kicks == 2) w = w + M.half_dt * F[d] / m;
+            M.v[3 * ci + d] = w;
+            du[d] = M.dt * w;
+        }
+        if (M.pack) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) M.disp[3 * ci + d] = du[d];
+            for (int d = 0; d < 3; ++d) M.disp[3 * ci + d] = du[d];
+        }
+        if (M.records) {
+            sanitize_move(du, A.a, A.L, M.bad);
+            M.dep_atomic[rs] = write_record_at<T>(A.L, A.a, qi, u, du, rs, M.O, lfail, lcell) ? 1 : 0;
+            if (M.r_next) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double un = u[d] + du[d];  // the movers' arithmetic
+                    M.r_next[3 * i + d] = un;
+                    pn[d] = qi * un;
+                }
+            }
+        }
     }
-    if (M.records) {
-        sanitize_move(du, A.a, A.L, M.bad);
-        M.dep_atomic[rs] = write_record_at<T>(A.L, A.a, qi, u, du, rs, M.O, lfail, lcell) ? 1 : 0;
+    if (M.r_next) {
+        block_sum<3>(pn);
+        if (threadIdx.x < 3) M.pos_dip[3 * blockIdx.x + threadIdx.x] = pn[threadIdx.x];
     }
 }
 
 hipError_t launch_md_ions(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk, bool gather,
-                          const double *mass, double *v, int kicks, double *disp, bool pack, bool records) {
+                          const double *mass, double *v, int kicks, double *disp, bool pack, bool records,
+                          bool positions) {
     if (c->n == 0) return hipSuccess;
     const int nb = ion_blocks_x8(c->n, 1);
+    double *rn = records && positions ? c->r_alt : nullptr;
+    if (rn) c->pos_nb = nb;
     auto fill = [&](auto &M) {
         M.gather = gather ? 1 : 0;
         M.fa.dip_partials = dip_partials;
@@ -894,6 +943,8 @@ hipError_t launch_md_ions(memd_ctx *c, const void *D, const double *dip_partials
         const bool cap = gather && c->ecap_tag != 0u;
         M.ecap_bad = cap ? c->ecap_bad : nullptr;
         M.cap_tag = c->ecap_tag;
+        M.r_next = rn;
+        M.pos_dip = rn ? c->dip[c->step_index & 1] : nullptr;
     };
     if (c->fp32) {
         MdIonArgs<float> M;

@@ -667,11 +667,16 @@ void swap_record_sets(memd_ctx *c) {
 // recs_ready (in): the caller wrote this step's records (k_md_ions); out:
 // whether the forces of the new state were gathered here (the plain path),
 // else the movers' dipole partials the caller's gather sums into P.
+// pos_ready (in): the caller also wrote where this step's moves end (r_alt)
+// and their dipole partials (dip[step_index & 1], pos_nb of them), so the
+// leapfrog runs no movers; its first tile sums those partials into P of the
+// new state.
 struct MdHandoff {
     bool recs_ready;
     bool gathered;
     const double *dip;
     int nb;
+    bool pos_ready;
 };
 
 memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, double sigma,
@@ -680,6 +685,7 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
     // the deposit records of this step were written by the previous step's
     // movers (or, for the ions' own dynamics, by the caller)
     bool recs_ready = md && md->recs_ready;
+    const bool md_pos = md && md->pos_ready;
     const double *dip_prev = nullptr;
     int dip_nb = 0;
     bool alone = false;
@@ -734,9 +740,17 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
             prof_pair(c, F_LEAPFROG, &e0, &e1);
         }
         c->fold_step = fold;
+        if (md_pos && fused) {
+            // the end positions and their partials are ready (or are written
+            // by the list build that a re-binning brings on)
+            dip_prev = c->dip[c->step_index & 1];
+            dip_nb = c->pos_nb;
+        }
+        c->md_pos = md_pos && fused;
         const hipError_t lf = launch_leapfrog(c, c->D[c->cur], c->B[c->cur], c->D[nx], c->B[nx], e0, e1, dstep,
                                               seed, tstep, sigma, fused, !recs_ready, fused ? dip_prev : nullptr,
-                                              dip_nb, fused ? &mv : nullptr, !md);
+                                              dip_nb, fused && !md_pos ? &mv : nullptr, !md);
+        c->md_pos = false;
         c->fold_step = false;
         CK(lf);
         if (fused) {
@@ -747,11 +761,15 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
                 CK(launch_ion_finish(c, c->D[c->cur], c->D[nx], !md));
                 prof_end(c, F_DEPOSIT);
             }
-            std::swap(c->r, c->r_alt);  // the movers' positions are now the current ones
+            std::swap(c->r, c->r_alt);  // the movers' (or the caller's) positions are now the current ones
             if (pack_next) swap_record_sets(c);
             recs_ready = pack_next;
-            dip_prev = mv.dip_out;
-            dip_nb = mv.nparts;
+            if (md_pos) {
+                dip_nb = c->pos_nb;  // (dip_prev: the partials of those positions)
+            } else {
+                dip_prev = mv.dip_out;
+                dip_nb = mv.nparts;
+            }
             c->cur = nx;
         } else {
             prof_begin(c, F_DEPOSIT);
@@ -866,6 +884,9 @@ memd_status memd_md_step(memd_ctx *c, double *v, const double *mass, int nsteps)
     // deposits.  The plain path gathers the forces in the step, and the ion
     // kernel only kicks and writes the move.
     const bool records = fused_deposit_ok(c);
+    // with the atomic path on the tiles' list, the ion kernel also writes the
+    // positions the next moves end at, and the leapfrog runs no movers
+    const bool pos = records && c->tile_irregular;
     if (records && !c->md_cap) {
         // the capture buffers of the fused path: E on the 12 links of each
         // ion's end cell (field type), the incomplete-capture stamps (0 marks
@@ -887,14 +908,15 @@ memd_status memd_md_step(memd_ctx *c, double *v, const double *mass, int nsteps)
     // the last ones were computed), the opening half kick, the first move
     CK(enqueue_dipole_forces(c));
     if (records && c->tile_irregular) CK(launch_clear_irregular(c));
-    CK(launch_md_ions(c, c->D[c->cur], nullptr, 0, false, dm, dv, 1, disp, true, records));
+    CK(launch_md_ions(c, c->D[c->cur], nullptr, 0, false, dm, dv, 1, disp, true, records, pos));
     for (int t = 0; t < nsteps; ++t) {
-        MdHandoff h{records, false, nullptr, 0};
+        MdHandoff h{records, false, nullptr, 0, pos};
         const memd_status st = run_steps(c, disp, 1, 0, 0.0, &h);
         if (st != MEMD_OK) return st;
         const bool last = t + 1 == nsteps;
-        CK(launch_md_ions(c, c->D[c->cur], h.dip, h.nb, !h.gathered, dm, dv, last ? 1 : 2, disp, !last,
-                          records && !last));
+        // (with pos the leapfrog's first tile has summed P of the new state)
+        CK(launch_md_ions(c, c->D[c->cur], pos ? nullptr : h.dip, pos ? 0 : h.nb, !h.gathered, dm, dv,
+                          last ? 1 : 2, disp, !last, records && !last, pos && !last));
     }
     if (!v_dev) CK(copy_out(c, v, dv, per * sizeof(double)));
     return MEMD_OK;

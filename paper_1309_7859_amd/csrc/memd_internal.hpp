@@ -164,6 +164,11 @@ struct memd_ctx {
     int *endc;
     unsigned int ecap_tag;  // tag of the leapfrog launch that captured (0: none)
     long irr_zeroed;        // step whose atomic-path count the last re-binning cleared (-1: none)
+    // the ions' own dynamics without movers in the leapfrog: a list build
+    // that packs records also writes the moves' end positions (r_alt) and
+    // their dipole partials (dip[step_index & 1], pos_nb of them)
+    bool md_pos;
+    int pos_nb;
     long perm_version;   // advanced whenever perm changes
 
     // reductions and audit
@@ -267,8 +272,12 @@ hipError_t refresh_forces(memd_ctx *c);
 // half kicks of v (caller order, masses too), with pack the next move dt v
 // into disp (caller order), with records also its deposit records (the
 // current set; the fused deposit only).
+// with positions also the end position of each next move into r_alt and
+// their dipole partials into dip[step_index & 1] (pos_nb of them), so that the
+// next step's leapfrog runs no movers.
 hipError_t launch_md_ions(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk, bool gather,
-                          const double *mass, double *v, int kicks, double *disp, bool pack, bool records);
+                          const double *mass, double *v, int kicks, double *disp, bool pack, bool records,
+                          bool positions = false);
 // grid of the sorted-order ion kernels (lanes_per_ion lanes per ion): a
 // multiple of the 8 XCDs
 inline int ion_blocks_x8(int n, int lanes_per_ion = 1) {
