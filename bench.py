@@ -173,8 +173,8 @@ def gpu_run(w, steps, warmup, precision, copy_mb=0, tile=None, solve_tol=1e-12, 
     torch.cuda.synchronize()
     # The steps that are one leapfrog launch and nothing else are timed in
     # runs (an event pair around each run of them, every launch counted);
-    # one in PROFILE_EVERY of the other leapfrog launches (those beside the
-    # cadence work) carries events of its own, the first of the call excepted
+    # the last of every PROFILE_EVERY other leapfrog launches (those beside
+    # the cadence work) carries events of its own, never the first of the call
     memd.memd_profile_enable(G.ctx, ["leapfrog"], PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -412,7 +412,7 @@ def main():
             "avg_launch_us": per_launch((lf_avg_s or 0.0) * 1e6, 2),
             "launches": r["lf_n"],
             "timing": "HIP events around each run of one-launch steps in the timed window (all their "
-                      f"launches), plus one in {PROFILE_EVERY} of the launches beside cadence work",
+                      f"launches), plus the last of every {PROFILE_EVERY} launches beside cadence work",
             "implementation_bytes_per_launch": impl,
             "implementation_frac": per_launch(impl / (lf_avg_s or 1.0) / 1e9 / HBM_PEAK_GBS, 4),
             "tile": {"x": 64, "y": 4 * r["tile"][0], "z_chunk": r["tile"][1],

@@ -267,8 +267,8 @@ memd_status memd_get_params(memd_ctx *ctx, double *c, double eps_h[3], double *e
  * runs: consecutive steps that are one fused launch and nothing else are
  * bracketed by one marker pair per run, and every launch of the run counts;
  * a leapfrog launch outside such runs gets events riding on its own launch,
- * one in `every`, except the first launch of a call.  Each call starts a
- * fresh collection.  memd_profile_read waits for the stream and returns the
+ * the last of each `every` such launches, never the first launch of a call.
+ * Each call starts a fresh collection.  memd_profile_read waits for the stream and returns the
  * total milliseconds and the number of timed launches of one family. */
 memd_status memd_profile_enable(memd_ctx *ctx, int mask, int every);
 memd_status memd_profile_read(memd_ctx *ctx, int family, double *total_ms, long *launches);

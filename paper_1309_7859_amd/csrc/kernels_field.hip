@@ -112,7 +112,11 @@ static hipError_t launch_lf_t(memd_ctx *c, const void *Din, const void *Bin, voi
         M.ahead = nblk <= slots ? 1 : 0;
         DepArgs P = *dep;
         P.dip_block = M.ahead ? M.nblocks : 0;  // the first tile sums the dipole
-        hipExtLaunchKernelGGL(kern, dim3(nblk + M.nblocks), dim3(256), 0, c->stream, e0, e1, 0, A, P, M);
+        // (the extended launch only where events ride on it)
+        if (e0 || e1)
+            hipExtLaunchKernelGGL(kern, dim3(nblk + M.nblocks), dim3(256), 0, c->stream, e0, e1, 0, A, P, M);
+        else
+            hipLaunchKernelGGL(kern, dim3(nblk + M.nblocks), dim3(256), 0, c->stream, A, P, M);
         return hipGetLastError();
     }
     if (R == 1)

@@ -305,7 +305,8 @@ hipError_t launch_clear_irregular(memd_ctx *c) {
 
 hipError_t launch_pack_ions(memd_ctx *c, const double *disp, uint64_t seed, uint32_t t, double sigma) {
     if (c->n == 0) return hipSuccess;
-    if (c->tile_irregular) launch_clear_irregular(c);
+    if (c->tile_irregular && c->irr_zeroed != c->step_index) launch_clear_irregular(c);
+    c->irr_zeroed = -1;
     const int nb = ion_blocks(c->n);
     if (c->fp32)
         hipLaunchKernelGGL(k_pack_ions<float>, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->L, c->a, c->q,
@@ -633,6 +634,7 @@ struct ForceArgs {
     const double *dip_partials;  // optional: deposit's per-block q r sums -> P
     int dip_nblk;
     int self_direct;  // 1: direct self subtraction
+    int *zero;        // optional: cleared (the next call's atomic-path count)
 };
 
 // Forces on every ion, one lane per ion following `order` (force_ion: the
@@ -643,6 +645,7 @@ struct ForceArgs {
 template <typename T>
 __global__ __launch_bounds__(256) void k_forces(ForceArgs<T> A) {
     __shared__ double Psh[3];
+    if (A.zero && blockIdx.x == 0 && threadIdx.x == 0) *A.zero = 0;
     const int slot = xcd_logical(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const bool live = slot < A.n;
     const int i = live ? (A.order ? A.order[slot] : slot) : 0;
@@ -709,23 +712,30 @@ static ForceArgs<T> force_args(memd_ctx *c, const void *D) {
     A.dip_partials = nullptr;
     A.dip_nblk = 0;
     A.self_direct = c->self_scheme == MEMD_SELF_DIRECT;
+    A.zero = nullptr;
     return A;
 }
 
-hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk) {
+hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk, bool zero_irr) {
     if (c->n == 0) return hipSuccess;
     const int nb = ion_blocks_x8(c->n, 1);
+    // the count of the next step's atomic-path ions, cleared here for the
+    // pack that starts the next call (nothing appends to it in between)
+    int *zero = zero_irr && c->tile_irregular ? irr_count(c, c->step_index) : nullptr;
     if (c->fp32) {
         auto A = force_args<float>(c, D);
         A.dip_partials = dip_partials;
         A.dip_nblk = dip_nblk;
+        A.zero = zero;
         hipLaunchKernelGGL(k_forces<float>, dim3(nb), dim3(kThreads), 0, c->stream, A);
     } else {
         auto A = force_args<double>(c, D);
         A.dip_partials = dip_partials;
         A.dip_nblk = dip_nblk;
+        A.zero = zero;
         hipLaunchKernelGGL(k_forces<double>, dim3(nb), dim3(kThreads), 0, c->stream, A);
     }
+    if (zero) c->irr_zeroed = c->step_index;
     return hipGetLastError();
 }
 

@@ -100,7 +100,11 @@ constexpr int kProfPoolPairs = 64;  // event pairs made per family when profilin
 
 static bool prof_take(memd_ctx *c, int fam) {
     if (!c->prof_on || !(c->prof_mask & (1u << fam))) return false;
-    return c->prof[fam].seen++ % c->prof_every == 0;
+    // the leapfrog's sampled launches (beside cadence work, where the host's
+    // event recording can leave the GPU idle) are the last of each group of
+    // `every`; other families take the first
+    const long k = c->prof[fam].seen++ % c->prof_every;
+    return k == (fam == F_LEAPFROG ? c->prof_every - 1 : 0);
 }
 
 // An event for a sample: from the pool made when profiling was enabled (so
@@ -815,7 +819,7 @@ memd_status run_steps(memd_ctx *c, const double *dd, int nsteps, uint64_t seed, 
     } else if (dip_prev && c->final_forces) {
         // forces (and P) of the final state
         prof_begin(c, F_FORCES);
-        CK(launch_forces(c, c->D[c->cur], dip_prev, dip_nb));
+        CK(launch_forces(c, c->D[c->cur], dip_prev, dip_nb, true));
         prof_end(c, F_FORCES);
     }
     return MEMD_OK;
@@ -908,6 +912,7 @@ memd_status memd_md_step(memd_ctx *c, double *v, const double *mass, int nsteps)
     // the last ones were computed), the opening half kick, the first move
     CK(enqueue_dipole_forces(c));
     if (records && c->tile_irregular) CK(launch_clear_irregular(c));
+    c->irr_zeroed = -1;  // (the ion kernel below appends to that count)
     CK(launch_md_ions(c, c->D[c->cur], nullptr, 0, false, dm, dv, 1, disp, true, records, pos));
     for (int t = 0; t < nsteps; ++t) {
         MdHandoff h{records, false, nullptr, 0, pos};

@@ -315,7 +315,10 @@ hipError_t launch_spread_raw(hipStream_t s, int n, int L, double a, const double
 // writes every vertex (no global atomics once the ions are in bin order).
 hipError_t launch_spread_dense(memd_ctx *c, bool weighted, double *dst, double *dst2 = nullptr);
 hipError_t launch_dipole(memd_ctx *c, double *partials, int *nblk);
-hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk);
+// zero_irr: also clear the atomic-path count of the current step (which the
+// next call's record pack then need not clear)
+hipError_t launch_forces(memd_ctx *c, const void *D, const double *dip_partials, int dip_nblk,
+                         bool zero_irr = false);
 // Row binning of the ions (order, slot, row counts/starts); with
 // reorder the ion arrays themselves move into bin order (see sorted).
 // zero_irr: the re-binning's scan also clears the count of this step's
