@@ -646,8 +646,8 @@ hipError_t launch_eta_sums(memd_ctx *c, double *partials, int *nblk) {
 // A workgroup takes tiles of 64 x 4 sites and marches through a chunk of
 // kSaltTZ planes.  Per plane R it stages cnt with a one-site halo in LDS,
 // forms the 3 x 3 sums over (x, y) for the 65 x 5 corners its cells need,
-// keeps three such planes, and from them nbar of plane R-1 (two planes
-// kept).  From nbar of planes P and P+1 (P = R-2) it computes eta of the own
+// keeps those of the last three planes in registers (each thread its own
+// corners), and from them nbar of plane R-1 (two planes kept in LDS).  From nbar of planes P and P+1 (P = R-2) it computes eta of the own
 // links of plane P's sites, the tile and a +1 halo in x and y, once each
 // (two planes kept in LDS), and stores the tile's; 12 / (sum of eta over the
 // 12 edges of a cell) of plane P-1 then reads them all from LDS.
@@ -658,7 +658,6 @@ __global__ __launch_bounds__(256) void k_salt_tile(const double *__restrict__ cn
                                                    double eps_floor, T *__restrict__ eta, T *__restrict__ ecell,
                                                    double *__restrict__ partials) {
     __shared__ double sc[7][67];      // cnt of plane R, x0-1 .. x0+65, y0-1 .. y0+5
-    __shared__ double sS[3][5][65];   // (x, y) box sums of planes R, R-1, R-2 (ring by plane)
     __shared__ double sN[2][5][65];   // nbar of two planes (ring by plane)
     __shared__ T sE[2][3][5][65];     // eta of the own links of two planes' sites (ring by plane)
     const int lx = threadIdx.x & 63, wy = threadIdx.x >> 6;
@@ -681,6 +680,7 @@ __global__ __launch_bounds__(256) void k_salt_tile(const double *__restrict__ cn
         };
         double pl[2];
         fetch(z0 - 1, pl);
+        double bs1[2] = {0.0, 0.0}, bs2[2] = {0.0, 0.0};  // box sums of planes R - 1 and R - 2
         for (int R = z0 - 1; R <= z1 + 2; ++R) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
@@ -689,23 +689,23 @@ __global__ __launch_bounds__(256) void k_salt_tile(const double *__restrict__ cn
             }
             if (R <= z1 + 1) fetch(R + 1, pl);
             __syncthreads();
-            const int rs = (R + 3) % 3;
-            for (int t = threadIdx.x; t < 5 * 65; t += 256) {
-                const int iy = t / 65, ix = t - iy * 65;
-                double b = 0.0;
+            // the box sums of plane R for this thread's entries (t, t + 256);
+            // those of the two planes before stay in registers, so nbar of
+            // plane Q = R - 1 follows without a barrier
+            const int Q = R - 1;
 #pragma unroll
-                for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                    for (int dx = 0; dx < 3; ++dx) b += sc[iy + dy][ix + dx];
-                sS[rs][iy][ix] = b;
-            }
-            __syncthreads();
-            const int Q = R - 1;  // nbar of plane Q from the box sums of Q-1, Q, Q+1
-            if (Q >= z0) {
-                for (int t = threadIdx.x; t < 5 * 65; t += 256) {
+            for (int j = 0; j < 2; ++j) {
+                const int t = threadIdx.x + 256 * j;
+                if (t < 5 * 65) {
                     const int iy = t / 65, ix = t - iy * 65;
-                    sN[(Q + 2) & 1][iy][ix] =
-                        (sS[(Q + 2) % 3][iy][ix] + sS[(Q + 3) % 3][iy][ix] + sS[rs][iy][ix]) * inv27;
+                    double b = 0.0;
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                        for (int dx = 0; dx < 3; ++dx) b += sc[iy + dy][ix + dx];
+                    if (Q >= z0) sN[(Q + 2) & 1][iy][ix] = (bs2[j] + bs1[j] + b) * inv27;
+                    bs2[j] = bs1[j];
+                    bs1[j] = b;
                 }
             }
             __syncthreads();
