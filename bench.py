@@ -248,8 +248,8 @@ def md_run(w, steps, warmup, tile=None):
     leapfrog with the deposit of the step's move, then the forces of the new
     state with both half kicks and the next move's records.  The ions move
     ballistically here, so they are re-binned every MD_REBIN_EVERY = 16
-    steps (measured: 0.0647 ms per step at 8, 0.0624-0.0625 at 16, 0.0651-0.0653
-    at 24, 0.0813 at 32)."""
+    steps (measured over 400 steps: 0.0552 ms per step at 12, 0.0549 at 16,
+    0.0551 at 20, 0.0579 at 24)."""
     import torch
     from paper_1309_7859_amd import memd
     from paper_1309_7859_amd import workloads as W
@@ -362,8 +362,9 @@ def main():
     ap.add_argument("--stream-mb", type=int, default=1024,
                     help="size of the on-box stream-copy ceiling measurement (0 = skip)")
     ap.add_argument("--tile", type=str, default="", help="rows,planes of the leapfrog tile")
-    ap.add_argument("--md-steps", type=int, default=100,
-                    help="steps of the c4 system under its own dynamics (0 = skip)")
+    ap.add_argument("--md-steps", type=int, default=400,
+                    help="steps of the c4 system under its own dynamics (0 = skip; the default, 400, "
+                         "is a whole number of cadence periods (50) and re-binning periods (16))")
     ap.add_argument("--diag256-steps", type=int, default=50,
                     help="steps of the same workload at 256^3 (8e5 ions), whose fields exceed the "
                          "256 MB Infinity Cache (0 = skip)")

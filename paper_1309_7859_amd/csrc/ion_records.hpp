@@ -40,7 +40,14 @@ struct DepOut {
 // path: irregular, drifted more than one cell from its list cell along an
 // axis, or missing from a list.
 // (list_fail and cb: the slot's entries of O.list_fail and O.cbin.)
-template <typename T>
+// WHOLE: the two cells' values are built in registers and stored whole with
+// 16-byte stores (entries of an axis the move does not use are zero; the
+// readers skip them by the axis flags; the second cell only when a move
+// crosses a face), else each value is stored where it is formed.  A kernel
+// that writes records on the path between two leapfrog launches (the ions'
+// own dynamics) takes the first, whose stores leave the wavefront sooner;
+// the movers beside the tiles the second, which writes fewer bytes.
+template <typename T, bool WHOLE = false>
 __device__ __forceinline__ bool write_record_at(int L, double a, double qi, const double (&u_in)[3],
                                                 const double (&du)[3], int s, const DepOut<T> &O, int list_fail,
                                                 int cb) {
@@ -81,6 +88,15 @@ __device__ __forceinline__ bool write_record_at(int L, double a, double qi, cons
     }
     const double a2 = a * a;
     unsigned int g[3] = {0u, 0u, 0u};
+    union {
+        T v[12];
+        uint4 w[kCellWords<T>];
+    } cv[2];
+    if constexpr (WHOLE) {
+#pragma unroll
+        for (int j = 0; j < 12; ++j) cv[0].v[j] = cv[1].v[j] = (T)0;
+    }
+    bool any_two = false;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
@@ -98,6 +114,7 @@ __device__ __forceinline__ bool write_record_at(int L, double a, double qi, cons
             corner[d1] = c1;
             corner[d2] = c2;
             const bool two = khi > klo;
+            any_two = any_two || two;
             g[d] = (unsigned)pack_cell(corner[0], corner[1], corner[2]) | kGroupOn | (two ? kGroupTwo : 0u);
             // a regular move spans at most two cells along the axis
 #pragma unroll
@@ -112,12 +129,24 @@ __device__ __forceinline__ bool write_record_at(int L, double a, double qi, cons
 #pragma unroll
                 for (int o2 = 0; o2 < 2; ++o2)
 #pragma unroll
-                    for (int o1 = 0; o1 < 2; ++o1)
-                        (cell ? O.con1 : O.con0)[s].v[4 * d + 2 * o2 + o1] =
-                            (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
+                    for (int o1 = 0; o1 < 2; ++o1) {
+                        const T val = (T)(-(amount * lin_w(o1, f1) * lin_w(o2, f2)));
+                        if constexpr (WHOLE) cv[cell].v[4 * d + 2 * o2 + o1] = val;
+                        else (cell ? O.con1 : O.con0)[s].v[4 * d + 2 * o2 + o1] = val;
+                    }
             }
         }
         u[d] = u1;
+    }
+    if constexpr (WHOLE) {
+        uint4 *d0 = reinterpret_cast<uint4 *>(&O.con0[s].v[0]);
+#pragma unroll
+        for (int q = 0; q < kCellWords<T>; ++q) d0[q] = cv[0].w[q];
+        if (any_two) {
+            uint4 *d1 = reinterpret_cast<uint4 *>(&O.con1[s].v[0]);
+#pragma unroll
+            for (int q = 0; q < kCellWords<T>; ++q) d1[q] = cv[1].w[q];
+        }
     }
     O.head[s] = make_int4(pack_cell(c0[0], c0[1], c0[2]), (int)g[0], (int)g[1], (int)g[2]);
     IonFQ<T> fq;

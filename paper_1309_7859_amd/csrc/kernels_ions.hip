@@ -871,21 +871,20 @@ __global__ __launch_bounds__(256) void k_md_ions(MdIonArgs<T> M) {
                              A.self_direct != 0);
             }
         }
-        if (psum) {
-            block_sum<3>(Ps);
-            if (threadIdx.x < 3) {
-                Psh[threadIdx.x] = Ps[threadIdx.x];
-                if (blockIdx.x == 0) A.scal[S_P + threadIdx.x] = Ps[threadIdx.x];
-            }
-        } else if (threadIdx.x < 3) {
-            Psh[threadIdx.x] = A.scal[S_P + threadIdx.x];
+        // the dipole field w P_d / (V eps_h_d), once per block
+        if (psum) block_sum<3>(Ps);
+        if (threadIdx.x < 3) {
+            const int d = threadIdx.x;
+            double Pd = d == 0 ? Ps[0] : (d == 1 ? Ps[1] : Ps[2]);
+            if (!psum) Pd = A.scal[S_P + d];
+            else if (blockIdx.x == 0) A.scal[S_P + d] = Pd;
+            Psh[d] = (A.scal[S_DIPW] * Pd) / (A.V * A.scal[S_EPSH + d]);
         }
         __syncthreads();
         if (live) {
-            const double w = A.scal[S_DIPW];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                F[d] = F[d] + qi * (w * Psh[d]) / (A.V * A.scal[S_EPSH + d]);
+                F[d] = F[d] + qi * Psh[d];
                 A.F[3 * i + d] = F[d];
             }
         }
@@ -896,10 +895,12 @@ __global__ __launch_bounds__(256) void k_md_ions(MdIonArgs<T> M) {
     double pn[3] = {0.0, 0.0, 0.0};
     if (live) {
         double du[3];
+        const double hm = M.half_dt / m;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            double w = vv[d] + M.half_dt * F[d] / m;
-            if (M.kicks == 2) w = w + M.half_dt * F[d] / m;
+            const double kick = hm * F[d];
+            double w = vv[d] + kick;
+            if (M.kicks == 2) w = w + kick;
             M.v[3 * ci + d] = w;
             du[d] = M.dt * w;
         }
@@ -909,7 +910,7 @@ __global__ __launch_bounds__(256) void k_md_ions(MdIonArgs<T> M) {
         }
         if (M.records) {
             sanitize_move(du, A.a, A.L, M.bad);
-            M.dep_atomic[rs] = write_record_at<T>(A.L, A.a, qi, u, du, rs, M.O, lfail, lcell) ? 1 : 0;
+            M.dep_atomic[rs] = write_record_at<T, true>(A.L, A.a, qi, u, du, rs, M.O, lfail, lcell) ? 1 : 0;
             if (M.r_next) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
