@@ -919,9 +919,16 @@ memd_status memd_md_step(memd_ctx *c, double *v, const double *mass, int nsteps)
         const memd_status st = run_steps(c, disp, 1, 0, 0.0, &h);
         if (st != MEMD_OK) return st;
         const bool last = t + 1 == nsteps;
+        // The move in caller order (disp) is read by the plain path's deposit
+        // and, with records, only by the list build of a re-binning step (the
+        // step about to run is c->step_index now; the first step of a call
+        // has it from the kernel before the loop, in case its lists are
+        // built then).
+        const bool rebin_next = c->sort_every > 0 && c->step_index % c->sort_every == 0;
+        const bool pack = !last && (!records || rebin_next);
         // (with pos the leapfrog's first tile has summed P of the new state)
         CK(launch_md_ions(c, c->D[c->cur], pos ? nullptr : h.dip, pos ? 0 : h.nb, !h.gathered, dm, dv,
-                          last ? 1 : 2, disp, !last, records && !last, pos && !last));
+                          last ? 1 : 2, disp, pack, records && !last, pos && !last));
     }
     if (!v_dev) CK(copy_out(c, v, dv, per * sizeof(double)));
     return MEMD_OK;
